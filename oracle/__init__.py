@@ -1,0 +1,30 @@
+"""CPU reference ("oracle") for residual-based Chebyshev filtered subspace iteration.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links
+anything in this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may use it.  It shares no code with the
+HIP library (no kernels, headers, helpers, constant generators or pre/post
+processing); the only common dependency is the seeded input module
+``workloads``, which holds no eigensolver arithmetic.
+
+Everything here is plain, slow, obviously-correct NumPy/SciPy in float64,
+following the paper (arXiv 2503.22652) step by step:
+
+* ``chebyshev``  -- affine map, scaled Chebyshev polynomials C_k, the scaling
+  coefficients sigma_k and the recurrence coefficients a_k, b_k, c_k
+  (Section 2.1, eq. ChFSIrecurrence; Section 3.2, eq. ChFSIrecurrenceSEPMP).
+* ``filters``    -- Algorithm 2 (Chebyshev filter) and Algorithm 3 (residual
+  based Chebyshev filter).
+* ``rr``         -- Rayleigh-Ritz on the non-orthogonal filtered basis
+  (Algorithm 1, step 2) with the column-scaled / SVQB treatment of a
+  numerically singular Gram matrix, and residual norms (Algorithm 1).
+* ``solver``     -- the outer loop of Algorithm 1 with either filter.
+* ``jacobi``     -- brute-force cyclic Jacobi eigensolver for tiny matrices
+  (an independent pin for the library eigensolver used in ``rr``).
+* ``stencil``    -- periodic 27-point operator application for grid pencils.
+* ``angles``     -- maximum principal angle (Definition 2.1).
+
+Parity status of each function is stated in its docstring; functions without
+an independent pin say "parity unpinned".
+"""
+from . import chebyshev, filters, rr, solver, jacobi, stencil, angles  # noqa: F401
