@@ -25,16 +25,20 @@ def jacobi_eigh(A: np.ndarray, tol: float = 1e-15, max_sweeps: int = 60):
     V = np.eye(n)
     fro = math.sqrt(float(np.sum(A * A))) or 1.0
     for _ in range(max_sweeps):
-        off = math.sqrt(max(float(np.sum(A * A) - np.sum(np.diag(A) ** 2)), 0.0))
+        off = float(np.linalg.norm(A - np.diag(np.diag(A))))
         if off <= tol * fro:
             break
         for p in range(n - 1):
             for q in range(p + 1, n):
                 apq = A[p, q]
-                if apq == 0.0:
+                diff = A[q, q] - A[p, p]
+                if apq == 0.0 or abs(apq) <= 1e-18 * abs(diff):
                     continue
-                theta = (A[q, q] - A[p, p]) / (2.0 * apq)
-                t = math.copysign(1.0, theta) / (abs(theta) + math.sqrt(theta * theta + 1.0))
+                theta = diff / (2.0 * apq)
+                if abs(theta) > 1e150:
+                    t = 0.5 / theta
+                else:
+                    t = math.copysign(1.0, theta) / (abs(theta) + math.sqrt(theta * theta + 1.0))
                 c = 1.0 / math.sqrt(t * t + 1.0)
                 s = t * c
                 # A <- J^T A J with J = rotation in (p, q)
