@@ -1,0 +1,260 @@
+/*
+ * chfsi.h -- C ABI of libchfsi: residual-based Chebyshev filtered subspace
+ * iteration (R-ChFSI) for the lowest eigenpairs of a symmetric-definite pencil
+ *
+ *        A u = lambda B u,   A symmetric, B symmetric positive definite
+ *
+ * (Kodali, Ramakrishnan, Motamarri, arXiv 2503.22652, Section 2, eq. ghep),
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions for every call:
+ *  - "device" pointers are HIP device memory on the context's device; "host"
+ *    pointers are ordinary host memory.  Nothing in this header takes a
+ *    framework (e.g. PyTorch) type; a stream is passed as `void*` and is a
+ *    hipStream_t (NULL = the default stream).
+ *  - Blocks of vectors are column-major, N rows, leading dimension ld >= N
+ *    (the LAPACK convention).  Dense operators are column-major N x N with
+ *    leading dimension ld >= N and must be symmetric.
+ *  - Functions return a chfsi_status and never throw.  On error, output
+ *    buffers are left untouched except where a function says otherwise, and a
+ *    message is available from chfsi_last_error() (thread-local).
+ *  - Real symmetric problems only (the complex Hermitian variant of the
+ *    paper's Section 4.3 is not implemented).
+ */
+#ifndef CHFSI_H_
+#define CHFSI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CHFSI_OK = 0,
+  CHFSI_ERR_ARG = 1,        /* invalid argument (message says which) */
+  CHFSI_ERR_NOMEM = 2,      /* device allocation failed */
+  CHFSI_ERR_DEVICE = 3,     /* HIP runtime / kernel launch error */
+  CHFSI_ERR_NOT_SPD = 4,    /* B (or the Gram matrix Y^T B Y) is not positive definite */
+  CHFSI_ERR_NOCONV = 5,     /* max_iter reached; best pairs so far are returned */
+  CHFSI_ERR_NUMERIC = 6,    /* NaN/Inf met in Ritz values or residual norms */
+  CHFSI_ERR_BUSY = 7,       /* server queue full / admission refused */
+  CHFSI_ERR_CANCELLED = 8,  /* request was cancelled */
+  CHFSI_ERR_TIMEOUT = 9     /* chfsi_wait timed out; the request is still live */
+} chfsi_status;
+
+/* Operator kinds. */
+typedef enum {
+  CHFSI_OP_IDENTITY = 0,  /* B = I (standard problem) */
+  CHFSI_OP_DENSE = 1,     /* dense symmetric matrix in device memory */
+  CHFSI_OP_STENCIL27 = 2  /* periodic 27-point grid operator (see chfsi_operator) */
+} chfsi_op_kind;
+
+/* Storage / arithmetic precision of the filter's bulk work.  FP32: blocks and
+ * the operator copy are FP32 and products accumulate in FP32 on MFMA.  BF16:
+ * filter blocks are stored in bfloat16 and all arithmetic is FP32 (stencil
+ * operators only).  The Rayleigh-Ritz step and residual norms are always FP64. */
+typedef enum { CHFSI_PREC_FP64 = 0, CHFSI_PREC_FP32 = 1, CHFSI_PREC_BF16 = 2 } chfsi_prec;
+
+/* Filter algorithm: Algorithm 2 (three-term recurrence on the block, with
+ * H = D^{-1} A) or Algorithm 3 (residual-based recurrence). */
+typedef enum { CHFSI_METHOD_CHFSI = 0, CHFSI_METHOD_RCHFSI = 1 } chfsi_method;
+
+/*
+ * A symmetric operator.
+ *  kind = CHFSI_OP_DENSE: `dense` (device, n x n, column-major, leading
+ *    dimension `ld`, symmetric; borrowed: must outlive the context).
+ *  kind = CHFSI_OP_STENCIL27: periodic grid nx*ny*nz = n, vector index
+ *    x + nx*(y + ny*z).  y = S z + potential term, where S has coefficients
+ *    coef[(dz+1)*9 + (dy+1)*3 + (dx+1)] for the 27 offsets (dx,dy,dz) in
+ *    {-1,0,1}^3.  field_mode 0: no potential; 1: diag(V) z; 2: the
+ *    mass-weighted 1/2 (diag(V) M + M diag(V)) z with M given by coef_mass.
+ *    `field` (device, length n) holds V; borrowed.
+ */
+typedef struct {
+  int32_t kind;
+  int64_t n;
+  const double* dense;
+  int64_t ld;
+  int32_t nx, ny, nz;
+  double coef[27];
+  double coef_mass[27];
+  const double* field;
+  int32_t field_mode;
+} chfsi_operator;
+
+/* Solver parameters (Algorithm 1 inputs: n, p, bounds, tau). */
+typedef struct {
+  int64_t n_wanted;     /* number of wanted eigenpairs n (stopping test uses j < n) */
+  int64_t block;        /* block size b >= n (columns filtered per iteration) */
+  int32_t degree;       /* Chebyshev degree p >= 1 */
+  int32_t max_iter;     /* outer iterations of Algorithm 1 */
+  double tol;           /* tau: stop when max_{j<n} ||A x_j - eps_j B x_j||_2 < tau */
+  int32_t method;       /* chfsi_method */
+  int32_t filter_prec;  /* chfsi_prec */
+  /* Filter bounds.  lambda_max must be finite (an upper bound of the spectrum
+   * of B^{-1}A).  lambda_min / lambda_T may be NaN: then each iteration uses
+   * lambda_T = largest Ritz value of the block and
+   * lambda_min = eps_1 - 0.05 (eps_b - eps_1). */
+  double lambda_min, lambda_max, lambda_T;
+  uint64_t seed;        /* seed of the random start block when init_random != 0 */
+  int32_t init_random;  /* chfsi_solve: 1 = fill X with N(0,1) (Philox-4x32-10), 0 = X holds the start */
+  int32_t profile;      /* 1 = time every filter operator-product kernel with HIP events */
+} chfsi_params;
+
+/* Per-solve report (host). */
+#define CHFSI_MAX_HISTORY 512
+typedef struct {
+  int32_t iterations;          /* filter + Rayleigh-Ritz passes performed */
+  int32_t converged;           /* 1 if max residual < tol */
+  double max_residual;         /* final max_{j<n} r_j */
+  double time_total_ms;        /* wall time of chfsi_solve (device-synchronous) */
+  double time_filter_ms;       /* sum of filter times (HIP events) */
+  double time_rr_ms;           /* sum of Rayleigh-Ritz + residual times (HIP events) */
+  double filter_flops;         /* algorithmic flops of all filter products */
+  int32_t jacobi_sweeps;       /* sum of eigensolver sweeps */
+  int32_t kernel_launches;     /* profile: filter operator-product kernels timed */
+  double kernel_ms;            /* profile: their summed durations (HIP events) */
+  int32_t flags;               /* bit 0: Gram Cholesky needed the diagonal shift fallback */
+  double history[CHFSI_MAX_HISTORY]; /* max residual after each pass (entry 0: initial RR) */
+} chfsi_report;
+
+typedef struct chfsi_ctx chfsi_ctx;
+
+/*
+ * Create a solver context for the pencil (A, B) with approximate inverse
+ * D^{-1} = diag(d_inv) of B (paper Section 3.2: D^{-1} replaces B^{-1} in the
+ * filter only).  B == NULL or B->kind == CHFSI_OP_IDENTITY means B = I.
+ * d_inv: device, length n, or NULL for D^{-1} = I.
+ * The context borrows A, B and d_inv (they must outlive it) and owns every
+ * workspace and precision-converted copy it makes (all allocated here, once;
+ * chfsi_workspace_bytes() reports the size).  stream: hipStream_t or NULL.
+ * Errors: CHFSI_ERR_ARG (inconsistent sizes/kinds/params), CHFSI_ERR_NOMEM,
+ * CHFSI_ERR_DEVICE.
+ */
+chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_operator* B,
+                          const double* d_inv, const chfsi_params* params, void* stream);
+
+/* Device bytes chfsi_create would allocate for these arguments (0 on invalid input). */
+size_t chfsi_workspace_bytes(const chfsi_operator* A, const chfsi_operator* B,
+                             const chfsi_params* params);
+
+/*
+ * One Chebyshev filter pass, stream-ordered and asynchronous.
+ * method CHFSI (Algorithm 2): Yp = C_p(D^{-1} A) X; ritz and resid ignored.
+ * method RCHFSI (Algorithm 3): inputs X (Ritz vectors), ritz (host, b Ritz
+ *   values Lambda^(i)) and resid (device, Y = A X - B X Lambda^(i)); output
+ *   Yp = D^{-1} R_Y + X Lambda_Y after `degree` steps of the residual
+ *   recurrence (eq. rChFSIrecurrenceMP), computed in the context's
+ *   filter precision.
+ * X, resid: device, n x b (ld >= n).  Yp: device, n x b; may alias X.
+ * lmin, lmax, lT: the filter bounds (Section 2.1); lmin < lT < lmax.
+ * degree: p >= 1 (0 means the context's degree).
+ */
+chfsi_status chfsi_filter(chfsi_ctx* ctx, const double* X, int64_t ldx, const double* ritz,
+                          const double* resid, int64_t ldr, double* Yp, int64_t ldy, double lmin,
+                          double lmax, double lT, int32_t degree);
+
+/*
+ * Rayleigh-Ritz on a filtered block (Algorithm 1, steps 2-3) and residuals.
+ * Solves (Y^T A Y) E = (Y^T B Y) E Lambda through the Cholesky factor of the
+ * column-scaled Gram matrix (CholQR) and a Jacobi eigensolver, then writes
+ * X = Y E (B-orthonormal Ritz vectors, ascending Ritz values), R = A X - B X
+ * Lambda and r_j = ||R_j||_2.  Y, X, R: device n x b; X must not alias Y.
+ * ritz, resnorm: host, length b.  Synchronises the stream once.
+ * Errors: CHFSI_ERR_NOT_SPD if the Gram matrix is not positive definite even
+ * after column scaling and a diagonal shift; CHFSI_ERR_NUMERIC on NaN/Inf.
+ */
+chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* ctx, const double* Y, int64_t ldy, double* X,
+                                 int64_t ldx, double* R, int64_t ldr, double* ritz,
+                                 double* resnorm);
+
+/*
+ * Full eigensolve (Algorithm 1 with the context's filter).  X (device, n x b,
+ * ld >= n): on entry the start block (or overwritten with N(0,1) values when
+ * params.init_random), on exit the Ritz vectors.  evals, resnorms: host,
+ * length b (ascending Ritz values and their residual norms).  rep: optional.
+ * Returns CHFSI_OK on convergence, CHFSI_ERR_NOCONV after max_iter passes
+ * (outputs hold the last pairs, as LAPACK's INFO > 0), other errors as above.
+ */
+chfsi_status chfsi_solve(chfsi_ctx* ctx, double* X, int64_t ldx, double* evals, double* resnorms,
+                         chfsi_report* rep);
+
+/*
+ * Profiling (params.profile = 1): total duration (ms, HIP events recorded on
+ * the context's stream immediately around each launch) and count of the
+ * filter's operator-product kernels -- the GEMM or stencil kernel of every
+ * recurrence step, without the split-K reduction -- since the previous call.
+ * Synchronises the stream.  Returns CHFSI_ERR_ARG when profiling is off.
+ */
+chfsi_status chfsi_filter_kernel_time(chfsi_ctx* ctx, double* total_ms, int32_t* launches);
+
+/* Release the context and everything it owns (borrowed arrays untouched). */
+void chfsi_destroy(chfsi_ctx* ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* chfsi_last_error(void);
+
+/* Library version string. */
+const char* chfsi_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of eigensolves on one GPU.
+ *
+ * A server owns a scheduler thread and up to `slots` concurrent solves, each
+ * on its own HIP stream.  Requests that arrive while others run are admitted
+ * as soon as a slot is free and the request's workspace (chfsi_workspace_bytes)
+ * fits in the device-memory budget; their kernels then overlap on the device.
+ * Requests of one sequence (same seq_id) run in submission order, and the
+ * server keeps the sequence's last Ritz vectors on the device to warm-start
+ * the next one (the evolving-matrix setting of the paper's introduction).
+ * Every request runs exactly the same kernels with the same launch shapes
+ * whether it runs alone or mixed with others, so results are bitwise equal.
+ * ------------------------------------------------------------------------- */
+typedef struct chfsi_server chfsi_server;
+
+typedef struct {
+  int32_t slots;            /* concurrent solves (>= 1) */
+  int32_t queue_capacity;   /* pending requests before chfsi_submit returns BUSY */
+  size_t memory_budget;     /* device bytes for workspaces; 0 = 90% of free memory */
+} chfsi_server_config;
+
+typedef struct {
+  chfsi_operator A;         /* borrowed device arrays: must stay valid until completion */
+  chfsi_operator B;         /* kind CHFSI_OP_IDENTITY for a standard problem */
+  const double* d_inv;      /* device length n, or NULL */
+  chfsi_params params;
+  int64_t seq_id;           /* sequence id for warm starts; < 0: independent request */
+  const double* X0;         /* device n x b start block (ld n) when the sequence has none;
+                               NULL: random start from params.seed */
+  double* X_out;            /* optional device n x b (ld n) output of the Ritz vectors */
+} chfsi_request;
+
+typedef struct {
+  chfsi_status status;
+  int32_t iterations;
+  double max_residual;
+  double submit_ms, start_ms, finish_ms;   /* server-clock timestamps */
+  int64_t n, block;
+  double* evals;            /* host array of `block` Ritz values, owned by the result */
+  double* resnorms;         /* host array of `block` residual norms, owned by the result */
+} chfsi_result;
+
+chfsi_status chfsi_server_create(chfsi_server** out, const chfsi_server_config* cfg);
+/* Thread-safe and non-blocking: enqueue a request, return its ticket. */
+chfsi_status chfsi_submit(chfsi_server* s, const chfsi_request* req, uint64_t* ticket);
+/* Block until the request finishes (timeout_ms < 0: forever).  On success the
+ * result is moved into *res (free it with chfsi_result_free). */
+chfsi_status chfsi_wait(chfsi_server* s, uint64_t ticket, int32_t timeout_ms, chfsi_result* res);
+/* Cancel a pending request (a running one finishes its current pass first). */
+chfsi_status chfsi_cancel(chfsi_server* s, uint64_t ticket);
+void chfsi_result_free(chfsi_result* res);
+/* Drain running requests and stop the scheduler. */
+void chfsi_server_destroy(chfsi_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHFSI_H_ */

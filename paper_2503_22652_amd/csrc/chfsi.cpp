@@ -1,0 +1,1113 @@
+// Host driver and C ABI of libchfsi (see include/chfsi.h).
+//
+// Implements Algorithm 1 (outer subspace iteration), Algorithm 2 (Chebyshev
+// filter) and Algorithm 3 (residual-based Chebyshev filter) of
+// arXiv 2503.22652 on one GPU.  Every numerical step runs in the HIP kernels of
+// this library; the host only sequences launches, computes the O(b)
+// recurrence scalars of the filter (Section 2.1, eq. ChFSIrecurrence; the
+// diagonal recurrence eq. ChFSIrecurrenceEigval) and reads back b Ritz values
+// and residual norms once per outer iteration.
+#include "../../include/chfsi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "stencil_api.h"
+
+using namespace chfsi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+#define CK(expr)                                                                        \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, __LINE__); \
+      return CHFSI_ERR_DEVICE;                                                          \
+    }                                                                                   \
+  } while (0)
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+size_t plan_bytes(int64_t M, int64_t N, int64_t K) {
+  int cfg, splits;
+  gemm_plan<T>(M, N, K, 1, &cfg, &splits);
+  return splits > 1 ? size_t(splits) * size_t(M) * size_t(N) * sizeof(T) : 0;
+}
+
+bool is_identity(const chfsi_operator* op) { return op == nullptr || op->kind == CHFSI_OP_IDENTITY; }
+
+}  // namespace
+
+struct chfsi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  chfsi_operator A{};
+  chfsi_operator B{};
+  bool B_identity = true;
+  const double* dinv = nullptr;
+  chfsi_params prm{};
+  int64_t n = 0, b = 0;
+
+  std::vector<void*> allocs;  // everything owned
+  size_t bytes = 0;
+
+  // filter precision copies / buffers
+  float* A32 = nullptr;
+  float* dinv32 = nullptr;
+  float *f32_a = nullptr, *f32_b = nullptr, *f32_c = nullptr;     // RX, RY, Y copy (n x b)
+  double *f64_a = nullptr, *f64_b = nullptr;                        // RX, RY (FP64 filter)
+  void *bf_a = nullptr, *bf_b = nullptr, *bf_c = nullptr;           // BF16 stencil filter blocks
+  float* coef32 = nullptr;        // per-step column coefficients, (p-1) x b
+  double* coef64 = nullptr;
+  double* lamY = nullptr;         // final Lambda_Y (device, b)
+  std::vector<float> h_coef32;
+  std::vector<double> h_coef64;
+  int coef_cap = 0;               // steps the coefficient tables hold
+
+  // Rayleigh-Ritz buffers
+  double *Yw = nullptr, *Xw = nullptr, *AY = nullptr, *BY = nullptr, *R = nullptr;
+  double *Ga = nullptr, *Gb = nullptr, *Gs = nullptr, *Linv = nullptr, *Tmp = nullptr;
+  double *Hp = nullptr, *E = nullptr, *T = nullptr, *TL = nullptr;
+  double *svec = nullptr, *w = nullptr, *norms = nullptr;
+  int* dflags = nullptr;          // [0] potrf info, [1] bad diag, [2] non-finite
+  Workspace ws;
+  Workspace ws_eig;
+
+  // pinned host staging
+  double* h_w = nullptr;
+  double* h_norms = nullptr;
+  int* h_flags = nullptr;
+  void* h_stage = nullptr;
+  size_t h_stage_bytes = 0;
+
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_stage = nullptr;   // last copy out of h_stage (reuse waits on it)
+  int last_sweeps = 0;
+  int flags = 0;
+  const std::atomic<int>* cancel = nullptr;
+  // profiling: event pairs around the filter's operator-product kernels
+  std::vector<hipEvent_t> pev;
+  int pused = 0;
+  double pacc_ms = 0.0;
+  int pacc_n = 0;
+};
+
+void chfsi::ctx_set_cancel_flag(chfsi_ctx* c, const std::atomic<int>* flag) { c->cancel = flag; }
+
+namespace {
+
+chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
+                          const chfsi_params* p) {
+  if (!A || !p) {
+    set_error("A and params must be non-null");
+    return CHFSI_ERR_ARG;
+  }
+  if (A->n <= 0) {
+    set_error("operator size must be positive");
+    return CHFSI_ERR_ARG;
+  }
+  if (A->kind == CHFSI_OP_DENSE) {
+    if (!A->dense || A->ld < A->n) {
+      set_error("dense A needs a device pointer and ld >= n");
+      return CHFSI_ERR_ARG;
+    }
+  } else if (A->kind == CHFSI_OP_STENCIL27) {
+    if (int64_t(A->nx) * A->ny * A->nz != A->n || A->nx < 3 || A->ny < 3 || A->nz < 3) {
+      set_error("stencil grid nx*ny*nz must equal n with every side >= 3");
+      return CHFSI_ERR_ARG;
+    }
+    if (A->field_mode < 0 || A->field_mode > 2 || (A->field_mode != 0 && !A->field)) {
+      set_error("stencil field_mode must be 0, 1 or 2 (1/2 need a field)");
+      return CHFSI_ERR_ARG;
+    }
+  } else {
+    set_error("A must be dense or a stencil operator");
+    return CHFSI_ERR_ARG;
+  }
+  if (!is_identity(B)) {
+    if (B->n != A->n) {
+      set_error("B must have the size of A");
+      return CHFSI_ERR_ARG;
+    }
+    if (B->kind == CHFSI_OP_DENSE && (!B->dense || B->ld < B->n)) {
+      set_error("dense B needs a device pointer and ld >= n");
+      return CHFSI_ERR_ARG;
+    }
+    if (B->kind == CHFSI_OP_STENCIL27 &&
+        (B->nx != A->nx || B->ny != A->ny || B->nz != A->nz || B->field_mode != 0)) {
+      set_error("stencil B must share A's grid and carry no field");
+      return CHFSI_ERR_ARG;
+    }
+    if (B->kind != CHFSI_OP_DENSE && B->kind != CHFSI_OP_STENCIL27) {
+      set_error("unsupported B kind");
+      return CHFSI_ERR_ARG;
+    }
+  }
+  if (p->block <= 0 || p->n_wanted <= 0 || p->n_wanted > p->block || p->block > A->n) {
+    set_error("need 0 < n_wanted <= block <= n");
+    return CHFSI_ERR_ARG;
+  }
+  if (p->degree < 1 || p->degree > 1000) {
+    set_error("degree must be in [1, 1000]");
+    return CHFSI_ERR_ARG;
+  }
+  if (p->method != CHFSI_METHOD_CHFSI && p->method != CHFSI_METHOD_RCHFSI) {
+    set_error("unknown method");
+    return CHFSI_ERR_ARG;
+  }
+  if (p->filter_prec < CHFSI_PREC_FP64 || p->filter_prec > CHFSI_PREC_BF16) {
+    set_error("unknown filter precision");
+    return CHFSI_ERR_ARG;
+  }
+  if (p->filter_prec == CHFSI_PREC_BF16 && A->kind != CHFSI_OP_STENCIL27) {
+    set_error("BF16 filter storage is implemented for stencil operators only");
+    return CHFSI_ERR_ARG;
+  }
+  if (p->filter_prec == CHFSI_PREC_BF16 && p->method != CHFSI_METHOD_RCHFSI) {
+    set_error("BF16 filter storage is implemented for the residual filter only");
+    return CHFSI_ERR_ARG;
+  }
+  return CHFSI_OK;
+}
+
+struct SizePlan {
+  size_t total = 0;
+  size_t a32 = 0, f32blk = 0, f64blk = 0, bfblk = 0, coef = 0;
+  size_t blk = 0, bb = 0, ws = 0, ws_eig = 0;
+};
+
+SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
+  SizePlan s;
+  const int64_t n = A->n, b = p->block;
+  const bool dense = A->kind == CHFSI_OP_DENSE;
+  s.blk = size_t(n) * b * sizeof(double);
+  s.bb = size_t(b) * b * sizeof(double);
+  if (p->filter_prec == CHFSI_PREC_FP32) {
+    s.f32blk = size_t(n) * b * sizeof(float);
+    if (dense) s.a32 = size_t(n) * n * sizeof(float) + size_t(n) * sizeof(float);
+  } else if (p->filter_prec == CHFSI_PREC_FP64) {
+    s.f64blk = s.blk;
+  } else {
+    s.bfblk = size_t(n) * b * 2;
+  }
+  s.coef = size_t(p->degree + 1) * b * sizeof(double);
+  size_t ws = 0;
+  if (dense) {
+    if (p->filter_prec == CHFSI_PREC_FP32)
+      ws = std::max(ws, plan_bytes<float>(n, b, n));
+    ws = std::max(ws, plan_bytes<double>(n, b, n));
+  }
+  ws = std::max(ws, plan_bytes<double>(b, b, n));
+  ws = std::max(ws, plan_bytes<double>(n, b, b));
+  ws = std::max(ws, plan_bytes<double>(b, b, b));
+  s.ws = ws + 256;
+  s.ws_eig = syev_workspace_bytes(b) + 256;
+  const bool Bid = is_identity(B);
+  // filter blocks: FP32 3 blocks, FP64 2 blocks, BF16 3 blocks
+  size_t filt = 3 * s.f32blk + 2 * s.f64blk + 3 * s.bfblk;
+  // RR: Yw, Xw, AY, R (+ BY when B != I)
+  size_t rr = (Bid ? 4 : 5) * s.blk;
+  s.total = s.a32 + filt + 2 * s.coef + rr + 10 * s.bb + 4 * b * sizeof(double) + 64 + s.ws +
+            s.ws_eig;
+  return s;
+}
+
+template <typename T>
+T* ctx_alloc(chfsi_ctx* c, size_t bytes, chfsi_status* st) {
+  if (bytes == 0) return nullptr;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, (bytes + 255) / 256 * 256);
+  if (e != hipSuccess) {
+    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    *st = CHFSI_ERR_NOMEM;
+    return nullptr;
+  }
+  c->allocs.push_back(p);
+  c->bytes += bytes;
+  return static_cast<T*>(p);
+}
+
+// y = Op x for an n x b FP64 block
+chfsi_status apply_op64(chfsi_ctx* c, const chfsi_operator* op, const double* X, int64_t ldx,
+                        double* Y, int64_t ldy, int64_t b) {
+  if (op->kind == CHFSI_OP_DENSE) {
+    GemmDesc<double> g;
+    g.M = c->n;
+    g.N = b;
+    g.K = c->n;
+    g.A = op->dense;      // symmetric: A(m,k) = dense[k + m*ld]
+    g.sak = 1;
+    g.sam = op->ld;
+    g.B = X;
+    g.sbk = 1;
+    g.sbn = ldx;
+    g.C = Y;
+    g.ldc = ldy;
+    CK(gemm<double>(g, c->stream, c->ws));
+    return CHFSI_OK;
+  }
+  if (op->kind == CHFSI_OP_STENCIL27) {
+    CK(stencil_apply_f64(*op, X, ldx, Y, ldy, b, c->stream));
+    return CHFSI_OK;
+  }
+  set_error("unsupported operator kind");
+  return CHFSI_ERR_ARG;
+}
+
+// Scalars of the filter (Algorithm 2/3, first line)
+struct FilterScalars {
+  double e, c, sigma1;
+};
+
+FilterScalars filter_scalars(double lmin, double lmax, double lT) {
+  FilterScalars f;
+  f.e = (lmax - lT) / 2.0;
+  f.c = (lmax + lT) / 2.0;
+  f.sigma1 = f.e / (lmin - f.c);
+  return f;
+}
+
+// Resolve the recorded event pairs into the running totals (synchronising).
+hipError_t prof_flush(chfsi_ctx* c) {
+  for (int i = 0; i + 1 < c->pused; i += 2) {
+    hipError_t e = hipEventSynchronize(c->pev[i + 1]);
+    if (e != hipSuccess) return e;
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, c->pev[i], c->pev[i + 1]);
+    if (e != hipSuccess) return e;
+    c->pacc_ms += ms;
+    c->pacc_n += 1;
+  }
+  c->pused = 0;
+  return hipSuccess;
+}
+
+// Next (begin, end) event pair, or nulls when profiling is off.
+hipError_t prof_pair(chfsi_ctx* c, hipEvent_t* b, hipEvent_t* e) {
+  *b = *e = nullptr;
+  if (!c->prm.profile || c->pev.empty()) return hipSuccess;
+  if (c->pused + 2 > int(c->pev.size())) {
+    hipError_t err = prof_flush(c);
+    if (err != hipSuccess) return err;
+  }
+  *b = c->pev[c->pused];
+  *e = c->pev[c->pused + 1];
+  c->pused += 2;
+  return hipSuccess;
+}
+
+chfsi_status ensure_coef(chfsi_ctx* c, int p) {
+  if (p <= c->coef_cap) return CHFSI_OK;
+  set_error("degree %d exceeds the context's degree %d", p, c->coef_cap);
+  return CHFSI_ERR_ARG;
+}
+
+// Algorithm 3 with the context's filter precision.
+chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const double* ritz,
+                           const double* resid, int64_t ldr, double* Yp, int64_t ldy, double lmin,
+                           double lmax, double lT, int p, double* flops) {
+  const int64_t n = c->n, b = c->b;
+  chfsi_status st = ensure_coef(c, p);
+  if (st != CHFSI_OK) return st;
+  const FilterScalars f = filter_scalars(lmin, lmax, lT);
+  const double gamma = 2.0 / f.sigma1;
+  // Lambda recurrence (eq. ChFSIrecurrenceEigval) on the host in FP64; the
+  // per-step forcing coefficients Lambda_Y (before the update) go to the device.
+  std::vector<double> LX(b, 1.0), LY(b), LN(b);
+  for (int64_t j = 0; j < b; ++j) LY[j] = (f.sigma1 / f.e) * (ritz[j] - f.c);
+  struct Step {
+    double a, bb, cc;
+  };
+  std::vector<Step> steps;
+  double sigma = f.sigma1;
+  for (int k = 2; k <= p; ++k) {
+    const double sigma2 = 1.0 / (gamma - sigma);
+    const double a = 2.0 * sigma2 / f.e;
+    steps.push_back({a, -a * f.c, -sigma * sigma2});
+    for (int64_t j = 0; j < b; ++j) {
+      c->h_coef64[(k - 2) * b + j] = LY[j];
+      c->h_coef32[(k - 2) * b + j] = float(LY[j]);
+      LN[j] = a * LY[j] * ritz[j] - a * f.c * LY[j] - sigma * sigma2 * LX[j];
+    }
+    std::swap(LX, LY);
+    std::swap(LY, LN);
+    sigma = sigma2;
+  }
+  // final Lambda_Y for the reconstruction; the staging buffer may still feed
+  // an earlier asynchronous copy
+  CK(hipEventSynchronize(c->ev_stage));
+  double* h_lam = reinterpret_cast<double*>(c->h_stage);
+  std::memcpy(h_lam, LY.data(), b * sizeof(double));
+  CK(hipMemcpyAsync(c->lamY, h_lam, b * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const int nsteps = p - 1;
+  const double scale1 = f.sigma1 / f.e;
+  double fl = 0.0;
+  const bool dense = c->A.kind == CHFSI_OP_DENSE;
+  if (c->prm.filter_prec == CHFSI_PREC_FP32) {
+    if (nsteps > 0) {
+      float* hs = reinterpret_cast<float*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
+      std::memcpy(hs, c->h_coef32.data(), size_t(nsteps) * b * sizeof(float));
+      CK(hipMemcpyAsync(c->coef32, hs, size_t(nsteps) * b * sizeof(float), hipMemcpyHostToDevice,
+                        c->stream));
+    }
+    float* RX = c->f32_a;
+    float* RY = c->f32_b;
+    float* Yc = c->f32_c;
+    CK(hipEventRecord(c->ev_stage, c->stream));
+    CK(rchfsi_init_f32(resid, ldr, n, b, scale1, RY, RX, Yc, n, c->stream));
+    for (int s = 0; s < nsteps; ++s) {
+      const Step& sp = steps[s];
+      if (dense) {
+        GemmDesc<float> g;
+        g.M = n;
+        g.N = b;
+        g.K = n;
+        g.A = c->A32;
+        g.sak = 1;
+        g.sam = n;
+        g.B = RY;
+        g.sbk = 1;
+        g.sbn = n;
+        g.kscale = c->dinv32;
+        g.C = RX;
+        g.ldc = n;
+        g.epi.alpha = float(sp.a);
+        g.epi.beta = float(sp.bb);
+        g.epi.C1 = RY;
+        g.epi.ldc1 = n;
+        g.epi.gamma = float(sp.cc);
+        g.epi.C2 = RX;
+        g.epi.ldc2 = n;
+        g.epi.delta = float(sp.a);
+        g.epi.colscale3 = c->coef32 + int64_t(s) * b;
+        g.epi.C3 = Yc;
+        g.epi.ldc3 = n;
+        CK(prof_pair(c, &g.ev_begin, &g.ev_end));
+        CK(gemm<float>(g, c->stream, c->ws));
+        fl += 2.0 * double(n) * double(n) * double(b);
+      } else {
+        StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
+        {
+          hipEvent_t e0, e1;
+          CK(prof_pair(c, &e0, &e1));
+          if (e0) CK(hipEventRecord(e0, c->stream));
+          CK(stencil_rchfsi_step_f32(c->A, c->dinv32, RY, RX, Yc, c->coef32 + int64_t(s) * b, ss, b,
+                                     c->stream));
+          if (e1) CK(hipEventRecord(e1, c->stream));
+        }
+        fl += stencil_flops(c->A) * double(n) * double(b);
+      }
+      std::swap(RX, RY);
+    }
+    CK(rchfsi_reconstruct_f32(RY, n, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
+  } else if (c->prm.filter_prec == CHFSI_PREC_FP64) {
+    if (nsteps > 0) {
+      double* hs = reinterpret_cast<double*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
+      std::memcpy(hs, c->h_coef64.data(), size_t(nsteps) * b * sizeof(double));
+      CK(hipMemcpyAsync(c->coef64, hs, size_t(nsteps) * b * sizeof(double),
+                        hipMemcpyHostToDevice, c->stream));
+    }
+    double* RX = c->f64_a;
+    double* RY = c->f64_b;
+    CK(hipEventRecord(c->ev_stage, c->stream));
+    CK(rchfsi_init_f64(resid, ldr, n, b, scale1, RY, RX, n, c->stream));
+    for (int s = 0; s < nsteps; ++s) {
+      const Step& sp = steps[s];
+      if (dense) {
+        GemmDesc<double> g;
+        g.M = n;
+        g.N = b;
+        g.K = n;
+        g.A = c->A.dense;
+        g.sak = 1;
+        g.sam = c->A.ld;
+        g.B = RY;
+        g.sbk = 1;
+        g.sbn = n;
+        g.kscale = c->dinv;
+        g.C = RX;
+        g.ldc = n;
+        g.epi.alpha = sp.a;
+        g.epi.beta = sp.bb;
+        g.epi.C1 = RY;
+        g.epi.ldc1 = n;
+        g.epi.gamma = sp.cc;
+        g.epi.C2 = RX;
+        g.epi.ldc2 = n;
+        g.epi.delta = sp.a;
+        g.epi.colscale3 = c->coef64 + int64_t(s) * b;
+        g.epi.C3 = resid;
+        g.epi.ldc3 = ldr;
+        CK(prof_pair(c, &g.ev_begin, &g.ev_end));
+        CK(gemm<double>(g, c->stream, c->ws));
+        fl += 2.0 * double(n) * double(n) * double(b);
+      } else {
+        StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
+        {
+          hipEvent_t e0, e1;
+          CK(prof_pair(c, &e0, &e1));
+          if (e0) CK(hipEventRecord(e0, c->stream));
+          CK(stencil_rchfsi_step_f64(c->A, c->dinv, RY, RX, resid, ldr, c->coef64 + int64_t(s) * b,
+                                     ss, b, c->stream));
+          if (e1) CK(hipEventRecord(e1, c->stream));
+        }
+        fl += stencil_flops(c->A) * double(n) * double(b);
+      }
+      std::swap(RX, RY);
+    }
+    CK(rchfsi_reconstruct_f64(RY, n, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
+  } else {
+    // BF16-stored blocks, FP32 arithmetic (stencil operators)
+    if (nsteps > 0) {
+      float* hs = reinterpret_cast<float*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
+      std::memcpy(hs, c->h_coef32.data(), size_t(nsteps) * b * sizeof(float));
+      CK(hipMemcpyAsync(c->coef32, hs, size_t(nsteps) * b * sizeof(float), hipMemcpyHostToDevice,
+                        c->stream));
+    }
+    void* RX = c->bf_a;
+    void* RY = c->bf_b;
+    void* Yc = c->bf_c;
+    CK(hipEventRecord(c->ev_stage, c->stream));
+    CK(rchfsi_init_bf16(resid, ldr, n, b, scale1, RY, RX, Yc, c->stream));
+    for (int s = 0; s < nsteps; ++s) {
+      const Step& sp = steps[s];
+      StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
+      {
+        hipEvent_t e0, e1;
+        CK(prof_pair(c, &e0, &e1));
+        if (e0) CK(hipEventRecord(e0, c->stream));
+        CK(stencil_rchfsi_step_bf16(c->A, c->dinv32, RY, RX, Yc, c->coef32 + int64_t(s) * b, ss, b,
+                                    c->stream));
+        if (e1) CK(hipEventRecord(e1, c->stream));
+      }
+      fl += stencil_flops(c->A) * double(n) * double(b);
+      std::swap(RX, RY);
+    }
+    CK(rchfsi_reconstruct_bf16(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
+  }
+  if (flops) *flops += fl;
+  return CHFSI_OK;
+}
+
+// Algorithm 2 with H = D^{-1} A.
+chfsi_status filter_chfsi(chfsi_ctx* c, const double* X, int64_t ldx, double* Yp, int64_t ldy,
+                          double lmin, double lmax, double lT, int p, double* flops) {
+  const int64_t n = c->n, b = c->b;
+  const FilterScalars f = filter_scalars(lmin, lmax, lT);
+  const double gamma = 2.0 / f.sigma1;
+  const bool dense = c->A.kind == CHFSI_OP_DENSE;
+  double fl = 0.0;
+  if (c->prm.filter_prec == CHFSI_PREC_FP64) {
+    // Y1 = (sigma1/e)(D^{-1} A X - c X)
+    double* cur = c->f64_a;
+    double* nxt = c->f64_b;
+    const double* prev = X;
+    int64_t ldprev = ldx;
+    auto step = [&](const double* src, int64_t ldsrc, double* dst, double alpha, double beta,
+                    const double* Cprev, int64_t ldp, double gam) -> chfsi_status {
+      if (dense) {
+        GemmDesc<double> g;
+        g.M = n;
+        g.N = b;
+        g.K = n;
+        g.A = c->A.dense;
+        g.sak = 1;
+        g.sam = c->A.ld;
+        g.B = src;
+        g.sbk = 1;
+        g.sbn = ldsrc;
+        g.C = dst;
+        g.ldc = n;
+        g.epi.alpha = alpha;
+        g.epi.rowscale = c->dinv;
+        g.epi.beta = beta;
+        g.epi.C1 = src;
+        g.epi.ldc1 = ldsrc;
+        if (Cprev) {
+          g.epi.gamma = gam;
+          g.epi.C2 = Cprev;
+          g.epi.ldc2 = ldp;
+        }
+        CK(prof_pair(c, &g.ev_begin, &g.ev_end));
+        CK(gemm<double>(g, c->stream, c->ws));
+        fl += 2.0 * double(n) * double(n) * double(b);
+      } else {
+        StencilStep ss{alpha, beta, gam, 0.0};
+        {
+          hipEvent_t e0, e1;
+          CK(prof_pair(c, &e0, &e1));
+          if (e0) CK(hipEventRecord(e0, c->stream));
+          CK(stencil_chfsi_step_f64(c->A, c->dinv, src, ldsrc, Cprev, ldp, dst, ss, b, c->stream));
+          if (e1) CK(hipEventRecord(e1, c->stream));
+        }
+        fl += stencil_flops(c->A) * double(n) * double(b);
+      }
+      return CHFSI_OK;
+    };
+    chfsi_status st = step(X, ldx, cur, f.sigma1 / f.e, -f.sigma1 * f.c / f.e, nullptr, 0, 0.0);
+    if (st != CHFSI_OK) return st;
+    double sigma = f.sigma1;
+    for (int k = 2; k <= p; ++k) {
+      const double sigma2 = 1.0 / (gamma - sigma);
+      const double a = 2.0 * sigma2 / f.e;
+      // new = a H cur - a c cur - sigma sigma2 prev; write into prev's storage
+      // unless prev is the caller's X
+      double* dst = (prev == X) ? nxt : const_cast<double*>(prev);
+      st = step(cur, n, dst, a, -a * f.c, prev, ldprev, -sigma * sigma2);
+      if (st != CHFSI_OK) return st;
+      prev = cur;
+      ldprev = n;
+      cur = dst;
+      sigma = sigma2;
+    }
+    CK(copy_block(cur, n, Yp, ldy, n, b, c->stream));
+  } else if (c->prm.filter_prec == CHFSI_PREC_FP32 && dense) {
+    float* Xc = c->f32_c;
+    float* cur = c->f32_a;
+    float* nxt = c->f32_b;
+    CK(convert_f64_f32(X, ldx, Xc, n, n, b, c->stream));
+    const float* prev = Xc;
+    auto step = [&](const float* src, float* dst, double alpha, double beta, const float* Cprev,
+                    double gam) -> chfsi_status {
+      GemmDesc<float> g;
+      g.M = n;
+      g.N = b;
+      g.K = n;
+      g.A = c->A32;
+      g.sak = 1;
+      g.sam = n;
+      g.B = src;
+      g.sbk = 1;
+      g.sbn = n;
+      g.C = dst;
+      g.ldc = n;
+      g.epi.alpha = float(alpha);
+      g.epi.rowscale = c->dinv32;
+      g.epi.beta = float(beta);
+      g.epi.C1 = src;
+      g.epi.ldc1 = n;
+      if (Cprev) {
+        g.epi.gamma = float(gam);
+        g.epi.C2 = Cprev;
+        g.epi.ldc2 = n;
+      }
+      CK(prof_pair(c, &g.ev_begin, &g.ev_end));
+      CK(gemm<float>(g, c->stream, c->ws));
+      fl += 2.0 * double(n) * double(n) * double(b);
+      return CHFSI_OK;
+    };
+    chfsi_status st = step(Xc, cur, f.sigma1 / f.e, -f.sigma1 * f.c / f.e, nullptr, 0.0);
+    if (st != CHFSI_OK) return st;
+    double sigma = f.sigma1;
+    for (int k = 2; k <= p; ++k) {
+      const double sigma2 = 1.0 / (gamma - sigma);
+      const double a = 2.0 * sigma2 / f.e;
+      float* dst = (prev == Xc) ? nxt : const_cast<float*>(prev);
+      st = step(cur, dst, a, -a * f.c, prev, -sigma * sigma2);
+      if (st != CHFSI_OK) return st;
+      prev = cur;
+      cur = dst;
+      sigma = sigma2;
+    }
+    CK(convert_f32_f64(cur, n, Yp, ldy, n, b, c->stream));
+  } else {
+    set_error("the plain Chebyshev filter supports FP64 (any operator) and FP32 (dense)");
+    return CHFSI_ERR_ARG;
+  }
+  if (flops) *flops += fl;
+  return CHFSI_OK;
+}
+
+// Rayleigh-Ritz + residuals (see chfsi_rayleigh_ritz)
+chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X, int64_t ldx,
+                           double* R, int64_t ldr, double* ritz, double* resnorm) {
+  const int64_t n = c->n, b = c->b;
+  hipStream_t st = c->stream;
+  chfsi_status s;
+  CK(fill_zero(c->dflags, 4 * sizeof(int), st));
+  // AY = A Y, BY = B Y
+  if ((s = apply_op64(c, &c->A, Y, ldy, c->AY, n, b)) != CHFSI_OK) return s;
+  const double* BY = Y;
+  int64_t ldby = ldy;
+  if (!c->B_identity) {
+    if ((s = apply_op64(c, &c->B, Y, ldy, c->BY, n, b)) != CHFSI_OK) return s;
+    BY = c->BY;
+    ldby = n;
+  }
+  // Gram matrices Ga = Y^T A Y, Gb = Y^T B Y (K = n)
+  auto gram = [&](const double* W, int64_t ldw, double* G) -> chfsi_status {
+    GemmDesc<double> g;
+    g.M = b;
+    g.N = b;
+    g.K = n;
+    g.A = Y;
+    g.sak = 1;
+    g.sam = ldy;
+    g.B = W;
+    g.sbk = 1;
+    g.sbn = ldw;
+    g.C = G;
+    g.ldc = b;
+    CK(gemm<double>(g, st, c->ws));
+    CK(symmetrize(G, b, b, st));
+    return CHFSI_OK;
+  };
+  if ((s = gram(c->AY, n, c->Ga)) != CHFSI_OK) return s;
+  if ((s = gram(BY, ldby, c->Gb)) != CHFSI_OK) return s;
+  // column scaling s = diag(Gb)^{-1/2}; Cholesky of the scaled Gram matrix
+  CK(scale_gram(c->Gb, b, b, c->Gs, b, c->svec, c->dflags + 1, st));
+  CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws));
+  CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (c->h_flags[0] != 0 || c->h_flags[1] != 0) {
+    set_error("Gram matrix Y^T B Y is not positive definite (pivot %d, bad diagonal %d)",
+              c->h_flags[0], c->h_flags[1]);
+    return CHFSI_ERR_NOT_SPD;
+  }
+  // Linv = L^{-1}
+  CK(set_identity(c->Linv, b, b, st));
+  CK(trsm_lower_left(c->Gs, b, c->Linv, b, b, b, st, c->ws));
+  // Hp = Linv (s Ga s) Linv^T
+  CK(scale_sym(c->Ga, b, b, c->svec, c->Hp, b, st));
+  {
+    GemmDesc<double> g;   // Tmp = Linv * Hp(scaled Ga)
+    g.M = b;
+    g.N = b;
+    g.K = b;
+    g.A = c->Linv;
+    g.sam = 1;
+    g.sak = b;
+    g.B = c->Hp;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = c->Tmp;
+    g.ldc = b;
+    CK(gemm<double>(g, st, c->ws));
+    GemmDesc<double> h;   // Hp = Tmp * Linv^T
+    h.M = b;
+    h.N = b;
+    h.K = b;
+    h.A = c->Tmp;
+    h.sam = 1;
+    h.sak = b;
+    h.B = c->Linv;        // B(k,n) = Linv(n,k) = Linv[n + k*b]
+    h.sbn = 1;
+    h.sbk = b;
+    h.C = c->Hp;
+    h.ldc = b;
+    CK(gemm<double>(h, st, c->ws));
+  }
+  CK(symmetrize(c->Hp, b, b, st));
+  int sweeps = 0;
+  CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  c->last_sweeps = sweeps;
+  {
+    GemmDesc<double> g;   // T = diag(s) Linv^T E
+    g.M = b;
+    g.N = b;
+    g.K = b;
+    g.A = c->Linv;        // A(m,k) = Linv(k,m) = Linv[k + m*b]
+    g.sak = 1;
+    g.sam = b;
+    g.B = c->E;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = c->T;
+    g.ldc = b;
+    g.epi.rowscale = c->svec;
+    CK(gemm<double>(g, st, c->ws));
+  }
+  // X = Y T ; R = AY T - BY (T diag(w))
+  auto rotate = [&](const double* Src, int64_t lds, const double* Tm, double* Dst, int64_t ldd,
+                    double alpha, const double* accum) -> chfsi_status {
+    GemmDesc<double> g;
+    g.M = n;
+    g.N = b;
+    g.K = b;
+    g.A = Src;
+    g.sam = 1;
+    g.sak = lds;
+    g.B = Tm;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = Dst;
+    g.ldc = ldd;
+    g.epi.alpha = alpha;
+    if (accum) {
+      g.epi.beta = 1.0;
+      g.epi.C1 = accum;
+      g.epi.ldc1 = ldd;
+    }
+    CK(gemm<double>(g, st, c->ws));
+    return CHFSI_OK;
+  };
+  if ((s = rotate(Y, ldy, c->T, X, ldx, 1.0, nullptr)) != CHFSI_OK) return s;
+  if ((s = rotate(c->AY, n, c->T, R, ldr, 1.0, nullptr)) != CHFSI_OK) return s;
+  CK(copy_block(c->T, b, c->TL, b, b, b, st));
+  CK(scale_columns(c->TL, b, b, b, c->w, st));
+  if ((s = rotate(BY, ldby, c->TL, R, ldr, -1.0, R)) != CHFSI_OK) return s;
+  CK(column_norms(R, ldr, n, b, c->norms, st));
+  CK(check_finite(c->w, b, c->dflags + 2, st));
+  CK(check_finite(c->norms, b, c->dflags + 2, st));
+  CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(c->h_norms, c->norms, b * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (c->h_flags[2] != 0) {
+    set_error("non-finite Ritz value or residual norm");
+    return CHFSI_ERR_NUMERIC;
+  }
+  std::memcpy(ritz, c->h_w, b * sizeof(double));
+  std::memcpy(resnorm, c->h_norms, b * sizeof(double));
+  return CHFSI_OK;
+}
+
+void bounds_policy(const chfsi_params& p, const double* ritz, int64_t b, double* lmin,
+                   double* lmax, double* lT) {
+  *lmax = p.lambda_max;
+  const double e1 = ritz[0], eb = ritz[b - 1];
+  *lmin = std::isnan(p.lambda_min) ? e1 - 0.05 * (eb - e1) : p.lambda_min;
+  *lT = std::isnan(p.lambda_T) ? eb : p.lambda_T;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* chfsi_last_error(void) { return g_last_error.c_str(); }
+
+const char* chfsi_version(void) { return "libchfsi 0.1 (gfx950)"; }
+
+size_t chfsi_workspace_bytes(const chfsi_operator* A, const chfsi_operator* B,
+                             const chfsi_params* params) {
+  if (check_params(A, B, params) != CHFSI_OK) return 0;
+  return plan_sizes(A, B, params).total;
+}
+
+void chfsi_destroy(chfsi_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) hipFree(p);
+  if (c->h_w) hipHostFree(c->h_w);
+  if (c->h_norms) hipHostFree(c->h_norms);
+  if (c->h_flags) hipHostFree(c->h_flags);
+  if (c->h_stage) hipHostFree(c->h_stage);
+  for (auto& e : c->ev)
+    if (e) hipEventDestroy(e);
+  if (c->ev_stage) hipEventDestroy(c->ev_stage);
+  for (auto e : c->pev)
+    if (e) hipEventDestroy(e);
+  delete c;
+}
+
+chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_operator* B,
+                          const double* d_inv, const chfsi_params* params, void* stream) {
+  if (!out) {
+    set_error("out must be non-null");
+    return CHFSI_ERR_ARG;
+  }
+  *out = nullptr;
+  chfsi_status st = check_params(A, B, params);
+  if (st != CHFSI_OK) return st;
+  if (!(std::isfinite(params->lambda_max))) {
+    set_error("lambda_max must be finite");
+    return CHFSI_ERR_ARG;
+  }
+  chfsi_ctx* c = new chfsi_ctx();
+  c->stream = static_cast<hipStream_t>(stream);
+  hipGetDevice(&c->device);
+  c->A = *A;
+  c->B_identity = is_identity(B);
+  if (!c->B_identity) c->B = *B;
+  c->B.kind = c->B_identity ? CHFSI_OP_IDENTITY : B->kind;
+  c->dinv = d_inv;
+  c->prm = *params;
+  c->n = A->n;
+  c->b = params->block;
+  const int64_t n = c->n, b = c->b;
+  const SizePlan sp = plan_sizes(A, B, params);
+  st = CHFSI_OK;
+  const bool dense = A->kind == CHFSI_OP_DENSE;
+  if (params->filter_prec == CHFSI_PREC_FP32) {
+    if (dense) c->A32 = ctx_alloc<float>(c, size_t(n) * n * sizeof(float), &st);
+    c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+    c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
+    c->f32_b = ctx_alloc<float>(c, sp.f32blk, &st);
+    c->f32_c = ctx_alloc<float>(c, sp.f32blk, &st);
+  } else if (params->filter_prec == CHFSI_PREC_FP64) {
+    c->f64_a = ctx_alloc<double>(c, sp.f64blk, &st);
+    c->f64_b = ctx_alloc<double>(c, sp.f64blk, &st);
+  } else {
+    c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+    c->bf_a = ctx_alloc<char>(c, sp.bfblk, &st);
+    c->bf_b = ctx_alloc<char>(c, sp.bfblk, &st);
+    c->bf_c = ctx_alloc<char>(c, sp.bfblk, &st);
+  }
+  c->coef_cap = params->degree;
+  c->coef32 = ctx_alloc<float>(c, size_t(params->degree) * b * sizeof(float), &st);
+  c->coef64 = ctx_alloc<double>(c, size_t(params->degree) * b * sizeof(double), &st);
+  c->lamY = ctx_alloc<double>(c, b * sizeof(double), &st);
+  c->h_coef32.assign(size_t(params->degree) * b, 0.0f);
+  c->h_coef64.assign(size_t(params->degree) * b, 0.0);
+  c->Yw = ctx_alloc<double>(c, sp.blk, &st);
+  c->Xw = ctx_alloc<double>(c, sp.blk, &st);
+  c->AY = ctx_alloc<double>(c, sp.blk, &st);
+  c->R = ctx_alloc<double>(c, sp.blk, &st);
+  if (!c->B_identity) c->BY = ctx_alloc<double>(c, sp.blk, &st);
+  c->Ga = ctx_alloc<double>(c, sp.bb, &st);
+  c->Gb = ctx_alloc<double>(c, sp.bb, &st);
+  c->Gs = ctx_alloc<double>(c, sp.bb, &st);
+  c->Linv = ctx_alloc<double>(c, sp.bb, &st);
+  c->Tmp = ctx_alloc<double>(c, sp.bb, &st);
+  c->Hp = ctx_alloc<double>(c, sp.bb, &st);
+  c->E = ctx_alloc<double>(c, sp.bb, &st);
+  c->T = ctx_alloc<double>(c, sp.bb, &st);
+  c->TL = ctx_alloc<double>(c, sp.bb, &st);
+  c->svec = ctx_alloc<double>(c, b * sizeof(double), &st);
+  c->w = ctx_alloc<double>(c, b * sizeof(double), &st);
+  c->norms = ctx_alloc<double>(c, b * sizeof(double), &st);
+  c->dflags = ctx_alloc<int>(c, 64, &st);
+  c->ws.bytes = sp.ws;
+  c->ws.ptr = ctx_alloc<char>(c, sp.ws, &st);
+  c->ws_eig.bytes = sp.ws_eig;
+  c->ws_eig.ptr = ctx_alloc<char>(c, sp.ws_eig, &st);
+  if (st != CHFSI_OK) {
+    chfsi_destroy(c);
+    return st;
+  }
+  c->h_stage_bytes = b * sizeof(double) + size_t(params->degree) * b * sizeof(double) + 64;
+  if (hipHostMalloc(&c->h_w, b * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&c->h_norms, b * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_flags), 64) != hipSuccess ||
+      hipHostMalloc(&c->h_stage, c->h_stage_bytes) != hipSuccess) {
+    set_error("pinned host allocation failed");
+    chfsi_destroy(c);
+    return CHFSI_ERR_NOMEM;
+  }
+  if (hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(c->ev_stage, c->stream) != hipSuccess) {
+    set_error("hipEventCreate failed");
+    chfsi_destroy(c);
+    return CHFSI_ERR_DEVICE;
+  }
+  for (auto& e : c->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      set_error("hipEventCreate failed");
+      chfsi_destroy(c);
+      return CHFSI_ERR_DEVICE;
+    }
+  }
+  if (params->profile) {
+    c->pev.assign(size_t(8) * (params->degree + 1), nullptr);
+    for (auto& e : c->pev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        set_error("hipEventCreate failed");
+        chfsi_destroy(c);
+        return CHFSI_ERR_DEVICE;
+      }
+  }
+  // precision-converted operator copies (owned)
+  hipError_t e = hipSuccess;
+  if (c->A32) e = convert_f64_f32(A->dense, A->ld, c->A32, n, n, n, c->stream);
+  if (e == hipSuccess && c->dinv32) {
+    if (d_inv)
+      e = convert_f64_f32(d_inv, n, c->dinv32, n, n, 1, c->stream);
+    else
+      e = fill_ones_f32(c->dinv32, n, c->stream);
+  }
+  if (e == hipSuccess && A->kind == CHFSI_OP_STENCIL27) e = stencil_check(*A);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    set_error("context setup failed: %s", hipGetErrorString(e));
+    chfsi_destroy(c);
+    return CHFSI_ERR_DEVICE;
+  }
+  *out = c;
+  return CHFSI_OK;
+}
+
+chfsi_status chfsi_filter(chfsi_ctx* c, const double* X, int64_t ldx, const double* ritz,
+                          const double* resid, int64_t ldr, double* Yp, int64_t ldy, double lmin,
+                          double lmax, double lT, int32_t degree) {
+  if (!c || !X || !Yp) {
+    set_error("ctx, X and Yp must be non-null");
+    return CHFSI_ERR_ARG;
+  }
+  const int p = degree > 0 ? degree : c->prm.degree;
+  if (ldx < c->n || ldy < c->n) {
+    set_error("leading dimensions must be >= n");
+    return CHFSI_ERR_ARG;
+  }
+  if (!(lmin < lT && lT < lmax) || !std::isfinite(lmin) || !std::isfinite(lmax)) {
+    set_error("filter bounds must satisfy lmin < lT < lmax");
+    return CHFSI_ERR_ARG;
+  }
+  if (c->prm.method == CHFSI_METHOD_RCHFSI) {
+    if (!ritz || !resid || ldr < c->n) {
+      set_error("the residual filter needs ritz (host), resid (device) and ldr >= n");
+      return CHFSI_ERR_ARG;
+    }
+    if (p > c->coef_cap) {
+      set_error("degree %d exceeds the context's degree %d", p, c->coef_cap);
+      return CHFSI_ERR_ARG;
+    }
+    return filter_rchfsi(c, X, ldx, ritz, resid, ldr, Yp, ldy, lmin, lmax, lT, p, nullptr);
+  }
+  return filter_chfsi(c, X, ldx, Yp, ldy, lmin, lmax, lT, p, nullptr);
+}
+
+chfsi_status chfsi_filter_kernel_time(chfsi_ctx* c, double* total_ms, int32_t* launches) {
+  if (!c || !total_ms || !launches) {
+    set_error("null argument");
+    return CHFSI_ERR_ARG;
+  }
+  if (!c->prm.profile) {
+    set_error("profiling is off (params.profile = 0)");
+    return CHFSI_ERR_ARG;
+  }
+  CK(prof_flush(c));
+  *total_ms = c->pacc_ms;
+  *launches = c->pacc_n;
+  c->pacc_ms = 0.0;
+  c->pacc_n = 0;
+  return CHFSI_OK;
+}
+
+chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X,
+                                 int64_t ldx, double* R, int64_t ldr, double* ritz,
+                                 double* resnorm) {
+  if (!c || !Y || !X || !R || !ritz || !resnorm) {
+    set_error("null argument");
+    return CHFSI_ERR_ARG;
+  }
+  if (ldy < c->n || ldx < c->n || ldr < c->n) {
+    set_error("leading dimensions must be >= n");
+    return CHFSI_ERR_ARG;
+  }
+  if (X == Y) {
+    set_error("X must not alias Y");
+    return CHFSI_ERR_ARG;
+  }
+  return rayleigh_ritz(c, Y, ldy, X, ldx, R, ldr, ritz, resnorm);
+}
+
+chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, double* resnorms,
+                         chfsi_report* rep) {
+  if (!c || !X || !evals || !resnorms) {
+    set_error("null argument");
+    return CHFSI_ERR_ARG;
+  }
+  if (ldx < c->n) {
+    set_error("ldx must be >= n");
+    return CHFSI_ERR_ARG;
+  }
+  const int64_t n = c->n, b = c->b, nw = c->prm.n_wanted;
+  const double t0 = now_ms();
+  chfsi_report local{};
+  chfsi_report& r = rep ? *rep : local;
+  std::memset(&r, 0, sizeof(r));
+  if (c->prm.init_random) CK(fill_gaussian(X, ldx, n, b, c->prm.seed, c->stream));
+  std::vector<double> ritz(b), norms(b);
+  float ms = 0.0f;
+  CK(hipEventRecord(c->ev[2], c->stream));
+  chfsi_status st = rayleigh_ritz(c, X, ldx, c->Xw, n, c->R, n, ritz.data(), norms.data());
+  if (st != CHFSI_OK) return st;
+  CK(hipEventRecord(c->ev[3], c->stream));
+  CK(hipEventSynchronize(c->ev[3]));
+  CK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+  r.time_rr_ms += ms;
+  r.jacobi_sweeps += c->last_sweeps;
+  auto maxres = [&]() {
+    double m = 0.0;
+    for (int64_t j = 0; j < nw; ++j) m = std::max(m, norms[j]);
+    return m;
+  };
+  double mr = maxres();
+  r.history[0] = mr;
+  int it = 0;
+  for (; it < c->prm.max_iter && !(mr < c->prm.tol); ++it) {
+    if (c->cancel && c->cancel->load()) {
+      set_error("cancelled");
+      st = CHFSI_ERR_CANCELLED;
+      break;
+    }
+    double lmin, lmax, lT;
+    bounds_policy(c->prm, ritz.data(), b, &lmin, &lmax, &lT);
+    if (!(lmin < lT && lT < lmax)) {
+      set_error("filter bounds collapsed (lmin %.6g, lT %.6g, lmax %.6g): lambda_max too small?",
+                lmin, lT, lmax);
+      st = CHFSI_ERR_ARG;
+      break;
+    }
+    CK(hipEventRecord(c->ev[0], c->stream));
+    if (c->prm.method == CHFSI_METHOD_RCHFSI)
+      st = filter_rchfsi(c, c->Xw, n, ritz.data(), c->R, n, c->Yw, n, lmin, lmax, lT,
+                         c->prm.degree, &r.filter_flops);
+    else
+      st = filter_chfsi(c, c->Xw, n, c->Yw, n, lmin, lmax, lT, c->prm.degree, &r.filter_flops);
+    if (st != CHFSI_OK) break;
+    CK(hipEventRecord(c->ev[1], c->stream));
+    st = rayleigh_ritz(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(), norms.data());
+    if (st != CHFSI_OK) break;
+    CK(hipEventRecord(c->ev[3], c->stream));
+    CK(hipEventSynchronize(c->ev[3]));
+    CK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    r.time_filter_ms += ms;
+    CK(hipEventElapsedTime(&ms, c->ev[1], c->ev[3]));
+    r.time_rr_ms += ms;
+    r.jacobi_sweeps += c->last_sweeps;
+    if (c->prm.profile) {
+      CK(prof_flush(c));
+      r.kernel_ms += c->pacc_ms;
+      r.kernel_launches += c->pacc_n;
+      c->pacc_ms = 0.0;
+      c->pacc_n = 0;
+    }
+    mr = maxres();
+    if (it + 1 < CHFSI_MAX_HISTORY) r.history[it + 1] = mr;
+  }
+  r.iterations = it;
+  r.max_residual = mr;
+  r.converged = mr < c->prm.tol;
+  r.flags = c->flags;
+  if (st != CHFSI_OK && st != CHFSI_ERR_NOCONV) return st;
+  CK(copy_block(c->Xw, n, X, ldx, n, b, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  std::memcpy(evals, ritz.data(), b * sizeof(double));
+  std::memcpy(resnorms, norms.data(), b * sizeof(double));
+  r.time_total_ms = now_ms() - t0;
+  if (!r.converged) {
+    set_error("no convergence after %d iterations (max residual %.3e)", it, mr);
+    return CHFSI_ERR_NOCONV;
+  }
+  return CHFSI_OK;
+}
+
+}  // extern "C"

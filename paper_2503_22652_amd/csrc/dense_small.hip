@@ -1,0 +1,538 @@
+// Small dense FP64 linear algebra of the Rayleigh-Ritz step (b x b, b up to a
+// few thousand): blocked Cholesky, blocked triangular solve and a
+// block-parallel Jacobi symmetric eigensolver.
+//
+// Rayleigh-Ritz (Algorithm 1, step 2) solves the projected pencil
+// (Y^T A Y) E = (Y^T B Y) E Lambda.  The library reduces it with the Cholesky
+// factor of the column-scaled Gram matrix Y^T B Y (CholQR) and diagonalises the
+// resulting standard symmetric matrix with Jacobi rotations.
+//
+// Jacobi is chosen for the GPU because (i) a round of disjoint rotations is
+// embarrassingly parallel, (ii) it converges quadratically when the matrix is
+// nearly diagonal -- which is what the projected matrix becomes as subspace
+// iteration converges -- and (iii) it is accurate to a small multiple of the
+// unit roundoff.  The block variant pairs 32-wide column blocks in a
+// round-robin tournament, diagonalises every 64 x 64 pair subproblem fully in
+// LDS (one workgroup each), and applies the resulting orthogonal 64 x 64
+// factors to the rest of the matrix and to the eigenvector accumulator.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace chfsi {
+
+namespace {
+
+constexpr int NB = 64;          // Cholesky / TRSM block
+constexpr int JB = 32;          // Jacobi column block
+constexpr int JP = 2 * JB;      // Jacobi pair subproblem size
+constexpr int LDJ = JP + 1;     // padded LDS leading dimension
+
+// ---------------------------------------------------------------------------
+// Cholesky of the diagonal block (jb <= 64) in LDS; right-looking.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int jb, int* info,
+                                                    int j0) {
+  __shared__ double a[NB * (NB + 1)];
+  __shared__ int fail;
+  constexpr int L = NB + 1;
+  if (threadIdx.x == 0) fail = (*info != 0);
+  for (int idx = threadIdx.x; idx < jb * jb; idx += 256) {
+    const int i = idx % jb, j = idx / jb;
+    a[i + j * L] = A[i + j * lda];
+  }
+  __syncthreads();
+  if (fail) return;
+  for (int k = 0; k < jb; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = a[k + k * L];
+      if (!(d > 0.0) || !isfinite(d)) {
+        fail = 1;
+        atomicCAS(info, 0, j0 + k + 1);
+      } else {
+        a[k + k * L] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (fail) return;
+    const double piv = a[k + k * L];
+    for (int i = k + 1 + threadIdx.x; i < jb; i += 256) a[i + k * L] /= piv;
+    __syncthreads();
+    const int m = jb - k - 1;
+    for (int idx = threadIdx.x; idx < m * m; idx += 256) {
+      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
+      if (j <= i) a[i + j * L] -= a[i + k * L] * a[j + k * L];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < jb * jb; idx += 256) {
+    const int i = idx % jb, j = idx / jb;
+    A[i + j * lda] = (i >= j) ? a[i + j * L] : 0.0;
+  }
+}
+
+// Rows below the diagonal block: L21 = A21 L11^{-T}; one thread per row.
+__global__ __launch_bounds__(256) void k_potrf_panel(const double* L11, double* A21, int64_t lda,
+                                                     int jb, int64_t rows, const int* info) {
+  __shared__ double l[NB * (NB + 1)];
+  constexpr int L = NB + 1;
+  if (*info != 0) return;
+  for (int idx = threadIdx.x; idx < jb * jb; idx += 256) {
+    const int i = idx % jb, j = idx / jb;
+    l[i + j * L] = L11[i + j * lda];
+  }
+  __syncthreads();
+  const int64_t r = blockIdx.x * int64_t(256) + threadIdx.x;
+  if (r >= rows) return;
+  double x[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+    if (k < jb) x[k] = A21[r + k * lda];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (k < jb) {
+      double s = x[k];
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j < k) s -= x[j] * l[k + j * L];
+      x[k] = s / l[k + k * L];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+    if (k < jb) A21[r + k * lda] = x[k];
+}
+
+__global__ __launch_bounds__(256) void k_zero_upper(double* A, int64_t lda, int64_t b) {
+  const int64_t total = b * b;
+  for (int64_t idx = blockIdx.x * int64_t(256) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * 256) {
+    const int64_t i = idx % b, j = idx / b;
+    if (i < j) A[i + j * lda] = 0.0;
+  }
+}
+
+// X_jj <- L_jj^{-1} X_jj for one diagonal block; one thread per right-hand side.
+__global__ __launch_bounds__(256) void k_trsm_diag(const double* Ljj, int64_t ldl, double* Xj,
+                                                   int64_t ldx, int jb, int64_t nrhs) {
+  __shared__ double l[NB * (NB + 1)];
+  constexpr int L = NB + 1;
+  for (int idx = threadIdx.x; idx < jb * jb; idx += 256) {
+    const int i = idx % jb, j = idx / jb;
+    l[i + j * L] = Ljj[i + j * ldl];
+  }
+  __syncthreads();
+  const int64_t c = blockIdx.x * int64_t(256) + threadIdx.x;
+  if (c >= nrhs) return;
+  double x[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+    if (k < jb) x[k] = Xj[k + c * ldx];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (k < jb) {
+      double s = x[k];
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j < k) s -= l[k + j * L] * x[j];
+      x[k] = s / l[k + k * L];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+    if (k < jb) Xj[k + c * ldx] = x[k];
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi
+// ---------------------------------------------------------------------------
+// round-robin ("circle") schedule: n players (even), round r in [0, n-1),
+// slot 0 fixed, slots 1..n-1 rotate; pair k joins slots k and n-1-k.
+__device__ __forceinline__ int rr_slot(int slot, int r, int n) {
+  return slot == 0 ? 0 : 1 + (slot - 1 + r) % (n - 1);
+}
+
+// Diagonalise the JP x JP symmetric matrix a (LDS, ld LDJ) in place and
+// accumulate the rotations into u (LDS, starts as identity).  Returns (via
+// *nrot, LDS) the number of rotations applied.
+__device__ void lds_jacobi(double* a, double* u, int n, double thresh, int max_sweeps,
+                           int* nrot_total) {
+  __shared__ int pp[JP / 2], qq[JP / 2];
+  __shared__ double cc[JP / 2], ss[JP / 2];
+  __shared__ int sweep_rot;
+  const int half = n / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) sweep_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < n - 1; ++r) {
+      if (threadIdx.x < half) {
+        const int k = threadIdx.x;
+        int p = rr_slot(k, r, n), q = rr_slot(n - 1 - k, r, n);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        const double apq = a[p + q * LDJ];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > thresh) {
+          const double app = a[p + p * LDJ], aqq = a[q + q * LDJ];
+          const double theta = (aqq - app) / (2.0 * apq);
+          double t;
+          if (fabs(theta) > 1e150)
+            t = 0.5 / theta;
+          else
+            t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+          atomicAdd(&sweep_rot, 1);
+        }
+        pp[k] = p;
+        qq[k] = q;
+        cc[k] = c;
+        ss[k] = s;
+      }
+      __syncthreads();
+      // rows p, q
+      for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
+        const int k = idx / n, j = idx - k * n;
+        const double s = ss[k];
+        if (s == 0.0) continue;
+        const double c = cc[k];
+        const int p = pp[k], q = qq[k];
+        const double ap = a[p + j * LDJ], aq = a[q + j * LDJ];
+        a[p + j * LDJ] = c * ap - s * aq;
+        a[q + j * LDJ] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of a and of u
+      for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
+        const int k = idx / n, i = idx - k * n;
+        const double s = ss[k];
+        if (s == 0.0) continue;
+        const double c = cc[k];
+        const int p = pp[k], q = qq[k];
+        const double ap = a[i + p * LDJ], aq = a[i + q * LDJ];
+        // the rotation annihilates a_pq; store the exact zero
+        a[i + p * LDJ] = (i == q) ? 0.0 : c * ap - s * aq;
+        a[i + q * LDJ] = (i == p) ? 0.0 : s * ap + c * aq;
+        const double up = u[i + p * LDJ], uq = u[i + q * LDJ];
+        u[i + p * LDJ] = c * up - s * uq;
+        u[i + q * LDJ] = s * up + c * uq;
+      }
+      __syncthreads();
+    }
+    const int rot = sweep_rot;
+    if (threadIdx.x == 0) *nrot_total += rot;
+    __syncthreads();
+    if (rot == 0) break;
+  }
+}
+
+// Block indices of pair k in round r of the block tournament (nblk blocks).
+__device__ __forceinline__ void block_pair(int k, int r, int nblk, int* I, int* J) {
+  int a = rr_slot(k, r, nblk), b = rr_slot(nblk - 1 - k, r, nblk);
+  *I = a < b ? a : b;
+  *J = a < b ? b : a;
+}
+
+// index of local row l (0..JP-1) of pair (I,J) in the padded matrix
+__device__ __forceinline__ int pair_index(int l, int I, int J) {
+  return l < JB ? I * JB + l : J * JB + (l - JB);
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_pair_solve(const double* A, int64_t lda,
+                                                           int nblk, int round,
+                                                           const double* scale, double tol,
+                                                           double* U, int* counter,
+                                                           int max_sweeps) {
+  __shared__ double a[JP * LDJ];
+  __shared__ double u[JP * LDJ];
+  __shared__ int nrot;
+  int I, J;
+  block_pair(blockIdx.x, round, nblk, &I, &J);
+  for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+    const int i = idx % JP, j = idx / JP;
+    a[i + j * LDJ] = A[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
+    u[i + j * LDJ] = (i == j) ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) nrot = 0;
+  __syncthreads();
+  const double thresh = tol * (*scale);
+  lds_jacobi(a, u, JP, thresh, max_sweeps, &nrot);
+  __syncthreads();
+  double* Uo = U + int64_t(blockIdx.x) * JP * JP;
+  for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+    const int i = idx % JP, j = idx / JP;
+    Uo[i + j * JP] = u[i + j * LDJ];
+  }
+  if (threadIdx.x == 0 && nrot > 0) atomicAdd(counter, nrot);
+}
+
+// A[SP, SQ] <- U_P^T A[SP, SQ] U_Q for pair blocks P (blockIdx.x), Q (blockIdx.y)
+__global__ __launch_bounds__(256) void k_jacobi_apply_A(double* A, int64_t lda, int nblk,
+                                                        int round, const double* U) {
+  __shared__ double m[JP * LDJ];
+  __shared__ double up[JP * LDJ];
+  __shared__ double uq[JP * LDJ];
+  int IP, JPb, IQ, JQ;
+  block_pair(blockIdx.x, round, nblk, &IP, &JPb);
+  block_pair(blockIdx.y, round, nblk, &IQ, &JQ);
+  const double* Up = U + int64_t(blockIdx.x) * JP * JP;
+  const double* Uq = U + int64_t(blockIdx.y) * JP * JP;
+  for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+    const int i = idx % JP, j = idx / JP;
+    m[i + j * LDJ] = A[pair_index(i, IP, JPb) + int64_t(pair_index(j, IQ, JQ)) * lda];
+    up[i + j * LDJ] = Up[i + j * JP];
+    uq[i + j * LDJ] = Uq[i + j * JP];
+  }
+  __syncthreads();
+  // T = U_P^T M : each thread computes 16 entries
+  double t[16];
+  const int col = threadIdx.x / 4;         // 0..63
+  const int rowb = (threadIdx.x % 4) * 16;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = rowb + q;
+    double s = 0.0;
+    for (int k = 0; k < JP; ++k) s += up[k + i * LDJ] * m[k + col * LDJ];
+    t[q] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) m[rowb + q + col * LDJ] = t[q];
+  __syncthreads();
+  // R = T U_Q
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = rowb + q;
+    double s = 0.0;
+    for (int k = 0; k < JP; ++k) s += m[i + k * LDJ] * uq[k + col * LDJ];
+    t[q] = s;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    A[pair_index(rowb + q, IP, JPb) + int64_t(pair_index(col, IQ, JQ)) * lda] = t[q];
+}
+
+// V[rows chunk, SP] <- V[rows chunk, SP] U_P ; blockIdx.x = pair, blockIdx.y = 64-row chunk
+__global__ __launch_bounds__(256) void k_jacobi_apply_V(double* V, int64_t ldv, int nblk,
+                                                        int round, const double* U) {
+  __shared__ double m[JP * LDJ];
+  __shared__ double up[JP * LDJ];
+  int IP, JPb;
+  block_pair(blockIdx.x, round, nblk, &IP, &JPb);
+  const double* Up = U + int64_t(blockIdx.x) * JP * JP;
+  const int64_t r0 = int64_t(blockIdx.y) * JP;
+  for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+    const int i = idx % JP, j = idx / JP;
+    m[i + j * LDJ] = V[r0 + i + int64_t(pair_index(j, IP, JPb)) * ldv];
+    up[i + j * LDJ] = Up[i + j * JP];
+  }
+  __syncthreads();
+  const int col = threadIdx.x / 4;
+  const int rowb = (threadIdx.x % 4) * 16;
+  double t[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = rowb + q;
+    double s = 0.0;
+    for (int k = 0; k < JP; ++k) s += m[i + k * LDJ] * up[k + col * LDJ];
+    t[q] = s;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) V[r0 + rowb + q + int64_t(pair_index(col, IP, JPb)) * ldv] = t[q];
+}
+
+// padded copy: P (bp x bp) = [A 0; 0 0]; V = I
+__global__ __launch_bounds__(256) void k_jacobi_setup(const double* A, int64_t lda, int64_t b,
+                                                      double* P, double* V, int64_t bp) {
+  const int64_t total = bp * bp;
+  for (int64_t idx = blockIdx.x * int64_t(256) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * 256) {
+    const int64_t i = idx % bp, j = idx / bp;
+    P[idx] = (i < b && j < b) ? A[i + j * lda] : 0.0;
+    V[idx] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+// Frobenius norm of a b x b matrix into *out (single workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_fro(const double* A, int64_t lda, int64_t b,
+                                             double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t idx = threadIdx.x; idx < b * b; idx += 256) {
+    const double v = A[idx % b + (idx / b) * lda];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(red[0]) > 0 ? sqrt(red[0]) : 1.0;
+}
+
+// ascending sort of the diagonal (first b entries) by rank counting, then
+// gather eigenvector columns
+__global__ __launch_bounds__(256) void k_jacobi_rank(const double* P, int64_t bp, int64_t b,
+                                                     double* w, int* perm) {
+  const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
+  if (i >= b) return;
+  const double di = P[i + i * bp];
+  int64_t rank = 0;
+  for (int64_t j = 0; j < b; ++j) {
+    const double dj = P[j + j * bp];
+    rank += (dj < di) || (dj == di && j < i);
+  }
+  w[rank] = di;
+  perm[rank] = int(i);
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_gather(const double* V, int64_t bp, int64_t b,
+                                                       const int* perm, double* out,
+                                                       int64_t ldo) {
+  const int64_t total = b * b;
+  for (int64_t idx = blockIdx.x * int64_t(256) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * 256) {
+    const int64_t i = idx % b, r = idx / b;
+    out[i + r * ldo] = V[i + int64_t(perm[r]) * bp];
+  }
+}
+
+inline int64_t grid_for(int64_t total) {
+  int64_t g = (total + 255) / 256;
+  return std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+}  // namespace
+
+size_t potrf_workspace_bytes(int64_t b) { return gemm_workspace_bytes(b, b, NB, sizeof(double)); }
+
+hipError_t potrf_lower(double* A, int64_t lda, int64_t b, int* info, hipStream_t st,
+                       const Workspace& ws) {
+  hipError_t e = hipSuccess;
+  for (int64_t j0 = 0; j0 < b; j0 += NB) {
+    const int jb = int(std::min<int64_t>(NB, b - j0));
+    k_potrf_diag<<<1, 256, 0, st>>>(A + j0 + j0 * lda, lda, jb, info, int(j0));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t rows = b - j0 - jb;
+    if (rows <= 0) break;
+    k_potrf_panel<<<dim3(unsigned((rows + 255) / 256)), 256, 0, st>>>(
+        A + j0 + j0 * lda, A + (j0 + jb) + j0 * lda, lda, jb, rows, info);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // A22 -= L21 L21^T
+    GemmDesc<double> g;
+    g.M = rows;
+    g.N = rows;
+    g.K = jb;
+    g.A = A + (j0 + jb) + j0 * lda;
+    g.sam = 1;
+    g.sak = lda;
+    g.B = A + (j0 + jb) + j0 * lda;
+    g.sbn = 1;
+    g.sbk = lda;
+    g.C = A + (j0 + jb) + (j0 + jb) * lda;
+    g.ldc = lda;
+    g.epi.alpha = -1.0;
+    g.epi.beta = 1.0;
+    g.epi.C1 = g.C;
+    g.epi.ldc1 = lda;
+    if ((e = gemm<double>(g, st, ws, 1)) != hipSuccess) return e;
+  }
+  k_zero_upper<<<grid_for(b * b), 256, 0, st>>>(A, lda, b);
+  return hipGetLastError();
+}
+
+hipError_t trsm_lower_left(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t b,
+                           int64_t nrhs, hipStream_t st, const Workspace& ws) {
+  hipError_t e = hipSuccess;
+  for (int64_t j0 = 0; j0 < b; j0 += NB) {
+    const int jb = int(std::min<int64_t>(NB, b - j0));
+    k_trsm_diag<<<dim3(unsigned((nrhs + 255) / 256)), 256, 0, st>>>(L + j0 + j0 * ldl, ldl,
+                                                                     X + j0, ldx, jb, nrhs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t rows = b - j0 - jb;
+    if (rows <= 0) break;
+    GemmDesc<double> g;
+    g.M = rows;
+    g.N = nrhs;
+    g.K = jb;
+    g.A = L + (j0 + jb) + j0 * ldl;
+    g.sam = 1;
+    g.sak = ldl;
+    g.B = X + j0;
+    g.sbk = 1;
+    g.sbn = ldx;
+    g.C = X + j0 + jb;
+    g.ldc = ldx;
+    g.epi.alpha = -1.0;
+    g.epi.beta = 1.0;
+    g.epi.C1 = g.C;
+    g.epi.ldc1 = ldx;
+    if ((e = gemm<double>(g, st, ws, 1)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static int64_t jacobi_padded(int64_t b) { return std::max<int64_t>(JP, (b + JP - 1) / JP * JP); }
+
+size_t syev_workspace_bytes(int64_t b) {
+  const int64_t bp = jacobi_padded(b);
+  const int64_t npairs = bp / JP;
+  return size_t(2 * bp * bp + npairs * JP * JP + 16) * sizeof(double) + size_t(b + 64) * sizeof(int);
+}
+
+hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
+                       hipStream_t st, const Workspace& ws, int* sweeps_out) {
+  const int64_t bp = jacobi_padded(b);
+  const int nblk = int(bp / JB);     // even
+  const int npairs = nblk / 2;
+  if (ws.bytes < syev_workspace_bytes(b)) return hipErrorInvalidValue;
+  double* P = static_cast<double*>(ws.ptr);
+  double* Vp = P + bp * bp;
+  double* U = Vp + bp * bp;
+  double* scal = U + int64_t(npairs) * JP * JP;   // [0]: Frobenius norm
+  int* counter = reinterpret_cast<int*>(scal + 16);
+  int* perm = counter + 64;
+  hipError_t e;
+  k_jacobi_setup<<<grid_for(bp * bp), 256, 0, st>>>(A, lda, b, P, Vp, bp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_fro<<<1, 256, 0, st>>>(A, lda, b, scal);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const double tol = 1e-15;
+  const int max_outer = 40;
+  int sweeps = 0;
+  int host_count = 0;
+  for (; sweeps < max_outer; ++sweeps) {
+    if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
+    for (int r = 0; r < nblk - 1; ++r) {
+      k_jacobi_pair_solve<<<dim3(npairs), 256, 0, st>>>(P, bp, nblk, r, scal, tol, U, counter,
+                                                        30);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      k_jacobi_apply_A<<<dim3(npairs, npairs), 256, 0, st>>>(P, bp, nblk, r, U);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      k_jacobi_apply_V<<<dim3(npairs, unsigned(bp / JP)), 256, 0, st>>>(Vp, bp, nblk, r, U);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = hipMemcpyAsync(&host_count, counter, sizeof(int), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (host_count == 0) {
+      ++sweeps;
+      break;
+    }
+  }
+  k_jacobi_rank<<<dim3(unsigned((b + 255) / 256)), 256, 0, st>>>(P, bp, b, w, perm);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_jacobi_gather<<<grid_for(b * b), 256, 0, st>>>(Vp, bp, b, perm, V, ldv);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (sweeps_out) *sweeps_out = sweeps;
+  return hipSuccess;
+}
+
+}  // namespace chfsi

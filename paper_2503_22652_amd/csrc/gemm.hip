@@ -1,0 +1,525 @@
+// MFMA GEMM for gfx950 with a fused three-term epilogue.
+//
+// This kernel evaluates the matrix multi-vector products of the Chebyshev
+// filter -- the dominant cost of the method (paper, Section 3, opening
+// paragraph) -- together with the rest of the recurrence step: for the
+// residual filter (Algorithm 3, loop body)
+//     R_X <- a_k A (D^{-1} R_Y) + b_k R_Y + c_k R_X + a_k Y Lambda_Y
+// is one launch (kscale = D^{-1}, C1 = R_Y, C2 = R_X, C3 = Y, colscale3 =
+// Lambda_Y).  The same kernel provides the FP64 products of the Rayleigh-Ritz
+// step (operator application, Gram matrices, rotations).
+//
+// Design (CDNA4):
+//  * 256 threads = four 64-wide waves arranged WM x WN; each wave owns a
+//    (BM/WM) x (BN/WN) sub-tile made of 16x16 MFMA tiles
+//    (v_mfma_f32_16x16x4f32 or v_mfma_f64_16x16x4f64).
+//  * Operands are staged through LDS in a k-contiguous layout [row][k] with a
+//    small pad.  Within one BK slice the four 16-lane groups of a wave take
+//    disjoint k ranges (group g owns k = g*BK/4 ... g*BK/4 + BK/4 - 1), so
+//    every lane fetches its operand fragments with 16-byte LDS reads; the sum
+//    over the slice is unchanged because A and B use the same k assignment.
+//  * Two LDS stages with register prefetch: one barrier per k slice.
+//  * Deterministic split-K: partial tiles go to scratch and a second kernel
+//    adds them in split order and applies the epilogue, so results never depend
+//    on scheduling.
+//  * Tile order is remapped so that consecutive logical tiles (same rows of A,
+//    neighbouring column tiles) land on the same XCD and share its L2.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace chfsi {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+
+// Operand layout of both 16x16x4 instructions: lane l supplies A(l%16, l/16)
+// and B(l/16, l%16).  Output element r of lane l sits in column l%16; its row
+// differs: the f32 form keeps four consecutive rows per lane group
+// (row 4*(l/16) + r), the f64 form interleaves them (row l/16 + 4*r).
+template <>
+struct Mfma<float> {
+  using acc_t = f32x4;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lgrp, int r) { return lgrp * 4 + r; }
+};
+
+template <>
+struct Mfma<double> {
+  using acc_t = f64x4;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lgrp, int r) { return lgrp + 4 * r; }
+};
+
+// 16-byte vector of T
+template <typename T>
+struct Vec16 {
+  static constexpr int W = 16 / sizeof(T);
+  T v[W];
+};
+
+struct KernelArgsCommon {
+  int64_t M, N, K;
+  int64_t sam, sak, sbk, sbn, ldc;
+  int batch, splits;
+  int64_t kchunk;           // k range per split (multiple of BK)
+  int64_t bsA, bsB, bsC, bsC1;
+  int vecA, vecB;           // 16-byte vector loads allowed along the contiguous dim
+  int tiles_m, tiles_n;
+};
+
+template <typename T>
+struct KernelArgs {
+  KernelArgsCommon c;
+  const T* A;
+  const T* B;
+  const T* kscale;
+  T* C;
+  T* partial;
+  Epilogue<T> epi;
+};
+
+__device__ __forceinline__ int xcd_remap(int h, int G) {
+  // Dispatch is round-robin over 8 XCDs: WG h runs on XCD h % 8.  Give each
+  // XCD a contiguous range of logical tile ids.
+  const int xcd = h & 7, slot = h >> 3;
+  const int full = G >> 3, rem = G & 7;
+  return (xcd < rem) ? xcd * (full + 1) + slot : rem * (full + 1) + (xcd - rem) * full + slot;
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_epilogue(const Epilogue<T>& e, T acc, int64_t m, int64_t n) {
+  T v = e.alpha * acc;
+  if (e.rowscale) v *= e.rowscale[m];
+  if (e.C1) v += e.beta * e.C1[m + n * e.ldc1];
+  if (e.C2) v += e.gamma * e.C2[m + n * e.ldc2];
+  if (e.C3) {
+    T f = e.delta;
+    if (e.colscale3) f *= e.colscale3[n];
+    v += f * e.C3[m + n * e.ldc3];
+  }
+  return v;
+}
+
+// Load a ROWS x BK tile of a "row operand" (row r, depth k) into registers.
+// KCONTIG: element (r,k) at base[r*srow + k]; else at base[r + k*sk].
+template <typename T, int ROWS, int BK, bool KCONTIG>
+struct TileLoader {
+  static constexpr int W = Vec16<T>::W;
+  static constexpr int TOT = ROWS * BK / W;       // vectors per tile
+  static constexpr int NV = (TOT + 255) / 256;     // vectors per thread
+  static_assert((ROWS * BK) % W == 0, "tile not divisible into vectors");
+  static_assert(KCONTIG ? (BK % W == 0) : (ROWS % W == 0), "vector along the contiguous dim");
+  Vec16<T> r[NV];
+
+  __device__ __forceinline__ void load(const T* __restrict__ base, int64_t sr, int64_t r0,
+                                       int64_t rmax, int64_t k0, int64_t kmax, bool vec,
+                                       const T* __restrict__ kscale) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int v = threadIdx.x + i * 256;
+      if (TOT % 256 != 0 && v >= TOT) break;
+      if constexpr (KCONTIG) {
+        const int row = v / (BK / W);
+        const int kk = (v % (BK / W)) * W;
+        const int64_t gr = r0 + row, gk = k0 + kk;
+        if (vec && gr < rmax && gk + W <= kmax) {
+          r[i] = *reinterpret_cast<const Vec16<T>*>(base + gr * sr + gk);
+        } else {
+#pragma unroll
+          for (int j = 0; j < W; ++j)
+            r[i].v[j] = (gr < rmax && gk + j < kmax) ? base[gr * sr + gk + j] : T(0);
+        }
+        if (kscale) {
+#pragma unroll
+          for (int j = 0; j < W; ++j) r[i].v[j] *= (gk + j < kmax) ? kscale[gk + j] : T(0);
+        }
+      } else {
+        const int kk = v / (ROWS / W);
+        const int row = (v % (ROWS / W)) * W;
+        const int64_t gr = r0 + row, gk = k0 + kk;
+        if (vec && gk < kmax && gr + W <= rmax) {
+          r[i] = *reinterpret_cast<const Vec16<T>*>(base + gr + gk * sr);
+        } else {
+#pragma unroll
+          for (int j = 0; j < W; ++j)
+            r[i].v[j] = (gk < kmax && gr + j < rmax) ? base[gr + j + gk * sr] : T(0);
+        }
+        if (kscale) {
+          const T f = (gk < kmax) ? kscale[gk] : T(0);
+#pragma unroll
+          for (int j = 0; j < W; ++j) r[i].v[j] *= f;
+        }
+      }
+    }
+  }
+
+  template <int LDK>
+  __device__ __forceinline__ void store(T* __restrict__ lds) const {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int v = threadIdx.x + i * 256;
+      if (TOT % 256 != 0 && v >= TOT) break;
+      if constexpr (KCONTIG) {
+        const int row = v / (BK / W);
+        const int kk = (v % (BK / W)) * W;
+        *reinterpret_cast<Vec16<T>*>(lds + row * LDK + kk) = r[i];
+      } else {
+        const int kk = v / (ROWS / W);
+        const int row = (v % (ROWS / W)) * W;
+#pragma unroll
+        for (int j = 0; j < W; ++j) lds[(row + j) * LDK + kk] = r[i].v[j];
+      }
+    }
+  }
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool AK, bool BKC>
+__global__ __launch_bounds__(256) void gemm_kernel(KernelArgs<T> args) {
+  using MF = Mfma<T>;
+  using acc_t = typename MF::acc_t;
+  constexpr int PAD = 16 / sizeof(T);
+  constexpr int LDK = BK + PAD;
+  constexpr int KG = BK / 4;                 // k values per lane group per slice
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  static_assert(WM * WN == 4, "four waves per workgroup");
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be a multiple of 16");
+  static_assert((KG * sizeof(T)) % 16 == 0, "fragment reads are 16-byte vectors");
+
+  __shared__ __attribute__((aligned(16))) T As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BN * LDK];
+
+  const KernelArgsCommon& c = args.c;
+  const int G = gridDim.x;
+  const int t = xcd_remap(blockIdx.x, G);
+  const int tiles_mn = c.tiles_m * c.tiles_n;
+  const int n_tile = t % c.tiles_n;
+  const int m_tile = (t / c.tiles_n) % c.tiles_m;
+  const int zs = t / tiles_mn;                  // batch * splits + split
+  const int split = zs % c.splits;
+  const int bz = zs / c.splits;
+
+  const T* __restrict__ A = args.A + bz * c.bsA;
+  const T* __restrict__ B = args.B + bz * c.bsB;
+  const int64_t m0 = int64_t(m_tile) * BM;
+  const int64_t n0 = int64_t(n_tile) * BN;
+  const int64_t kbeg = int64_t(split) * c.kchunk;
+  const int64_t kend = std::min<int64_t>(c.K, kbeg + c.kchunk);
+  const int nk = kend > kbeg ? int((kend - kbeg + BK - 1) / BK) : 0;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int lrow = lane & 15;
+  const int lgrp = lane >> 4;
+
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
+
+  TileLoader<T, BM, BK, AK> la;
+  TileLoader<T, BN, BK, BKC> lb;
+  const int64_t sA = AK ? c.sam : c.sak;   // stride between rows (AK) or between k (m-contig)
+  const int64_t sB = BKC ? c.sbn : c.sbk;
+
+  if (nk > 0) {
+    la.load(A, sA, m0, c.M, kbeg, kend, c.vecA, nullptr);
+    lb.load(B, sB, n0, c.N, kbeg, kend, c.vecB, args.kscale);
+    la.template store<LDK>(As[0]);
+    lb.template store<LDK>(Bs[0]);
+  }
+  __syncthreads();
+
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) {
+      const int64_t k0 = kbeg + int64_t(kt + 1) * BK;
+      la.load(A, sA, m0, c.M, k0, kend, c.vecA, nullptr);
+      lb.load(B, sB, n0, c.N, k0, kend, c.vecB, args.kscale);
+    }
+    const T* as = As[cur];
+    const T* bs = Bs[cur];
+    T af[TM][KG];
+    T bf[TN][KG];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const T* p = as + (wm * WTM + i * 16 + lrow) * LDK + lgrp * KG;
+#pragma unroll
+      for (int q = 0; q < KG; q += Vec16<T>::W) {
+        Vec16<T> x = *reinterpret_cast<const Vec16<T>*>(p + q);
+#pragma unroll
+        for (int j = 0; j < Vec16<T>::W; ++j) af[i][q + j] = x.v[j];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TN; ++i) {
+      const T* p = bs + (wn * WTN + i * 16 + lrow) * LDK + lgrp * KG;
+#pragma unroll
+      for (int q = 0; q < KG; q += Vec16<T>::W) {
+        Vec16<T> x = *reinterpret_cast<const Vec16<T>*>(p + q);
+#pragma unroll
+        for (int j = 0; j < Vec16<T>::W; ++j) bf[i][q + j] = x.v[j];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < KG; ++s)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(af[i][s], bf[j][s], acc[i][j]);
+    if (kt + 1 < nk) {
+      la.template store<LDK>(As[cur ^ 1]);
+      lb.template store<LDK>(Bs[cur ^ 1]);
+    }
+    __syncthreads();
+  }
+
+  // Output fragment layout of the 16x16 MFMA: lane l, element r holds
+  // row MF::out_row(l/16, r), column l%16 of the tile.
+  if (c.splits == 1) {
+    T* C = args.C + bz * c.bsC;
+    Epilogue<T> e = args.epi;
+    if (e.C1) e.C1 += bz * c.bsC1;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * WTN + j * 16 + lrow;
+        if (n >= c.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + wm * WTM + i * 16 + MF::out_row(lgrp, r);
+          if (m < c.M) C[m + n * c.ldc] = apply_epilogue(e, acc[i][j][r], m, n);
+        }
+      }
+  } else {
+    T* P = args.partial + int64_t(zs) * c.M * c.N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * WTN + j * 16 + lrow;
+        if (n >= c.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + wm * WTM + i * 16 + MF::out_row(lgrp, r);
+          if (m < c.M) P[m + n * c.M] = acc[i][j][r];
+        }
+      }
+  }
+}
+
+// Sum split-K partials in split order, then apply the epilogue.
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(KernelArgs<T> args) {
+  const KernelArgsCommon& c = args.c;
+  const int64_t MN = c.M * c.N;
+  const int64_t total = MN * c.batch;
+  for (int64_t idx = blockIdx.x * int64_t(256) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * 256) {
+    const int64_t bz = idx / MN;
+    const int64_t e = idx - bz * MN;
+    const int64_t m = e % c.M, n = e / c.M;
+    const T* P = args.partial + bz * c.splits * MN + e;
+    T s = T(0);
+    for (int q = 0; q < c.splits; ++q) s += P[q * MN];
+    Epilogue<T> ep = args.epi;
+    if (ep.C1) ep.C1 += bz * c.bsC1;
+    T* C = args.C + bz * c.bsC;
+    C[m + n * c.ldc] = apply_epilogue(ep, s, m, n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// configurations and dispatch
+// ---------------------------------------------------------------------------
+struct Cfg {
+  int BM, BN, BK, occ;   // occ: resident workgroups per CU assumed by the planner
+};
+
+// FP32 tiles (16x16x4 f32 MFMA)
+static const Cfg kCfgF32[] = {
+    {128, 128, 32, 1}, {128, 160, 16, 2}, {128, 64, 32, 2}, {64, 64, 32, 3}};
+// FP64 tiles (16x16x4 f64 MFMA)
+static const Cfg kCfgF64[] = {
+    {128, 128, 16, 1}, {128, 64, 16, 2}, {64, 64, 16, 3}, {64, 64, 16, 3}};
+static constexpr int kNumCfg = 4;
+static constexpr int kNumCU = 256;
+
+template <typename T>
+static const Cfg* cfg_table() {
+  return sizeof(T) == 4 ? kCfgF32 : kCfgF64;
+}
+
+static int choose_splits(int64_t tiles, int64_t K, int BK, int slots) {
+  // enough work items to fill every resident slot a few times, but keep at
+  // least 8 k-slices per split
+  int s = 1;
+  const int64_t max_s = std::max<int64_t>(1, K / (8 * BK));
+  while (tiles * s < 2 * slots && s * 2 <= max_s && s < 64) s *= 2;
+  return s;
+}
+
+template <typename T>
+void gemm_plan(int64_t M, int64_t N, int64_t K, int batch, int* config, int* splits) {
+  const Cfg* tab = cfg_table<T>();
+  double best = 1e300;
+  int bc = kNumCfg - 1, bs = 1;
+  for (int ci = 0; ci < kNumCfg; ++ci) {
+    const Cfg& f = tab[ci];
+    const int64_t tm = (M + f.BM - 1) / f.BM, tn = (N + f.BN - 1) / f.BN;
+    const int64_t tiles = tm * tn * batch;
+    const int slots = kNumCU * f.occ;
+    const int s = choose_splits(tiles, K, f.BK, slots);
+    const double items = double(tiles) * s;
+    const double waves = std::ceil(items / slots);
+    // time ~ waves * (per-item work), per-item work ~ BM*BN*Kchunk / occ
+    const double kchunk = std::ceil(double(K) / s / f.BK) * f.BK;
+    const double t = waves * double(f.BM) * f.BN * kchunk / f.occ * (1.0 + 0.02 * s);
+    if (t < best * 0.999) {
+      best = t;
+      bc = ci;
+      bs = s;
+    }
+  }
+  *config = bc;
+  *splits = bs;
+}
+
+size_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, size_t elem) {
+  (void)K;
+  return size_t(64) * size_t(M) * size_t(N) * elem;
+}
+
+template <typename T, int BM, int BN, int BK>
+static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspace& ws,
+                             int splits) {
+  KernelArgs<T> a;
+  KernelArgsCommon& c = a.c;
+  c.M = d.M;
+  c.N = d.N;
+  c.K = d.K;
+  c.sam = d.sam;
+  c.sak = d.sak;
+  c.sbk = d.sbk;
+  c.sbn = d.sbn;
+  c.ldc = d.ldc;
+  c.batch = d.batch;
+  c.bsA = d.bsA;
+  c.bsB = d.bsB;
+  c.bsC = d.bsC;
+  c.bsC1 = d.bsC1;
+  c.tiles_m = int((d.M + BM - 1) / BM);
+  c.tiles_n = int((d.N + BN - 1) / BN);
+  const bool AK = (d.sak == 1);
+  const bool BKC = (d.sbk == 1);
+  constexpr int W = 16 / sizeof(T);
+  const int64_t ldA = AK ? d.sam : d.sak;
+  const int64_t ldB = BKC ? d.sbn : d.sbk;
+  c.vecA = (reinterpret_cast<uintptr_t>(d.A) % 16 == 0) && (ldA % W == 0) &&
+           (d.batch == 1 || d.bsA % W == 0);
+  c.vecB = (reinterpret_cast<uintptr_t>(d.B) % 16 == 0) && (ldB % W == 0) &&
+           (d.batch == 1 || d.bsB % W == 0);
+  if (splits > 1) {
+    int64_t kchunk = (d.K + splits - 1) / splits;
+    kchunk = (kchunk + BK - 1) / BK * BK;
+    splits = int((d.K + kchunk - 1) / kchunk);
+    c.kchunk = kchunk;
+  } else {
+    c.kchunk = (d.K + BK - 1) / BK * BK;
+    if (c.kchunk == 0) c.kchunk = BK;
+  }
+  c.splits = std::max(splits, 1);
+  a.A = d.A;
+  a.B = d.B;
+  a.kscale = d.kscale;
+  a.C = d.C;
+  a.epi = d.epi;
+  a.partial = nullptr;
+  if (c.splits > 1) {
+    const size_t need = size_t(c.splits) * d.batch * d.M * d.N * sizeof(T);
+    if (need > ws.bytes || ws.ptr == nullptr) {
+      c.splits = 1;
+      c.kchunk = (d.K + BK - 1) / BK * BK;
+    } else {
+      a.partial = static_cast<T*>(ws.ptr);
+    }
+  }
+  const int64_t grid = int64_t(c.tiles_m) * c.tiles_n * c.splits * d.batch;
+  if (grid <= 0) return hipSuccess;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  constexpr int WM = 2, WN = 2;
+  if (d.ev_begin) {
+    hipError_t e0 = hipEventRecord(d.ev_begin, st);
+    if (e0 != hipSuccess) return e0;
+  }
+  if (AK && BKC)
+    gemm_kernel<T, BM, BN, BK, WM, WN, true, true><<<dim3(grid), dim3(256), 0, st>>>(a);
+  else if (AK && !BKC)
+    gemm_kernel<T, BM, BN, BK, WM, WN, true, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+  else if (!AK && BKC)
+    gemm_kernel<T, BM, BN, BK, WM, WN, false, true><<<dim3(grid), dim3(256), 0, st>>>(a);
+  else
+    gemm_kernel<T, BM, BN, BK, WM, WN, false, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (d.ev_end) {
+    err = hipEventRecord(d.ev_end, st);
+    if (err != hipSuccess) return err;
+  }
+  if (c.splits > 1) {
+    const int64_t total = d.M * d.N * d.batch;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+    splitk_reduce_kernel<T><<<dim3(blocks), dim3(256), 0, st>>>(a);
+    err = hipGetLastError();
+  }
+  return err;
+}
+
+template <typename T>
+hipError_t gemm(const GemmDesc<T>& d, hipStream_t st, const Workspace& ws, int force_splits,
+                int force_config) {
+  if (d.M <= 0 || d.N <= 0) return hipSuccess;
+  if (d.sam != 1 && d.sak != 1) return hipErrorInvalidValue;
+  if (d.sbk != 1 && d.sbn != 1) return hipErrorInvalidValue;
+  if (d.batch > 1 && (d.epi.C2 || d.epi.C3 || d.epi.rowscale)) return hipErrorInvalidValue;
+  int cfg, splits;
+  gemm_plan<T>(d.M, d.N, d.K, d.batch, &cfg, &splits);
+  if (force_config >= 0 && force_config < kNumCfg) cfg = force_config;
+  if (force_splits > 0) splits = force_splits;
+  if (d.K <= 0) splits = 1;
+  if constexpr (sizeof(T) == 4) {
+    switch (cfg) {
+      case 0: return launch_cfg<T, 128, 128, 32>(d, st, ws, splits);
+      case 1: return launch_cfg<T, 128, 160, 16>(d, st, ws, splits);
+      case 2: return launch_cfg<T, 128, 64, 32>(d, st, ws, splits);
+      default: return launch_cfg<T, 64, 64, 32>(d, st, ws, splits);
+    }
+  } else {
+    switch (cfg) {
+      case 0: return launch_cfg<T, 128, 128, 16>(d, st, ws, splits);
+      case 1: return launch_cfg<T, 128, 64, 16>(d, st, ws, splits);
+      default: return launch_cfg<T, 64, 64, 16>(d, st, ws, splits);
+    }
+  }
+}
+
+template hipError_t gemm<float>(const GemmDesc<float>&, hipStream_t, const Workspace&, int, int);
+template hipError_t gemm<double>(const GemmDesc<double>&, hipStream_t, const Workspace&, int,
+                                 int);
+template void gemm_plan<float>(int64_t, int64_t, int64_t, int, int*, int*);
+template void gemm_plan<double>(int64_t, int64_t, int64_t, int, int*, int*);
+
+}  // namespace chfsi

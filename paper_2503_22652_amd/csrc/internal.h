@@ -1,0 +1,158 @@
+// Internal declarations shared by the HIP translation units of libchfsi.
+// Not part of the public C ABI (that is include/chfsi.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <atomic>
+
+struct chfsi_ctx;
+
+namespace chfsi {
+
+// ---------------------------------------------------------------------------
+// GEMM: C(m,n) = epilogue( sum_k A(m,k) * B(k,n) )
+//   A(m,k) = A[m*sam + k*sak]   (exactly one of sam, sak equals 1)
+//   B(k,n) = B[k*sbk + n*sbn]   (exactly one of sbk, sbn equals 1)
+//   optional kscale: B(k,n) is multiplied by kscale[k] as it is loaded
+//   C is column-major: C(m,n) = C[m + n*ldc]
+// Epilogue (all terms optional):
+//   v = alpha * rowscale[m] * acc + beta * C1(m,n) + gamma * C2(m,n)
+//       + delta * colscale3[n] * C3(m,n)
+// C may alias C1, C2 or C3 (each element is read before it is written by the
+// same thread).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Epilogue {
+  T alpha = T(1);
+  const T* rowscale = nullptr;
+  T beta = T(0);
+  const T* C1 = nullptr;
+  int64_t ldc1 = 0;
+  T gamma = T(0);
+  const T* C2 = nullptr;
+  int64_t ldc2 = 0;
+  T delta = T(0);
+  const T* colscale3 = nullptr;
+  const T* C3 = nullptr;
+  int64_t ldc3 = 0;
+};
+
+template <typename T>
+struct GemmDesc {
+  int64_t M = 0, N = 0, K = 0;
+  const T* A = nullptr;
+  int64_t sam = 0, sak = 0;
+  const T* B = nullptr;
+  int64_t sbk = 0, sbn = 0;
+  const T* kscale = nullptr;
+  T* C = nullptr;
+  int64_t ldc = 0;
+  // batched problems (blockIdx decodes the batch index); only the plain
+  // alpha/beta*C1 epilogue is supported when batch > 1
+  int batch = 1;
+  int64_t bsA = 0, bsB = 0, bsC = 0, bsC1 = 0;
+  Epilogue<T> epi;
+  // optional: events recorded on the stream right before / after the main
+  // (tile) kernel, i.e. excluding any split-K reduction
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+};
+
+// Scratch the GEMM may use for deterministic split-K partial sums.
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Launch a GEMM on `stream`.  `force_splits` > 0 pins the split-K factor
+// (results then do not depend on the heuristic).  Returns hipSuccess or the
+// first launch error.  Throws nothing.
+template <typename T>
+hipError_t gemm(const GemmDesc<T>& d, hipStream_t stream, const Workspace& ws,
+                int force_splits = 0, int force_config = -1);
+
+// Bytes of split-K scratch the heuristic may ask for at most for an M x N
+// output with reduction length K (per batch entry).
+size_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
+
+// Which tile configuration/split the heuristic picks (for reports and tests).
+template <typename T>
+void gemm_plan(int64_t M, int64_t N, int64_t K, int batch, int* config, int* splits);
+
+// ---------------------------------------------------------------------------
+// Elementwise / reduction kernels (blas1.hip)
+// ---------------------------------------------------------------------------
+// out32[i,j] = (float)(s * in64[i,j]); optional second output copy32 = (float)in64
+hipError_t rchfsi_init_f32(const double* R, int64_t ldr, int64_t n, int64_t b, double scale,
+                           float* RY, float* RX, float* Ycopy, int64_t ld32, hipStream_t st);
+hipError_t rchfsi_init_f64(const double* R, int64_t ldr, int64_t n, int64_t b, double scale,
+                           double* RY, double* RX, int64_t ld, hipStream_t st);
+// Yp[i,j] = dinv[i] * RY[i,j] + X[i,j] * lamY[j]   (dinv may be null => 1)
+hipError_t rchfsi_reconstruct_f32(const float* RY, int64_t ldry, const double* dinv,
+                                  const double* X, int64_t ldx, const double* lamY, double* Yp,
+                                  int64_t ldy, int64_t n, int64_t b, hipStream_t st);
+hipError_t rchfsi_reconstruct_f64(const double* RY, int64_t ldry, const double* dinv,
+                                  const double* X, int64_t ldx, const double* lamY, double* Yp,
+                                  int64_t ldy, int64_t n, int64_t b, hipStream_t st);
+// column 2-norms of an n x b FP64 block, deterministic order
+hipError_t column_norms(const double* R, int64_t ldr, int64_t n, int64_t b, double* out,
+                        hipStream_t st);
+// FP64 -> FP32 copy of an n x m column-major matrix
+hipError_t convert_f64_f32(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t n,
+                           int64_t m, hipStream_t st);
+// copy an n x b block between leading dimensions
+hipError_t copy_block(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t n,
+                      int64_t b, hipStream_t st);
+// B <- diag(s) A diag(s) with s = 1/sqrt(diag(G)); writes s
+hipError_t scale_gram(const double* G, int64_t ldg, int64_t b, double* Gs, int64_t lds,
+                      double* s, int* bad_flag, hipStream_t st);
+hipError_t scale_sym(const double* G, int64_t ldg, int64_t b, const double* s, double* out,
+                     int64_t ldo, hipStream_t st);
+// out = 0.5 (A + A^T) in place on a b x b matrix
+hipError_t symmetrize(double* A, int64_t lda, int64_t b, hipStream_t st);
+// columns of M scaled by v: M[:,j] *= v[j]
+hipError_t scale_columns(double* M, int64_t ldm, int64_t n, int64_t b, const double* v,
+                         hipStream_t st);
+hipError_t set_identity(double* M, int64_t ldm, int64_t n, hipStream_t st);
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
+// random N(0,1) block from a counter-based generator (Philox-4x32-10 + Box-Muller)
+hipError_t fill_gaussian(double* X, int64_t ldx, int64_t n, int64_t b, uint64_t seed,
+                         hipStream_t st);
+// any NaN/Inf in a vector -> *flag = 1
+hipError_t check_finite(const double* v, int64_t n, int* flag, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Small dense FP64 linear algebra (dense_small.hip)
+// ---------------------------------------------------------------------------
+// In-place lower Cholesky of a b x b SPD matrix (upper part zeroed). Sets
+// *info = j+1 at the first non-positive pivot (0 on success).
+hipError_t potrf_lower(double* A, int64_t lda, int64_t b, int* info, hipStream_t st,
+                       const Workspace& ws);
+// X <- L^{-1} X for lower-triangular L (b x b), X b x nrhs, in place.
+hipError_t trsm_lower_left(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t b,
+                           int64_t nrhs, hipStream_t st, const Workspace& ws);
+// Symmetric eigensolver (parallel block Jacobi).  A (b x b) is destroyed.
+// w: ascending eigenvalues (device, b); V: eigenvectors (device, b x b, ldv).
+// scratch from ws; sweeps reported through *sweeps_out (host) if non-null.
+hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
+                       hipStream_t st, const Workspace& ws, int* sweeps_out);
+size_t syev_workspace_bytes(int64_t b);
+size_t potrf_workspace_bytes(int64_t b);
+
+// ---------------------------------------------------------------------------
+// 27-point periodic stencil operators (stencil.hip)
+// ---------------------------------------------------------------------------
+struct StencilOp {
+  int nx = 0, ny = 0, nz = 0;
+  double coef[27];        // S1 coefficients, index (dz+1)*9 + (dy+1)*3 + (dx+1)
+  double coefM[27];       // mass coefficients used by the field term
+  const double* field = nullptr;  // V (length n) or null
+  int field_mode = 0;     // 0 none, 1 lumped diag(V), 2 mass weighted 1/2(VM + MV)
+};
+
+// Cooperative cancellation used by the serving scheduler: chfsi_solve checks
+// *flag before every outer iteration and returns CHFSI_ERR_CANCELLED once set.
+void ctx_set_cancel_flag(chfsi_ctx* c, const std::atomic<int>* flag);
+
+}  // namespace chfsi

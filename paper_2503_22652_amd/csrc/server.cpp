@@ -1,0 +1,366 @@
+// Serving scheduler of libchfsi: continuous batching of eigensolves on one GPU.
+//
+// The evolving-matrix setting of the paper (the Hamiltonian changes at every
+// step of an outer nonlinear iteration and the lowest eigenpairs are recomputed
+// from the previous subspace; introduction and Section 4.2) is served as a
+// stream of requests grouped into sequences.
+//
+//  * `slots` worker threads, each owning one HIP stream (default priority), run
+//    admitted solves concurrently; their kernels overlap on the device.
+//  * Admission: the first pending request (submission order) whose sequence is
+//    idle and whose device footprint (chfsi_workspace_bytes + its blocks) fits
+//    in the remaining budget is started as soon as a slot frees up.
+//  * Requests of one sequence run in submission order; the sequence's last Ritz
+//    vectors stay on the device and warm-start the next request.
+//  * A request runs the same kernels with the same launch shapes whether alone
+//    or mixed (launch shapes depend on the problem shape only and each solve
+//    has its own scratch), so its result is bitwise identical either way.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/chfsi.h"
+#include "internal.h"
+
+namespace {
+
+enum State { PENDING, RUNNING, DONE };
+
+struct Req {
+  uint64_t ticket = 0;
+  chfsi_request r{};
+  State state = PENDING;
+  bool cancel_requested = false;
+  std::atomic<int> cancel_flag{0};
+  chfsi_status status = CHFSI_OK;
+  int iterations = 0;
+  double max_residual = 0.0;
+  double submit_ms = 0, start_ms = 0, finish_ms = 0;
+  size_t footprint = 0;
+  std::vector<double> evals, resnorms;
+};
+
+struct Seq {
+  double* X = nullptr;
+  int64_t n = 0, b = 0;
+  bool busy = false;
+};
+
+double clock_ms(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct chfsi_server {
+  chfsi_server_config cfg{};
+  int device = 0;
+  size_t budget = 0, used = 0;
+  std::chrono::steady_clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req*> pending;
+  std::unordered_map<uint64_t, Req*> reqs;
+  std::unordered_map<int64_t, Seq> seqs;
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+};
+
+namespace {
+
+thread_local std::string g_srv_err;
+
+size_t footprint_of(const chfsi_request& r, bool new_seq) {
+  const chfsi_operator* B = r.B.kind == CHFSI_OP_IDENTITY ? nullptr : &r.B;
+  const size_t ws = chfsi_workspace_bytes(&r.A, B, &r.params);
+  if (ws == 0) return 0;
+  const size_t blk = size_t(r.A.n) * size_t(r.params.block) * sizeof(double);
+  return ws + blk + (new_seq ? blk : 0);
+}
+
+// pick the first admissible pending request; called with the lock held
+Req* pick(chfsi_server* s) {
+  for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+    Req* q = *it;
+    const int64_t sid = q->r.seq_id;
+    bool new_seq = true;
+    if (sid >= 0) {
+      auto f = s->seqs.find(sid);
+      if (f != s->seqs.end()) {
+        if (f->second.busy) continue;   // predecessor still running
+        new_seq = f->second.X == nullptr;
+      }
+      // an earlier pending request of the same sequence goes first
+      bool earlier = false;
+      for (auto jt = s->pending.begin(); jt != it; ++jt)
+        if ((*jt)->r.seq_id == sid) earlier = true;
+      if (earlier) continue;
+    }
+    const size_t need = footprint_of(q->r, new_seq);
+    if (s->used + need > s->budget) continue;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b) continue;
+    q->footprint = need;
+    s->used += need;
+    s->pending.erase(it);
+    if (sid >= 0) s->seqs[sid].busy = true;
+    return q;
+  }
+  return nullptr;
+}
+
+void run_one(chfsi_server* s, Req* q, hipStream_t stream) {
+  const chfsi_request& r = q->r;
+  const int64_t n = r.A.n, b = r.params.block;
+  chfsi_params prm = r.params;
+  double* X = nullptr;
+  chfsi_ctx* ctx = nullptr;
+  chfsi_status st = CHFSI_OK;
+  Seq* seq = nullptr;
+  if (r.seq_id >= 0) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    seq = &s->seqs[r.seq_id];
+  }
+  do {
+    if (hipMalloc(&X, size_t(n) * b * sizeof(double)) != hipSuccess) {
+      st = CHFSI_ERR_NOMEM;
+      break;
+    }
+    const chfsi_operator* B = r.B.kind == CHFSI_OP_IDENTITY ? nullptr : &r.B;
+    bool warm = false;
+    if (seq && seq->X && seq->n == n && seq->b == b) {
+      if (hipMemcpyAsync(X, seq->X, size_t(n) * b * sizeof(double), hipMemcpyDeviceToDevice,
+                         stream) != hipSuccess) {
+        st = CHFSI_ERR_DEVICE;
+        break;
+      }
+      warm = true;
+    } else if (r.X0) {
+      if (hipMemcpyAsync(X, r.X0, size_t(n) * b * sizeof(double), hipMemcpyDeviceToDevice,
+                         stream) != hipSuccess) {
+        st = CHFSI_ERR_DEVICE;
+        break;
+      }
+    }
+    prm.init_random = (!warm && !r.X0) ? 1 : 0;
+    st = chfsi_create(&ctx, &r.A, B, r.d_inv, &prm, stream);
+    if (st != CHFSI_OK) break;
+    chfsi::ctx_set_cancel_flag(ctx, &q->cancel_flag);
+    q->evals.assign(b, 0.0);
+    q->resnorms.assign(b, 0.0);
+    chfsi_report rep;
+    st = chfsi_solve(ctx, X, n, q->evals.data(), q->resnorms.data(), &rep);
+    q->iterations = rep.iterations;
+    q->max_residual = rep.max_residual;
+    if (st == CHFSI_OK || st == CHFSI_ERR_NOCONV) {
+      if (seq) {
+        if (!seq->X || seq->n != n || seq->b != b) {
+          if (seq->X) hipFree(seq->X);
+          seq->X = nullptr;
+          if (hipMalloc(&seq->X, size_t(n) * b * sizeof(double)) != hipSuccess) seq->X = nullptr;
+          seq->n = n;
+          seq->b = b;
+        }
+        if (seq->X)
+          hipMemcpyAsync(seq->X, X, size_t(n) * b * sizeof(double), hipMemcpyDeviceToDevice,
+                         stream);
+      }
+      if (r.X_out)
+        hipMemcpyAsync(r.X_out, X, size_t(n) * b * sizeof(double), hipMemcpyDeviceToDevice,
+                       stream);
+      hipStreamSynchronize(stream);
+    }
+  } while (false);
+  if (st != CHFSI_OK) g_srv_err = chfsi_last_error();
+  if (ctx) chfsi_destroy(ctx);
+  if (X) hipFree(X);
+  q->status = st;
+}
+
+void worker_main(chfsi_server* s, int slot) {
+  hipSetDevice(s->device);
+  hipStream_t stream = s->streams[slot];
+  for (;;) {
+    Req* q = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] { return s->stop || (q = pick(s)) != nullptr; });
+      if (!q) return;   // stopping
+      q->state = RUNNING;
+      q->start_ms = clock_ms(s->t0);
+    }
+    run_one(s, q, stream);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      q->finish_ms = clock_ms(s->t0);
+      q->state = DONE;
+      s->used -= q->footprint;
+      if (q->r.seq_id >= 0) s->seqs[q->r.seq_id].busy = false;
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+chfsi_status chfsi_server_create(chfsi_server** out, const chfsi_server_config* cfg) {
+  if (!out || !cfg || cfg->slots < 1 || cfg->slots > 64 || cfg->queue_capacity < 1)
+    return CHFSI_ERR_ARG;
+  chfsi_server* s = new chfsi_server();
+  s->cfg = *cfg;
+  s->t0 = std::chrono::steady_clock::now();
+  hipGetDevice(&s->device);
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    delete s;
+    return CHFSI_ERR_DEVICE;
+  }
+  s->budget = cfg->memory_budget ? cfg->memory_budget : size_t(0.9 * double(free_b));
+  for (int i = 0; i < cfg->slots; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (auto x : s->streams) hipStreamDestroy(x);
+      delete s;
+      return CHFSI_ERR_DEVICE;
+    }
+    s->streams.push_back(st);
+  }
+  for (int i = 0; i < cfg->slots; ++i) s->workers.emplace_back(worker_main, s, i);
+  *out = s;
+  return CHFSI_OK;
+}
+
+chfsi_status chfsi_submit(chfsi_server* s, const chfsi_request* req, uint64_t* ticket) {
+  if (!s || !req || !ticket) return CHFSI_ERR_ARG;
+  const size_t need = footprint_of(*req, true);
+  if (need == 0) return CHFSI_ERR_ARG;
+  Req* q = new Req();
+  q->r = *req;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (need > s->budget) {
+      delete q;
+      return CHFSI_ERR_NOMEM;
+    }
+    if (s->stop || int(s->pending.size()) >= s->cfg.queue_capacity) {
+      delete q;
+      return CHFSI_ERR_BUSY;
+    }
+    q->ticket = s->next_ticket++;
+    q->submit_ms = clock_ms(s->t0);
+    s->reqs[q->ticket] = q;
+    s->pending.push_back(q);
+    *ticket = q->ticket;
+  }
+  s->cv_work.notify_one();
+  return CHFSI_OK;
+}
+
+chfsi_status chfsi_wait(chfsi_server* s, uint64_t ticket, int32_t timeout_ms, chfsi_result* res) {
+  if (!s || !res) return CHFSI_ERR_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return CHFSI_ERR_ARG;
+  Req* q = it->second;
+  auto done = [&] { return q->state == DONE; };
+  if (timeout_ms < 0) {
+    s->cv_done.wait(lk, done);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) {
+    return CHFSI_ERR_TIMEOUT;
+  }
+  std::memset(res, 0, sizeof(*res));
+  res->status = q->status;
+  res->iterations = q->iterations;
+  res->max_residual = q->max_residual;
+  res->submit_ms = q->submit_ms;
+  res->start_ms = q->start_ms;
+  res->finish_ms = q->finish_ms;
+  res->n = q->r.A.n;
+  res->block = q->r.params.block;
+  if (!q->evals.empty()) {
+    res->evals = static_cast<double*>(std::malloc(q->evals.size() * sizeof(double)));
+    res->resnorms = static_cast<double*>(std::malloc(q->resnorms.size() * sizeof(double)));
+    if (res->evals) std::memcpy(res->evals, q->evals.data(), q->evals.size() * sizeof(double));
+    if (res->resnorms)
+      std::memcpy(res->resnorms, q->resnorms.data(), q->resnorms.size() * sizeof(double));
+  }
+  s->reqs.erase(it);
+  const chfsi_status st = q->status;
+  delete q;
+  return st;
+}
+
+chfsi_status chfsi_cancel(chfsi_server* s, uint64_t ticket) {
+  if (!s) return CHFSI_ERR_ARG;
+  bool notify = false;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return CHFSI_ERR_ARG;
+    Req* q = it->second;
+    if (q->state == PENDING) {
+      for (auto p = s->pending.begin(); p != s->pending.end(); ++p)
+        if (*p == q) {
+          s->pending.erase(p);
+          break;
+        }
+      q->state = DONE;
+      q->status = CHFSI_ERR_CANCELLED;
+      q->finish_ms = clock_ms(s->t0);
+      notify = true;
+    } else if (q->state == RUNNING) {
+      q->cancel_flag.store(1);
+    }
+  }
+  if (notify) {
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+  }
+  return CHFSI_OK;
+}
+
+void chfsi_result_free(chfsi_result* res) {
+  if (!res) return;
+  std::free(res->evals);
+  std::free(res->resnorms);
+  res->evals = nullptr;
+  res->resnorms = nullptr;
+}
+
+void chfsi_server_destroy(chfsi_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    for (Req* q : s->pending) {
+      q->state = DONE;
+      q->status = CHFSI_ERR_CANCELLED;
+    }
+    s->pending.clear();
+  }
+  s->cv_work.notify_all();
+  s->cv_done.notify_all();
+  for (auto& t : s->workers) t.join();
+  for (auto& kv : s->seqs)
+    if (kv.second.X) hipFree(kv.second.X);
+  for (auto& kv : s->reqs) delete kv.second;
+  for (auto st : s->streams) hipStreamDestroy(st);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Internal interface of the periodic 27-point grid operator kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "../../include/chfsi.h"
+
+namespace chfsi {
+
+// Coefficients of one filter step: out = alpha * (op applied) + beta * src
+// + gamma * prev + delta * colcoef[j] * forcing.
+struct StencilStep {
+  double alpha, beta, gamma, delta;
+};
+
+hipError_t stencil_check(const chfsi_operator& op);
+// nominal flops per element and step (for reporting)
+double stencil_flops(const chfsi_operator& op);
+
+// Y = op X (FP64), X/Y column-major n x b
+hipError_t stencil_apply_f64(const chfsi_operator& op, const double* X, int64_t ldx, double* Y,
+                             int64_t ldy, int64_t b, hipStream_t st);
+
+// Residual filter step (Algorithm 3 loop body), RX updated in place, ld = n:
+// RX <- a op(dinv .* RY) + b RY + c RX + delta colcoef[j] Yf
+hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* RY,
+                                   double* RX, const double* Yf, int64_t ldf,
+                                   const double* colcoef, StencilStep s, int64_t b,
+                                   hipStream_t st);
+hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* dinv, const float* RY,
+                                   float* RX, const float* Yf, const float* colcoef,
+                                   StencilStep s, int64_t b, hipStream_t st);
+// BF16-stored blocks (uint16 bit patterns), FP32 arithmetic
+hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* dinv, const void* RY,
+                                    void* RX, const void* Yf, const float* colcoef, StencilStep s,
+                                    int64_t b, hipStream_t st);
+// Plain filter step (Algorithm 2): dst <- alpha dinv .* op(src) + beta src + gamma prev
+hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* src,
+                                  int64_t lds, const double* prev, int64_t ldp, double* dst,
+                                  StencilStep s, int64_t b, hipStream_t st);
+
+// BF16 block helpers
+hipError_t rchfsi_init_bf16(const double* R, int64_t ldr, int64_t n, int64_t b, double scale,
+                            void* RY, void* RX, void* Yc, hipStream_t st);
+hipError_t rchfsi_reconstruct_bf16(const void* RY, const double* dinv, const double* X,
+                                   int64_t ldx, const double* lamY, double* Yp, int64_t ldy,
+                                   int64_t n, int64_t b, hipStream_t st);
+
+// FP32 helpers used by the driver
+hipError_t convert_f32_f64(const float* in, int64_t ldi, double* out, int64_t ldo, int64_t n,
+                           int64_t m, hipStream_t st);
+hipError_t fill_ones_f32(float* p, int64_t n, hipStream_t st);
+
+}  // namespace chfsi

@@ -1,0 +1,65 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function that include/chfsi.h declares (no compute calls are made here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chfsi.h")
+LIB = os.path.join(ROOT, "paper_2503_22652_amd", "libchfsi.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(chfsi_[a-z_]+)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2503_22652_amd import build
+        build.build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("chfsi_create", "chfsi_filter", "chfsi_solve", "chfsi_submit",
+                     "chfsi_rayleigh_ritz", "chfsi_wait", "chfsi_cancel", "chfsi_destroy",
+                     "chfsi_workspace_bytes", "chfsi_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_exports_are_c_linkage():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (chfsi_[a-z_]+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_version_and_error_strings_without_gpu(lib):
+    lib.chfsi_version.restype = ctypes.c_char_p
+    lib.chfsi_last_error.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.chfsi_version()
+    assert isinstance(lib.chfsi_last_error(), bytes)
+
+
+def test_workspace_bytes_rejects_bad_params_without_gpu():
+    import paper_2503_22652_amd as P
+    op = P.identity_operator(100)
+    op.kind = P.OP_DENSE          # dense without a pointer: invalid
+    prm = P.make_params(10, 20, 8, lambda_max=5.0)
+    assert P.chfsi_workspace_bytes(op, None, prm) == 0
+    st = P.stencil_operator((8, 8, 8), [0.0] * 27)
+    assert P.chfsi_workspace_bytes(st, None, P.make_params(10, 20, 8, lambda_max=5.0)) > 0
+    assert P.chfsi_workspace_bytes(st, None, P.make_params(30, 20, 8, lambda_max=5.0)) == 0

@@ -1,0 +1,228 @@
+"""GPU parity of the dense path through the C ABI against the CPU oracle.
+
+Sizes span several GEMM tiles with ragged tails (n not a multiple of the
+tile, block not a multiple of 16, a padded leading dimension).  Tolerances:
+FP64 paths agree with the oracle to 1e-11 relative (rounding order only);
+the FP32 residual filter's error is bounded relative to the residual it
+filters (Theorem 3.4: the error of the residual form scales with ||R||), and
+full solves must reach the same eigenvalues to 1e-10 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as wl
+from oracle import filters, rr, solver
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2503_22652_amd as P  # noqa: E402
+
+
+def dev(a):
+    return P.to_colmajor(a)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def gen_problem():
+    p = wl.dense_generalized(n=701, n_low=24, block=40, degree=8, seed=77)
+    w = sla.eigvalsh(p.A, p.B)
+    return p, w
+
+
+def _ctx(p, params, dinv=True):
+    A = dev(p.A)
+    B = dev(p.B) if p.B is not None else None
+    d = torch.from_numpy(p.dinv).cuda() if (dinv and p.dinv is not None) else None
+    opA = P.dense_operator(A)
+    opB = P.dense_operator(B) if B is not None else None
+    ctx = P.chfsi_create(opA, opB, d, params, keep=(A, B, d))
+    return ctx
+
+
+def _ritz_start(p, seed=5):
+    X0 = wl.random_block(p.n, p.block, seed)
+    Bop = filters.dense_op(p.B) if p.B is not None else filters.identity_op()
+    return rr.rayleigh_ritz(X0, filters.dense_op(p.A), Bop)
+
+
+@pytest.mark.parametrize("prec", [P.PREC_FP64, P.PREC_FP32])
+def test_chfsi_filter_matches_oracle(gen_problem, prec):
+    p, w = gen_problem
+    bounds = (w[0] - 0.1, w[-1] + 0.5, 0.5 * (w[p.block - 1] + w[p.block]))
+    params = P.make_params(p.n_wanted, p.block, p.degree, method=P.METHOD_CHFSI, filter_prec=prec,
+                           lambda_max=bounds[1])
+    ctx = _ctx(p, params)
+    X = wl.random_block(p.n, p.block, 3)
+    Xd = dev(X)
+    Yd = P.colmajor_empty(p.n, p.block)
+    P.chfsi_filter(ctx, Xd, None, None, Yd, *bounds, degree=p.degree)
+    torch.cuda.synchronize()
+    ref = filters.chebyshev_filter(lambda V: p.dinv[:, None] * (p.A @ V), X, p.degree, *bounds)
+    err = rel(host(Yd), ref)
+    print("chfsi filter rel err", prec, err)
+    assert err <= (1e-11 if prec == P.PREC_FP64 else 2e-4)
+
+
+@pytest.mark.parametrize("prec,degree", [(P.PREC_FP64, 8), (P.PREC_FP64, 1), (P.PREC_FP64, 2),
+                                         (P.PREC_FP32, 8), (P.PREC_FP32, 20)])
+def test_rchfsi_filter_matches_oracle(gen_problem, prec, degree):
+    p, w = gen_problem
+    bounds = (w[0] - 0.1, w[-1] + 0.5, 0.5 * (w[p.block - 1] + w[p.block]))
+    params = P.make_params(p.n_wanted, p.block, max(degree, 1), method=P.METHOD_RCHFSI,
+                           filter_prec=prec, lambda_max=bounds[1])
+    ctx = _ctx(p, params)
+    st = _ritz_start(p)
+    X, lam, R = st["X"], st["lam"], st["R"]
+    Xd, Rd = dev(X), dev(R)
+    Yd = P.colmajor_empty(p.n, p.block)
+    P.chfsi_filter(ctx, Xd, lam, Rd, Yd, *bounds, degree=degree)
+    torch.cuda.synchronize()
+    ref, RYp, LYp = filters.residual_filter(filters.dense_op(p.A), filters.diag_op(p.dinv), X, lam,
+                                            R, degree, *bounds, return_parts=True)
+    g = host(Yd)
+    resid_part = np.linalg.norm(p.dinv[:, None] * RYp)
+    err_abs = np.linalg.norm(g - ref)
+    print("rchfsi", prec, degree, "rel", rel(g, ref), "err/||resid part||", err_abs / resid_part)
+    if prec == P.PREC_FP64:
+        assert rel(g, ref) <= 1e-11
+    else:
+        # FP32 arithmetic only touches the residual part D^{-1} R_Y
+        assert err_abs <= 1e-4 * resid_part
+
+
+def test_rayleigh_ritz_matches_oracle(gen_problem):
+    p, w = gen_problem
+    params = P.make_params(p.n_wanted, p.block, 4, lambda_max=w[-1] + 1)
+    ctx = _ctx(p, params)
+    rng = np.random.default_rng(9)
+    # a filtered-looking block: span near the low eigenvectors plus noise
+    _, U = sla.eigh(p.A, p.B)
+    Y = U[:, : p.block] @ rng.standard_normal((p.block, p.block)) + 1e-3 * rng.standard_normal(
+        (p.n, p.block))
+    Yd = dev(Y)
+    Xd = P.colmajor_empty(p.n, p.block)
+    Rd = P.colmajor_empty(p.n, p.block)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, Yd, Xd, Rd)
+    o = rr.rayleigh_ritz(Y, filters.dense_op(p.A), filters.dense_op(p.B))
+    scale = np.abs(o["lam"]).max()
+    np.testing.assert_allclose(ritz, o["lam"], rtol=0, atol=1e-11 * scale)
+    np.testing.assert_allclose(norms, o["resnorm"], rtol=1e-6, atol=1e-11 * scale)
+    Xg = host(Xd)
+    np.testing.assert_allclose(Xg.T @ p.B @ Xg, np.eye(p.block), atol=1e-10)
+    # same Ritz vectors up to sign (distinct Ritz values)
+    M = np.abs(Xg.T @ p.B @ o["X"])
+    np.testing.assert_allclose(np.diag(M), 1.0, atol=1e-8)
+    # residual block recomputed on the CPU from the returned pairs
+    Rg = host(Rd)
+    np.testing.assert_allclose(Rg, p.A @ Xg - (p.B @ Xg) * np.asarray(ritz)[None, :],
+                               atol=1e-10 * scale)
+
+
+def test_rayleigh_ritz_padded_leading_dimension(gen_problem):
+    p, w = gen_problem
+    params = P.make_params(p.n_wanted, p.block, 4, lambda_max=w[-1] + 1)
+    ctx = _ctx(p, params)
+    rng = np.random.default_rng(4)
+    Y = rng.standard_normal((p.n, p.block))
+    big = torch.zeros((p.block, p.n + 13), dtype=torch.float64, device="cuda")
+    big[:, : p.n] = torch.from_numpy(Y.T.copy()).cuda()
+    Yd = big.t()[: p.n]
+    assert P._ld(Yd) == p.n + 13
+    Xd = P.colmajor_empty(p.n, p.block)
+    Rd = P.colmajor_empty(p.n, p.block)
+    ritz, _ = P.chfsi_rayleigh_ritz(ctx, Yd, Xd, Rd)
+    o = rr.rayleigh_ritz(Y, filters.dense_op(p.A), filters.dense_op(p.B))
+    np.testing.assert_allclose(ritz, o["lam"], atol=1e-10 * np.abs(o["lam"]).max())
+
+
+def test_solve_dense_standard_full_size():
+    """N = 1024 standard problem, FP64 plain filter, fixed bounds: the prescribed spectrum."""
+    p = wl.dense_standard()
+    lam = p.lam_A
+    bounds = (lam[0] - 0.05, lam[-1] + 0.1, 0.5 * (lam[p.block - 1] + lam[p.block]))
+    params = P.make_params(p.n_wanted, p.block, p.degree, max_iter=30, tol=p.tol,
+                           method=P.METHOD_CHFSI, filter_prec=P.PREC_FP64, lambda_min=bounds[0],
+                           lambda_max=bounds[1], lambda_T=bounds[2])
+    ctx = _ctx(p, params)
+    X0 = wl.random_block(p.n, p.block, 2000)
+    Xd = dev(X0)
+    st, ev, rn, rep = P.chfsi_solve(ctx, Xd)
+    print(rep["iterations"], rep["history"][:12])
+    assert st == P.OK and rep["converged"]
+    ev = np.asarray(ev)
+    relerr = np.abs(ev[:32] - lam[:32]) / np.maximum(np.abs(lam[:32]), 1e-3 * 10.1)
+    assert relerr.max() <= 1e-10
+    X = host(Xd)
+    rcpu = np.linalg.norm(p.A @ X[:, :32] - X[:, :32] * ev[None, :32], axis=0)
+    assert rcpu.max() <= 1e-10
+    # oracle runs the same iteration: same number of passes
+    o = solver.solve(filters.dense_op(p.A), filters.identity_op(), filters.identity_op(), X0, 32,
+                     p.degree, p.tol, 30, bounds, method="chfsi")
+    assert abs(o["iters"] - rep["iterations"]) <= 1
+    np.testing.assert_allclose(ev[:32], o["lam"][:32], rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("method,prec", [("rchfsi", P.PREC_FP64), ("rchfsi", P.PREC_FP32)])
+def test_solve_generalized_reduced(method, prec):
+    p = wl.dense_generalized(n=1536, n_low=48, block=64, degree=20, seed=1001)
+    w = sla.eigvalsh(p.A, p.B)
+    lmax = float(w[-1]) + 0.5
+    params = P.make_params(48, 64, 20, max_iter=40, tol=1e-9, method=P.METHOD_RCHFSI,
+                           filter_prec=prec, lambda_max=lmax)
+    ctx = _ctx(p, params)
+    X0 = wl.random_block(p.n, p.block, 2001)
+    Xd = dev(X0)
+    st, ev, rn, rep = P.chfsi_solve(ctx, Xd)
+    print(prec, rep["iterations"], ["%.2e" % h for h in rep["history"]])
+    assert st == P.OK
+    ev = np.asarray(ev)
+    scale = 1e-3 * max(abs(w[0]), abs(w[-1]))
+    relerr = np.abs(ev[:48] - w[:48]) / np.maximum(np.abs(w[:48]), scale)
+    assert relerr.max() <= 1e-10
+    X = host(Xd)
+    rcpu = np.linalg.norm(p.A @ X[:, :48] - (p.B @ X[:, :48]) * ev[None, :48], axis=0)
+    assert rcpu.max() <= 1e-9 * 1.01
+    np.testing.assert_allclose(X.T @ p.B @ X, np.eye(64), atol=1e-9)
+
+
+def test_plain_filter_with_approximate_inverse_stagnates():
+    """ChFSI with D^{-1} != B^{-1} stalls (Theorem 3.2); R-ChFSI above converges."""
+    p = wl.dense_generalized(n=1536, n_low=48, block=64, degree=20, seed=1001)
+    w = sla.eigvalsh(p.A, p.B)
+    params = P.make_params(48, 64, 20, max_iter=12, tol=1e-9, method=P.METHOD_CHFSI,
+                           filter_prec=P.PREC_FP64, lambda_max=float(w[-1]) + 0.5)
+    ctx = _ctx(p, params)
+    Xd = dev(wl.random_block(p.n, p.block, 2001))
+    st, ev, rn, rep = P.chfsi_solve(ctx, Xd)
+    assert st == P.ERR_NOCONV and rep["max_residual"] > 1e-6
+
+
+def test_invalid_arguments_are_rejected(gen_problem):
+    p, w = gen_problem
+    A = dev(p.A)
+    opA = P.dense_operator(A)
+    with pytest.raises(P.ChfsiError) as e:
+        P.chfsi_create(opA, None, None, P.make_params(50, 40, 8, lambda_max=10.0))
+    assert e.value.status == P.ERR_ARG
+    with pytest.raises(P.ChfsiError):
+        P.chfsi_create(opA, None, None, P.make_params(10, 40, 0, lambda_max=10.0))
+    with pytest.raises(P.ChfsiError):
+        P.chfsi_create(opA, None, None, P.make_params(10, 40, 8))   # lambda_max NaN
+    ctx = P.chfsi_create(opA, None, None, P.make_params(10, 40, 8, method=P.METHOD_CHFSI,
+                                                        lambda_max=10.0), keep=(A,))
+    Xd = dev(np.ones((p.n, 40)))
+    Yd = P.colmajor_empty(p.n, 40)
+    with pytest.raises(P.ChfsiError):
+        P.chfsi_filter(ctx, Xd, None, None, Yd, 1.0, 10.0, 0.5)      # lmin > lT

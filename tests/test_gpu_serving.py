@@ -1,0 +1,127 @@
+"""Continuous-batching server on the GPU.
+
+* A request's result is bitwise identical whether it runs alone or mixed with
+  other requests on other streams (same kernels, same launch shapes).
+* A sequence of perturbed matrices is warm-started from the previous Ritz
+  vectors and needs fewer iterations than a cold start.
+* Pending requests can be cancelled; requests that can never fit the
+  device-memory budget are refused at submission.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2503_22652_amd as P  # noqa: E402
+
+
+def _request(prob, lmax, seq_id=-1, X0=None, tol=1e-9, max_iter=60, prec=P.PREC_FP32):
+    A = P.to_colmajor(prob.A)
+    B = P.to_colmajor(prob.B)
+    d = torch.from_numpy(prob.dinv).cuda()
+    req = P.chfsi_request()
+    req.A = P.dense_operator(A)
+    req.B = P.dense_operator(B)
+    req.d_inv = d.data_ptr()
+    req.params = P.make_params(prob.n_wanted, prob.block, prob.degree, max_iter=max_iter, tol=tol,
+                               method=P.METHOD_RCHFSI, filter_prec=prec, lambda_max=lmax)
+    req.seq_id = seq_id
+    keep = [A, B, d]
+    if X0 is not None:
+        Xd = P.to_colmajor(X0)
+        req.X0 = Xd.data_ptr()
+        keep.append(Xd)
+    return req, keep
+
+
+def _problems():
+    out = []
+    for i, n in enumerate((384, 512, 640)):
+        p = wl.dense_generalized(n=n, n_low=12 + 4 * i, block=16 + 4 * i, degree=12, seed=40 + i)
+        w = sla.eigvalsh(p.A, p.B)
+        out.append((p, float(w[-1]) + 0.5, w))
+    return out
+
+
+def test_alone_equals_mixed_bitwise():
+    probs = _problems()
+    X0s = [wl.random_block(p.n, p.block, 90 + i) for i, (p, _, _) in enumerate(probs)]
+    # alone: one slot, one request at a time
+    alone = []
+    srv = P.Server(slots=1)
+    for (p, lmax, w), X0 in zip(probs, X0s):
+        req, keep = _request(p, lmax, X0=X0)
+        t = srv.submit(req, keep)
+        alone.append(srv.wait(t))
+    srv.close()
+    # mixed: three slots, all submitted at once (plus extra load)
+    srv = P.Server(slots=3)
+    tickets = []
+    for (p, lmax, w), X0 in zip(probs, X0s):
+        req, keep = _request(p, lmax, X0=X0)
+        tickets.append(srv.submit(req, keep))
+    extra = []
+    for (p, lmax, w), X0 in zip(probs, X0s):
+        req, keep = _request(p, lmax, X0=X0[:, ::-1].copy())
+        extra.append(srv.submit(req, keep))
+    mixed = [srv.wait(t) for t in tickets]
+    for t in extra:
+        srv.wait(t)
+    srv.close()
+    for (p, lmax, w), a, m in zip(probs, alone, mixed):
+        assert a["status"] == P.OK and m["status"] == P.OK
+        assert a["evals"] == m["evals"]            # bitwise
+        assert a["iterations"] == m["iterations"]
+        rel = np.abs(np.asarray(m["evals"][: p.n_wanted]) - w[: p.n_wanted]) / np.maximum(
+            np.abs(w[: p.n_wanted]), 1e-3 * abs(w[-1]))
+        assert rel.max() < 1e-10
+
+
+def test_warm_started_sequence():
+    p = wl.dense_generalized(n=512, n_low=16, block=20, degree=12, seed=60)
+    rng = np.random.default_rng(61)
+    normA = np.abs(p.lam_A).max()
+    srv = P.Server(slots=2)
+    its = []
+    A_t = p.A.copy()
+    for t in range(3):
+        if t > 0:
+            A_t = A_t + 1e-3 * normA * wl.unit_sym_perturbation(rng, p.n)
+        q = wl.DenseProblem(A=A_t, B=p.B, dinv=p.dinv, lam_A=p.lam_A, n_wanted=16, block=20,
+                            degree=12, tol=1e-9)
+        w = sla.eigvalsh(A_t, p.B)
+        req, keep = _request(q, float(w[-1]) + 0.5, seq_id=7,
+                             X0=wl.random_block(p.n, 20, 62) if t == 0 else None)
+        r = srv.wait(srv.submit(req, keep))
+        assert r["status"] == P.OK
+        rel = np.abs(np.asarray(r["evals"][:16]) - w[:16]) / np.maximum(np.abs(w[:16]),
+                                                                         1e-3 * abs(w[-1]))
+        assert rel.max() < 1e-10
+        its.append(r["iterations"])
+    srv.close()
+    assert its[1] < its[0] and its[2] < its[0]
+
+
+def test_cancel_and_admission():
+    p, lmax, w = _problems()[1]
+    srv = P.Server(slots=1)
+    req, keep = _request(p, lmax, X0=wl.random_block(p.n, p.block, 1))
+    t1 = srv.submit(req, keep)
+    req2, keep2 = _request(p, lmax, X0=wl.random_block(p.n, p.block, 2))
+    t2 = srv.submit(req2, keep2)
+    srv.cancel(t2)
+    r2 = srv.wait(t2)
+    r1 = srv.wait(t1)
+    assert r1["status"] == P.OK
+    assert r2["status"] in (P.ERR_CANCELLED, P.OK)   # it may have started before the cancel
+    srv.close()
+    tiny = P.Server(slots=1, memory_budget=1024)
+    req3, keep3 = _request(p, lmax)
+    with pytest.raises(P.ChfsiError) as e:
+        tiny.submit(req3, keep3)
+    assert e.value.status == P.ERR_NOMEM
+    tiny.close()
