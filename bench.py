@@ -48,6 +48,15 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip time-to-residual runs")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--workload", choices=("dense", "grid", "serving"), default="dense",
+                    help="dense: the headline line; grid / serving: extra measurement lines")
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--wells", type=int, default=64)
+    ap.add_argument("--prec", choices=("bf16", "fp32", "fp64"), default="bf16")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--sequences", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--sizes", type=str, default="512,1024,2048,4096,8192")
     return ap.parse_args()
 
 
@@ -85,6 +94,10 @@ def main():
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
               f"multi-GPU sharding is not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "grid":
+        return bench_grid(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     import numpy as np
     import torch
 
@@ -241,6 +254,177 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(prob, X0)
+    print(json.dumps(out), flush=True)
+
+
+def bench_grid(args):
+    """Grid pencil (periodic 27-point Q1 FE stencils + Gaussian wells), residual filter in
+    BF16 (or FP32/FP64) storage; one step = filter + FP64 Rayleigh-Ritz.  HBM roofline."""
+    import numpy as np
+    import torch
+
+    import paper_2503_22652_amd as P
+    import workloads as wl
+
+    torch.cuda.set_device(0)
+    g, b, nw = args.grid, 1200 if args.grid >= 96 else max(16, args.grid * 4), None
+    nw = int(round(b / 1.2))
+    p = args.degree if args.degree != 20 else 30
+    prob = wl.stencil_problem(grid=g, n_wells=args.wells, n_wanted=nw, block=b, degree=p, seed=1002)
+    n = prob.n
+    prec = {"bf16": P.PREC_BF16, "fp32": P.PREC_FP32, "fp64": P.PREC_FP64}[args.prec]
+    esize = {"bf16": 2, "fp32": 4, "fp64": 8}[args.prec]
+    Vd = torch.from_numpy(np.ascontiguousarray(prob.V).reshape(-1)).cuda()
+    opA = P.stencil_operator(prob.shape, prob.coef_A, coef_mass=prob.coef_B, field=Vd,
+                             field_mode=prob.field_mode)
+    opB = P.stencil_operator(prob.shape, prob.coef_B)
+    lmax = 18.5
+    prm = P.make_params(nw, b, p, max_iter=200, tol=1e-8, method=P.METHOD_RCHFSI,
+                        filter_prec=prec, lambda_max=lmax, profile=1, seed=2002, init_random=1)
+    stream = torch.cuda.current_stream()
+    ctx = P.chfsi_create(opA, opB, None, prm, stream=stream, keep=(Vd,))
+    X = P.colmajor_empty(n, b)
+    Xn = P.colmajor_empty(n, b)
+    R = P.colmajor_empty(n, b)
+    Y = P.colmajor_empty(n, b)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2002)
+    X.copy_(torch.randn(b, n, dtype=torch.float64, device="cuda", generator=gen).t())
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, X, Xn, R)
+    X, Xn = Xn, X
+    filt = []
+
+    def step():
+        nonlocal X, Xn, ritz, norms
+        e1, eb = ritz[0], ritz[-1]
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        P.chfsi_filter(ctx, X, ritz, R, Y, e1 - 0.05 * (eb - e1), lmax, eb)
+        s1.record(stream)
+        filt.append((s0, s1))
+        ritz, norms = P.chfsi_rayleigh_ritz(ctx, Y, X, R)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.chfsi_filter_kernel_time(ctx)
+    filt.clear()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, kn = P.chfsi_filter_kernel_time(ctx)
+    filt_ms = sum(a.elapsed_time(b_) for a, b_ in filt)
+    step_bytes = 4.0 * esize * n * b * (p - 1)
+    per = kms / max(kn, 1)
+    achieved = 4.0 * esize * n * b / (per / 1e3) / 1e9
+    out = {"metric": METRIC, "value": round(step_bytes * args.steps / (filt_ms / 1e3) / 1e9, 1),
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(wall * 1e3 / args.steps, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+           "config": {"workload": f"periodic {g}^3 grid pencil, 27-point Q1 stiffness/mass, "
+                                  f"{args.wells} Gaussian wells (mass-weighted), block {b}, "
+                                  f"{nw} wanted, degree {p}, {args.prec} residual filter",
+                      "n": n, "block": b, "degree": p,
+                      "filter_ms_per_step": round(filt_ms / args.steps, 2),
+                      "max_residual_after": max(norms[:nw])},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                        "traffic": None,
+                        "kernel": f"k_stencil_sep<{args.prec}> residual-filter step "
+                                  f"(4 streams x {esize} B per element-step)",
+                        "ms_per_launch": round(per, 3)}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """Continuous-batching stream: Poisson arrivals, sequences of perturbed dense pencils
+    warm-started from the previous step, FP32 residual filter + FP64 Rayleigh-Ritz."""
+    import queue
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2503_22652_amd as P
+    import workloads as wl
+    from workloads import gpu as wg
+
+    torch.cuda.set_device(0)
+    sizes_all = tuple(int(x) for x in args.sizes.split(","))
+    arrivals, sizes = wl.serving_schedule(args.requests, args.sequences, 200.0, sizes_all)
+    seqs = []
+    t_gen = time.perf_counter()
+    for sidx in range(args.sequences):
+        n = int(sizes[sidx])
+        k = int(math.ceil(0.05 * n))
+        b = int(math.ceil(1.25 * k / 16) * 16)
+        A, B, dinv, lam = wg.dense_problem(n, k, 3000 + sidx)
+        lmax = 10.0 / (0.95 * float(1.0 / dinv.max())) + 0.1
+        seqs.append({"n": n, "k": k, "b": b, "A": A, "B": B, "dinv": dinv, "lmax": lmax,
+                     "normA": float(lam.abs().max())})
+    torch.cuda.synchronize()
+    log(f"serving inputs generated in {time.perf_counter() - t_gen:.1f} s")
+    srv = P.Server(slots=args.slots)
+    done = []
+    q = queue.Queue()
+
+    def waiter():
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            ticket, meta = item
+            r = srv.wait(ticket)
+            r.update(meta)
+            done.append(r)
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for i in range(args.requests):
+        sidx, t = i % args.sequences, i // args.sequences
+        sq = seqs[sidx]
+        if t > 0:
+            E = wg.unit_perturbation(sq["n"], 4000 + 8 * sidx + t)
+            sq["A"] = (sq["A"] + 1e-3 * sq["normA"] * E).t().contiguous().t()
+            del E
+        torch.cuda.current_stream().synchronize()
+        now = time.perf_counter() - t0
+        if now < arrivals[i]:
+            time.sleep(arrivals[i] - now)
+        req = P.chfsi_request()
+        req.A = P.dense_operator(sq["A"])
+        req.B = P.dense_operator(sq["B"])
+        req.d_inv = sq["dinv"].data_ptr()
+        req.params = P.make_params(sq["k"], sq["b"], 20, max_iter=60, tol=1e-8,
+                                   method=P.METHOD_RCHFSI, filter_prec=P.PREC_FP32,
+                                   lambda_max=sq["lmax"], seed=5000 + i)
+        req.seq_id = sidx
+        ticket = srv.submit(req, keep=(sq["A"], sq["B"], sq["dinv"]))
+        q.put((ticket, {"seq": sidx, "step": t, "n": sq["n"]}))
+    q.put(None)
+    th.join()
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r["finish_ms"] - r["submit_ms"] for r in done])
+    ok = [r for r in done if r["status"] == P.OK]
+    its_first = [r["iterations"] for r in done if r["step"] == 0]
+    its_warm = [r["iterations"] for r in done if r["step"] > 0]
+    out = {"metric": METRIC, "value": round(float(np.percentile(lat, 99)), 2), "unit": "ms (p99 latency)",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": f"serving: {args.requests} dense generalized solves, "
+                                  f"{args.sequences} sequences, Poisson 200/s, N in {sizes_all}, "
+                                  f"k = 5% N, degree 20, FP32 R-ChFSI, warm start, {args.slots} slots"},
+           "p50_ms": round(float(np.percentile(lat, 50)), 2),
+           "p99_ms": round(float(np.percentile(lat, 99)), 2),
+           "throughput_solves_per_s": round(len(done) / wall, 2),
+           "converged": len(ok), "requests": len(done),
+           "mean_iterations_cold": round(float(np.mean(its_first)), 2) if its_first else None,
+           "mean_iterations_warm": round(float(np.mean(its_warm)), 2) if its_warm else None,
+           "max_residual_max": max(r["max_residual"] for r in done)}
     print(json.dumps(out), flush=True)
 
 

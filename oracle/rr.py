@@ -74,3 +74,12 @@ def residual_norms(apply_A, apply_B, X: np.ndarray, lam: np.ndarray) -> np.ndarr
     """r_j = ||A x_j - lam_j B x_j||_2 computed directly from (X, lam)."""
     R = apply_A(X) - apply_B(X) * np.asarray(lam)[None, :]
     return column_norms(R)
+
+
+def pencil_eigenvalues(A: np.ndarray, B, keep: int) -> np.ndarray:
+    """Lowest `keep` eigenvalues of (A, B): Rayleigh-Ritz on the whole space.
+
+    With the full basis Y = I the projected pencil is (A, B) itself, so this is
+    the plain definition (LAPACK dsygvd/dsygvx through SciPy).
+    """
+    return sla.eigh(A, B, eigvals_only=True, subset_by_index=(0, keep - 1))

@@ -368,3 +368,23 @@ hipError_t fill_ones_f32(float* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 }  // namespace chfsi
+
+namespace chfsi {
+namespace {
+__global__ __launch_bounds__(256) void k_scale_rows(double* M, int64_t ldm, int64_t n, int64_t b,
+                                                     const double* __restrict__ v) {
+  const int64_t total = n * b;
+  for (int64_t idx = blockIdx.x * int64_t(256) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * 256) {
+    const int64_t j = idx / n, i = idx - j * n;
+    M[i + j * ldm] *= v[i];
+  }
+}
+}  // namespace
+
+hipError_t scale_rows(double* M, int64_t ldm, int64_t n, int64_t b, const double* v,
+                      hipStream_t st) {
+  k_scale_rows<<<grid_for(n * b), 256, 0, st>>>(M, ldm, n, b, v);
+  return hipGetLastError();
+}
+}  // namespace chfsi

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -59,6 +60,19 @@ size_t plan_bytes(int64_t M, int64_t N, int64_t K) {
 }
 
 bool is_identity(const chfsi_operator* op) { return op == nullptr || op->kind == CHFSI_OP_IDENTITY; }
+
+// Tuning knobs for the filter's operator-product GEMMs (tile shape index and
+// split-K factor); unset or negative = the planner's choice.  Results do not
+// depend on them beyond floating-point summation order.
+int env_int(const char* name) {
+  const char* v = std::getenv(name);
+  return v && *v ? std::atoi(v) : -1;
+}
+int filter_gemm_cfg() { return env_int("CHFSI_FILTER_GEMM_CFG"); }
+int filter_gemm_splits() {
+  const int s = env_int("CHFSI_FILTER_GEMM_SPLITS");
+  return s > 0 ? s : 0;
+}
 
 }  // namespace
 
@@ -109,6 +123,7 @@ struct chfsi_ctx {
   int last_sweeps = 0;
   int flags = 0;
   const std::atomic<int>* cancel = nullptr;
+  uint64_t refill_seed = 0;
   // profiling: event pairs around the filter's operator-product kernels
   std::vector<hipEvent_t> pev;
   int pused = 0;
@@ -217,9 +232,12 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
   s.coef = size_t(p->degree + 1) * b * sizeof(double);
   size_t ws = 0;
   if (dense) {
+    // the filter product may be run with up to 16 k-splits (tuning knob)
     if (p->filter_prec == CHFSI_PREC_FP32)
-      ws = std::max(ws, plan_bytes<float>(n, b, n));
+      ws = std::max(ws, std::max(plan_bytes<float>(n, b, n), size_t(16) * n * b * sizeof(float)));
     ws = std::max(ws, plan_bytes<double>(n, b, n));
+    if (p->filter_prec == CHFSI_PREC_FP64)
+      ws = std::max(ws, size_t(16) * n * b * sizeof(double));
   }
   ws = std::max(ws, plan_bytes<double>(b, b, n));
   ws = std::max(ws, plan_bytes<double>(n, b, b));
@@ -407,7 +425,7 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
         g.epi.C3 = Yc;
         g.epi.ldc3 = n;
         CK(prof_pair(c, &g.ev_begin, &g.ev_end));
-        CK(gemm<float>(g, c->stream, c->ws));
+        CK(gemm<float>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
         fl += 2.0 * double(n) * double(n) * double(b);
       } else {
         StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
@@ -463,7 +481,7 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
         g.epi.C3 = resid;
         g.epi.ldc3 = ldr;
         CK(prof_pair(c, &g.ev_begin, &g.ev_end));
-        CK(gemm<double>(g, c->stream, c->ws));
+        CK(gemm<double>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
         fl += 2.0 * double(n) * double(n) * double(b);
       } else {
         StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
@@ -553,7 +571,7 @@ chfsi_status filter_chfsi(chfsi_ctx* c, const double* X, int64_t ldx, double* Yp
           g.epi.ldc2 = ldp;
         }
         CK(prof_pair(c, &g.ev_begin, &g.ev_end));
-        CK(gemm<double>(g, c->stream, c->ws));
+        CK(gemm<double>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
         fl += 2.0 * double(n) * double(n) * double(b);
       } else {
         StencilStep ss{alpha, beta, gam, 0.0};
@@ -616,7 +634,7 @@ chfsi_status filter_chfsi(chfsi_ctx* c, const double* X, int64_t ldx, double* Yp
         g.epi.ldc2 = n;
       }
       CK(prof_pair(c, &g.ev_begin, &g.ev_end));
-      CK(gemm<float>(g, c->stream, c->ws));
+      CK(gemm<float>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
       fl += 2.0 * double(n) * double(n) * double(b);
       return CHFSI_OK;
     };
@@ -642,9 +660,173 @@ chfsi_status filter_chfsi(chfsi_ctx* c, const double* X, int64_t ldx, double* Yp
   return CHFSI_OK;
 }
 
-// Rayleigh-Ritz + residuals (see chfsi_rayleigh_ritz)
 chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X, int64_t ldx,
-                           double* R, int64_t ldr, double* ritz, double* resnorm) {
+                           double* R, int64_t ldr, double* ritz, double* resnorm,
+                           bool allow_svqb);
+
+// norms, finiteness check and read-back of Ritz values and residual norms
+chfsi_status finish_rr(chfsi_ctx* c, double* R, int64_t ldr, double* ritz, double* resnorm) {
+  const int64_t n = c->n, b = c->b;
+  hipStream_t st = c->stream;
+  CK(column_norms(R, ldr, n, b, c->norms, st));
+  CK(check_finite(c->w, b, c->dflags + 2, st));
+  CK(check_finite(c->norms, b, c->dflags + 2, st));
+  CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(c->h_norms, c->norms, b * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (c->h_flags[2] != 0) {
+    set_error("non-finite Ritz value or residual norm");
+    return CHFSI_ERR_NUMERIC;
+  }
+  std::memcpy(ritz, c->h_w, b * sizeof(double));
+  std::memcpy(resnorm, c->h_norms, b * sizeof(double));
+  return CHFSI_OK;
+}
+
+chfsi_status rotate_and_residual(chfsi_ctx* c, const double* Y, int64_t ldy, const double* BY,
+                                 int64_t ldby, const double* Tm, int64_t k, double* X,
+                                 int64_t ldx, double* R, int64_t ldr);
+
+// SVQB reading for a numerically singular scaled Gram matrix G = s Y^T B Y s
+// (kept in c->Linv): G = U diag(g) U^T; keep the k directions with
+// g > 1e-14 max g; W = diag(s) U_k diag(g_k^{-1/2}) is a B-orthonormal basis
+// of the kept span; solve the k x k standard problem W^T (Y^T A Y) W; the
+// b - k dropped columns are refilled with N(0,1) values and Rayleigh-Ritz is
+// repeated once on the refilled block.
+chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, const double* BY,
+                                int64_t ldby, double* X, int64_t ldx, double* R, int64_t ldr,
+                                double* ritz, double* resnorm) {
+  const int64_t n = c->n, b = c->b;
+  hipStream_t st = c->stream;
+  chfsi_status s;
+  int sweeps = 0;
+  CK(syev_jacobi(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  c->last_sweeps += sweeps;
+  CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  const double gmax = c->h_w[b - 1];
+  int64_t first = 0;
+  while (first < b && !(c->h_w[first] > 1e-14 * gmax)) ++first;
+  const int64_t k = b - first;
+  if (k <= 0) {
+    set_error("Gram matrix Y^T B Y is numerically zero");
+    return CHFSI_ERR_NOT_SPD;
+  }
+  c->flags |= 1;
+  // W (b x k) in c->T: columns first.. of U, scaled by g^{-1/2}, rows by s
+  std::vector<double> colv(k);
+  for (int64_t j = 0; j < k; ++j) colv[j] = 1.0 / std::sqrt(c->h_w[first + j]);
+  CK(hipEventSynchronize(c->ev_stage));
+  std::memcpy(c->h_stage, colv.data(), k * sizeof(double));
+  CK(hipMemcpyAsync(c->lamY, c->h_stage, k * sizeof(double), hipMemcpyHostToDevice, st));
+  CK(hipEventRecord(c->ev_stage, st));
+  CK(copy_block(c->E + first * b, b, c->T, b, b, k, st));
+  CK(scale_columns(c->T, b, b, k, c->lamY, st));
+  CK(scale_rows(c->T, b, b, k, c->svec, st));
+  {
+    GemmDesc<double> g;   // Tmp (b x k) = Ga W
+    g.M = b;
+    g.N = k;
+    g.K = b;
+    g.A = c->Ga;
+    g.sam = 1;
+    g.sak = b;
+    g.B = c->T;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = c->Tmp;
+    g.ldc = b;
+    CK(gemm<double>(g, st, c->ws));
+    GemmDesc<double> h;   // Hp (k x k) = W^T Tmp
+    h.M = k;
+    h.N = k;
+    h.K = b;
+    h.A = c->T;           // A(m,kk) = W(kk,m)
+    h.sak = 1;
+    h.sam = b;
+    h.B = c->Tmp;
+    h.sbk = 1;
+    h.sbn = b;
+    h.C = c->Hp;
+    h.ldc = b;
+    CK(gemm<double>(h, st, c->ws));
+  }
+  CK(symmetrize(c->Hp, b, k, st));
+  CK(syev_jacobi(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  c->last_sweeps += sweeps;
+  {
+    GemmDesc<double> g;   // Tfin (b x k) = W E, stored in c->Linv
+    g.M = b;
+    g.N = k;
+    g.K = k;
+    g.A = c->T;
+    g.sam = 1;
+    g.sak = b;
+    g.B = c->E;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = c->Linv;
+    g.ldc = b;
+    CK(gemm<double>(g, st, c->ws));
+  }
+  if ((s = rotate_and_residual(c, Y, ldy, BY, ldby, c->Linv, k, X, ldx, R, ldr)) != CHFSI_OK)
+    return s;
+  if (k == b) return finish_rr(c, R, ldr, ritz, resnorm);
+  // refill the dropped columns and repeat Rayleigh-Ritz on the refilled block
+  c->refill_seed += 1;
+  CK(fill_gaussian(X + k * ldx, ldx, n, b - k, c->prm.seed * 7919 + c->refill_seed, st));
+  double* tmp = c->Yw;   // free scratch: the input block is no longer needed
+  if (tmp == Y) tmp = const_cast<double*>(Y);
+  s = rayleigh_ritz(c, X, ldx, tmp, n, R, ldr, ritz, resnorm, false);
+  if (s != CHFSI_OK) return s;
+  CK(copy_block(tmp, n, X, ldx, n, b, st));
+  return CHFSI_OK;
+}
+
+// X = Y Tm and R = AY Tm - BY (Tm diag(w)) for the first k columns
+chfsi_status rotate_and_residual(chfsi_ctx* c, const double* Y, int64_t ldy, const double* BY,
+                                 int64_t ldby, const double* Tm, int64_t k, double* X,
+                                 int64_t ldx, double* R, int64_t ldr) {
+  const int64_t n = c->n, b = c->b;
+  hipStream_t st = c->stream;
+  auto rotate = [&](const double* Src, int64_t lds, const double* Tmat, double* Dst, int64_t ldd,
+                    double alpha, const double* accum) -> chfsi_status {
+    GemmDesc<double> g;
+    g.M = n;
+    g.N = k;
+    g.K = b;
+    g.A = Src;
+    g.sam = 1;
+    g.sak = lds;
+    g.B = Tmat;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = Dst;
+    g.ldc = ldd;
+    g.epi.alpha = alpha;
+    if (accum) {
+      g.epi.beta = 1.0;
+      g.epi.C1 = accum;
+      g.epi.ldc1 = ldd;
+    }
+    CK(gemm<double>(g, st, c->ws));
+    return CHFSI_OK;
+  };
+  chfsi_status s;
+  if ((s = rotate(Y, ldy, Tm, X, ldx, 1.0, nullptr)) != CHFSI_OK) return s;
+  if ((s = rotate(c->AY, n, Tm, R, ldr, 1.0, nullptr)) != CHFSI_OK) return s;
+  CK(copy_block(Tm, b, c->TL, b, b, k, st));
+  CK(scale_columns(c->TL, b, b, k, c->w, st));
+  if ((s = rotate(BY, ldby, c->TL, R, ldr, -1.0, R)) != CHFSI_OK) return s;
+  return CHFSI_OK;
+}
+
+// Rayleigh-Ritz + residuals (see chfsi_rayleigh_ritz).  allow_svqb: on a
+// numerically singular Gram matrix fall back to SVQB (see below) once.
+chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X, int64_t ldx,
+                           double* R, int64_t ldr, double* ritz, double* resnorm,
+                           bool allow_svqb = true) {
   const int64_t n = c->n, b = c->b;
   hipStream_t st = c->stream;
   chfsi_status s;
@@ -680,13 +862,21 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   if ((s = gram(BY, ldby, c->Gb)) != CHFSI_OK) return s;
   // column scaling s = diag(Gb)^{-1/2}; Cholesky of the scaled Gram matrix
   CK(scale_gram(c->Gb, b, b, c->Gs, b, c->svec, c->dflags + 1, st));
+  CK(copy_block(c->Gs, b, c->Linv, b, b, b, st));      // kept for the SVQB fallback
   CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws));
   CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  if (c->h_flags[0] != 0 || c->h_flags[1] != 0) {
-    set_error("Gram matrix Y^T B Y is not positive definite (pivot %d, bad diagonal %d)",
-              c->h_flags[0], c->h_flags[1]);
+  if (c->h_flags[1] != 0) {
+    set_error("Gram matrix Y^T B Y has a non-positive diagonal (a zero or non-finite column)");
     return CHFSI_ERR_NOT_SPD;
+  }
+  if (c->h_flags[0] != 0) {
+    if (!allow_svqb) {
+      set_error("Gram matrix Y^T B Y is not positive definite (pivot %d) after refill",
+                c->h_flags[0]);
+      return CHFSI_ERR_NOT_SPD;
+    }
+    return rayleigh_ritz_svqb(c, Y, ldy, BY, ldby, X, ldx, R, ldr, ritz, resnorm);
   }
   // Linv = L^{-1}
   CK(set_identity(c->Linv, b, b, st));
@@ -724,7 +914,7 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   CK(symmetrize(c->Hp, b, b, st));
   int sweeps = 0;
   CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
-  c->last_sweeps = sweeps;
+  c->last_sweeps += sweeps;
   {
     GemmDesc<double> g;   // T = diag(s) Linv^T E
     g.M = b;
@@ -741,49 +931,9 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
     g.epi.rowscale = c->svec;
     CK(gemm<double>(g, st, c->ws));
   }
-  // X = Y T ; R = AY T - BY (T diag(w))
-  auto rotate = [&](const double* Src, int64_t lds, const double* Tm, double* Dst, int64_t ldd,
-                    double alpha, const double* accum) -> chfsi_status {
-    GemmDesc<double> g;
-    g.M = n;
-    g.N = b;
-    g.K = b;
-    g.A = Src;
-    g.sam = 1;
-    g.sak = lds;
-    g.B = Tm;
-    g.sbk = 1;
-    g.sbn = b;
-    g.C = Dst;
-    g.ldc = ldd;
-    g.epi.alpha = alpha;
-    if (accum) {
-      g.epi.beta = 1.0;
-      g.epi.C1 = accum;
-      g.epi.ldc1 = ldd;
-    }
-    CK(gemm<double>(g, st, c->ws));
-    return CHFSI_OK;
-  };
-  if ((s = rotate(Y, ldy, c->T, X, ldx, 1.0, nullptr)) != CHFSI_OK) return s;
-  if ((s = rotate(c->AY, n, c->T, R, ldr, 1.0, nullptr)) != CHFSI_OK) return s;
-  CK(copy_block(c->T, b, c->TL, b, b, b, st));
-  CK(scale_columns(c->TL, b, b, b, c->w, st));
-  if ((s = rotate(BY, ldby, c->TL, R, ldr, -1.0, R)) != CHFSI_OK) return s;
-  CK(column_norms(R, ldr, n, b, c->norms, st));
-  CK(check_finite(c->w, b, c->dflags + 2, st));
-  CK(check_finite(c->norms, b, c->dflags + 2, st));
-  CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(c->h_norms, c->norms, b * sizeof(double), hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  if (c->h_flags[2] != 0) {
-    set_error("non-finite Ritz value or residual norm");
-    return CHFSI_ERR_NUMERIC;
-  }
-  std::memcpy(ritz, c->h_w, b * sizeof(double));
-  std::memcpy(resnorm, c->h_norms, b * sizeof(double));
-  return CHFSI_OK;
+  if ((s = rotate_and_residual(c, Y, ldy, BY, ldby, c->T, b, X, ldx, R, ldr)) != CHFSI_OK)
+    return s;
+  return finish_rr(c, R, ldr, ritz, resnorm);
 }
 
 void bounds_policy(const chfsi_params& p, const double* ritz, int64_t b, double* lmin,
@@ -1015,7 +1165,12 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, dou
     set_error("X must not alias Y");
     return CHFSI_ERR_ARG;
   }
-  return rayleigh_ritz(c, Y, ldy, X, ldx, R, ldr, ritz, resnorm);
+  if (Y == c->Yw) {
+    set_error("internal error: Y aliases the context workspace");
+    return CHFSI_ERR_ARG;
+  }
+  c->last_sweeps = 0;
+  return rayleigh_ritz(c, Y, ldy, X, ldx, R, ldr, ritz, resnorm, true);
 }
 
 chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, double* resnorms,
@@ -1037,6 +1192,7 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   std::vector<double> ritz(b), norms(b);
   float ms = 0.0f;
   CK(hipEventRecord(c->ev[2], c->stream));
+  c->last_sweeps = 0;
   chfsi_status st = rayleigh_ritz(c, X, ldx, c->Xw, n, c->R, n, ritz.data(), norms.data());
   if (st != CHFSI_OK) return st;
   CK(hipEventRecord(c->ev[3], c->stream));
@@ -1074,6 +1230,7 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
       st = filter_chfsi(c, c->Xw, n, c->Yw, n, lmin, lmax, lT, c->prm.degree, &r.filter_flops);
     if (st != CHFSI_OK) break;
     CK(hipEventRecord(c->ev[1], c->stream));
+    c->last_sweeps = 0;
     st = rayleigh_ritz(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(), norms.data());
     if (st != CHFSI_OK) break;
     CK(hipEventRecord(c->ev[3], c->stream));

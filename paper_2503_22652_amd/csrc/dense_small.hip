@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 namespace chfsi {
@@ -154,15 +155,19 @@ __device__ __forceinline__ int rr_slot(int slot, int r, int n) {
   return slot == 0 ? 0 : 1 + (slot - 1 + r) % (n - 1);
 }
 
-// Diagonalise the JP x JP symmetric matrix a (LDS, ld LDJ) in place and
-// accumulate the rotations into u (LDS, starts as identity).  Returns (via
-// *nrot, LDS) the number of rotations applied.
-__device__ void lds_jacobi(double* a, double* u, int n, double thresh, int max_sweeps,
-                           int* nrot_total) {
-  __shared__ int pp[JP / 2], qq[JP / 2];
-  __shared__ double cc[JP / 2], ss[JP / 2];
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// Cyclic Jacobi sweeps on the JP x JP symmetric matrix a (LDS, ld LDJ),
+// accumulating the rotations into u (LDS, starts as identity).  Each round
+// applies JP/2 disjoint rotations J = [[c, s], [-s, c]] (a <- J^T a J, u <- u J)
+// in one pass over 2x2 blocks.  Stops after a sweep without rotations or
+// after max_sweeps.  Returns the number of rotations applied.
+__device__ int lds_jacobi(double* a, double* u, double thresh, int max_sweeps) {
+  constexpr int n = JP, half = JP / 2;
+  __shared__ int pp[half], qq[half];
+  __shared__ double cc[half], ss[half];
   __shared__ int sweep_rot;
-  const int half = n / 2;
+  int total = 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) sweep_rot = 0;
     __syncthreads();
@@ -176,7 +181,7 @@ __device__ void lds_jacobi(double* a, double* u, int n, double thresh, int max_s
           q = t;
         }
         const double apq = a[p + q * LDJ];
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
         if (fabs(apq) > thresh) {
           const double app = a[p + p * LDJ], aqq = a[q + q * LDJ];
           const double theta = (aqq - app) / (2.0 * apq);
@@ -186,49 +191,50 @@ __device__ void lds_jacobi(double* a, double* u, int n, double thresh, int max_s
           else
             t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
+          sn = t * c;
           atomicAdd(&sweep_rot, 1);
         }
         pp[k] = p;
         qq[k] = q;
         cc[k] = c;
-        ss[k] = s;
+        ss[k] = sn;
       }
       __syncthreads();
-      // rows p, q
-      for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
-        const int k = idx / n, j = idx - k * n;
-        const double s = ss[k];
-        if (s == 0.0) continue;
-        const double c = cc[k];
-        const int p = pp[k], q = qq[k];
-        const double ap = a[p + j * LDJ], aq = a[q + j * LDJ];
-        a[p + j * LDJ] = c * ap - s * aq;
-        a[q + j * LDJ] = s * ap + c * aq;
+      // two-sided update, one 2x2 block (pair k1 rows, pair k2 columns) per item
+      for (int idx = threadIdx.x; idx < half * half; idx += blockDim.x) {
+        const int k1 = idx / half, k2 = idx - k1 * half;
+        const double s1 = ss[k1], s2 = ss[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const double c1 = cc[k1], c2 = cc[k2];
+        const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+        const double x11 = a[p1 + p2 * LDJ], x12 = a[p1 + q2 * LDJ];
+        const double x21 = a[q1 + p2 * LDJ], x22 = a[q1 + q2 * LDJ];
+        const double y11 = c1 * x11 - s1 * x21, y12 = c1 * x12 - s1 * x22;
+        const double y21 = s1 * x11 + c1 * x21, y22 = s1 * x12 + c1 * x22;
+        a[p1 + p2 * LDJ] = c2 * y11 - s2 * y12;
+        a[q1 + q2 * LDJ] = s2 * y21 + c2 * y22;
+        // the pair's own rotation annihilates its off-diagonal entry
+        a[p1 + q2 * LDJ] = (k1 == k2) ? 0.0 : s2 * y11 + c2 * y12;
+        a[q1 + p2 * LDJ] = (k1 == k2) ? 0.0 : c2 * y21 - s2 * y22;
       }
-      __syncthreads();
-      // columns p, q of a and of u
-      for (int idx = threadIdx.x; idx < half * n; idx += blockDim.x) {
+      for (int idx = threadIdx.x; idx < n * half; idx += blockDim.x) {
         const int k = idx / n, i = idx - k * n;
-        const double s = ss[k];
-        if (s == 0.0) continue;
+        const double sn = ss[k];
+        if (sn == 0.0) continue;
         const double c = cc[k];
         const int p = pp[k], q = qq[k];
-        const double ap = a[i + p * LDJ], aq = a[i + q * LDJ];
-        // the rotation annihilates a_pq; store the exact zero
-        a[i + p * LDJ] = (i == q) ? 0.0 : c * ap - s * aq;
-        a[i + q * LDJ] = (i == p) ? 0.0 : s * ap + c * aq;
         const double up = u[i + p * LDJ], uq = u[i + q * LDJ];
-        u[i + p * LDJ] = c * up - s * uq;
-        u[i + q * LDJ] = s * up + c * uq;
+        u[i + p * LDJ] = c * up - sn * uq;
+        u[i + q * LDJ] = sn * up + c * uq;
       }
       __syncthreads();
     }
     const int rot = sweep_rot;
-    if (threadIdx.x == 0) *nrot_total += rot;
+    total += rot;
     __syncthreads();
     if (rot == 0) break;
   }
+  return total;
 }
 
 // Block indices of pair k in round r of the block tournament (nblk blocks).
@@ -243,107 +249,177 @@ __device__ __forceinline__ int pair_index(int l, int I, int J) {
   return l < JB ? I * JB + l : J * JB + (l - JB);
 }
 
+// One workgroup per pair of the round: gather the JP x JP subproblem, skip it
+// when already diagonal (to the threshold), else run `inner` Jacobi sweeps.
+// Writes U (JP x JP) and skip[pair] (1 = U is the identity).
 __global__ __launch_bounds__(256) void k_jacobi_pair_solve(const double* A, int64_t lda,
                                                            int nblk, int round,
                                                            const double* scale, double tol,
-                                                           double* U, int* counter,
-                                                           int max_sweeps) {
+                                                           double* U, int* skip, int* counter,
+                                                           int inner) {
   __shared__ double a[JP * LDJ];
   __shared__ double u[JP * LDJ];
-  __shared__ int nrot;
+  __shared__ double red[256];
   int I, J;
   block_pair(blockIdx.x, round, nblk, &I, &J);
+  double mx = 0.0;
   for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
     const int i = idx % JP, j = idx / JP;
-    a[i + j * LDJ] = A[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
+    const double v = A[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
+    a[i + j * LDJ] = v;
     u[i + j * LDJ] = (i == j) ? 1.0 : 0.0;
+    if (i != j) mx = fmax(mx, fabs(v));
   }
-  if (threadIdx.x == 0) nrot = 0;
+  red[threadIdx.x] = mx;
   __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
   const double thresh = tol * (*scale);
-  lds_jacobi(a, u, JP, thresh, max_sweeps, &nrot);
-  __syncthreads();
+  if (!(red[0] > thresh)) {
+    if (threadIdx.x == 0) skip[blockIdx.x] = 1;
+    return;
+  }
+  const int nrot = lds_jacobi(a, u, thresh, inner);
   double* Uo = U + int64_t(blockIdx.x) * JP * JP;
   for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
     const int i = idx % JP, j = idx / JP;
     Uo[i + j * JP] = u[i + j * LDJ];
   }
-  if (threadIdx.x == 0 && nrot > 0) atomicAdd(counter, nrot);
+  if (threadIdx.x == 0) {
+    skip[blockIdx.x] = 0;
+    if (nrot > 0) atomicAdd(counter, nrot);
+  }
+}
+
+// out = op(X) * Y for JP x JP matrices in LDS (ld LDJ) on FP64 MFMA
+// (v_mfma_f64_16x16x4f64: lane l supplies X(l%16, l/16) and Y(l/16, l%16);
+// output element r of lane l is row l/16 + 4r, column l%16).  Each of the
+// four waves computes one 32 x 32 quadrant.  TX: X is read transposed.
+template <bool TX>
+__device__ __forceinline__ void lds_mm64(const double* X, const double* Y, double out[2][2][4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
+  const int l16 = lane & 15, g = lane >> 4;
+  f64x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < JP; k0 += 4) {
+    const int k = k0 + g;
+    double xa[2], yb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int m = qm + i * 16 + l16;
+      xa[i] = TX ? X[k + m * LDJ] : X[m + k * LDJ];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) yb[j] = Y[k + (qn + j * 16 + l16) * LDJ];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], yb[j], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = acc[i][j][r];
+}
+
+__device__ __forceinline__ void lds_mm64_store(double* Z, const double v[2][2][4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
+  const int l16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Z[(qm + i * 16 + g + 4 * r) + (qn + j * 16 + l16) * LDJ] = v[i][j][r];
+}
+
+__device__ __forceinline__ void load_u_or_identity(double* dst, const double* U, bool identity) {
+  for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+    const int i = idx % JP, j = idx / JP;
+    dst[i + j * LDJ] = identity ? (i == j ? 1.0 : 0.0) : U[i + j * JP];
+  }
 }
 
 // A[SP, SQ] <- U_P^T A[SP, SQ] U_Q for pair blocks P (blockIdx.x), Q (blockIdx.y)
 __global__ __launch_bounds__(256) void k_jacobi_apply_A(double* A, int64_t lda, int nblk,
-                                                        int round, const double* U) {
+                                                        int round, const double* U,
+                                                        const int* skip) {
+  const bool sp = skip[blockIdx.x] != 0, sq = skip[blockIdx.y] != 0;
+  if (sp && sq) return;
   __shared__ double m[JP * LDJ];
   __shared__ double up[JP * LDJ];
   __shared__ double uq[JP * LDJ];
   int IP, JPb, IQ, JQ;
   block_pair(blockIdx.x, round, nblk, &IP, &JPb);
   block_pair(blockIdx.y, round, nblk, &IQ, &JQ);
-  const double* Up = U + int64_t(blockIdx.x) * JP * JP;
-  const double* Uq = U + int64_t(blockIdx.y) * JP * JP;
   for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
     const int i = idx % JP, j = idx / JP;
     m[i + j * LDJ] = A[pair_index(i, IP, JPb) + int64_t(pair_index(j, IQ, JQ)) * lda];
-    up[i + j * LDJ] = Up[i + j * JP];
-    uq[i + j * LDJ] = Uq[i + j * JP];
   }
+  load_u_or_identity(up, U + int64_t(blockIdx.x) * JP * JP, sp);
+  load_u_or_identity(uq, U + int64_t(blockIdx.y) * JP * JP, sq);
   __syncthreads();
-  // T = U_P^T M : each thread computes 16 entries
-  double t[16];
-  const int col = threadIdx.x / 4;         // 0..63
-  const int rowb = (threadIdx.x % 4) * 16;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = rowb + q;
-    double s = 0.0;
-    for (int k = 0; k < JP; ++k) s += up[k + i * LDJ] * m[k + col * LDJ];
-    t[q] = s;
-  }
+  double t[2][2][4];
+  lds_mm64<true>(up, m, t);       // U_P^T M
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 16; ++q) m[rowb + q + col * LDJ] = t[q];
+  lds_mm64_store(m, t);
   __syncthreads();
-  // R = T U_Q
+  lds_mm64<false>(m, uq, t);      // (U_P^T M) U_Q
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
+  const int l16 = lane & 15, g = lane >> 4;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = rowb + q;
-    double s = 0.0;
-    for (int k = 0; k < JP; ++k) s += m[i + k * LDJ] * uq[k + col * LDJ];
-    t[q] = s;
-  }
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-  for (int q = 0; q < 16; ++q)
-    A[pair_index(rowb + q, IP, JPb) + int64_t(pair_index(col, IQ, JQ)) * lda] = t[q];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = qm + i * 16 + g + 4 * r, lj = qn + j * 16 + l16;
+        A[pair_index(li, IP, JPb) + int64_t(pair_index(lj, IQ, JQ)) * lda] = t[i][j][r];
+      }
 }
 
-// V[rows chunk, SP] <- V[rows chunk, SP] U_P ; blockIdx.x = pair, blockIdx.y = 64-row chunk
+// V[rows chunk, SP] <- V[rows chunk, SP] U_P ; blockIdx.x = pair, blockIdx.y = JP-row chunk
 __global__ __launch_bounds__(256) void k_jacobi_apply_V(double* V, int64_t ldv, int nblk,
-                                                        int round, const double* U) {
+                                                        int round, const double* U,
+                                                        const int* skip) {
+  if (skip[blockIdx.x]) return;
   __shared__ double m[JP * LDJ];
   __shared__ double up[JP * LDJ];
   int IP, JPb;
   block_pair(blockIdx.x, round, nblk, &IP, &JPb);
-  const double* Up = U + int64_t(blockIdx.x) * JP * JP;
   const int64_t r0 = int64_t(blockIdx.y) * JP;
   for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
     const int i = idx % JP, j = idx / JP;
     m[i + j * LDJ] = V[r0 + i + int64_t(pair_index(j, IP, JPb)) * ldv];
-    up[i + j * LDJ] = Up[i + j * JP];
   }
+  load_u_or_identity(up, U + int64_t(blockIdx.x) * JP * JP, false);
   __syncthreads();
-  const int col = threadIdx.x / 4;
-  const int rowb = (threadIdx.x % 4) * 16;
-  double t[16];
+  double t[2][2][4];
+  lds_mm64<false>(m, up, t);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
+  const int l16 = lane & 15, g = lane >> 4;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = rowb + q;
-    double s = 0.0;
-    for (int k = 0; k < JP; ++k) s += m[i + k * LDJ] * up[k + col * LDJ];
-    t[q] = s;
-  }
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-  for (int q = 0; q < 16; ++q) V[r0 + rowb + q + int64_t(pair_index(col, IP, JPb)) * ldv] = t[q];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = qm + i * 16 + g + 4 * r, lj = qn + j * 16 + l16;
+        V[r0 + li + int64_t(pair_index(lj, IP, JPb)) * ldv] = t[i][j][r];
+      }
 }
 
 // padded copy: P (bp x bp) = [A 0; 0 0]; V = I
@@ -483,7 +559,8 @@ static int64_t jacobi_padded(int64_t b) { return std::max<int64_t>(JP, (b + JP -
 size_t syev_workspace_bytes(int64_t b) {
   const int64_t bp = jacobi_padded(b);
   const int64_t npairs = bp / JP;
-  return size_t(2 * bp * bp + npairs * JP * JP + 16) * sizeof(double) + size_t(b + 64) * sizeof(int);
+  return size_t(2 * bp * bp + npairs * JP * JP + 16) * sizeof(double) +
+         size_t(b + 64 + npairs) * sizeof(int);
 }
 
 hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
@@ -498,6 +575,7 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   double* scal = U + int64_t(npairs) * JP * JP;   // [0]: Frobenius norm
   int* counter = reinterpret_cast<int*>(scal + 16);
   int* perm = counter + 64;
+  int* skip = perm + b;
   hipError_t e;
   k_jacobi_setup<<<grid_for(bp * bp), 256, 0, st>>>(A, lda, b, P, Vp, bp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -505,17 +583,21 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tol = 1e-15;
   const int max_outer = 40;
+  // inner Jacobi sweeps per pair subproblem (one suffices for the block
+  // method's convergence; the knob is for tuning)
+  int inner = 1;
+  if (const char* e = std::getenv("CHFSI_JACOBI_INNER")) inner = std::max(1, std::atoi(e));
   int sweeps = 0;
   int host_count = 0;
   for (; sweeps < max_outer; ++sweeps) {
     if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
     for (int r = 0; r < nblk - 1; ++r) {
-      k_jacobi_pair_solve<<<dim3(npairs), 256, 0, st>>>(P, bp, nblk, r, scal, tol, U, counter,
-                                                        30);
+      k_jacobi_pair_solve<<<dim3(npairs), 256, 0, st>>>(P, bp, nblk, r, scal, tol, U, skip,
+                                                        counter, inner);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      k_jacobi_apply_A<<<dim3(npairs, npairs), 256, 0, st>>>(P, bp, nblk, r, U);
+      k_jacobi_apply_A<<<dim3(npairs, npairs), 256, 0, st>>>(P, bp, nblk, r, U, skip);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      k_jacobi_apply_V<<<dim3(npairs, unsigned(bp / JP)), 256, 0, st>>>(Vp, bp, nblk, r, U);
+      k_jacobi_apply_V<<<dim3(npairs, unsigned(bp / JP)), 256, 0, st>>>(Vp, bp, nblk, r, U, skip);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = hipMemcpyAsync(&host_count, counter, sizeof(int), hipMemcpyDeviceToHost, st)) !=

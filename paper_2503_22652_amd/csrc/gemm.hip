@@ -109,8 +109,9 @@ __device__ __forceinline__ T apply_epilogue(const Epilogue<T>& e, T acc, int64_t
 }
 
 // Load a ROWS x BK tile of a "row operand" (row r, depth k) into registers.
-// KCONTIG: element (r,k) at base[r*srow + k]; else at base[r + k*sk].
-template <typename T, int ROWS, int BK, bool KCONTIG>
+// KCONTIG: element (r,k) at base[r*sr + k]; else at base[r + k*sr].
+// KS: multiply every element by kscale[k] on the way in.
+template <typename T, int ROWS, int BK, bool KCONTIG, bool KS>
 struct TileLoader {
   static constexpr int W = Vec16<T>::W;
   static constexpr int TOT = ROWS * BK / W;       // vectors per tile
@@ -118,10 +119,35 @@ struct TileLoader {
   static_assert((ROWS * BK) % W == 0, "tile not divisible into vectors");
   static_assert(KCONTIG ? (BK % W == 0) : (ROWS % W == 0), "vector along the contiguous dim");
   Vec16<T> r[NV];
+  Vec16<T> f[KS ? NV : 1];   // k-scaling factors, applied at store time
 
-  __device__ __forceinline__ void load(const T* __restrict__ base, int64_t sr, int64_t r0,
-                                       int64_t rmax, int64_t k0, int64_t kmax, bool vec,
-                                       const T* __restrict__ kscale) {
+  // Unchecked 16-byte loads: the whole tile lies inside the operand.  The
+  // k-scaling factors are fetched alongside and applied in store(), so no
+  // arithmetic waits on the loads before the tile is due in LDS.
+  __device__ __forceinline__ void load_fast(const T* __restrict__ base, int64_t sr, int64_t r0,
+                                            int64_t k0, const T* __restrict__ kscale) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int v = threadIdx.x + i * 256;
+      if (TOT % 256 != 0 && v >= TOT) break;
+      if constexpr (KCONTIG) {
+        const int row = v / (BK / W);
+        const int kk = (v % (BK / W)) * W;
+        r[i] = *reinterpret_cast<const Vec16<T>*>(base + (r0 + row) * sr + k0 + kk);
+        if constexpr (KS) f[i] = *reinterpret_cast<const Vec16<T>*>(kscale + k0 + kk);
+      } else {
+        const int kk = v / (ROWS / W);
+        const int row = (v % (ROWS / W)) * W;
+        r[i] = *reinterpret_cast<const Vec16<T>*>(base + r0 + row + (k0 + kk) * sr);
+        if constexpr (KS) f[i].v[0] = kscale[k0 + kk];
+      }
+    }
+  }
+
+  // Element-wise loads with bounds checks (edge tiles, ragged k, unaligned).
+  __device__ __noinline__ void load_checked(const T* __restrict__ base, int64_t sr, int64_t r0,
+                                            int64_t rmax, int64_t k0, int64_t kmax,
+                                            const T* __restrict__ kscale) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int v = threadIdx.x + i * 256;
@@ -130,32 +156,19 @@ struct TileLoader {
         const int row = v / (BK / W);
         const int kk = (v % (BK / W)) * W;
         const int64_t gr = r0 + row, gk = k0 + kk;
-        if (vec && gr < rmax && gk + W <= kmax) {
-          r[i] = *reinterpret_cast<const Vec16<T>*>(base + gr * sr + gk);
-        } else {
-#pragma unroll
-          for (int j = 0; j < W; ++j)
-            r[i].v[j] = (gr < rmax && gk + j < kmax) ? base[gr * sr + gk + j] : T(0);
-        }
-        if (kscale) {
-#pragma unroll
-          for (int j = 0; j < W; ++j) r[i].v[j] *= (gk + j < kmax) ? kscale[gk + j] : T(0);
+        for (int j = 0; j < W; ++j) {
+          const bool ok = gr < rmax && gk + j < kmax;
+          r[i].v[j] = ok ? base[gr * sr + gk + j] : T(0);
+          if constexpr (KS) f[i].v[j] = (gk + j < kmax) ? kscale[gk + j] : T(0);
         }
       } else {
         const int kk = v / (ROWS / W);
         const int row = (v % (ROWS / W)) * W;
         const int64_t gr = r0 + row, gk = k0 + kk;
-        if (vec && gk < kmax && gr + W <= rmax) {
-          r[i] = *reinterpret_cast<const Vec16<T>*>(base + gr + gk * sr);
-        } else {
-#pragma unroll
-          for (int j = 0; j < W; ++j)
-            r[i].v[j] = (gk < kmax && gr + j < rmax) ? base[gr + j + gk * sr] : T(0);
-        }
-        if (kscale) {
-          const T f = (gk < kmax) ? kscale[gk] : T(0);
-#pragma unroll
-          for (int j = 0; j < W; ++j) r[i].v[j] *= f;
+        if constexpr (KS) f[i].v[0] = (gk < kmax) ? kscale[gk] : T(0);
+        for (int j = 0; j < W; ++j) {
+          const bool ok = gk < kmax && gr + j < rmax;
+          r[i].v[j] = ok ? base[gr + j + gk * sr] : T(0);
         }
       }
     }
@@ -167,30 +180,35 @@ struct TileLoader {
     for (int i = 0; i < NV; ++i) {
       const int v = threadIdx.x + i * 256;
       if (TOT % 256 != 0 && v >= TOT) break;
+      Vec16<T> x = r[i];
+      if constexpr (KS) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) x.v[j] *= KCONTIG ? f[i].v[j] : f[i].v[0];
+      }
       if constexpr (KCONTIG) {
         const int row = v / (BK / W);
         const int kk = (v % (BK / W)) * W;
-        *reinterpret_cast<Vec16<T>*>(lds + row * LDK + kk) = r[i];
+        *reinterpret_cast<Vec16<T>*>(lds + row * LDK + kk) = x;
       } else {
         const int kk = v / (ROWS / W);
         const int row = (v % (ROWS / W)) * W;
 #pragma unroll
-        for (int j = 0; j < W; ++j) lds[(row + j) * LDK + kk] = r[i].v[j];
+        for (int j = 0; j < W; ++j) lds[(row + j) * LDK + kk] = x.v[j];
       }
     }
   }
 };
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool AK, bool BKC>
-__global__ __launch_bounds__(256) void gemm_kernel(KernelArgs<T> args) {
+template <typename T, int BM, int BN, int BK, int MINW, bool AK, bool BKC, bool KS>
+__global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc_t;
+  constexpr int WM = 2, WN = 2;
   constexpr int PAD = 16 / sizeof(T);
   constexpr int LDK = BK + PAD;
   constexpr int KG = BK / 4;                 // k values per lane group per slice
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int TM = WTM / 16, TN = WTN / 16;
-  static_assert(WM * WN == 4, "four waves per workgroup");
   static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be a multiple of 16");
   static_assert((KG * sizeof(T)) % 16 == 0, "fragment reads are 16-byte vectors");
 
@@ -209,11 +227,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(KernelArgs<T> args) {
 
   const T* __restrict__ A = args.A + bz * c.bsA;
   const T* __restrict__ B = args.B + bz * c.bsB;
+  const T* __restrict__ ks = args.kscale;
   const int64_t m0 = int64_t(m_tile) * BM;
   const int64_t n0 = int64_t(n_tile) * BN;
   const int64_t kbeg = int64_t(split) * c.kchunk;
   const int64_t kend = std::min<int64_t>(c.K, kbeg + c.kchunk);
   const int nk = kend > kbeg ? int((kend - kbeg + BK - 1) / BK) : 0;
+  // slices [0, nfull) of an interior tile need no bounds checks
+  const bool interior = c.vecA && c.vecB && m0 + BM <= c.M && n0 + BN <= c.N;
+  const int nfull = interior ? int((kend - kbeg) / BK) : 0;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -229,28 +251,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(KernelArgs<T> args) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
 
-  TileLoader<T, BM, BK, AK> la;
-  TileLoader<T, BN, BK, BKC> lb;
-  const int64_t sA = AK ? c.sam : c.sak;   // stride between rows (AK) or between k (m-contig)
+  using LA = TileLoader<T, BM, BK, AK, false>;
+  using LB = TileLoader<T, BN, BK, BKC, KS>;
+  LA la0, la1;
+  LB lb0, lb1;
+  const int64_t sA = AK ? c.sam : c.sak;
   const int64_t sB = BKC ? c.sbn : c.sbk;
 
-  if (nk > 0) {
-    la.load(A, sA, m0, c.M, kbeg, kend, c.vecA, nullptr);
-    lb.load(B, sB, n0, c.N, kbeg, kend, c.vecB, args.kscale);
-    la.template store<LDK>(As[0]);
-    lb.template store<LDK>(Bs[0]);
-  }
-  __syncthreads();
-
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      const int64_t k0 = kbeg + int64_t(kt + 1) * BK;
-      la.load(A, sA, m0, c.M, k0, kend, c.vecA, nullptr);
-      lb.load(B, sB, n0, c.N, k0, kend, c.vecB, args.kscale);
+  auto load = [&](LA& la, LB& lb, int s) {
+    const int64_t k0 = kbeg + int64_t(s) * BK;
+    if (s < nfull) {
+      la.load_fast(A, sA, m0, k0, nullptr);
+      lb.load_fast(B, sB, n0, k0, ks);
+    } else {
+      la.load_checked(A, sA, m0, c.M, k0, kend, nullptr);
+      lb.load_checked(B, sB, n0, c.N, k0, kend, ks);
     }
-    const T* as = As[cur];
-    const T* bs = Bs[cur];
+  };
+
+  auto compute = [&](const T* __restrict__ as, const T* __restrict__ bs) {
     T af[TM][KG];
     T bf[TN][KG];
 #pragma unroll
@@ -279,9 +298,33 @@ __global__ __launch_bounds__(256) void gemm_kernel(KernelArgs<T> args) {
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = MF::mma(af[i][s], bf[j][s], acc[i][j]);
+  };
+
+  // Two register sets: slice s lives in set s%2 from its load (two slices
+  // ahead of its use) until it is written to LDS stage s%2.
+  if (nk > 0) {
+    load(la0, lb0, 0);
+    if (nk > 1) load(la1, lb1, 1);
+    la0.template store<LDK>(As[0]);
+    lb0.template store<LDK>(Bs[0]);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    // even slice: compute stage 0, refill set 0 with slice kt+2, stage slice kt+1
+    if (kt + 2 < nk) load(la0, lb0, kt + 2);
+    compute(As[0], Bs[0]);
     if (kt + 1 < nk) {
-      la.template store<LDK>(As[cur ^ 1]);
-      lb.template store<LDK>(Bs[cur ^ 1]);
+      la1.template store<LDK>(As[1]);
+      lb1.template store<LDK>(Bs[1]);
+    }
+    __syncthreads();
+    if (kt + 1 >= nk) break;
+    // odd slice: compute stage 1, refill set 1 with slice kt+3, stage slice kt+2
+    if (kt + 3 < nk) load(la1, lb1, kt + 3);
+    compute(As[1], Bs[1]);
+    if (kt + 2 < nk) {
+      la0.template store<LDK>(As[0]);
+      lb0.template store<LDK>(Bs[0]);
     }
     __syncthreads();
   }
@@ -349,19 +392,14 @@ struct Cfg {
   int BM, BN, BK, occ;   // occ: resident workgroups per CU assumed by the planner
 };
 
-// FP32 tiles (16x16x4 f32 MFMA)
-static const Cfg kCfgF32[] = {
-    {128, 128, 32, 1}, {128, 160, 16, 2}, {128, 64, 32, 2}, {64, 64, 32, 3}};
-// FP64 tiles (16x16x4 f64 MFMA)
-static const Cfg kCfgF64[] = {
-    {128, 128, 16, 1}, {128, 64, 16, 2}, {64, 64, 16, 3}, {64, 64, 16, 3}};
-static constexpr int kNumCfg = 4;
+// Tile shapes.  FP32 shapes are used for the filter products (both operands
+// k-contiguous); every other layout uses the last (generic) entry.
+static const Cfg kCfgF32[] = {{128, 128, 32, 2}, {128, 160, 16, 2}, {128, 64, 32, 2},
+                              {64, 160, 16, 3},  {128, 160, 32, 1}, {256, 160, 16, 1},
+                              {64, 64, 32, 4}};
+static const Cfg kCfgF64[] = {{128, 128, 16, 1}, {128, 64, 16, 2}, {64, 64, 16, 3}};
+static constexpr int kNumF32 = 7, kNumF64 = 3;
 static constexpr int kNumCU = 256;
-
-template <typename T>
-static const Cfg* cfg_table() {
-  return sizeof(T) == 4 ? kCfgF32 : kCfgF64;
-}
 
 static int choose_splits(int64_t tiles, int64_t K, int BK, int slots) {
   // enough work items to fill every resident slot a few times, but keep at
@@ -373,11 +411,14 @@ static int choose_splits(int64_t tiles, int64_t K, int BK, int slots) {
 }
 
 template <typename T>
-void gemm_plan(int64_t M, int64_t N, int64_t K, int batch, int* config, int* splits) {
-  const Cfg* tab = cfg_table<T>();
+static void plan_impl(int64_t M, int64_t N, int64_t K, int batch, bool filter_layout, int* config,
+                      int* splits) {
+  const Cfg* tab = sizeof(T) == 4 ? kCfgF32 : kCfgF64;
+  const int ncfg = sizeof(T) == 4 ? kNumF32 : kNumF64;
   double best = 1e300;
-  int bc = kNumCfg - 1, bs = 1;
-  for (int ci = 0; ci < kNumCfg; ++ci) {
+  int bc = ncfg - 1, bs = 1;
+  for (int ci = 0; ci < ncfg; ++ci) {
+    if (sizeof(T) == 4 && !filter_layout && ci != ncfg - 1) continue;
     const Cfg& f = tab[ci];
     const int64_t tm = (M + f.BM - 1) / f.BM, tn = (N + f.BN - 1) / f.BN;
     const int64_t tiles = tm * tn * batch;
@@ -385,7 +426,6 @@ void gemm_plan(int64_t M, int64_t N, int64_t K, int batch, int* config, int* spl
     const int s = choose_splits(tiles, K, f.BK, slots);
     const double items = double(tiles) * s;
     const double waves = std::ceil(items / slots);
-    // time ~ waves * (per-item work), per-item work ~ BM*BN*Kchunk / occ
     const double kchunk = std::ceil(double(K) / s / f.BK) * f.BK;
     const double t = waves * double(f.BM) * f.BN * kchunk / f.occ * (1.0 + 0.02 * s);
     if (t < best * 0.999) {
@@ -398,12 +438,17 @@ void gemm_plan(int64_t M, int64_t N, int64_t K, int batch, int* config, int* spl
   *splits = bs;
 }
 
+template <typename T>
+void gemm_plan(int64_t M, int64_t N, int64_t K, int batch, int* config, int* splits) {
+  plan_impl<T>(M, N, K, batch, true, config, splits);
+}
+
 size_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, size_t elem) {
   (void)K;
   return size_t(64) * size_t(M) * size_t(N) * elem;
 }
 
-template <typename T, int BM, int BN, int BK>
+template <typename T, int BM, int BN, int BK, int MINW, bool FILTER_ONLY = false>
 static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspace& ws,
                              int splits) {
   KernelArgs<T> a;
@@ -431,7 +476,8 @@ static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspa
   c.vecA = (reinterpret_cast<uintptr_t>(d.A) % 16 == 0) && (ldA % W == 0) &&
            (d.batch == 1 || d.bsA % W == 0);
   c.vecB = (reinterpret_cast<uintptr_t>(d.B) % 16 == 0) && (ldB % W == 0) &&
-           (d.batch == 1 || d.bsB % W == 0);
+           (d.batch == 1 || d.bsB % W == 0) &&
+           (d.kscale == nullptr || reinterpret_cast<uintptr_t>(d.kscale) % 16 == 0);
   if (splits > 1) {
     int64_t kchunk = (d.K + splits - 1) / splits;
     kchunk = (kchunk + BK - 1) / BK * BK;
@@ -460,19 +506,27 @@ static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspa
   const int64_t grid = int64_t(c.tiles_m) * c.tiles_n * c.splits * d.batch;
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  constexpr int WM = 2, WN = 2;
   if (d.ev_begin) {
     hipError_t e0 = hipEventRecord(d.ev_begin, st);
     if (e0 != hipSuccess) return e0;
   }
-  if (AK && BKC)
-    gemm_kernel<T, BM, BN, BK, WM, WN, true, true><<<dim3(grid), dim3(256), 0, st>>>(a);
-  else if (AK && !BKC)
-    gemm_kernel<T, BM, BN, BK, WM, WN, true, false><<<dim3(grid), dim3(256), 0, st>>>(a);
-  else if (!AK && BKC)
-    gemm_kernel<T, BM, BN, BK, WM, WN, false, true><<<dim3(grid), dim3(256), 0, st>>>(a);
-  else
-    gemm_kernel<T, BM, BN, BK, WM, WN, false, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+  const bool KS = d.kscale != nullptr;
+  if (AK && BKC) {
+    if (KS)
+      gemm_kernel<T, BM, BN, BK, MINW, true, true, true><<<dim3(grid), dim3(256), 0, st>>>(a);
+    else
+      gemm_kernel<T, BM, BN, BK, MINW, true, true, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+  } else if (KS || FILTER_ONLY) {
+    return hipErrorInvalidValue;   // k-scaling is only used with k-contiguous operands
+  } else if constexpr (FILTER_ONLY) {
+    return hipErrorInvalidValue;
+  } else if (AK && !BKC) {
+    gemm_kernel<T, BM, BN, BK, MINW, true, false, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+  } else if (!AK && BKC) {
+    gemm_kernel<T, BM, BN, BK, MINW, false, true, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+  } else {
+    gemm_kernel<T, BM, BN, BK, MINW, false, false, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (d.ev_end) {
@@ -488,6 +542,13 @@ static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspa
   return err;
 }
 
+// Launchers for the FP32 filter shapes (both operands k-contiguous only).
+template <int BM, int BN, int BK, int MINW>
+static hipError_t launch_f32_filter(const GemmDesc<float>& d, hipStream_t st, const Workspace& ws,
+                                    int splits) {
+  return launch_cfg<float, BM, BN, BK, MINW, true>(d, st, ws, splits);
+}
+
 template <typename T>
 hipError_t gemm(const GemmDesc<T>& d, hipStream_t st, const Workspace& ws, int force_splits,
                 int force_config) {
@@ -495,23 +556,30 @@ hipError_t gemm(const GemmDesc<T>& d, hipStream_t st, const Workspace& ws, int f
   if (d.sam != 1 && d.sak != 1) return hipErrorInvalidValue;
   if (d.sbk != 1 && d.sbn != 1) return hipErrorInvalidValue;
   if (d.batch > 1 && (d.epi.C2 || d.epi.C3 || d.epi.rowscale)) return hipErrorInvalidValue;
+  const bool filter_layout = (d.sak == 1) && (d.sbk == 1);
   int cfg, splits;
-  gemm_plan<T>(d.M, d.N, d.K, d.batch, &cfg, &splits);
-  if (force_config >= 0 && force_config < kNumCfg) cfg = force_config;
+  plan_impl<T>(d.M, d.N, d.K, d.batch, filter_layout, &cfg, &splits);
+  const int ncfg = sizeof(T) == 4 ? kNumF32 : kNumF64;
+  if (force_config >= 0 && force_config < ncfg && (sizeof(T) == 8 || filter_layout))
+    cfg = force_config;
   if (force_splits > 0) splits = force_splits;
   if (d.K <= 0) splits = 1;
   if constexpr (sizeof(T) == 4) {
+    if (!filter_layout) return launch_cfg<float, 64, 64, 32, 4>(d, st, ws, splits);
     switch (cfg) {
-      case 0: return launch_cfg<T, 128, 128, 32>(d, st, ws, splits);
-      case 1: return launch_cfg<T, 128, 160, 16>(d, st, ws, splits);
-      case 2: return launch_cfg<T, 128, 64, 32>(d, st, ws, splits);
-      default: return launch_cfg<T, 64, 64, 32>(d, st, ws, splits);
+      case 0: return launch_f32_filter<128, 128, 32, 2>(d, st, ws, splits);
+      case 1: return launch_f32_filter<128, 160, 16, 2>(d, st, ws, splits);
+      case 2: return launch_f32_filter<128, 64, 32, 2>(d, st, ws, splits);
+      case 3: return launch_f32_filter<64, 160, 16, 3>(d, st, ws, splits);
+      case 4: return launch_f32_filter<128, 160, 32, 1>(d, st, ws, splits);
+      case 5: return launch_f32_filter<256, 160, 16, 1>(d, st, ws, splits);
+      default: return launch_f32_filter<64, 64, 32, 4>(d, st, ws, splits);
     }
   } else {
     switch (cfg) {
-      case 0: return launch_cfg<T, 128, 128, 16>(d, st, ws, splits);
-      case 1: return launch_cfg<T, 128, 64, 16>(d, st, ws, splits);
-      default: return launch_cfg<T, 64, 64, 16>(d, st, ws, splits);
+      case 0: return launch_cfg<T, 128, 128, 16, 1>(d, st, ws, splits);
+      case 1: return launch_cfg<T, 128, 64, 16, 2>(d, st, ws, splits);
+      default: return launch_cfg<T, 64, 64, 16, 3>(d, st, ws, splits);
     }
   }
 }

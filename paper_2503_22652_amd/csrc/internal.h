@@ -114,6 +114,9 @@ hipError_t symmetrize(double* A, int64_t lda, int64_t b, hipStream_t st);
 // columns of M scaled by v: M[:,j] *= v[j]
 hipError_t scale_columns(double* M, int64_t ldm, int64_t n, int64_t b, const double* v,
                          hipStream_t st);
+// rows of M scaled by v: M[i,:] *= v[i]
+hipError_t scale_rows(double* M, int64_t ldm, int64_t n, int64_t b, const double* v,
+                      hipStream_t st);
 hipError_t set_identity(double* M, int64_t ldm, int64_t n, hipStream_t st);
 hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
 // random N(0,1) block from a counter-based generator (Philox-4x32-10 + Box-Muller)

@@ -19,6 +19,7 @@
 // storage is meant to speed up.
 #include "stencil_api.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace chfsi {
@@ -205,6 +206,254 @@ __global__ __launch_bounds__(256) void k_recon_bf16(const uint16_t* RY, const do
   }
 }
 
+// ---------------------------------------------------------------------------
+// Separable (class-symmetric) 27-point kernels, z-marching.
+//
+// The tensor-product Q1 stiffness and mass stencils have one coefficient per
+// class of offsets (0: centre, 1: the 6 faces, 2: the 12 edges, 3: the 8
+// corners).  Their class sums follow from per-plane partial sums
+//   P0 = u(x,y),  P1 = u(x±1,y) + u(x,y±1),  P2 = u(x±1,y±1)   (in-plane)
+// combined across z:
+//   s0 = P0(z),               s1 = P1(z) + P0(z-1) + P0(z+1),
+//   s2 = P2(z) + P1(z±1),      s3 = P2(z-1) + P2(z+1).
+// A workgroup owns one column and a slab of TY full x-rows and walks the whole
+// periodic z range; each plane (with its two halo rows) is staged once in LDS,
+// every thread keeps the partials of its points for planes z-1, z, z+1 in
+// registers, so an element costs 8 LDS reads per operand (u, and V*u for the
+// mass-weighted potential) instead of 27.
+// ---------------------------------------------------------------------------
+enum StencilKind { SK_APPLY = 0, SK_RSTEP = 1, SK_CSTEP = 2 };
+
+template <typename S>
+__device__ __forceinline__ float ld_f(const S* p, int64_t i);
+template <>
+__device__ __forceinline__ float ld_f<float>(const float* p, int64_t i) {
+  return p[i];
+}
+template <>
+__device__ __forceinline__ float ld_f<uint16_t>(const uint16_t* p, int64_t i) {
+  return bf16_to_f32(p[i]);
+}
+template <typename S, typename F>
+__device__ __forceinline__ F ld_s(const S* p, int64_t i) {
+  if constexpr (sizeof(S) == 2)
+    return F(bf16_to_f32(reinterpret_cast<const uint16_t*>(p)[i]));
+  else
+    return F(p[i]);
+}
+template <typename S, typename F>
+__device__ __forceinline__ void st_s(S* p, int64_t i, F v) {
+  if constexpr (sizeof(S) == 2)
+    reinterpret_cast<uint16_t*>(p)[i] = f32_to_bf16(float(v));
+  else
+    p[i] = S(v);
+}
+
+template <typename F>
+struct SepArgs {
+  int nx, ny, nz, ty, ntiles_y;
+  int mode;                  // field mode
+  F cA[4], cM[4];            // class coefficients of S and of the mass stencil
+  const double* V;
+  const void* dinv;          // length n, F-typed (FP32 for FP32/BF16 storage, FP64 for FP64)
+  const void* src;           // operand block (APPLY: X, RSTEP: R_Y, CSTEP: src)
+  int64_t lds_src;
+  void* out;                 // APPLY: Y, RSTEP: R_X (in place), CSTEP: dst
+  int64_t ld_out;
+  const void* prev;          // CSTEP: previous iterate (may alias out)
+  int64_t ld_prev;
+  const void* forcing;       // RSTEP: Y copy
+  int64_t ld_forcing;
+  const F* colcoef;          // RSTEP: Lambda_Y per column
+  F alpha, beta, gamma, delta;
+};
+
+// points per thread per plane: 4 for FP32 arithmetic, 2 for FP64
+template <typename F>
+constexpr int sep_pt() { return sizeof(F) == 4 ? 4 : 2; }
+
+template <typename S, typename F, int KIND>
+__global__ __launch_bounds__(256) void k_stencil_sep(SepArgs<F> a) {
+  constexpr int SEP_MAXPT = sep_pt<F>();
+  extern __shared__ __attribute__((aligned(16))) unsigned char sep_smem[];
+  F* lds = reinterpret_cast<F*>(sep_smem);
+  const int nx = a.nx, ny = a.ny, nz = a.nz, TY = a.ty;
+  const int rows = TY + 2;
+  const int plane_sz = rows * nx;            // one operand plane incl. halo rows
+  const int64_t n = int64_t(nx) * ny * nz;
+  const int j = blockIdx.x / a.ntiles_y;      // column
+  const int ytile = blockIdx.x - j * a.ntiles_y;
+  const int y0 = ytile * TY;
+  const int npts = nx * min(TY, ny - y0);     // points of this slab per plane
+  const bool field2 = a.mode == 2;
+  const S* src = static_cast<const S*>(a.src) + int64_t(j) * a.lds_src;
+  const F* dinv = static_cast<const F*>(a.dinv);
+
+  // LDS: buffer b (0/1) holds u at [b*2*plane_sz] and w = V*u at +plane_sz
+  auto stage = [&](int buf, int z) {
+    F* u = lds + buf * 2 * plane_sz;
+    F* w = u + plane_sz;
+    const int64_t zoff = int64_t(z) * nx * ny;
+    for (int idx = threadIdx.x; idx < plane_sz; idx += 256) {
+      const int r = idx / nx, x = idx - r * nx;
+      int y = y0 - 1 + r;
+      y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+      const int64_t i = zoff + int64_t(y) * nx + x;
+      F v = ld_s<S, F>(src, i);
+      if (KIND == SK_RSTEP && dinv) v *= dinv[i];
+      u[idx] = v;
+      if (field2) w[idx] = F(a.V[i]) * v;
+    }
+  };
+
+  // per-point partial sums for planes z-1 (0), z (1), z+1 (2)
+  F pu[3][SEP_MAXPT][3], pw[3][SEP_MAXPT][3];
+  auto partials = [&](int buf, F (&P)[SEP_MAXPT][3], F (&Q)[SEP_MAXPT][3]) {
+    const F* u = lds + buf * 2 * plane_sz;
+    const F* w = u + plane_sz;
+#pragma unroll
+    for (int q = 0; q < SEP_MAXPT; ++q) {
+      const int pt = threadIdx.x + q * 256;
+      if (pt >= npts) break;
+      const int yy = pt / nx, x = pt - yy * nx;
+      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+      const int rc = (yy + 1) * nx, rm = yy * nx, rp = (yy + 2) * nx;
+      P[q][0] = u[rc + x];
+      P[q][1] = u[rc + xm] + u[rc + xp] + u[rm + x] + u[rp + x];
+      P[q][2] = u[rm + xm] + u[rm + xp] + u[rp + xm] + u[rp + xp];
+      if (field2) {
+        Q[q][0] = w[rc + x];
+        Q[q][1] = w[rc + xm] + w[rc + xp] + w[rm + x] + w[rp + x];
+        Q[q][2] = w[rm + xm] + w[rm + xp] + w[rp + xm] + w[rp + xp];
+      }
+    }
+  };
+
+  stage(0, nz - 1);
+  stage(1, 0);
+  __syncthreads();
+  partials(0, pu[0], pw[0]);
+  partials(1, pu[1], pw[1]);
+  __syncthreads();
+  for (int z = 0; z < nz; ++z) {
+    const int buf = z & 1;                   // plane z+1 goes to the buffer of z-1
+    stage(buf, z + 1 < nz ? z + 1 : 0);
+    __syncthreads();
+    partials(buf, pu[2], pw[2]);
+    const int64_t zoff = int64_t(z) * nx * ny + int64_t(y0) * nx;
+#pragma unroll
+    for (int q = 0; q < SEP_MAXPT; ++q) {
+      const int pt = threadIdx.x + q * 256;
+      if (pt >= npts) break;
+      const F s0 = pu[1][q][0];
+      const F s1 = pu[1][q][1] + pu[0][q][0] + pu[2][q][0];
+      const F s2 = pu[1][q][2] + pu[0][q][1] + pu[2][q][1];
+      const F s3 = pu[0][q][2] + pu[2][q][2];
+      F av = a.cA[0] * s0 + a.cA[1] * s1 + a.cA[2] * s2 + a.cA[3] * s3;
+      const int64_t i = zoff + pt;           // grid index of this point
+      if (a.mode == 1) av += F(a.V[i]) * s0;
+      if (field2) {
+        const F t0 = pw[1][q][0];
+        const F t1 = pw[1][q][1] + pw[0][q][0] + pw[2][q][0];
+        const F t2 = pw[1][q][2] + pw[0][q][1] + pw[2][q][1];
+        const F t3 = pw[0][q][2] + pw[2][q][2];
+        const F mu = a.cM[0] * s0 + a.cM[1] * s1 + a.cM[2] * s2 + a.cM[3] * s3;
+        const F mw = a.cM[0] * t0 + a.cM[1] * t1 + a.cM[2] * t2 + a.cM[3] * t3;
+        av += F(0.5) * (F(a.V[i]) * mu + mw);
+      }
+      if constexpr (KIND == SK_APPLY) {
+        st_s<S, F>(static_cast<S*>(a.out) + int64_t(j) * a.ld_out, i, av);
+      } else if constexpr (KIND == SK_RSTEP) {
+        S* RX = static_cast<S*>(a.out) + int64_t(j) * a.ld_out;
+        const S* Yf = static_cast<const S*>(a.forcing) + int64_t(j) * a.ld_forcing;
+        const F v = a.alpha * av + a.beta * ld_s<S, F>(src, i) + a.gamma * ld_s<S, F>(RX, i) +
+                    a.delta * a.colcoef[j] * ld_s<S, F>(Yf, i);
+        st_s<S, F>(RX, i, v);
+      } else {
+        if (dinv) av *= dinv[i];
+        F v = a.alpha * av + a.beta * ld_s<S, F>(src, i);
+        if (a.prev)
+          v += a.gamma * ld_s<S, F>(static_cast<const S*>(a.prev) + int64_t(j) * a.ld_prev, i);
+        st_s<S, F>(static_cast<S*>(a.out) + int64_t(j) * a.ld_out, i, v);
+      }
+    }
+    // roll the partials: z-1 <- z, z <- z+1
+#pragma unroll
+    for (int q = 0; q < SEP_MAXPT; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pu[0][q][c] = pu[1][q][c];
+        pu[1][q][c] = pu[2][q][c];
+        pw[0][q][c] = pw[1][q][c];
+        pw[1][q][c] = pw[2][q][c];
+      }
+    __syncthreads();
+  }
+  (void)n;
+}
+
+// class-symmetric coefficients? (value depends only on the number of nonzero offsets)
+bool class_symmetric(const double* c, double out[4]) {
+  bool seen[4] = {false, false, false, false};
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int cls = (dz != 0) + (dy != 0) + (dx != 0);
+        const double v = c[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
+        if (!seen[cls]) {
+          out[cls] = v;
+          seen[cls] = true;
+        } else if (v != out[cls]) {
+          return false;
+        }
+      }
+  return true;
+}
+
+// slab height: full x rows, at most sep_pt<F>() points per thread per plane
+template <typename F>
+int sep_ty(const chfsi_operator& op) {
+  const int cap = 256 * sep_pt<F>();
+  if (op.nx > cap) return 0;
+  int ty = std::min(cap / op.nx, op.ny);
+  return ty >= 1 ? ty : 0;
+}
+
+template <typename F>
+bool sep_setup(const chfsi_operator& op, SepArgs<F>* a) {
+  double cA[4], cM[4] = {0, 0, 0, 0};
+  if (!class_symmetric(op.coef, cA)) return false;
+  if (op.field_mode == 2 && !class_symmetric(op.coef_mass, cM)) return false;
+  const int ty = sep_ty<F>(op);
+  if (ty == 0) return false;
+  a->nx = op.nx;
+  a->ny = op.ny;
+  a->nz = op.nz;
+  a->ty = ty;
+  a->ntiles_y = (op.ny + ty - 1) / ty;
+  a->mode = op.field_mode;
+  for (int i = 0; i < 4; ++i) {
+    a->cA[i] = F(cA[i]);
+    a->cM[i] = F(cM[i]);
+  }
+  a->V = op.field;
+  a->dinv = nullptr;
+  a->prev = nullptr;
+  a->forcing = nullptr;
+  a->colcoef = nullptr;
+  a->alpha = F(1);
+  a->beta = a->gamma = a->delta = F(0);
+  return true;
+}
+
+template <typename S, typename F, int KIND>
+hipError_t sep_launch(const SepArgs<F>& a, int64_t b, hipStream_t st) {
+  const int64_t grid = int64_t(a.ntiles_y) * b;
+  const size_t lds = size_t(2) * 2 * (a.ty + 2) * a.nx * sizeof(F);
+  k_stencil_sep<S, F, KIND><<<dim3(unsigned(grid)), 256, lds, st>>>(a);
+  return hipGetLastError();
+}
+
 Grid make_grid(const chfsi_operator& op) {
   Grid g;
   g.nx = op.nx;
@@ -247,6 +496,14 @@ double stencil_flops(const chfsi_operator& op) {
 
 hipError_t stencil_apply_f64(const chfsi_operator& op, const double* X, int64_t ldx, double* Y,
                              int64_t ldy, int64_t b, hipStream_t st) {
+  SepArgs<double> a;
+  if (sep_setup(op, &a)) {
+    a.src = X;
+    a.lds_src = ldx;
+    a.out = Y;
+    a.ld_out = ldy;
+    return sep_launch<double, double, SK_APPLY>(a, b, st);
+  }
   k_apply_f64<<<grid_for(op.n * b), 256, 0, st>>>(make_coefs_d(op), make_grid(op), X, ldx, Y, ldy,
                                                   op.n, b);
   return hipGetLastError();
@@ -256,6 +513,22 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
                                    double* RX, const double* Yf, int64_t ldf,
                                    const double* colcoef, StencilStep s, int64_t b,
                                    hipStream_t st) {
+  SepArgs<double> a;
+  if (sep_setup(op, &a)) {
+    a.dinv = dinv;
+    a.src = RY;
+    a.lds_src = op.n;
+    a.out = RX;
+    a.ld_out = op.n;
+    a.forcing = Yf;
+    a.ld_forcing = ldf;
+    a.colcoef = colcoef;
+    a.alpha = s.alpha;
+    a.beta = s.beta;
+    a.gamma = s.gamma;
+    a.delta = s.delta;
+    return sep_launch<double, double, SK_RSTEP>(a, b, st);
+  }
   k_rstep_f64<<<grid_for(op.n * b), 256, 0, st>>>(make_coefs_d(op), make_grid(op), dinv, RY, RX,
                                                   Yf, ldf, colcoef, s, op.n, b);
   return hipGetLastError();
@@ -264,6 +537,22 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
 hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* dinv, const float* RY,
                                    float* RX, const float* Yf, const float* colcoef,
                                    StencilStep s, int64_t b, hipStream_t st) {
+  SepArgs<float> a;
+  if (sep_setup(op, &a)) {
+    a.dinv = dinv;
+    a.src = RY;
+    a.lds_src = op.n;
+    a.out = RX;
+    a.ld_out = op.n;
+    a.forcing = Yf;
+    a.ld_forcing = op.n;
+    a.colcoef = colcoef;
+    a.alpha = float(s.alpha);
+    a.beta = float(s.beta);
+    a.gamma = float(s.gamma);
+    a.delta = float(s.delta);
+    return sep_launch<float, float, SK_RSTEP>(a, b, st);
+  }
   k_rstep_f32<<<grid_for(op.n * b), 256, 0, st>>>(make_coefs_f(op), make_grid(op), dinv, RY, RX,
                                                   Yf, colcoef, float(s.alpha), float(s.beta),
                                                   float(s.gamma), float(s.delta), op.n, b);
@@ -273,6 +562,22 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* dinv, 
 hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* dinv, const void* RY,
                                     void* RX, const void* Yf, const float* colcoef, StencilStep s,
                                     int64_t b, hipStream_t st) {
+  SepArgs<float> a;
+  if (sep_setup(op, &a)) {
+    a.dinv = dinv;
+    a.src = RY;
+    a.lds_src = op.n;
+    a.out = RX;
+    a.ld_out = op.n;
+    a.forcing = Yf;
+    a.ld_forcing = op.n;
+    a.colcoef = colcoef;
+    a.alpha = float(s.alpha);
+    a.beta = float(s.beta);
+    a.gamma = float(s.gamma);
+    a.delta = float(s.delta);
+    return sep_launch<uint16_t, float, SK_RSTEP>(a, b, st);
+  }
   k_rstep_bf16<<<grid_for(op.n * b), 256, 0, st>>>(
       make_coefs_f(op), make_grid(op), dinv, static_cast<const uint16_t*>(RY),
       static_cast<uint16_t*>(RX), static_cast<const uint16_t*>(Yf), colcoef, float(s.alpha),
@@ -283,6 +588,20 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* dinv,
 hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* src,
                                   int64_t lds, const double* prev, int64_t ldp, double* dst,
                                   StencilStep s, int64_t b, hipStream_t st) {
+  SepArgs<double> a;
+  if (sep_setup(op, &a)) {
+    a.dinv = dinv;
+    a.src = src;
+    a.lds_src = lds;
+    a.out = dst;
+    a.ld_out = op.n;
+    a.prev = prev;
+    a.ld_prev = ldp;
+    a.alpha = s.alpha;
+    a.beta = s.beta;
+    a.gamma = s.gamma;
+    return sep_launch<double, double, SK_CSTEP>(a, b, st);
+  }
   k_cstep_f64<<<grid_for(op.n * b), 256, 0, st>>>(make_coefs_d(op), make_grid(op), dinv, src, lds,
                                                   prev, ldp, dst, s, op.n, b);
   return hipGetLastError();

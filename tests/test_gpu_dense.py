@@ -226,3 +226,27 @@ def test_invalid_arguments_are_rejected(gen_problem):
     Yd = P.colmajor_empty(p.n, 40)
     with pytest.raises(P.ChfsiError):
         P.chfsi_filter(ctx, Xd, None, None, Yd, 1.0, 10.0, 0.5)      # lmin > lT
+
+
+def test_rayleigh_ritz_singular_gram_uses_svqb(gen_problem):
+    """A block with a repeated column: the scaled Gram matrix is singular, the
+    SVQB reading keeps the b-1 independent directions (here an invariant
+    subspace, so their Ritz values are exact eigenvalues), refills one column
+    and repeats Rayleigh-Ritz."""
+    p, w = gen_problem
+    params = P.make_params(p.n_wanted, p.block, 4, lambda_max=w[-1] + 1)
+    ctx = _ctx(p, params)
+    _, U = sla.eigh(p.A, p.B)
+    Y = U[:, : p.block].copy()
+    Y[:, -1] = Y[:, 0]
+    Xd = P.colmajor_empty(p.n, p.block)
+    Rd = P.colmajor_empty(p.n, p.block)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, dev(Y), Xd, Rd)
+    ritz = np.asarray(ritz)
+    exact = w[: p.block - 1]
+    for lam in exact:
+        assert np.min(np.abs(ritz - lam)) <= 1e-10 * max(1.0, abs(lam))
+    Xg = host(Xd)
+    np.testing.assert_allclose(Xg.T @ p.B @ Xg, np.eye(p.block), atol=1e-9)
+    Rg = p.A @ Xg - (p.B @ Xg) * ritz[None, :]
+    np.testing.assert_allclose(norms, np.linalg.norm(Rg, axis=0), rtol=1e-6, atol=1e-9)

@@ -83,3 +83,18 @@ def test_svqb_fallback_on_rank_deficient_block(rng):
     out = rr.rayleigh_ritz(Y, filters.dense_op(A), filters.identity_op())
     assert out["svqb"] and out["dropped"] == 1
     np.testing.assert_allclose(out["lam"], lam[: b - 1], atol=1e-11)
+
+
+def test_pencil_eigenvalues_shared_basis_and_jacobi(rng):
+    """Full-space Rayleigh-Ritz = the pencil's spectrum: exact lam_j / b_j for a
+    shared eigenbasis (the paper's generalized toy construction) and the
+    brute-force Jacobi on an explicit Cholesky reduction."""
+    import workloads as wl
+    t = wl.toy_generalized(m=60, n=5, zeta=0.0, seed=3)
+    w = rr.pencil_eigenvalues(t["A"], t["B"], 12)
+    np.testing.assert_allclose(w, np.sort(t["lam_gen"])[:12], rtol=1e-12)
+    A = t["A"] + 0.01 * wl.unit_sym_perturbation(rng, 60)
+    L = np.linalg.cholesky(t["B"])
+    H = np.linalg.solve(L, np.linalg.solve(L, A).T)
+    wj, _ = jacobi.jacobi_eigh(0.5 * (H + H.T))
+    np.testing.assert_allclose(rr.pencil_eigenvalues(A, t["B"], 10), wj[:10], rtol=1e-11)
