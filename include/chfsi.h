@@ -101,6 +101,15 @@ typedef struct {
   uint64_t seed;        /* seed of the random start block when init_random != 0 */
   int32_t init_random;  /* chfsi_solve: 1 = fill X with N(0,1) (Philox-4x32-10), 0 = X holds the start */
   int32_t profile;      /* 1 = time every filter operator-product kernel with HIP events */
+  /* 0: Rayleigh-Ritz keeps A Y and B Y as full n x b FP64 blocks.
+   * 1: slab-wise Rayleigh-Ritz for stencil operators with tensor-product
+   *    coefficients and the residual filter: Gram matrices are accumulated over
+   *    z-slabs, the rotation X = Y E is done slab by slab in place and the
+   *    residual in one fused stencil pass, so the context holds only the
+   *    residual block, the filter blocks and two slabs (chfsi_solve then works
+   *    in the caller's X). */
+  int32_t memory_mode;
+  int32_t reserved;
 } chfsi_params;
 
 /* Per-solve report (host). */

@@ -124,6 +124,10 @@ struct chfsi_ctx {
   int flags = 0;
   const std::atomic<int>* cancel = nullptr;
   uint64_t refill_seed = 0;
+  // slab-wise Rayleigh-Ritz (memory_mode 1)
+  int slab_planes = 0;
+  double* S1 = nullptr;
+  double* S2 = nullptr;
   // profiling: event pairs around the filter's operator-product kernels
   std::vector<hipEvent_t> pev;
   int pused = 0;
@@ -206,10 +210,30 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
     set_error("BF16 filter storage is implemented for the residual filter only");
     return CHFSI_ERR_ARG;
   }
+  if (p->memory_mode != 0) {
+    if (p->memory_mode != 1 || A->kind != CHFSI_OP_STENCIL27 || !stencil_separable(*A) ||
+        (!is_identity(B) && (B->kind != CHFSI_OP_STENCIL27 || !stencil_separable(*B))) ||
+        p->method != CHFSI_METHOD_RCHFSI || p->filter_prec == CHFSI_PREC_FP64) {
+      set_error("memory_mode 1 needs tensor-product stencil operators and the residual filter "
+                "in FP32 or BF16");
+      return CHFSI_ERR_ARG;
+    }
+  }
   return CHFSI_OK;
 }
 
+// z-planes per slab of the slab-wise Rayleigh-Ritz: about 1/16 of the grid,
+// at most 2 GiB per slab block
+int slab_planes_for(const chfsi_operator& A, int64_t b) {
+  const double plane = double(A.nx) * A.ny * b * sizeof(double);
+  int nzs = std::max(1, A.nz / 16);
+  while (nzs > 1 && plane * nzs > 2.0 * 1024 * 1024 * 1024) --nzs;
+  return nzs;
+}
+
 struct SizePlan {
+  int slab_planes = 0;
+  size_t slab = 0;
   size_t total = 0;
   size_t a32 = 0, f32blk = 0, f64blk = 0, bfblk = 0, coef = 0;
   size_t blk = 0, bb = 0, ws = 0, ws_eig = 0;
@@ -241,14 +265,24 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
   }
   ws = std::max(ws, plan_bytes<double>(b, b, n));
   ws = std::max(ws, plan_bytes<double>(n, b, b));
+  if (p->memory_mode == 1) {
+    const int64_t rows = int64_t(A->nx) * A->ny * slab_planes_for(*A, b);
+    ws = std::max(ws, plan_bytes<double>(b, b, rows));
+    ws = std::max(ws, plan_bytes<double>(rows, b, b));
+  }
   ws = std::max(ws, plan_bytes<double>(b, b, b));
   s.ws = ws + 256;
   s.ws_eig = syev_workspace_bytes(b) + 256;
   const bool Bid = is_identity(B);
   // filter blocks: FP32 3 blocks, FP64 2 blocks, BF16 3 blocks
   size_t filt = 3 * s.f32blk + 2 * s.f64blk + 3 * s.bfblk;
-  // RR: Yw, Xw, AY, R (+ BY when B != I)
+  // RR: Yw, Xw, AY, R (+ BY when B != I); slab-wise: R + two slabs
   size_t rr = (Bid ? 4 : 5) * s.blk;
+  if (p->memory_mode == 1) {
+    s.slab_planes = slab_planes_for(*A, b);
+    s.slab = size_t(A->nx) * A->ny * s.slab_planes * b * sizeof(double);
+    rr = s.blk + 2 * s.slab;
+  }
   s.total = s.a32 + filt + 2 * s.coef + rr + 10 * s.bb + 4 * b * sizeof(double) + 64 + s.ws +
             s.ws_eig;
   return s;
@@ -936,6 +970,234 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   return finish_rr(c, R, ldr, ritz, resnorm);
 }
 
+// ---------------------------------------------------------------------------
+// Slab-wise Rayleigh-Ritz (memory_mode 1): the same algebra as rayleigh_ritz,
+// with A Y and B Y materialised one z-slab at a time.  X is rotated in place.
+// ---------------------------------------------------------------------------
+chfsi_status slab_grams(chfsi_ctx* c, const double* X, int64_t ldx) {
+  const int64_t b = c->b;
+  const int nz = c->A.nz, nzs = c->slab_planes;
+  const int64_t plane = int64_t(c->A.nx) * c->A.ny;
+  hipStream_t st = c->stream;
+  for (int z0 = 0; z0 < nz; z0 += nzs) {
+    const int cnt = std::min(nzs, nz - z0);
+    const int64_t rows = plane * cnt, r0 = plane * z0;
+    CK(stencil_apply_slab_f64(c->A, X, ldx, c->S1, rows, b, z0, cnt, st));
+    const double* BYs = X + r0;
+    int64_t ldby = ldx;
+    if (!c->B_identity) {
+      CK(stencil_apply_slab_f64(c->B, X, ldx, c->S2, rows, b, z0, cnt, st));
+      BYs = c->S2;
+      ldby = rows;
+    }
+    for (int which = 0; which < 2; ++which) {
+      GemmDesc<double> g;
+      g.M = b;
+      g.N = b;
+      g.K = rows;
+      g.A = X + r0;
+      g.sak = 1;
+      g.sam = ldx;
+      g.B = which == 0 ? c->S1 : BYs;
+      g.sbk = 1;
+      g.sbn = which == 0 ? rows : ldby;
+      g.C = which == 0 ? c->Ga : c->Gb;
+      g.ldc = b;
+      if (z0 > 0) {
+        g.epi.beta = 1.0;
+        g.epi.C1 = g.C;
+        g.epi.ldc1 = b;
+      }
+      CK(gemm<double>(g, st, c->ws));
+    }
+  }
+  CK(symmetrize(c->Ga, b, b, st));
+  CK(symmetrize(c->Gb, b, b, st));
+  return CHFSI_OK;
+}
+
+// X[:, :k] <- X Tm (b x k, ld b), slab by slab in place
+chfsi_status slab_rotate(chfsi_ctx* c, double* X, int64_t ldx, const double* Tm, int64_t k) {
+  const int64_t b = c->b;
+  const int nz = c->A.nz, nzs = c->slab_planes;
+  const int64_t plane = int64_t(c->A.nx) * c->A.ny;
+  hipStream_t st = c->stream;
+  for (int z0 = 0; z0 < nz; z0 += nzs) {
+    const int cnt = std::min(nzs, nz - z0);
+    const int64_t rows = plane * cnt, r0 = plane * z0;
+    GemmDesc<double> g;
+    g.M = rows;
+    g.N = k;
+    g.K = b;
+    g.A = X + r0;
+    g.sam = 1;
+    g.sak = ldx;
+    g.B = Tm;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = c->S1;
+    g.ldc = rows;
+    CK(gemm<double>(g, st, c->ws));
+    CK(copy_block(c->S1, rows, X + r0, ldx, rows, k, st));
+  }
+  return CHFSI_OK;
+}
+
+chfsi_status slab_residual(chfsi_ctx* c, const double* X, int64_t ldx, double* R, int64_t ldr) {
+  CK(stencil_residual_f64(c->A, c->B_identity ? nullptr : &c->B, X, ldx, c->w, R, ldr, c->b,
+                          c->stream));
+  return CHFSI_OK;
+}
+
+chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R, int64_t ldr,
+                                 double* ritz, double* resnorm, bool allow_svqb) {
+  const int64_t n = c->n, b = c->b;
+  hipStream_t st = c->stream;
+  chfsi_status s;
+  CK(fill_zero(c->dflags, 4 * sizeof(int), st));
+  if ((s = slab_grams(c, X, ldx)) != CHFSI_OK) return s;
+  CK(scale_gram(c->Gb, b, b, c->Gs, b, c->svec, c->dflags + 1, st));
+  CK(copy_block(c->Gs, b, c->Linv, b, b, b, st));
+  CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws));
+  CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (c->h_flags[1] != 0) {
+    set_error("Gram matrix Y^T B Y has a non-positive diagonal (a zero or non-finite column)");
+    return CHFSI_ERR_NOT_SPD;
+  }
+  int sweeps = 0;
+  if (c->h_flags[0] == 0) {
+    CK(set_identity(c->Linv, b, b, st));
+    CK(trsm_lower_left(c->Gs, b, c->Linv, b, b, b, st, c->ws));
+    CK(scale_sym(c->Ga, b, b, c->svec, c->Hp, b, st));
+    GemmDesc<double> g;
+    g.M = b;
+    g.N = b;
+    g.K = b;
+    g.A = c->Linv;
+    g.sam = 1;
+    g.sak = b;
+    g.B = c->Hp;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = c->Tmp;
+    g.ldc = b;
+    CK(gemm<double>(g, st, c->ws));
+    GemmDesc<double> h;
+    h.M = b;
+    h.N = b;
+    h.K = b;
+    h.A = c->Tmp;
+    h.sam = 1;
+    h.sak = b;
+    h.B = c->Linv;
+    h.sbn = 1;
+    h.sbk = b;
+    h.C = c->Hp;
+    h.ldc = b;
+    CK(gemm<double>(h, st, c->ws));
+    CK(symmetrize(c->Hp, b, b, st));
+    CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
+    c->last_sweeps += sweeps;
+    GemmDesc<double> t;
+    t.M = b;
+    t.N = b;
+    t.K = b;
+    t.A = c->Linv;
+    t.sak = 1;
+    t.sam = b;
+    t.B = c->E;
+    t.sbk = 1;
+    t.sbn = b;
+    t.C = c->T;
+    t.ldc = b;
+    t.epi.rowscale = c->svec;
+    CK(gemm<double>(t, st, c->ws));
+    if ((s = slab_rotate(c, X, ldx, c->T, b)) != CHFSI_OK) return s;
+    if ((s = slab_residual(c, X, ldx, R, ldr)) != CHFSI_OK) return s;
+    return finish_rr(c, R, ldr, ritz, resnorm);
+  }
+  if (!allow_svqb) {
+    set_error("Gram matrix Y^T B Y is not positive definite (pivot %d) after refill",
+              c->h_flags[0]);
+    return CHFSI_ERR_NOT_SPD;
+  }
+  // SVQB on the scaled Gram matrix kept in c->Linv (same reading as rayleigh_ritz_svqb)
+  CK(syev_jacobi(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  c->last_sweeps += sweeps;
+  CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  const double gmax = c->h_w[b - 1];
+  int64_t first = 0;
+  while (first < b && !(c->h_w[first] > 1e-14 * gmax)) ++first;
+  const int64_t k = b - first;
+  if (k <= 0) {
+    set_error("Gram matrix Y^T B Y is numerically zero");
+    return CHFSI_ERR_NOT_SPD;
+  }
+  c->flags |= 1;
+  std::vector<double> colv(k);
+  for (int64_t j = 0; j < k; ++j) colv[j] = 1.0 / std::sqrt(c->h_w[first + j]);
+  CK(hipEventSynchronize(c->ev_stage));
+  std::memcpy(c->h_stage, colv.data(), k * sizeof(double));
+  CK(hipMemcpyAsync(c->lamY, c->h_stage, k * sizeof(double), hipMemcpyHostToDevice, st));
+  CK(hipEventRecord(c->ev_stage, st));
+  CK(copy_block(c->E + first * b, b, c->T, b, b, k, st));
+  CK(scale_columns(c->T, b, b, k, c->lamY, st));
+  CK(scale_rows(c->T, b, b, k, c->svec, st));
+  {
+    GemmDesc<double> g;
+    g.M = b;
+    g.N = k;
+    g.K = b;
+    g.A = c->Ga;
+    g.sam = 1;
+    g.sak = b;
+    g.B = c->T;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = c->Tmp;
+    g.ldc = b;
+    CK(gemm<double>(g, st, c->ws));
+    GemmDesc<double> h;
+    h.M = k;
+    h.N = k;
+    h.K = b;
+    h.A = c->T;
+    h.sak = 1;
+    h.sam = b;
+    h.B = c->Tmp;
+    h.sbk = 1;
+    h.sbn = b;
+    h.C = c->Hp;
+    h.ldc = b;
+    CK(gemm<double>(h, st, c->ws));
+  }
+  CK(symmetrize(c->Hp, b, k, st));
+  CK(syev_jacobi(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  c->last_sweeps += sweeps;
+  {
+    GemmDesc<double> g;
+    g.M = b;
+    g.N = k;
+    g.K = k;
+    g.A = c->T;
+    g.sam = 1;
+    g.sak = b;
+    g.B = c->E;
+    g.sbk = 1;
+    g.sbn = b;
+    g.C = c->Linv;
+    g.ldc = b;
+    CK(gemm<double>(g, st, c->ws));
+  }
+  if ((s = slab_rotate(c, X, ldx, c->Linv, k)) != CHFSI_OK) return s;
+  c->refill_seed += 1;
+  if (k < b)
+    CK(fill_gaussian(X + k * ldx, ldx, n, b - k, c->prm.seed * 7919 + c->refill_seed, st));
+  return rayleigh_ritz_slabs(c, X, ldx, R, ldr, ritz, resnorm, false);
+}
+
 void bounds_policy(const chfsi_params& p, const double* ritz, int64_t b, double* lmin,
                    double* lmax, double* lT) {
   *lmax = p.lambda_max;
@@ -1026,11 +1288,18 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   c->lamY = ctx_alloc<double>(c, b * sizeof(double), &st);
   c->h_coef32.assign(size_t(params->degree) * b, 0.0f);
   c->h_coef64.assign(size_t(params->degree) * b, 0.0);
-  c->Yw = ctx_alloc<double>(c, sp.blk, &st);
-  c->Xw = ctx_alloc<double>(c, sp.blk, &st);
-  c->AY = ctx_alloc<double>(c, sp.blk, &st);
-  c->R = ctx_alloc<double>(c, sp.blk, &st);
-  if (!c->B_identity) c->BY = ctx_alloc<double>(c, sp.blk, &st);
+  if (params->memory_mode == 1) {
+    c->slab_planes = sp.slab_planes;
+    c->R = ctx_alloc<double>(c, sp.blk, &st);
+    c->S1 = ctx_alloc<double>(c, sp.slab, &st);
+    c->S2 = ctx_alloc<double>(c, sp.slab, &st);
+  } else {
+    c->Yw = ctx_alloc<double>(c, sp.blk, &st);
+    c->Xw = ctx_alloc<double>(c, sp.blk, &st);
+    c->AY = ctx_alloc<double>(c, sp.blk, &st);
+    c->R = ctx_alloc<double>(c, sp.blk, &st);
+    if (!c->B_identity) c->BY = ctx_alloc<double>(c, sp.blk, &st);
+  }
   c->Ga = ctx_alloc<double>(c, sp.bb, &st);
   c->Gb = ctx_alloc<double>(c, sp.bb, &st);
   c->Gs = ctx_alloc<double>(c, sp.bb, &st);
@@ -1161,15 +1430,16 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, dou
     set_error("leading dimensions must be >= n");
     return CHFSI_ERR_ARG;
   }
-  if (X == Y) {
+  if (X == Y && c->prm.memory_mode != 1) {
     set_error("X must not alias Y");
     return CHFSI_ERR_ARG;
   }
-  if (Y == c->Yw) {
-    set_error("internal error: Y aliases the context workspace");
-    return CHFSI_ERR_ARG;
-  }
   c->last_sweeps = 0;
+  if (c->prm.memory_mode == 1) {
+    // slab-wise: rotate in the output buffer
+    CK(copy_block(Y, ldy, X, ldx, c->n, c->b, c->stream));
+    return rayleigh_ritz_slabs(c, X, ldx, R, ldr, ritz, resnorm, true);
+  }
   return rayleigh_ritz(c, Y, ldy, X, ldx, R, ldr, ritz, resnorm, true);
 }
 
@@ -1193,7 +1463,12 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   float ms = 0.0f;
   CK(hipEventRecord(c->ev[2], c->stream));
   c->last_sweeps = 0;
-  chfsi_status st = rayleigh_ritz(c, X, ldx, c->Xw, n, c->R, n, ritz.data(), norms.data());
+  const bool slabs = c->prm.memory_mode == 1;
+  double* Xw = slabs ? X : c->Xw;            // working Ritz block
+  const int64_t ldw = slabs ? ldx : n;
+  chfsi_status st = slabs ? rayleigh_ritz_slabs(c, X, ldx, c->R, n, ritz.data(), norms.data(), true)
+                          : rayleigh_ritz(c, X, ldx, c->Xw, n, c->R, n, ritz.data(), norms.data(),
+                                          true);
   if (st != CHFSI_OK) return st;
   CK(hipEventRecord(c->ev[3], c->stream));
   CK(hipEventSynchronize(c->ev[3]));
@@ -1224,14 +1499,15 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
     }
     CK(hipEventRecord(c->ev[0], c->stream));
     if (c->prm.method == CHFSI_METHOD_RCHFSI)
-      st = filter_rchfsi(c, c->Xw, n, ritz.data(), c->R, n, c->Yw, n, lmin, lmax, lT,
-                         c->prm.degree, &r.filter_flops);
+      st = filter_rchfsi(c, Xw, ldw, ritz.data(), c->R, n, slabs ? Xw : c->Yw, slabs ? ldw : n,
+                         lmin, lmax, lT, c->prm.degree, &r.filter_flops);
     else
       st = filter_chfsi(c, c->Xw, n, c->Yw, n, lmin, lmax, lT, c->prm.degree, &r.filter_flops);
     if (st != CHFSI_OK) break;
     CK(hipEventRecord(c->ev[1], c->stream));
     c->last_sweeps = 0;
-    st = rayleigh_ritz(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(), norms.data());
+    st = slabs ? rayleigh_ritz_slabs(c, Xw, ldw, c->R, n, ritz.data(), norms.data(), true)
+               : rayleigh_ritz(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(), norms.data(), true);
     if (st != CHFSI_OK) break;
     CK(hipEventRecord(c->ev[3], c->stream));
     CK(hipEventSynchronize(c->ev[3]));
@@ -1255,7 +1531,7 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   r.converged = mr < c->prm.tol;
   r.flags = c->flags;
   if (st != CHFSI_OK && st != CHFSI_ERR_NOCONV) return st;
-  CK(copy_block(c->Xw, n, X, ldx, n, b, c->stream));
+  if (!slabs) CK(copy_block(c->Xw, n, X, ldx, n, b, c->stream));
   CK(hipStreamSynchronize(c->stream));
   std::memcpy(evals, ritz.data(), b * sizeof(double));
   std::memcpy(resnorms, norms.data(), b * sizeof(double));

@@ -58,11 +58,18 @@ struct Mfma<double> {
   static __device__ __forceinline__ int out_row(int lgrp, int r) { return lgrp + 4 * r; }
 };
 
-// 16-byte vector of T
+// 16-byte native vector of T
 template <typename T>
-struct Vec16 {
-  static constexpr int W = 16 / sizeof(T);
-  T v[W];
+struct Vec16;
+template <>
+struct Vec16<float> {
+  static constexpr int W = 4;
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec16<double> {
+  static constexpr int W = 2;
+  typedef double type __attribute__((ext_vector_type(2)));
 };
 
 struct KernelArgsCommon {
@@ -118,12 +125,10 @@ struct TileLoader {
   static constexpr int NV = (TOT + 255) / 256;     // vectors per thread
   static_assert((ROWS * BK) % W == 0, "tile not divisible into vectors");
   static_assert(KCONTIG ? (BK % W == 0) : (ROWS % W == 0), "vector along the contiguous dim");
-  Vec16<T> r[NV];
-  Vec16<T> f[KS ? NV : 1];   // k-scaling factors, applied at store time
+  using vec_t = typename Vec16<T>::type;
+  vec_t r[NV];
 
-  // Unchecked 16-byte loads: the whole tile lies inside the operand.  The
-  // k-scaling factors are fetched alongside and applied in store(), so no
-  // arithmetic waits on the loads before the tile is due in LDS.
+  // Unchecked 16-byte loads: the whole tile lies inside the operand.
   __device__ __forceinline__ void load_fast(const T* __restrict__ base, int64_t sr, int64_t r0,
                                             int64_t k0, const T* __restrict__ kscale) {
 #pragma unroll
@@ -133,19 +138,17 @@ struct TileLoader {
       if constexpr (KCONTIG) {
         const int row = v / (BK / W);
         const int kk = (v % (BK / W)) * W;
-        r[i] = *reinterpret_cast<const Vec16<T>*>(base + (r0 + row) * sr + k0 + kk);
-        if constexpr (KS) f[i] = *reinterpret_cast<const Vec16<T>*>(kscale + k0 + kk);
+        r[i] = *reinterpret_cast<const vec_t*>(base + (r0 + row) * sr + k0 + kk);
       } else {
         const int kk = v / (ROWS / W);
         const int row = (v % (ROWS / W)) * W;
-        r[i] = *reinterpret_cast<const Vec16<T>*>(base + r0 + row + (k0 + kk) * sr);
-        if constexpr (KS) f[i].v[0] = kscale[k0 + kk];
+        r[i] = *reinterpret_cast<const vec_t*>(base + r0 + row + (k0 + kk) * sr);
       }
     }
   }
 
   // Element-wise loads with bounds checks (edge tiles, ragged k, unaligned).
-  __device__ __noinline__ void load_checked(const T* __restrict__ base, int64_t sr, int64_t r0,
+  __device__ __forceinline__ void load_checked(const T* __restrict__ base, int64_t sr, int64_t r0,
                                             int64_t rmax, int64_t k0, int64_t kmax,
                                             const T* __restrict__ kscale) {
 #pragma unroll
@@ -158,17 +161,15 @@ struct TileLoader {
         const int64_t gr = r0 + row, gk = k0 + kk;
         for (int j = 0; j < W; ++j) {
           const bool ok = gr < rmax && gk + j < kmax;
-          r[i].v[j] = ok ? base[gr * sr + gk + j] : T(0);
-          if constexpr (KS) f[i].v[j] = (gk + j < kmax) ? kscale[gk + j] : T(0);
+          r[i][j] = ok ? base[gr * sr + gk + j] : T(0);
         }
       } else {
         const int kk = v / (ROWS / W);
         const int row = (v % (ROWS / W)) * W;
         const int64_t gr = r0 + row, gk = k0 + kk;
-        if constexpr (KS) f[i].v[0] = (gk < kmax) ? kscale[gk] : T(0);
         for (int j = 0; j < W; ++j) {
           const bool ok = gk < kmax && gr + j < rmax;
-          r[i].v[j] = ok ? base[gr + j + gk * sr] : T(0);
+          r[i][j] = ok ? base[gr + j + gk * sr] : T(0);
         }
       }
     }
@@ -180,26 +181,25 @@ struct TileLoader {
     for (int i = 0; i < NV; ++i) {
       const int v = threadIdx.x + i * 256;
       if (TOT % 256 != 0 && v >= TOT) break;
-      Vec16<T> x = r[i];
-      if constexpr (KS) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) x.v[j] *= KCONTIG ? f[i].v[j] : f[i].v[0];
-      }
+      const vec_t x = r[i];
       if constexpr (KCONTIG) {
         const int row = v / (BK / W);
         const int kk = (v % (BK / W)) * W;
-        *reinterpret_cast<Vec16<T>*>(lds + row * LDK + kk) = x;
+        *reinterpret_cast<vec_t*>(lds + row * LDK + kk) = x;
       } else {
         const int kk = v / (ROWS / W);
         const int row = (v % (ROWS / W)) * W;
 #pragma unroll
-        for (int j = 0; j < W; ++j) lds[(row + j) * LDK + kk] = x.v[j];
+        for (int j = 0; j < W; ++j) lds[(row + j) * LDK + kk] = x[j];
       }
     }
   }
 };
 
-template <typename T, int BM, int BN, int BK, int MINW, bool AK, bool BKC, bool KS>
+// CHECK = false: every tile is interior and every k slice is full (M, N
+// multiples of the tile, K a multiple of BK, 16-byte aligned operands) -- the
+// host launches this variant only then; it carries no bounds checks at all.
+template <typename T, int BM, int BN, int BK, int MINW, bool AK, bool BKC, bool KS, bool CHECK>
 __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc_t;
@@ -214,6 +214,8 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
 
   __shared__ __attribute__((aligned(16))) T As[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) T Bs[2][BN * LDK];
+  // k-scaling factors (B(k,n) *= kscale[k]) of each staged slice
+  __shared__ __attribute__((aligned(16))) T Ks[2][KS ? BK : 1];
 
   const KernelArgsCommon& c = args.c;
   const int G = gridDim.x;
@@ -234,8 +236,8 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
   const int64_t kend = std::min<int64_t>(c.K, kbeg + c.kchunk);
   const int nk = kend > kbeg ? int((kend - kbeg + BK - 1) / BK) : 0;
   // slices [0, nfull) of an interior tile need no bounds checks
-  const bool interior = c.vecA && c.vecB && m0 + BM <= c.M && n0 + BN <= c.N;
-  const int nfull = interior ? int((kend - kbeg) / BK) : 0;
+  const bool interior = !CHECK || (c.vecA && c.vecB && m0 + BM <= c.M && n0 + BN <= c.N);
+  const int nfull = !CHECK ? nk : (interior ? int((kend - kbeg) / BK) : 0);
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -252,24 +254,35 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
       for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
 
   using LA = TileLoader<T, BM, BK, AK, false>;
-  using LB = TileLoader<T, BN, BK, BKC, KS>;
+  using LB = TileLoader<T, BN, BK, BKC, false>;
   LA la0, la1;
   LB lb0, lb1;
+  T kv0 = T(0), kv1 = T(0);        // one k-scaling factor per thread < BK, per set
   const int64_t sA = AK ? c.sam : c.sak;
   const int64_t sB = BKC ? c.sbn : c.sbk;
 
-  auto load = [&](LA& la, LB& lb, int s) {
+  auto load = [&](LA& la, LB& lb, T& kv, int s) __attribute__((always_inline)) {
     const int64_t k0 = kbeg + int64_t(s) * BK;
-    if (s < nfull) {
+    if (!CHECK || s < nfull) {
       la.load_fast(A, sA, m0, k0, nullptr);
-      lb.load_fast(B, sB, n0, k0, ks);
+      lb.load_fast(B, sB, n0, k0, nullptr);
     } else {
       la.load_checked(A, sA, m0, c.M, k0, kend, nullptr);
-      lb.load_checked(B, sB, n0, c.N, k0, kend, ks);
+      lb.load_checked(B, sB, n0, c.N, k0, kend, nullptr);
+    }
+    if constexpr (KS) {
+      if (threadIdx.x < BK)
+        kv = (!CHECK || k0 + threadIdx.x < kend) ? ks[k0 + threadIdx.x] : T(0);
+    }
+  };
+  auto stage_ks = [&](T kv, int stg) __attribute__((always_inline)) {
+    if constexpr (KS) {
+      if (threadIdx.x < BK) Ks[stg][threadIdx.x] = kv;
     }
   };
 
-  auto compute = [&](const T* __restrict__ as, const T* __restrict__ bs) {
+  auto compute = [&](const T* __restrict__ as, const T* __restrict__ bs,
+                     const T* __restrict__ kss) __attribute__((always_inline)) {
     T af[TM][KG];
     T bf[TN][KG];
 #pragma unroll
@@ -277,9 +290,9 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
       const T* p = as + (wm * WTM + i * 16 + lrow) * LDK + lgrp * KG;
 #pragma unroll
       for (int q = 0; q < KG; q += Vec16<T>::W) {
-        Vec16<T> x = *reinterpret_cast<const Vec16<T>*>(p + q);
+        const typename Vec16<T>::type x = *reinterpret_cast<const typename Vec16<T>::type*>(p + q);
 #pragma unroll
-        for (int j = 0; j < Vec16<T>::W; ++j) af[i][q + j] = x.v[j];
+        for (int j = 0; j < Vec16<T>::W; ++j) af[i][q + j] = x[j];
       }
     }
 #pragma unroll
@@ -287,10 +300,24 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
       const T* p = bs + (wn * WTN + i * 16 + lrow) * LDK + lgrp * KG;
 #pragma unroll
       for (int q = 0; q < KG; q += Vec16<T>::W) {
-        Vec16<T> x = *reinterpret_cast<const Vec16<T>*>(p + q);
+        const typename Vec16<T>::type x = *reinterpret_cast<const typename Vec16<T>::type*>(p + q);
 #pragma unroll
-        for (int j = 0; j < Vec16<T>::W; ++j) bf[i][q + j] = x.v[j];
+        for (int j = 0; j < Vec16<T>::W; ++j) bf[i][q + j] = x[j];
       }
+    }
+    if constexpr (KS) {
+      T kf[KG];
+#pragma unroll
+      for (int q = 0; q < KG; q += Vec16<T>::W) {
+        const typename Vec16<T>::type x =
+            *reinterpret_cast<const typename Vec16<T>::type*>(kss + lgrp * KG + q);
+#pragma unroll
+        for (int j = 0; j < Vec16<T>::W; ++j) kf[q + j] = x[j];
+      }
+#pragma unroll
+      for (int i = 0; i < TN; ++i)
+#pragma unroll
+        for (int q = 0; q < KG; ++q) bf[i][q] *= kf[q];
     }
 #pragma unroll
     for (int s = 0; s < KG; ++s)
@@ -303,28 +330,31 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
   // Two register sets: slice s lives in set s%2 from its load (two slices
   // ahead of its use) until it is written to LDS stage s%2.
   if (nk > 0) {
-    load(la0, lb0, 0);
-    if (nk > 1) load(la1, lb1, 1);
+    load(la0, lb0, kv0, 0);
+    if (nk > 1) load(la1, lb1, kv1, 1);
     la0.template store<LDK>(As[0]);
     lb0.template store<LDK>(Bs[0]);
+    stage_ks(kv0, 0);
   }
   __syncthreads();
   for (int kt = 0; kt < nk; kt += 2) {
     // even slice: compute stage 0, refill set 0 with slice kt+2, stage slice kt+1
-    if (kt + 2 < nk) load(la0, lb0, kt + 2);
-    compute(As[0], Bs[0]);
+    if (kt + 2 < nk) load(la0, lb0, kv0, kt + 2);
+    compute(As[0], Bs[0], Ks[0]);
     if (kt + 1 < nk) {
       la1.template store<LDK>(As[1]);
       lb1.template store<LDK>(Bs[1]);
+      stage_ks(kv1, 1);
     }
     __syncthreads();
     if (kt + 1 >= nk) break;
     // odd slice: compute stage 1, refill set 1 with slice kt+3, stage slice kt+2
-    if (kt + 3 < nk) load(la1, lb1, kt + 3);
-    compute(As[1], Bs[1]);
+    if (kt + 3 < nk) load(la1, lb1, kv1, kt + 3);
+    compute(As[1], Bs[1], Ks[1]);
     if (kt + 2 < nk) {
       la0.template store<LDK>(As[0]);
       lb0.template store<LDK>(Bs[0]);
+      stage_ks(kv0, 0);
     }
     __syncthreads();
   }
@@ -340,11 +370,11 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int64_t n = n0 + wn * WTN + j * 16 + lrow;
-        if (n >= c.N) continue;
+        if (CHECK && n >= c.N) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t m = m0 + wm * WTM + i * 16 + MF::out_row(lgrp, r);
-          if (m < c.M) C[m + n * c.ldc] = apply_epilogue(e, acc[i][j][r], m, n);
+          if (!CHECK || m < c.M) C[m + n * c.ldc] = apply_epilogue(e, acc[i][j][r], m, n);
         }
       }
   } else {
@@ -354,11 +384,11 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int64_t n = n0 + wn * WTN + j * 16 + lrow;
-        if (n >= c.N) continue;
+        if (CHECK && n >= c.N) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t m = m0 + wm * WTM + i * 16 + MF::out_row(lgrp, r);
-          if (m < c.M) P[m + n * c.M] = acc[i][j][r];
+          if (!CHECK || m < c.M) P[m + n * c.M] = acc[i][j][r];
         }
       }
   }
@@ -394,8 +424,8 @@ struct Cfg {
 
 // Tile shapes.  FP32 shapes are used for the filter products (both operands
 // k-contiguous); every other layout uses the last (generic) entry.
-static const Cfg kCfgF32[] = {{128, 128, 32, 2}, {128, 160, 16, 2}, {128, 64, 32, 2},
-                              {64, 160, 16, 3},  {128, 160, 32, 1}, {256, 160, 16, 1},
+static const Cfg kCfgF32[] = {{128, 128, 32, 1}, {128, 160, 16, 1}, {128, 64, 32, 2},
+                              {64, 160, 16, 2},  {128, 160, 32, 1}, {64, 320, 16, 1},
                               {64, 64, 32, 4}};
 static const Cfg kCfgF64[] = {{128, 128, 16, 1}, {128, 64, 16, 2}, {64, 64, 16, 3}};
 static constexpr int kNumF32 = 7, kNumF64 = 3;
@@ -511,21 +541,31 @@ static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspa
     if (e0 != hipSuccess) return e0;
   }
   const bool KS = d.kscale != nullptr;
+  // the unchecked variant needs whole tiles, whole k slices and aligned operands
+  const bool aligned = c.vecA && c.vecB && d.M % BM == 0 && d.N % BN == 0 && d.K % BK == 0 &&
+                       c.kchunk % BK == 0;
   if (AK && BKC) {
-    if (KS)
-      gemm_kernel<T, BM, BN, BK, MINW, true, true, true><<<dim3(grid), dim3(256), 0, st>>>(a);
-    else
-      gemm_kernel<T, BM, BN, BK, MINW, true, true, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+    if (aligned) {
+      if (KS)
+        gemm_kernel<T, BM, BN, BK, MINW, true, true, true, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+      else
+        gemm_kernel<T, BM, BN, BK, MINW, true, true, false, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+    } else {
+      if (KS)
+        gemm_kernel<T, BM, BN, BK, MINW, true, true, true, true><<<dim3(grid), dim3(256), 0, st>>>(a);
+      else
+        gemm_kernel<T, BM, BN, BK, MINW, true, true, false, true><<<dim3(grid), dim3(256), 0, st>>>(a);
+    }
   } else if (KS || FILTER_ONLY) {
     return hipErrorInvalidValue;   // k-scaling is only used with k-contiguous operands
   } else if constexpr (FILTER_ONLY) {
     return hipErrorInvalidValue;
   } else if (AK && !BKC) {
-    gemm_kernel<T, BM, BN, BK, MINW, true, false, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+    gemm_kernel<T, BM, BN, BK, MINW, true, false, false, true><<<dim3(grid), dim3(256), 0, st>>>(a);
   } else if (!AK && BKC) {
-    gemm_kernel<T, BM, BN, BK, MINW, false, true, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+    gemm_kernel<T, BM, BN, BK, MINW, false, true, false, true><<<dim3(grid), dim3(256), 0, st>>>(a);
   } else {
-    gemm_kernel<T, BM, BN, BK, MINW, false, false, false><<<dim3(grid), dim3(256), 0, st>>>(a);
+    gemm_kernel<T, BM, BN, BK, MINW, false, false, false, true><<<dim3(grid), dim3(256), 0, st>>>(a);
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
@@ -567,12 +607,12 @@ hipError_t gemm(const GemmDesc<T>& d, hipStream_t st, const Workspace& ws, int f
   if constexpr (sizeof(T) == 4) {
     if (!filter_layout) return launch_cfg<float, 64, 64, 32, 4>(d, st, ws, splits);
     switch (cfg) {
-      case 0: return launch_f32_filter<128, 128, 32, 2>(d, st, ws, splits);
-      case 1: return launch_f32_filter<128, 160, 16, 2>(d, st, ws, splits);
+      case 0: return launch_f32_filter<128, 128, 32, 1>(d, st, ws, splits);
+      case 1: return launch_f32_filter<128, 160, 16, 1>(d, st, ws, splits);
       case 2: return launch_f32_filter<128, 64, 32, 2>(d, st, ws, splits);
-      case 3: return launch_f32_filter<64, 160, 16, 3>(d, st, ws, splits);
+      case 3: return launch_f32_filter<64, 160, 16, 2>(d, st, ws, splits);
       case 4: return launch_f32_filter<128, 160, 32, 1>(d, st, ws, splits);
-      case 5: return launch_f32_filter<256, 160, 16, 1>(d, st, ws, splits);
+      case 5: return launch_f32_filter<64, 320, 16, 1>(d, st, ws, splits);
       default: return launch_f32_filter<64, 64, 32, 4>(d, st, ws, splits);
     }
   } else {

@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_recon_bf16(const uint16_t* RY, const do
 // registers, so an element costs 8 LDS reads per operand (u, and V*u for the
 // mass-weighted potential) instead of 27.
 // ---------------------------------------------------------------------------
-enum StencilKind { SK_APPLY = 0, SK_RSTEP = 1, SK_CSTEP = 2 };
+enum StencilKind { SK_APPLY = 0, SK_RSTEP = 1, SK_CSTEP = 2, SK_RESID = 3 };
 
 template <typename S>
 __device__ __forceinline__ float ld_f(const S* p, int64_t i);
@@ -252,8 +252,12 @@ __device__ __forceinline__ void st_s(S* p, int64_t i, F v) {
 template <typename F>
 struct SepArgs {
   int nx, ny, nz, ty, ntiles_y;
+  int z0, nzs;               // output planes [z0, z0 + nzs)
+  int64_t out_off;           // output row index = grid index - out_off
   int mode;                  // field mode
   F cA[4], cM[4];            // class coefficients of S and of the mass stencil
+  F cB[4];                   // SK_RESID: class coefficients of B (b_identity: B = I)
+  int b_identity;
   const double* V;
   const void* dinv;          // length n, F-typed (FP32 for FP32/BF16 storage, FP64 for FP64)
   const void* src;           // operand block (APPLY: X, RSTEP: R_Y, CSTEP: src)
@@ -329,14 +333,15 @@ __global__ __launch_bounds__(256) void k_stencil_sep(SepArgs<F> a) {
     }
   };
 
-  stage(0, nz - 1);
-  stage(1, 0);
+  const int zb = a.z0, ze = a.z0 + a.nzs;
+  stage(0, zb == 0 ? nz - 1 : zb - 1);
+  stage(1, zb);
   __syncthreads();
   partials(0, pu[0], pw[0]);
   partials(1, pu[1], pw[1]);
   __syncthreads();
-  for (int z = 0; z < nz; ++z) {
-    const int buf = z & 1;                   // plane z+1 goes to the buffer of z-1
+  for (int z = zb; z < ze; ++z) {
+    const int buf = (z - zb) & 1;            // plane z+1 goes to the buffer of z-1
     stage(buf, z + 1 < nz ? z + 1 : 0);
     __syncthreads();
     partials(buf, pu[2], pw[2]);
@@ -362,7 +367,12 @@ __global__ __launch_bounds__(256) void k_stencil_sep(SepArgs<F> a) {
         av += F(0.5) * (F(a.V[i]) * mu + mw);
       }
       if constexpr (KIND == SK_APPLY) {
-        st_s<S, F>(static_cast<S*>(a.out) + int64_t(j) * a.ld_out, i, av);
+        st_s<S, F>(static_cast<S*>(a.out) + int64_t(j) * a.ld_out, i - a.out_off, av);
+      } else if constexpr (KIND == SK_RESID) {
+        // r = A x - lambda_j B x from the same class sums
+        const F bx = a.b_identity ? s0 : a.cB[0] * s0 + a.cB[1] * s1 + a.cB[2] * s2 + a.cB[3] * s3;
+        st_s<S, F>(static_cast<S*>(a.out) + int64_t(j) * a.ld_out, i - a.out_off,
+                   av - a.colcoef[j] * bx);
       } else if constexpr (KIND == SK_RSTEP) {
         S* RX = static_cast<S*>(a.out) + int64_t(j) * a.ld_out;
         const S* Yf = static_cast<const S*>(a.forcing) + int64_t(j) * a.ld_forcing;
@@ -429,6 +439,11 @@ bool sep_setup(const chfsi_operator& op, SepArgs<F>* a) {
   a->nx = op.nx;
   a->ny = op.ny;
   a->nz = op.nz;
+  a->z0 = 0;
+  a->nzs = op.nz;
+  a->out_off = 0;
+  a->b_identity = 1;
+  for (int i = 0; i < 4; ++i) a->cB[i] = F(0);
   a->ty = ty;
   a->ntiles_y = (op.ny + ty - 1) / ty;
   a->mode = op.field_mode;
@@ -621,6 +636,48 @@ hipError_t rchfsi_reconstruct_bf16(const void* RY, const double* dinv, const dou
   k_recon_bf16<<<grid_for(n * b), 256, 0, st>>>(static_cast<const uint16_t*>(RY), dinv, X, ldx,
                                                 lamY, Yp, ldy, n, b);
   return hipGetLastError();
+}
+
+// Y_slab = (op X)[rows of planes z0 .. z0+nzs-1]; Y_slab rows are indexed
+// from the slab's first grid point.  Class-symmetric coefficients only.
+hipError_t stencil_apply_slab_f64(const chfsi_operator& op, const double* X, int64_t ldx,
+                                  double* Yslab, int64_t ldy, int64_t b, int z0, int nzs,
+                                  hipStream_t st) {
+  SepArgs<double> a;
+  if (!sep_setup(op, &a) || z0 < 0 || nzs < 1 || z0 + nzs > op.nz) return hipErrorInvalidValue;
+  a.z0 = z0;
+  a.nzs = nzs;
+  a.out_off = int64_t(z0) * op.nx * op.ny;
+  a.src = X;
+  a.lds_src = ldx;
+  a.out = Yslab;
+  a.ld_out = ldy;
+  return sep_launch<double, double, SK_APPLY>(a, b, st);
+}
+
+// R = A X - B X diag(lam) in one pass (B = NULL: identity).  Class-symmetric only.
+hipError_t stencil_residual_f64(const chfsi_operator& A, const chfsi_operator* B, const double* X,
+                                int64_t ldx, const double* lam, double* R, int64_t ldr, int64_t b,
+                                hipStream_t st) {
+  SepArgs<double> a;
+  if (!sep_setup(A, &a)) return hipErrorInvalidValue;
+  if (B) {
+    double cb[4];
+    if (!class_symmetric(B->coef, cb)) return hipErrorInvalidValue;
+    for (int i = 0; i < 4; ++i) a.cB[i] = cb[i];
+    a.b_identity = 0;
+  }
+  a.src = X;
+  a.lds_src = ldx;
+  a.out = R;
+  a.ld_out = ldr;
+  a.colcoef = lam;
+  return sep_launch<double, double, SK_RESID>(a, b, st);
+}
+
+bool stencil_separable(const chfsi_operator& op) {
+  SepArgs<double> a;
+  return sep_setup(op, &a);
 }
 
 }  // namespace chfsi

@@ -40,6 +40,17 @@ hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, 
                                   int64_t lds, const double* prev, int64_t ldp, double* dst,
                                   StencilStep s, int64_t b, hipStream_t st);
 
+// Slab-wise application: Yslab = rows of (op X) in planes [z0, z0 + nzs)
+hipError_t stencil_apply_slab_f64(const chfsi_operator& op, const double* X, int64_t ldx,
+                                  double* Yslab, int64_t ldy, int64_t b, int z0, int nzs,
+                                  hipStream_t st);
+// Fused residual R = A X - B X diag(lam) (B NULL: identity)
+hipError_t stencil_residual_f64(const chfsi_operator& A, const chfsi_operator* B, const double* X,
+                                int64_t ldx, const double* lam, double* R, int64_t ldr, int64_t b,
+                                hipStream_t st);
+// true when the z-marching class-sum kernels apply (tensor-product coefficients)
+bool stencil_separable(const chfsi_operator& op);
+
 // BF16 block helpers
 hipError_t rchfsi_init_bf16(const double* R, int64_t ldr, int64_t n, int64_t b, double scale,
                             void* RY, void* RX, void* Yc, hipStream_t st);
