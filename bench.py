@@ -259,7 +259,8 @@ def main():
 
 def bench_grid(args):
     """Grid pencil (periodic 27-point Q1 FE stencils + Gaussian wells), residual filter in
-    BF16 (or FP32/FP64) storage; one step = filter + FP64 Rayleigh-Ritz.  HBM roofline."""
+    BF16 (or FP32/FP64) storage, through chfsi_solve; one step = one outer iteration
+    (filter + FP64 Rayleigh-Ritz).  HBM roofline of the fused stencil filter step."""
     import numpy as np
     import torch
 
@@ -267,10 +268,12 @@ def bench_grid(args):
     import workloads as wl
 
     torch.cuda.set_device(0)
-    g, b, nw = args.grid, 1200 if args.grid >= 96 else max(16, args.grid * 4), None
-    nw = int(round(b / 1.2))
-    p = args.degree if args.degree != 20 else 30
-    prob = wl.stencil_problem(grid=g, n_wells=args.wells, n_wanted=nw, block=b, degree=p, seed=1002)
+    g = args.grid
+    b = {128: 1200, 160: 2400}.get(g, max(16, (g * g) // 12))
+    nw = int(round(b / 1.2)) if g not in (128, 160) else {128: 1000, 160: 2000}[g]
+    p = args.degree if args.degree != 20 else {160: 40}.get(g, 30)
+    prob = wl.stencil_problem(grid=g, n_wells=args.wells, n_wanted=nw, block=b, degree=p,
+                              seed=1002 if g != 160 else 1004)
     n = prob.n
     prec = {"bf16": P.PREC_BF16, "fp32": P.PREC_FP32, "fp64": P.PREC_FP64}[args.prec]
     esize = {"bf16": 2, "fp32": 4, "fp64": 8}[args.prec]
@@ -279,61 +282,53 @@ def bench_grid(args):
                              field_mode=prob.field_mode)
     opB = P.stencil_operator(prob.shape, prob.coef_B)
     lmax = 18.5
-    prm = P.make_params(nw, b, p, max_iter=200, tol=1e-8, method=P.METHOD_RCHFSI,
+    free, _ = torch.cuda.mem_get_info()
+    mode = 0
+    prm = P.make_params(nw, b, p, max_iter=args.warmup, tol=0.0, method=P.METHOD_RCHFSI,
                         filter_prec=prec, lambda_max=lmax, profile=1, seed=2002, init_random=1)
+    need = P.chfsi_workspace_bytes(opA, opB, prm) + n * b * 8
+    if need > 0.9 * free and prec != P.PREC_FP64:
+        mode = 1
+    prm.memory_mode = mode
+    log(f"grid {g}^3: n={n}, b={b}, p={p}, memory_mode={mode}, "
+        f"workspace {P.chfsi_workspace_bytes(opA, opB, prm) / 2**30:.1f} GiB")
     stream = torch.cuda.current_stream()
     ctx = P.chfsi_create(opA, opB, None, prm, stream=stream, keep=(Vd,))
     X = P.colmajor_empty(n, b)
-    Xn = P.colmajor_empty(n, b)
-    R = P.colmajor_empty(n, b)
-    Y = P.colmajor_empty(n, b)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(2002)
-    X.copy_(torch.randn(b, n, dtype=torch.float64, device="cuda", generator=gen).t())
-    ritz, norms = P.chfsi_rayleigh_ritz(ctx, X, Xn, R)
-    X, Xn = Xn, X
-    filt = []
-
-    def step():
-        nonlocal X, Xn, ritz, norms
-        e1, eb = ritz[0], ritz[-1]
-        s0 = torch.cuda.Event(enable_timing=True)
-        s1 = torch.cuda.Event(enable_timing=True)
-        s0.record(stream)
-        P.chfsi_filter(ctx, X, ritz, R, Y, e1 - 0.05 * (eb - e1), lmax, eb)
-        s1.record(stream)
-        filt.append((s0, s1))
-        ritz, norms = P.chfsi_rayleigh_ritz(ctx, Y, X, R)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    if args.warmup > 0:
+        P.chfsi_solve(ctx, X)                      # random start + warm-up iterations
     P.chfsi_filter_kernel_time(ctx)
-    filt.clear()
+    prm2 = P.make_params(nw, b, p, max_iter=args.steps, tol=0.0, method=P.METHOD_RCHFSI,
+                         filter_prec=prec, lambda_max=lmax, profile=1, seed=2002,
+                         init_random=0 if args.warmup > 0 else 1, memory_mode=mode)
+    ctx.close()
+    ctx = P.chfsi_create(opA, opB, None, prm2, stream=stream, keep=(Vd,))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    st, ev, rn, rep = P.chfsi_solve(ctx, X)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms, kn = P.chfsi_filter_kernel_time(ctx)
-    filt_ms = sum(a.elapsed_time(b_) for a, b_ in filt)
-    step_bytes = 4.0 * esize * n * b * (p - 1)
-    per = kms / max(kn, 1)
+    its = max(rep["iterations"], 1)
+    per = rep["kernel_ms"] / max(rep["kernel_launches"], 1)
     achieved = 4.0 * esize * n * b / (per / 1e3) / 1e9
-    out = {"metric": METRIC, "value": round(step_bytes * args.steps / (filt_ms / 1e3) / 1e9, 1),
-           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(wall * 1e3 / args.steps, 2), "higher_is_better": True,
+    step_bytes = 4.0 * esize * n * b * (p - 1)
+    out = {"metric": METRIC,
+           "value": round(step_bytes * its / (rep["time_filter_ms"] / 1e3) / 1e9, 1),
+           "unit": "GB/s", "n_gpus": 1, "steps": its, "warmup": args.warmup,
+           "ms_per_step": round(wall * 1e3 / its, 2), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
            "config": {"workload": f"periodic {g}^3 grid pencil, 27-point Q1 stiffness/mass, "
                                   f"{args.wells} Gaussian wells (mass-weighted), block {b}, "
                                   f"{nw} wanted, degree {p}, {args.prec} residual filter",
-                      "n": n, "block": b, "degree": p,
-                      "filter_ms_per_step": round(filt_ms / args.steps, 2),
-                      "max_residual_after": max(norms[:nw])},
+                      "n": n, "block": b, "degree": p, "memory_mode": mode,
+                      "filter_ms_per_step": round(rep["time_filter_ms"] / its, 2),
+                      "rr_ms_per_step": round(rep["time_rr_ms"] / its, 2),
+                      "jacobi_sweeps": rep["jacobi_sweeps"],
+                      "max_residual_after": rep["max_residual"]},
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                         "traffic": None,
-                        "kernel": f"k_stencil_sep<{args.prec}> residual-filter step "
+                        "kernel": f"k_zmarch<{args.prec}> residual-filter step "
                                   f"(4 streams x {esize} B per element-step)",
                         "ms_per_launch": round(per, 3)}}
     print(json.dumps(out), flush=True)

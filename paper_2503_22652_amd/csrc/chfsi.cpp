@@ -91,7 +91,8 @@ struct chfsi_ctx {
 
   // filter precision copies / buffers
   float* A32 = nullptr;
-  float* dinv32 = nullptr;
+  float* dinv32 = nullptr;        // FP32 D^{-1} (dense: always; stencil: only when given)
+  float* Vf = nullptr;            // FP32 potential of a stencil operator (FP32/BF16 filter)
   float *f32_a = nullptr, *f32_b = nullptr, *f32_c = nullptr;     // RX, RY, Y copy (n x b)
   double *f64_a = nullptr, *f64_b = nullptr;                        // RX, RY (FP64 filter)
   void *bf_a = nullptr, *bf_b = nullptr, *bf_c = nullptr;           // BF16 stencil filter blocks
@@ -253,6 +254,9 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
   } else {
     s.bfblk = size_t(n) * b * 2;
   }
+  // stencil filters in FP32/BF16: FP32 copies of D^{-1} and of the potential
+  if (!dense && p->filter_prec != CHFSI_PREC_FP64)
+    s.a32 += size_t(n) * sizeof(float) * (1 + (A->field_mode != 0 ? 1 : 0));
   s.coef = size_t(p->degree + 1) * b * sizeof(double);
   size_t ws = 0;
   if (dense) {
@@ -467,7 +471,7 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
           hipEvent_t e0, e1;
           CK(prof_pair(c, &e0, &e1));
           if (e0) CK(hipEventRecord(e0, c->stream));
-          CK(stencil_rchfsi_step_f32(c->A, c->dinv32, RY, RX, Yc, c->coef32 + int64_t(s) * b, ss, b,
+          CK(stencil_rchfsi_step_f32(c->A, c->Vf, c->dinv32, RY, RX, Yc, c->coef32 + int64_t(s) * b, ss, b,
                                      c->stream));
           if (e1) CK(hipEventRecord(e1, c->stream));
         }
@@ -552,7 +556,7 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
         hipEvent_t e0, e1;
         CK(prof_pair(c, &e0, &e1));
         if (e0) CK(hipEventRecord(e0, c->stream));
-        CK(stencil_rchfsi_step_bf16(c->A, c->dinv32, RY, RX, Yc, c->coef32 + int64_t(s) * b, ss, b,
+        CK(stencil_rchfsi_step_bf16(c->A, c->Vf, c->dinv32, RY, RX, Yc, c->coef32 + int64_t(s) * b, ss, b,
                                     c->stream));
         if (e1) CK(hipEventRecord(e1, c->stream));
       }
@@ -1269,7 +1273,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   const bool dense = A->kind == CHFSI_OP_DENSE;
   if (params->filter_prec == CHFSI_PREC_FP32) {
     if (dense) c->A32 = ctx_alloc<float>(c, size_t(n) * n * sizeof(float), &st);
-    c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+    if (dense || d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
     c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
     c->f32_b = ctx_alloc<float>(c, sp.f32blk, &st);
     c->f32_c = ctx_alloc<float>(c, sp.f32blk, &st);
@@ -1277,11 +1281,13 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     c->f64_a = ctx_alloc<double>(c, sp.f64blk, &st);
     c->f64_b = ctx_alloc<double>(c, sp.f64blk, &st);
   } else {
-    c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+    if (dense || d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
     c->bf_a = ctx_alloc<char>(c, sp.bfblk, &st);
     c->bf_b = ctx_alloc<char>(c, sp.bfblk, &st);
     c->bf_c = ctx_alloc<char>(c, sp.bfblk, &st);
   }
+  if (!dense && params->filter_prec != CHFSI_PREC_FP64 && A->field_mode != 0)
+    c->Vf = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
   c->coef_cap = params->degree;
   c->coef32 = ctx_alloc<float>(c, size_t(params->degree) * b * sizeof(float), &st);
   c->coef64 = ctx_alloc<double>(c, size_t(params->degree) * b * sizeof(double), &st);
@@ -1361,6 +1367,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     else
       e = fill_ones_f32(c->dinv32, n, c->stream);
   }
+  if (e == hipSuccess && c->Vf) e = convert_f64_f32(A->field, n, c->Vf, n, n, 1, c->stream);
   if (e == hipSuccess && A->kind == CHFSI_OP_STENCIL27) e = stencil_check(*A);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {

@@ -21,6 +21,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <cstdlib>
 
 namespace chfsi {
 
@@ -134,7 +136,8 @@ __global__ __launch_bounds__(256) void k_rstep_f32(Coefs cf, Grid g, const float
     const int64_t j = idx / n, i = idx - j * n;
     const int x = int(i % g.nx), y = int((i / g.nx) % g.ny), z = int(i / (int64_t(g.nx) * g.ny));
     const float* col = RY + j * n;
-    const float av = apply_point<float>(cf, g, x, y, z, [&](int64_t k) { return dinv[k] * col[k]; });
+    const float av = apply_point<float>(cf, g, x, y, z,
+                                        [&](int64_t k) { return dinv ? dinv[k] * col[k] : col[k]; });
     const int64_t e = i + j * n;
     RX[e] = a * av + bb * RY[e] + cc * RX[e] + dd * colcoef[j] * Yf[e];
   }
@@ -152,7 +155,10 @@ __global__ __launch_bounds__(256) void k_rstep_bf16(Coefs cf, Grid g, const floa
     const int x = int(i % g.nx), y = int((i / g.nx) % g.ny), z = int(i / (int64_t(g.nx) * g.ny));
     const uint16_t* col = RY + j * n;
     const float av = apply_point<float>(cf, g, x, y, z,
-                                        [&](int64_t k) { return dinv[k] * bf16_to_f32(col[k]); });
+                                        [&](int64_t k) {
+                                          const float u = bf16_to_f32(col[k]);
+                                          return dinv ? dinv[k] * u : u;
+                                        });
     const int64_t e = i + j * n;
     const float v = a * av + bb * bf16_to_f32(RY[e]) + cc * bf16_to_f32(RX[e]) +
                     dd * colcoef[j] * bf16_to_f32(Yf[e]);
@@ -402,6 +408,371 @@ __global__ __launch_bounds__(256) void k_stencil_sep(SepArgs<F> a) {
   (void)n;
 }
 
+// ---------------------------------------------------------------------------
+// Vectorised, software-pipelined z-marching kernel (class-symmetric
+// coefficients, no diagonal scaling of the operand).
+//
+// Every plane p contributes to the outputs of planes p-1, p and p+1 through
+// two class combinations of its in-plane partial sums P0, P1, P2:
+//   centre     C = c0 P0 + c1 P1 + c2 P2      (p is the output plane)
+//   neighbour  N = c1 P0 + c2 P1 + c3 P2      (p is one plane above or below)
+// so out(z) = N(z-1) + C(z) + N(z+1) needs two running sums per operator and
+// point.  Two such operators are carried: K (the stencil on u plus the
+// stencil on w = V u) and M (the mass stencil on u, multiplied by V at the
+// output point), which together give the mass-weighted potential
+// 1/2 (diag(V) M + M diag(V)) u; the diagonal potential is M = identity.
+// Linear terms of the step (beta * src, -lambda_j * B u) fold into the
+// coefficients, so one pass gives every kind of update:
+//   out = K + V * M + gamma * e1 + delta * colcoef[j] * e2.
+//
+// A workgroup owns CP columns, a slab of TY full x rows and a range of z
+// planes.  Thread t owns PT consecutive x points of one slab row in all CP
+// columns.  Each plane (CP operand columns and the potential, with one halo row
+// on each side and the periodic x wrap cells) is staged into one of two LDS
+// buffers from registers loaded one plane ahead, so a single barrier per plane
+// separates the writes from the reads and the global loads of plane z+2 and of
+// the epilogue operands of z+1 are in flight while plane z+1 is processed.
+// Workgroup ids are remapped so that the y-tiles of one column group run on
+// the same XCD, where the halo rows they share hit that XCD's L2.
+// ---------------------------------------------------------------------------
+enum ZmKind { ZM_APPLY = 0, ZM_RESID = 1, ZM_STEP = 2 };
+
+template <typename F>
+struct ZmArgs {
+  int nx, ny, nz, ty, ntiles_y, b;
+  int z0, nzs;               // output planes [z0, z0 + nzs)
+  int64_t out_off;           // output row index = grid index - out_off
+  F cu[4], cw[4], cm[4];     // class coefficients on u, on w = V u, and of M
+  F cb[4];                   // ZM_RESID: B class coefficients (scaled by -lambda_j)
+  const F* V;                // potential (has_v)
+  const void* src;
+  int64_t ld_src;
+  void* out;
+  int64_t ld_out;
+  const void* e1;            // ZM_STEP: first extra stream (may alias out)
+  int64_t ld_e1;
+  F gamma;
+  const void* e2;            // ZM_STEP: second extra stream, scaled per column
+  int64_t ld_e2;
+  F delta;
+  const F* colcoef;          // ZM_STEP: per-column factor of e2; ZM_RESID: lambda_j
+};
+
+template <typename S, typename F, int PT>
+__device__ __forceinline__ void zm_cvt(const S __attribute__((ext_vector_type(PT))) & v,
+                                       F (&o)[PT]) {
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    if constexpr (sizeof(S) == 2)
+      o[i] = F(__uint_as_float(uint32_t(v[i]) << 16));
+    else
+      o[i] = F(v[i]);
+  }
+}
+
+template <typename S, typename F, int PT, int CP, int KIND, bool HASV, int DIST>
+__global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
+  using SV = S __attribute__((ext_vector_type(PT)));
+  using FV = F __attribute__((ext_vector_type(PT)));
+  extern __shared__ __attribute__((aligned(16))) unsigned char zm_smem[];
+  F* lds = reinterpret_cast<F*>(zm_smem);
+  const int nx = a.nx, ny = a.ny, nz = a.nz, TY = a.ty;
+  const int RS = nx + 8;                     // LDS row: [3] = x(-1), [4..4+nx) = row, [4+nx] = x(nx)
+  const int plane = (TY + 2) * RS;
+  constexpr int NOPS = CP + (HASV ? 1 : 0);  // operand planes per buffer (columns, then V)
+  const int bufsz = NOPS * plane;
+
+  // XCD-aware tile order: consecutive ids on one XCD take consecutive tiles
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = bid & 7, loc = bid >> 3;
+  const int t = xcd < r8 ? xcd * (q8 + 1) + loc : r8 * (q8 + 1) + (xcd - r8) * q8 + loc;
+  const int cg = t / a.ntiles_y, ytile = t - cg * a.ntiles_y;
+  const int y0 = ytile * TY, tyn = min(TY, ny - y0);
+  const int col0 = cg * CP, ncol = min(CP, a.b - col0);
+  const int64_t pstride = int64_t(nx) * ny;
+
+  const int tpr = nx / PT;
+  const int tid = threadIdx.x;
+  const int my_row = tid / tpr, xq = (tid - my_row * tpr) * PT;
+  const bool active = my_row < tyn;
+
+  // staging chunks: PT consecutive elements of one of the tyn+2 slab rows
+  const int nchunk = (tyn + 2) * tpr;
+  int g_off[2], l_off[2], wrapl[2], wrapr[2];
+  bool okc[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int k = tid + 256 * m;
+    okc[m] = k < nchunk;
+    const int rr = okc[m] ? k / tpr : 0;
+    const int xx = (k - rr * tpr) * PT;
+    int y = y0 - 1 + rr;
+    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    g_off[m] = y * nx + xx;
+    l_off[m] = rr * RS + 4 + xx;
+    wrapl[m] = xx == nx - PT ? rr * RS + 3 : -1;   // last chunk of a row feeds x = -1
+    wrapr[m] = xx == 0 ? rr * RS + 4 + nx : -1;    // first chunk feeds x = nx
+  }
+
+  const S* src = static_cast<const S*>(a.src);
+  struct Staged {
+    SV us[2][CP];
+    FV vs[2];
+  };
+  auto load_plane = [&](int zp, Staged& R) __attribute__((always_inline)) {
+    const int64_t zo = int64_t(zp) * pstride;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (!okc[m]) continue;
+#pragma unroll
+      for (int c = 0; c < CP; ++c)
+        if (c < ncol)
+          R.us[m][c] =
+              *reinterpret_cast<const SV*>(src + int64_t(col0 + c) * a.ld_src + zo + g_off[m]);
+      if constexpr (HASV) R.vs[m] = *reinterpret_cast<const FV*>(a.V + zo + g_off[m]);
+    }
+  };
+  auto write_plane = [&](int buf, const Staged& R) __attribute__((always_inline)) {
+    F* base = lds + buf * bufsz;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (!okc[m]) continue;
+#pragma unroll
+      for (int c = 0; c < NOPS; ++c) {
+        F v[PT];
+        if (HASV && c == CP) {
+#pragma unroll
+          for (int i = 0; i < PT; ++i) v[i] = R.vs[m][i];
+        } else if (c < ncol) {
+          zm_cvt<S, F, PT>(R.us[m][c < CP ? c : 0], v);
+        } else {
+#pragma unroll
+          for (int i = 0; i < PT; ++i) v[i] = F(0);
+        }
+        F* pl = base + c * plane;
+        FV w;
+#pragma unroll
+        for (int i = 0; i < PT; ++i) w[i] = v[i];
+        *reinterpret_cast<FV*>(pl + l_off[m]) = w;
+        if (wrapl[m] >= 0) pl[wrapl[m]] = v[PT - 1];
+        if (wrapr[m] >= 0) pl[wrapr[m]] = v[0];
+      }
+    }
+  };
+
+  // per-column coefficients on u (RESID subtracts lambda_j times B's)
+  F cu[CP][4];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) {
+    const F lam = (KIND == ZM_RESID && c < ncol) ? a.colcoef[col0 + c] : F(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cu[c][k] = KIND == ZM_RESID ? a.cu[k] - lam * a.cb[k] : a.cu[k];
+  }
+
+  // potential around this thread's points (3 rows x PT+2), read once per plane
+  F vseg[3][PT + 2], vcen[PT];
+  auto vread = [&](int buf) __attribute__((always_inline)) {
+    if constexpr (HASV) {
+      const F* vb = lds + buf * bufsz + CP * plane + my_row * RS + 3 + xq;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const FV mid = *reinterpret_cast<const FV*>(vb + r * RS + 1);
+        vseg[r][0] = vb[r * RS];
+#pragma unroll
+        for (int i = 0; i < PT; ++i) vseg[r][i + 1] = mid[i];
+        vseg[r][PT + 1] = vb[r * RS + PT + 1];
+      }
+#pragma unroll
+      for (int i = 0; i < PT; ++i) vcen[i] = vseg[1][i + 1];
+    }
+  };
+  // centre and neighbour combinations of column c in one staged plane
+  auto combos = [&](int buf, int c, F (&ck)[PT], F (&nk)[PT], F (&cmv)[PT], F (&nmv)[PT])
+      __attribute__((always_inline)) {
+    const F* ub = lds + buf * bufsz + c * plane + my_row * RS + 3 + xq;   // row y-1, x = xq-1
+    F useg[3][PT + 2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const FV mid = *reinterpret_cast<const FV*>(ub + r * RS + 1);
+      useg[r][0] = ub[r * RS];
+#pragma unroll
+      for (int i = 0; i < PT; ++i) useg[r][i + 1] = mid[i];
+      useg[r][PT + 1] = ub[r * RS + PT + 1];
+    }
+    F vsu[PT + 2];
+#pragma unroll
+    for (int k = 0; k < PT + 2; ++k) vsu[k] = useg[0][k] + useg[2][k];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const F p0 = useg[1][i + 1];
+      const F p1 = useg[1][i] + useg[1][i + 2] + vsu[i + 1];
+      const F p2 = vsu[i] + vsu[i + 2];
+      ck[i] = cu[c][0] * p0 + cu[c][1] * p1 + cu[c][2] * p2;
+      nk[i] = cu[c][1] * p0 + cu[c][2] * p1 + cu[c][3] * p2;
+      if constexpr (HASV) {
+        cmv[i] = a.cm[0] * p0 + a.cm[1] * p1 + a.cm[2] * p2;
+        nmv[i] = a.cm[1] * p0 + a.cm[2] * p1 + a.cm[3] * p2;
+      }
+    }
+    if constexpr (HASV) {
+      F wseg[3][PT + 2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < PT + 2; ++k) wseg[r][k] = vseg[r][k] * useg[r][k];
+      F vsw[PT + 2];
+#pragma unroll
+      for (int k = 0; k < PT + 2; ++k) vsw[k] = wseg[0][k] + wseg[2][k];
+#pragma unroll
+      for (int i = 0; i < PT; ++i) {
+        const F p0 = wseg[1][i + 1];
+        const F p1 = wseg[1][i] + wseg[1][i + 2] + vsw[i + 1];
+        const F p2 = vsw[i] + vsw[i + 2];
+        ck[i] += a.cw[0] * p0 + a.cw[1] * p1 + a.cw[2] * p2;
+        nk[i] += a.cw[1] * p0 + a.cw[2] * p1 + a.cw[3] * p2;
+      }
+    }
+  };
+
+  // epilogue operands of one output plane
+  struct Extra {
+    SV e1[CP], e2[CP];
+  };
+  const S* e1p = static_cast<const S*>(a.e1);
+  const S* e2p = static_cast<const S*>(a.e2);
+  auto load_e = [&](int z, Extra& E) __attribute__((always_inline)) {
+    if constexpr (KIND == ZM_STEP) {
+      if (!active) return;
+      const int64_t gi = int64_t(z) * pstride + int64_t(y0 + my_row) * nx + xq;
+#pragma unroll
+      for (int c = 0; c < CP; ++c) {
+        if (c >= ncol) continue;
+        if (e1p) E.e1[c] = *reinterpret_cast<const SV*>(e1p + int64_t(col0 + c) * a.ld_e1 + gi);
+        if (e2p) E.e2[c] = *reinterpret_cast<const SV*>(e2p + int64_t(col0 + c) * a.ld_e2 + gi);
+      }
+    }
+  };
+
+  F accK[CP][PT], accKn[CP][PT], accM[CP][PT], accMn[CP][PT], vc[PT];
+  const int zb = a.z0, ze = a.z0 + a.nzs;
+  auto wz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+
+  // Planes and epilogue operands are prefetched DIST iterations ahead.  With
+  // DIST = 2 the register set A carries the planes zb-1, zb+1, zb+3, ... and
+  // B the others; the epilogue operands of output plane z are loaded right
+  // after output z-DIST has consumed their set.
+  static_assert(DIST == 1 || DIST == 2, "prefetch distance");
+  Staged A, B;
+  Extra EA, EB;
+  load_plane(wz(zb - 1), A);
+  if (DIST == 2) load_plane(wz(zb), B);
+  load_e(zb, EA);
+  if (DIST == 2 && zb + 1 < ze) load_e(zb + 1, EB);
+  write_plane(0, A);
+  load_plane(wz(DIST == 2 ? zb + 1 : zb), A);
+  __syncthreads();
+  if (active) {
+    vread(0);
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      F ck[PT], nk[PT], cmv[PT], nmv[PT];
+      combos(0, c, ck, nk, cmv, nmv);
+#pragma unroll
+      for (int i = 0; i < PT; ++i) {
+        accK[c][i] = nk[i];
+        accM[c][i] = HASV ? nmv[i] : F(0);
+      }
+    }
+  }
+  Staged& R1 = DIST == 2 ? B : A;
+  write_plane(1, R1);
+  if (zb + DIST <= ze) load_plane(wz(zb + DIST), R1);
+  __syncthreads();
+  if (active) {
+    vread(1);
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      F ck[PT], nk[PT], cmv[PT], nmv[PT];
+      combos(1, c, ck, nk, cmv, nmv);
+#pragma unroll
+      for (int i = 0; i < PT; ++i) {
+        accK[c][i] += ck[i];
+        accKn[c][i] = nk[i];
+        if constexpr (HASV) {
+          accM[c][i] += cmv[i];
+          accMn[c][i] = nmv[i];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PT; ++i) vc[i] = HASV ? vcen[i] : F(0);
+  }
+
+  // one output plane: stage plane z+1 from R (and refill R with plane
+  // z+1+DIST), combine, write out(z) with the operands in E (and refill E
+  // with those of z+DIST)
+  auto step = [&](int z, Staged& R, Extra& E) __attribute__((always_inline)) {
+    const int buf = (z - zb) & 1;            // plane z+1 goes where plane z-1 was
+    write_plane(buf, R);
+    if (z + 1 + DIST <= ze) load_plane(wz(z + 1 + DIST), R);
+    __syncthreads();
+    if (active) {
+      vread(buf);
+      const int64_t gi = int64_t(z) * pstride + int64_t(y0 + my_row) * nx + xq;
+#pragma unroll
+      for (int c = 0; c < CP; ++c) {
+        F ck[PT], nk[PT], cmv[PT], nmv[PT];
+        combos(buf, c, ck, nk, cmv, nmv);
+        if (c < ncol) {
+          F e1v[PT], e2v[PT];
+          if constexpr (KIND == ZM_STEP) {
+            if (e1p) zm_cvt<S, F, PT>(E.e1[c], e1v);
+            if (e2p) zm_cvt<S, F, PT>(E.e2[c], e2v);
+          }
+          const F d = (KIND == ZM_STEP && e2p) ? a.delta * a.colcoef[col0 + c] : F(0);
+          SV o;
+#pragma unroll
+          for (int i = 0; i < PT; ++i) {
+            F v = accK[c][i] + nk[i];
+            if constexpr (HASV) v += vc[i] * (accM[c][i] + nmv[i]);
+            if constexpr (KIND == ZM_STEP) {
+              if (e1p) v += a.gamma * e1v[i];
+              if (e2p) v += d * e2v[i];
+            }
+            if constexpr (sizeof(S) == 2)
+              o[i] = f32_to_bf16(float(v));
+            else
+              o[i] = S(v);
+          }
+          *reinterpret_cast<SV*>(static_cast<S*>(a.out) + int64_t(col0 + c) * a.ld_out + gi -
+                                 a.out_off) = o;
+        }
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+          accK[c][i] = accKn[c][i] + ck[i];
+          accKn[c][i] = nk[i];
+          if constexpr (HASV) {
+            accM[c][i] = accMn[c][i] + cmv[i];
+            accMn[c][i] = nmv[i];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PT; ++i) vc[i] = HASV ? vcen[i] : F(0);
+    }
+    if (z + DIST < ze) load_e(z + DIST, E);
+  };
+
+  if constexpr (DIST == 2) {
+    for (int z = zb; z < ze; z += 2) {
+      step(z, A, EA);
+      if (z + 1 < ze) step(z + 1, B, EB);
+    }
+  } else {
+    for (int z = zb; z < ze; ++z) step(z, A, EA);
+  }
+}
+
 // class-symmetric coefficients? (value depends only on the number of nonzero offsets)
 bool class_symmetric(const double* c, double out[4]) {
   bool seen[4] = {false, false, false, false};
@@ -469,6 +840,101 @@ hipError_t sep_launch(const SepArgs<F>& a, int64_t b, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---- vectorised z-march: set-up and launch --------------------------------
+inline bool zm_aligned(const void* p, int64_t ld, size_t vec_bytes, int PT) {
+  return p == nullptr || ((reinterpret_cast<uintptr_t>(p) % vec_bytes) == 0 && ld % PT == 0);
+}
+
+// Coefficients for out = alpha * op(u) + beta * u (+ extra streams).  Returns
+// false when the operator is not class-symmetric or the grid does not fit the
+// thread layout (nx a multiple of PT, at most 128 PT-chunks per row).
+inline size_t zm_lds_bytes(int nx, int ty, int cp, bool hasv, size_t fbytes) {
+  return size_t(2) * (cp + (hasv ? 1 : 0)) * (ty + 2) * (nx + 8) * fbytes;
+}
+
+template <typename F>
+bool zm_setup(const chfsi_operator& op, int PT, int CP, double alpha, double beta, ZmArgs<F>* a) {
+  double cA[4], cM[4] = {0, 0, 0, 0};
+  if (!class_symmetric(op.coef, cA)) return false;
+  if (op.field_mode == 2 && !class_symmetric(op.coef_mass, cM)) return false;
+  if (op.nx % PT != 0 || op.nx / PT > 128 || op.nx < 2 * PT) return false;
+  const int tpr = op.nx / PT;
+  if (zm_lds_bytes(op.nx, std::min(256 / tpr, op.ny), CP, op.field_mode != 0, sizeof(F)) > 65536)
+    return false;
+  *a = ZmArgs<F>{};
+  a->nx = op.nx;
+  a->ny = op.ny;
+  a->nz = op.nz;
+  a->ty = std::min(256 / tpr, op.ny);
+  a->ntiles_y = (op.ny + a->ty - 1) / a->ty;
+  a->z0 = 0;
+  a->nzs = op.nz;
+  a->out_off = 0;
+  for (int k = 0; k < 4; ++k) {
+    a->cu[k] = F(alpha * cA[k] + (k == 0 ? beta : 0.0));
+    a->cw[k] = F(op.field_mode == 2 ? 0.5 * alpha * cM[k] : 0.0);
+    a->cm[k] = F(op.field_mode == 2 ? 0.5 * alpha * cM[k]
+                                    : (op.field_mode == 1 && k == 0 ? alpha : 0.0));
+    a->cb[k] = F(0);
+  }
+  a->gamma = F(0);
+  a->delta = F(0);
+  return true;
+}
+
+// prefetch distance of the z-march (tuning knob; 0 = per-type default)
+int zm_dist(int dflt) {
+  static const int v = [] {
+    const char* e = std::getenv("CHFSI_STENCIL_DIST");
+    const int d = e ? std::atoi(e) : 0;
+    return (d == 1 || d == 2) ? d : 0;
+  }();
+  return v ? v : dflt;
+}
+
+template <typename S, typename F, int PT, int CP, int KIND>
+hipError_t zm_launch(const ZmArgs<F>& a, bool hasv, hipStream_t st) {
+  const int64_t grid = int64_t((a.b + CP - 1) / CP) * a.ntiles_y;
+  const size_t lds = zm_lds_bytes(a.nx, a.ty, CP, hasv, sizeof(F));
+  if (lds > 65536) return hipErrorInvalidValue;
+  const dim3 g{unsigned(grid)};
+  const bool deep = zm_dist(1) == 2;
+  if (hasv && deep)
+    k_zmarch<S, F, PT, CP, KIND, true, 2><<<g, 256, lds, st>>>(a);
+  else if (hasv)
+    k_zmarch<S, F, PT, CP, KIND, true, 1><<<g, 256, lds, st>>>(a);
+  else if (deep)
+    k_zmarch<S, F, PT, CP, KIND, false, 2><<<g, 256, lds, st>>>(a);
+  else
+    k_zmarch<S, F, PT, CP, KIND, false, 1><<<g, 256, lds, st>>>(a);
+  return hipGetLastError();
+}
+
+// Columns per workgroup of the reduced-precision filter steps and prefetch
+// distance (tuning knobs).  Measured on MI355X at 128^3 x 1200 columns with the
+// mass-weighted potential: one column and distance 1 give the highest
+// occupancy (117 VGPRs, 4 waves/SIMD) and the best bandwidth (BF16 3.4 TB/s,
+// FP32 4.4-5.0 TB/s); more columns or a deeper prefetch cost more in
+// occupancy than they gain in reuse of the staged potential.
+int zm_cols_lowp(int dflt) {
+  static const int v = [] {
+    const char* e = std::getenv("CHFSI_STENCIL_COLS");
+    const int c = e ? std::atoi(e) : 0;
+    return (c == 1 || c == 2 || c == 4) ? c : 0;
+  }();
+  return v ? v : dflt;
+}
+
+template <typename S, int KIND>
+hipError_t zm_launch_lowp(const ZmArgs<float>& a, bool hasv, hipStream_t st) {
+  switch (zm_cols_lowp(1)) {
+    case 1: return zm_launch<S, float, 4, 1, KIND>(a, hasv, st);
+    case 2: return zm_launch<S, float, 4, 2, KIND>(a, hasv, st);
+    case 4: return zm_launch<S, float, 4, 4, KIND>(a, hasv, st);
+    default: return zm_launch<S, float, 4, 1, KIND>(a, hasv, st);
+  }
+}
+
 Grid make_grid(const chfsi_operator& op) {
   Grid g;
   g.nx = op.nx;
@@ -511,6 +977,17 @@ double stencil_flops(const chfsi_operator& op) {
 
 hipError_t stencil_apply_f64(const chfsi_operator& op, const double* X, int64_t ldx, double* Y,
                              int64_t ldy, int64_t b, hipStream_t st) {
+  ZmArgs<double> z;
+  if (zm_setup(op, 2, 1, 1.0, 0.0, &z) && zm_aligned(X, ldx, 16, 2) && zm_aligned(Y, ldy, 16, 2) &&
+      zm_aligned(op.field, 0, 16, 2)) {
+    z.b = int(b);
+    z.V = op.field;
+    z.src = X;
+    z.ld_src = ldx;
+    z.out = Y;
+    z.ld_out = ldy;
+    return zm_launch<double, double, 2, 1, ZM_APPLY>(z, op.field_mode != 0, st);
+  }
   SepArgs<double> a;
   if (sep_setup(op, &a)) {
     a.src = X;
@@ -528,6 +1005,24 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
                                    double* RX, const double* Yf, int64_t ldf,
                                    const double* colcoef, StencilStep s, int64_t b,
                                    hipStream_t st) {
+  ZmArgs<double> z;
+  if (!dinv && zm_setup(op, 2, 1, s.alpha, s.beta, &z) && zm_aligned(RY, op.n, 16, 2) &&
+      zm_aligned(RX, op.n, 16, 2) && zm_aligned(Yf, ldf, 16, 2) && zm_aligned(op.field, 0, 16, 2)) {
+    z.b = int(b);
+    z.V = op.field;
+    z.src = RY;
+    z.ld_src = op.n;
+    z.out = RX;
+    z.ld_out = op.n;
+    z.e1 = RX;
+    z.ld_e1 = op.n;
+    z.gamma = s.gamma;
+    z.e2 = Yf;
+    z.ld_e2 = ldf;
+    z.delta = s.delta;
+    z.colcoef = colcoef;
+    return zm_launch<double, double, 2, 1, ZM_STEP>(z, op.field_mode != 0, st);
+  }
   SepArgs<double> a;
   if (sep_setup(op, &a)) {
     a.dinv = dinv;
@@ -549,9 +1044,29 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
   return hipGetLastError();
 }
 
-hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* dinv, const float* RY,
-                                   float* RX, const float* Yf, const float* colcoef,
-                                   StencilStep s, int64_t b, hipStream_t st) {
+hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, const float* dinv,
+                                   const float* RY, float* RX, const float* Yf,
+                                   const float* colcoef, StencilStep s, int64_t b, hipStream_t st) {
+  ZmArgs<float> z;
+  if (!dinv && (op.field_mode == 0 || Vf) &&
+      zm_setup(op, 4, zm_cols_lowp(1), s.alpha, s.beta, &z) &&
+      zm_aligned(RY, op.n, 16, 4) && zm_aligned(RX, op.n, 16, 4) && zm_aligned(Yf, op.n, 16, 4) &&
+      zm_aligned(Vf, 0, 16, 4)) {
+    z.b = int(b);
+    z.V = Vf;
+    z.src = RY;
+    z.ld_src = op.n;
+    z.out = RX;
+    z.ld_out = op.n;
+    z.e1 = RX;
+    z.ld_e1 = op.n;
+    z.gamma = float(s.gamma);
+    z.e2 = Yf;
+    z.ld_e2 = op.n;
+    z.delta = float(s.delta);
+    z.colcoef = colcoef;
+    return zm_launch_lowp<float, ZM_STEP>(z, op.field_mode != 0, st);
+  }
   SepArgs<float> a;
   if (sep_setup(op, &a)) {
     a.dinv = dinv;
@@ -574,9 +1089,30 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* dinv, 
   return hipGetLastError();
 }
 
-hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* dinv, const void* RY,
-                                    void* RX, const void* Yf, const float* colcoef, StencilStep s,
-                                    int64_t b, hipStream_t st) {
+hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, const float* dinv,
+                                    const void* RY, void* RX, const void* Yf,
+                                    const float* colcoef, StencilStep s, int64_t b,
+                                    hipStream_t st) {
+  ZmArgs<float> z;
+  if (!dinv && (op.field_mode == 0 || Vf) &&
+      zm_setup(op, 4, zm_cols_lowp(1), s.alpha, s.beta, &z) &&
+      zm_aligned(RY, op.n, 8, 4) && zm_aligned(RX, op.n, 8, 4) && zm_aligned(Yf, op.n, 8, 4) &&
+      zm_aligned(Vf, 0, 16, 4)) {
+    z.b = int(b);
+    z.V = Vf;
+    z.src = RY;
+    z.ld_src = op.n;
+    z.out = RX;
+    z.ld_out = op.n;
+    z.e1 = RX;
+    z.ld_e1 = op.n;
+    z.gamma = float(s.gamma);
+    z.e2 = Yf;
+    z.ld_e2 = op.n;
+    z.delta = float(s.delta);
+    z.colcoef = colcoef;
+    return zm_launch_lowp<uint16_t, ZM_STEP>(z, op.field_mode != 0, st);
+  }
   SepArgs<float> a;
   if (sep_setup(op, &a)) {
     a.dinv = dinv;
@@ -603,6 +1139,21 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* dinv,
 hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* src,
                                   int64_t lds, const double* prev, int64_t ldp, double* dst,
                                   StencilStep s, int64_t b, hipStream_t st) {
+  ZmArgs<double> z;
+  if (!dinv && zm_setup(op, 2, 1, s.alpha, s.beta, &z) && zm_aligned(src, lds, 16, 2) &&
+      zm_aligned(prev, ldp, 16, 2) && zm_aligned(dst, op.n, 16, 2) &&
+      zm_aligned(op.field, 0, 16, 2)) {
+    z.b = int(b);
+    z.V = op.field;
+    z.src = src;
+    z.ld_src = lds;
+    z.out = dst;
+    z.ld_out = op.n;
+    z.e1 = prev;
+    z.ld_e1 = ldp;
+    z.gamma = s.gamma;
+    return zm_launch<double, double, 2, 1, ZM_STEP>(z, op.field_mode != 0, st);
+  }
   SepArgs<double> a;
   if (sep_setup(op, &a)) {
     a.dinv = dinv;
@@ -643,8 +1194,23 @@ hipError_t rchfsi_reconstruct_bf16(const void* RY, const double* dinv, const dou
 hipError_t stencil_apply_slab_f64(const chfsi_operator& op, const double* X, int64_t ldx,
                                   double* Yslab, int64_t ldy, int64_t b, int z0, int nzs,
                                   hipStream_t st) {
+  if (z0 < 0 || nzs < 1 || z0 + nzs > op.nz) return hipErrorInvalidValue;
+  ZmArgs<double> z;
+  if (zm_setup(op, 2, 1, 1.0, 0.0, &z) && zm_aligned(X, ldx, 16, 2) && zm_aligned(Yslab, ldy, 16, 2) &&
+      zm_aligned(op.field, 0, 16, 2)) {
+    z.b = int(b);
+    z.z0 = z0;
+    z.nzs = nzs;
+    z.out_off = int64_t(z0) * op.nx * op.ny;
+    z.V = op.field;
+    z.src = X;
+    z.ld_src = ldx;
+    z.out = Yslab;
+    z.ld_out = ldy;
+    return zm_launch<double, double, 2, 1, ZM_APPLY>(z, op.field_mode != 0, st);
+  }
   SepArgs<double> a;
-  if (!sep_setup(op, &a) || z0 < 0 || nzs < 1 || z0 + nzs > op.nz) return hipErrorInvalidValue;
+  if (!sep_setup(op, &a)) return hipErrorInvalidValue;
   a.z0 = z0;
   a.nzs = nzs;
   a.out_off = int64_t(z0) * op.nx * op.ny;
@@ -659,6 +1225,20 @@ hipError_t stencil_apply_slab_f64(const chfsi_operator& op, const double* X, int
 hipError_t stencil_residual_f64(const chfsi_operator& A, const chfsi_operator* B, const double* X,
                                 int64_t ldx, const double* lam, double* R, int64_t ldr, int64_t b,
                                 hipStream_t st) {
+  ZmArgs<double> z;
+  double cb[4] = {1.0, 0.0, 0.0, 0.0};
+  if ((!B || class_symmetric(B->coef, cb)) && zm_setup(A, 2, 1, 1.0, 0.0, &z) &&
+      zm_aligned(X, ldx, 16, 2) && zm_aligned(R, ldr, 16, 2) && zm_aligned(A.field, 0, 16, 2)) {
+    for (int k = 0; k < 4; ++k) z.cb[k] = cb[k];
+    z.b = int(b);
+    z.V = A.field;
+    z.src = X;
+    z.ld_src = ldx;
+    z.out = R;
+    z.ld_out = ldr;
+    z.colcoef = lam;
+    return zm_launch<double, double, 2, 1, ZM_RESID>(z, A.field_mode != 0, st);
+  }
   SepArgs<double> a;
   if (!sep_setup(A, &a)) return hipErrorInvalidValue;
   if (B) {

@@ -28,13 +28,16 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
                                    double* RX, const double* Yf, int64_t ldf,
                                    const double* colcoef, StencilStep s, int64_t b,
                                    hipStream_t st);
-hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* dinv, const float* RY,
-                                   float* RX, const float* Yf, const float* colcoef,
-                                   StencilStep s, int64_t b, hipStream_t st);
+// Vf: the potential in FP32 (length n; may be NULL when the operator has no
+// field); dinv: NULL for D^{-1} = I.
+hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, const float* dinv,
+                                   const float* RY, float* RX, const float* Yf,
+                                   const float* colcoef, StencilStep s, int64_t b, hipStream_t st);
 // BF16-stored blocks (uint16 bit patterns), FP32 arithmetic
-hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* dinv, const void* RY,
-                                    void* RX, const void* Yf, const float* colcoef, StencilStep s,
-                                    int64_t b, hipStream_t st);
+hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, const float* dinv,
+                                    const void* RY, void* RX, const void* Yf,
+                                    const float* colcoef, StencilStep s, int64_t b,
+                                    hipStream_t st);
 // Plain filter step (Algorithm 2): dst <- alpha dinv .* op(src) + beta src + gamma prev
 hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* src,
                                   int64_t lds, const double* prev, int64_t ldp, double* dst,

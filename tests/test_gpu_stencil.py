@@ -1,7 +1,11 @@
 """GPU parity of the periodic 27-point (grid pencil) path against the oracle.
 
-The grid is ragged (not a multiple of any wave or tile size) and carries the
-mass-weighted Gaussian-well potential.  FP64 filters match the oracle to 1e-11;
+The grids are ragged and carry the mass-weighted Gaussian-well potential.
+Shapes (nz, ny, nx) cover the vectorised z-marching kernel with one y tile,
+several y tiles with a ragged last one (ny = 20 over 16- and 8-row tiles),
+rows that leave threads idle (nx = 40: 10 or 20 threads per row), block
+widths that leave a partial column group, and the scalar fallback
+(nx = 10, not a multiple of 4).  FP64 filters match the oracle to 1e-11;
 FP32 / BF16-stored residual filters have an error bounded by the size of the
 residual part they carry (Theorem 3.4); a small solve with BF16 storage
 reaches the eigenvalues of the dense pencil.
@@ -40,8 +44,12 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def test_plain_filter_fp64_matches_oracle():
-    shape, cA, cB, V, apply_A, apply_B = _grid_problem()
+SHAPES = [(9, 10, 12), (5, 20, 64), (4, 30, 40), (6, 9, 10)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_plain_filter_fp64_matches_oracle(shape):
+    shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=shape)
     n = int(np.prod(shape))
     b = 7
     opA, opB, Vd = _ops(shape, cA, cB, V)
@@ -57,10 +65,11 @@ def test_plain_filter_fp64_matches_oracle():
         assert _rel(Y.cpu().numpy(), ref) <= 1e-11
 
 
+@pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("prec,tol", [(P.PREC_FP64, 1e-11), (P.PREC_FP32, 1e-4),
                                       (P.PREC_BF16, 1e-1)])
-def test_residual_filter_matches_oracle(prec, tol):
-    shape, cA, cB, V, apply_A, apply_B = _grid_problem()
+def test_residual_filter_matches_oracle(prec, tol, shape):
+    shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=shape)
     n = int(np.prod(shape))
     b = 9
     opA, opB, Vd = _ops(shape, cA, cB, V)
@@ -82,8 +91,9 @@ def test_residual_filter_matches_oracle(prec, tol):
         assert err <= tol * part
 
 
-def test_rayleigh_ritz_with_mass_matrix():
-    shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=(8, 9, 10))
+@pytest.mark.parametrize("shape", [(8, 9, 10), (5, 20, 64), (4, 30, 40)])
+def test_rayleigh_ritz_with_mass_matrix(shape):
+    shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=shape)
     n = int(np.prod(shape))
     b = 12
     opA, opB, Vd = _ops(shape, cA, cB, V)
@@ -119,10 +129,11 @@ def test_small_grid_solve(prec):
     assert res.max() <= 1e-9 * 1.01
 
 
-def test_slab_wise_rayleigh_ritz_matches_oracle():
+@pytest.mark.parametrize("shape", [(16, 10, 12), (6, 20, 64)])
+def test_slab_wise_rayleigh_ritz_matches_oracle(shape):
     """memory_mode 1: Gram matrices accumulated over z-slabs, in-place rotation,
     fused residual -- same Ritz pairs as the oracle."""
-    shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=(16, 10, 12), wells=3, seed=9)
+    shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=shape, wells=3, seed=9)
     n = int(np.prod(shape))
     b = 10
     opA, opB, Vd = _ops(shape, cA, cB, V)
