@@ -29,6 +29,12 @@ METRIC = "filter GFLOP/s + time-to-residual 1e-8, FP64 ChFSI vs FP32/BF16 R-ChFS
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the FP32 filter GEMM (64x64x32 tiles, split-K 8) at
+# N = 8192, b = 320: FETCH_SIZE and WRITE_SIZE from two rocprofv3 counter
+# passes over this script, scaled by what the same counters read for a 1 GiB
+# device copy (FETCH x 2.000, WRITE x 1.000); summary under profiles/.  Other
+# shapes report null.
+TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.5e6}
 
 
 def log(*a):
@@ -200,7 +206,8 @@ def main():
             "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
-            "traffic": None,
+            "traffic": TRAFFIC_F32_FILTER_GEMM.get((n, b)),
+            "traffic_unit": "bytes per launch",
             "kernel": "gemm_kernel<float> (FP32 residual-filter step, 2*N^2*b flops per launch)",
             "ms_per_launch": round(per_launch_ms, 4),
         },
