@@ -338,6 +338,15 @@ def bench_grid(args):
                         "kernel": f"k_zmarch<{args.prec}> residual-filter step "
                                   f"(4 streams x {esize} B per element-step)",
                         "ms_per_launch": round(per, 3)}}
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy * (1 << 20)
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = nbytes
     print(json.dumps(out), flush=True)
 
 

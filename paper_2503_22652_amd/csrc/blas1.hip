@@ -150,6 +150,28 @@ __global__ __launch_bounds__(kThreads) void k_symmetrize(double* A, int64_t lda,
   }
 }
 
+// Symmetric matrix of which only the block panels on and below the diagonal
+// were formed (panel width w: column block p holds rows >= p*w): the upper
+// part outside the diagonal blocks is copied from the lower part, entries of
+// the diagonal blocks (both triangles formed) are averaged.
+__global__ __launch_bounds__(kThreads) void k_symmetrize_panels(double* A, int64_t lda, int64_t b,
+                                                                 int64_t w) {
+  const int64_t total = b * b;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / b, i = idx - j * b;
+    if (i < j) {
+      if (i >= (j / w) * w) {
+        const double v = 0.5 * (A[i + j * lda] + A[j + i * lda]);
+        A[i + j * lda] = v;
+        A[j + i * lda] = v;
+      } else {
+        A[i + j * lda] = A[j + i * lda];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_scale_columns(double* M, int64_t ldm, int64_t n,
                                                              int64_t b,
                                                              const double* __restrict__ v) {
@@ -299,6 +321,12 @@ hipError_t scale_sym(const double* G, int64_t ldg, int64_t b, const double* s, d
 
 hipError_t symmetrize(double* A, int64_t lda, int64_t b, hipStream_t st) {
   k_symmetrize<<<grid_for(b * b), kThreads, 0, st>>>(A, lda, b);
+  return hipGetLastError();
+}
+
+hipError_t symmetrize_panels(double* A, int64_t lda, int64_t b, int64_t w, hipStream_t st) {
+  if (w < 1) return hipErrorInvalidValue;
+  k_symmetrize_panels<<<grid_for(b * b), kThreads, 0, st>>>(A, lda, b, w);
   return hipGetLastError();
 }
 

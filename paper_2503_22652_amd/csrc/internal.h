@@ -111,6 +111,14 @@ hipError_t scale_sym(const double* G, int64_t ldg, int64_t b, const double* s, d
                      int64_t ldo, hipStream_t st);
 // out = 0.5 (A + A^T) in place on a b x b matrix
 hipError_t symmetrize(double* A, int64_t lda, int64_t b, hipStream_t st);
+// completes a symmetric matrix of which the lower block panels of width w were formed
+hipError_t symmetrize_panels(double* A, int64_t lda, int64_t b, int64_t w, hipStream_t st);
+// panel width for the lower-panel Gram products of a block of b columns
+inline int64_t gram_panel(int64_t b) {
+  if (b <= 256) return b;
+  const int64_t w = (b + 5) / 6;
+  return (w + 15) / 16 * 16;
+}
 // columns of M scaled by v: M[:,j] *= v[j]
 hipError_t scale_columns(double* M, int64_t ldm, int64_t n, int64_t b, const double* v,
                          hipStream_t st);

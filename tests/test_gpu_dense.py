@@ -130,6 +130,26 @@ def test_rayleigh_ritz_matches_oracle(gen_problem):
                                atol=1e-10 * scale)
 
 
+def test_rayleigh_ritz_wide_block_matches_oracle():
+    """b = 300 > 256: the symmetric Gram matrices are formed as lower block
+    panels (several panel widths, a ragged last panel) and mirrored."""
+    p = wl.dense_generalized(n=1100, n_low=40, block=300, degree=8, seed=78)
+    params = P.make_params(p.n_wanted, p.block, 4, lambda_max=20.0)
+    ctx = _ctx(p, params)
+    rng = np.random.default_rng(10)
+    _, U = sla.eigh(p.A, p.B)
+    Y = U[:, : p.block] @ rng.standard_normal((p.block, p.block)) + 1e-3 * rng.standard_normal(
+        (p.n, p.block))
+    Xd, Rd = P.colmajor_empty(p.n, p.block), P.colmajor_empty(p.n, p.block)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, dev(Y), Xd, Rd)
+    o = rr.rayleigh_ritz(Y, filters.dense_op(p.A), filters.dense_op(p.B))
+    scale = np.abs(o["lam"]).max()
+    np.testing.assert_allclose(ritz, o["lam"], rtol=0, atol=1e-11 * scale)
+    np.testing.assert_allclose(norms, o["resnorm"], rtol=1e-6, atol=1e-11 * scale)
+    Xg = host(Xd)
+    np.testing.assert_allclose(Xg.T @ p.B @ Xg, np.eye(p.block), atol=1e-10)
+
+
 def test_rayleigh_ritz_padded_leading_dimension(gen_problem):
     p, w = gen_problem
     params = P.make_params(p.n_wanted, p.block, 4, lambda_max=w[-1] + 1)

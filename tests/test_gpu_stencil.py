@@ -109,6 +109,29 @@ def test_rayleigh_ritz_with_mass_matrix(shape):
     np.testing.assert_allclose(X.T @ apply_B(X), np.eye(b), atol=1e-10)
 
 
+@pytest.mark.parametrize("memory_mode", [0, 1])
+def test_rayleigh_ritz_wide_block(memory_mode):
+    """b = 300: lower-panel Gram products (several panels, ragged last one)
+    and, for grid operators, the residual as one stencil pass over X."""
+    shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=(5, 20, 64), wells=3, seed=11)
+    n = int(np.prod(shape))
+    b = 300
+    opA, opB, Vd = _ops(shape, cA, cB, V)
+    prm = P.make_params(200, b, 6, method=P.METHOD_RCHFSI, filter_prec=P.PREC_BF16,
+                        lambda_max=18.5, memory_mode=memory_mode)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    Y = wl.random_block(n, b, 12)
+    Xd, Rd = P.colmajor_empty(n, b), P.colmajor_empty(n, b)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor(Y), Xd, Rd)
+    o = rr.rayleigh_ritz(Y, apply_A, apply_B)
+    np.testing.assert_allclose(ritz, o["lam"], atol=1e-11 * np.abs(o["lam"]).max())
+    np.testing.assert_allclose(norms, o["resnorm"], rtol=1e-7)
+    X = Xd.cpu().numpy()
+    np.testing.assert_allclose(X.T @ apply_B(X), np.eye(b), atol=1e-10)
+    np.testing.assert_allclose(Rd.cpu().numpy(), apply_A(X) - apply_B(X) * np.asarray(ritz)[None, :],
+                               atol=1e-11)
+
+
 @pytest.mark.parametrize("prec", [P.PREC_FP64, P.PREC_BF16])
 def test_small_grid_solve(prec):
     shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=(8, 8, 8), wells=2, seed=5)
