@@ -63,6 +63,11 @@ def parse():
     ap.add_argument("--sequences", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--sizes", type=str, default="512,1024,2048,4096,8192")
+    ap.add_argument("--ttr", action="store_true",
+                    help="grid workload: also run solves to residual 1e-8 (reduced precision "
+                         "R-ChFSI, FP64 R-ChFSI, FP64 ChFSI with D^-1 = I)")
+    ap.add_argument("--ttr-iters", type=int, default=120)
+    ap.add_argument("--ttr-chfsi-iters", type=int, default=25)
     return ap.parse_args()
 
 
@@ -338,6 +343,46 @@ def bench_grid(args):
                         "kernel": f"k_zmarch<{args.prec}> residual-filter step "
                                   f"(4 streams x {esize} B per element-step)",
                         "ms_per_launch": round(per, 3)}}
+    if args.ttr:
+        # time to max residual < tau over the wanted pairs, from the same random
+        # start (Philox seed 2002): reduced-precision R-ChFSI vs the FP64 baselines
+        ctx.close()
+        del X
+        torch.cuda.synchronize()
+        ttr = {}
+        runs = [(args.prec + "_rchfsi", P.METHOD_RCHFSI, prec, args.ttr_iters),
+                ("fp64_rchfsi", P.METHOD_RCHFSI, P.PREC_FP64, args.ttr_iters),
+                ("fp64_chfsi_dinv_identity", P.METHOD_CHFSI, P.PREC_FP64, args.ttr_chfsi_iters)]
+        for name, method, pr, iters in runs:
+            if name == "fp64_rchfsi" and prec == P.PREC_FP64:
+                continue
+            pm = P.make_params(nw, b, p, max_iter=iters, tol=1e-8, method=method, filter_prec=pr,
+                               lambda_max=lmax, seed=2002, init_random=1)
+            md = 0
+            if P.chfsi_workspace_bytes(opA, opB, pm) + n * b * 8 > 0.9 * torch.cuda.mem_get_info()[0]:
+                md = 1
+            pm.memory_mode = md
+            log(f"time-to-residual: {name} (memory_mode {md}) ...")
+            c2 = P.chfsi_create(opA, opB, None, pm, stream=stream, keep=(Vd,))
+            X2 = P.colmajor_empty(n, b)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st2, ev2, rn2, rep2 = P.chfsi_solve(c2, X2)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t1
+            ttr[name] = {"status": "OK" if st2 == P.OK else "ERR_NOCONV", "seconds": round(sec, 2),
+                         "iterations": rep2["iterations"], "max_residual": rep2["max_residual"],
+                         "filter_ms": round(rep2["time_filter_ms"], 1),
+                         "rr_ms": round(rep2["time_rr_ms"], 1), "memory_mode": md}
+            log(f"  {ttr[name]}")
+            c2.close()
+            del X2
+            torch.cuda.synchronize()
+        lo = ttr.get(args.prec + "_rchfsi")
+        hi = ttr.get("fp64_rchfsi")
+        if lo and hi and lo["status"] == "OK" and hi["status"] == "OK":
+            ttr["speedup_vs_fp64_rchfsi"] = round(hi["seconds"] / lo["seconds"], 3)
+        out["time_to_residual"] = ttr
     if args.calibrate_copy:
         nbytes = args.calibrate_copy * (1 << 20)
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

@@ -69,6 +69,11 @@ int env_int(const char* name) {
   return v && *v ? std::atoi(v) : -1;
 }
 int filter_gemm_cfg() { return env_int("CHFSI_FILTER_GEMM_CFG"); }
+// CHFSI_PROGRESS=1: chfsi_solve prints one line per outer iteration to stderr
+bool progress_log() {
+  static const bool v = env_int("CHFSI_PROGRESS") > 0;
+  return v;
+}
 int filter_gemm_splits() {
   const int s = env_int("CHFSI_FILTER_GEMM_SPLITS");
   return s > 0 ? s : 0;
@@ -1554,6 +1559,9 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
     }
     mr = maxres();
     if (it + 1 < CHFSI_MAX_HISTORY) r.history[it + 1] = mr;
+    if (progress_log())
+      std::fprintf(stderr, "chfsi_solve: iteration %d, max residual %.3e (filter %.1f ms, RR %.1f ms)\n",
+                   it + 1, mr, r.time_filter_ms, r.time_rr_ms);
   }
   r.iterations = it;
   r.max_residual = mr;

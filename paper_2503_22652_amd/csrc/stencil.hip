@@ -440,6 +440,7 @@ enum ZmKind { ZM_APPLY = 0, ZM_RESID = 1, ZM_STEP = 2 };
 template <typename F>
 struct ZmArgs {
   int nx, ny, nz, ty, ntiles_y, b;
+  int order;                 // workgroup -> tile order (see k_zmarch)
   int z0, nzs;               // output planes [z0, z0 + nzs)
   int64_t out_off;           // output row index = grid index - out_off
   F cu[4], cw[4], cm[4];     // class coefficients on u, on w = V u, and of M
@@ -470,8 +471,8 @@ __device__ __forceinline__ void zm_cvt(const S __attribute__((ext_vector_type(PT
   }
 }
 
-template <typename S, typename F, int PT, int CP, int KIND, bool HASV, int DIST>
-__global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
+template <typename S, typename F, int PT, int CP, int NG, int KIND, bool HASV>
+__global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   using SV = S __attribute__((ext_vector_type(PT)));
   using FV = F __attribute__((ext_vector_type(PT)));
   extern __shared__ __attribute__((aligned(16))) unsigned char zm_smem[];
@@ -479,22 +480,38 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
   const int nx = a.nx, ny = a.ny, nz = a.nz, TY = a.ty;
   const int RS = nx + 8;                     // LDS row: [3] = x(-1), [4..4+nx) = row, [4+nx] = x(nx)
   const int plane = (TY + 2) * RS;
-  constexpr int NOPS = CP + (HASV ? 1 : 0);  // operand planes per buffer (columns, then V)
+  // operand planes per buffer: CP columns for each of the NG groups, then V
+  constexpr int NOPS = NG * CP + (HASV ? 1 : 0);
+  constexpr int VPL = NG * CP;               // index of the potential's plane
   const int bufsz = NOPS * plane;
 
   // XCD-aware tile order: consecutive ids on one XCD take consecutive tiles
   const int nb = gridDim.x, bid = blockIdx.x;
   const int q8 = nb >> 3, r8 = nb & 7, xcd = bid & 7, loc = bid >> 3;
   const int t = xcd < r8 ? xcd * (q8 + 1) + loc : r8 * (q8 + 1) + (xcd - r8) * q8 + loc;
-  const int cg = t / a.ntiles_y, ytile = t - cg * a.ntiles_y;
+  // order 0: a column group's y-tiles are consecutive (they share halo rows);
+  // order 1: the column groups of one y-tile are consecutive (they share the
+  // staged potential's planes, which are 2 x the BF16 operand bytes)
+  int cg, ytile;
+  if (a.order == 0) {
+    cg = t / a.ntiles_y;
+    ytile = t - cg * a.ntiles_y;
+  } else {
+    const int ncg = nb / a.ntiles_y;
+    ytile = t / ncg;
+    cg = t - ytile * ncg;
+  }
   const int y0 = ytile * TY, tyn = min(TY, ny - y0);
-  const int col0 = cg * CP, ncol = min(CP, a.b - col0);
+  // group g (256 threads) owns columns col0 .. col0 + ncol - 1; all groups
+  // share the staged potential
+  const int g = threadIdx.x >> 8;
+  const int col0 = (cg * NG + g) * CP, ncol = min(CP, a.b - col0);
   const int64_t pstride = int64_t(nx) * ny;
 
   const int tpr = nx / PT;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x & 255;
   const int my_row = tid / tpr, xq = (tid - my_row * tpr) * PT;
-  const bool active = my_row < tyn;
+  const bool active = my_row < tyn && ncol > 0;
 
   // staging chunks: PT consecutive elements of one of the tyn+2 slab rows
   const int nchunk = (tyn + 2) * tpr;
@@ -529,7 +546,8 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
         if (c < ncol)
           R.us[m][c] =
               *reinterpret_cast<const SV*>(src + int64_t(col0 + c) * a.ld_src + zo + g_off[m]);
-      if constexpr (HASV) R.vs[m] = *reinterpret_cast<const FV*>(a.V + zo + g_off[m]);
+      if constexpr (HASV)
+        if (m % NG == g) R.vs[m] = *reinterpret_cast<const FV*>(a.V + zo + g_off[m]);
     }
   };
   auto write_plane = [&](int buf, const Staged& R) __attribute__((always_inline)) {
@@ -538,7 +556,8 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
     for (int m = 0; m < 2; ++m) {
       if (!okc[m]) continue;
 #pragma unroll
-      for (int c = 0; c < NOPS; ++c) {
+      for (int c = 0; c < CP + (HASV ? 1 : 0); ++c) {
+        if (c == CP && m % NG != g) continue;   // another group stages this potential chunk
         F v[PT];
         if (HASV && c == CP) {
 #pragma unroll
@@ -549,7 +568,7 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
 #pragma unroll
           for (int i = 0; i < PT; ++i) v[i] = F(0);
         }
-        F* pl = base + c * plane;
+        F* pl = base + (c == CP ? VPL : g * CP + c) * plane;
         FV w;
 #pragma unroll
         for (int i = 0; i < PT; ++i) w[i] = v[i];
@@ -573,7 +592,7 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
   F vseg[3][PT + 2], vcen[PT];
   auto vread = [&](int buf) __attribute__((always_inline)) {
     if constexpr (HASV) {
-      const F* vb = lds + buf * bufsz + CP * plane + my_row * RS + 3 + xq;
+      const F* vb = lds + buf * bufsz + VPL * plane + my_row * RS + 3 + xq;
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         const FV mid = *reinterpret_cast<const FV*>(vb + r * RS + 1);
@@ -589,7 +608,7 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
   // centre and neighbour combinations of column c in one staged plane
   auto combos = [&](int buf, int c, F (&ck)[PT], F (&nk)[PT], F (&cmv)[PT], F (&nmv)[PT])
       __attribute__((always_inline)) {
-    const F* ub = lds + buf * bufsz + c * plane + my_row * RS + 3 + xq;   // row y-1, x = xq-1
+    const F* ub = lds + buf * bufsz + (g * CP + c) * plane + my_row * RS + 3 + xq;  // y-1, xq-1
     F useg[3][PT + 2];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -657,19 +676,14 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
   const int zb = a.z0, ze = a.z0 + a.nzs;
   auto wz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
 
-  // Planes and epilogue operands are prefetched DIST iterations ahead.  With
-  // DIST = 2 the register set A carries the planes zb-1, zb+1, zb+3, ... and
-  // B the others; the epilogue operands of output plane z are loaded right
-  // after output z-DIST has consumed their set.
-  static_assert(DIST == 1 || DIST == 2, "prefetch distance");
-  Staged A, B;
-  Extra EA, EB;
+  // The next plane and the next output's epilogue operands are loaded one
+  // iteration ahead, into registers.
+  Staged A;
+  Extra EA;
   load_plane(wz(zb - 1), A);
-  if (DIST == 2) load_plane(wz(zb), B);
   load_e(zb, EA);
-  if (DIST == 2 && zb + 1 < ze) load_e(zb + 1, EB);
   write_plane(0, A);
-  load_plane(wz(DIST == 2 ? zb + 1 : zb), A);
+  load_plane(wz(zb), A);
   __syncthreads();
   if (active) {
     vread(0);
@@ -684,9 +698,8 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
       }
     }
   }
-  Staged& R1 = DIST == 2 ? B : A;
-  write_plane(1, R1);
-  if (zb + DIST <= ze) load_plane(wz(zb + DIST), R1);
+  write_plane(1, A);
+  if (zb + 1 <= ze) load_plane(wz(zb + 1), A);
   __syncthreads();
   if (active) {
     vread(1);
@@ -708,13 +721,12 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
     for (int i = 0; i < PT; ++i) vc[i] = HASV ? vcen[i] : F(0);
   }
 
-  // one output plane: stage plane z+1 from R (and refill R with plane
-  // z+1+DIST), combine, write out(z) with the operands in E (and refill E
-  // with those of z+DIST)
+  // one output plane: stage plane z+1 from R (and refill R with plane z+2),
+  // combine, write out(z) with the operands in E (and refill E with z+1)
   auto step = [&](int z, Staged& R, Extra& E) __attribute__((always_inline)) {
     const int buf = (z - zb) & 1;            // plane z+1 goes where plane z-1 was
     write_plane(buf, R);
-    if (z + 1 + DIST <= ze) load_plane(wz(z + 1 + DIST), R);
+    if (z + 2 <= ze) load_plane(wz(z + 2), R);
     __syncthreads();
     if (active) {
       vread(buf);
@@ -760,17 +772,10 @@ __global__ __launch_bounds__(256) void k_zmarch(ZmArgs<F> a) {
 #pragma unroll
       for (int i = 0; i < PT; ++i) vc[i] = HASV ? vcen[i] : F(0);
     }
-    if (z + DIST < ze) load_e(z + DIST, E);
+    if (z + 1 < ze) load_e(z + 1, E);
   };
 
-  if constexpr (DIST == 2) {
-    for (int z = zb; z < ze; z += 2) {
-      step(z, A, EA);
-      if (z + 1 < ze) step(z + 1, B, EB);
-    }
-  } else {
-    for (int z = zb; z < ze; ++z) step(z, A, EA);
-  }
+  for (int z = zb; z < ze; ++z) step(z, A, EA);
 }
 
 // class-symmetric coefficients? (value depends only on the number of nonzero offsets)
@@ -882,57 +887,87 @@ bool zm_setup(const chfsi_operator& op, int PT, int CP, double alpha, double bet
   return true;
 }
 
-// prefetch distance of the z-march (tuning knob; 0 = per-type default)
-int zm_dist(int dflt) {
+// workgroup -> tile order (tuning knob CHFSI_STENCIL_ORDER = 1 or 2 selects
+// order 0 or 1; unset = default)
+int zm_order(bool hasv) {
   static const int v = [] {
-    const char* e = std::getenv("CHFSI_STENCIL_DIST");
-    const int d = e ? std::atoi(e) : 0;
-    return (d == 1 || d == 2) ? d : 0;
+    const char* e = std::getenv("CHFSI_STENCIL_ORDER");
+    const int o = e ? std::atoi(e) : 0;
+    return (o == 1 || o == 2) ? o : 0;
   }();
-  return v ? v : dflt;
+  if (v) return v - 1;
+  return hasv ? 1 : 0;
 }
 
-template <typename S, typename F, int PT, int CP, int KIND>
-hipError_t zm_launch(const ZmArgs<F>& a, bool hasv, hipStream_t st) {
-  const int64_t grid = int64_t((a.b + CP - 1) / CP) * a.ntiles_y;
-  const size_t lds = zm_lds_bytes(a.nx, a.ty, CP, hasv, sizeof(F));
+template <typename S, typename F, int PT, int CP, int NG, int KIND>
+hipError_t zm_launch_ng(const ZmArgs<F>& a, bool hasv, hipStream_t st) {
+  const int per = CP * NG;
+  const int64_t grid = int64_t((a.b + per - 1) / per) * a.ntiles_y;
+  ZmArgs<F> ar = a;
+  ar.order = zm_order(hasv);
+  const size_t lds = zm_lds_bytes(a.nx, a.ty, per, hasv, sizeof(F));
   if (lds > 65536) return hipErrorInvalidValue;
-  const dim3 g{unsigned(grid)};
-  const bool deep = zm_dist(1) == 2;
-  if (hasv && deep)
-    k_zmarch<S, F, PT, CP, KIND, true, 2><<<g, 256, lds, st>>>(a);
-  else if (hasv)
-    k_zmarch<S, F, PT, CP, KIND, true, 1><<<g, 256, lds, st>>>(a);
-  else if (deep)
-    k_zmarch<S, F, PT, CP, KIND, false, 2><<<g, 256, lds, st>>>(a);
+  const dim3 gd{unsigned(grid)};
+  if (hasv)
+    k_zmarch<S, F, PT, CP, NG, KIND, true><<<gd, 256 * NG, lds, st>>>(ar);
   else
-    k_zmarch<S, F, PT, CP, KIND, false, 1><<<g, 256, lds, st>>>(a);
+    k_zmarch<S, F, PT, CP, NG, KIND, false><<<gd, 256 * NG, lds, st>>>(ar);
   return hipGetLastError();
 }
 
-// Columns per workgroup of the reduced-precision filter steps and prefetch
-// distance (tuning knobs).  Measured on MI355X at 128^3 x 1200 columns with the
-// mass-weighted potential: one column and distance 1 give the highest
-// occupancy (117 VGPRs, 4 waves/SIMD) and the best bandwidth (BF16 3.4 TB/s,
-// FP32 4.4-5.0 TB/s); more columns or a deeper prefetch cost more in
-// occupancy than they gain in reuse of the staged potential.
-int zm_cols_lowp(int dflt) {
-  static const int v = [] {
-    const char* e = std::getenv("CHFSI_STENCIL_COLS");
-    const int c = e ? std::atoi(e) : 0;
-    return (c == 1 || c == 2 || c == 4) ? c : 0;
-  }();
-  return v ? v : dflt;
+// Workgroup shape of the z-march: CP columns per thread, NG groups of 256
+// threads sharing the staged potential (tuning knobs CHFSI_STENCIL_COLS and
+// CHFSI_STENCIL_GROUPS; 0 = default).  Measured on MI355X at 128^3 x 1200
+// columns with the mass-weighted potential: one column per thread gives the
+// highest occupancy (108 VGPRs, 4 waves/SIMD); more columns per thread cost
+// more in occupancy than they save.  Groups share the potential's plane
+// without costing registers, but coupling 8 or 16 waves at every plane's
+// barrier costs more than the saved potential reads (BF16: 1 group 5.98 ms,
+// 2 groups 7.13 ms, 4 groups 6.94 ms per step).
+struct ZmShape {
+  int cp, ng;
+};
+int zm_env(const char* name) {
+  const char* e = std::getenv(name);
+  const int v = e ? std::atoi(e) : 0;
+  return (v == 1 || v == 2 || v == 4) ? v : 0;
+}
+ZmShape zm_shape(bool lowp) {
+  static const int cp = zm_env("CHFSI_STENCIL_COLS");
+  static const int ng = zm_env("CHFSI_STENCIL_GROUPS");
+  ZmShape sh{cp ? cp : 1, ng ? ng : 1};
+  if (!lowp) {
+    sh.cp = 1;
+    sh.ng = std::min(sh.ng, 2);
+  }
+  if (sh.cp == 4) sh.ng = 1;
+  if (sh.cp == 2) sh.ng = std::min(sh.ng, 2);
+  return sh;
 }
 
-template <typename S, int KIND>
-hipError_t zm_launch_lowp(const ZmArgs<float>& a, bool hasv, hipStream_t st) {
-  switch (zm_cols_lowp(1)) {
-    case 1: return zm_launch<S, float, 4, 1, KIND>(a, hasv, st);
-    case 2: return zm_launch<S, float, 4, 2, KIND>(a, hasv, st);
-    case 4: return zm_launch<S, float, 4, 4, KIND>(a, hasv, st);
-    default: return zm_launch<S, float, 4, 1, KIND>(a, hasv, st);
+template <typename S, typename F, int PT, int KIND>
+hipError_t zm_launch(const ZmArgs<F>& a, bool hasv, hipStream_t st) {
+  const ZmShape sh = zm_shape(sizeof(F) == 4);
+  if constexpr (sizeof(F) == 8) {
+    // FP64: at most 2 groups (4 would cap the kernel at 128 VGPRs and spill)
+    if (sh.ng == 1) return zm_launch_ng<S, F, PT, 1, 1, KIND>(a, hasv, st);
+    return zm_launch_ng<S, F, PT, 1, 2, KIND>(a, hasv, st);
+  } else {
+    if (sh.cp == 2) {
+      if (sh.ng == 1) return zm_launch_ng<S, F, PT, 2, 1, KIND>(a, hasv, st);
+      return zm_launch_ng<S, F, PT, 2, 2, KIND>(a, hasv, st);
+    }
+    if (sh.cp == 4) return zm_launch_ng<S, F, PT, 4, 1, KIND>(a, hasv, st);
+    if (sh.ng == 1) return zm_launch_ng<S, F, PT, 1, 1, KIND>(a, hasv, st);
+    if (sh.ng == 2) return zm_launch_ng<S, F, PT, 1, 2, KIND>(a, hasv, st);
+    return zm_launch_ng<S, F, PT, 1, 4, KIND>(a, hasv, st);
   }
+}
+
+// columns sharing one workgroup's staged planes (for the LDS-size check)
+int zm_per_wg(bool lowp) {
+  const ZmShape sh = zm_shape(lowp);
+  return sh.cp * sh.ng;
 }
 
 Grid make_grid(const chfsi_operator& op) {
@@ -978,7 +1013,7 @@ double stencil_flops(const chfsi_operator& op) {
 hipError_t stencil_apply_f64(const chfsi_operator& op, const double* X, int64_t ldx, double* Y,
                              int64_t ldy, int64_t b, hipStream_t st) {
   ZmArgs<double> z;
-  if (zm_setup(op, 2, 1, 1.0, 0.0, &z) && zm_aligned(X, ldx, 16, 2) && zm_aligned(Y, ldy, 16, 2) &&
+  if (zm_setup(op, 2, zm_per_wg(false), 1.0, 0.0, &z) && zm_aligned(X, ldx, 16, 2) && zm_aligned(Y, ldy, 16, 2) &&
       zm_aligned(op.field, 0, 16, 2)) {
     z.b = int(b);
     z.V = op.field;
@@ -986,7 +1021,7 @@ hipError_t stencil_apply_f64(const chfsi_operator& op, const double* X, int64_t 
     z.ld_src = ldx;
     z.out = Y;
     z.ld_out = ldy;
-    return zm_launch<double, double, 2, 1, ZM_APPLY>(z, op.field_mode != 0, st);
+    return zm_launch<double, double, 2, ZM_APPLY>(z, op.field_mode != 0, st);
   }
   SepArgs<double> a;
   if (sep_setup(op, &a)) {
@@ -1006,7 +1041,7 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
                                    const double* colcoef, StencilStep s, int64_t b,
                                    hipStream_t st) {
   ZmArgs<double> z;
-  if (!dinv && zm_setup(op, 2, 1, s.alpha, s.beta, &z) && zm_aligned(RY, op.n, 16, 2) &&
+  if (!dinv && zm_setup(op, 2, zm_per_wg(false), s.alpha, s.beta, &z) && zm_aligned(RY, op.n, 16, 2) &&
       zm_aligned(RX, op.n, 16, 2) && zm_aligned(Yf, ldf, 16, 2) && zm_aligned(op.field, 0, 16, 2)) {
     z.b = int(b);
     z.V = op.field;
@@ -1021,7 +1056,7 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
     z.ld_e2 = ldf;
     z.delta = s.delta;
     z.colcoef = colcoef;
-    return zm_launch<double, double, 2, 1, ZM_STEP>(z, op.field_mode != 0, st);
+    return zm_launch<double, double, 2, ZM_STEP>(z, op.field_mode != 0, st);
   }
   SepArgs<double> a;
   if (sep_setup(op, &a)) {
@@ -1049,7 +1084,7 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, co
                                    const float* colcoef, StencilStep s, int64_t b, hipStream_t st) {
   ZmArgs<float> z;
   if (!dinv && (op.field_mode == 0 || Vf) &&
-      zm_setup(op, 4, zm_cols_lowp(1), s.alpha, s.beta, &z) &&
+      zm_setup(op, 4, zm_per_wg(true), s.alpha, s.beta, &z) &&
       zm_aligned(RY, op.n, 16, 4) && zm_aligned(RX, op.n, 16, 4) && zm_aligned(Yf, op.n, 16, 4) &&
       zm_aligned(Vf, 0, 16, 4)) {
     z.b = int(b);
@@ -1065,7 +1100,7 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, co
     z.ld_e2 = op.n;
     z.delta = float(s.delta);
     z.colcoef = colcoef;
-    return zm_launch_lowp<float, ZM_STEP>(z, op.field_mode != 0, st);
+    return zm_launch<float, float, 4, ZM_STEP>(z, op.field_mode != 0, st);
   }
   SepArgs<float> a;
   if (sep_setup(op, &a)) {
@@ -1095,7 +1130,7 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, c
                                     hipStream_t st) {
   ZmArgs<float> z;
   if (!dinv && (op.field_mode == 0 || Vf) &&
-      zm_setup(op, 4, zm_cols_lowp(1), s.alpha, s.beta, &z) &&
+      zm_setup(op, 4, zm_per_wg(true), s.alpha, s.beta, &z) &&
       zm_aligned(RY, op.n, 8, 4) && zm_aligned(RX, op.n, 8, 4) && zm_aligned(Yf, op.n, 8, 4) &&
       zm_aligned(Vf, 0, 16, 4)) {
     z.b = int(b);
@@ -1111,7 +1146,7 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, c
     z.ld_e2 = op.n;
     z.delta = float(s.delta);
     z.colcoef = colcoef;
-    return zm_launch_lowp<uint16_t, ZM_STEP>(z, op.field_mode != 0, st);
+    return zm_launch<uint16_t, float, 4, ZM_STEP>(z, op.field_mode != 0, st);
   }
   SepArgs<float> a;
   if (sep_setup(op, &a)) {
@@ -1140,7 +1175,7 @@ hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, 
                                   int64_t lds, const double* prev, int64_t ldp, double* dst,
                                   StencilStep s, int64_t b, hipStream_t st) {
   ZmArgs<double> z;
-  if (!dinv && zm_setup(op, 2, 1, s.alpha, s.beta, &z) && zm_aligned(src, lds, 16, 2) &&
+  if (!dinv && zm_setup(op, 2, zm_per_wg(false), s.alpha, s.beta, &z) && zm_aligned(src, lds, 16, 2) &&
       zm_aligned(prev, ldp, 16, 2) && zm_aligned(dst, op.n, 16, 2) &&
       zm_aligned(op.field, 0, 16, 2)) {
     z.b = int(b);
@@ -1152,7 +1187,7 @@ hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, 
     z.e1 = prev;
     z.ld_e1 = ldp;
     z.gamma = s.gamma;
-    return zm_launch<double, double, 2, 1, ZM_STEP>(z, op.field_mode != 0, st);
+    return zm_launch<double, double, 2, ZM_STEP>(z, op.field_mode != 0, st);
   }
   SepArgs<double> a;
   if (sep_setup(op, &a)) {
@@ -1196,7 +1231,7 @@ hipError_t stencil_apply_slab_f64(const chfsi_operator& op, const double* X, int
                                   hipStream_t st) {
   if (z0 < 0 || nzs < 1 || z0 + nzs > op.nz) return hipErrorInvalidValue;
   ZmArgs<double> z;
-  if (zm_setup(op, 2, 1, 1.0, 0.0, &z) && zm_aligned(X, ldx, 16, 2) && zm_aligned(Yslab, ldy, 16, 2) &&
+  if (zm_setup(op, 2, zm_per_wg(false), 1.0, 0.0, &z) && zm_aligned(X, ldx, 16, 2) && zm_aligned(Yslab, ldy, 16, 2) &&
       zm_aligned(op.field, 0, 16, 2)) {
     z.b = int(b);
     z.z0 = z0;
@@ -1207,7 +1242,7 @@ hipError_t stencil_apply_slab_f64(const chfsi_operator& op, const double* X, int
     z.ld_src = ldx;
     z.out = Yslab;
     z.ld_out = ldy;
-    return zm_launch<double, double, 2, 1, ZM_APPLY>(z, op.field_mode != 0, st);
+    return zm_launch<double, double, 2, ZM_APPLY>(z, op.field_mode != 0, st);
   }
   SepArgs<double> a;
   if (!sep_setup(op, &a)) return hipErrorInvalidValue;
@@ -1227,7 +1262,7 @@ hipError_t stencil_residual_f64(const chfsi_operator& A, const chfsi_operator* B
                                 hipStream_t st) {
   ZmArgs<double> z;
   double cb[4] = {1.0, 0.0, 0.0, 0.0};
-  if ((!B || class_symmetric(B->coef, cb)) && zm_setup(A, 2, 1, 1.0, 0.0, &z) &&
+  if ((!B || class_symmetric(B->coef, cb)) && zm_setup(A, 2, zm_per_wg(false), 1.0, 0.0, &z) &&
       zm_aligned(X, ldx, 16, 2) && zm_aligned(R, ldr, 16, 2) && zm_aligned(A.field, 0, 16, 2)) {
     for (int k = 0; k < 4; ++k) z.cb[k] = cb[k];
     z.b = int(b);
@@ -1237,7 +1272,7 @@ hipError_t stencil_residual_f64(const chfsi_operator& A, const chfsi_operator* B
     z.out = R;
     z.ld_out = ldr;
     z.colcoef = lam;
-    return zm_launch<double, double, 2, 1, ZM_RESID>(z, A.field_mode != 0, st);
+    return zm_launch<double, double, 2, ZM_RESID>(z, A.field_mode != 0, st);
   }
   SepArgs<double> a;
   if (!sep_setup(A, &a)) return hipErrorInvalidValue;
