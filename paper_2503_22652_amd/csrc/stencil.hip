@@ -952,6 +952,8 @@ hipError_t zm_launch(const ZmArgs<F>& a, bool hasv, hipStream_t st) {
     // FP64: at most 2 groups (4 would cap the kernel at 128 VGPRs and spill)
     if (sh.ng == 1) return zm_launch_ng<S, F, PT, 1, 1, KIND>(a, hasv, st);
     return zm_launch_ng<S, F, PT, 1, 2, KIND>(a, hasv, st);
+  } else if constexpr (PT == 2) {
+    return zm_launch_ng<S, F, 2, 1, 1, KIND>(a, hasv, st);
   } else {
     if (sh.cp == 2) {
       if (sh.ng == 1) return zm_launch_ng<S, F, PT, 2, 1, KIND>(a, hasv, st);
@@ -962,6 +964,12 @@ hipError_t zm_launch(const ZmArgs<F>& a, bool hasv, hipStream_t st) {
     if (sh.ng == 2) return zm_launch_ng<S, F, PT, 1, 2, KIND>(a, hasv, st);
     return zm_launch_ng<S, F, PT, 1, 4, KIND>(a, hasv, st);
   }
+}
+
+// points per thread of the FP32/BF16 filter steps (tuning knob CHFSI_STENCIL_PT)
+int zm_pt_lowp() {
+  static const int v = zm_env("CHFSI_STENCIL_PT");
+  return v == 2 ? 2 : 4;
 }
 
 // columns sharing one workgroup's staged planes (for the LDS-size check)
@@ -1083,10 +1091,11 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, co
                                    const float* RY, float* RX, const float* Yf,
                                    const float* colcoef, StencilStep s, int64_t b, hipStream_t st) {
   ZmArgs<float> z;
+  const int pt = zm_pt_lowp();
+  const size_t vb = size_t(pt) * sizeof(float);
   if (!dinv && (op.field_mode == 0 || Vf) &&
-      zm_setup(op, 4, zm_per_wg(true), s.alpha, s.beta, &z) &&
-      zm_aligned(RY, op.n, 16, 4) && zm_aligned(RX, op.n, 16, 4) && zm_aligned(Yf, op.n, 16, 4) &&
-      zm_aligned(Vf, 0, 16, 4)) {
+      zm_setup(op, pt, zm_per_wg(true), s.alpha, s.beta, &z) && zm_aligned(RY, op.n, vb, pt) &&
+      zm_aligned(RX, op.n, vb, pt) && zm_aligned(Yf, op.n, vb, pt) && zm_aligned(Vf, 0, vb, pt)) {
     z.b = int(b);
     z.V = Vf;
     z.src = RY;
@@ -1100,7 +1109,8 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, co
     z.ld_e2 = op.n;
     z.delta = float(s.delta);
     z.colcoef = colcoef;
-    return zm_launch<float, float, 4, ZM_STEP>(z, op.field_mode != 0, st);
+    return pt == 2 ? zm_launch<float, float, 2, ZM_STEP>(z, op.field_mode != 0, st)
+                   : zm_launch<float, float, 4, ZM_STEP>(z, op.field_mode != 0, st);
   }
   SepArgs<float> a;
   if (sep_setup(op, &a)) {
@@ -1129,10 +1139,11 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, c
                                     const float* colcoef, StencilStep s, int64_t b,
                                     hipStream_t st) {
   ZmArgs<float> z;
+  const int pt = zm_pt_lowp();
+  const size_t vb = size_t(pt) * 2, vf = size_t(pt) * sizeof(float);
   if (!dinv && (op.field_mode == 0 || Vf) &&
-      zm_setup(op, 4, zm_per_wg(true), s.alpha, s.beta, &z) &&
-      zm_aligned(RY, op.n, 8, 4) && zm_aligned(RX, op.n, 8, 4) && zm_aligned(Yf, op.n, 8, 4) &&
-      zm_aligned(Vf, 0, 16, 4)) {
+      zm_setup(op, pt, zm_per_wg(true), s.alpha, s.beta, &z) && zm_aligned(RY, op.n, vb, pt) &&
+      zm_aligned(RX, op.n, vb, pt) && zm_aligned(Yf, op.n, vb, pt) && zm_aligned(Vf, 0, vf, pt)) {
     z.b = int(b);
     z.V = Vf;
     z.src = RY;
@@ -1146,7 +1157,8 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, c
     z.ld_e2 = op.n;
     z.delta = float(s.delta);
     z.colcoef = colcoef;
-    return zm_launch<uint16_t, float, 4, ZM_STEP>(z, op.field_mode != 0, st);
+    return pt == 2 ? zm_launch<uint16_t, float, 2, ZM_STEP>(z, op.field_mode != 0, st)
+                   : zm_launch<uint16_t, float, 4, ZM_STEP>(z, op.field_mode != 0, st);
   }
   SepArgs<float> a;
   if (sep_setup(op, &a)) {
