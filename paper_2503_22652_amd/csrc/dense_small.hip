@@ -27,7 +27,7 @@ namespace chfsi {
 namespace {
 
 constexpr int NB = 64;          // Cholesky / TRSM block
-constexpr int JB = 32;          // Jacobi column block
+constexpr int JB = 16;          // Jacobi column block
 constexpr int JP = 2 * JB;      // Jacobi pair subproblem size
 constexpr int LDJ = JP + 1;     // padded LDS leading dimension
 
@@ -172,6 +172,7 @@ __device__ int lds_jacobi(double* a, double* u, double thresh, int max_sweeps) {
     if (threadIdx.x == 0) sweep_rot = 0;
     __syncthreads();
     for (int r = 0; r < n - 1; ++r) {
+      static_assert(half <= 64, "the rotations of a round are computed by one wave");
       if (threadIdx.x < half) {
         const int k = threadIdx.x;
         int p = rr_slot(k, r, n), q = rr_slot(n - 1 - k, r, n);
@@ -182,7 +183,8 @@ __device__ int lds_jacobi(double* a, double* u, double thresh, int max_sweeps) {
         }
         const double apq = a[p + q * LDJ];
         double c = 1.0, sn = 0.0;
-        if (fabs(apq) > thresh) {
+        const bool rot = fabs(apq) > thresh;
+        if (rot) {
           const double app = a[p + p * LDJ], aqq = a[q + q * LDJ];
           const double theta = (aqq - app) / (2.0 * apq);
           double t;
@@ -192,8 +194,10 @@ __device__ int lds_jacobi(double* a, double* u, double thresh, int max_sweeps) {
             t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
           sn = t * c;
-          atomicAdd(&sweep_rot, 1);
         }
+        // one count per round (a single LDS update instead of one atomic per rotation)
+        const unsigned long long m = __ballot(rot);
+        if (k == 0) sweep_rot += __popcll(m);
         pp[k] = p;
         qq[k] = q;
         cc[k] = c;
@@ -296,52 +300,61 @@ __global__ __launch_bounds__(256) void k_jacobi_pair_solve(const double* A, int6
 // out = op(X) * Y for JP x JP matrices in LDS (ld LDJ) on FP64 MFMA
 // (v_mfma_f64_16x16x4f64: lane l supplies X(l%16, l/16) and Y(l/16, l%16);
 // output element r of lane l is row l/16 + 4r, column l%16).  Each of the
-// four waves computes one 32 x 32 quadrant.  TX: X is read transposed.
+// four waves computes one JP/2 x JP/2 quadrant as NT x NT tiles of 16 x 16.
+// TX: X is read transposed.
+constexpr int NT = JP / 32;
 template <bool TX>
-__device__ __forceinline__ void lds_mm64(const double* X, const double* Y, double out[2][2][4]) {
+__device__ __forceinline__ void lds_mm(const double* X, const double* Y, double out[NT][NT][4]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
+  const int qm = (wave & 1) * (JP / 2), qn = (wave >> 1) * (JP / 2);
   const int l16 = lane & 15, g = lane >> 4;
-  f64x4_t acc[2][2];
+  f64x4_t acc[NT][NT];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NT; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int k0 = 0; k0 < JP; k0 += 4) {
     const int k = k0 + g;
-    double xa[2], yb[2];
+    double xa[NT], yb[NT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NT; ++i) {
       const int m = qm + i * 16 + l16;
       xa[i] = TX ? X[k + m * LDJ] : X[m + k * LDJ];
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) yb[j] = Y[k + (qn + j * 16 + l16) * LDJ];
+    for (int j = 0; j < NT; ++j) yb[j] = Y[k + (qn + j * 16 + l16) * LDJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NT; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], yb[j], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) out[i][j][r] = acc[i][j][r];
 }
 
-__device__ __forceinline__ void lds_mm64_store(double* Z, const double v[2][2][4]) {
+// row / column (local) of output element r of tile (i, j) held by this lane
+__device__ __forceinline__ int mm_row(int i, int r) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
-  const int l16 = lane & 15, g = lane >> 4;
+  return (wave & 1) * (JP / 2) + i * 16 + (lane >> 4) + 4 * r;
+}
+__device__ __forceinline__ int mm_col(int j) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave >> 1) * (JP / 2) + j * 16 + (lane & 15);
+}
+
+__device__ __forceinline__ void lds_mm_store(double* Z, const double v[NT][NT][4]) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NT; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Z[(qm + i * 16 + g + 4 * r) + (qn + j * 16 + l16) * LDJ] = v[i][j][r];
+      for (int r = 0; r < 4; ++r) Z[mm_row(i, r) + mm_col(j) * LDJ] = v[i][j][r];
 }
 
 __device__ __forceinline__ void load_u_or_identity(double* dst, const double* U, bool identity) {
@@ -370,24 +383,20 @@ __global__ __launch_bounds__(256) void k_jacobi_apply_A(double* A, int64_t lda, 
   load_u_or_identity(up, U + int64_t(blockIdx.x) * JP * JP, sp);
   load_u_or_identity(uq, U + int64_t(blockIdx.y) * JP * JP, sq);
   __syncthreads();
-  double t[2][2][4];
-  lds_mm64<true>(up, m, t);       // U_P^T M
+  double t[NT][NT][4];
+  lds_mm<true>(up, m, t);         // U_P^T M
   __syncthreads();
-  lds_mm64_store(m, t);
+  lds_mm_store(m, t);
   __syncthreads();
-  lds_mm64<false>(m, uq, t);      // (U_P^T M) U_Q
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
-  const int l16 = lane & 15, g = lane >> 4;
+  lds_mm<false>(m, uq, t);        // (U_P^T M) U_Q
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NT; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int li = qm + i * 16 + g + 4 * r, lj = qn + j * 16 + l16;
-        A[pair_index(li, IP, JPb) + int64_t(pair_index(lj, IQ, JQ)) * lda] = t[i][j][r];
-      }
+      for (int r = 0; r < 4; ++r)
+        A[pair_index(mm_row(i, r), IP, JPb) + int64_t(pair_index(mm_col(j), IQ, JQ)) * lda] =
+            t[i][j][r];
 }
 
 // V[rows chunk, SP] <- V[rows chunk, SP] U_P ; blockIdx.x = pair, blockIdx.y = JP-row chunk
@@ -406,20 +415,15 @@ __global__ __launch_bounds__(256) void k_jacobi_apply_V(double* V, int64_t ldv, 
   }
   load_u_or_identity(up, U + int64_t(blockIdx.x) * JP * JP, false);
   __syncthreads();
-  double t[2][2][4];
-  lds_mm64<false>(m, up, t);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int qm = (wave & 1) * 32, qn = (wave >> 1) * 32;
-  const int l16 = lane & 15, g = lane >> 4;
+  double t[NT][NT][4];
+  lds_mm<false>(m, up, t);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NT; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int li = qm + i * 16 + g + 4 * r, lj = qn + j * 16 + l16;
-        V[r0 + li + int64_t(pair_index(lj, IP, JPb)) * ldv] = t[i][j][r];
-      }
+      for (int r = 0; r < 4; ++r)
+        V[r0 + mm_row(i, r) + int64_t(pair_index(mm_col(j), IP, JPb)) * ldv] = t[i][j][r];
 }
 
 // padded copy: P (bp x bp) = [A 0; 0 0]; V = I
@@ -434,13 +438,17 @@ __global__ __launch_bounds__(256) void k_jacobi_setup(const double* A, int64_t l
   }
 }
 
-// Frobenius norm of a b x b matrix into *out (single workgroup, fixed order)
-__global__ __launch_bounds__(256) void k_fro(const double* A, int64_t lda, int64_t b,
-                                             double* out) {
+// Frobenius norm of a b x b matrix: per-workgroup partial sums of squares
+// (k_fro_part, one column range each), then one workgroup adds the partials
+// in a fixed order (deterministic)
+constexpr int kFroParts = 64;
+__global__ __launch_bounds__(256) void k_fro_part(const double* A, int64_t lda, int64_t b,
+                                                  double* part) {
   __shared__ double red[256];
   double s = 0.0;
-  for (int64_t idx = threadIdx.x; idx < b * b; idx += 256) {
-    const double v = A[idx % b + (idx / b) * lda];
+  const int64_t c0 = b * blockIdx.x / kFroParts, c1 = b * (blockIdx.x + 1) / kFroParts;
+  for (int64_t idx = threadIdx.x; idx < (c1 - c0) * b; idx += 256) {
+    const double v = A[idx % b + (c0 + idx / b) * lda];
     s += v * v;
   }
   red[threadIdx.x] = s;
@@ -449,7 +457,14 @@ __global__ __launch_bounds__(256) void k_fro(const double* A, int64_t lda, int64
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = sqrt(red[0]) > 0 ? sqrt(red[0]) : 1.0;
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(64) void k_fro_final(const double* part, double* out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < kFroParts; ++i) s += part[i];
+    *out = sqrt(s) > 0 ? sqrt(s) : 1.0;
+  }
 }
 
 // ascending sort of the diagonal (first b entries) by rank counting, then
@@ -559,7 +574,7 @@ static int64_t jacobi_padded(int64_t b) { return std::max<int64_t>(JP, (b + JP -
 size_t syev_workspace_bytes(int64_t b) {
   const int64_t bp = jacobi_padded(b);
   const int64_t npairs = bp / JP;
-  return size_t(2 * bp * bp + npairs * JP * JP + 16) * sizeof(double) +
+  return size_t(2 * bp * bp + npairs * JP * JP + 16 + kFroParts) * sizeof(double) +
          size_t(b + 64 + npairs) * sizeof(int);
 }
 
@@ -573,13 +588,15 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   double* Vp = P + bp * bp;
   double* U = Vp + bp * bp;
   double* scal = U + int64_t(npairs) * JP * JP;   // [0]: Frobenius norm
-  int* counter = reinterpret_cast<int*>(scal + 16);
+  int* counter = reinterpret_cast<int*>(scal + 16 + kFroParts);
   int* perm = counter + 64;
   int* skip = perm + b;
   hipError_t e;
   k_jacobi_setup<<<grid_for(bp * bp), 256, 0, st>>>(A, lda, b, P, Vp, bp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_fro<<<1, 256, 0, st>>>(A, lda, b, scal);
+  k_fro_part<<<kFroParts, 256, 0, st>>>(A, lda, b, scal + 16);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_fro_final<<<1, 64, 0, st>>>(scal + 16, scal);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tol = 1e-15;
   const int max_outer = 40;
