@@ -98,6 +98,7 @@ struct chfsi_ctx {
   float* A32 = nullptr;
   float* dinv32 = nullptr;        // FP32 D^{-1} (dense: always; stencil: only when given)
   float* Vf = nullptr;            // FP32 potential of a stencil operator (FP32/BF16 filter)
+  double* tri = nullptr;          // Cholesky / triangular-solve scratch
   float *f32_a = nullptr, *f32_b = nullptr, *f32_c = nullptr;     // RX, RY, Y copy (n x b)
   double *f64_a = nullptr, *f64_b = nullptr;                        // RX, RY (FP64 filter)
   void *bf_a = nullptr, *bf_b = nullptr, *bf_c = nullptr;           // BF16 stencil filter blocks
@@ -242,7 +243,7 @@ struct SizePlan {
   size_t slab = 0;
   size_t total = 0;
   size_t a32 = 0, f32blk = 0, f64blk = 0, bfblk = 0, coef = 0;
-  size_t blk = 0, bb = 0, ws = 0, ws_eig = 0;
+  size_t blk = 0, bb = 0, ws = 0, ws_eig = 0, tri = 0;
 };
 
 SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
@@ -284,6 +285,7 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
   ws = std::max(ws, plan_bytes<double>(b, b, b));
   s.ws = ws + 256;
   s.ws_eig = syev_workspace_bytes(b) + 256;
+  s.tri = tri_workspace_bytes(b, b);
   const bool Bid = is_identity(B);
   // filter blocks: FP32 3 blocks, FP64 2 blocks, BF16 3 blocks
   size_t filt = 3 * s.f32blk + 2 * s.f64blk + 3 * s.bfblk;
@@ -295,7 +297,7 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
     rr = s.blk + 2 * s.slab;
   }
   s.total = s.a32 + filt + 2 * s.coef + rr + 10 * s.bb + 4 * b * sizeof(double) + 64 + s.ws +
-            s.ws_eig;
+            s.ws_eig + s.tri;
   return s;
 }
 
@@ -925,7 +927,7 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   // column scaling s = diag(Gb)^{-1/2}; Cholesky of the scaled Gram matrix
   CK(scale_gram(c->Gb, b, b, c->Gs, b, c->svec, c->dflags + 1, st));
   CK(copy_block(c->Gs, b, c->Linv, b, b, b, st));      // kept for the SVQB fallback
-  CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws));
+  CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws, c->tri));
   CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   if (c->h_flags[1] != 0) {
@@ -942,7 +944,7 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   }
   // Linv = L^{-1}
   CK(set_identity(c->Linv, b, b, st));
-  CK(trsm_lower_left(c->Gs, b, c->Linv, b, b, b, st, c->ws));
+  CK(trsm_lower_left(c->Gs, b, c->Linv, b, b, b, st, c->ws, c->tri, true));
   // Hp = Linv (s Ga s) Linv^T
   CK(scale_sym(c->Ga, b, b, c->svec, c->Hp, b, st));
   {
@@ -1089,7 +1091,7 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
   if ((s = slab_grams(c, X, ldx)) != CHFSI_OK) return s;
   CK(scale_gram(c->Gb, b, b, c->Gs, b, c->svec, c->dflags + 1, st));
   CK(copy_block(c->Gs, b, c->Linv, b, b, b, st));
-  CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws));
+  CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws, c->tri));
   CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   if (c->h_flags[1] != 0) {
@@ -1099,7 +1101,7 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
   int sweeps = 0;
   if (c->h_flags[0] == 0) {
     CK(set_identity(c->Linv, b, b, st));
-    CK(trsm_lower_left(c->Gs, b, c->Linv, b, b, b, st, c->ws));
+    CK(trsm_lower_left(c->Gs, b, c->Linv, b, b, b, st, c->ws, c->tri, true));
     CK(scale_sym(c->Ga, b, b, c->svec, c->Hp, b, st));
     GemmDesc<double> g;
     g.M = b;
@@ -1319,6 +1321,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   c->coef32 = ctx_alloc<float>(c, size_t(params->degree) * b * sizeof(float), &st);
   c->coef64 = ctx_alloc<double>(c, size_t(params->degree) * b * sizeof(double), &st);
   c->lamY = ctx_alloc<double>(c, b * sizeof(double), &st);
+  c->tri = ctx_alloc<double>(c, sp.tri, &st);
   c->h_coef32.assign(size_t(params->degree) * b, 0.0f);
   c->h_coef64.assign(size_t(params->degree) * b, 0.0);
   if (params->memory_mode == 1) {

@@ -74,36 +74,34 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int 
   }
 }
 
-// Rows below the diagonal block: L21 = A21 L11^{-T}; one thread per row.
-__global__ __launch_bounds__(256) void k_potrf_panel(const double* L11, double* A21, int64_t lda,
-                                                     int jb, int64_t rows, const int* info) {
+// Inverse of one lower-triangular diagonal block (jb <= NB) of L: one wave,
+// lane c forms column c of L^{-1} by forward substitution in registers
+// (entries above the diagonal are zero).  Block blockIdx.x starts at row and
+// column j0 + blockIdx.x * NB.
+__global__ __launch_bounds__(64) void k_trtri_diag(const double* L, int64_t ldl, int64_t b,
+                                                   int64_t j0, double* Li, const int* info) {
   __shared__ double l[NB * (NB + 1)];
-  constexpr int L = NB + 1;
-  if (*info != 0) return;
-  for (int idx = threadIdx.x; idx < jb * jb; idx += 256) {
-    const int i = idx % jb, j = idx / jb;
-    l[i + j * L] = L11[i + j * lda];
+  constexpr int LD = NB + 1;
+  if (info && *info != 0) return;
+  const int64_t o = j0 + int64_t(blockIdx.x) * NB;
+  const int jb = int(b - o < NB ? b - o : NB);
+  for (int idx = threadIdx.x; idx < NB * NB; idx += 64) {
+    const int i = idx % NB, j = idx / NB;
+    l[i + j * LD] = (i < jb && j < jb) ? L[(o + i) + (o + j) * ldl] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int64_t r = blockIdx.x * int64_t(256) + threadIdx.x;
-  if (r >= rows) return;
+  const int c = threadIdx.x;
   double x[NB];
 #pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (k < jb) x[k] = A21[r + k * lda];
-#pragma unroll
   for (int k = 0; k < NB; ++k) {
-    if (k < jb) {
-      double s = x[k];
+    double s = (k == c) ? 1.0 : 0.0;
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (j < k) s -= x[j] * l[k + j * L];
-      x[k] = s / l[k + k * L];
-    }
+    for (int j = 0; j < k; ++j) s -= l[k + j * LD] * x[j];
+    x[k] = s / l[k + k * LD];
   }
+  double* out = Li + int64_t(blockIdx.x) * NB * NB;
 #pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (k < jb) A21[r + k * lda] = x[k];
+  for (int k = 0; k < NB; ++k) out[k + c * NB] = x[k];
 }
 
 __global__ __launch_bounds__(256) void k_zero_upper(double* A, int64_t lda, int64_t b) {
@@ -113,37 +111,6 @@ __global__ __launch_bounds__(256) void k_zero_upper(double* A, int64_t lda, int6
     const int64_t i = idx % b, j = idx / b;
     if (i < j) A[i + j * lda] = 0.0;
   }
-}
-
-// X_jj <- L_jj^{-1} X_jj for one diagonal block; one thread per right-hand side.
-__global__ __launch_bounds__(256) void k_trsm_diag(const double* Ljj, int64_t ldl, double* Xj,
-                                                   int64_t ldx, int jb, int64_t nrhs) {
-  __shared__ double l[NB * (NB + 1)];
-  constexpr int L = NB + 1;
-  for (int idx = threadIdx.x; idx < jb * jb; idx += 256) {
-    const int i = idx % jb, j = idx / jb;
-    l[i + j * L] = Ljj[i + j * ldl];
-  }
-  __syncthreads();
-  const int64_t c = blockIdx.x * int64_t(256) + threadIdx.x;
-  if (c >= nrhs) return;
-  double x[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (k < jb) x[k] = Xj[k + c * ldx];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (k < jb) {
-      double s = x[k];
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (j < k) s -= l[k + j * L] * x[j];
-      x[k] = s / l[k + k * L];
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (k < jb) Xj[k + c * ldx] = x[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -503,18 +470,45 @@ inline int64_t grid_for(int64_t total) {
 
 size_t potrf_workspace_bytes(int64_t b) { return gemm_workspace_bytes(b, b, NB, sizeof(double)); }
 
+size_t tri_workspace_bytes(int64_t b, int64_t nrhs) {
+  const int64_t nblk = (b + NB - 1) / NB;
+  return size_t(nblk * NB * NB + NB * std::max(b, nrhs)) * sizeof(double);
+}
+
+// Blocked right-looking Cholesky.  Per diagonal block: factor it in LDS,
+// invert it (kept in tri for trsm_lower_left), form the panel below as a GEMM
+// with the inverse, then update the trailing matrix with a GEMM.
 hipError_t potrf_lower(double* A, int64_t lda, int64_t b, int* info, hipStream_t st,
-                       const Workspace& ws) {
+                       const Workspace& ws, double* tri) {
   hipError_t e = hipSuccess;
+  const int64_t nblk = (b + NB - 1) / NB;
+  double* tmp = tri + nblk * NB * NB;
   for (int64_t j0 = 0; j0 < b; j0 += NB) {
     const int jb = int(std::min<int64_t>(NB, b - j0));
+    double* Li = tri + (j0 / NB) * NB * NB;
     k_potrf_diag<<<1, 256, 0, st>>>(A + j0 + j0 * lda, lda, jb, info, int(j0));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_trtri_diag<<<1, 64, 0, st>>>(A, lda, b, j0, Li, info);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t rows = b - j0 - jb;
     if (rows <= 0) break;
-    k_potrf_panel<<<dim3(unsigned((rows + 255) / 256)), 256, 0, st>>>(
-        A + j0 + j0 * lda, A + (j0 + jb) + j0 * lda, lda, jb, rows, info);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {   // tmp (rows x jb) = A21 L11^{-T}; A21 <- tmp
+      GemmDesc<double> g;
+      g.M = rows;
+      g.N = jb;
+      g.K = jb;
+      g.A = A + (j0 + jb) + j0 * lda;
+      g.sam = 1;
+      g.sak = lda;
+      g.B = Li;           // B(k, n) = L11^{-1}(n, k)
+      g.sbn = 1;
+      g.sbk = NB;
+      g.C = tmp;
+      g.ldc = rows;
+      if ((e = gemm<double>(g, st, ws, 1)) != hipSuccess) return e;
+      if ((e = copy_block(tmp, rows, A + (j0 + jb) + j0 * lda, lda, rows, jb, st)) != hipSuccess)
+        return e;
+    }
     // A22 -= L21 L21^T
     GemmDesc<double> g;
     g.M = rows;
@@ -538,14 +532,37 @@ hipError_t potrf_lower(double* A, int64_t lda, int64_t b, int* info, hipStream_t
   return hipGetLastError();
 }
 
+// X <- L^{-1} X by block forward substitution with the diagonal blocks'
+// inverses (computed here unless inverses_ready, i.e. left in tri by
+// potrf_lower for the same L).
 hipError_t trsm_lower_left(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t b,
-                           int64_t nrhs, hipStream_t st, const Workspace& ws) {
+                           int64_t nrhs, hipStream_t st, const Workspace& ws, double* tri,
+                           bool inverses_ready) {
   hipError_t e = hipSuccess;
+  const int64_t nblk = (b + NB - 1) / NB;
+  double* tmp = tri + nblk * NB * NB;
+  if (!inverses_ready) {
+    k_trtri_diag<<<dim3(unsigned(nblk)), 64, 0, st>>>(L, ldl, b, 0, tri, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   for (int64_t j0 = 0; j0 < b; j0 += NB) {
     const int jb = int(std::min<int64_t>(NB, b - j0));
-    k_trsm_diag<<<dim3(unsigned((nrhs + 255) / 256)), 256, 0, st>>>(L + j0 + j0 * ldl, ldl,
-                                                                     X + j0, ldx, jb, nrhs);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {   // tmp (jb x nrhs) = L_jj^{-1} X_j; X_j <- tmp
+      GemmDesc<double> g;
+      g.M = jb;
+      g.N = nrhs;
+      g.K = jb;
+      g.A = tri + (j0 / NB) * NB * NB;
+      g.sam = 1;
+      g.sak = NB;
+      g.B = X + j0;
+      g.sbk = 1;
+      g.sbn = ldx;
+      g.C = tmp;
+      g.ldc = jb;
+      if ((e = gemm<double>(g, st, ws, 1)) != hipSuccess) return e;
+      if ((e = copy_block(tmp, jb, X + j0, ldx, jb, nrhs, st)) != hipSuccess) return e;
+    }
     const int64_t rows = b - j0 - jb;
     if (rows <= 0) break;
     GemmDesc<double> g;

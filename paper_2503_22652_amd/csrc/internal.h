@@ -138,11 +138,18 @@ hipError_t check_finite(const double* v, int64_t n, int* flag, hipStream_t st);
 // ---------------------------------------------------------------------------
 // In-place lower Cholesky of a b x b SPD matrix (upper part zeroed). Sets
 // *info = j+1 at the first non-positive pivot (0 on success).
+// scratch of potrf_lower / trsm_lower_left: inverses of the diagonal blocks
+// and one block row or column of temporaries
+size_t tri_workspace_bytes(int64_t b, int64_t nrhs);
+// lower Cholesky factor in place (upper part zeroed); info: first failing
+// pivot (1-based) or 0
 hipError_t potrf_lower(double* A, int64_t lda, int64_t b, int* info, hipStream_t st,
-                       const Workspace& ws);
-// X <- L^{-1} X for lower-triangular L (b x b), X b x nrhs, in place.
+                       const Workspace& ws, double* tri);
+// X <- L^{-1} X (L lower b x b, X b x nrhs); inverses_ready: tri holds the
+// diagonal blocks' inverses of this L (left by potrf_lower)
 hipError_t trsm_lower_left(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t b,
-                           int64_t nrhs, hipStream_t st, const Workspace& ws);
+                           int64_t nrhs, hipStream_t st, const Workspace& ws, double* tri,
+                           bool inverses_ready);
 // Symmetric eigensolver (parallel block Jacobi).  A (b x b) is destroyed.
 // w: ascending eigenvalues (device, b); V: eigenvectors (device, b x b, ldv).
 // scratch from ws; sweeps reported through *sweeps_out (host) if non-null.
