@@ -274,12 +274,10 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
       ws = std::max(ws, size_t(16) * n * b * sizeof(double));
   }
   ws = std::max(ws, plan_bytes<double>(b, b, n));
-  ws = std::max(ws, plan_bytes<double>(b, gram_panel(b), n));
   ws = std::max(ws, plan_bytes<double>(n, b, b));
   if (p->memory_mode == 1) {
     const int64_t rows = int64_t(A->nx) * A->ny * slab_planes_for(*A, b);
     ws = std::max(ws, plan_bytes<double>(b, b, rows));
-    ws = std::max(ws, plan_bytes<double>(b, gram_panel(b), rows));
     ws = std::max(ws, plan_bytes<double>(rows, b, b));
   }
   ws = std::max(ws, plan_bytes<double>(b, b, b));
@@ -900,26 +898,23 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
     ldby = n;
   }
   // Gram matrices Ga = Y^T A Y, Gb = Y^T B Y (K = n).  Both are symmetric:
-  // only the column panels' rows on and below the diagonal block are formed
-  // (about 60 % of the products for wide blocks), then mirrored.
-  const int64_t gw = gram_panel(b);
+  // only the tiles on and below the diagonal are formed, then mirrored.
   auto gram = [&](const double* W, int64_t ldw, double* G) -> chfsi_status {
-    for (int64_t j0 = 0; j0 < b; j0 += gw) {
-      GemmDesc<double> g;
-      g.M = b - j0;
-      g.N = std::min(gw, b - j0);
-      g.K = n;
-      g.A = Y + j0 * ldy;
-      g.sak = 1;
-      g.sam = ldy;
-      g.B = W + j0 * ldw;
-      g.sbk = 1;
-      g.sbn = ldw;
-      g.C = G + j0 + j0 * b;
-      g.ldc = b;
-      CK(gemm<double>(g, st, c->ws));
-    }
-    CK(symmetrize_panels(G, b, b, gw, st));
+    GemmDesc<double> g;
+    g.M = b;
+    g.N = b;
+    g.K = n;
+    g.A = Y;
+    g.sak = 1;
+    g.sam = ldy;
+    g.B = W;
+    g.sbk = 1;
+    g.sbn = ldw;
+    g.C = G;
+    g.ldc = b;
+    g.lower_only = true;
+    CK(gemm<double>(g, st, c->ws));
+    CK(symmetrize_panels(G, b, b, 1, st));
     return CHFSI_OK;
   };
   if ((s = gram(c->AY, n, c->Ga)) != CHFSI_OK) return s;
@@ -1006,7 +1001,6 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
 // ---------------------------------------------------------------------------
 chfsi_status slab_grams(chfsi_ctx* c, const double* X, int64_t ldx) {
   const int64_t b = c->b;
-  const int64_t gw = gram_panel(b);
   const int nz = c->A.nz, nzs = c->slab_planes;
   const int64_t plane = int64_t(c->A.nx) * c->A.ny;
   hipStream_t st = c->stream;
@@ -1021,31 +1015,31 @@ chfsi_status slab_grams(chfsi_ctx* c, const double* X, int64_t ldx) {
       BYs = c->S2;
       ldby = rows;
     }
-    // lower block panels only (the Gram matrices are symmetric)
-    for (int which = 0; which < 2; ++which)
-      for (int64_t j0 = 0; j0 < b; j0 += gw) {
-        GemmDesc<double> g;
-        g.M = b - j0;
-        g.N = std::min(gw, b - j0);
-        g.K = rows;
-        g.A = X + r0 + j0 * ldx;
-        g.sak = 1;
-        g.sam = ldx;
-        g.B = which == 0 ? c->S1 + j0 * rows : BYs + j0 * ldby;
-        g.sbk = 1;
-        g.sbn = which == 0 ? rows : ldby;
-        g.C = (which == 0 ? c->Ga : c->Gb) + j0 + j0 * b;
-        g.ldc = b;
-        if (z0 > 0) {
-          g.epi.beta = 1.0;
-          g.epi.C1 = g.C;
-          g.epi.ldc1 = b;
-        }
-        CK(gemm<double>(g, st, c->ws));
+    // tiles on and below the diagonal only (the Gram matrices are symmetric)
+    for (int which = 0; which < 2; ++which) {
+      GemmDesc<double> g;
+      g.M = b;
+      g.N = b;
+      g.K = rows;
+      g.A = X + r0;
+      g.sak = 1;
+      g.sam = ldx;
+      g.B = which == 0 ? c->S1 : BYs;
+      g.sbk = 1;
+      g.sbn = which == 0 ? rows : ldby;
+      g.C = which == 0 ? c->Ga : c->Gb;
+      g.ldc = b;
+      g.lower_only = true;
+      if (z0 > 0) {
+        g.epi.beta = 1.0;
+        g.epi.C1 = g.C;
+        g.epi.ldc1 = b;
       }
+      CK(gemm<double>(g, st, c->ws));
+    }
   }
-  CK(symmetrize_panels(c->Ga, b, b, gw, st));
-  CK(symmetrize_panels(c->Gb, b, b, gw, st));
+  CK(symmetrize_panels(c->Ga, b, b, 1, st));
+  CK(symmetrize_panels(c->Gb, b, b, 1, st));
   return CHFSI_OK;
 }
 

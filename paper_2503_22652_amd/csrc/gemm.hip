@@ -27,6 +27,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace chfsi {
 
@@ -80,6 +81,7 @@ struct KernelArgsCommon {
   int64_t bsA, bsB, bsC, bsC1;
   int vecA, vecB;           // 16-byte vector loads allowed along the contiguous dim
   int tiles_m, tiles_n;
+  int lower;                // skip tiles strictly above the diagonal
 };
 
 template <typename T>
@@ -232,6 +234,7 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
   const T* __restrict__ ks = args.kscale;
   const int64_t m0 = int64_t(m_tile) * BM;
   const int64_t n0 = int64_t(n_tile) * BN;
+  if (c.lower && n0 >= m0 + BM) return;        // whole tile above the diagonal
   const int64_t kbeg = int64_t(split) * c.kchunk;
   const int64_t kend = std::min<int64_t>(c.K, kbeg + c.kchunk);
   const int nk = kend > kbeg ? int((kend - kbeg + BK - 1) / BK) : 0;
@@ -446,11 +449,34 @@ static constexpr int kNumCU = 256;
 // (FP32 k-scaled: 64x64x32 / 8 splits 118 TFLOP/s vs 128x160 95; FP64:
 // 64x64x16 / 4 splits 58-61 TFLOP/s).  Larger tiles remain selectable through
 // force_config for other shapes.
+// Optional rule (knob CHFSI_GEMM64_WIDE=1): FP64 products with a long
+// reduction (Gram matrices Y^T W, K >> M, N) on 128 x 128 tiles (16 flop per
+// byte loaded vs 8 for 64 x 64).  Measured slower on the 128^3 x 1200 Gram
+// panels (Rayleigh-Ritz 653 vs 586 ms), so off by default.
+static int wide64_mode() {
+  static const int v = [] {
+    const char* e = std::getenv("CHFSI_GEMM64_WIDE");
+    return e ? std::atoi(e) : -1;
+  }();
+  return v;
+}
+
 template <typename T>
 static void plan_impl(int64_t M, int64_t N, int64_t K, int batch, bool filter_layout, int* config,
                       int* splits) {
   (void)filter_layout;
   const int ncfg = sizeof(T) == 4 ? kNumF32 : kNumF64;
+  if (sizeof(T) == 8 && wide64_mode() == 1 && batch == 1 && M >= 128 && N >= 128 &&
+      K >= 16 * std::max(M, N)) {
+    const Cfg& w = kCfgF64[0];
+    const int64_t tiles = ((M + w.BM - 1) / w.BM) * ((N + w.BN - 1) / w.BN);
+    const int64_t max_s = std::max<int64_t>(1, K / (8 * w.BK));
+    int s = 1;
+    while (tiles * s < int64_t(kNumCU) * 4 && s * 2 <= max_s && s < 64) s *= 2;
+    *config = 0;
+    *splits = s;
+    return;
+  }
   const Cfg& f = (sizeof(T) == 4 ? kCfgF32 : kCfgF64)[ncfg - 1];
   const int64_t tiles = ((M + f.BM - 1) / f.BM) * ((N + f.BN - 1) / f.BN) * batch;
   const int64_t target = int64_t(kNumCU) * (sizeof(T) == 4 ? 16 : 8);
@@ -490,6 +516,7 @@ static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspa
   c.bsC = d.bsC;
   c.bsC1 = d.bsC1;
   c.tiles_m = int((d.M + BM - 1) / BM);
+  c.lower = d.lower_only ? 1 : 0;
   c.tiles_n = int((d.N + BN - 1) / BN);
   const bool AK = (d.sak == 1);
   const bool BKC = (d.sbk == 1);

@@ -53,6 +53,9 @@ struct GemmDesc {
   // alpha/beta*C1 epilogue is supported when batch > 1
   int batch = 1;
   int64_t bsA = 0, bsB = 0, bsC = 0, bsC1 = 0;
+  // symmetric result: only tiles that reach the diagonal or below are formed
+  // (tiles strictly above it are left unwritten; mirror the lower part after)
+  bool lower_only = false;
   Epilogue<T> epi;
   // optional: events recorded on the stream right before / after the main
   // (tile) kernel, i.e. excluding any split-K reduction
@@ -111,14 +114,9 @@ hipError_t scale_sym(const double* G, int64_t ldg, int64_t b, const double* s, d
                      int64_t ldo, hipStream_t st);
 // out = 0.5 (A + A^T) in place on a b x b matrix
 hipError_t symmetrize(double* A, int64_t lda, int64_t b, hipStream_t st);
-// completes a symmetric matrix of which the lower block panels of width w were formed
+// completes a symmetric matrix of which the lower block panels of width w were
+// formed (w = 1: copies the strictly lower part to the upper part)
 hipError_t symmetrize_panels(double* A, int64_t lda, int64_t b, int64_t w, hipStream_t st);
-// panel width for the lower-panel Gram products of a block of b columns
-inline int64_t gram_panel(int64_t b) {
-  if (b <= 256) return b;
-  const int64_t w = (b + 5) / 6;
-  return (w + 15) / 16 * 16;
-}
 // columns of M scaled by v: M[:,j] *= v[j]
 hipError_t scale_columns(double* M, int64_t ldm, int64_t n, int64_t b, const double* v,
                          hipStream_t st);
