@@ -34,7 +34,9 @@ PEAK_HBM_GBS = 8000.0
 # passes over this script, scaled by what the same counters read for a 1 GiB
 # device copy (FETCH x 2.000, WRITE x 1.000); summary under profiles/.  Other
 # shapes report null.
-TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.5e6}
+TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.8e6}
+# the same for the BF16 z-march filter step on the 128^3 grid, block 1200
+TRAFFIC_ZMARCH = {(128, 1200, "bf16"): 21.90e9}
 
 
 def log(*a):
@@ -339,7 +341,8 @@ def bench_grid(args):
                       "max_residual_after": rep["max_residual"]},
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                        "traffic": None,
+                        "traffic": TRAFFIC_ZMARCH.get((g, b, args.prec)),
+                        "traffic_unit": "bytes per launch",
                         "kernel": f"k_zmarch<{args.prec}> residual-filter step "
                                   f"(4 streams x {esize} B per element-step)",
                         "ms_per_launch": round(per, 3)}}
