@@ -227,6 +227,7 @@ def main():
     if not args.no_extras:
         ttr = {}
         for name, method, prec, iters in (("fp32_rchfsi", P.METHOD_RCHFSI, P.PREC_FP32, 60),
+                                          ("bf16_rchfsi", P.METHOD_RCHFSI, P.PREC_BF16, 60),
                                           ("fp64_rchfsi", P.METHOD_RCHFSI, P.PREC_FP64, 60),
                                           ("fp64_chfsi_dinv", P.METHOD_CHFSI, P.PREC_FP64, 15)):
             c2 = ctx_for(method, prec, profile=1, max_iter=iters)
@@ -243,11 +244,16 @@ def main():
                          "filter_ms": round(rep["time_filter_ms"], 2),
                          "rr_ms": round(rep["time_rr_ms"], 2),
                          "jacobi_sweeps": rep["jacobi_sweeps"]}
+            if rep["kernel_launches"]:
+                ttr[name]["product_ms_per_launch"] = round(rep["kernel_ms"] / rep["kernel_launches"], 4)
+                ttr[name]["product_tflops"] = round(
+                    2.0 * n * n * b / (rep["kernel_ms"] / rep["kernel_launches"] / 1e3) / 1e12, 1)
             log(name, ttr[name])
             del c2, Xs
-        if ttr["fp32_rchfsi"]["status"] == "OK" and ttr["fp64_rchfsi"]["status"] == "OK":
-            ttr["speedup_fp32_vs_fp64_rchfsi"] = round(
-                ttr["fp64_rchfsi"]["seconds"] / ttr["fp32_rchfsi"]["seconds"], 3)
+        for lo in ("fp32", "bf16"):
+            if ttr[lo + "_rchfsi"]["status"] == "OK" and ttr["fp64_rchfsi"]["status"] == "OK":
+                ttr[f"speedup_{lo}_vs_fp64_rchfsi"] = round(
+                    ttr["fp64_rchfsi"]["seconds"] / ttr[lo + "_rchfsi"]["seconds"], 3)
         ttr["fp64_chfsi_filter_vs_fp32_rchfsi_filter_rate"] = round(
             ttr["fp32_rchfsi"]["filter_gflops"] / max(ttr["fp64_chfsi_dinv"]["filter_gflops"], 1e-9), 3)
         out["time_to_residual"] = ttr

@@ -101,6 +101,24 @@ __global__ __launch_bounds__(kThreads) void k_convert(const double* __restrict__
   }
 }
 
+// FP64 -> bfloat16 (rounded to FP32, then to bfloat16 nearest-even)
+__global__ __launch_bounds__(kThreads) void k_convert_bf16(const double* __restrict__ in,
+                                                            int64_t ldi, uint16_t* out,
+                                                            int64_t ldo, int64_t n, int64_t m) {
+  const int64_t total = n * m;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / n, i = idx - j * n;
+    uint32_t u = __float_as_uint(float(in[i + j * ldi]));
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      out[i + j * ldo] = uint16_t((u >> 16) | 0x40u);
+    } else {
+      u += 0x7fffu + ((u >> 16) & 1u);
+      out[i + j * ldo] = uint16_t(u >> 16);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_copy(const double* __restrict__ in, int64_t ldi,
                                                     double* out, int64_t ldo, int64_t n,
                                                     int64_t b) {
@@ -295,6 +313,12 @@ hipError_t column_norms(const double* R, int64_t ldr, int64_t n, int64_t b, doub
 hipError_t convert_f64_f32(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t n,
                            int64_t m, hipStream_t st) {
   k_convert<<<grid_for(n * m), kThreads, 0, st>>>(in, ldi, out, ldo, n, m);
+  return hipGetLastError();
+}
+
+hipError_t convert_f64_bf16(const double* in, int64_t ldi, uint16_t* out, int64_t ldo, int64_t n,
+                            int64_t m, hipStream_t st) {
+  k_convert_bf16<<<grid_for(n * m), kThreads, 0, st>>>(in, ldi, out, ldo, n, m);
   return hipGetLastError();
 }
 

@@ -96,6 +96,7 @@ struct chfsi_ctx {
 
   // filter precision copies / buffers
   float* A32 = nullptr;
+  uint16_t* A16 = nullptr;        // bfloat16 copy of a dense operator (BF16 residual filter)
   float* dinv32 = nullptr;        // FP32 D^{-1} (dense: always; stencil: only when given)
   float* Vf = nullptr;            // FP32 potential of a stencil operator (FP32/BF16 filter)
   double* tri = nullptr;          // Cholesky / triangular-solve scratch
@@ -209,12 +210,13 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
     set_error("unknown filter precision");
     return CHFSI_ERR_ARG;
   }
-  if (p->filter_prec == CHFSI_PREC_BF16 && A->kind != CHFSI_OP_STENCIL27) {
-    set_error("BF16 filter storage is implemented for stencil operators only");
+  if (p->filter_prec == CHFSI_PREC_BF16 && A->kind != CHFSI_OP_STENCIL27 &&
+      A->kind != CHFSI_OP_DENSE) {
+    set_error("BF16 filters are implemented for dense and stencil operators");
     return CHFSI_ERR_ARG;
   }
   if (p->filter_prec == CHFSI_PREC_BF16 && p->method != CHFSI_METHOD_RCHFSI) {
-    set_error("BF16 filter storage is implemented for the residual filter only");
+    set_error("BF16 filters are implemented for the residual filter only");
     return CHFSI_ERR_ARG;
   }
   if (p->memory_mode != 0) {
@@ -255,6 +257,10 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
   if (p->filter_prec == CHFSI_PREC_FP32) {
     s.f32blk = size_t(n) * b * sizeof(float);
     if (dense) s.a32 = size_t(n) * n * sizeof(float) + size_t(n) * sizeof(float);
+  } else if (p->filter_prec == CHFSI_PREC_BF16 && dense) {
+    // BF16 products on a bfloat16 copy of A, FP32 filter blocks
+    s.f32blk = size_t(n) * b * sizeof(float);
+    s.a32 = size_t(n) * n * sizeof(uint16_t) + size_t(n) * sizeof(float);
   } else if (p->filter_prec == CHFSI_PREC_FP64) {
     s.f64blk = s.blk;
   } else {
@@ -272,6 +278,7 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
     ws = std::max(ws, plan_bytes<double>(n, b, n));
     if (p->filter_prec == CHFSI_PREC_FP64)
       ws = std::max(ws, size_t(16) * n * b * sizeof(double));
+    if (p->filter_prec == CHFSI_PREC_BF16) ws = std::max(ws, gemm_bf16_workspace_bytes(n, b));
   }
   ws = std::max(ws, plan_bytes<double>(b, b, n));
   ws = std::max(ws, plan_bytes<double>(n, b, b));
@@ -430,7 +437,9 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
   const double scale1 = f.sigma1 / f.e;
   double fl = 0.0;
   const bool dense = c->A.kind == CHFSI_OP_DENSE;
-  if (c->prm.filter_prec == CHFSI_PREC_FP32) {
+  if (c->prm.filter_prec == CHFSI_PREC_FP32 || (c->prm.filter_prec == CHFSI_PREC_BF16 && dense)) {
+    // FP32 filter blocks; the operator product is FP32 MFMA, or BF16 MFMA on
+    // the bfloat16 copy of A (dense BF16)
     if (nsteps > 0) {
       float* hs = reinterpret_cast<float*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
       std::memcpy(hs, c->h_coef32.data(), size_t(nsteps) * b * sizeof(float));
@@ -470,7 +479,10 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
         g.epi.C3 = Yc;
         g.epi.ldc3 = n;
         CK(prof_pair(c, &g.ev_begin, &g.ev_end));
-        CK(gemm<float>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
+        if (c->A16)
+          CK(gemm_bf16_filter(g, c->A16, n, c->stream, c->ws, filter_gemm_splits()));
+        else
+          CK(gemm<float>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
         fl += 2.0 * double(n) * double(n) * double(b);
       } else {
         StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
@@ -1303,8 +1315,14 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   } else if (params->filter_prec == CHFSI_PREC_FP64) {
     c->f64_a = ctx_alloc<double>(c, sp.f64blk, &st);
     c->f64_b = ctx_alloc<double>(c, sp.f64blk, &st);
+  } else if (dense) {
+    c->A16 = ctx_alloc<uint16_t>(c, size_t(n) * n * sizeof(uint16_t), &st);
+    c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+    c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
+    c->f32_b = ctx_alloc<float>(c, sp.f32blk, &st);
+    c->f32_c = ctx_alloc<float>(c, sp.f32blk, &st);
   } else {
-    if (dense || d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+    if (d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
     c->bf_a = ctx_alloc<char>(c, sp.bfblk, &st);
     c->bf_b = ctx_alloc<char>(c, sp.bfblk, &st);
     c->bf_c = ctx_alloc<char>(c, sp.bfblk, &st);
@@ -1385,6 +1403,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   // precision-converted operator copies (owned)
   hipError_t e = hipSuccess;
   if (c->A32) e = convert_f64_f32(A->dense, A->ld, c->A32, n, n, n, c->stream);
+  if (e == hipSuccess && c->A16) e = convert_f64_bf16(A->dense, A->ld, c->A16, n, n, n, c->stream);
   if (e == hipSuccess && c->dinv32) {
     if (d_inv)
       e = convert_f64_f32(d_inv, n, c->dinv32, n, n, 1, c->stream);

@@ -644,6 +644,272 @@ hipError_t gemm(const GemmDesc<T>& d, hipStream_t st, const Workspace& ws, int f
   }
 }
 
+// ---------------------------------------------------------------------------
+// BF16-input product for the dense residual filter: C = epilogue(A16 * bf16(
+// kscale .* B)).  A16 is the operator rounded once to bfloat16 (k-contiguous
+// rows: A(m, k) at A16[k + m * lda16]); B is the FP32 block (k-contiguous
+// columns), scaled by kscale and rounded to bfloat16 (nearest-even) while it
+// is staged in LDS; products on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation; the FP32 three-term epilogue (or split-K partials) as in
+// gemm_kernel.  Lane l supplies A(l%16, 8 k-values of group l/16) and the same
+// k-values of B(., l%16); output element r of lane l is row 4 (l/16) + r,
+// column l%16 of the 16 x 16 tile.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+template <int BM, int BN, int BK, bool CHECK>
+__global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(KernelArgs<float> args,
+                                                           const unsigned short* __restrict__ A16) {
+  constexpr int WM = 2, WN = 2, WTM = BM / WM, WTN = BN / WN;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  constexpr int LDK = BK + 8;                  // bf16 elements per LDS row (16-byte pad)
+  constexpr int NVA = BM * BK / 8 / 256;       // 8-element A vectors per thread
+  constexpr int NVB = BN * BK / 4 / 256;       // 4-element B vectors per thread
+  static_assert(NVA * 8 * 256 == BM * BK && NVB * 4 * 256 == BN * BK, "tile / thread mismatch");
+  static_assert(BK % 32 == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile shape");
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN * LDK];
+
+  const KernelArgsCommon& c = args.c;
+  const int G = gridDim.x;
+  const int t = xcd_remap(blockIdx.x, G);
+  const int tiles_mn = c.tiles_m * c.tiles_n;
+  const int n_tile = t % c.tiles_n;
+  const int m_tile = (t / c.tiles_n) % c.tiles_m;
+  const int split = t / tiles_mn;
+  const int64_t m0 = int64_t(m_tile) * BM, n0 = int64_t(n_tile) * BN;
+  const int64_t kbeg = int64_t(split) * c.kchunk;
+  const int64_t kend = std::min<int64_t>(c.K, kbeg + c.kchunk);
+  const int nk = kend > kbeg ? int((kend - kbeg + BK - 1) / BK) : 0;
+  const float* __restrict__ B = args.B;
+  const float* __restrict__ ks = args.kscale;
+  const int64_t lda = c.sam, ldb = c.sbn;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int lrow = lane & 15, lgrp = lane >> 4;
+
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  struct Regs {
+    u16x8_t a[NVA];
+    f32x4 b[NVB];
+    f32x4 k[NVB];
+  };
+  Regs r0, r1;
+  auto load = [&](Regs& R, int s) __attribute__((always_inline)) {
+    const int64_t k0 = kbeg + int64_t(s) * BK;
+#pragma unroll
+    for (int i = 0; i < NVA; ++i) {
+      const int v = threadIdx.x + i * 256;
+      const int row = v / (BK / 8), kk = (v % (BK / 8)) * 8;
+      const int64_t gm = m0 + row, gk = k0 + kk;
+      if (!CHECK) {
+        R.a[i] = *reinterpret_cast<const u16x8_t*>(A16 + gm * lda + gk);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          R.a[i][j] = (gm < c.M && gk + j < kend) ? A16[gm * lda + gk + j] : (unsigned short)0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) {
+      const int v = threadIdx.x + i * 256;
+      const int col = v / (BK / 4), kk = (v % (BK / 4)) * 4;
+      const int64_t gn = n0 + col, gk = k0 + kk;
+      if (!CHECK) {
+        R.b[i] = *reinterpret_cast<const f32x4*>(B + gn * ldb + gk);
+        R.k[i] = ks ? *reinterpret_cast<const f32x4*>(ks + gk) : f32x4{1.f, 1.f, 1.f, 1.f};
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bool ok = gn < c.N && gk + j < kend;
+          R.b[i][j] = ok ? B[gn * ldb + gk + j] : 0.f;
+          R.k[i][j] = (ks && gk + j < kend) ? ks[gk + j] : 1.f;
+        }
+      }
+    }
+  };
+  auto store = [&](const Regs& R, int stg) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < NVA; ++i) {
+      const int v = threadIdx.x + i * 256;
+      const int row = v / (BK / 8), kk = (v % (BK / 8)) * 8;
+      *reinterpret_cast<u16x8_t*>(&As[stg][row * LDK + kk]) = R.a[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) {
+      const int v = threadIdx.x + i * 256;
+      const int col = v / (BK / 4), kk = (v % (BK / 4)) * 4;
+      u16x4_t h;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[j] = f32_to_bf16_rne(R.b[i][j] * R.k[i][j]);
+      *reinterpret_cast<u16x4_t*>(&Bs[stg][col * LDK + kk]) = h;
+    }
+  };
+  auto compute = [&](int stg) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k0 = 0; k0 < BK; k0 += 32) {
+      bf16x8_t af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const u16x8_t x = *reinterpret_cast<const u16x8_t*>(
+            &As[stg][(wm * WTM + i * 16 + lrow) * LDK + k0 + lgrp * 8]);
+        af[i] = __builtin_bit_cast(bf16x8_t, x);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const u16x8_t x = *reinterpret_cast<const u16x8_t*>(
+            &Bs[stg][(wn * WTN + j * 16 + lrow) * LDK + k0 + lgrp * 8]);
+        bf[j] = __builtin_bit_cast(bf16x8_t, x);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  };
+
+  // two register sets: slice s is loaded two slices ahead of its use
+  if (nk > 0) {
+    load(r0, 0);
+    if (nk > 1) load(r1, 1);
+    store(r0, 0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    if (kt + 2 < nk) load(r0, kt + 2);
+    compute(0);
+    if (kt + 1 < nk) store(r1, 1);
+    __syncthreads();
+    if (kt + 1 >= nk) break;
+    if (kt + 3 < nk) load(r1, kt + 3);
+    compute(1);
+    if (kt + 2 < nk) store(r0, 0);
+    __syncthreads();
+  }
+
+  if (c.splits == 1) {
+    const Epilogue<float> e = args.epi;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * WTN + j * 16 + lrow;
+        if (CHECK && n >= c.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + wm * WTM + i * 16 + lgrp * 4 + r;
+          if (!CHECK || m < c.M) args.C[m + n * c.ldc] = apply_epilogue(e, acc[i][j][r], m, n);
+        }
+      }
+  } else {
+    float* P = args.partial + int64_t(split) * c.M * c.N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * WTN + j * 16 + lrow;
+        if (CHECK && n >= c.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + wm * WTM + i * 16 + lgrp * 4 + r;
+          if (!CHECK || m < c.M) P[m + n * c.M] = acc[i][j][r];
+        }
+      }
+  }
+}
+
+hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
+                            hipStream_t st, const Workspace& ws, int force_splits) {
+  constexpr int BM = 64, BN = 64, BK = 64;
+  if (d.M <= 0 || d.N <= 0) return hipSuccess;
+  if (d.sbk != 1 || d.batch != 1 || !A16) return hipErrorInvalidValue;
+  KernelArgs<float> a;
+  KernelArgsCommon& c = a.c;
+  c.M = d.M;
+  c.N = d.N;
+  c.K = d.K;
+  c.sam = lda16;
+  c.sak = 1;
+  c.sbk = 1;
+  c.sbn = d.sbn;
+  c.ldc = d.ldc;
+  c.batch = 1;
+  c.bsA = c.bsB = c.bsC = c.bsC1 = 0;
+  c.lower = 0;
+  c.tiles_m = int((d.M + BM - 1) / BM);
+  c.tiles_n = int((d.N + BN - 1) / BN);
+  const int64_t tiles = int64_t(c.tiles_m) * c.tiles_n;
+  int splits = force_splits;
+  if (splits <= 0) {
+    splits = 1;
+    const int64_t max_s = std::max<int64_t>(1, d.K / (8 * BK));
+    while (tiles * splits < int64_t(kNumCU) * 8 && splits * 2 <= max_s && splits < 16) splits *= 2;
+  }
+  int64_t kchunk = (d.K + splits - 1) / splits;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  if (kchunk == 0) kchunk = BK;
+  splits = int((d.K + kchunk - 1) / kchunk);
+  c.kchunk = kchunk;
+  c.splits = std::max(splits, 1);
+  a.A = nullptr;
+  a.B = d.B;
+  a.kscale = d.kscale;
+  a.C = d.C;
+  a.epi = d.epi;
+  a.partial = nullptr;
+  if (c.splits > 1) {
+    const size_t need = size_t(c.splits) * d.M * d.N * sizeof(float);
+    if (need > ws.bytes || ws.ptr == nullptr) {
+      c.splits = 1;
+      c.kchunk = (d.K + BK - 1) / BK * BK;
+    } else {
+      a.partial = static_cast<float*>(ws.ptr);
+    }
+  }
+  const int64_t grid = tiles * c.splits;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  const bool aligned =
+      d.M % BM == 0 && d.N % BN == 0 && d.K % BK == 0 && c.kchunk % BK == 0 &&
+      reinterpret_cast<uintptr_t>(A16) % 16 == 0 && lda16 % 8 == 0 &&
+      reinterpret_cast<uintptr_t>(d.B) % 16 == 0 && d.sbn % 4 == 0 &&
+      (d.kscale == nullptr || reinterpret_cast<uintptr_t>(d.kscale) % 16 == 0);
+  hipError_t err;
+  if (d.ev_begin && (err = hipEventRecord(d.ev_begin, st)) != hipSuccess) return err;
+  if (aligned)
+    gemm_bf16_kernel<BM, BN, BK, false><<<dim3(unsigned(grid)), dim3(256), 0, st>>>(a, A16);
+  else
+    gemm_bf16_kernel<BM, BN, BK, true><<<dim3(unsigned(grid)), dim3(256), 0, st>>>(a, A16);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if (d.ev_end && (err = hipEventRecord(d.ev_end, st)) != hipSuccess) return err;
+  if (c.splits > 1) {
+    const int64_t total = d.M * d.N;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+    splitk_reduce_kernel<float><<<dim3(blocks), dim3(256), 0, st>>>(a);
+    err = hipGetLastError();
+  }
+  return err;
+}
+
+size_t gemm_bf16_workspace_bytes(int64_t M, int64_t N) {
+  return size_t(16) * size_t(M) * size_t(N) * sizeof(float);
+}
+
 template hipError_t gemm<float>(const GemmDesc<float>&, hipStream_t, const Workspace&, int, int);
 template hipError_t gemm<double>(const GemmDesc<double>&, hipStream_t, const Workspace&, int,
                                  int);

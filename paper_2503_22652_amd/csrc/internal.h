@@ -78,6 +78,13 @@ hipError_t gemm(const GemmDesc<T>& d, hipStream_t stream, const Workspace& ws,
 // Bytes of split-K scratch the heuristic may ask for at most for an M x N
 // output with reduction length K (per batch entry).
 size_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
+// BF16-input filter product: C = epilogue(A16 * bf16(kscale .* B)), A16 the
+// k-contiguous bfloat16 copy of the operator (ld lda16), B FP32 k-contiguous;
+// FP32 accumulation and epilogue.  Split-K partials need at most
+// gemm_bf16_workspace_bytes(M, N) of ws.
+hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
+                            hipStream_t st, const Workspace& ws, int force_splits = 0);
+size_t gemm_bf16_workspace_bytes(int64_t M, int64_t N);
 
 // Which tile configuration/split the heuristic picks (for reports and tests).
 template <typename T>
@@ -104,6 +111,8 @@ hipError_t column_norms(const double* R, int64_t ldr, int64_t n, int64_t b, doub
 // FP64 -> FP32 copy of an n x m column-major matrix
 hipError_t convert_f64_f32(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t n,
                            int64_t m, hipStream_t st);
+hipError_t convert_f64_bf16(const double* in, int64_t ldi, uint16_t* out, int64_t ldo, int64_t n,
+                            int64_t m, hipStream_t st);
 // copy an n x b block between leading dimensions
 hipError_t copy_block(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t n,
                       int64_t b, hipStream_t st);

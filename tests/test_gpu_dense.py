@@ -76,7 +76,8 @@ def test_chfsi_filter_matches_oracle(gen_problem, prec):
 
 
 @pytest.mark.parametrize("prec,degree", [(P.PREC_FP64, 8), (P.PREC_FP64, 1), (P.PREC_FP64, 2),
-                                         (P.PREC_FP32, 8), (P.PREC_FP32, 20)])
+                                         (P.PREC_FP32, 8), (P.PREC_FP32, 20),
+                                         (P.PREC_BF16, 8), (P.PREC_BF16, 20)])
 def test_rchfsi_filter_matches_oracle(gen_problem, prec, degree):
     p, w = gen_problem
     bounds = (w[0] - 0.1, w[-1] + 0.5, 0.5 * (w[p.block - 1] + w[p.block]))
@@ -97,9 +98,15 @@ def test_rchfsi_filter_matches_oracle(gen_problem, prec, degree):
     print("rchfsi", prec, degree, "rel", rel(g, ref), "err/||resid part||", err_abs / resid_part)
     if prec == P.PREC_FP64:
         assert rel(g, ref) <= 1e-11
-    else:
+    elif prec == P.PREC_FP32:
         # FP32 arithmetic only touches the residual part D^{-1} R_Y
         assert err_abs <= 1e-4 * resid_part
+    else:
+        # BF16 products (A and D^{-1} R_Y rounded to bfloat16, FP32 accumulation
+        # and storage): Theorem 3.4 bounds the error by a small multiple of the
+        # unit roundoff 2^-8 times the residual part (a CPU emulation of this
+        # arithmetic gives 0.004-0.006 here)
+        assert err_abs <= 3e-2 * resid_part
 
 
 def test_rayleigh_ritz_matches_oracle(gen_problem):
@@ -194,7 +201,8 @@ def test_solve_dense_standard_full_size():
     np.testing.assert_allclose(ev[:32], o["lam"][:32], rtol=1e-10, atol=1e-12)
 
 
-@pytest.mark.parametrize("method,prec", [("rchfsi", P.PREC_FP64), ("rchfsi", P.PREC_FP32)])
+@pytest.mark.parametrize("method,prec", [("rchfsi", P.PREC_FP64), ("rchfsi", P.PREC_FP32),
+                                         ("rchfsi", P.PREC_BF16)])
 def test_solve_generalized_reduced(method, prec):
     p = wl.dense_generalized(n=1536, n_low=48, block=64, degree=20, seed=1001)
     w = sla.eigvalsh(p.A, p.B)

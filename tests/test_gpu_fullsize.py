@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size (dense generalized, N = 8192, block 320,
-256 wanted, degree 20), in the launch configuration bench.py times.
+256 wanted, degree 20), in the launch configuration bench.py times, for the
+FP32 filter (the bench's) and the BF16-product filter.
 
 * The FP32 residual filter on column samples: the filter is column-independent
   (Lambda is diagonal), so the oracle filters a sample of columns exactly and
@@ -36,13 +37,15 @@ def big():
     return p, lmax, A, B, d
 
 
-def test_fp32_filter_column_samples(big):
+@pytest.mark.parametrize("prec,tol", [(P.PREC_FP32, 1e-4), (P.PREC_BF16, 3e-2)])
+def test_filter_column_samples(big, prec, tol):
+    """FP32 (FP32 MFMA) and BF16 (bfloat16 products on BF16 MFMA, FP32 storage)."""
     p, lmax, A, B, d = big
     X0 = wl.random_block(p.n, p.block, 2001)
     o = rr.rayleigh_ritz(X0, filters.dense_op(p.A), filters.dense_op(p.B))
     lam = o["lam"]
     bounds = (lam[0] - 0.05 * (lam[-1] - lam[0]), lmax, lam[-1])
-    prm = P.make_params(256, 320, 20, method=P.METHOD_RCHFSI, filter_prec=P.PREC_FP32,
+    prm = P.make_params(256, 320, 20, method=P.METHOD_RCHFSI, filter_prec=prec,
                         lambda_max=lmax)
     ctx = P.chfsi_create(P.dense_operator(A), P.dense_operator(B), d, prm, keep=(A, B, d))
     Y = P.colmajor_empty(p.n, p.block)
@@ -56,15 +59,16 @@ def test_fp32_filter_column_samples(big):
     part = np.linalg.norm(p.dinv[:, None] * RYp, axis=0)
     err = np.linalg.norm(g - ref, axis=0)
     print("per-column err / residual part:", err / part)
-    assert np.all(err <= 1e-4 * part)
+    assert np.all(err <= tol * part)
 
 
-def test_fp32_rchfsi_solve_full_size(big):
+@pytest.mark.parametrize("prec", [P.PREC_FP32, P.PREC_BF16])
+def test_rchfsi_solve_full_size(big, prec):
     p, lmax, A, B, d = big
     gold = json.load(open(GOLD))
     wref = np.asarray(gold["eigenvalues"])
     prm = P.make_params(256, 320, 20, max_iter=60, tol=1e-8, method=P.METHOD_RCHFSI,
-                        filter_prec=P.PREC_FP32, lambda_max=lmax)
+                        filter_prec=prec, lambda_max=lmax)
     ctx = P.chfsi_create(P.dense_operator(A), P.dense_operator(B), d, prm, keep=(A, B, d))
     Xd = P.to_colmajor(wl.random_block(p.n, p.block, 2001))
     st, ev, rn, rep = P.chfsi_solve(ctx, Xd)
