@@ -260,7 +260,7 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
   } else if (p->filter_prec == CHFSI_PREC_BF16 && dense) {
     // BF16 products on a bfloat16 copy of A, FP32 filter blocks
     s.f32blk = size_t(n) * b * sizeof(float);
-    s.a32 = size_t(n) * n * sizeof(uint16_t) + size_t(n) * sizeof(float);
+    s.a32 = size_t(n) * n * sizeof(uint16_t) + size_t(n) * sizeof(float) + size_t(n) * b * 2;
   } else if (p->filter_prec == CHFSI_PREC_FP64) {
     s.f64blk = s.blk;
   } else {
@@ -480,7 +480,8 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
         g.epi.ldc3 = n;
         CK(prof_pair(c, &g.ev_begin, &g.ev_end));
         if (c->A16)
-          CK(gemm_bf16_filter(g, c->A16, n, c->stream, c->ws, filter_gemm_splits()));
+          CK(gemm_bf16_filter(g, c->A16, n, static_cast<uint16_t*>(c->bf_a), c->stream, c->ws,
+                              filter_gemm_splits()));
         else
           CK(gemm<float>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
         fl += 2.0 * double(n) * double(n) * double(b);
@@ -1317,6 +1318,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     c->f64_b = ctx_alloc<double>(c, sp.f64blk, &st);
   } else if (dense) {
     c->A16 = ctx_alloc<uint16_t>(c, size_t(n) * n * sizeof(uint16_t), &st);
+    c->bf_a = ctx_alloc<char>(c, size_t(n) * b * sizeof(uint16_t), &st);   // bf16(D^-1 R_Y)
     c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
     c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
     c->f32_b = ctx_alloc<float>(c, sp.f32blk, &st);

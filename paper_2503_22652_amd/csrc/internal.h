@@ -78,12 +78,14 @@ hipError_t gemm(const GemmDesc<T>& d, hipStream_t stream, const Workspace& ws,
 // Bytes of split-K scratch the heuristic may ask for at most for an M x N
 // output with reduction length K (per batch entry).
 size_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
-// BF16-input filter product: C = epilogue(A16 * bf16(kscale .* B)), A16 the
+// BF16 filter product: C = epilogue(A16 * bf16(kscale .* B)), A16 the
 // k-contiguous bfloat16 copy of the operator (ld lda16), B FP32 k-contiguous;
-// FP32 accumulation and epilogue.  Split-K partials need at most
+// B16 (K x N bfloat16, ld K) receives the rounded right operand; FP32
+// accumulation and epilogue.  Split-K partials need at most
 // gemm_bf16_workspace_bytes(M, N) of ws.
 hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
-                            hipStream_t st, const Workspace& ws, int force_splits = 0);
+                            uint16_t* B16, hipStream_t st, const Workspace& ws,
+                            int force_splits = 0);
 size_t gemm_bf16_workspace_bytes(int64_t M, int64_t N);
 
 // Which tile configuration/split the heuristic picks (for reports and tests).
