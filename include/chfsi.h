@@ -51,10 +51,15 @@ typedef enum {
   CHFSI_OP_STENCIL27 = 2  /* periodic 27-point grid operator (see chfsi_operator) */
 } chfsi_op_kind;
 
-/* Storage / arithmetic precision of the filter's bulk work.  FP32: blocks and
- * the operator copy are FP32 and products accumulate in FP32 on MFMA.  BF16:
- * filter blocks are stored in bfloat16 and all arithmetic is FP32 (stencil
- * operators only).  The Rayleigh-Ritz step and residual norms are always FP64. */
+/* Storage / arithmetic precision of the filter's bulk work (the residual
+ * filter's reduced-precision product of Section 3.2).  FP32: blocks and the
+ * operator copy are FP32 and products accumulate in FP32 on MFMA.  BF16,
+ * stencil operators: filter blocks are stored in bfloat16 and all arithmetic
+ * is FP32.  BF16, dense operators (residual filter only): the product's
+ * inputs -- an owned bfloat16 copy of A and D^{-1} R_Y, both rounded to
+ * nearest-even -- run on bfloat16 MFMA with FP32 accumulation; the filter
+ * blocks and the three-term update stay FP32.  The Rayleigh-Ritz step,
+ * reconstruction and residual norms are always FP64. */
 typedef enum { CHFSI_PREC_FP64 = 0, CHFSI_PREC_FP32 = 1, CHFSI_PREC_BF16 = 2 } chfsi_prec;
 
 /* Filter algorithm: Algorithm 2 (three-term recurrence on the block, with
