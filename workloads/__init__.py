@@ -230,6 +230,22 @@ def toy_generalized(m: int = 1000, n: int = 10, zeta: float = 0.0, seed: int = 0
             "lam_gen": lam / bj, "Q": Q, "bj": bj}
 
 
+def toy_diagonal_mass(m: int = 1000, n: int = 10, seed: int = 0, mass_seed: int = 1):
+    """Toy spectrum for A (as ``toy_standard``) with a diagonal mass matrix.
+
+    B = diag(b), b ~ U[1, 5] (kappa(B) <= 5, the range of Section 4.1.1), so
+    the diagonal D^{-1} = B^{-1} is exact and a reduced-precision filter is
+    the only source of filtering error.
+    """
+    rng = np.random.default_rng(seed)
+    Q = _qr_orthogonal(rng, m)
+    lam = toy_spectrum(m, n)
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    b = np.random.default_rng(mass_seed).uniform(1.0, 5.0, size=m)
+    return {"A": A, "B": np.diag(b), "Binv": np.diag(1.0 / b), "dinv": 1.0 / b}
+
+
 # ----------------------------------------------------------------------------
 # periodic Q1 finite-element stencil pencils
 # ----------------------------------------------------------------------------
