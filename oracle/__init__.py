@@ -23,8 +23,11 @@ following the paper (arXiv 2503.22652) step by step:
   (an independent pin for the library eigensolver used in ``rr``).
 * ``stencil``    -- periodic 27-point operator application for grid pencils.
 * ``angles``     -- maximum principal angle (Definition 2.1).
+* ``diagnostics`` -- filtering error, angle and both sides of the convergence
+  condition of Section 3.1 with Theorem 3.1's bound, per outer iteration
+  (the check of Section 4.1.3).
 
 Parity status of each function is stated in its docstring; functions without
 an independent pin say "parity unpinned".
 """
-from . import chebyshev, filters, rr, solver, jacobi, stencil, angles  # noqa: F401
+from . import chebyshev, filters, rr, solver, jacobi, stencil, angles, diagnostics  # noqa: F401
