@@ -427,21 +427,26 @@ __global__ __launch_bounds__(256) void k_stencil_sep(SepArgs<F> a) {
 //
 // A workgroup owns CP columns, a slab of TY full x rows and a range of z
 // planes.  Thread t owns PT consecutive x points of one slab row in all CP
-// columns.  Each plane (CP operand columns and the potential, with one halo row
-// on each side and the periodic x wrap cells) is staged into one of two LDS
-// buffers from registers loaded one plane ahead, so a single barrier per plane
-// separates the writes from the reads and the global loads of plane z+2 and of
-// the epilogue operands of z+1 are in flight while plane z+1 is processed.
-// Workgroup ids are remapped so that the y-tiles of one column group run on
-// the same XCD, where the halo rows they share hit that XCD's L2.
+// columns.  Each plane (the CP operand columns and, with the mass-weighted
+// potential, w = V u of each, with one halo row on each side; the periodic x
+// neighbours are read across the row) is staged into one of two LDS buffers from registers loaded
+// one plane ahead; w is formed once per staged element, not once per use.  A
+// single barrier per plane separates the writes from the reads, and the
+// global loads of plane z+2 and of the epilogue operands of z+1 are in flight
+// while plane z+1 is processed.  Workgroup ids are remapped so that the y-tiles of one column
+// group (order 0), or the column groups of one y-tile (order 1), run on the
+// same XCD, where the rows they share hit that XCD's L2.
 // ---------------------------------------------------------------------------
-enum ZmKind { ZM_APPLY = 0, ZM_RESID = 1, ZM_STEP = 2 };
+// ZM_STEP: residual-filter step, e1 and e2 both present; ZM_CSTEP: plain
+// Chebyshev step, e1 optional, no e2.
+enum ZmKind { ZM_APPLY = 0, ZM_RESID = 1, ZM_STEP = 2, ZM_CSTEP = 3 };
 
 template <typename F>
 struct ZmArgs {
   int nx, ny, nz, ty, ntiles_y, b;
   int order;                 // workgroup -> tile order (see k_zmarch)
   int z0, nzs;               // output planes [z0, z0 + nzs)
+  int use_w;                 // the stencil on w = V u is present (cw != 0)
   int64_t out_off;           // output row index = grid index - out_off
   F cu[4], cw[4], cm[4];     // class coefficients on u, on w = V u, and of M
   F cb[4];                   // ZM_RESID: B class coefficients (scaled by -lambda_j)
@@ -450,7 +455,7 @@ struct ZmArgs {
   int64_t ld_src;
   void* out;
   int64_t ld_out;
-  const void* e1;            // ZM_STEP: first extra stream (may alias out)
+  const void* e1;            // ZM_STEP / ZM_CSTEP: first extra stream (may alias out)
   int64_t ld_e1;
   F gamma;
   const void* e2;            // ZM_STEP: second extra stream, scaled per column
@@ -471,6 +476,21 @@ __device__ __forceinline__ void zm_cvt(const S __attribute__((ext_vector_type(PT
   }
 }
 
+// storage element of an output value (bfloat16: round to nearest even, by the
+// hardware conversion)
+template <typename S, typename F>
+__device__ __forceinline__ S zm_store_elem(F v) {
+  if constexpr (sizeof(S) == 2)
+    return __builtin_bit_cast(uint16_t, static_cast<__bf16>(float(v)));
+  else
+    return S(v);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* zm_byte_off(const T* p, uint32_t bytes) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + bytes);
+}
+
 template <typename S, typename F, int PT, int CP, int NG, int KIND, bool HASV>
 __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   using SV = S __attribute__((ext_vector_type(PT)));
@@ -478,12 +498,14 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char zm_smem[];
   F* lds = reinterpret_cast<F*>(zm_smem);
   const int nx = a.nx, ny = a.ny, nz = a.nz, TY = a.ty;
-  const int RS = nx + 8;                     // LDS row: [3] = x(-1), [4..4+nx) = row, [4+nx] = x(nx)
+  const int RS = nx + 8;                     // LDS row: [4..4+nx) = the grid row (16-byte aligned)
   const int plane = (TY + 2) * RS;
-  // operand planes per buffer: CP columns for each of the NG groups, then V
-  constexpr int NOPS = NG * CP + (HASV ? 1 : 0);
-  constexpr int VPL = NG * CP;               // index of the potential's plane
+  // planes per buffer: u of every column slot, then (potential) w of every slot
+  constexpr int NC = NG * CP;
+  constexpr int NOPS = HASV ? 2 * NC : NC;
+  constexpr bool ONE_COL = NG == 1 && CP == 1;   // every launched workgroup owns its column
   const int bufsz = NOPS * plane;
+  const bool use_w = HASV && a.use_w != 0;
 
   // XCD-aware tile order: consecutive ids on one XCD take consecutive tiles
   const int nb = gridDim.x, bid = blockIdx.x;
@@ -491,7 +513,7 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   const int t = xcd < r8 ? xcd * (q8 + 1) + loc : r8 * (q8 + 1) + (xcd - r8) * q8 + loc;
   // order 0: a column group's y-tiles are consecutive (they share halo rows);
   // order 1: the column groups of one y-tile are consecutive (they share the
-  // staged potential's planes, which are 2 x the BF16 operand bytes)
+  // potential's planes, which are 2 x the BF16 operand bytes)
   int cg, ytile;
   if (a.order == 0) {
     cg = t / a.ntiles_y;
@@ -502,10 +524,10 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
     cg = t - ytile * ncg;
   }
   const int y0 = ytile * TY, tyn = min(TY, ny - y0);
-  // group g (256 threads) owns columns col0 .. col0 + ncol - 1; all groups
-  // share the staged potential
-  const int g = threadIdx.x >> 8;
-  const int col0 = (cg * NG + g) * CP, ncol = min(CP, a.b - col0);
+  // group g (256 threads) owns columns col0 .. col0 + ncol - 1
+  const int g = NG == 1 ? 0 : int(threadIdx.x >> 8);
+  const int col0 = (cg * NG + g) * CP;
+  const int ncol = ONE_COL ? 1 : min(CP, a.b - col0);
   const int64_t pstride = int64_t(nx) * ny;
 
   const int tpr = nx / PT;
@@ -514,24 +536,37 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   const bool active = my_row < tyn && ncol > 0;
 
   // staging chunks: PT consecutive elements of one of the tyn+2 slab rows
+  // (byte offsets within a plane: operand and potential element sizes).
+  // Chunk 0 of a thread is its own output points (slab row my_row + 1), so the
+  // potential it stages there is the one its output needs; chunk 1 covers the
+  // halo rows 0 and tyn + 1 (threads below 2 * tpr).  Together they cover the
+  // (tyn + 2) * tpr chunks once: tyn * tpr <= 256 and tpr <= 128.
   const int nchunk = (tyn + 2) * tpr;
-  int g_off[2], l_off[2], wrapl[2], wrapr[2];
+  uint32_t boff_s[2], boff_f[2];
+  int l_off[2];
   bool okc[2];
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    const int k = tid + 256 * m;
+    const int k = m == 0 ? tid + tpr : (tid < tpr ? tid : tid + 256);
     okc[m] = k < nchunk;
     const int rr = okc[m] ? k / tpr : 0;
     const int xx = (k - rr * tpr) * PT;
     int y = y0 - 1 + rr;
     y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-    g_off[m] = y * nx + xx;
+    boff_s[m] = uint32_t(y * nx + xx) * uint32_t(sizeof(S));
+    boff_f[m] = uint32_t(y * nx + xx) * uint32_t(sizeof(F));
     l_off[m] = rr * RS + 4 + xx;
-    wrapl[m] = xx == nx - PT ? rr * RS + 3 : -1;   // last chunk of a row feeds x = -1
-    wrapr[m] = xx == 0 ? rr * RS + 4 + nx : -1;    // first chunk feeds x = nx
   }
+  // this thread's points and their periodic x neighbours within an LDS row
+  const int x_mid = 4 + xq;
+  const int x_lo = 4 + (xq == 0 ? nx - 1 : xq - 1);
+  const int x_hi = 4 + (xq + PT == nx ? 0 : xq + PT);
 
-  const S* src = static_cast<const S*>(a.src);
+  // column base pointers (uniform within a group)
+  const S* srcc[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c)
+    srcc[c] = static_cast<const S*>(a.src) + int64_t(col0 + c) * a.ld_src;
   struct Staged {
     SV us[2][CP];
     FV vs[2];
@@ -543,12 +578,18 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
       if (!okc[m]) continue;
 #pragma unroll
       for (int c = 0; c < CP; ++c)
-        if (c < ncol)
-          R.us[m][c] =
-              *reinterpret_cast<const SV*>(src + int64_t(col0 + c) * a.ld_src + zo + g_off[m]);
+        if (ONE_COL || c < ncol)
+          R.us[m][c] = *reinterpret_cast<const SV*>(zm_byte_off(srcc[c] + zo, boff_s[m]));
       if constexpr (HASV)
-        if (m % NG == g) R.vs[m] = *reinterpret_cast<const FV*>(a.V + zo + g_off[m]);
+        if (m == 0 || use_w)
+          R.vs[m] = *reinterpret_cast<const FV*>(zm_byte_off(a.V + zo, boff_f[m]));
     }
+  };
+  auto put = [&](F* pl, int m, const F (&v)[PT]) __attribute__((always_inline)) {
+    FV w;
+#pragma unroll
+    for (int i = 0; i < PT; ++i) w[i] = v[i];
+    *reinterpret_cast<FV*>(pl + l_off[m]) = w;
   };
   auto write_plane = [&](int buf, const Staged& R) __attribute__((always_inline)) {
     F* base = lds + buf * bufsz;
@@ -556,99 +597,92 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
     for (int m = 0; m < 2; ++m) {
       if (!okc[m]) continue;
 #pragma unroll
-      for (int c = 0; c < CP + (HASV ? 1 : 0); ++c) {
-        if (c == CP && m % NG != g) continue;   // another group stages this potential chunk
+      for (int c = 0; c < CP; ++c) {
         F v[PT];
-        if (HASV && c == CP) {
-#pragma unroll
-          for (int i = 0; i < PT; ++i) v[i] = R.vs[m][i];
-        } else if (c < ncol) {
-          zm_cvt<S, F, PT>(R.us[m][c < CP ? c : 0], v);
+        if (ONE_COL || c < ncol) {
+          zm_cvt<S, F, PT>(R.us[m][c], v);
         } else {
 #pragma unroll
           for (int i = 0; i < PT; ++i) v[i] = F(0);
         }
-        F* pl = base + (c == CP ? VPL : g * CP + c) * plane;
-        FV w;
+        put(base + (g * CP + c) * plane, m, v);
+        if constexpr (HASV) {
+          if (use_w) {
+            F w[PT];
 #pragma unroll
-        for (int i = 0; i < PT; ++i) w[i] = v[i];
-        *reinterpret_cast<FV*>(pl + l_off[m]) = w;
-        if (wrapl[m] >= 0) pl[wrapl[m]] = v[PT - 1];
-        if (wrapr[m] >= 0) pl[wrapr[m]] = v[0];
+            for (int i = 0; i < PT; ++i) w[i] = R.vs[m][i] * v[i];
+            put(base + (NC + g * CP + c) * plane, m, w);
+          }
+        }
       }
     }
   };
 
-  // per-column coefficients on u (RESID subtracts lambda_j times B's)
-  F cu[CP][4];
+  // per-column coefficients on u (RESID subtracts lambda_j times B's) and the
+  // step's per-column factor of e2
+  F cu[CP][4], dcol[CP];
 #pragma unroll
   for (int c = 0; c < CP; ++c) {
-    const F lam = (KIND == ZM_RESID && c < ncol) ? a.colcoef[col0 + c] : F(0);
+    const bool have = ONE_COL || c < ncol;
+    const F lam = (KIND == ZM_RESID && have) ? a.colcoef[col0 + c] : F(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) cu[c][k] = KIND == ZM_RESID ? a.cu[k] - lam * a.cb[k] : a.cu[k];
+    dcol[c] = (KIND == ZM_STEP && have) ? a.delta * a.colcoef[col0 + c] : F(0);
   }
 
-  // potential around this thread's points (3 rows x PT+2), read once per plane
-  F vseg[3][PT + 2], vcen[PT];
-  auto vread = [&](int buf) __attribute__((always_inline)) {
-    if constexpr (HASV) {
-      const F* vb = lds + buf * bufsz + VPL * plane + my_row * RS + 3 + xq;
+  // three rows x (PT + 2) values around this thread's points in one staged
+  // plane (p: row y-1 of this thread's slab row)
+  auto rows = [&](const F* p, F (&seg)[3][PT + 2]) __attribute__((always_inline)) {
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const FV mid = *reinterpret_cast<const FV*>(vb + r * RS + 1);
-        vseg[r][0] = vb[r * RS];
+    for (int r = 0; r < 3; ++r) {
+      const FV mid = *reinterpret_cast<const FV*>(p + r * RS + x_mid);
+      seg[r][0] = p[r * RS + x_lo];
 #pragma unroll
-        for (int i = 0; i < PT; ++i) vseg[r][i + 1] = mid[i];
-        vseg[r][PT + 1] = vb[r * RS + PT + 1];
-      }
+      for (int i = 0; i < PT; ++i) seg[r][i + 1] = mid[i];
+      seg[r][PT + 1] = p[r * RS + x_hi];
+    }
+  };
+  // in-plane class sums: centre, the 4 face neighbours, the 4 corners
+  auto sums = [&](const F (&s)[3][PT + 2], F (&p0)[PT], F (&p1)[PT], F (&p2)[PT])
+      __attribute__((always_inline)) {
+    F vs[PT + 2];
 #pragma unroll
-      for (int i = 0; i < PT; ++i) vcen[i] = vseg[1][i + 1];
+    for (int k = 0; k < PT + 2; ++k) vs[k] = s[0][k] + s[2][k];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      p0[i] = s[1][i + 1];
+      p1[i] = s[1][i] + s[1][i + 2] + vs[i + 1];
+      p2[i] = vs[i] + vs[i + 2];
     }
   };
   // centre and neighbour combinations of column c in one staged plane
   auto combos = [&](int buf, int c, F (&ck)[PT], F (&nk)[PT], F (&cmv)[PT], F (&nmv)[PT])
       __attribute__((always_inline)) {
-    const F* ub = lds + buf * bufsz + (g * CP + c) * plane + my_row * RS + 3 + xq;  // y-1, xq-1
-    F useg[3][PT + 2];
+    const int off = my_row * RS;               // row y-1 of this thread's points
+    {
+      F seg[3][PT + 2], p0[PT], p1[PT], p2[PT];
+      rows(lds + buf * bufsz + (g * CP + c) * plane + off, seg);
+      sums(seg, p0, p1, p2);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const FV mid = *reinterpret_cast<const FV*>(ub + r * RS + 1);
-      useg[r][0] = ub[r * RS];
-#pragma unroll
-      for (int i = 0; i < PT; ++i) useg[r][i + 1] = mid[i];
-      useg[r][PT + 1] = ub[r * RS + PT + 1];
-    }
-    F vsu[PT + 2];
-#pragma unroll
-    for (int k = 0; k < PT + 2; ++k) vsu[k] = useg[0][k] + useg[2][k];
-#pragma unroll
-    for (int i = 0; i < PT; ++i) {
-      const F p0 = useg[1][i + 1];
-      const F p1 = useg[1][i] + useg[1][i + 2] + vsu[i + 1];
-      const F p2 = vsu[i] + vsu[i + 2];
-      ck[i] = cu[c][0] * p0 + cu[c][1] * p1 + cu[c][2] * p2;
-      nk[i] = cu[c][1] * p0 + cu[c][2] * p1 + cu[c][3] * p2;
-      if constexpr (HASV) {
-        cmv[i] = a.cm[0] * p0 + a.cm[1] * p1 + a.cm[2] * p2;
-        nmv[i] = a.cm[1] * p0 + a.cm[2] * p1 + a.cm[3] * p2;
+      for (int i = 0; i < PT; ++i) {
+        ck[i] = cu[c][0] * p0[i] + cu[c][1] * p1[i] + cu[c][2] * p2[i];
+        nk[i] = cu[c][1] * p0[i] + cu[c][2] * p1[i] + cu[c][3] * p2[i];
+        if constexpr (HASV) {
+          cmv[i] = a.cm[0] * p0[i] + a.cm[1] * p1[i] + a.cm[2] * p2[i];
+          nmv[i] = a.cm[1] * p0[i] + a.cm[2] * p1[i] + a.cm[3] * p2[i];
+        }
       }
     }
     if constexpr (HASV) {
-      F wseg[3][PT + 2];
+      if (use_w) {
+        F seg[3][PT + 2], p0[PT], p1[PT], p2[PT];
+        rows(lds + buf * bufsz + (NC + g * CP + c) * plane + off, seg);
+        sums(seg, p0, p1, p2);
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int k = 0; k < PT + 2; ++k) wseg[r][k] = vseg[r][k] * useg[r][k];
-      F vsw[PT + 2];
-#pragma unroll
-      for (int k = 0; k < PT + 2; ++k) vsw[k] = wseg[0][k] + wseg[2][k];
-#pragma unroll
-      for (int i = 0; i < PT; ++i) {
-        const F p0 = wseg[1][i + 1];
-        const F p1 = wseg[1][i] + wseg[1][i + 2] + vsw[i + 1];
-        const F p2 = vsw[i] + vsw[i + 2];
-        ck[i] += a.cw[0] * p0 + a.cw[1] * p1 + a.cw[2] * p2;
-        nk[i] += a.cw[1] * p0 + a.cw[2] * p1 + a.cw[3] * p2;
+        for (int i = 0; i < PT; ++i) {
+          ck[i] += a.cw[0] * p0[i] + a.cw[1] * p1[i] + a.cw[2] * p2[i];
+          nk[i] += a.cw[1] * p0[i] + a.cw[2] * p1[i] + a.cw[3] * p2[i];
+        }
       }
     }
   };
@@ -659,20 +693,31 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   };
   const S* e1p = static_cast<const S*>(a.e1);
   const S* e2p = static_cast<const S*>(a.e2);
+  constexpr bool HAS_E = KIND == ZM_STEP || KIND == ZM_CSTEP;
   auto load_e = [&](int z, Extra& E) __attribute__((always_inline)) {
+    if (!active) return;
+    const int64_t gi = int64_t(z) * pstride + int64_t(y0 + my_row) * nx + xq;
     if constexpr (KIND == ZM_STEP) {
-      if (!active) return;
-      const int64_t gi = int64_t(z) * pstride + int64_t(y0 + my_row) * nx + xq;
 #pragma unroll
       for (int c = 0; c < CP; ++c) {
-        if (c >= ncol) continue;
-        if (e1p) E.e1[c] = *reinterpret_cast<const SV*>(e1p + int64_t(col0 + c) * a.ld_e1 + gi);
-        if (e2p) E.e2[c] = *reinterpret_cast<const SV*>(e2p + int64_t(col0 + c) * a.ld_e2 + gi);
+        if (!ONE_COL && c >= ncol) continue;
+        E.e1[c] = *reinterpret_cast<const SV*>(e1p + int64_t(col0 + c) * a.ld_e1 + gi);
+        E.e2[c] = *reinterpret_cast<const SV*>(e2p + int64_t(col0 + c) * a.ld_e2 + gi);
+      }
+    } else if constexpr (KIND == ZM_CSTEP) {
+      if (e1p) {
+#pragma unroll
+        for (int c = 0; c < CP; ++c) {
+          if (!ONE_COL && c >= ncol) continue;
+          E.e1[c] = *reinterpret_cast<const SV*>(e1p + int64_t(col0 + c) * a.ld_e1 + gi);
+        }
       }
     }
   };
 
-  F accK[CP][PT], accKn[CP][PT], accM[CP][PT], accMn[CP][PT], vc[PT];
+  F accK[CP][PT], accKn[CP][PT], accM[CP][PT], accMn[CP][PT];
+  // potential at this thread's points of the next output plane (from staging)
+  FV vcur;
   const int zb = a.z0, ze = a.z0 + a.nzs;
   auto wz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
 
@@ -686,7 +731,6 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   load_plane(wz(zb), A);
   __syncthreads();
   if (active) {
-    vread(0);
 #pragma unroll
     for (int c = 0; c < CP; ++c) {
       F ck[PT], nk[PT], cmv[PT], nmv[PT];
@@ -699,10 +743,10 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
     }
   }
   write_plane(1, A);
+  if constexpr (HASV) vcur = A.vs[0];
   if (zb + 1 <= ze) load_plane(wz(zb + 1), A);
   __syncthreads();
   if (active) {
-    vread(1);
 #pragma unroll
     for (int c = 0; c < CP; ++c) {
       F ck[PT], nk[PT], cmv[PT], nmv[PT];
@@ -717,8 +761,6 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
         }
       }
     }
-#pragma unroll
-    for (int i = 0; i < PT; ++i) vc[i] = HASV ? vcen[i] : F(0);
   }
 
   // one output plane: stage plane z+1 from R (and refill R with plane z+2),
@@ -726,35 +768,39 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   auto step = [&](int z, Staged& R, Extra& E) __attribute__((always_inline)) {
     const int buf = (z - zb) & 1;            // plane z+1 goes where plane z-1 was
     write_plane(buf, R);
+    F vc[PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) vc[i] = HASV ? F(vcur[i]) : F(0);
+    if constexpr (HASV) vcur = R.vs[0];      // plane z+1, for the next output
     if (z + 2 <= ze) load_plane(wz(z + 2), R);
     __syncthreads();
     if (active) {
-      vread(buf);
       const int64_t gi = int64_t(z) * pstride + int64_t(y0 + my_row) * nx + xq;
 #pragma unroll
       for (int c = 0; c < CP; ++c) {
         F ck[PT], nk[PT], cmv[PT], nmv[PT];
         combos(buf, c, ck, nk, cmv, nmv);
-        if (c < ncol) {
+        if (ONE_COL || c < ncol) {
           F e1v[PT], e2v[PT];
           if constexpr (KIND == ZM_STEP) {
-            if (e1p) zm_cvt<S, F, PT>(E.e1[c], e1v);
-            if (e2p) zm_cvt<S, F, PT>(E.e2[c], e2v);
+            zm_cvt<S, F, PT>(E.e1[c], e1v);
+            zm_cvt<S, F, PT>(E.e2[c], e2v);
+          } else if constexpr (KIND == ZM_CSTEP) {
+            if (e1p) {
+              zm_cvt<S, F, PT>(E.e1[c], e1v);
+            } else {
+#pragma unroll
+              for (int i = 0; i < PT; ++i) e1v[i] = F(0);
+            }
           }
-          const F d = (KIND == ZM_STEP && e2p) ? a.delta * a.colcoef[col0 + c] : F(0);
           SV o;
 #pragma unroll
           for (int i = 0; i < PT; ++i) {
             F v = accK[c][i] + nk[i];
             if constexpr (HASV) v += vc[i] * (accM[c][i] + nmv[i]);
-            if constexpr (KIND == ZM_STEP) {
-              if (e1p) v += a.gamma * e1v[i];
-              if (e2p) v += d * e2v[i];
-            }
-            if constexpr (sizeof(S) == 2)
-              o[i] = f32_to_bf16(float(v));
-            else
-              o[i] = S(v);
+            if constexpr (HAS_E) v += a.gamma * e1v[i];
+            if constexpr (KIND == ZM_STEP) v += dcol[c] * e2v[i];
+            o[i] = zm_store_elem<S, F>(v);
           }
           *reinterpret_cast<SV*>(static_cast<S*>(a.out) + int64_t(col0 + c) * a.ld_out + gi -
                                  a.out_off) = o;
@@ -769,8 +815,6 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
           }
         }
       }
-#pragma unroll
-      for (int i = 0; i < PT; ++i) vc[i] = HASV ? vcen[i] : F(0);
     }
     if (z + 1 < ze) load_e(z + 1, E);
   };
@@ -854,7 +898,8 @@ inline bool zm_aligned(const void* p, int64_t ld, size_t vec_bytes, int PT) {
 // false when the operator is not class-symmetric or the grid does not fit the
 // thread layout (nx a multiple of PT, at most 128 PT-chunks per row).
 inline size_t zm_lds_bytes(int nx, int ty, int cp, bool hasv, size_t fbytes) {
-  return size_t(2) * (cp + (hasv ? 1 : 0)) * (ty + 2) * (nx + 8) * fbytes;
+  // two buffers of: u of every column, and with a potential w = V u of every column
+  return size_t(2) * (hasv ? 2 * cp : cp) * (ty + 2) * (nx + 8) * fbytes;
 }
 
 template <typename F>
@@ -875,6 +920,7 @@ bool zm_setup(const chfsi_operator& op, int PT, int CP, double alpha, double bet
   a->z0 = 0;
   a->nzs = op.nz;
   a->out_off = 0;
+  a->use_w = op.field_mode == 2 ? 1 : 0;
   for (int k = 0; k < 4; ++k) {
     a->cu[k] = F(alpha * cA[k] + (k == 0 ? beta : 0.0));
     a->cw[k] = F(op.field_mode == 2 ? 0.5 * alpha * cM[k] : 0.0);
@@ -1049,8 +1095,9 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
                                    const double* colcoef, StencilStep s, int64_t b,
                                    hipStream_t st) {
   ZmArgs<double> z;
-  if (!dinv && zm_setup(op, 2, zm_per_wg(false), s.alpha, s.beta, &z) && zm_aligned(RY, op.n, 16, 2) &&
-      zm_aligned(RX, op.n, 16, 2) && zm_aligned(Yf, ldf, 16, 2) && zm_aligned(op.field, 0, 16, 2)) {
+  if (!dinv && RX && Yf && zm_setup(op, 2, zm_per_wg(false), s.alpha, s.beta, &z) &&
+      zm_aligned(RY, op.n, 16, 2) && zm_aligned(RX, op.n, 16, 2) && zm_aligned(Yf, ldf, 16, 2) &&
+      zm_aligned(op.field, 0, 16, 2)) {
     z.b = int(b);
     z.V = op.field;
     z.src = RY;
@@ -1093,7 +1140,7 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, co
   ZmArgs<float> z;
   const int pt = zm_pt_lowp();
   const size_t vb = size_t(pt) * sizeof(float);
-  if (!dinv && (op.field_mode == 0 || Vf) &&
+  if (!dinv && RX && Yf && (op.field_mode == 0 || Vf) &&
       zm_setup(op, pt, zm_per_wg(true), s.alpha, s.beta, &z) && zm_aligned(RY, op.n, vb, pt) &&
       zm_aligned(RX, op.n, vb, pt) && zm_aligned(Yf, op.n, vb, pt) && zm_aligned(Vf, 0, vb, pt)) {
     z.b = int(b);
@@ -1141,7 +1188,7 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, c
   ZmArgs<float> z;
   const int pt = zm_pt_lowp();
   const size_t vb = size_t(pt) * 2, vf = size_t(pt) * sizeof(float);
-  if (!dinv && (op.field_mode == 0 || Vf) &&
+  if (!dinv && RX && Yf && (op.field_mode == 0 || Vf) &&
       zm_setup(op, pt, zm_per_wg(true), s.alpha, s.beta, &z) && zm_aligned(RY, op.n, vb, pt) &&
       zm_aligned(RX, op.n, vb, pt) && zm_aligned(Yf, op.n, vb, pt) && zm_aligned(Vf, 0, vf, pt)) {
     z.b = int(b);
@@ -1199,7 +1246,7 @@ hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, 
     z.e1 = prev;
     z.ld_e1 = ldp;
     z.gamma = s.gamma;
-    return zm_launch<double, double, 2, ZM_STEP>(z, op.field_mode != 0, st);
+    return zm_launch<double, double, 2, ZM_CSTEP>(z, op.field_mode != 0, st);
   }
   SepArgs<double> a;
   if (sep_setup(op, &a)) {
