@@ -562,27 +562,31 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   const int x_lo = 4 + (xq == 0 ? nx - 1 : xq - 1);
   const int x_hi = 4 + (xq + PT == nx ? 0 : xq + PT);
 
-  // column base pointers (uniform within a group)
+  // Column base pointers are uniform within a group; every per-lane offset is
+  // a 32-bit byte count added to a uniform plane offset (the host keeps a
+  // column below 2^31 bytes), so the loads address base + 32-bit offset.
   const S* srcc[CP];
 #pragma unroll
   for (int c = 0; c < CP; ++c)
     srcc[c] = static_cast<const S*>(a.src) + int64_t(col0 + c) * a.ld_src;
+  const uint32_t own_b = uint32_t((y0 + my_row) * nx + xq) * uint32_t(sizeof(S));
   struct Staged {
     SV us[2][CP];
     FV vs[2];
   };
   auto load_plane = [&](int zp, Staged& R) __attribute__((always_inline)) {
-    const int64_t zo = int64_t(zp) * pstride;
+    const uint32_t zo = uint32_t(zp) * uint32_t(pstride);
+    const uint32_t zs = zo * uint32_t(sizeof(S)), zf = zo * uint32_t(sizeof(F));
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       if (!okc[m]) continue;
 #pragma unroll
       for (int c = 0; c < CP; ++c)
         if (ONE_COL || c < ncol)
-          R.us[m][c] = *reinterpret_cast<const SV*>(zm_byte_off(srcc[c] + zo, boff_s[m]));
+          R.us[m][c] = *reinterpret_cast<const SV*>(zm_byte_off(srcc[c], zs + boff_s[m]));
       if constexpr (HASV)
         if (m == 0 || use_w)
-          R.vs[m] = *reinterpret_cast<const FV*>(zm_byte_off(a.V + zo, boff_f[m]));
+          R.vs[m] = *reinterpret_cast<const FV*>(zm_byte_off(a.V, zf + boff_f[m]));
     }
   };
   auto put = [&](F* pl, int m, const F (&v)[PT]) __attribute__((always_inline)) {
@@ -693,23 +697,32 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
   };
   const S* e1p = static_cast<const S*>(a.e1);
   const S* e2p = static_cast<const S*>(a.e2);
+  const S* e1c[CP];
+  const S* e2c[CP];
+  S* outc[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) {
+    e1c[c] = e1p ? e1p + int64_t(col0 + c) * a.ld_e1 : nullptr;
+    e2c[c] = e2p ? e2p + int64_t(col0 + c) * a.ld_e2 : nullptr;
+    outc[c] = static_cast<S*>(a.out) + int64_t(col0 + c) * a.ld_out;
+  }
   constexpr bool HAS_E = KIND == ZM_STEP || KIND == ZM_CSTEP;
   auto load_e = [&](int z, Extra& E) __attribute__((always_inline)) {
     if (!active) return;
-    const int64_t gi = int64_t(z) * pstride + int64_t(y0 + my_row) * nx + xq;
+    const uint32_t gb = uint32_t(z) * uint32_t(pstride) * uint32_t(sizeof(S)) + own_b;
     if constexpr (KIND == ZM_STEP) {
 #pragma unroll
       for (int c = 0; c < CP; ++c) {
         if (!ONE_COL && c >= ncol) continue;
-        E.e1[c] = *reinterpret_cast<const SV*>(e1p + int64_t(col0 + c) * a.ld_e1 + gi);
-        E.e2[c] = *reinterpret_cast<const SV*>(e2p + int64_t(col0 + c) * a.ld_e2 + gi);
+        E.e1[c] = *reinterpret_cast<const SV*>(zm_byte_off(e1c[c], gb));
+        E.e2[c] = *reinterpret_cast<const SV*>(zm_byte_off(e2c[c], gb));
       }
     } else if constexpr (KIND == ZM_CSTEP) {
       if (e1p) {
 #pragma unroll
         for (int c = 0; c < CP; ++c) {
           if (!ONE_COL && c >= ncol) continue;
-          E.e1[c] = *reinterpret_cast<const SV*>(e1p + int64_t(col0 + c) * a.ld_e1 + gi);
+          E.e1[c] = *reinterpret_cast<const SV*>(zm_byte_off(e1c[c], gb));
         }
       }
     }
@@ -775,7 +788,9 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
     if (z + 2 <= ze) load_plane(wz(z + 2), R);
     __syncthreads();
     if (active) {
-      const int64_t gi = int64_t(z) * pstride + int64_t(y0 + my_row) * nx + xq;
+      // output byte offset: plane z of the grid, rows shifted by out_off
+      const uint32_t ob =
+          uint32_t(int64_t(z) * pstride - a.out_off) * uint32_t(sizeof(S)) + own_b;
 #pragma unroll
       for (int c = 0; c < CP; ++c) {
         F ck[PT], nk[PT], cmv[PT], nmv[PT];
@@ -802,8 +817,7 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
             if constexpr (KIND == ZM_STEP) v += dcol[c] * e2v[i];
             o[i] = zm_store_elem<S, F>(v);
           }
-          *reinterpret_cast<SV*>(static_cast<S*>(a.out) + int64_t(col0 + c) * a.ld_out + gi -
-                                 a.out_off) = o;
+          *reinterpret_cast<SV*>(reinterpret_cast<char*>(outc[c]) + ob) = o;
         }
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
@@ -908,6 +922,8 @@ bool zm_setup(const chfsi_operator& op, int PT, int CP, double alpha, double bet
   if (!class_symmetric(op.coef, cA)) return false;
   if (op.field_mode == 2 && !class_symmetric(op.coef_mass, cM)) return false;
   if (op.nx % PT != 0 || op.nx / PT > 128 || op.nx < 2 * PT) return false;
+  // per-lane byte offsets within a column are 32-bit
+  if (int64_t(op.n) * int64_t(sizeof(double)) >= (int64_t(1) << 31)) return false;
   const int tpr = op.nx / PT;
   if (zm_lds_bytes(op.nx, std::min(256 / tpr, op.ny), CP, op.field_mode != 0, sizeof(F)) > 65536)
     return false;
