@@ -4,8 +4,10 @@ The grids are ragged and carry the mass-weighted Gaussian-well potential.
 Shapes (nz, ny, nx) cover the vectorised z-marching kernel with one y tile,
 several y tiles with a ragged last one (ny = 20 over 16- and 8-row tiles),
 rows that leave threads idle (nx = 40: 10 or 20 threads per row), block
-widths that leave a partial column group, and the scalar fallback
-(nx = 10, not a multiple of 4).  FP64 filters match the oracle to 1e-11;
+widths that leave a partial column group, the filter-step kernels compiled
+for rows of 128 and 160 points (with ragged last y tiles at every slab
+height: 8/8/4 and 6/6/2 rows, or 4 and 3 rows for FP64), and the scalar
+fallback (nx = 10, not a multiple of 4).  FP64 filters match the oracle to 1e-11;
 FP32 / BF16-stored residual filters have an error bounded by the size of the
 residual part they carry (Theorem 3.4); a small solve with BF16 storage
 reaches the eigenvalues of the dense pencil.
@@ -44,7 +46,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-SHAPES = [(9, 10, 12), (5, 20, 64), (4, 30, 40), (6, 9, 10)]
+SHAPES = [(9, 10, 12), (5, 20, 64), (4, 30, 40), (6, 9, 10), (4, 20, 128), (3, 14, 160)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
