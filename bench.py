@@ -34,9 +34,9 @@ PEAK_HBM_GBS = 8000.0
 # passes over this script, scaled by what the same counters read for a 1 GiB
 # device copy (FETCH x 2.000, WRITE x 1.000); summary under profiles/.  Other
 # shapes report null.
-TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.8e6}
+TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.4e6}
 # the same for the BF16 z-march filter step on the 128^3 grid, block 1200
-TRAFFIC_ZMARCH = {(128, 1200, "bf16"): 21.90e9}
+TRAFFIC_ZMARCH = {(128, 1200, "bf16"): 21.98e9}
 
 
 def log(*a):
