@@ -484,16 +484,19 @@ static constexpr int kNumCU = 256;
 // (FP32 k-scaled: 64x64x32 / 8 splits 118 TFLOP/s vs 128x160 95; FP64:
 // 64x64x16 / 4 splits 58-61 TFLOP/s).  Larger tiles remain selectable through
 // force_config for other shapes.
-// Optional rule (knob CHFSI_GEMM64_WIDE=1): FP64 products with a long
-// reduction (Gram matrices Y^T W, K >> M, N) on 128 x 128 tiles (16 flop per
-// byte loaded vs 8 for 64 x 64).  Measured slower on the 128^3 x 1200 Gram
-// panels (Rayleigh-Ritz 653 vs 586 ms), so off by default.
-static int wide64_mode() {
-  static const int v = [] {
-    const char* e = std::getenv("CHFSI_GEMM64_WIDE");
-    return e ? std::atoi(e) : -1;
-  }();
-  return v;
+//
+// FP64 products with a long reduction (K >= 16 max(M, N), M, N >= 128: the
+// Gram matrices Y^T W of Rayleigh-Ritz) use 128 x 64 tiles and 8 k-splits.
+// The tile -> XCD remap then gives each XCD one k-range, whose panels every
+// tile on that XCD shares in its L2.  Measured on the 128^3 x 1200 grid
+// pencil (whole Rayleigh-Ritz, same process): 128x64 / 8 splits 375 ms,
+// 64x64 / 8 402 ms, 128x128 / 8 403 ms; 4 splits 456-593 ms; 16-64 splits
+// 610-990 ms (a k-range per XCD no longer holds).  Tuning knobs (read per
+// call): CHFSI_GEMM64_LONG_CFG (0 = 128x128, 1 = 128x64, 2 = 64x64) and
+// CHFSI_GEMM64_LONG_SPLITS (power of two, at most 64).
+static int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
 }
 
 template <typename T>
@@ -501,14 +504,15 @@ static void plan_impl(int64_t M, int64_t N, int64_t K, int batch, bool filter_la
                       int* splits) {
   (void)filter_layout;
   const int ncfg = sizeof(T) == 4 ? kNumF32 : kNumF64;
-  if (sizeof(T) == 8 && wide64_mode() == 1 && batch == 1 && M >= 128 && N >= 128 &&
-      K >= 16 * std::max(M, N)) {
-    const Cfg& w = kCfgF64[0];
-    const int64_t tiles = ((M + w.BM - 1) / w.BM) * ((N + w.BN - 1) / w.BN);
+  if (sizeof(T) == 8 && batch == 1 && M >= 128 && N >= 128 && K >= 16 * std::max(M, N)) {
+    int lcfg = env_int("CHFSI_GEMM64_LONG_CFG", 1);
+    if (lcfg < 0 || lcfg >= kNumF64) lcfg = 1;
+    const int lsplits = env_int("CHFSI_GEMM64_LONG_SPLITS", 8);
+    const Cfg& w = kCfgF64[lcfg];
     const int64_t max_s = std::max<int64_t>(1, K / (8 * w.BK));
     int s = 1;
-    while (tiles * s < int64_t(kNumCU) * 4 && s * 2 <= max_s && s < 64) s *= 2;
-    *config = 0;
+    while (s * 2 <= lsplits && s * 2 <= max_s && s < 64) s *= 2;
+    *config = lcfg;
     *splits = s;
     return;
   }
