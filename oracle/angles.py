@@ -28,9 +28,9 @@ def _b_orthonormalize(X: np.ndarray, B=None) -> np.ndarray:
     if B is None:
         Q, _ = np.linalg.qr(X)
         return Q
-    G = X.T @ (B @ X)
-    L = np.linalg.cholesky(0.5 * (G + G.T))
-    return np.linalg.solve(L, X.T).T
+    G = X.conj().T @ (B @ X)
+    L = np.linalg.cholesky(0.5 * (G + G.conj().T))
+    return np.linalg.solve(L.conj(), X.T).T
 
 
 def max_principal_angle(U: np.ndarray, X: np.ndarray, B=None) -> float:
@@ -40,10 +40,10 @@ def max_principal_angle(U: np.ndarray, X: np.ndarray, B=None) -> float:
     projector onto span(X) and U B-orthonormal, which stays accurate for tiny
     angles (the cosine route loses them below ~1e-8).
     """
-    Uo = _b_orthonormalize(np.asarray(U, dtype=np.float64), B)
-    Xo = _b_orthonormalize(np.asarray(X, dtype=np.float64), B)
+    Uo = _b_orthonormalize(np.asarray(U, dtype=np.result_type(U, np.float64)), B)
+    Xo = _b_orthonormalize(np.asarray(X, dtype=np.result_type(X, np.float64)), B)
     BU = Uo if B is None else B @ Uo
-    W = Uo - Xo @ (Xo.T @ BU)
-    G = W.T @ (W if B is None else B @ W)
-    s2 = float(np.max(np.linalg.eigvalsh(0.5 * (G + G.T))))
+    W = Uo - Xo @ (Xo.conj().T @ BU)
+    G = W.conj().T @ (W if B is None else B @ W)
+    s2 = float(np.max(np.linalg.eigvalsh(0.5 * (G + G.conj().T))))
     return float(np.arcsin(min(max(s2, 0.0), 1.0) ** 0.5))

@@ -51,8 +51,8 @@ from .angles import max_principal_angle
 
 def b_norm2(Dlt: np.ndarray, B: Optional[np.ndarray]) -> float:
     """||B^{1/2} Dlt||_2 = sqrt(lambda_max(Dlt^T B Dlt))."""
-    G = Dlt.T @ (Dlt if B is None else B @ Dlt)
-    return float(np.sqrt(max(np.max(np.linalg.eigvalsh(0.5 * (G + G.T))), 0.0)))
+    G = Dlt.conj().T @ (Dlt if B is None else B @ Dlt)
+    return float(np.sqrt(max(np.max(np.linalg.eigvalsh(0.5 * (G + G.conj().T))), 0.0)))
 
 
 def chebyshev_gap(lam_exact: np.ndarray, n: int, p: int, bounds):

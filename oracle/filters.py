@@ -10,6 +10,9 @@ Y_p = D^{-1} R_Y + X Lambda_Y at the end (Proposition 3.3 and
 eq. rChFSIrecurrenceMP).  Operators are passed as callables so that dense
 matrices, perturbed filter matrices and grid stencils all work.
 
+Blocks may be real or complex (Section 4.3's Hermitian problems): the
+recurrences have real coefficients, so they act on complex blocks unchanged.
+
 Pins: on a matrix with known eigenvectors the filter must equal
 Q C_p(Lambda) Q^T X (exact up to rounding); Algorithm 3 with D^{-1} = B^{-1}
 equals Algorithm 2 with H = B^{-1} A (Section 3.2, closing remark); the
@@ -36,7 +39,7 @@ def chebyshev_filter(apply_H: Op, X: np.ndarray, p: int, lmin: float, lmax: floa
     e, c, sigma = affine(lmin, lmax, lT)
     sigma1 = sigma
     gamma = 2.0 / sigma1
-    Xt = np.array(X, dtype=np.float64, copy=True)
+    Xt = np.array(X, dtype=np.result_type(X, np.float64), copy=True)
     Yt = (sigma1 / e) * (apply_H(Xt) - c * Xt)
     for _k in range(2, p + 1):
         sigma2 = 1.0 / (gamma - sigma)
@@ -61,7 +64,7 @@ def residual_filter(apply_A: Op, apply_Dinv: Op, X: np.ndarray, lam: np.ndarray,
     sigma1 = sigma
     gamma = 2.0 / sigma1
     lam = np.asarray(lam, dtype=np.float64)
-    Y = np.asarray(Yres, dtype=np.float64)
+    Y = np.asarray(Yres, dtype=np.result_type(Yres, np.float64))
     RX = np.zeros_like(Y)
     RY = (sigma1 / e) * Y
     LX = np.ones_like(lam)
@@ -74,7 +77,7 @@ def residual_filter(apply_A: Op, apply_Dinv: Op, X: np.ndarray, lam: np.ndarray,
         RX, RY = RY, RX
         LX, LY = LY, LX
         sigma = sigma2
-    out = apply_Dinv(RY) + np.asarray(X, dtype=np.float64) * LY[None, :]
+    out = apply_Dinv(RY) + np.asarray(X, dtype=np.result_type(X, np.float64)) * LY[None, :]
     if return_parts:
         return out, RY, LY
     return out

@@ -14,6 +14,9 @@ fall back to SVQB -- keep the eigen-directions of the scaled Gram matrix whose
 eigenvalue exceeds ``drop_tol`` times the largest, and solve the standard
 problem in that basis.  The caller refills dropped columns.
 
+Complex blocks (Section 4.3's Hermitian problems) take the same steps with
+conjugate transposes: Y^H A Y, Y^H B Y and X^H B X = I.
+
 Pins: Ritz values against scipy's dsygvd on the same pencil AND against the
 brute-force Jacobi of ``oracle.jacobi`` (tiny sizes); X^T B X = I; on a block
 that spans an invariant subspace the Ritz values are exact eigenvalues
@@ -27,7 +30,7 @@ import scipy.linalg as sla
 
 def column_norms(R: np.ndarray) -> np.ndarray:
     """Euclidean norm of every column."""
-    return np.sqrt(np.sum(np.asarray(R) ** 2, axis=0))
+    return np.sqrt(np.sum(np.abs(np.asarray(R)) ** 2, axis=0))
 
 
 def rayleigh_ritz(Y: np.ndarray, apply_A, apply_B, drop_tol: float = 1e-14):
@@ -37,14 +40,14 @@ def rayleigh_ritz(Y: np.ndarray, apply_A, apply_B, drop_tol: float = 1e-14):
     lam, R = A X - B X diag(lam), resnorm (column norms of R), dropped (number
     of basis directions discarded by the SVQB fallback) and svqb (bool).
     """
-    Y = np.asarray(Y, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.result_type(Y, np.float64))
     AY = apply_A(Y)
     BY = apply_B(Y)
-    Ga = Y.T @ AY
-    Gb = Y.T @ BY
-    Ga = 0.5 * (Ga + Ga.T)
-    Gb = 0.5 * (Gb + Gb.T)
-    s = 1.0 / np.sqrt(np.diag(Gb))
+    Ga = Y.conj().T @ AY
+    Gb = Y.conj().T @ BY
+    Ga = 0.5 * (Ga + Ga.conj().T)
+    Gb = 0.5 * (Gb + Gb.conj().T)
+    s = 1.0 / np.sqrt(np.diag(Gb).real)
     Gas = s[:, None] * Ga * s[None, :]
     Gbs = s[:, None] * Gb * s[None, :]
     svqb = False
@@ -58,8 +61,8 @@ def rayleigh_ritz(Y: np.ndarray, apply_A, apply_B, drop_tol: float = 1e-14):
         keep = w > drop_tol * w[-1]
         dropped = int(np.count_nonzero(~keep))
         T = U[:, keep] / np.sqrt(w[keep])[None, :]
-        Hp = T.T @ Gas @ T
-        Hp = 0.5 * (Hp + Hp.T)
+        Hp = T.conj().T @ Gas @ T
+        Hp = 0.5 * (Hp + Hp.conj().T)
         lam, E = np.linalg.eigh(Hp)
         W = s[:, None] * (T @ E)
     X = Y @ W

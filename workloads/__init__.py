@@ -18,6 +18,8 @@ Workload families (sizes are parameters so that tests can shrink them):
   target (the approximate inverse of B is then D^{-1}).
 * ``stencil_problem``  -- a periodic tensor-product Q1 finite-element pencil:
   stiffness/mass 27-point coefficients and a potential made of Gaussian wells.
+* ``dense_hermitian`` -- the complex Hermitian counterpart of
+  ``dense_generalized`` (complex reflectors, complex Hermitian S, real D).
 * ``toy_standard`` / ``toy_generalized`` -- the paper's controlled dense
   experiments (Section 4.1): prescribed spectra, a QR-generated orthogonal
   basis and a unit-norm symmetric perturbation.
@@ -36,7 +38,8 @@ __all__ = [
     "stencil_coefficients_1d", "tensor_stencil_27", "gaussian_wells",
     "stencil_problem", "random_block", "unit_sym_perturbation",
     "toy_standard", "toy_generalized", "DenseProblem", "StencilProblem",
-    "serving_schedule",
+    "serving_schedule", "complex_householder_vectors", "hermitian_from_spectrum",
+    "dense_hermitian", "random_block_complex",
 ]
 
 
@@ -168,6 +171,95 @@ def dense_generalized(n: int = 8192, n_low: int = 256, block: int = 320, degree:
                         degree=degree, tol=tol, eps=eps,
                         meta={"seed": seed, "sigma_max": sigma_max, "target": target,
                               "dmin": float(d.min()), "dmax": float(d.max())})
+
+
+# ----------------------------------------------------------------------------
+# complex Hermitian problems (Section 4.3)
+# ----------------------------------------------------------------------------
+
+def complex_householder_vectors(rng: np.random.Generator, n: int, count: int) -> np.ndarray:
+    """``count`` complex reflector vectors v_i = a_i + i b_i, a_i, b_i ~ N(0,1)^n,
+    drawn in the order a_1, b_1, a_2, b_2, ... (columns)."""
+    cols = []
+    for _ in range(count):
+        a = rng.standard_normal(n)
+        b = rng.standard_normal(n)
+        cols.append(a + 1j * b)
+    return np.stack(cols, axis=1)
+
+
+def hermitian_from_spectrum(lam: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """Q diag(lam) Q^H with Q = H_1 ... H_c, H_i = I - 2 v_i v_i^H / (v_i^H v_i)
+    (each H_i is Hermitian and unitary), applied reflector by reflector."""
+    A = np.diag(np.asarray(lam, dtype=np.complex128))
+    for i in range(V.shape[1] - 1, -1, -1):
+        v = V[:, i]
+        beta = 2.0 / float(np.real(np.vdot(v, v)))
+        w = v.conj() @ A                  # v^H A
+        A -= beta * np.outer(v, w)
+        u = A @ v                         # A v
+        A -= beta * np.outer(u, v.conj())
+    return 0.5 * (A + A.conj().T)
+
+
+def _sigma_max_power_complex(S: np.ndarray, dinv: np.ndarray, seed: int = 12345) -> float:
+    """Largest singular value of diag(dinv) S for Hermitian complex S (Lanczos on
+    M^H M from a fixed start vector); input construction only."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+    n = S.shape[0]
+    v0 = np.random.default_rng(seed).standard_normal(n).astype(np.complex128)
+
+    def mhm(x):
+        x = np.asarray(x).reshape(-1)
+        y = dinv * (S @ x)
+        return S @ (dinv * y)
+
+    op = LinearOperator((n, n), matvec=mhm, dtype=np.complex128)
+    w = eigsh(op, k=1, which="LA", v0=v0, tol=1e-13, return_eigenvectors=False)
+    return float(math.sqrt(abs(w[0])))
+
+
+def dense_hermitian(n: int = 8192, n_low: int = 256, block: int = 320, degree: int = 20,
+                    tol: float = 1e-8, seed: int = 1003, n_refl: int = 8,
+                    target: float = 0.05, generalized: bool = True) -> DenseProblem:
+    """Complex Hermitian counterpart of ``dense_generalized`` (Section 4.3).
+
+    Draw order: the complex reflector vectors, the n - n_low uniforms of the
+    spectrum (as ``cfg1_spectrum``), then (generalized) the n diagonal entries
+    D ~ U[0.5, 2] and G = G_r + i G_i with G_r, G_i ~ N(0,1)^{n x n}
+    (row-major, G_r first).  A = Q Lambda Q^H; B = D + eps S with
+    S = (G + G^H)/2 and eps = target / sigma_max(D^{-1} S), so that
+    ||D^{-1} eps S||_2 = target; the approximate inverse is the real D^{-1}.
+    With ``generalized=False`` B = I and D^{-1} = I.
+    """
+    rng = np.random.default_rng(seed)
+    V = complex_householder_vectors(rng, n, n_refl)
+    lam = cfg1_spectrum(rng, n, n_low=n_low)
+    A = hermitian_from_spectrum(lam, V)
+    if not generalized:
+        return DenseProblem(A=A, B=None, dinv=None, lam_A=lam, n_wanted=n_low, block=block,
+                            degree=degree, tol=tol, meta={"seed": seed, "complex": True})
+    d = rng.uniform(0.5, 2.0, size=n)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    S = 0.5 * (G + G.conj().T)
+    dinv = 1.0 / d
+    sigma_max = _sigma_max_power_complex(S, dinv)
+    eps = target / sigma_max
+    B = eps * S
+    B[np.diag_indices(n)] += d
+    return DenseProblem(A=A, B=B, dinv=dinv, lam_A=lam, n_wanted=n_low, block=block,
+                        degree=degree, tol=tol, eps=eps,
+                        meta={"seed": seed, "sigma_max": sigma_max, "target": target,
+                              "dmin": float(d.min()), "dmax": float(d.max()), "complex": True})
+
+
+def random_block_complex(n: int, b: int, seed: int) -> np.ndarray:
+    """Complex start block: real parts N(0,1)^{n x b} then imaginary parts, each
+    drawn as in ``random_block``."""
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal((b, n)).T
+    im = rng.standard_normal((b, n)).T
+    return np.asfortranarray(re + 1j * im)
 
 
 def random_block(n: int, b: int, seed: int) -> np.ndarray:
