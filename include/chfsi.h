@@ -18,8 +18,13 @@
  *  - Functions return a chfsi_status and never throw.  On error, output
  *    buffers are left untouched except where a function says otherwise, and a
  *    message is available from chfsi_last_error() (thread-local).
- *  - Real symmetric problems only (the complex Hermitian variant of the
- *    paper's Section 4.3 is not implemented).
+ *  - Complex Hermitian problems (the paper's Section 4.3): an operator of
+ *    kind CHFSI_OP_DENSE_HERMITIAN makes a complex context.  Its blocks
+ *    (X, resid, Yp of chfsi_filter) are interleaved complex -- (re, im) pairs
+ *    of doubles, column-major, leading dimensions counted in complex
+ *    elements -- while Ritz values and d_inv stay real.  Such a context runs
+ *    the residual filter (Algorithm 3) in FP64, FP32 or BF16;
+ *    chfsi_rayleigh_ritz and chfsi_solve return CHFSI_ERR_ARG for it.
  */
 #ifndef CHFSI_H_
 #define CHFSI_H_
@@ -46,9 +51,10 @@ typedef enum {
 
 /* Operator kinds. */
 typedef enum {
-  CHFSI_OP_IDENTITY = 0,  /* B = I (standard problem) */
-  CHFSI_OP_DENSE = 1,     /* dense symmetric matrix in device memory */
-  CHFSI_OP_STENCIL27 = 2  /* periodic 27-point grid operator (see chfsi_operator) */
+  CHFSI_OP_IDENTITY = 0,        /* B = I (standard problem) */
+  CHFSI_OP_DENSE = 1,           /* dense symmetric matrix in device memory */
+  CHFSI_OP_STENCIL27 = 2,       /* periodic 27-point grid operator (see chfsi_operator) */
+  CHFSI_OP_DENSE_HERMITIAN = 3  /* dense complex Hermitian matrix (Section 4.3; see below) */
 } chfsi_op_kind;
 
 /* Storage / arithmetic precision of the filter's bulk work (the residual
@@ -70,6 +76,14 @@ typedef enum { CHFSI_METHOD_CHFSI = 0, CHFSI_METHOD_RCHFSI = 1 } chfsi_method;
  * A symmetric operator.
  *  kind = CHFSI_OP_DENSE: `dense` (device, n x n, column-major, leading
  *    dimension `ld`, symmetric; borrowed: must outlive the context).
+ *  kind = CHFSI_OP_DENSE_HERMITIAN: `dense` (device) holds an n x n complex
+ *    Hermitian matrix, interleaved (entry (i, j) at dense[2 (i + j ld)] and
+ *    dense[2 (i + j ld) + 1]), `ld` in complex elements; borrowed.  With a
+ *    Hermitian A, B is NULL / the identity or Hermitian dense of A's size,
+ *    params.method must be CHFSI_METHOD_RCHFSI and params.memory_mode 0.  The
+ *    context keeps a planar copy [Re A | Im A] in the filter precision (2 n^2
+ *    elements) and runs each recurrence step as one real MFMA product of
+ *    2n x 2b operands (Section 4.3's complex product, 8 n^2 b flops).
  *  kind = CHFSI_OP_STENCIL27: periodic grid nx*ny*nz = n, vector index
  *    x + nx*(y + ny*z).  y = S z + potential term, where S has coefficients
  *    coef[(dz+1)*9 + (dy+1)*3 + (dx+1)] for the 27 offsets (dx,dy,dz) in

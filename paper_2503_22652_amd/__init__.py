@@ -23,7 +23,7 @@ OK, ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_NOT_SPD, ERR_NOCONV, ERR_NUMERIC, ERR_BU
     ERR_CANCELLED, ERR_TIMEOUT = range(10)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_NOMEM", "ERR_DEVICE", "ERR_NOT_SPD", "ERR_NOCONV",
                 "ERR_NUMERIC", "ERR_BUSY", "ERR_CANCELLED", "ERR_TIMEOUT"]
-OP_IDENTITY, OP_DENSE, OP_STENCIL27 = 0, 1, 2
+OP_IDENTITY, OP_DENSE, OP_STENCIL27, OP_DENSE_HERMITIAN = 0, 1, 2, 3
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 METHOD_CHFSI, METHOD_RCHFSI = 0, 1
 MAX_HISTORY = 512
@@ -150,6 +150,31 @@ def dense_operator(A) -> chfsi_operator:
     op.dense = _ptr(A)
     op.ld = A.stride(1) if A.stride(0) == 1 else A.stride(0)
     return op
+
+
+def hermitian_operator(A) -> chfsi_operator:
+    """Operator struct for a complex Hermitian complex128 CUDA tensor (column-major:
+    a transposed view of a contiguous buffer); ld in complex elements."""
+    op = chfsi_operator()
+    op.kind = OP_DENSE_HERMITIAN
+    op.n = A.shape[0]
+    op.dense = _ptr(A)
+    op.ld = A.stride(1) if A.stride(0) == 1 else A.stride(0)
+    return op
+
+
+def to_colmajor_complex(a, device="cuda"):
+    """Copy a host complex array to a column-major complex128 device tensor."""
+    import numpy as np
+    import torch
+    arr = np.asarray(a, dtype=np.complex128)
+    return torch.from_numpy(np.ascontiguousarray(arr.T)).to(device).t()
+
+
+def colmajor_empty_complex(n: int, b: int, device="cuda"):
+    """Uninitialised column-major complex128 n x b tensor."""
+    import torch
+    return torch.empty((b, n), dtype=torch.complex128, device=device).t()
 
 
 def identity_operator(n: int) -> chfsi_operator:

@@ -99,6 +99,14 @@ struct chfsi_ctx {
   uint16_t* A16 = nullptr;        // bfloat16 copy of a dense operator (BF16 residual filter)
   float* dinv32 = nullptr;        // FP32 D^{-1} (dense: always; stencil: only when given)
   float* Vf = nullptr;            // FP32 potential of a stencil operator (FP32/BF16 filter)
+  // complex Hermitian operator (residual filter only): planar left operand
+  // L = [A_r | A_i] (n x 2n, filter precision), [d; d], the materialised right
+  // operand Z~ (2n x 2b, FP32/FP64) and its bfloat16 copy (BF16)
+  bool cplx = false;
+  void* Lc = nullptr;
+  void* dinv2 = nullptr;
+  void* Zt = nullptr;
+  double* f64_c = nullptr;        // planar FP64 copy of the residual (complex FP64 filter)
   double* tri = nullptr;          // Cholesky / triangular-solve scratch
   float *f32_a = nullptr, *f32_b = nullptr, *f32_c = nullptr;     // RX, RY, Y copy (n x b)
   double *f64_a = nullptr, *f64_b = nullptr;                        // RX, RY (FP64 filter)
@@ -156,6 +164,35 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
   if (A->n <= 0) {
     set_error("operator size must be positive");
     return CHFSI_ERR_ARG;
+  }
+  if (A->kind == CHFSI_OP_DENSE_HERMITIAN) {
+    // complex Hermitian problems (Section 4.3): the residual filter only
+    if (!A->dense || A->ld < A->n) {
+      set_error("dense A needs a device pointer and ld >= n");
+      return CHFSI_ERR_ARG;
+    }
+    if (!is_identity(B) && (B->kind != CHFSI_OP_DENSE_HERMITIAN || B->n != A->n || !B->dense ||
+                            B->ld < B->n)) {
+      set_error("with a Hermitian A, B must be the identity or a Hermitian dense matrix of A's size");
+      return CHFSI_ERR_ARG;
+    }
+    if (p->method != CHFSI_METHOD_RCHFSI || p->memory_mode != 0) {
+      set_error("complex Hermitian operators support the residual filter with memory_mode 0");
+      return CHFSI_ERR_ARG;
+    }
+    if (p->block <= 0 || p->n_wanted <= 0 || p->n_wanted > p->block || p->block > A->n) {
+      set_error("need 0 < n_wanted <= block <= n");
+      return CHFSI_ERR_ARG;
+    }
+    if (p->degree < 1 || p->degree > 1000) {
+      set_error("degree must be in [1, 1000]");
+      return CHFSI_ERR_ARG;
+    }
+    if (p->filter_prec < CHFSI_PREC_FP64 || p->filter_prec > CHFSI_PREC_BF16) {
+      set_error("unknown filter precision");
+      return CHFSI_ERR_ARG;
+    }
+    return CHFSI_OK;
   }
   if (A->kind == CHFSI_OP_DENSE) {
     if (!A->dense || A->ld < A->n) {
@@ -248,7 +285,27 @@ struct SizePlan {
   size_t blk = 0, bb = 0, ws = 0, ws_eig = 0, tri = 0;
 };
 
+SizePlan plan_sizes_complex(const chfsi_operator* A, const chfsi_params* p) {
+  SizePlan s;
+  const int64_t n = A->n, b = p->block;
+  const size_t el = p->filter_prec == CHFSI_PREC_FP64 ? sizeof(double) : sizeof(float);
+  const size_t lel = p->filter_prec == CHFSI_PREC_BF16 ? sizeof(uint16_t) : el;
+  s.a32 = size_t(n) * 2 * n * lel + size_t(2) * n * el;              // L, [d; d]
+  s.f32blk = size_t(n) * 2 * b * el;                                   // one planar block
+  size_t zt = size_t(2) * n * 2 * b * el;                              // Z~
+  if (p->filter_prec == CHFSI_PREC_BF16) zt += size_t(2) * n * 2 * b * sizeof(uint16_t);
+  s.coef = size_t(p->degree + 1) * 2 * b * sizeof(double);
+  size_t ws = p->filter_prec == CHFSI_PREC_FP64
+                  ? std::max(plan_bytes<double>(n, 2 * b, 2 * n), size_t(16) * n * 2 * b * el)
+                  : std::max(plan_bytes<float>(n, 2 * b, 2 * n), size_t(16) * n * 2 * b * el);
+  if (p->filter_prec == CHFSI_PREC_BF16) ws = std::max(ws, gemm_bf16_workspace_bytes(n, 2 * b));
+  s.ws = ws + 256;
+  s.total = s.a32 + 3 * s.f32blk + zt + 2 * s.coef + b * sizeof(double) + s.ws + 64;
+  return s;
+}
+
 SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
+  if (A->kind == CHFSI_OP_DENSE_HERMITIAN) return plan_sizes_complex(A, p);
   SizePlan s;
   const int64_t n = A->n, b = p->block;
   const bool dense = A->kind == CHFSI_OP_DENSE;
@@ -584,6 +641,153 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
       std::swap(RX, RY);
     }
     CK(rchfsi_reconstruct_bf16(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
+  }
+  if (flops) *flops += fl;
+  return CHFSI_OK;
+}
+
+// Algorithm 3 for a complex Hermitian A (Section 4.3).  The recurrence's
+// coefficients and Lambda are real, so every step is one real product on
+// planar blocks (see complex.hip): R_X <- a (L Z~) + b R_Y + c R_X + a Yc diag(Lambda_Y),
+// Z~ built from D^{-1}-scaled R_Y (the product's k-scale [d; d]).  The
+// per-column coefficients cover both halves of the planar block.
+chfsi_status filter_rchfsi_complex(chfsi_ctx* c, const double* X, int64_t ldx, const double* ritz,
+                                   const double* resid, int64_t ldr, double* Yp, int64_t ldy,
+                                   double lmin, double lmax, double lT, int p, double* flops) {
+  const int64_t n = c->n, b = c->b, b2 = 2 * b;
+  chfsi_status st = ensure_coef(c, p);
+  if (st != CHFSI_OK) return st;
+  const FilterScalars f = filter_scalars(lmin, lmax, lT);
+  const double gamma = 2.0 / f.sigma1;
+  std::vector<double> LX(b, 1.0), LY(b), LN(b);
+  for (int64_t j = 0; j < b; ++j) LY[j] = (f.sigma1 / f.e) * (ritz[j] - f.c);
+  struct Step {
+    double a, bb, cc;
+  };
+  std::vector<Step> steps;
+  double sigma = f.sigma1;
+  for (int k = 2; k <= p; ++k) {
+    const double sigma2 = 1.0 / (gamma - sigma);
+    const double a = 2.0 * sigma2 / f.e;
+    steps.push_back({a, -a * f.c, -sigma * sigma2});
+    for (int64_t j = 0; j < b; ++j) {
+      for (int h = 0; h < 2; ++h) {
+        c->h_coef64[(k - 2) * b2 + h * b + j] = LY[j];
+        c->h_coef32[(k - 2) * b2 + h * b + j] = float(LY[j]);
+      }
+      LN[j] = a * LY[j] * ritz[j] - a * f.c * LY[j] - sigma * sigma2 * LX[j];
+    }
+    std::swap(LX, LY);
+    std::swap(LY, LN);
+    sigma = sigma2;
+  }
+  CK(hipEventSynchronize(c->ev_stage));
+  double* h_lam = reinterpret_cast<double*>(c->h_stage);
+  std::memcpy(h_lam, LY.data(), b * sizeof(double));
+  CK(hipMemcpyAsync(c->lamY, h_lam, b * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const int nsteps = p - 1;
+  const double scale1 = f.sigma1 / f.e;
+  double fl = 0.0;
+  if (c->prm.filter_prec == CHFSI_PREC_FP64) {
+    if (nsteps > 0) {
+      double* hs = reinterpret_cast<double*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
+      std::memcpy(hs, c->h_coef64.data(), size_t(nsteps) * b2 * sizeof(double));
+      CK(hipMemcpyAsync(c->coef64, hs, size_t(nsteps) * b2 * sizeof(double),
+                        hipMemcpyHostToDevice, c->stream));
+    }
+    double* RX = c->f64_a;
+    double* RY = c->f64_b;
+    double* Yc = c->f64_c;
+    double* Zt = static_cast<double*>(c->Zt);
+    CK(hipEventRecord(c->ev_stage, c->stream));
+    CK(cplx_init<double>(resid, ldr, n, b, scale1, RY, RX, Yc, c->stream));
+    for (int s = 0; s < nsteps; ++s) {
+      const Step& sp = steps[s];
+      CK(cplx_rhs<double>(RY, n, b, Zt, c->stream));
+      GemmDesc<double> g;
+      g.M = n;
+      g.N = b2;
+      g.K = 2 * n;
+      g.A = static_cast<const double*>(c->Lc);
+      g.sak = 1;
+      g.sam = 2 * n;
+      g.B = Zt;
+      g.sbk = 1;
+      g.sbn = 2 * n;
+      g.kscale = static_cast<const double*>(c->dinv2);
+      g.C = RX;
+      g.ldc = n;
+      g.epi.alpha = sp.a;
+      g.epi.beta = sp.bb;
+      g.epi.C1 = RY;
+      g.epi.ldc1 = n;
+      g.epi.gamma = sp.cc;
+      g.epi.C2 = RX;
+      g.epi.ldc2 = n;
+      g.epi.delta = sp.a;
+      g.epi.colscale3 = c->coef64 + int64_t(s) * b2;
+      g.epi.C3 = Yc;
+      g.epi.ldc3 = n;
+      CK(prof_pair(c, &g.ev_begin, &g.ev_end));
+      CK(gemm<double>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
+      fl += 8.0 * double(n) * double(n) * double(b);
+      std::swap(RX, RY);
+    }
+    CK(cplx_reconstruct<double>(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
+  } else {
+    // FP32 blocks; FP32 MFMA on the FP32 L, or bfloat16 MFMA on the bfloat16 L
+    if (nsteps > 0) {
+      float* hs = reinterpret_cast<float*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
+      std::memcpy(hs, c->h_coef32.data(), size_t(nsteps) * b2 * sizeof(float));
+      CK(hipMemcpyAsync(c->coef32, hs, size_t(nsteps) * b2 * sizeof(float), hipMemcpyHostToDevice,
+                        c->stream));
+    }
+    float* RX = c->f32_a;
+    float* RY = c->f32_b;
+    float* Yc = c->f32_c;
+    float* Zt = static_cast<float*>(c->Zt);
+    const bool bf = c->prm.filter_prec == CHFSI_PREC_BF16;
+    CK(hipEventRecord(c->ev_stage, c->stream));
+    CK(cplx_init<float>(resid, ldr, n, b, scale1, RY, RX, Yc, c->stream));
+    for (int s = 0; s < nsteps; ++s) {
+      const Step& sp = steps[s];
+      CK(cplx_rhs<float>(RY, n, b, Zt, c->stream));
+      GemmDesc<float> g;
+      g.M = n;
+      g.N = b2;
+      g.K = 2 * n;
+      g.A = bf ? nullptr : static_cast<const float*>(c->Lc);
+      g.sak = 1;
+      g.sam = 2 * n;
+      g.B = Zt;
+      g.sbk = 1;
+      g.sbn = 2 * n;
+      g.kscale = static_cast<const float*>(c->dinv2);
+      g.C = RX;
+      g.ldc = n;
+      g.epi.alpha = float(sp.a);
+      g.epi.beta = float(sp.bb);
+      g.epi.C1 = RY;
+      g.epi.ldc1 = n;
+      g.epi.gamma = float(sp.cc);
+      g.epi.C2 = RX;
+      g.epi.ldc2 = n;
+      g.epi.delta = float(sp.a);
+      g.epi.colscale3 = c->coef32 + int64_t(s) * b2;
+      g.epi.C3 = Yc;
+      g.epi.ldc3 = n;
+      CK(prof_pair(c, &g.ev_begin, &g.ev_end));
+      if (bf) {
+        uint16_t* Zt16 = reinterpret_cast<uint16_t*>(Zt + size_t(2) * n * b2);
+        CK(gemm_bf16_filter(g, static_cast<const uint16_t*>(c->Lc), 2 * n, Zt16, c->stream, c->ws,
+                            filter_gemm_splits()));
+      } else {
+        CK(gemm<float>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
+      }
+      fl += 8.0 * double(n) * double(n) * double(b);
+      std::swap(RX, RY);
+    }
+    CK(cplx_reconstruct<float>(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
   }
   if (flops) *flops += fl;
   return CHFSI_OK;
@@ -1307,7 +1511,36 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   const SizePlan sp = plan_sizes(A, B, params);
   st = CHFSI_OK;
   const bool dense = A->kind == CHFSI_OP_DENSE;
-  if (params->filter_prec == CHFSI_PREC_FP32) {
+  c->cplx = A->kind == CHFSI_OP_DENSE_HERMITIAN;
+  if (c->cplx) {
+    // planar operator copy, [d; d], three planar blocks, Z~ (and its bfloat16
+    // copy), the coefficient tables for 2b columns; no Rayleigh-Ritz buffers
+    const bool f64 = params->filter_prec == CHFSI_PREC_FP64;
+    const size_t el = f64 ? sizeof(double) : sizeof(float);
+    const size_t lel = params->filter_prec == CHFSI_PREC_BF16 ? sizeof(uint16_t) : el;
+    c->Lc = ctx_alloc<char>(c, size_t(n) * 2 * n * lel, &st);
+    c->dinv2 = ctx_alloc<char>(c, size_t(2) * n * el, &st);
+    size_t zt = size_t(2) * n * 2 * b * el;
+    if (params->filter_prec == CHFSI_PREC_BF16) zt += size_t(2) * n * 2 * b * sizeof(uint16_t);
+    c->Zt = ctx_alloc<char>(c, zt, &st);
+    if (f64) {
+      c->f64_a = ctx_alloc<double>(c, sp.f32blk, &st);
+      c->f64_b = ctx_alloc<double>(c, sp.f32blk, &st);
+      c->f64_c = ctx_alloc<double>(c, sp.f32blk, &st);
+    } else {
+      c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
+      c->f32_b = ctx_alloc<float>(c, sp.f32blk, &st);
+      c->f32_c = ctx_alloc<float>(c, sp.f32blk, &st);
+    }
+    c->coef_cap = params->degree;
+    c->coef32 = ctx_alloc<float>(c, size_t(params->degree) * 2 * b * sizeof(float), &st);
+    c->coef64 = ctx_alloc<double>(c, size_t(params->degree) * 2 * b * sizeof(double), &st);
+    c->lamY = ctx_alloc<double>(c, b * sizeof(double), &st);
+    c->h_coef32.assign(size_t(params->degree) * 2 * b, 0.0f);
+    c->h_coef64.assign(size_t(params->degree) * 2 * b, 0.0);
+    c->ws.bytes = sp.ws;
+    c->ws.ptr = ctx_alloc<char>(c, sp.ws, &st);
+  } else if (params->filter_prec == CHFSI_PREC_FP32) {
     if (dense) c->A32 = ctx_alloc<float>(c, size_t(n) * n * sizeof(float), &st);
     if (dense || d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
     c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
@@ -1329,6 +1562,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     c->bf_b = ctx_alloc<char>(c, sp.bfblk, &st);
     c->bf_c = ctx_alloc<char>(c, sp.bfblk, &st);
   }
+  if (!c->cplx) {
   if (!dense && params->filter_prec != CHFSI_PREC_FP64 && A->field_mode != 0)
     c->Vf = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
   c->coef_cap = params->degree;
@@ -1367,11 +1601,13 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   c->ws.ptr = ctx_alloc<char>(c, sp.ws, &st);
   c->ws_eig.bytes = sp.ws_eig;
   c->ws_eig.ptr = ctx_alloc<char>(c, sp.ws_eig, &st);
+  }
   if (st != CHFSI_OK) {
     chfsi_destroy(c);
     return st;
   }
-  c->h_stage_bytes = b * sizeof(double) + size_t(params->degree) * b * sizeof(double) + 64;
+  c->h_stage_bytes = b * sizeof(double) + size_t(params->degree) * (c->cplx ? 2 : 1) * b *
+                                                sizeof(double) + 64;
   if (hipHostMalloc(&c->h_w, b * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&c->h_norms, b * sizeof(double)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_flags), 64) != hipSuccess ||
@@ -1404,6 +1640,18 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   }
   // precision-converted operator copies (owned)
   hipError_t e = hipSuccess;
+  if (c->cplx) {
+    if (params->filter_prec == CHFSI_PREC_FP64) {
+      e = herm_to_planar<double>(A->dense, A->ld, n, static_cast<double*>(c->Lc), c->stream);
+      if (e == hipSuccess) e = dup_dinv<double>(d_inv, n, static_cast<double*>(c->dinv2), c->stream);
+    } else {
+      if (params->filter_prec == CHFSI_PREC_BF16)
+        e = herm_to_planar<uint16_t>(A->dense, A->ld, n, static_cast<uint16_t*>(c->Lc), c->stream);
+      else
+        e = herm_to_planar<float>(A->dense, A->ld, n, static_cast<float*>(c->Lc), c->stream);
+      if (e == hipSuccess) e = dup_dinv<float>(d_inv, n, static_cast<float*>(c->dinv2), c->stream);
+    }
+  }
   if (c->A32) e = convert_f64_f32(A->dense, A->ld, c->A32, n, n, n, c->stream);
   if (e == hipSuccess && c->A16) e = convert_f64_bf16(A->dense, A->ld, c->A16, n, n, n, c->stream);
   if (e == hipSuccess && c->dinv32) {
@@ -1449,6 +1697,9 @@ chfsi_status chfsi_filter(chfsi_ctx* c, const double* X, int64_t ldx, const doub
       set_error("degree %d exceeds the context's degree %d", p, c->coef_cap);
       return CHFSI_ERR_ARG;
     }
+    if (c->cplx)
+      return filter_rchfsi_complex(c, X, ldx, ritz, resid, ldr, Yp, ldy, lmin, lmax, lT, p,
+                                   nullptr);
     return filter_rchfsi(c, X, ldx, ritz, resid, ldr, Yp, ldy, lmin, lmax, lT, p, nullptr);
   }
   return filter_chfsi(c, X, ldx, Yp, ldy, lmin, lmax, lT, p, nullptr);
@@ -1478,6 +1729,10 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, dou
     set_error("null argument");
     return CHFSI_ERR_ARG;
   }
+  if (c->cplx) {
+    set_error("Rayleigh-Ritz is not implemented for complex Hermitian operators (filter only)");
+    return CHFSI_ERR_ARG;
+  }
   if (ldy < c->n || ldx < c->n || ldr < c->n) {
     set_error("leading dimensions must be >= n");
     return CHFSI_ERR_ARG;
@@ -1499,6 +1754,10 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
                          chfsi_report* rep) {
   if (!c || !X || !evals || !resnorms) {
     set_error("null argument");
+    return CHFSI_ERR_ARG;
+  }
+  if (c->cplx) {
+    set_error("chfsi_solve is not implemented for complex Hermitian operators (filter only)");
     return CHFSI_ERR_ARG;
   }
   if (ldx < c->n) {

@@ -1,0 +1,182 @@
+// Complex Hermitian problems (Section 4.3): layout kernels that let the real
+// MFMA GEMM carry the complex residual filter.
+//
+// A complex product A Z (A Hermitian n x n, Z n x b) is one real product on
+// planar data:
+//   [Re(AZ) | Im(AZ)] = L Z~,   L = [A_r | A_i]  (n x 2n),
+//   Z~ = [[Z_r, Z_i], [-Z_i, Z_r]]               (2n x 2b),
+// where A_r(m,k) = Re A(m,k), A_i(m,k) = Im A(m,k).  The library keeps L
+// k-contiguous (row m of L at L + m * 2n): since A(m,k) = conj(A(k,m)), row m
+// of L is [Re A(:,m), -Im A(:,m)], read down column m of the column-major
+// input.  Blocks are kept planar (n x 2b: real parts in columns 0..b-1,
+// imaginary parts in b..2b-1); the recurrence's coefficients are real, so the
+// fused three-term update of the real path applies to both halves unchanged.
+// Interleaved complex data (the ABI's layout) is (re, im) pairs of doubles.
+//
+// All are grid-stride kernels with 64-bit indexing.
+#include "internal.h"
+
+#include <cstdint>
+
+namespace chfsi {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int64_t grid_for(int64_t total, int64_t cap = 65536) {
+  int64_t g = (total + kThreads - 1) / kThreads;
+  if (g < 1) g = 1;
+  return g > cap ? cap : g;
+}
+
+template <typename F>
+__device__ __forceinline__ F to_elem(double v) {
+  return F(v);
+}
+template <>
+__device__ __forceinline__ uint16_t to_elem<uint16_t>(double v) {
+  // bfloat16, round to nearest even (hardware conversion)
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(float(v)));
+}
+
+// L (n x 2n, k-contiguous rows) from the interleaved column-major Hermitian A
+template <typename F>
+__global__ __launch_bounds__(kThreads) void k_herm_planar(const double* __restrict__ A, int64_t lda,
+                                                          int64_t n, F* __restrict__ L) {
+  const int64_t total = n * n;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t m = idx / n, k = idx - m * n;
+    const double re = A[2 * (k + m * lda)], im = A[2 * (k + m * lda) + 1];
+    L[m * 2 * n + k] = to_elem<F>(re);
+    L[m * 2 * n + n + k] = to_elem<F>(-im);
+  }
+}
+
+// [d; d] (length 2n) in the filter precision; d = 1 when dinv is null
+template <typename F>
+__global__ __launch_bounds__(kThreads) void k_dup_dinv(const double* __restrict__ dinv, int64_t n,
+                                                       F* __restrict__ out) {
+  for (int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kThreads) {
+    const F v = F(dinv ? dinv[i] : 1.0);
+    out[i] = v;
+    out[n + i] = v;
+  }
+}
+
+// R_Y = scale * R, R_X = 0, Yc = R (planar, ld n) from the interleaved residual
+template <typename F>
+__global__ __launch_bounds__(kThreads) void k_cinit(const double* __restrict__ R, int64_t ldr,
+                                                    int64_t n, int64_t b, double scale,
+                                                    F* __restrict__ RY, F* __restrict__ RX,
+                                                    F* __restrict__ Yc) {
+  const int64_t total = n * b;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / n, i = idx - j * n;
+    const double re = R[2 * (i + j * ldr)], im = R[2 * (i + j * ldr) + 1];
+    const int64_t pr = i + j * n, pi = i + (b + j) * n;
+    RY[pr] = F(scale * re);
+    RY[pi] = F(scale * im);
+    RX[pr] = F(0);
+    RX[pi] = F(0);
+    Yc[pr] = F(re);
+    Yc[pi] = F(im);
+  }
+}
+
+// Z~ (2n x 2b, ld 2n) from the planar block Z (n x 2b, ld n)
+template <typename F>
+__global__ __launch_bounds__(kThreads) void k_crhs(const F* __restrict__ Z, int64_t n, int64_t b,
+                                                   F* __restrict__ Zt) {
+  const int64_t total = n * b;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / n, k = idx - j * n;
+    const F re = Z[k + j * n], im = Z[k + (b + j) * n];
+    F* c0 = Zt + j * 2 * n;          // column j: [Z_r; -Z_i]
+    F* c1 = Zt + (b + j) * 2 * n;    // column b + j: [Z_i; Z_r]
+    c0[k] = re;
+    c0[n + k] = -im;
+    c1[k] = im;
+    c1[n + k] = re;
+  }
+}
+
+// Yp = D^{-1} R_Y + X Lambda_Y (interleaved complex, FP64)
+template <typename F>
+__global__ __launch_bounds__(kThreads) void k_crecon(const F* __restrict__ RY,
+                                                     const double* __restrict__ dinv,
+                                                     const double* __restrict__ X, int64_t ldx,
+                                                     const double* __restrict__ lam, double* Yp,
+                                                     int64_t ldy, int64_t n, int64_t b) {
+  const int64_t total = n * b;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / n, i = idx - j * n;
+    const double d = dinv ? dinv[i] : 1.0, l = lam[j];
+    const double xr = X[2 * (i + j * ldx)], xi = X[2 * (i + j * ldx) + 1];
+    const double re = d * double(RY[i + j * n]) + xr * l;
+    const double im = d * double(RY[i + (b + j) * n]) + xi * l;
+    Yp[2 * (i + j * ldy)] = re;
+    Yp[2 * (i + j * ldy) + 1] = im;
+  }
+}
+
+}  // namespace
+
+template <typename F>
+hipError_t herm_to_planar(const double* A, int64_t lda, int64_t n, F* L, hipStream_t st) {
+  k_herm_planar<F><<<grid_for(n * n), kThreads, 0, st>>>(A, lda, n, L);
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t dup_dinv(const double* dinv, int64_t n, F* out, hipStream_t st) {
+  k_dup_dinv<F><<<grid_for(n), kThreads, 0, st>>>(dinv, n, out);
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t cplx_init(const double* R, int64_t ldr, int64_t n, int64_t b, double scale, F* RY,
+                     F* RX, F* Yc, hipStream_t st) {
+  k_cinit<F><<<grid_for(n * b), kThreads, 0, st>>>(R, ldr, n, b, scale, RY, RX, Yc);
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t cplx_rhs(const F* Z, int64_t n, int64_t b, F* Zt, hipStream_t st) {
+  k_crhs<F><<<grid_for(n * b), kThreads, 0, st>>>(Z, n, b, Zt);
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t cplx_reconstruct(const F* RY, const double* dinv, const double* X, int64_t ldx,
+                            const double* lamY, double* Yp, int64_t ldy, int64_t n, int64_t b,
+                            hipStream_t st) {
+  k_crecon<F><<<grid_for(n * b), kThreads, 0, st>>>(RY, dinv, X, ldx, lamY, Yp, ldy, n, b);
+  return hipGetLastError();
+}
+
+template hipError_t herm_to_planar<float>(const double*, int64_t, int64_t, float*, hipStream_t);
+template hipError_t herm_to_planar<double>(const double*, int64_t, int64_t, double*, hipStream_t);
+template hipError_t herm_to_planar<uint16_t>(const double*, int64_t, int64_t, uint16_t*,
+                                             hipStream_t);
+template hipError_t dup_dinv<float>(const double*, int64_t, float*, hipStream_t);
+template hipError_t dup_dinv<double>(const double*, int64_t, double*, hipStream_t);
+template hipError_t cplx_init<float>(const double*, int64_t, int64_t, int64_t, double, float*,
+                                     float*, float*, hipStream_t);
+template hipError_t cplx_init<double>(const double*, int64_t, int64_t, int64_t, double, double*,
+                                      double*, double*, hipStream_t);
+template hipError_t cplx_rhs<float>(const float*, int64_t, int64_t, float*, hipStream_t);
+template hipError_t cplx_rhs<double>(const double*, int64_t, int64_t, double*, hipStream_t);
+template hipError_t cplx_reconstruct<float>(const float*, const double*, const double*, int64_t,
+                                            const double*, double*, int64_t, int64_t, int64_t,
+                                            hipStream_t);
+template hipError_t cplx_reconstruct<double>(const double*, const double*, const double*, int64_t,
+                                             const double*, double*, int64_t, int64_t, int64_t,
+                                             hipStream_t);
+
+}  // namespace chfsi

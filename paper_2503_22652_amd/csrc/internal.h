@@ -93,6 +93,31 @@ template <typename T>
 void gemm_plan(int64_t M, int64_t N, int64_t K, int batch, int* config, int* splits);
 
 // ---------------------------------------------------------------------------
+// Complex Hermitian layouts (complex.hip).  Interleaved complex data are
+// (re, im) double pairs with leading dimensions in complex elements; planar
+// blocks are n x 2b (real parts, then imaginary parts), ld n.
+// ---------------------------------------------------------------------------
+// L (n x 2n, row m at L + m*2n) = [Re A(:,m), -Im A(:,m)]: the left operand of
+// the planar real product (F = float, double or uint16_t bfloat16)
+template <typename F>
+hipError_t herm_to_planar(const double* A, int64_t lda, int64_t n, F* L, hipStream_t st);
+// out[0..n) = out[n..2n) = dinv (1 when null)
+template <typename F>
+hipError_t dup_dinv(const double* dinv, int64_t n, F* out, hipStream_t st);
+// planar RY = scale * R, RX = 0, Yc = R from the interleaved residual
+template <typename F>
+hipError_t cplx_init(const double* R, int64_t ldr, int64_t n, int64_t b, double scale, F* RY,
+                     F* RX, F* Yc, hipStream_t st);
+// Zt (2n x 2b, ld 2n) = [[Z_r, Z_i], [-Z_i, Z_r]] from the planar Z
+template <typename F>
+hipError_t cplx_rhs(const F* Z, int64_t n, int64_t b, F* Zt, hipStream_t st);
+// interleaved Yp = dinv .* RY + X diag(lamY)
+template <typename F>
+hipError_t cplx_reconstruct(const F* RY, const double* dinv, const double* X, int64_t ldx,
+                            const double* lamY, double* Yp, int64_t ldy, int64_t n, int64_t b,
+                            hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // Elementwise / reduction kernels (blas1.hip)
 // ---------------------------------------------------------------------------
 // out32[i,j] = (float)(s * in64[i,j]); optional second output copy32 = (float)in64
