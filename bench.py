@@ -260,6 +260,7 @@ def main():
         out["paper_context"] = ("paper reports up to 2.7x filtering / 2.1x eigensolve speedup "
                                 "(TF32B vs FP64 R-ChFSI, complex Hermitian) on Intel Data Center "
                                 "GPU Max (Aurora); context only")
+        out["complex_hermitian_filter"] = complex_filter_rates(P, n, b, nw, p, stream)
 
     if args.calibrate_copy:
         nbytes = args.calibrate_copy * (1 << 20)
@@ -275,6 +276,57 @@ def main():
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(prob, X0)
     print(json.dumps(out), flush=True)
+
+
+def complex_filter_rates(P, n, b, nw, p, stream):
+    """Residual filter of the complex Hermitian counterpart of the dense workload
+    (device-built: complex reflectors, complex Hermitian S, real D): one pass
+    of degree p in FP64, FP32 and BF16 products; 8 n^2 b flops per step."""
+    import numpy as np
+    import torch
+    from workloads.gpu import hermitian_problem
+    A, B, dinv, _ = hermitian_problem(n, nw, seed=1003)
+    lmax = 10.0 / (0.95 * float((1.0 / dinv).min())) + 0.1
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2003)
+    X = torch.complex(torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g),
+                      torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g)).t()
+    R = (1e-3 * torch.complex(torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g),
+                              torch.randn((b, n), dtype=torch.float64, device="cuda",
+                                          generator=g))).t()
+    lam = np.sort(np.random.default_rng(2003).uniform(-1.0, 0.2, b))
+    bounds = (lam[0] - 0.05 * (lam[-1] - lam[0]), lmax, lam[-1])
+    Y = P.colmajor_empty_complex(n, b)
+    step_flops = 8.0 * n * n * b
+    res = {"workload": f"complex Hermitian A x = lambda B x, N={n}, block {b}, degree {p}, "
+                       f"||D^-1 eps S||_2=0.05 (residual filter only)"}
+    for name, prec in (("fp64", P.PREC_FP64), ("fp32", P.PREC_FP32), ("bf16", P.PREC_BF16)):
+        prm = P.make_params(nw, b, p, method=P.METHOD_RCHFSI, filter_prec=prec, lambda_max=lmax,
+                            profile=1)
+        ctx = P.chfsi_create(P.hermitian_operator(A), P.hermitian_operator(B), dinv, prm,
+                             stream=stream, keep=(A, B, dinv))
+        P.chfsi_filter(ctx, X, lam, R, Y, *bounds)
+        torch.cuda.synchronize()
+        P.chfsi_filter_kernel_time(ctx)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            P.chfsi_filter(ctx, X, lam, R, Y, *bounds)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        kms, kn = P.chfsi_filter_kernel_time(ctx)
+        per = kms / max(kn, 1)
+        res[name] = {"filter_ms": round(ms, 3),
+                     "filter_tflops": round(step_flops * (p - 1) / (ms / 1e3) / 1e12, 1),
+                     "product_ms_per_launch": round(per, 4),
+                     "product_tflops": round(step_flops / (per / 1e3) / 1e12, 1)}
+        log("complex", name, res[name])
+        del ctx
+    for lo in ("fp32", "bf16"):
+        res[f"filter_speedup_{lo}_vs_fp64"] = round(res["fp64"]["filter_ms"] / res[lo]["filter_ms"], 3)
+    return res
 
 
 def bench_grid(args):
