@@ -23,8 +23,11 @@
  *    (X, resid, Yp of chfsi_filter) are interleaved complex -- (re, im) pairs
  *    of doubles, column-major, leading dimensions counted in complex
  *    elements -- while Ritz values and d_inv stay real.  Such a context runs
- *    the residual filter (Algorithm 3) in FP64, FP32 or BF16;
- *    chfsi_rayleigh_ritz and chfsi_solve return CHFSI_ERR_ARG for it.
+ *    the residual filter (Algorithm 3) in FP64, FP32 or BF16 and an FP64
+ *    Rayleigh-Ritz on the real embedding [[G_r, -G_i], [G_i, G_r]] of the
+ *    projected Hermitian pencil (no SVQB fallback: a singular Gram matrix is
+ *    CHFSI_ERR_NOT_SPD; Ritz values closer than 1e-8 relative that the
+ *    embedding cannot separate are CHFSI_ERR_NUMERIC).
  */
 #ifndef CHFSI_H_
 #define CHFSI_H_

@@ -107,6 +107,11 @@ struct chfsi_ctx {
   void* dinv2 = nullptr;
   void* Zt = nullptr;
   double* f64_c = nullptr;        // planar FP64 copy of the residual (complex FP64 filter)
+  // complex Rayleigh-Ritz: FP64 planar A and B, planar n x 2b blocks, the
+  // 2n x 2b right operand, the 2b x 2b rotation operand and pair selection
+  double *LA64 = nullptr, *LB64 = nullptr;
+  double *Ypl = nullptr, *AYpl = nullptr, *BYpl = nullptr, *Xpl = nullptr, *Rpl = nullptr;
+  double *Yt = nullptr, *Xt = nullptr, *Zx = nullptr, *wdup = nullptr;
   double* tri = nullptr;          // Cholesky / triangular-solve scratch
   float *f32_a = nullptr, *f32_b = nullptr, *f32_c = nullptr;     // RX, RY, Y copy (n x b)
   double *f64_a = nullptr, *f64_b = nullptr;                        // RX, RY (FP64 filter)
@@ -295,12 +300,27 @@ SizePlan plan_sizes_complex(const chfsi_operator* A, const chfsi_params* p) {
   size_t zt = size_t(2) * n * 2 * b * el;                              // Z~
   if (p->filter_prec == CHFSI_PREC_BF16) zt += size_t(2) * n * 2 * b * sizeof(uint16_t);
   s.coef = size_t(p->degree + 1) * 2 * b * sizeof(double);
+  // Rayleigh-Ritz on the 2b x 2b real embedding
+  const int64_t m = 2 * b;
+  s.blk = size_t(n) * b * 2 * sizeof(double);                          // one complex block
+  s.bb = size_t(m) * m * sizeof(double);
+  s.ws_eig = syev_workspace_bytes(m) + 256;
+  s.tri = tri_workspace_bytes(m, m);
+  size_t rr = size_t(n) * 2 * n * sizeof(double) * (p->filter_prec == CHFSI_PREC_FP64 ? 0 : 1) +
+              size_t(n) * 2 * n * sizeof(double) +                     // LA64 (FP32/BF16), LB64
+              5 * s.blk + size_t(2) * n * 2 * b * sizeof(double) +     // planar blocks, Y~
+              3 * s.blk + 12 * s.bb + 8 * m * sizeof(double);         // Xw, Yw, R, small
   size_t ws = p->filter_prec == CHFSI_PREC_FP64
                   ? std::max(plan_bytes<double>(n, 2 * b, 2 * n), size_t(16) * n * 2 * b * el)
                   : std::max(plan_bytes<float>(n, 2 * b, 2 * n), size_t(16) * n * 2 * b * el);
   if (p->filter_prec == CHFSI_PREC_BF16) ws = std::max(ws, gemm_bf16_workspace_bytes(n, 2 * b));
+  ws = std::max(ws, plan_bytes<double>(n, m, 2 * n));
+  ws = std::max(ws, plan_bytes<double>(m, m, n));
+  ws = std::max(ws, plan_bytes<double>(n, m, m));
+  ws = std::max(ws, plan_bytes<double>(m, m, m));
   s.ws = ws + 256;
-  s.total = s.a32 + 3 * s.f32blk + zt + 2 * s.coef + b * sizeof(double) + s.ws + 64;
+  s.total = s.a32 + 3 * s.f32blk + zt + 2 * s.coef + b * sizeof(double) + s.ws + 64 + rr +
+            s.ws_eig + s.tri;
   return s;
 }
 
@@ -1213,6 +1233,201 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
 }
 
 // ---------------------------------------------------------------------------
+// Rayleigh-Ritz for a complex Hermitian pencil (Section 4.3), on interleaved
+// complex blocks.  The projected pencil (Y^H A Y, Y^H B Y) is carried by its
+// real embedding M(G) = [[G_r, -G_i], [G_i, G_r]] (2b x 2b, real symmetric):
+// M(Ga) t = lambda M(Gb) t exactly when x = t(0:b) + i t(b:2b) solves
+// Ga x = lambda Gb x, so every Ritz value appears twice and each pair's
+// eigenspace is {x c : c complex}.  The real CholQR + Jacobi path runs on the
+// embedding unchanged; the first vector of each (ascending) pair gives the
+// complex Ritz vector.  Products use the planar real form: AY = L_A Y~,
+// Grams P = [Y_r Y_i]^T [W_r W_i], rotation X = [Y_r Y_i] X~.
+// ---------------------------------------------------------------------------
+chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, double* X,
+                                   int64_t ldx, double* R, int64_t ldr, double* ritz,
+                                   double* resnorm) {
+  const int64_t n = c->n, b = c->b, m = 2 * b;
+  hipStream_t st = c->stream;
+  CK(fill_zero(c->dflags, 4 * sizeof(int), st));
+  CK(cplx_to_planar(Y, ldy, n, b, c->Ypl, st));
+  CK(cplx_rhs<double>(c->Ypl, n, b, c->Yt, st));
+  auto product = [&](const double* L, double* out) -> chfsi_status {
+    GemmDesc<double> g;   // out (n x 2b planar) = L (n x 2n) Y~ (2n x 2b)
+    g.M = n;
+    g.N = m;
+    g.K = 2 * n;
+    g.A = L;
+    g.sak = 1;
+    g.sam = 2 * n;
+    g.B = c->Yt;
+    g.sbk = 1;
+    g.sbn = 2 * n;
+    g.C = out;
+    g.ldc = n;
+    CK(gemm<double>(g, st, c->ws));
+    return CHFSI_OK;
+  };
+  chfsi_status s;
+  if ((s = product(c->LA64, c->AYpl)) != CHFSI_OK) return s;
+  const double* BYpl = c->Ypl;
+  if (!c->B_identity) {
+    if ((s = product(c->LB64, c->BYpl)) != CHFSI_OK) return s;
+    BYpl = c->BYpl;
+  }
+  auto gram = [&](const double* W, double* G) -> chfsi_status {
+    GemmDesc<double> g;   // P (2b x 2b) = [Y_r Y_i]^T [W_r W_i], then the embedding
+    g.M = m;
+    g.N = m;
+    g.K = n;
+    g.A = c->Ypl;
+    g.sak = 1;
+    g.sam = n;
+    g.B = W;
+    g.sbk = 1;
+    g.sbn = n;
+    g.C = c->Tmp;
+    g.ldc = m;
+    CK(gemm<double>(g, st, c->ws));
+    CK(embed_gram(c->Tmp, b, G, st));
+    return CHFSI_OK;
+  };
+  if ((s = gram(c->AYpl, c->Ga)) != CHFSI_OK) return s;
+  if ((s = gram(BYpl, c->Gb)) != CHFSI_OK) return s;
+  // CholQR of the scaled embedded Gram matrix, projected matrix, Jacobi
+  CK(scale_gram(c->Gb, m, m, c->Gs, m, c->svec, c->dflags + 1, st));
+  CK(potrf_lower(c->Gs, m, m, c->dflags, st, c->ws, c->tri));
+  CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (c->h_flags[1] != 0 || c->h_flags[0] != 0) {
+    set_error("Gram matrix Y^H B Y is not positive definite (complex blocks have no SVQB "
+              "fallback)");
+    return CHFSI_ERR_NOT_SPD;
+  }
+  CK(set_identity(c->Linv, m, m, st));
+  CK(trsm_lower_left(c->Gs, m, c->Linv, m, m, m, st, c->ws, c->tri, true));
+  CK(scale_sym(c->Ga, m, m, c->svec, c->Hp, m, st));
+  {
+    GemmDesc<double> g;   // Tmp = Linv Hp
+    g.M = m;
+    g.N = m;
+    g.K = m;
+    g.A = c->Linv;
+    g.sam = 1;
+    g.sak = m;
+    g.B = c->Hp;
+    g.sbk = 1;
+    g.sbn = m;
+    g.C = c->Tmp;
+    g.ldc = m;
+    CK(gemm<double>(g, st, c->ws));
+    GemmDesc<double> h;   // Hp = Tmp Linv^T
+    h.M = m;
+    h.N = m;
+    h.K = m;
+    h.A = c->Tmp;
+    h.sam = 1;
+    h.sak = m;
+    h.B = c->Linv;
+    h.sbn = 1;
+    h.sbk = m;
+    h.C = c->Hp;
+    h.ldc = m;
+    CK(gemm<double>(h, st, c->ws));
+  }
+  CK(symmetrize(c->Hp, m, m, st));
+  int sweeps = 0;
+  CK(syev_jacobi(c->Hp, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps));
+  c->last_sweeps += sweeps;
+  {
+    GemmDesc<double> g;   // T = diag(s) Linv^T E
+    g.M = m;
+    g.N = m;
+    g.K = m;
+    g.A = c->Linv;
+    g.sak = 1;
+    g.sam = m;
+    g.B = c->E;
+    g.sbk = 1;
+    g.sbn = m;
+    g.C = c->T;
+    g.ldc = m;
+    g.epi.rowscale = c->svec;
+    CK(gemm<double>(g, st, c->ws));
+  }
+  // the embedded eigenvalues come in equal pairs; Ritz value j is pair j
+  CK(hipMemcpyAsync(c->h_w, c->w, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  double scale = 0.0, split = 0.0;
+  for (int64_t j = 0; j < m; ++j) scale = std::max(scale, std::fabs(c->h_w[j]));
+  for (int64_t j = 0; j < b; ++j)
+    split = std::max(split, std::fabs(c->h_w[2 * j + 1] - c->h_w[2 * j]));
+  if (!(split <= 1e-8 * std::max(scale, 1e-300))) {
+    set_error("embedded Ritz values are not paired (split %.3e of %.3e): nearly equal complex "
+              "Ritz values are not separated",
+              split, scale);
+    return CHFSI_ERR_NUMERIC;
+  }
+  std::vector<double> lam(b), dup(m);
+  for (int64_t j = 0; j < b; ++j) {
+    lam[j] = c->h_w[2 * j];
+    dup[j] = dup[b + j] = lam[j];
+  }
+  CK(hipEventSynchronize(c->ev_stage));
+  std::memcpy(c->h_stage, dup.data(), m * sizeof(double));
+  CK(hipMemcpyAsync(c->wdup, c->h_stage, m * sizeof(double), hipMemcpyHostToDevice, st));
+  CK(hipEventRecord(c->ev_stage, st));
+  // X~ = [[x_r, x_i], [-x_i, x_r]] (2b x 2b) from the selected complex vectors
+  CK(select_pairs(c->T, b, c->Zx, st));
+  CK(cplx_rhs<double>(c->Zx, b, b, c->Xt, st));
+  auto rotate = [&](const double* Src, const double* Tmat, double* Dst, double alpha,
+                    const double* accum) -> chfsi_status {
+    GemmDesc<double> g;   // Dst (n x 2b planar) = alpha Src (n x 2b planar) Tmat (2b x 2b)
+    g.M = n;
+    g.N = m;
+    g.K = m;
+    g.A = Src;
+    g.sam = 1;
+    g.sak = n;
+    g.B = Tmat;
+    g.sbk = 1;
+    g.sbn = m;
+    g.C = Dst;
+    g.ldc = n;
+    g.epi.alpha = alpha;
+    if (accum) {
+      g.epi.beta = 1.0;
+      g.epi.C1 = accum;
+      g.epi.ldc1 = n;
+    }
+    CK(gemm<double>(g, st, c->ws));
+    return CHFSI_OK;
+  };
+  if ((s = rotate(c->Ypl, c->Xt, c->Xpl, 1.0, nullptr)) != CHFSI_OK) return s;
+  if ((s = rotate(c->AYpl, c->Xt, c->Rpl, 1.0, nullptr)) != CHFSI_OK) return s;
+  CK(copy_block(c->Xt, m, c->TL, m, m, m, st));
+  CK(scale_columns(c->TL, m, m, m, c->wdup, st));
+  if ((s = rotate(BYpl, c->TL, c->Rpl, -1.0, c->Rpl)) != CHFSI_OK) return s;
+  // residual norms: r_j^2 = ||Re R_j||^2 + ||Im R_j||^2
+  CK(column_norms(c->Rpl, n, n, m, c->norms, st));
+  CK(check_finite(c->wdup, m, c->dflags + 2, st));
+  CK(check_finite(c->norms, m, c->dflags + 2, st));
+  CK(planar_to_cplx(c->Xpl, n, b, X, ldx, st));
+  CK(planar_to_cplx(c->Rpl, n, b, R, ldr, st));
+  CK(hipMemcpyAsync(c->h_norms, c->norms, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (c->h_flags[2] != 0) {
+    set_error("non-finite Ritz value or residual norm");
+    return CHFSI_ERR_NUMERIC;
+  }
+  for (int64_t j = 0; j < b; ++j) {
+    ritz[j] = lam[j];
+    resnorm[j] = std::sqrt(c->h_norms[j] * c->h_norms[j] + c->h_norms[b + j] * c->h_norms[b + j]);
+  }
+  return CHFSI_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Slab-wise Rayleigh-Ritz (memory_mode 1): the same algebra as rayleigh_ritz,
 // with A Y and B Y materialised one z-slab at a time.  X is rotated in place.
 // ---------------------------------------------------------------------------
@@ -1540,6 +1755,39 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     c->h_coef64.assign(size_t(params->degree) * 2 * b, 0.0);
     c->ws.bytes = sp.ws;
     c->ws.ptr = ctx_alloc<char>(c, sp.ws, &st);
+    // Rayleigh-Ritz (FP64) on the real embedding of the 2b x 2b projected pencil
+    const int64_t m = 2 * b;
+    c->LA64 = f64 ? static_cast<double*>(c->Lc)
+                  : ctx_alloc<double>(c, size_t(n) * 2 * n * sizeof(double), &st);
+    if (!c->B_identity) c->LB64 = ctx_alloc<double>(c, size_t(n) * 2 * n * sizeof(double), &st);
+    c->Ypl = ctx_alloc<double>(c, sp.blk, &st);
+    c->AYpl = ctx_alloc<double>(c, sp.blk, &st);
+    c->BYpl = c->B_identity ? nullptr : ctx_alloc<double>(c, sp.blk, &st);
+    c->Xpl = ctx_alloc<double>(c, sp.blk, &st);
+    c->Rpl = ctx_alloc<double>(c, sp.blk, &st);
+    c->Yt = ctx_alloc<double>(c, size_t(2) * n * m * sizeof(double), &st);
+    c->Xw = ctx_alloc<double>(c, sp.blk, &st);
+    c->Yw = ctx_alloc<double>(c, sp.blk, &st);
+    c->R = ctx_alloc<double>(c, sp.blk, &st);
+    c->Ga = ctx_alloc<double>(c, sp.bb, &st);
+    c->Gb = ctx_alloc<double>(c, sp.bb, &st);
+    c->Gs = ctx_alloc<double>(c, sp.bb, &st);
+    c->Linv = ctx_alloc<double>(c, sp.bb, &st);
+    c->Tmp = ctx_alloc<double>(c, sp.bb, &st);
+    c->Hp = ctx_alloc<double>(c, sp.bb, &st);
+    c->E = ctx_alloc<double>(c, sp.bb, &st);
+    c->T = ctx_alloc<double>(c, sp.bb, &st);
+    c->TL = ctx_alloc<double>(c, sp.bb, &st);
+    c->Xt = ctx_alloc<double>(c, sp.bb, &st);
+    c->Zx = ctx_alloc<double>(c, sp.bb, &st);
+    c->svec = ctx_alloc<double>(c, m * sizeof(double), &st);
+    c->w = ctx_alloc<double>(c, m * sizeof(double), &st);
+    c->norms = ctx_alloc<double>(c, m * sizeof(double), &st);
+    c->wdup = ctx_alloc<double>(c, m * sizeof(double), &st);
+    c->dflags = ctx_alloc<int>(c, 64, &st);
+    c->tri = ctx_alloc<double>(c, sp.tri, &st);
+    c->ws_eig.bytes = sp.ws_eig;
+    c->ws_eig.ptr = ctx_alloc<char>(c, sp.ws_eig, &st);
   } else if (params->filter_prec == CHFSI_PREC_FP32) {
     if (dense) c->A32 = ctx_alloc<float>(c, size_t(n) * n * sizeof(float), &st);
     if (dense || d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
@@ -1608,8 +1856,9 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   }
   c->h_stage_bytes = b * sizeof(double) + size_t(params->degree) * (c->cplx ? 2 : 1) * b *
                                                 sizeof(double) + 64;
-  if (hipHostMalloc(&c->h_w, b * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(&c->h_norms, b * sizeof(double)) != hipSuccess ||
+  const int64_t hb = c->cplx ? 2 * b : b;
+  if (hipHostMalloc(&c->h_w, hb * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&c->h_norms, hb * sizeof(double)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_flags), 64) != hipSuccess ||
       hipHostMalloc(&c->h_stage, c->h_stage_bytes) != hipSuccess) {
     set_error("pinned host allocation failed");
@@ -1641,16 +1890,18 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   // precision-converted operator copies (owned)
   hipError_t e = hipSuccess;
   if (c->cplx) {
-    if (params->filter_prec == CHFSI_PREC_FP64) {
-      e = herm_to_planar<double>(A->dense, A->ld, n, static_cast<double*>(c->Lc), c->stream);
-      if (e == hipSuccess) e = dup_dinv<double>(d_inv, n, static_cast<double*>(c->dinv2), c->stream);
-    } else {
-      if (params->filter_prec == CHFSI_PREC_BF16)
-        e = herm_to_planar<uint16_t>(A->dense, A->ld, n, static_cast<uint16_t*>(c->Lc), c->stream);
-      else
-        e = herm_to_planar<float>(A->dense, A->ld, n, static_cast<float*>(c->Lc), c->stream);
-      if (e == hipSuccess) e = dup_dinv<float>(d_inv, n, static_cast<float*>(c->dinv2), c->stream);
-    }
+    // FP64 planar A (Rayleigh-Ritz; also the FP64 filter's operand) and B
+    e = herm_to_planar<double>(A->dense, A->ld, n, c->LA64, c->stream);
+    if (e == hipSuccess && c->LB64) e = herm_to_planar<double>(B->dense, B->ld, n, c->LB64, c->stream);
+    // the filter's operand in its precision, and [d; d]
+    if (e == hipSuccess && params->filter_prec == CHFSI_PREC_FP64)
+      e = dup_dinv<double>(d_inv, n, static_cast<double*>(c->dinv2), c->stream);
+    if (e == hipSuccess && params->filter_prec == CHFSI_PREC_FP32)
+      e = herm_to_planar<float>(A->dense, A->ld, n, static_cast<float*>(c->Lc), c->stream);
+    if (e == hipSuccess && params->filter_prec == CHFSI_PREC_BF16)
+      e = herm_to_planar<uint16_t>(A->dense, A->ld, n, static_cast<uint16_t*>(c->Lc), c->stream);
+    if (e == hipSuccess && params->filter_prec != CHFSI_PREC_FP64)
+      e = dup_dinv<float>(d_inv, n, static_cast<float*>(c->dinv2), c->stream);
   }
   if (c->A32) e = convert_f64_f32(A->dense, A->ld, c->A32, n, n, n, c->stream);
   if (e == hipSuccess && c->A16) e = convert_f64_bf16(A->dense, A->ld, c->A16, n, n, n, c->stream);
@@ -1729,13 +1980,17 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, dou
     set_error("null argument");
     return CHFSI_ERR_ARG;
   }
-  if (c->cplx) {
-    set_error("Rayleigh-Ritz is not implemented for complex Hermitian operators (filter only)");
-    return CHFSI_ERR_ARG;
-  }
   if (ldy < c->n || ldx < c->n || ldr < c->n) {
     set_error("leading dimensions must be >= n");
     return CHFSI_ERR_ARG;
+  }
+  if (c->cplx) {
+    if (X == Y) {
+      set_error("X must not alias Y");
+      return CHFSI_ERR_ARG;
+    }
+    c->last_sweeps = 0;
+    return rayleigh_ritz_complex(c, Y, ldy, X, ldx, R, ldr, ritz, resnorm);
   }
   if (X == Y && c->prm.memory_mode != 1) {
     set_error("X must not alias Y");
@@ -1756,10 +2011,6 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
     set_error("null argument");
     return CHFSI_ERR_ARG;
   }
-  if (c->cplx) {
-    set_error("chfsi_solve is not implemented for complex Hermitian operators (filter only)");
-    return CHFSI_ERR_ARG;
-  }
   if (ldx < c->n) {
     set_error("ldx must be >= n");
     return CHFSI_ERR_ARG;
@@ -1769,7 +2020,10 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   chfsi_report local{};
   chfsi_report& r = rep ? *rep : local;
   std::memset(&r, 0, sizeof(r));
-  if (c->prm.init_random) CK(fill_gaussian(X, ldx, n, b, c->prm.seed, c->stream));
+  // complex contexts: interleaved blocks are 2n x b real arrays for fills and copies
+  const int64_t rows = c->cplx ? 2 * n : n, lds = c->cplx ? 2 * ldx : ldx,
+                ldn = c->cplx ? 2 * n : n;
+  if (c->prm.init_random) CK(fill_gaussian(X, lds, rows, b, c->prm.seed, c->stream));
   std::vector<double> ritz(b), norms(b);
   float ms = 0.0f;
   CK(hipEventRecord(c->ev[2], c->stream));
@@ -1777,9 +2031,10 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   const bool slabs = c->prm.memory_mode == 1;
   double* Xw = slabs ? X : c->Xw;            // working Ritz block
   const int64_t ldw = slabs ? ldx : n;
-  chfsi_status st = slabs ? rayleigh_ritz_slabs(c, X, ldx, c->R, n, ritz.data(), norms.data(), true)
-                          : rayleigh_ritz(c, X, ldx, c->Xw, n, c->R, n, ritz.data(), norms.data(),
-                                          true);
+  chfsi_status st =
+      c->cplx ? rayleigh_ritz_complex(c, X, ldx, c->Xw, n, c->R, n, ritz.data(), norms.data())
+      : slabs ? rayleigh_ritz_slabs(c, X, ldx, c->R, n, ritz.data(), norms.data(), true)
+              : rayleigh_ritz(c, X, ldx, c->Xw, n, c->R, n, ritz.data(), norms.data(), true);
   if (st != CHFSI_OK) return st;
   CK(hipEventRecord(c->ev[3], c->stream));
   CK(hipEventSynchronize(c->ev[3]));
@@ -1809,7 +2064,10 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
       break;
     }
     CK(hipEventRecord(c->ev[0], c->stream));
-    if (c->prm.method == CHFSI_METHOD_RCHFSI)
+    if (c->cplx)
+      st = filter_rchfsi_complex(c, c->Xw, n, ritz.data(), c->R, n, c->Yw, n, lmin, lmax, lT,
+                                 c->prm.degree, &r.filter_flops);
+    else if (c->prm.method == CHFSI_METHOD_RCHFSI)
       st = filter_rchfsi(c, Xw, ldw, ritz.data(), c->R, n, slabs ? Xw : c->Yw, slabs ? ldw : n,
                          lmin, lmax, lT, c->prm.degree, &r.filter_flops);
     else
@@ -1817,8 +2075,10 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
     if (st != CHFSI_OK) break;
     CK(hipEventRecord(c->ev[1], c->stream));
     c->last_sweeps = 0;
-    st = slabs ? rayleigh_ritz_slabs(c, Xw, ldw, c->R, n, ritz.data(), norms.data(), true)
-               : rayleigh_ritz(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(), norms.data(), true);
+    st = c->cplx ? rayleigh_ritz_complex(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(),
+                                         norms.data())
+         : slabs ? rayleigh_ritz_slabs(c, Xw, ldw, c->R, n, ritz.data(), norms.data(), true)
+                 : rayleigh_ritz(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(), norms.data(), true);
     if (st != CHFSI_OK) break;
     CK(hipEventRecord(c->ev[3], c->stream));
     CK(hipEventSynchronize(c->ev[3]));
@@ -1845,7 +2105,7 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   r.converged = mr < c->prm.tol;
   r.flags = c->flags;
   if (st != CHFSI_OK && st != CHFSI_ERR_NOCONV) return st;
-  if (!slabs) CK(copy_block(c->Xw, n, X, ldx, n, b, c->stream));
+  if (!slabs) CK(copy_block(c->Xw, ldn, X, lds, rows, b, c->stream));
   CK(hipStreamSynchronize(c->stream));
   std::memcpy(evals, ritz.data(), b * sizeof(double));
   std::memcpy(resnorms, norms.data(), b * sizeof(double));

@@ -125,7 +125,87 @@ __global__ __launch_bounds__(kThreads) void k_crecon(const F* __restrict__ RY,
   }
 }
 
+// planar P (n x 2b, ld n) from interleaved Z (ld ldz), and back
+__global__ __launch_bounds__(kThreads) void k_to_planar(const double* __restrict__ Z, int64_t ldz,
+                                                        int64_t n, int64_t b,
+                                                        double* __restrict__ P) {
+  const int64_t total = n * b;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / n, i = idx - j * n;
+    P[i + j * n] = Z[2 * (i + j * ldz)];
+    P[i + (b + j) * n] = Z[2 * (i + j * ldz) + 1];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_from_planar(const double* __restrict__ P, int64_t n,
+                                                          int64_t b, double* __restrict__ Z,
+                                                          int64_t ldz) {
+  const int64_t total = n * b;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / n, i = idx - j * n;
+    Z[2 * (i + j * ldz)] = P[i + j * n];
+    Z[2 * (i + j * ldz) + 1] = P[i + (b + j) * n];
+  }
+}
+
+// The real embedding M(G) = [[G_r, -G_i], [G_i, G_r]] (2b x 2b, ld 2b) of
+// G = Y^H W from P = [Y_r Y_i]^T [W_r W_i] (2b x 2b, ld 2b):
+// G_r = P11 + P22, G_i = P12 - P21; symmetrised, (M + M^T) / 2.
+__global__ __launch_bounds__(kThreads) void k_embed_gram(const double* __restrict__ P, int64_t b,
+                                                         double* __restrict__ M) {
+  const int64_t m = 2 * b, total = m * m;
+  auto emb = [&](int64_t r, int64_t c) {
+    const int64_t i = r % b, j = c % b;
+    const double gr = P[i + j * m] + P[(b + i) + (b + j) * m];
+    const double gi = P[i + (b + j) * m] - P[(b + i) + j * m];
+    const bool top = r < b, left = c < b;
+    return top == left ? gr : (top ? -gi : gi);
+  };
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t c = idx / m, r = idx - c * m;
+    M[r + c * m] = 0.5 * (emb(r, c) + emb(c, r));
+  }
+}
+
+// planar b x b complex matrix Zx (b x 2b, ld b) from the first vector of each
+// eigenvalue pair of the embedded problem: x_j = T(0:b, 2j) + i T(b:2b, 2j)
+__global__ __launch_bounds__(kThreads) void k_select_pairs(const double* __restrict__ T, int64_t b,
+                                                           double* __restrict__ Zx) {
+  const int64_t m = 2 * b, total = b * b;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / b, i = idx - j * b;
+    Zx[i + j * b] = T[i + (2 * j) * m];
+    Zx[i + (b + j) * b] = T[(b + i) + (2 * j) * m];
+  }
+}
+
 }  // namespace
+
+hipError_t cplx_to_planar(const double* Z, int64_t ldz, int64_t n, int64_t b, double* P,
+                          hipStream_t st) {
+  k_to_planar<<<grid_for(n * b), kThreads, 0, st>>>(Z, ldz, n, b, P);
+  return hipGetLastError();
+}
+
+hipError_t planar_to_cplx(const double* P, int64_t n, int64_t b, double* Z, int64_t ldz,
+                          hipStream_t st) {
+  k_from_planar<<<grid_for(n * b), kThreads, 0, st>>>(P, n, b, Z, ldz);
+  return hipGetLastError();
+}
+
+hipError_t embed_gram(const double* P, int64_t b, double* M, hipStream_t st) {
+  k_embed_gram<<<grid_for(4 * b * b), kThreads, 0, st>>>(P, b, M);
+  return hipGetLastError();
+}
+
+hipError_t select_pairs(const double* T, int64_t b, double* Zx, hipStream_t st) {
+  k_select_pairs<<<grid_for(b * b), kThreads, 0, st>>>(T, b, Zx);
+  return hipGetLastError();
+}
 
 template <typename F>
 hipError_t herm_to_planar(const double* A, int64_t lda, int64_t n, F* L, hipStream_t st) {

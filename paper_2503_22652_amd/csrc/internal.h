@@ -117,6 +117,18 @@ hipError_t cplx_reconstruct(const F* RY, const double* dinv, const double* X, in
                             const double* lamY, double* Yp, int64_t ldy, int64_t n, int64_t b,
                             hipStream_t st);
 
+// planar P (n x 2b, ld n) <-> interleaved Z (n x b, ld ldz)
+hipError_t cplx_to_planar(const double* Z, int64_t ldz, int64_t n, int64_t b, double* P,
+                          hipStream_t st);
+hipError_t planar_to_cplx(const double* P, int64_t n, int64_t b, double* Z, int64_t ldz,
+                          hipStream_t st);
+// M (2b x 2b, ld 2b) = symmetrised real embedding [[G_r, -G_i], [G_i, G_r]] of
+// G = Y^H W, from P = [Y_r Y_i]^T [W_r W_i] (2b x 2b, ld 2b)
+hipError_t embed_gram(const double* P, int64_t b, double* M, hipStream_t st);
+// Zx (b x 2b planar, ld b): column j = T(0:b, 2j), column b+j = T(b:2b, 2j)
+// of the 2b x 2b eigenvector matrix T of an embedded problem
+hipError_t select_pairs(const double* T, int64_t b, double* Zx, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Elementwise / reduction kernels (blas1.hip)
 // ---------------------------------------------------------------------------

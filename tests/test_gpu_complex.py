@@ -6,9 +6,11 @@ The pencil is the complex counterpart of the dense generalized workload
 diagonal approximate inverse D^{-1}) at a ragged size (N = 701, block 40: no
 tile divides either).  FP64 filters match the oracle to 1e-11 relative; FP32
 and bfloat16 products have an error bounded by the residual part they carry
-(Theorem 3.4), with the bounds of the real dense tests.  A solve that runs
-the GPU filter inside Algorithm 1 (with the oracle's complex Rayleigh-Ritz)
-reaches LAPACK's eigenvalues of the Hermitian pencil.
+(Theorem 3.4), with the bounds of the real dense tests.  The GPU
+Rayleigh-Ritz (on the real embedding of the projected Hermitian pencil)
+matches the oracle's Ritz values to 1e-11; full solves, with the GPU filter
+inside the oracle's Algorithm 1 and entirely on the GPU through chfsi_solve,
+reach LAPACK's eigenvalues of the Hermitian pencil.
 """
 import numpy as np
 import pytest
@@ -94,15 +96,50 @@ def test_complex_solve_with_gpu_filter(prec):
     assert np.max(np.abs(o["lam"][:32] - w)) <= 1e-10 * np.max(np.abs(w))
 
 
-def test_complex_context_limits(herm):
+def test_complex_rayleigh_ritz_matches_oracle(herm):
+    """Rayleigh-Ritz on the real embedding of the projected Hermitian pencil."""
     p, lmax = herm
     ctx = _ctx(p, P.PREC_FP32, lmax, 8)
+    Yh = wl.random_block_complex(p.n, p.block, 6)
     X = P.colmajor_empty_complex(p.n, p.block)
-    with pytest.raises(RuntimeError, match="complex"):
-        P.chfsi_rayleigh_ritz(ctx, X, P.colmajor_empty_complex(p.n, p.block),
-                              P.colmajor_empty_complex(p.n, p.block))
-    with pytest.raises(RuntimeError, match="complex"):
-        P.chfsi_solve(ctx, X)
+    R = P.colmajor_empty_complex(p.n, p.block)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor_complex(Yh), X, R)
+    o = rr.rayleigh_ritz(Yh, filters.dense_op(p.A), filters.dense_op(p.B))
+    lam = np.array(ritz)
+    scale = np.max(np.abs(o["lam"]))
+    assert np.max(np.abs(lam - o["lam"])) <= 1e-11 * scale
+    Xg, Rg = X.cpu().numpy(), R.cpu().numpy()
+    assert np.linalg.norm(Xg.conj().T @ p.B @ Xg - np.eye(p.block)) <= 1e-10
+    Rref = p.A @ Xg - p.B @ Xg * lam[None, :]
+    assert np.linalg.norm(Rg - Rref) <= 1e-10 * np.linalg.norm(p.A, 2)
+    assert np.allclose(norms, np.linalg.norm(Rref, axis=0), rtol=1e-8, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", [P.PREC_FP64, P.PREC_FP32, P.PREC_BF16])
+def test_complex_solve_on_gpu(prec):
+    """Algorithm 1 entirely on the GPU (filter, Rayleigh-Ritz, residuals)."""
+    p = wl.dense_hermitian(n=1024, n_low=32, block=40, degree=16, seed=78)
+    lmax = 10.0 / (0.95 * p.meta["dmin"]) + 0.1
+    w = sla.eigh(p.A, p.B, eigvals_only=True, subset_by_index=(0, 31))
+    A = P.to_colmajor_complex(p.A)
+    B = P.to_colmajor_complex(p.B)
+    d = torch.from_numpy(p.dinv).cuda()
+    prm = P.make_params(32, 40, 16, max_iter=40, tol=1e-10, method=P.METHOD_RCHFSI,
+                        filter_prec=prec, lambda_max=lmax)
+    ctx = P.chfsi_create(P.hermitian_operator(A), P.hermitian_operator(B), d, prm, keep=(A, B, d))
+    X = P.to_colmajor_complex(wl.random_block_complex(p.n, p.block, 9))
+    st, ev, rn, rep = P.chfsi_solve(ctx, X)
+    print("complex GPU solve prec", prec, rep["iterations"], "iterations, max residual",
+          rep["max_residual"])
+    assert st == P.OK and rep["converged"]
+    assert np.max(np.abs(np.array(ev[:32]) - w)) <= 1e-10 * np.max(np.abs(w))
+    Xg = X.cpu().numpy()[:, :32]
+    res = np.linalg.norm(p.A @ Xg - p.B @ Xg * np.array(ev[:32])[None, :], axis=0)
+    assert np.max(res) < 1e-9
+
+
+def test_complex_context_limits(herm):
+    p, lmax = herm
     A = P.to_colmajor_complex(p.A)
     prm = P.make_params(p.n_wanted, p.block, 8, method=P.METHOD_CHFSI, filter_prec=P.PREC_FP64,
                         lambda_max=lmax)
