@@ -279,9 +279,10 @@ def main():
 
 
 def complex_filter_rates(P, n, b, nw, p, stream):
-    """Residual filter of the complex Hermitian counterpart of the dense workload
-    (device-built: complex reflectors, complex Hermitian S, real D): one pass
-    of degree p in FP64, FP32 and BF16 products; 8 n^2 b flops per step."""
+    """Complex Hermitian counterpart of the dense workload (device-built: complex
+    reflectors, complex Hermitian S, real D): one residual-filter pass of degree
+    p in FP64, FP32 and BF16 products (8 n^2 b flops per step), and the time to
+    max residual 1e-8 of full solves in each."""
     import numpy as np
     import torch
     from workloads.gpu import hermitian_problem
@@ -298,8 +299,8 @@ def complex_filter_rates(P, n, b, nw, p, stream):
     bounds = (lam[0] - 0.05 * (lam[-1] - lam[0]), lmax, lam[-1])
     Y = P.colmajor_empty_complex(n, b)
     step_flops = 8.0 * n * n * b
-    res = {"workload": f"complex Hermitian A x = lambda B x, N={n}, block {b}, degree {p}, "
-                       f"||D^-1 eps S||_2=0.05 (residual filter only)"}
+    res = {"workload": f"complex Hermitian A x = lambda B x, N={n}, block {b}, {nw} wanted, "
+                       f"degree {p}, ||D^-1 eps S||_2=0.05"}
     for name, prec in (("fp64", P.PREC_FP64), ("fp32", P.PREC_FP32), ("bf16", P.PREC_BF16)):
         prm = P.make_params(nw, b, p, method=P.METHOD_RCHFSI, filter_prec=prec, lambda_max=lmax,
                             profile=1)
@@ -326,6 +327,30 @@ def complex_filter_rates(P, n, b, nw, p, stream):
         del ctx
     for lo in ("fp32", "bf16"):
         res[f"filter_speedup_{lo}_vs_fp64"] = round(res["fp64"]["filter_ms"] / res[lo]["filter_ms"], 3)
+    # time to max residual 1e-8 over the nw wanted pairs, from one random start
+    X0 = torch.complex(torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g),
+                       torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g)).t()
+    ttr = {}
+    for name, prec in (("fp64", P.PREC_FP64), ("fp32", P.PREC_FP32), ("bf16", P.PREC_BF16)):
+        prm = P.make_params(nw, b, p, max_iter=60, tol=1e-8, method=P.METHOD_RCHFSI,
+                            filter_prec=prec, lambda_max=lmax)
+        ctx = P.chfsi_create(P.hermitian_operator(A), P.hermitian_operator(B), dinv, prm,
+                             stream=stream, keep=(A, B, dinv))
+        Xs = X0.t().clone().t()   # a fresh copy: the solve overwrites its block
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, ev, rn, rep = P.chfsi_solve(ctx, Xs)
+        dt = time.perf_counter() - t1
+        ttr[name] = {"status": P.STATUS_NAMES[st], "seconds": round(dt, 3),
+                     "iterations": rep["iterations"], "max_residual": rep["max_residual"],
+                     "filter_ms": round(rep["time_filter_ms"], 2),
+                     "rr_ms": round(rep["time_rr_ms"], 2)}
+        log("complex solve", name, ttr[name])
+        del ctx, Xs
+    for lo in ("fp32", "bf16"):
+        if ttr[lo]["status"] == "OK" and ttr["fp64"]["status"] == "OK":
+            ttr[f"speedup_{lo}_vs_fp64"] = round(ttr["fp64"]["seconds"] / ttr[lo]["seconds"], 3)
+    res["time_to_residual"] = ttr
     return res
 
 
