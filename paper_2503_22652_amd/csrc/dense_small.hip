@@ -222,19 +222,21 @@ __device__ __forceinline__ int pair_index(int l, int I, int J) {
 
 // One workgroup per pair of the round: gather the JP x JP subproblem, skip it
 // when already diagonal (to the threshold), else run `inner` Jacobi sweeps.
-// Writes U (JP x JP) and skip[pair] (1 = U is the identity).
-__global__ __launch_bounds__(256) void k_jacobi_pair_solve(const double* A, int64_t lda,
-                                                           int nblk, int round,
-                                                           const double* scale, double tol,
-                                                           double* U, int* skip, int* counter,
-                                                           int inner) {
+// Writes U (JP x JP) and skip[pair] (1 = U is the identity).  The rotation
+// rounds are latency-bound; 8 waves per subproblem measured fastest on
+// MI355X (whole Rayleigh-Ritz, N = 8192, b = 320: 12.2 ms with 512 threads,
+// 12.9 with 256, 22.2 with one wave; 1024 as 512).
+constexpr int kPairThreads = 512;
+__global__ __launch_bounds__(kPairThreads) void k_jacobi_pair_solve(
+    const double* A, int64_t lda, int nblk, int round, const double* scale, double tol, double* U,
+    int* skip, int* counter, int inner) {
   __shared__ double a[JP * LDJ];
   __shared__ double u[JP * LDJ];
-  __shared__ double red[256];
+  __shared__ double red[kPairThreads];
   int I, J;
   block_pair(blockIdx.x, round, nblk, &I, &J);
   double mx = 0.0;
-  for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+  for (int idx = threadIdx.x; idx < JP * JP; idx += kPairThreads) {
     const int i = idx % JP, j = idx / JP;
     const double v = A[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
     a[i + j * LDJ] = v;
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(256) void k_jacobi_pair_solve(const double* A, int6
   }
   red[threadIdx.x] = mx;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kPairThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(256) void k_jacobi_pair_solve(const double* A, int6
   }
   const int nrot = lds_jacobi(a, u, thresh, inner);
   double* Uo = U + int64_t(blockIdx.x) * JP * JP;
-  for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+  for (int idx = threadIdx.x; idx < JP * JP; idx += kPairThreads) {
     const int i = idx % JP, j = idx / JP;
     Uo[i + j * JP] = u[i + j * LDJ];
   }
@@ -626,7 +628,7 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   for (; sweeps < max_outer; ++sweeps) {
     if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
     for (int r = 0; r < nblk - 1; ++r) {
-      k_jacobi_pair_solve<<<dim3(npairs), 256, 0, st>>>(P, bp, nblk, r, scal, tol, U, skip,
+      k_jacobi_pair_solve<<<dim3(npairs), kPairThreads, 0, st>>>(P, bp, nblk, r, scal, tol, U, skip,
                                                         counter, inner);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       k_jacobi_apply_A<<<dim3(npairs, npairs), 256, 0, st>>>(P, bp, nblk, r, U, skip);

@@ -145,3 +145,39 @@ def test_complex_context_limits(herm):
                         lambda_max=lmax)
     with pytest.raises(RuntimeError, match="residual filter"):
         P.chfsi_create(P.hermitian_operator(A), None, None, prm, keep=(A,))
+
+
+def test_complex_standard_problem_padded_leading_dimensions():
+    """B = I (D^{-1} = I), blocks with padded leading dimensions, block 37."""
+    p = wl.dense_hermitian(n=517, n_low=30, block=37, degree=12, seed=81, generalized=False)
+    w = np.linalg.eigvalsh(p.A)[:30]
+    A = P.to_colmajor_complex(p.A)
+    prm = P.make_params(30, 37, 12, max_iter=60, tol=1e-10, method=P.METHOD_RCHFSI,
+                        filter_prec=P.PREC_FP32, lambda_max=10.1)
+    ctx = P.chfsi_create(P.hermitian_operator(A), None, None, prm, keep=(A,))
+    ld = 530
+    buf = torch.zeros((37, ld), dtype=torch.complex128, device="cuda")
+    X = buf.t()[:517]
+    X.copy_(P.to_colmajor_complex(wl.random_block_complex(517, 37, 12)))
+    assert X.stride(1) == ld
+    st, ev, rn, rep = P.chfsi_solve(ctx, X)
+    print("complex standard solve:", rep["iterations"], "iterations, max residual",
+          rep["max_residual"])
+    assert st == P.OK
+    assert np.max(np.abs(np.array(ev[:30]) - w)) <= 1e-10 * np.max(np.abs(w))
+    assert torch.all(buf.t()[517:] == 0)          # the padding rows are untouched
+    # the filter on padded blocks matches the oracle (D^{-1} = I)
+    o = rr.rayleigh_ritz(wl.random_block_complex(517, 37, 13), filters.dense_op(p.A),
+                         filters.identity_op())
+    lam = o["lam"]
+    bounds = (lam[0] - 0.05 * (lam[-1] - lam[0]), 10.1, lam[-1])
+    Xb = torch.zeros((37, ld), dtype=torch.complex128, device="cuda").t()[:517]
+    Rb = torch.zeros((37, ld), dtype=torch.complex128, device="cuda").t()[:517]
+    Yb = torch.zeros((37, ld), dtype=torch.complex128, device="cuda").t()[:517]
+    Xb.copy_(P.to_colmajor_complex(o["X"]))
+    Rb.copy_(P.to_colmajor_complex(o["R"]))
+    P.chfsi_filter(ctx, Xb, lam, Rb, Yb, *bounds, degree=12)
+    torch.cuda.synchronize()
+    ref, RYp, _ = filters.residual_filter(filters.dense_op(p.A), filters.identity_op(), o["X"], lam,
+                                          o["R"], 12, *bounds, return_parts=True)
+    assert np.linalg.norm(Yb.cpu().numpy() - ref) <= 1e-4 * np.linalg.norm(RYp)
