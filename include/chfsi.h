@@ -19,7 +19,8 @@
  *    buffers are left untouched except where a function says otherwise, and a
  *    message is available from chfsi_last_error() (thread-local).
  *  - Complex Hermitian problems (the paper's Section 4.3): an operator of
- *    kind CHFSI_OP_DENSE_HERMITIAN makes a complex context.  Its blocks
+ *    kind CHFSI_OP_DENSE_HERMITIAN or CHFSI_OP_STENCIL27_BLOCH makes a
+ *    complex context.  Its blocks
  *    (X, resid, Yp of chfsi_filter) are interleaved complex -- (re, im) pairs
  *    of doubles, column-major, leading dimensions counted in complex
  *    elements -- while Ritz values and d_inv stay real.  Such a context runs
@@ -57,7 +58,8 @@ typedef enum {
   CHFSI_OP_IDENTITY = 0,        /* B = I (standard problem) */
   CHFSI_OP_DENSE = 1,           /* dense symmetric matrix in device memory */
   CHFSI_OP_STENCIL27 = 2,       /* periodic 27-point grid operator (see chfsi_operator) */
-  CHFSI_OP_DENSE_HERMITIAN = 3  /* dense complex Hermitian matrix (Section 4.3; see below) */
+  CHFSI_OP_DENSE_HERMITIAN = 3, /* dense complex Hermitian matrix (Section 4.3; see below) */
+  CHFSI_OP_STENCIL27_BLOCH = 4  /* grid operator with Bloch phases, complex (Section 4.3) */
 } chfsi_op_kind;
 
 /* Storage / arithmetic precision of the filter's bulk work (the residual
@@ -93,6 +95,19 @@ typedef enum { CHFSI_METHOD_CHFSI = 0, CHFSI_METHOD_RCHFSI = 1 } chfsi_method;
  *    {-1,0,1}^3.  field_mode 0: no potential; 1: diag(V) z; 2: the
  *    mass-weighted 1/2 (diag(V) M + M diag(V)) z with M given by coef_mass.
  *    `field` (device, length n) holds V; borrowed.
+ *  kind = CHFSI_OP_STENCIL27_BLOCH: the grid operator above on cell-periodic
+ *    complex vectors at wave vector k = (bloch[0], bloch[1], bloch[2]) (kx,
+ *    ky, kz in radians per grid step): the coefficient of offset (dx,dy,dz)
+ *    is multiplied by exp(i (kx dx + ky dy + kz dz)), in S and in the mass
+ *    stencil of field_mode 2 alike; field_mode 1 is unchanged.  The result
+ *    is Hermitian (the k-point problems of Section 4.3 on a grid).  It makes
+ *    a complex context like CHFSI_OP_DENSE_HERMITIAN (interleaved blocks,
+ *    the residual filter only, memory_mode 0, FP64/FP32/BF16 filter); B is
+ *    NULL / the identity or of this kind on A's grid with the same k and
+ *    field_mode 0; block <= 65535.  The context runs in the frame twisted
+ *    by D = diag(exp(i k.r)): the real z-marching kernels on the planar real
+ *    and imaginary parts plus a correction at the boundary points for the
+ *    phase of wrapped neighbours.  bloch[] is ignored for other kinds.
  */
 typedef struct {
   int32_t kind;
@@ -104,6 +119,7 @@ typedef struct {
   double coef_mass[27];
   const double* field;
   int32_t field_mode;
+  double bloch[3];
 } chfsi_operator;
 
 /* Solver parameters (Algorithm 1 inputs: n, p, bounds, tau). */
@@ -258,8 +274,10 @@ typedef struct {
   chfsi_params params;
   int64_t seq_id;           /* sequence id for warm starts; < 0: independent request */
   const double* X0;         /* device n x b start block (ld n) when the sequence has none;
-                               NULL: random start from params.seed */
-  double* X_out;            /* optional device n x b (ld n) output of the Ritz vectors */
+                               NULL: random start from params.seed; interleaved complex
+                               (2 n b doubles) for a complex A */
+  double* X_out;            /* optional device n x b (ld n) output of the Ritz vectors,
+                               interleaved complex for a complex A */
 } chfsi_request;
 
 typedef struct {

@@ -23,7 +23,7 @@ OK, ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_NOT_SPD, ERR_NOCONV, ERR_NUMERIC, ERR_BU
     ERR_CANCELLED, ERR_TIMEOUT = range(10)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_NOMEM", "ERR_DEVICE", "ERR_NOT_SPD", "ERR_NOCONV",
                 "ERR_NUMERIC", "ERR_BUSY", "ERR_CANCELLED", "ERR_TIMEOUT"]
-OP_IDENTITY, OP_DENSE, OP_STENCIL27, OP_DENSE_HERMITIAN = 0, 1, 2, 3
+OP_IDENTITY, OP_DENSE, OP_STENCIL27, OP_DENSE_HERMITIAN, OP_STENCIL27_BLOCH = 0, 1, 2, 3, 4
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 METHOD_CHFSI, METHOD_RCHFSI = 0, 1
 MAX_HISTORY = 512
@@ -33,7 +33,7 @@ class chfsi_operator(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int64), ("dense", C.c_void_p), ("ld", C.c_int64),
                 ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("coef", C.c_double * 27), ("coef_mass", C.c_double * 27),
-                ("field", C.c_void_p), ("field_mode", C.c_int32)]
+                ("field", C.c_void_p), ("field_mode", C.c_int32), ("bloch", C.c_double * 3)]
 
 
 class chfsi_params(C.Structure):
@@ -184,11 +184,17 @@ def identity_operator(n: int) -> chfsi_operator:
     return op
 
 
-def stencil_operator(shape, coef, coef_mass=None, field=None, field_mode: int = 0) -> chfsi_operator:
-    """Periodic 27-point operator; shape = (nz, ny, nx); coef indexed [dz+1][dy+1][dx+1]."""
+def stencil_operator(shape, coef, coef_mass=None, field=None, field_mode: int = 0,
+                     bloch=None) -> chfsi_operator:
+    """Periodic 27-point operator; shape = (nz, ny, nx); coef indexed [dz+1][dy+1][dx+1].
+    With bloch = (kx, ky, kz) the operator acts on complex vectors with the
+    Bloch phase exp(i k.o) on every offset o (kind OP_STENCIL27_BLOCH)."""
     nz, ny, nx = shape
     op = chfsi_operator()
-    op.kind = OP_STENCIL27
+    op.kind = OP_STENCIL27 if bloch is None else OP_STENCIL27_BLOCH
+    if bloch is not None:
+        for i in range(3):
+            op.bloch[i] = float(bloch[i])
     op.n = nx * ny * nz
     op.nx, op.ny, op.nz = nx, ny, nz
     flat = [float(v) for v in _flat27(coef)]

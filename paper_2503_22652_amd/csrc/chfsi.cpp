@@ -103,6 +103,7 @@ struct chfsi_ctx {
   // L = [A_r | A_i] (n x 2n, filter precision), [d; d], the materialised right
   // operand Z~ (2n x 2b, FP32/FP64) and its bfloat16 copy (BF16)
   bool cplx = false;
+  bool bloch = false;             // Bloch-phase grid operator (twisted frame, planar blocks)
   void* Lc = nullptr;
   void* dinv2 = nullptr;
   void* Zt = nullptr;
@@ -169,6 +170,48 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
   if (A->n <= 0) {
     set_error("operator size must be positive");
     return CHFSI_ERR_ARG;
+  }
+  if (A->kind == CHFSI_OP_STENCIL27_BLOCH) {
+    // complex grid problems at a wave vector k (Section 4.3): the residual filter only
+    if (int64_t(A->nx) * A->ny * A->nz != A->n || A->nx < 3 || A->ny < 3 || A->nz < 3) {
+      set_error("stencil grid nx*ny*nz must equal n with every side >= 3");
+      return CHFSI_ERR_ARG;
+    }
+    if (A->field_mode < 0 || A->field_mode > 2 || (A->field_mode != 0 && !A->field)) {
+      set_error("stencil field_mode must be 0, 1 or 2 (1/2 need a field)");
+      return CHFSI_ERR_ARG;
+    }
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(A->bloch[d])) {
+        set_error("the Bloch vector must be finite");
+        return CHFSI_ERR_ARG;
+      }
+    if (!is_identity(B) &&
+        (B->kind != CHFSI_OP_STENCIL27_BLOCH || B->n != A->n || B->nx != A->nx ||
+         B->ny != A->ny || B->nz != A->nz || B->field_mode != 0 || B->bloch[0] != A->bloch[0] ||
+         B->bloch[1] != A->bloch[1] || B->bloch[2] != A->bloch[2])) {
+      set_error("with a Bloch grid A, B must be the identity or a Bloch grid operator on A's grid "
+                "with the same wave vector and no field");
+      return CHFSI_ERR_ARG;
+    }
+    if (p->method != CHFSI_METHOD_RCHFSI || p->memory_mode != 0) {
+      set_error("complex Hermitian operators support the residual filter with memory_mode 0");
+      return CHFSI_ERR_ARG;
+    }
+    if (p->block <= 0 || p->n_wanted <= 0 || p->n_wanted > p->block || p->block > A->n ||
+        p->block > 65535) {
+      set_error("need 0 < n_wanted <= block <= min(n, 65535)");
+      return CHFSI_ERR_ARG;
+    }
+    if (p->degree < 1 || p->degree > 1000) {
+      set_error("degree must be in [1, 1000]");
+      return CHFSI_ERR_ARG;
+    }
+    if (p->filter_prec < CHFSI_PREC_FP64 || p->filter_prec > CHFSI_PREC_BF16) {
+      set_error("unknown filter precision");
+      return CHFSI_ERR_ARG;
+    }
+    return CHFSI_OK;
   }
   if (A->kind == CHFSI_OP_DENSE_HERMITIAN) {
     // complex Hermitian problems (Section 4.3): the residual filter only
@@ -324,8 +367,36 @@ SizePlan plan_sizes_complex(const chfsi_operator* A, const chfsi_params* p) {
   return s;
 }
 
+// Bloch grid contexts: three planar filter blocks (n x 2b) in the filter
+// precision, FP32 copies of D^{-1} and V (FP32/BF16), and the complex
+// Rayleigh-Ritz buffers without any n x n operand
+SizePlan plan_sizes_bloch(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
+  SizePlan s;
+  const int64_t n = A->n, b = p->block, m = 2 * b;
+  const size_t el = p->filter_prec == CHFSI_PREC_FP64   ? sizeof(double)
+                    : p->filter_prec == CHFSI_PREC_FP32 ? sizeof(float)
+                                                        : sizeof(uint16_t);
+  s.f32blk = size_t(n) * 2 * b * el;
+  if (p->filter_prec != CHFSI_PREC_FP64)
+    s.a32 = size_t(n) * sizeof(float) * (1 + (A->field_mode != 0 ? 1 : 0));
+  s.coef = size_t(p->degree + 1) * 2 * b * sizeof(double);
+  s.blk = size_t(n) * b * 2 * sizeof(double);
+  s.bb = size_t(m) * m * sizeof(double);
+  s.ws_eig = syev_workspace_bytes(m) + 256;
+  s.tri = tri_workspace_bytes(m, m);
+  const size_t rr = (is_identity(B) ? 4 : 5) * s.blk + 3 * s.blk + 12 * s.bb + 8 * m * sizeof(double);
+  size_t ws = plan_bytes<double>(m, m, n);
+  ws = std::max(ws, plan_bytes<double>(n, m, m));
+  ws = std::max(ws, plan_bytes<double>(m, m, m));
+  s.ws = ws + 256;
+  s.total = s.a32 + 3 * s.f32blk + 2 * s.coef + b * sizeof(double) + s.ws + 64 + rr + s.ws_eig +
+            s.tri;
+  return s;
+}
+
 SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
   if (A->kind == CHFSI_OP_DENSE_HERMITIAN) return plan_sizes_complex(A, p);
+  if (A->kind == CHFSI_OP_STENCIL27_BLOCH) return plan_sizes_bloch(A, B, p);
   SizePlan s;
   const int64_t n = A->n, b = p->block;
   const bool dense = A->kind == CHFSI_OP_DENSE;
@@ -666,6 +737,10 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
   return CHFSI_OK;
 }
 
+Twist twist_of(const chfsi_ctx* c) {
+  return Twist{c->A.bloch[0], c->A.bloch[1], c->A.bloch[2], c->A.nx, c->A.ny};
+}
+
 // Algorithm 3 for a complex Hermitian A (Section 4.3).  The recurrence's
 // coefficients and Lambda are real, so every step is one real product on
 // planar blocks (see complex.hip): R_X <- a (L Z~) + b R_Y + c R_X + a Yc diag(Lambda_Y),
@@ -708,7 +783,85 @@ chfsi_status filter_rchfsi_complex(chfsi_ctx* c, const double* X, int64_t ldx, c
   const int nsteps = p - 1;
   const double scale1 = f.sigma1 / f.e;
   double fl = 0.0;
-  if (c->prm.filter_prec == CHFSI_PREC_FP64) {
+  if (c->bloch) {
+    // grid operator in the twisted frame: each step is the real z-march on
+    // the 2b planar columns plus the boundary correction for wrapped phases
+    const Twist tw = twist_of(c);
+    const bool f64 = c->prm.filter_prec == CHFSI_PREC_FP64;
+    if (nsteps > 0) {
+      char* hs = static_cast<char*>(c->h_stage) + b * sizeof(double);
+      const size_t bytes = size_t(nsteps) * b2 * (f64 ? sizeof(double) : sizeof(float));
+      if (f64)
+        std::memcpy(hs, c->h_coef64.data(), bytes);
+      else
+        std::memcpy(hs, c->h_coef32.data(), bytes);
+      CK(hipMemcpyAsync(f64 ? static_cast<void*>(c->coef64) : static_cast<void*>(c->coef32), hs,
+                        bytes, hipMemcpyHostToDevice, c->stream));
+    }
+    CK(hipEventRecord(c->ev_stage, c->stream));
+    const double step_fl = (stencil_flops(c->A) * double(n) +
+                            27.0 * 8.0 * double(bloch_boundary_points(c->A.nx, c->A.ny, c->A.nz))) *
+                           double(b2);
+    if (f64) {
+      double* RX = c->f64_a;
+      double* RY = c->f64_b;
+      double* Yc = c->f64_c;
+      CK(bloch_init<double>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream));
+      for (int s = 0; s < nsteps; ++s) {
+        const Step& sp = steps[s];
+        StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
+        hipEvent_t e0, e1;
+        CK(prof_pair(c, &e0, &e1));
+        if (e0) CK(hipEventRecord(e0, c->stream));
+        CK(stencil_rchfsi_step_f64(c->A, c->dinv, RY, RX, Yc, n, c->coef64 + int64_t(s) * b2, ss,
+                                   b2, c->stream));
+        CK(bloch_fix<double>(c->A, c->dinv, sp.a, RY, n, RX, n, b, c->stream));
+        if (e1) CK(hipEventRecord(e1, c->stream));
+        fl += step_fl;
+        std::swap(RX, RY);
+      }
+      CK(bloch_reconstruct<double>(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, tw, c->stream));
+    } else if (c->prm.filter_prec == CHFSI_PREC_FP32) {
+      float* RX = c->f32_a;
+      float* RY = c->f32_b;
+      float* Yc = c->f32_c;
+      CK(bloch_init<float>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream));
+      for (int s = 0; s < nsteps; ++s) {
+        const Step& sp = steps[s];
+        StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
+        hipEvent_t e0, e1;
+        CK(prof_pair(c, &e0, &e1));
+        if (e0) CK(hipEventRecord(e0, c->stream));
+        CK(stencil_rchfsi_step_f32(c->A, c->Vf, c->dinv32, RY, RX, Yc,
+                                   c->coef32 + int64_t(s) * b2, ss, b2, c->stream));
+        CK(bloch_fix<float>(c->A, c->dinv, sp.a, RY, n, RX, n, b, c->stream));
+        if (e1) CK(hipEventRecord(e1, c->stream));
+        fl += step_fl;
+        std::swap(RX, RY);
+      }
+      CK(bloch_reconstruct<float>(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, tw, c->stream));
+    } else {
+      uint16_t* RX = static_cast<uint16_t*>(c->bf_a);
+      uint16_t* RY = static_cast<uint16_t*>(c->bf_b);
+      uint16_t* Yc = static_cast<uint16_t*>(c->bf_c);
+      CK(bloch_init<uint16_t>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream));
+      for (int s = 0; s < nsteps; ++s) {
+        const Step& sp = steps[s];
+        StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
+        hipEvent_t e0, e1;
+        CK(prof_pair(c, &e0, &e1));
+        if (e0) CK(hipEventRecord(e0, c->stream));
+        CK(stencil_rchfsi_step_bf16(c->A, c->Vf, c->dinv32, RY, RX, Yc,
+                                    c->coef32 + int64_t(s) * b2, ss, b2, c->stream));
+        CK(bloch_fix<uint16_t>(c->A, c->dinv, sp.a, RY, n, RX, n, b, c->stream));
+        if (e1) CK(hipEventRecord(e1, c->stream));
+        fl += step_fl;
+        std::swap(RX, RY);
+      }
+      CK(bloch_reconstruct<uint16_t>(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, tw,
+                                     c->stream));
+    }
+  } else if (c->prm.filter_prec == CHFSI_PREC_FP64) {
     if (nsteps > 0) {
       double* hs = reinterpret_cast<double*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
       std::memcpy(hs, c->h_coef64.data(), size_t(nsteps) * b2 * sizeof(double));
@@ -1249,14 +1402,26 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
   const int64_t n = c->n, b = c->b, m = 2 * b;
   hipStream_t st = c->stream;
   CK(fill_zero(c->dflags, 4 * sizeof(int), st));
-  CK(cplx_to_planar(Y, ldy, n, b, c->Ypl, st));
-  CK(cplx_rhs<double>(c->Ypl, n, b, c->Yt, st));
-  auto product = [&](const double* L, double* out) -> chfsi_status {
+  // a Bloch grid context works in the twisted frame (planar D Y)
+  if (c->bloch) {
+    CK(bloch_to_planar(Y, ldy, n, b, c->Ypl, twist_of(c), st));
+  } else {
+    CK(cplx_to_planar(Y, ldy, n, b, c->Ypl, st));
+    CK(cplx_rhs<double>(c->Ypl, n, b, c->Yt, st));
+  }
+  auto product = [&](bool useB, double* out) -> chfsi_status {
+    if (c->bloch) {
+      // out = A_tw Y: the periodic stencil on 2b columns plus the wrap correction
+      const chfsi_operator& op = useB ? c->B : c->A;
+      CK(stencil_apply_f64(op, c->Ypl, n, out, n, m, st));
+      CK(bloch_fix<double>(op, nullptr, 1.0, c->Ypl, n, out, n, b, st));
+      return CHFSI_OK;
+    }
     GemmDesc<double> g;   // out (n x 2b planar) = L (n x 2n) Y~ (2n x 2b)
     g.M = n;
     g.N = m;
     g.K = 2 * n;
-    g.A = L;
+    g.A = useB ? c->LB64 : c->LA64;
     g.sak = 1;
     g.sam = 2 * n;
     g.B = c->Yt;
@@ -1268,10 +1433,10 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
     return CHFSI_OK;
   };
   chfsi_status s;
-  if ((s = product(c->LA64, c->AYpl)) != CHFSI_OK) return s;
+  if ((s = product(false, c->AYpl)) != CHFSI_OK) return s;
   const double* BYpl = c->Ypl;
   if (!c->B_identity) {
-    if ((s = product(c->LB64, c->BYpl)) != CHFSI_OK) return s;
+    if ((s = product(true, c->BYpl)) != CHFSI_OK) return s;
     BYpl = c->BYpl;
   }
   auto gram = [&](const double* W, double* G) -> chfsi_status {
@@ -1411,8 +1576,13 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
   CK(column_norms(c->Rpl, n, n, m, c->norms, st));
   CK(check_finite(c->wdup, m, c->dflags + 2, st));
   CK(check_finite(c->norms, m, c->dflags + 2, st));
-  CK(planar_to_cplx(c->Xpl, n, b, X, ldx, st));
-  CK(planar_to_cplx(c->Rpl, n, b, R, ldr, st));
+  if (c->bloch) {
+    CK(bloch_from_planar(c->Xpl, n, b, X, ldx, twist_of(c), st));
+    CK(bloch_from_planar(c->Rpl, n, b, R, ldr, twist_of(c), st));
+  } else {
+    CK(planar_to_cplx(c->Xpl, n, b, X, ldx, st));
+    CK(planar_to_cplx(c->Rpl, n, b, R, ldr, st));
+  }
   CK(hipMemcpyAsync(c->h_norms, c->norms, m * sizeof(double), hipMemcpyDeviceToHost, st));
   CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -1726,22 +1896,33 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   const SizePlan sp = plan_sizes(A, B, params);
   st = CHFSI_OK;
   const bool dense = A->kind == CHFSI_OP_DENSE;
-  c->cplx = A->kind == CHFSI_OP_DENSE_HERMITIAN;
+  c->bloch = A->kind == CHFSI_OP_STENCIL27_BLOCH;
+  c->cplx = A->kind == CHFSI_OP_DENSE_HERMITIAN || c->bloch;
   if (c->cplx) {
-    // planar operator copy, [d; d], three planar blocks, Z~ (and its bfloat16
-    // copy), the coefficient tables for 2b columns; no Rayleigh-Ritz buffers
+    // dense: planar operator copy, [d; d], Z~ (and its bfloat16 copy); grid:
+    // FP32 copies of D^{-1} and V for FP32/BF16 filters.  Three planar filter
+    // blocks and the coefficient tables for 2b columns.
     const bool f64 = params->filter_prec == CHFSI_PREC_FP64;
     const size_t el = f64 ? sizeof(double) : sizeof(float);
     const size_t lel = params->filter_prec == CHFSI_PREC_BF16 ? sizeof(uint16_t) : el;
-    c->Lc = ctx_alloc<char>(c, size_t(n) * 2 * n * lel, &st);
-    c->dinv2 = ctx_alloc<char>(c, size_t(2) * n * el, &st);
-    size_t zt = size_t(2) * n * 2 * b * el;
-    if (params->filter_prec == CHFSI_PREC_BF16) zt += size_t(2) * n * 2 * b * sizeof(uint16_t);
-    c->Zt = ctx_alloc<char>(c, zt, &st);
+    if (c->bloch) {
+      if (!f64 && d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+      if (!f64 && A->field_mode != 0) c->Vf = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+    } else {
+      c->Lc = ctx_alloc<char>(c, size_t(n) * 2 * n * lel, &st);
+      c->dinv2 = ctx_alloc<char>(c, size_t(2) * n * el, &st);
+      size_t zt = size_t(2) * n * 2 * b * el;
+      if (params->filter_prec == CHFSI_PREC_BF16) zt += size_t(2) * n * 2 * b * sizeof(uint16_t);
+      c->Zt = ctx_alloc<char>(c, zt, &st);
+    }
     if (f64) {
       c->f64_a = ctx_alloc<double>(c, sp.f32blk, &st);
       c->f64_b = ctx_alloc<double>(c, sp.f32blk, &st);
       c->f64_c = ctx_alloc<double>(c, sp.f32blk, &st);
+    } else if (c->bloch && params->filter_prec == CHFSI_PREC_BF16) {
+      c->bf_a = ctx_alloc<char>(c, sp.f32blk, &st);
+      c->bf_b = ctx_alloc<char>(c, sp.f32blk, &st);
+      c->bf_c = ctx_alloc<char>(c, sp.f32blk, &st);
     } else {
       c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
       c->f32_b = ctx_alloc<float>(c, sp.f32blk, &st);
@@ -1757,15 +1938,18 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     c->ws.ptr = ctx_alloc<char>(c, sp.ws, &st);
     // Rayleigh-Ritz (FP64) on the real embedding of the 2b x 2b projected pencil
     const int64_t m = 2 * b;
-    c->LA64 = f64 ? static_cast<double*>(c->Lc)
-                  : ctx_alloc<double>(c, size_t(n) * 2 * n * sizeof(double), &st);
-    if (!c->B_identity) c->LB64 = ctx_alloc<double>(c, size_t(n) * 2 * n * sizeof(double), &st);
+    if (!c->bloch) {
+      c->LA64 = f64 ? static_cast<double*>(c->Lc)
+                    : ctx_alloc<double>(c, size_t(n) * 2 * n * sizeof(double), &st);
+      if (!c->B_identity)
+        c->LB64 = ctx_alloc<double>(c, size_t(n) * 2 * n * sizeof(double), &st);
+    }
     c->Ypl = ctx_alloc<double>(c, sp.blk, &st);
     c->AYpl = ctx_alloc<double>(c, sp.blk, &st);
     c->BYpl = c->B_identity ? nullptr : ctx_alloc<double>(c, sp.blk, &st);
     c->Xpl = ctx_alloc<double>(c, sp.blk, &st);
     c->Rpl = ctx_alloc<double>(c, sp.blk, &st);
-    c->Yt = ctx_alloc<double>(c, size_t(2) * n * m * sizeof(double), &st);
+    if (!c->bloch) c->Yt = ctx_alloc<double>(c, size_t(2) * n * m * sizeof(double), &st);
     c->Xw = ctx_alloc<double>(c, sp.blk, &st);
     c->Yw = ctx_alloc<double>(c, sp.blk, &st);
     c->R = ctx_alloc<double>(c, sp.blk, &st);
@@ -1889,7 +2073,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   }
   // precision-converted operator copies (owned)
   hipError_t e = hipSuccess;
-  if (c->cplx) {
+  if (c->cplx && !c->bloch) {
     // FP64 planar A (Rayleigh-Ritz; also the FP64 filter's operand) and B
     e = herm_to_planar<double>(A->dense, A->ld, n, c->LA64, c->stream);
     if (e == hipSuccess && c->LB64) e = herm_to_planar<double>(B->dense, B->ld, n, c->LB64, c->stream);
@@ -1912,7 +2096,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
       e = fill_ones_f32(c->dinv32, n, c->stream);
   }
   if (e == hipSuccess && c->Vf) e = convert_f64_f32(A->field, n, c->Vf, n, n, 1, c->stream);
-  if (e == hipSuccess && A->kind == CHFSI_OP_STENCIL27) e = stencil_check(*A);
+  if (e == hipSuccess && (A->kind == CHFSI_OP_STENCIL27 || c->bloch)) e = stencil_check(*A);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     set_error("context setup failed: %s", hipGetErrorString(e));

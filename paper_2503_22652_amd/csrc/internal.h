@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <atomic>
 
+#include "../../include/chfsi.h"
+
 struct chfsi_ctx;
 
 namespace chfsi {
@@ -128,6 +130,38 @@ hipError_t embed_gram(const double* P, int64_t b, double* M, hipStream_t st);
 // Zx (b x 2b planar, ld b): column j = T(0:b, 2j), column b+j = T(b:2b, 2j)
 // of the 2b x 2b eigenvector matrix T of an embedded problem
 hipError_t select_pairs(const double* T, int64_t b, double* Zx, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Bloch-phase grid operators in the twisted frame (bloch.hip).  D =
+// diag(exp(i k.r)), r = (x, y, z) of grid point x + nx (y + ny z); planar
+// blocks as above.
+// ---------------------------------------------------------------------------
+struct Twist {
+  double kx, ky, kz;
+  int64_t nx, ny;
+};
+// number of grid points with a neighbour across a periodic face
+int64_t bloch_boundary_points(int nx, int ny, int nz);
+// planar RY = scale D R, RX = 0, Yc = D R from the interleaved residual
+template <typename F>
+hipError_t bloch_init(const double* R, int64_t ldr, int64_t n, int64_t b, double scale, F* RY,
+                      F* RX, F* Yc, const Twist& tw, hipStream_t st);
+// interleaved Yp = D^* (dinv .* RY) + X diag(lamY)
+template <typename F>
+hipError_t bloch_reconstruct(const F* RY, const double* dinv, const double* X, int64_t ldx,
+                             const double* lamY, double* Yp, int64_t ldy, int64_t n, int64_t b,
+                             const Twist& tw, hipStream_t st);
+// planar P = D Z from interleaved Z, and interleaved Z = D^* P
+hipError_t bloch_to_planar(const double* Z, int64_t ldz, int64_t n, int64_t b, double* P,
+                           const Twist& tw, hipStream_t st);
+hipError_t bloch_from_planar(const double* P, int64_t n, int64_t b, double* Z, int64_t ldz,
+                             const Twist& tw, hipStream_t st);
+// dst += alpha (A_tw - A_per)(dinv .* src) at the boundary points, for the b
+// column pairs of the planar blocks src (ld lds) and dst (ld ldd); op's
+// coefficients, field (mode 2) and bloch vector define A (dinv null: identity)
+template <typename F>
+hipError_t bloch_fix(const chfsi_operator& op, const double* dinv, double alpha, const F* src,
+                     int64_t lds, F* dst, int64_t ldd, int64_t b, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Elementwise / reduction kernels (blas1.hip)

@@ -53,6 +53,7 @@ struct Req {
 struct Seq {
   double* X = nullptr;
   int64_t n = 0, b = 0;
+  size_t bytes = 0;          // size of X (complex blocks are twice a real one)
   bool busy = false;
 };
 
@@ -82,11 +83,17 @@ namespace {
 
 thread_local std::string g_srv_err;
 
+// bytes of one n x b block of the request's vectors (complex kinds: interleaved pairs)
+size_t block_bytes(const chfsi_request& r) {
+  const bool cplx = r.A.kind == CHFSI_OP_DENSE_HERMITIAN || r.A.kind == CHFSI_OP_STENCIL27_BLOCH;
+  return size_t(r.A.n) * size_t(r.params.block) * sizeof(double) * (cplx ? 2 : 1);
+}
+
 size_t footprint_of(const chfsi_request& r, bool new_seq) {
   const chfsi_operator* B = r.B.kind == CHFSI_OP_IDENTITY ? nullptr : &r.B;
   const size_t ws = chfsi_workspace_bytes(&r.A, B, &r.params);
   if (ws == 0) return 0;
-  const size_t blk = size_t(r.A.n) * size_t(r.params.block) * sizeof(double);
+  const size_t blk = block_bytes(r);
   return ws + blk + (new_seq ? blk : 0);
 }
 
@@ -124,6 +131,7 @@ Req* pick(chfsi_server* s) {
 void run_one(chfsi_server* s, Req* q, hipStream_t stream) {
   const chfsi_request& r = q->r;
   const int64_t n = r.A.n, b = r.params.block;
+  const size_t blk = block_bytes(r);
   chfsi_params prm = r.params;
   double* X = nullptr;
   chfsi_ctx* ctx = nullptr;
@@ -134,22 +142,20 @@ void run_one(chfsi_server* s, Req* q, hipStream_t stream) {
     seq = &s->seqs[r.seq_id];
   }
   do {
-    if (hipMalloc(&X, size_t(n) * b * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(&X, blk) != hipSuccess) {
       st = CHFSI_ERR_NOMEM;
       break;
     }
     const chfsi_operator* B = r.B.kind == CHFSI_OP_IDENTITY ? nullptr : &r.B;
     bool warm = false;
-    if (seq && seq->X && seq->n == n && seq->b == b) {
-      if (hipMemcpyAsync(X, seq->X, size_t(n) * b * sizeof(double), hipMemcpyDeviceToDevice,
-                         stream) != hipSuccess) {
+    if (seq && seq->X && seq->n == n && seq->b == b && seq->bytes == blk) {
+      if (hipMemcpyAsync(X, seq->X, blk, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
         st = CHFSI_ERR_DEVICE;
         break;
       }
       warm = true;
     } else if (r.X0) {
-      if (hipMemcpyAsync(X, r.X0, size_t(n) * b * sizeof(double), hipMemcpyDeviceToDevice,
-                         stream) != hipSuccess) {
+      if (hipMemcpyAsync(X, r.X0, blk, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
         st = CHFSI_ERR_DEVICE;
         break;
       }
@@ -166,20 +172,17 @@ void run_one(chfsi_server* s, Req* q, hipStream_t stream) {
     q->max_residual = rep.max_residual;
     if (st == CHFSI_OK || st == CHFSI_ERR_NOCONV) {
       if (seq) {
-        if (!seq->X || seq->n != n || seq->b != b) {
+        if (!seq->X || seq->n != n || seq->b != b || seq->bytes != blk) {
           if (seq->X) hipFree(seq->X);
           seq->X = nullptr;
-          if (hipMalloc(&seq->X, size_t(n) * b * sizeof(double)) != hipSuccess) seq->X = nullptr;
+          if (hipMalloc(&seq->X, blk) != hipSuccess) seq->X = nullptr;
           seq->n = n;
           seq->b = b;
+          seq->bytes = blk;
         }
-        if (seq->X)
-          hipMemcpyAsync(seq->X, X, size_t(n) * b * sizeof(double), hipMemcpyDeviceToDevice,
-                         stream);
+        if (seq->X) hipMemcpyAsync(seq->X, X, blk, hipMemcpyDeviceToDevice, stream);
       }
-      if (r.X_out)
-        hipMemcpyAsync(r.X_out, X, size_t(n) * b * sizeof(double), hipMemcpyDeviceToDevice,
-                       stream);
+      if (r.X_out) hipMemcpyAsync(r.X_out, X, blk, hipMemcpyDeviceToDevice, stream);
       hipStreamSynchronize(stream);
     }
   } while (false);

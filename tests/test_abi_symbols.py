@@ -63,3 +63,30 @@ def test_workspace_bytes_rejects_bad_params_without_gpu():
     st = P.stencil_operator((8, 8, 8), [0.0] * 27)
     assert P.chfsi_workspace_bytes(st, None, P.make_params(10, 20, 8, lambda_max=5.0)) > 0
     assert P.chfsi_workspace_bytes(st, None, P.make_params(30, 20, 8, lambda_max=5.0)) == 0
+
+
+def test_bloch_operator_checks_without_gpu():
+    """Host-side checks of the Bloch-phase grid kind (complex contexts)."""
+    import paper_2503_22652_amd as P
+    k = (0.3, -0.7, 1.1)
+    coef = [0.0] * 27
+    A = P.stencil_operator((8, 8, 8), coef, bloch=k)
+    assert A.kind == P.OP_STENCIL27_BLOCH and tuple(A.bloch) == k
+
+    def ws(B, **kw):
+        kw.setdefault("method", P.METHOD_RCHFSI)
+        return P.chfsi_workspace_bytes(A, B, P.make_params(10, 20, 8, lambda_max=5.0, **kw))
+
+    f64, f32, bf16 = (ws(None, filter_prec=p) for p in (P.PREC_FP64, P.PREC_FP32, P.PREC_BF16))
+    assert f64 > f32 > bf16 > 0          # planar filter blocks in the filter precision
+    assert ws(P.stencil_operator((8, 8, 8), coef, bloch=k)) > f64    # B Y block
+    # B on another wave vector, a real B, B on another grid, plain ChFSI, slab mode
+    assert ws(P.stencil_operator((8, 8, 8), coef, bloch=(0.3, 0.0, 0.0))) == 0
+    assert ws(P.stencil_operator((8, 8, 8), coef)) == 0
+    assert ws(P.stencil_operator((8, 8, 4), coef, bloch=k)) == 0
+    assert ws(None, method=P.METHOD_CHFSI) == 0
+    assert ws(None, memory_mode=1) == 0
+    nan = P.stencil_operator((8, 8, 8), coef, bloch=(float("nan"), 0.0, 0.0))
+    assert P.chfsi_workspace_bytes(nan, None, P.make_params(10, 20, 8, lambda_max=5.0)) == 0
+    nofield = P.stencil_operator((8, 8, 8), coef, field_mode=2, bloch=k)   # mode 2 without V
+    assert P.chfsi_workspace_bytes(nofield, None, P.make_params(10, 20, 8, lambda_max=5.0)) == 0
