@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--workload", choices=("dense", "grid", "serving"), default="dense",
                     help="dense: the headline line; grid / serving: extra measurement lines")
     ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--bloch", type=str, default="",
+                    help="kx,ky,kz: the grid pencil at this wave vector (complex, Section 4.3), "
+                         "half the block in complex vectors")
     ap.add_argument("--wells", type=int, default=64)
     ap.add_argument("--prec", choices=("bf16", "fp32", "fp64"), default="bf16")
     ap.add_argument("--requests", type=int, default=512)
@@ -372,26 +375,31 @@ def bench_grid(args):
     prob = wl.stencil_problem(grid=g, n_wells=args.wells, n_wanted=nw, block=b, degree=p,
                               seed=1002 if g != 160 else 1004)
     n = prob.n
+    kvec = tuple(float(v) for v in args.bloch.split(",")) if args.bloch else None
+    if kvec is not None:
+        # complex vectors: b planar columns = b / 2 complex vectors
+        b, nw = b // 2, nw // 2
     prec = {"bf16": P.PREC_BF16, "fp32": P.PREC_FP32, "fp64": P.PREC_FP64}[args.prec]
     esize = {"bf16": 2, "fp32": 4, "fp64": 8}[args.prec]
     Vd = torch.from_numpy(np.ascontiguousarray(prob.V).reshape(-1)).cuda()
     opA = P.stencil_operator(prob.shape, prob.coef_A, coef_mass=prob.coef_B, field=Vd,
-                             field_mode=prob.field_mode)
-    opB = P.stencil_operator(prob.shape, prob.coef_B)
+                             field_mode=prob.field_mode, bloch=kvec)
+    opB = P.stencil_operator(prob.shape, prob.coef_B, bloch=kvec)
     lmax = 18.5
     free, _ = torch.cuda.mem_get_info()
     mode = 0
     prm = P.make_params(nw, b, p, max_iter=args.warmup, tol=0.0, method=P.METHOD_RCHFSI,
                         filter_prec=prec, lambda_max=lmax, profile=1, seed=2002, init_random=1)
-    need = P.chfsi_workspace_bytes(opA, opB, prm) + n * b * 8
-    if need > 0.9 * free and prec != P.PREC_FP64:
+    cw = 2 if kvec is not None else 1          # planar columns per vector
+    need = P.chfsi_workspace_bytes(opA, opB, prm) + n * b * 8 * cw
+    if need > 0.9 * free and prec != P.PREC_FP64 and kvec is None:
         mode = 1
     prm.memory_mode = mode
     log(f"grid {g}^3: n={n}, b={b}, p={p}, memory_mode={mode}, "
         f"workspace {P.chfsi_workspace_bytes(opA, opB, prm) / 2**30:.1f} GiB")
     stream = torch.cuda.current_stream()
     ctx = P.chfsi_create(opA, opB, None, prm, stream=stream, keep=(Vd,))
-    X = P.colmajor_empty(n, b)
+    X = P.colmajor_empty(n, b) if kvec is None else P.colmajor_empty_complex(n, b)
     if args.warmup > 0:
         P.chfsi_solve(ctx, X)                      # random start + warm-up iterations
     P.chfsi_filter_kernel_time(ctx)
@@ -407,8 +415,13 @@ def bench_grid(args):
     wall = time.perf_counter() - t0
     its = max(rep["iterations"], 1)
     per = rep["kernel_ms"] / max(rep["kernel_launches"], 1)
-    achieved = 4.0 * esize * n * b / (per / 1e3) / 1e9
-    step_bytes = 4.0 * esize * n * b * (p - 1)
+    # algorithmic bytes of one filter step: four streams over the n x (cw b)
+    # planar block; a Bloch step adds the boundary pass (read the wrapped
+    # neighbours' source values once, read and write the output there)
+    nbnd = n - (g - 2) ** 3 if kvec is not None else 0
+    launch_bytes = 4.0 * esize * n * b * cw + 3.0 * esize * nbnd * b * cw
+    achieved = launch_bytes / (per / 1e3) / 1e9
+    step_bytes = launch_bytes * (p - 1)
     out = {"metric": METRIC,
            "value": round(step_bytes * its / (rep["time_filter_ms"] / 1e3) / 1e9, 1),
            "unit": "GB/s", "n_gpus": 1, "steps": its, "warmup": args.warmup,
@@ -416,7 +429,8 @@ def bench_grid(args):
            "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
            "config": {"workload": f"periodic {g}^3 grid pencil, 27-point Q1 stiffness/mass, "
                                   f"{args.wells} Gaussian wells (mass-weighted), block {b}, "
-                                  f"{nw} wanted, degree {p}, {args.prec} residual filter",
+                                  f"{nw} wanted, degree {p}, {args.prec} residual filter" +
+                                  (f", Bloch wave vector {kvec} (complex)" if kvec else ""),
                       "n": n, "block": b, "degree": p, "memory_mode": mode,
                       "filter_ms_per_step": round(rep["time_filter_ms"] / its, 2),
                       "rr_ms_per_step": round(rep["time_rr_ms"] / its, 2),
@@ -427,7 +441,8 @@ def bench_grid(args):
                         "traffic": TRAFFIC_ZMARCH.get((g, b, args.prec)),
                         "traffic_unit": "bytes per launch",
                         "kernel": f"k_zmarch<{args.prec}> residual-filter step "
-                                  f"(4 streams x {esize} B per element-step)",
+                                  f"(4 streams x {esize} B per element-step)" +
+                                  (" + k_bloch_fix boundary pass" if kvec else ""),
                         "ms_per_launch": round(per, 3)}}
     if args.ttr:
         # time to max residual < tau over the wanted pairs, from the same random
@@ -442,15 +457,18 @@ def bench_grid(args):
         for name, method, pr, iters in runs:
             if name == "fp64_rchfsi" and prec == P.PREC_FP64:
                 continue
+            if kvec is not None and method == P.METHOD_CHFSI:
+                continue                        # complex contexts run the residual filter only
             pm = P.make_params(nw, b, p, max_iter=iters, tol=1e-8, method=method, filter_prec=pr,
                                lambda_max=lmax, seed=2002, init_random=1)
             md = 0
-            if P.chfsi_workspace_bytes(opA, opB, pm) + n * b * 8 > 0.9 * torch.cuda.mem_get_info()[0]:
+            if (kvec is None and P.chfsi_workspace_bytes(opA, opB, pm) + n * b * 8 >
+                    0.9 * torch.cuda.mem_get_info()[0]):
                 md = 1
             pm.memory_mode = md
             log(f"time-to-residual: {name} (memory_mode {md}) ...")
             c2 = P.chfsi_create(opA, opB, None, pm, stream=stream, keep=(Vd,))
-            X2 = P.colmajor_empty(n, b)
+            X2 = P.colmajor_empty(n, b) if kvec is None else P.colmajor_empty_complex(n, b)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             st2, ev2, rn2, rep2 = P.chfsi_solve(c2, X2)

@@ -104,6 +104,9 @@ struct chfsi_ctx {
   // operand Z~ (2n x 2b, FP32/FP64) and its bfloat16 copy (BF16)
   bool cplx = false;
   bool bloch = false;             // Bloch-phase grid operator (twisted frame, planar blocks)
+  void* bcorr = nullptr;          // its filter step's boundary correction (boundary points x 2b)
+  int64_t nbnd = 0;
+  void* bedge[2] = {nullptr, nullptr};   // row-end values of the filter blocks (2 ny nz x 2b)
   void* Lc = nullptr;
   void* dinv2 = nullptr;
   void* Zt = nullptr;
@@ -359,6 +362,7 @@ SizePlan plan_sizes_complex(const chfsi_operator* A, const chfsi_params* p) {
   if (p->filter_prec == CHFSI_PREC_BF16) ws = std::max(ws, gemm_bf16_workspace_bytes(n, 2 * b));
   ws = std::max(ws, plan_bytes<double>(n, m, 2 * n));
   ws = std::max(ws, plan_bytes<double>(m, m, n));
+  ws = std::max(ws, 2 * gemm_workspace_bytes(b, b, n, sizeof(double)));   // batched Gram blocks
   ws = std::max(ws, plan_bytes<double>(n, m, m));
   ws = std::max(ws, plan_bytes<double>(m, m, m));
   s.ws = ws + 256;
@@ -379,6 +383,11 @@ SizePlan plan_sizes_bloch(const chfsi_operator* A, const chfsi_operator* B, cons
   s.f32blk = size_t(n) * 2 * b * el;
   if (p->filter_prec != CHFSI_PREC_FP64)
     s.a32 = size_t(n) * sizeof(float) * (1 + (A->field_mode != 0 ? 1 : 0));
+  // the boundary correction, in the step's arithmetic type, and two copies of
+  // the blocks' row ends
+  s.a32 += size_t(bloch_boundary_points(A->nx, A->ny, A->nz)) * 2 * b *
+               (p->filter_prec == CHFSI_PREC_FP64 ? sizeof(double) : sizeof(float)) +
+           size_t(2) * 2 * A->ny * A->nz * 2 * b * el;
   s.coef = size_t(p->degree + 1) * 2 * b * sizeof(double);
   s.blk = size_t(n) * b * 2 * sizeof(double);
   s.bb = size_t(m) * m * sizeof(double);
@@ -386,6 +395,7 @@ SizePlan plan_sizes_bloch(const chfsi_operator* A, const chfsi_operator* B, cons
   s.tri = tri_workspace_bytes(m, m);
   const size_t rr = (is_identity(B) ? 4 : 5) * s.blk + 3 * s.blk + 12 * s.bb + 8 * m * sizeof(double);
   size_t ws = plan_bytes<double>(m, m, n);
+  ws = std::max(ws, 2 * gemm_workspace_bytes(b, b, n, sizeof(double)));   // batched Gram blocks
   ws = std::max(ws, plan_bytes<double>(n, m, m));
   ws = std::max(ws, plan_bytes<double>(m, m, m));
   s.ws = ws + 256;
@@ -799,64 +809,75 @@ chfsi_status filter_rchfsi_complex(chfsi_ctx* c, const double* X, int64_t ldx, c
                         bytes, hipMemcpyHostToDevice, c->stream));
     }
     CK(hipEventRecord(c->ev_stage, c->stream));
-    const double step_fl = (stencil_flops(c->A) * double(n) +
-                            27.0 * 8.0 * double(bloch_boundary_points(c->A.nx, c->A.ny, c->A.nz))) *
+    const double step_fl = (stencil_flops(c->A) * double(n) + 27.0 * 8.0 * double(c->nbnd)) *
                            double(b2);
+    // the boundary correction goes through the z-march's epilogue when it
+    // runs the step, else it is added in place after the step
+    // (the row ends of R_Y come from the initialisation, then from each step)
+    void* ein = c->bedge[0];
+    void* eout = c->bedge[1];
+    auto bstep = [&]() { return BlochStep{c->bcorr, c->nbnd, c->dinv, ein, eout}; };
     if (f64) {
       double* RX = c->f64_a;
       double* RY = c->f64_b;
       double* Yc = c->f64_c;
-      CK(bloch_init<double>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream));
+      CK(bloch_init<double>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream,
+                            static_cast<double*>(c->bedge[0])));
       for (int s = 0; s < nsteps; ++s) {
         const Step& sp = steps[s];
         StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
         hipEvent_t e0, e1;
+        const BlochStep bs = bstep();
         CK(prof_pair(c, &e0, &e1));
         if (e0) CK(hipEventRecord(e0, c->stream));
         CK(stencil_rchfsi_step_f64(c->A, c->dinv, RY, RX, Yc, n, c->coef64 + int64_t(s) * b2, ss,
-                                   b2, c->stream));
-        CK(bloch_fix<double>(c->A, c->dinv, sp.a, RY, n, RX, n, b, c->stream));
+                                   b2, c->stream, &bs));
         if (e1) CK(hipEventRecord(e1, c->stream));
         fl += step_fl;
         std::swap(RX, RY);
+        std::swap(ein, eout);
       }
       CK(bloch_reconstruct<double>(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, tw, c->stream));
     } else if (c->prm.filter_prec == CHFSI_PREC_FP32) {
       float* RX = c->f32_a;
       float* RY = c->f32_b;
       float* Yc = c->f32_c;
-      CK(bloch_init<float>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream));
+      CK(bloch_init<float>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream,
+                            static_cast<float*>(c->bedge[0])));
       for (int s = 0; s < nsteps; ++s) {
         const Step& sp = steps[s];
         StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
         hipEvent_t e0, e1;
+        const BlochStep bs = bstep();
         CK(prof_pair(c, &e0, &e1));
         if (e0) CK(hipEventRecord(e0, c->stream));
         CK(stencil_rchfsi_step_f32(c->A, c->Vf, c->dinv32, RY, RX, Yc,
-                                   c->coef32 + int64_t(s) * b2, ss, b2, c->stream));
-        CK(bloch_fix<float>(c->A, c->dinv, sp.a, RY, n, RX, n, b, c->stream));
+                                   c->coef32 + int64_t(s) * b2, ss, b2, c->stream, &bs));
         if (e1) CK(hipEventRecord(e1, c->stream));
         fl += step_fl;
         std::swap(RX, RY);
+        std::swap(ein, eout);
       }
       CK(bloch_reconstruct<float>(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, tw, c->stream));
     } else {
       uint16_t* RX = static_cast<uint16_t*>(c->bf_a);
       uint16_t* RY = static_cast<uint16_t*>(c->bf_b);
       uint16_t* Yc = static_cast<uint16_t*>(c->bf_c);
-      CK(bloch_init<uint16_t>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream));
+      CK(bloch_init<uint16_t>(resid, ldr, n, b, scale1, RY, RX, Yc, tw, c->stream,
+                            static_cast<uint16_t*>(c->bedge[0])));
       for (int s = 0; s < nsteps; ++s) {
         const Step& sp = steps[s];
         StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
         hipEvent_t e0, e1;
+        const BlochStep bs = bstep();
         CK(prof_pair(c, &e0, &e1));
         if (e0) CK(hipEventRecord(e0, c->stream));
         CK(stencil_rchfsi_step_bf16(c->A, c->Vf, c->dinv32, RY, RX, Yc,
-                                    c->coef32 + int64_t(s) * b2, ss, b2, c->stream));
-        CK(bloch_fix<uint16_t>(c->A, c->dinv, sp.a, RY, n, RX, n, b, c->stream));
+                                    c->coef32 + int64_t(s) * b2, ss, b2, c->stream, &bs));
         if (e1) CK(hipEventRecord(e1, c->stream));
         fl += step_fl;
         std::swap(RX, RY);
+        std::swap(ein, eout);
       }
       CK(bloch_reconstruct<uint16_t>(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, tw,
                                      c->stream));
@@ -1440,20 +1461,30 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
     BYpl = c->BYpl;
   }
   auto gram = [&](const double* W, double* G) -> chfsi_status {
-    GemmDesc<double> g;   // P (2b x 2b) = [Y_r Y_i]^T [W_r W_i], then the embedding
-    g.M = m;
-    g.N = m;
-    g.K = n;
-    g.A = c->Ypl;
-    g.sak = 1;
-    g.sam = n;
-    g.B = W;
-    g.sbk = 1;
-    g.sbn = n;
-    g.C = c->Tmp;
-    g.ldc = m;
-    CK(gemm<double>(g, st, c->ws));
-    CK(embed_gram(c->Tmp, b, G, st));
+    // the embedding of G = Y^H W needs only the lower triangles of the four
+    // b x b blocks of [Y_r Y_i]^T [W_r W_i]: P11, P22 (one batched product)
+    // and P12, P21 (a second, stepping back through W), into Tmp
+    for (int h = 0; h < 2; ++h) {
+      GemmDesc<double> g;
+      g.M = b;
+      g.N = b;
+      g.K = n;
+      g.A = c->Ypl;
+      g.sak = 1;
+      g.sam = n;
+      g.B = h == 0 ? W : W + b * n;
+      g.sbk = 1;
+      g.sbn = n;
+      g.C = c->Tmp + h * 2 * b * b;
+      g.ldc = b;
+      g.batch = 2;
+      g.bsA = b * n;
+      g.bsB = h == 0 ? b * n : -b * n;
+      g.bsC = b * b;
+      g.lower_only = true;
+      CK(gemm<double>(g, st, c->ws));
+    }
+    CK(embed_gram_lower(c->Tmp, b, G, st));
     return CHFSI_OK;
   };
   if ((s = gram(c->AYpl, c->Ga)) != CHFSI_OK) return s;
@@ -1568,10 +1599,20 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
     return CHFSI_OK;
   };
   if ((s = rotate(c->Ypl, c->Xt, c->Xpl, 1.0, nullptr)) != CHFSI_OK) return s;
-  if ((s = rotate(c->AYpl, c->Xt, c->Rpl, 1.0, nullptr)) != CHFSI_OK) return s;
-  CK(copy_block(c->Xt, m, c->TL, m, m, m, st));
-  CK(scale_columns(c->TL, m, m, m, c->wdup, st));
-  if ((s = rotate(BYpl, c->TL, c->Rpl, -1.0, c->Rpl)) != CHFSI_OK) return s;
+  if (c->bloch && stencil_separable(c->A) && (c->B_identity || stencil_separable(c->B))) {
+    // grid operators: R = A_tw X - B_tw X Lambda as one periodic stencil pass
+    // over X plus the wrap corrections (instead of rotating A Y and B Y)
+    CK(stencil_residual_f64(c->A, c->B_identity ? nullptr : &c->B, c->Xpl, n, c->wdup, c->Rpl,
+                            n, m, st));
+    CK(bloch_fix<double>(c->A, nullptr, 1.0, c->Xpl, n, c->Rpl, n, b, st));
+    if (!c->B_identity)
+      CK(bloch_fix<double>(c->B, nullptr, -1.0, c->Xpl, n, c->Rpl, n, b, st, c->wdup));
+  } else {
+    if ((s = rotate(c->AYpl, c->Xt, c->Rpl, 1.0, nullptr)) != CHFSI_OK) return s;
+    CK(copy_block(c->Xt, m, c->TL, m, m, m, st));
+    CK(scale_columns(c->TL, m, m, m, c->wdup, st));
+    if ((s = rotate(BYpl, c->TL, c->Rpl, -1.0, c->Rpl)) != CHFSI_OK) return s;
+  }
   // residual norms: r_j^2 = ||Re R_j||^2 + ||Im R_j||^2
   CK(column_norms(c->Rpl, n, n, m, c->norms, st));
   CK(check_finite(c->wdup, m, c->dflags + 2, st));
@@ -1908,6 +1949,11 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     if (c->bloch) {
       if (!f64 && d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
       if (!f64 && A->field_mode != 0) c->Vf = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+      c->nbnd = bloch_boundary_points(A->nx, A->ny, A->nz);
+      c->bcorr = ctx_alloc<char>(c, size_t(c->nbnd) * 2 * b * el, &st);
+      const size_t sel = params->filter_prec == CHFSI_PREC_BF16 ? sizeof(uint16_t) : el;
+      for (auto& e : c->bedge)
+        e = ctx_alloc<char>(c, size_t(2) * A->ny * A->nz * 2 * b * sel, &st);
     } else {
       c->Lc = ctx_alloc<char>(c, size_t(n) * 2 * n * lel, &st);
       c->dinv2 = ctx_alloc<char>(c, size_t(2) * n * el, &st);

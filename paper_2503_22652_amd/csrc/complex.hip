@@ -151,22 +151,26 @@ __global__ __launch_bounds__(kThreads) void k_from_planar(const double* __restri
 }
 
 // The real embedding M(G) = [[G_r, -G_i], [G_i, G_r]] (2b x 2b, ld 2b) of
-// G = Y^H W from P = [Y_r Y_i]^T [W_r W_i] (2b x 2b, ld 2b):
-// G_r = P11 + P22, G_i = P12 - P21; symmetrised, (M + M^T) / 2.
-__global__ __launch_bounds__(kThreads) void k_embed_gram(const double* __restrict__ P, int64_t b,
-                                                         double* __restrict__ M) {
-  const int64_t m = 2 * b, total = m * m;
-  auto emb = [&](int64_t r, int64_t c) {
-    const int64_t i = r % b, j = c % b;
-    const double gr = P[i + j * m] + P[(b + i) + (b + j) * m];
-    const double gi = P[i + (b + j) * m] - P[(b + i) + j * m];
-    const bool top = r < b, left = c < b;
-    return top == left ? gr : (top ? -gi : gi);
-  };
+// G = Y^H W, G_r = P11 + P22 and G_i = P12 - P21 with P11 = Y_r^T W_r,
+// P22 = Y_i^T W_i, P12 = Y_r^T W_i, P21 = Y_i^T W_r.  For a Hermitian
+// operator G_r is symmetric and G_i antisymmetric, so the lower triangles
+// (i >= j) of the four b x b blocks (consecutive in P4, ld b) determine M,
+// which comes out exactly symmetric.
+__global__ __launch_bounds__(kThreads) void k_embed_gram_lower(const double* __restrict__ P4,
+                                                               int64_t b,
+                                                               double* __restrict__ M) {
+  const int64_t m = 2 * b, total = m * m, bb = b * b;
   for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
        idx += int64_t(gridDim.x) * kThreads) {
     const int64_t c = idx / m, r = idx - c * m;
-    M[r + c * m] = 0.5 * (emb(r, c) + emb(c, r));
+    const int64_t i = r % b, j = c % b;
+    const int64_t lo = i >= j ? i + j * b : j + i * b;     // lower-triangle entry
+    const double gr = P4[lo] + P4[bb + lo];
+    double gi = P4[2 * bb + lo] - P4[3 * bb + lo];
+    if (i == j) gi = 0.0;
+    if (i < j) gi = -gi;
+    const bool top = r < b, left = c < b;
+    M[r + c * m] = top == left ? gr : (top ? -gi : gi);
   }
 }
 
@@ -197,8 +201,8 @@ hipError_t planar_to_cplx(const double* P, int64_t n, int64_t b, double* Z, int6
   return hipGetLastError();
 }
 
-hipError_t embed_gram(const double* P, int64_t b, double* M, hipStream_t st) {
-  k_embed_gram<<<grid_for(4 * b * b), kThreads, 0, st>>>(P, b, M);
+hipError_t embed_gram_lower(const double* P4, int64_t b, double* M, hipStream_t st) {
+  k_embed_gram_lower<<<grid_for(4 * b * b), kThreads, 0, st>>>(P4, b, M);
   return hipGetLastError();
 }
 

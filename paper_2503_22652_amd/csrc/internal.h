@@ -124,9 +124,11 @@ hipError_t cplx_to_planar(const double* Z, int64_t ldz, int64_t n, int64_t b, do
                           hipStream_t st);
 hipError_t planar_to_cplx(const double* P, int64_t n, int64_t b, double* Z, int64_t ldz,
                           hipStream_t st);
-// M (2b x 2b, ld 2b) = symmetrised real embedding [[G_r, -G_i], [G_i, G_r]] of
-// G = Y^H W, from P = [Y_r Y_i]^T [W_r W_i] (2b x 2b, ld 2b)
-hipError_t embed_gram(const double* P, int64_t b, double* M, hipStream_t st);
+// M (2b x 2b, ld 2b) = the real embedding [[G_r, -G_i], [G_i, G_r]] of the
+// Hermitian G = Y^H W from the lower triangles of the four b x b blocks
+// P11 = Y_r^T W_r, P22 = Y_i^T W_i, P12 = Y_r^T W_i, P21 = Y_i^T W_r of
+// [Y_r Y_i]^T [W_r W_i] (consecutive in P4, ld b)
+hipError_t embed_gram_lower(const double* P4, int64_t b, double* M, hipStream_t st);
 // Zx (b x 2b planar, ld b): column j = T(0:b, 2j), column b+j = T(b:2b, 2j)
 // of the 2b x 2b eigenvector matrix T of an embedded problem
 hipError_t select_pairs(const double* T, int64_t b, double* Zx, hipStream_t st);
@@ -142,10 +144,12 @@ struct Twist {
 };
 // number of grid points with a neighbour across a periodic face
 int64_t bloch_boundary_points(int nx, int ny, int nz);
-// planar RY = scale D R, RX = 0, Yc = D R from the interleaved residual
+// planar RY = scale D R, RX = 0, Yc = D R from the interleaved residual; E
+// (may be null) receives RY's x = 0 and x = nx-1 values, ((z ny + y) 2 +
+// (x == nx-1)) per column, ld 2 n / nx
 template <typename F>
 hipError_t bloch_init(const double* R, int64_t ldr, int64_t n, int64_t b, double scale, F* RY,
-                      F* RX, F* Yc, const Twist& tw, hipStream_t st);
+                      F* RX, F* Yc, const Twist& tw, hipStream_t st, F* E = nullptr);
 // interleaved Yp = D^* (dinv .* RY) + X diag(lamY)
 template <typename F>
 hipError_t bloch_reconstruct(const F* RY, const double* dinv, const double* X, int64_t ldx,
@@ -156,12 +160,7 @@ hipError_t bloch_to_planar(const double* Z, int64_t ldz, int64_t n, int64_t b, d
                            const Twist& tw, hipStream_t st);
 hipError_t bloch_from_planar(const double* P, int64_t n, int64_t b, double* Z, int64_t ldz,
                              const Twist& tw, hipStream_t st);
-// dst += alpha (A_tw - A_per)(dinv .* src) at the boundary points, for the b
-// column pairs of the planar blocks src (ld lds) and dst (ld ldd); op's
-// coefficients, field (mode 2) and bloch vector define A (dinv null: identity)
-template <typename F>
-hipError_t bloch_fix(const chfsi_operator& op, const double* dinv, double alpha, const F* src,
-                     int64_t lds, F* dst, int64_t ldd, int64_t b, hipStream_t st);
+// (the boundary correction kernels are declared with the grid kernels, stencil_api.h)
 
 // ---------------------------------------------------------------------------
 // Elementwise / reduction kernels (blas1.hip)

@@ -438,8 +438,12 @@ __global__ __launch_bounds__(256) void k_stencil_sep(SepArgs<F> a) {
 // same XCD, where the rows they share hit that XCD's L2.
 // ---------------------------------------------------------------------------
 // ZM_STEP: residual-filter step, e1 and e2 both present; ZM_CSTEP: plain
-// Chebyshev step, e1 optional, no e2.
-enum ZmKind { ZM_APPLY = 0, ZM_RESID = 1, ZM_STEP = 2, ZM_CSTEP = 3 };
+// Chebyshev step, e1 optional, no e2; ZM_BSTEP: ZM_STEP plus a precomputed
+// correction at the grid's boundary points (Bloch-phase operators in the
+// twisted frame: corr holds, per column, one value per boundary point in the
+// enumeration of bloch.hip -- both z faces, the y = 0 / ny-1 rows of the
+// inner planes, the x = 0 / nx-1 points of the inner rows).
+enum ZmKind { ZM_APPLY = 0, ZM_RESID = 1, ZM_STEP = 2, ZM_CSTEP = 3, ZM_BSTEP = 4 };
 
 template <typename F>
 struct ZmArgs {
@@ -462,6 +466,10 @@ struct ZmArgs {
   int64_t ld_e2;
   F delta;
   const F* colcoef;          // ZM_STEP: per-column factor of e2; ZM_RESID: lambda_j
+  const F* corr;             // ZM_BSTEP: boundary correction, column-major, ld ld_corr
+  int64_t ld_corr;
+  void* edge_out;            // ZM_BSTEP (may be null): the output's x = 0 and x = nx-1
+                             // values, ((z ny + y) 2 + (x == nx-1)) per column, ld 2 ny nz
 };
 
 template <typename S, typename F, int PT>
@@ -624,6 +632,7 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
 
   // per-column coefficients on u (RESID subtracts lambda_j times B's) and the
   // step's per-column factor of e2
+  constexpr bool STEPK = KIND == ZM_STEP || KIND == ZM_BSTEP;
   F cu[CP][4], dcol[CP];
 #pragma unroll
   for (int c = 0; c < CP; ++c) {
@@ -631,7 +640,7 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
     const F lam = (KIND == ZM_RESID && have) ? a.colcoef[col0 + c] : F(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) cu[c][k] = KIND == ZM_RESID ? a.cu[k] - lam * a.cb[k] : a.cu[k];
-    dcol[c] = (KIND == ZM_STEP && have) ? a.delta * a.colcoef[col0 + c] : F(0);
+    dcol[c] = (STEPK && have) ? a.delta * a.colcoef[col0 + c] : F(0);
   }
 
   // three rows x (PT + 2) values around this thread's points in one staged
@@ -706,11 +715,11 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
     e2c[c] = e2p ? e2p + int64_t(col0 + c) * a.ld_e2 : nullptr;
     outc[c] = static_cast<S*>(a.out) + int64_t(col0 + c) * a.ld_out;
   }
-  constexpr bool HAS_E = KIND == ZM_STEP || KIND == ZM_CSTEP;
+  constexpr bool HAS_E = STEPK || KIND == ZM_CSTEP;
   auto load_e = [&](int z, Extra& E) __attribute__((always_inline)) {
     if (!active) return;
     const uint32_t gb = uint32_t(z) * uint32_t(pstride) * uint32_t(sizeof(S)) + own_b;
-    if constexpr (KIND == ZM_STEP) {
+    if constexpr (STEPK) {
 #pragma unroll
       for (int c = 0; c < CP; ++c) {
         if (!ONE_COL && c >= ncol) continue;
@@ -796,8 +805,35 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
         F ck[PT], nk[PT], cmv[PT], nmv[PT];
         combos(buf, c, ck, nk, cmv, nmv);
         if (ONE_COL || c < ncol) {
-          F e1v[PT], e2v[PT];
-          if constexpr (KIND == ZM_STEP) {
+          F e1v[PT], e2v[PT], cv[PT];
+#pragma unroll
+          for (int i = 0; i < PT; ++i) cv[i] = F(0);
+          if constexpr (KIND == ZM_BSTEP) {
+            // boundary correction of this thread's points in plane z
+            const int gy = y0 + my_row;
+            const F* cc = a.corr + int64_t(col0 + c) * a.ld_corr;
+            int64_t t0;
+            bool full = true;
+            if (z == 0) {
+              t0 = int64_t(gy) * nx + xq;
+            } else if (z == nz - 1) {
+              t0 = pstride + int64_t(gy) * nx + xq;
+            } else if (gy == 0 || gy == ny - 1) {
+              t0 = 2 * pstride + int64_t(z - 1) * 2 * nx + (gy == 0 ? 0 : nx) + xq;
+            } else {
+              full = false;
+              t0 = 2 * pstride + int64_t(2) * nx * (nz - 2) + int64_t(z - 1) * 2 * (ny - 2) +
+                   2 * (gy - 1);
+            }
+            if (full) {
+#pragma unroll
+              for (int i = 0; i < PT; ++i) cv[i] = cc[t0 + i];
+            } else {
+              if (xq == 0) cv[0] = cc[t0];
+              if (xq + PT == nx) cv[PT - 1] = cc[t0 + 1];
+            }
+          }
+          if constexpr (STEPK) {
             zm_cvt<S, F, PT>(E.e1[c], e1v);
             zm_cvt<S, F, PT>(E.e2[c], e2v);
           } else if constexpr (KIND == ZM_CSTEP) {
@@ -814,10 +850,20 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
             F v = accK[c][i] + nk[i];
             if constexpr (HASV) v += vc[i] * (accM[c][i] + nmv[i]);
             if constexpr (HAS_E) v += a.gamma * e1v[i];
-            if constexpr (KIND == ZM_STEP) v += dcol[c] * e2v[i];
+            if constexpr (STEPK) v += dcol[c] * e2v[i];
+            if constexpr (KIND == ZM_BSTEP) v += cv[i];
             o[i] = zm_store_elem<S, F>(v);
           }
           *reinterpret_cast<SV*>(reinterpret_cast<char*>(outc[c]) + ob) = o;
+          if constexpr (KIND == ZM_BSTEP) {
+            // the row-end values, for the next step's wrap correction
+            if (a.edge_out && (xq == 0 || xq + PT == nx)) {
+              S* eo = static_cast<S*>(a.edge_out) + int64_t(col0 + c) * (int64_t(2) * ny * nz) +
+                      (int64_t(z) * ny + (y0 + my_row)) * 2;
+              if (xq == 0) eo[0] = o[0];
+              if (xq + PT == nx) eo[1] = o[PT - 1];
+            }
+          }
         }
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
@@ -1109,7 +1155,8 @@ hipError_t stencil_apply_f64(const chfsi_operator& op, const double* X, int64_t 
 hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* RY,
                                    double* RX, const double* Yf, int64_t ldf,
                                    const double* colcoef, StencilStep s, int64_t b,
-                                   hipStream_t st) {
+                                   hipStream_t st, const BlochStep* bloch) {
+  if (bloch && b % 2 != 0) return hipErrorInvalidValue;
   ZmArgs<double> z;
   if (!dinv && RX && Yf && zm_setup(op, 2, zm_per_wg(false), s.alpha, s.beta, &z) &&
       zm_aligned(RY, op.n, 16, 2) && zm_aligned(RX, op.n, 16, 2) && zm_aligned(Yf, ldf, 16, 2) &&
@@ -1127,6 +1174,17 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
     z.ld_e2 = ldf;
     z.delta = s.delta;
     z.colcoef = colcoef;
+    if (bloch) {
+      double* corr = static_cast<double*>(bloch->corr);
+      const hipError_t e = bloch_corr<double, double>(
+          op, bloch->dinv, s.alpha, RY, op.n, static_cast<const double*>(bloch->edge_in), corr,
+          bloch->ld_corr, b / 2, st);
+      if (e != hipSuccess) return e;
+      z.corr = corr;
+      z.ld_corr = bloch->ld_corr;
+      z.edge_out = bloch->edge_out;
+      return zm_launch<double, double, 2, ZM_BSTEP>(z, op.field_mode != 0, st);
+    }
     return zm_launch<double, double, 2, ZM_STEP>(z, op.field_mode != 0, st);
   }
   SepArgs<double> a;
@@ -1143,16 +1201,22 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
     a.beta = s.beta;
     a.gamma = s.gamma;
     a.delta = s.delta;
-    return sep_launch<double, double, SK_RSTEP>(a, b, st);
+    const hipError_t e = sep_launch<double, double, SK_RSTEP>(a, b, st);
+    if (e != hipSuccess || !bloch) return e;
+  } else {
+    k_rstep_f64<<<grid_for(op.n * b), 256, 0, st>>>(make_coefs_d(op), make_grid(op), dinv, RY,
+                                                    RX, Yf, ldf, colcoef, s, op.n, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !bloch) return e;
   }
-  k_rstep_f64<<<grid_for(op.n * b), 256, 0, st>>>(make_coefs_d(op), make_grid(op), dinv, RY, RX,
-                                                  Yf, ldf, colcoef, s, op.n, b);
-  return hipGetLastError();
+  return bloch_fix<double>(op, bloch->dinv, s.alpha, RY, op.n, RX, op.n, b / 2, st);
 }
 
 hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, const float* dinv,
                                    const float* RY, float* RX, const float* Yf,
-                                   const float* colcoef, StencilStep s, int64_t b, hipStream_t st) {
+                                   const float* colcoef, StencilStep s, int64_t b, hipStream_t st,
+                                   const BlochStep* bloch) {
+  if (bloch && b % 2 != 0) return hipErrorInvalidValue;
   ZmArgs<float> z;
   const int pt = zm_pt_lowp();
   const size_t vb = size_t(pt) * sizeof(float);
@@ -1172,6 +1236,18 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, co
     z.ld_e2 = op.n;
     z.delta = float(s.delta);
     z.colcoef = colcoef;
+    if (bloch) {
+      float* corr = static_cast<float*>(bloch->corr);
+      const hipError_t e = bloch_corr<float, float>(
+          op, bloch->dinv, s.alpha, RY, op.n, static_cast<const float*>(bloch->edge_in), corr,
+          bloch->ld_corr, b / 2, st);
+      if (e != hipSuccess) return e;
+      z.corr = corr;
+      z.ld_corr = bloch->ld_corr;
+      z.edge_out = bloch->edge_out;
+      return pt == 2 ? zm_launch<float, float, 2, ZM_BSTEP>(z, op.field_mode != 0, st)
+                     : zm_launch<float, float, 4, ZM_BSTEP>(z, op.field_mode != 0, st);
+    }
     return pt == 2 ? zm_launch<float, float, 2, ZM_STEP>(z, op.field_mode != 0, st)
                    : zm_launch<float, float, 4, ZM_STEP>(z, op.field_mode != 0, st);
   }
@@ -1189,18 +1265,25 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, co
     a.beta = float(s.beta);
     a.gamma = float(s.gamma);
     a.delta = float(s.delta);
-    return sep_launch<float, float, SK_RSTEP>(a, b, st);
+    const hipError_t e = sep_launch<float, float, SK_RSTEP>(a, b, st);
+    if (e != hipSuccess || !bloch) return e;
+  } else {
+    k_rstep_f32<<<grid_for(op.n * b), 256, 0, st>>>(make_coefs_f(op), make_grid(op), dinv, RY,
+                                                    RX, Yf, colcoef, float(s.alpha),
+                                                    float(s.beta), float(s.gamma),
+                                                    float(s.delta), op.n, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !bloch) return e;
   }
-  k_rstep_f32<<<grid_for(op.n * b), 256, 0, st>>>(make_coefs_f(op), make_grid(op), dinv, RY, RX,
-                                                  Yf, colcoef, float(s.alpha), float(s.beta),
-                                                  float(s.gamma), float(s.delta), op.n, b);
-  return hipGetLastError();
+  return bloch_fix<float>(op, bloch->dinv, s.alpha, RY, op.n, RX, op.n, b / 2, st);
 }
 
 hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, const float* dinv,
                                     const void* RY, void* RX, const void* Yf,
                                     const float* colcoef, StencilStep s, int64_t b,
-                                    hipStream_t st) {
+                                    hipStream_t st, const BlochStep* bloch) {
+  if (bloch && b % 2 != 0) return hipErrorInvalidValue;
+  const uint16_t* RY16 = static_cast<const uint16_t*>(RY);
   ZmArgs<float> z;
   const int pt = zm_pt_lowp();
   const size_t vb = size_t(pt) * 2, vf = size_t(pt) * sizeof(float);
@@ -1220,6 +1303,18 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, c
     z.ld_e2 = op.n;
     z.delta = float(s.delta);
     z.colcoef = colcoef;
+    if (bloch) {
+      float* corr = static_cast<float*>(bloch->corr);
+      const hipError_t e = bloch_corr<uint16_t, float>(
+          op, bloch->dinv, s.alpha, RY16, op.n, static_cast<const uint16_t*>(bloch->edge_in), corr,
+          bloch->ld_corr, b / 2, st);
+      if (e != hipSuccess) return e;
+      z.corr = corr;
+      z.ld_corr = bloch->ld_corr;
+      z.edge_out = bloch->edge_out;
+      return pt == 2 ? zm_launch<uint16_t, float, 2, ZM_BSTEP>(z, op.field_mode != 0, st)
+                     : zm_launch<uint16_t, float, 4, ZM_BSTEP>(z, op.field_mode != 0, st);
+    }
     return pt == 2 ? zm_launch<uint16_t, float, 2, ZM_STEP>(z, op.field_mode != 0, st)
                    : zm_launch<uint16_t, float, 4, ZM_STEP>(z, op.field_mode != 0, st);
   }
@@ -1237,13 +1332,18 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, c
     a.beta = float(s.beta);
     a.gamma = float(s.gamma);
     a.delta = float(s.delta);
-    return sep_launch<uint16_t, float, SK_RSTEP>(a, b, st);
+    const hipError_t e = sep_launch<uint16_t, float, SK_RSTEP>(a, b, st);
+    if (e != hipSuccess || !bloch) return e;
+  } else {
+    k_rstep_bf16<<<grid_for(op.n * b), 256, 0, st>>>(
+        make_coefs_f(op), make_grid(op), dinv, RY16, static_cast<uint16_t*>(RX),
+        static_cast<const uint16_t*>(Yf), colcoef, float(s.alpha), float(s.beta),
+        float(s.gamma), float(s.delta), op.n, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !bloch) return e;
   }
-  k_rstep_bf16<<<grid_for(op.n * b), 256, 0, st>>>(
-      make_coefs_f(op), make_grid(op), dinv, static_cast<const uint16_t*>(RY),
-      static_cast<uint16_t*>(RX), static_cast<const uint16_t*>(Yf), colcoef, float(s.alpha),
-      float(s.beta), float(s.gamma), float(s.delta), op.n, b);
-  return hipGetLastError();
+  return bloch_fix<uint16_t>(op, bloch->dinv, s.alpha, RY16, op.n, static_cast<uint16_t*>(RX),
+                             op.n, b / 2, st);
 }
 
 hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* src,

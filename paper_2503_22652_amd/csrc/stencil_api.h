@@ -15,6 +15,37 @@ struct StencilStep {
 };
 
 hipError_t stencil_check(const chfsi_operator& op);
+
+// Bloch-phase operators in the twisted frame (bloch.hip).  Planar blocks of
+// `pairs` complex columns (real parts, then imaginary parts; 2 x pairs
+// columns).  The correction (A_tw - A_per) psi (p) = sum over the offsets o
+// wrapped at p of w(p, o) (phi(o) - 1) psi(p + o), phi the wrap phase, is
+// nonzero at the n - (nx-2)(ny-2)(nz-2) boundary points only.
+// dst += alpha * colscale[j] * correction of (dinv .* src) for column pair j,
+// in place (dinv NULL: identity; colscale NULL: ones; both device arrays)
+template <typename F>
+hipError_t bloch_fix(const chfsi_operator& op, const double* dinv, double alpha, const F* src,
+                     int64_t lds, F* dst, int64_t ldd, int64_t pairs, hipStream_t st,
+                     const double* colscale = nullptr);
+// corr (boundary points x 2 pairs, ld ldc >= boundary points) = alpha *
+// correction of (dinv .* src), in the boundary-point enumeration of bloch.hip.
+// edge (may be null): src's x = 0 and x = nx-1 values, ((z ny + y) 2 +
+// (x == nx-1)) per column, ld 2 ny nz; the x-face points then read their
+// wrapped neighbours there instead of gathering them from src.
+template <typename T, typename C>
+hipError_t bloch_corr(const chfsi_operator& op, const double* dinv, double alpha, const T* src,
+                      int64_t lds, const T* edge, C* corr, int64_t ldc, int64_t pairs,
+                      hipStream_t st);
+// A residual-filter step on a Bloch operator's planar block adds the
+// correction: through `corr` in the z-marching kernel's epilogue, else by
+// bloch_fix after the step.
+struct BlochStep {
+  void* corr;          // boundary points x b buffer in the step's arithmetic type
+  int64_t ld_corr;
+  const double* dinv;  // FP64 D^{-1} of the correction (NULL: identity)
+  const void* edge_in; // row-end values of RY (storage type; may be null)
+  void* edge_out;      // receives the row-end values of the step's output (may be null)
+};
 // nominal flops per element and step (for reporting)
 double stencil_flops(const chfsi_operator& op);
 
@@ -27,17 +58,20 @@ hipError_t stencil_apply_f64(const chfsi_operator& op, const double* X, int64_t 
 hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* RY,
                                    double* RX, const double* Yf, int64_t ldf,
                                    const double* colcoef, StencilStep s, int64_t b,
-                                   hipStream_t st);
+                                   hipStream_t st,
+                                   const BlochStep* bloch = nullptr);
 // Vf: the potential in FP32 (length n; may be NULL when the operator has no
 // field); dinv: NULL for D^{-1} = I.
 hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, const float* dinv,
                                    const float* RY, float* RX, const float* Yf,
-                                   const float* colcoef, StencilStep s, int64_t b, hipStream_t st);
+                                   const float* colcoef, StencilStep s, int64_t b, hipStream_t st,
+                                   const BlochStep* bloch = nullptr);
 // BF16-stored blocks (uint16 bit patterns), FP32 arithmetic
 hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, const float* dinv,
                                     const void* RY, void* RX, const void* Yf,
                                     const float* colcoef, StencilStep s, int64_t b,
-                                    hipStream_t st);
+                                    hipStream_t st,
+                                   const BlochStep* bloch = nullptr);
 // Plain filter step (Algorithm 2): dst <- alpha dinv .* op(src) + beta src + gamma prev
 hipError_t stencil_chfsi_step_f64(const chfsi_operator& op, const double* dinv, const double* src,
                                   int64_t lds, const double* prev, int64_t ldp, double* dst,

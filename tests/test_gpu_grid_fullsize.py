@@ -55,3 +55,46 @@ def test_bf16_grid_filter_fullsize_sampled_columns():
     print("per-column err / residual part:", err / part)
     assert np.all(np.isfinite(got))
     assert np.all(err <= 1e-1 * part)
+
+
+def test_bf16_bloch_grid_filter_fullsize_sampled_columns():
+    """The same pencil at wave vector k = (0.013, -0.021, 0.034) (complex, Section
+    4.3) with 600 complex vectors -- the 1200 planar columns of the real case --
+    as bench.py's grid workload with --bloch times it."""
+    k = (0.013, -0.021, 0.034)
+    torch.cuda.empty_cache()          # the complex context needs about 175 GiB
+    prob = wl.stencil_problem()
+    shape, b = prob.shape, prob.block // 2
+    n = int(np.prod(shape))
+    apply_A, _ = stencil.make_ops_bloch(prob.coef_A, prob.coef_B, prob.V, shape, prob.field_mode,
+                                        k)
+    Vd = torch.from_numpy(np.ascontiguousarray(prob.V).reshape(-1)).cuda()
+    opA = P.stencil_operator(shape, prob.coef_A, coef_mass=prob.coef_B, field=Vd,
+                             field_mode=prob.field_mode, bloch=k)
+    opB = P.stencil_operator(shape, prob.coef_B, bloch=k)
+    prm = P.make_params(prob.n_wanted // 2, b, prob.degree, method=P.METHOD_RCHFSI,
+                        filter_prec=P.PREC_BF16, lambda_max=18.5)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2003)
+    X = torch.randn((b, n), dtype=torch.complex128, device="cuda", generator=g).t()
+    R = torch.randn((b, n), dtype=torch.complex128, device="cuda", generator=g).t().mul_(1e-3)
+    lam = np.sort(np.random.default_rng(2003).uniform(-4.0, 1.0, b))
+    bounds = (lam[0] - 0.5, 18.5, lam[-1])
+    Y = P.colmajor_empty_complex(n, b)
+    print("Bloch grid 128^3 b=600 complex BF16 filter, degree 4", flush=True)
+    P.chfsi_filter(ctx, X, lam, R, Y, *bounds, degree=4)
+    torch.cuda.synchronize()
+    cols = [0, 1, 2, 3, b - 1]
+    Xc = X[:, cols].cpu().numpy()
+    Rc = R[:, cols].cpu().numpy()
+    got = Y[:, cols].cpu().numpy()
+    del X, R, Y
+    ctx.close()
+    ref, RYp, _ = filters.residual_filter(apply_A, filters.identity_op(), Xc, lam[cols], Rc, 4,
+                                          *bounds, return_parts=True)
+    err = np.linalg.norm(got - ref, axis=0)
+    part = np.linalg.norm(RYp, axis=0)
+    print("per-column err / residual part:", err / part)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= 1e-1 * part)
