@@ -442,7 +442,7 @@ def bench_grid(args):
                         "traffic_unit": "bytes per launch",
                         "kernel": f"k_zmarch<{args.prec}> residual-filter step "
                                   f"(4 streams x {esize} B per element-step)" +
-                                  (" + k_bloch_fix boundary pass" if kvec else ""),
+                                  (" + k_bloch boundary-correction pass" if kvec else ""),
                         "ms_per_launch": round(per, 3)}}
     if args.ttr:
         # time to max residual < tau over the wanted pairs, from the same random

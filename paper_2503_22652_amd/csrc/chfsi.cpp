@@ -104,8 +104,8 @@ struct chfsi_ctx {
   // operand Z~ (2n x 2b, FP32/FP64) and its bfloat16 copy (BF16)
   bool cplx = false;
   bool bloch = false;             // Bloch-phase grid operator (twisted frame, planar blocks)
-  void* bcorr = nullptr;          // its filter step's boundary correction (boundary points x 2b)
-  int64_t nbnd = 0;
+  void* bcorr = nullptr;          // its filter step's boundary correction (nbnd x 2b)
+  int64_t nbnd = 0;               // boundary points rounded up to a multiple of 4
   void* bedge[2] = {nullptr, nullptr};   // row-end values of the filter blocks (2 ny nz x 2b)
   void* Lc = nullptr;
   void* dinv2 = nullptr;
@@ -385,7 +385,7 @@ SizePlan plan_sizes_bloch(const chfsi_operator* A, const chfsi_operator* B, cons
     s.a32 = size_t(n) * sizeof(float) * (1 + (A->field_mode != 0 ? 1 : 0));
   // the boundary correction, in the step's arithmetic type, and two copies of
   // the blocks' row ends
-  s.a32 += size_t(bloch_boundary_points(A->nx, A->ny, A->nz)) * 2 * b *
+  s.a32 += size_t((bloch_boundary_points(A->nx, A->ny, A->nz) + 3) / 4 * 4) * 2 * b *
                (p->filter_prec == CHFSI_PREC_FP64 ? sizeof(double) : sizeof(float)) +
            size_t(2) * 2 * A->ny * A->nz * 2 * b * el;
   s.coef = size_t(p->degree + 1) * 2 * b * sizeof(double);
@@ -809,7 +809,8 @@ chfsi_status filter_rchfsi_complex(chfsi_ctx* c, const double* X, int64_t ldx, c
                         bytes, hipMemcpyHostToDevice, c->stream));
     }
     CK(hipEventRecord(c->ev_stage, c->stream));
-    const double step_fl = (stencil_flops(c->A) * double(n) + 27.0 * 8.0 * double(c->nbnd)) *
+    const double step_fl = (stencil_flops(c->A) * double(n) +
+                            27.0 * 8.0 * double(bloch_boundary_points(c->A.nx, c->A.ny, c->A.nz))) *
                            double(b2);
     // the boundary correction goes through the z-march's epilogue when it
     // runs the step, else it is added in place after the step
@@ -1949,7 +1950,9 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     if (c->bloch) {
       if (!f64 && d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
       if (!f64 && A->field_mode != 0) c->Vf = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
-      c->nbnd = bloch_boundary_points(A->nx, A->ny, A->nz);
+      // leading dimension of the correction: the boundary point count rounded
+      // up to a multiple of 4 (aligned vector loads in the z-march)
+      c->nbnd = (bloch_boundary_points(A->nx, A->ny, A->nz) + 3) / 4 * 4;
       c->bcorr = ctx_alloc<char>(c, size_t(c->nbnd) * 2 * b * el, &st);
       const size_t sel = params->filter_prec == CHFSI_PREC_BF16 ? sizeof(uint16_t) : el;
       for (auto& e : c->bedge)

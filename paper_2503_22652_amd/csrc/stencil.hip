@@ -500,7 +500,11 @@ __device__ __forceinline__ const T* zm_byte_off(const T* p, uint32_t bytes) {
 }
 
 template <typename S, typename F, int PT, int CP, int NG, int KIND, bool HASV>
-__global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
+// (the BF16 Bloch step is held to 96 VGPRs, five waves per SIMD like the
+// plain step; unconstrained it takes 97 and drops to four)
+__global__ __launch_bounds__(256 * NG)
+__attribute__((amdgpu_waves_per_eu(KIND == ZM_BSTEP && sizeof(S) == 2 ? 5 : 1)))
+void k_zmarch(ZmArgs<F> a) {
   using SV = S __attribute__((ext_vector_type(PT)));
   using FV = F __attribute__((ext_vector_type(PT)));
   extern __shared__ __attribute__((aligned(16))) unsigned char zm_smem[];
@@ -809,26 +813,23 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
 #pragma unroll
           for (int i = 0; i < PT; ++i) cv[i] = F(0);
           if constexpr (KIND == ZM_BSTEP) {
-            // boundary correction of this thread's points in plane z
+            // boundary correction of this thread's points in plane z (32-bit
+            // offsets: the boundary has fewer than 2^31 points; ld_corr is a
+            // multiple of 4, so a full row's PT values are one aligned load)
             const int gy = y0 + my_row;
             const F* cc = a.corr + int64_t(col0 + c) * a.ld_corr;
-            int64_t t0;
-            bool full = true;
-            if (z == 0) {
-              t0 = int64_t(gy) * nx + xq;
-            } else if (z == nz - 1) {
-              t0 = pstride + int64_t(gy) * nx + xq;
-            } else if (gy == 0 || gy == ny - 1) {
-              t0 = 2 * pstride + int64_t(z - 1) * 2 * nx + (gy == 0 ? 0 : nx) + xq;
-            } else {
-              full = false;
-              t0 = 2 * pstride + int64_t(2) * nx * (nz - 2) + int64_t(z - 1) * 2 * (ny - 2) +
-                   2 * (gy - 1);
-            }
-            if (full) {
+            const uint32_t face = uint32_t(pstride);
+            if (z == 0 || z == nz - 1 || gy == 0 || gy == ny - 1) {
+              const uint32_t t0 =
+                  z == 0        ? uint32_t(gy * nx + xq)
+                  : z == nz - 1 ? face + uint32_t(gy * nx + xq)
+                                : 2 * face + uint32_t((z - 1) * 2 * nx + (gy == 0 ? 0 : nx) + xq);
+              const FV w = *reinterpret_cast<const FV*>(cc + t0);
 #pragma unroll
-              for (int i = 0; i < PT; ++i) cv[i] = cc[t0 + i];
-            } else {
+              for (int i = 0; i < PT; ++i) cv[i] = w[i];
+            } else if (xq == 0 || xq + PT == nx) {
+              const uint32_t t0 = 2 * face + uint32_t(2 * nx * (nz - 2)) +
+                                  uint32_t((z - 1) * 2 * (ny - 2) + 2 * (gy - 1));
               if (xq == 0) cv[0] = cc[t0];
               if (xq + PT == nx) cv[PT - 1] = cc[t0 + 1];
             }
@@ -858,10 +859,10 @@ __global__ __launch_bounds__(256 * NG) void k_zmarch(ZmArgs<F> a) {
           if constexpr (KIND == ZM_BSTEP) {
             // the row-end values, for the next step's wrap correction
             if (a.edge_out && (xq == 0 || xq + PT == nx)) {
-              S* eo = static_cast<S*>(a.edge_out) + int64_t(col0 + c) * (int64_t(2) * ny * nz) +
-                      (int64_t(z) * ny + (y0 + my_row)) * 2;
-              if (xq == 0) eo[0] = o[0];
-              if (xq + PT == nx) eo[1] = o[PT - 1];
+              S* eo = static_cast<S*>(a.edge_out) + int64_t(col0 + c) * (int64_t(2) * ny * nz);
+              const uint32_t e = uint32_t((z * ny + y0 + my_row) * 2);
+              if (xq == 0) eo[e] = o[0];
+              if (xq + PT == nx) eo[e + 1] = o[PT - 1];
             }
           }
         }
