@@ -164,3 +164,54 @@ def test_bloch_zero_wave_vector_matches_real_context():
     Xr, Rr = P.colmajor_empty(n, b), P.colmajor_empty(n, b)
     ritz_r, _ = P.chfsi_rayleigh_ritz(ctx_r, P.to_colmajor(Yr), Xr, Rr)
     np.testing.assert_allclose(ritz_c, ritz_r, rtol=0, atol=1e-11 * LMAX)
+
+
+@pytest.mark.parametrize("prec,tol", [(P.PREC_FP64, 1e-11), (P.PREC_FP32, 1e-4),
+                                      (P.PREC_BF16, 1e-1)])
+@pytest.mark.parametrize("shape", [(5, 20, 64), (6, 9, 10)])
+def test_bloch_filter_many_column_pairs(prec, tol, shape):
+    """37 complex vectors: the correction kernels take column pairs in chunks of
+    16 (16 + 16 + a ragged 5), in the fused z-march path (nx = 64) and the
+    in-place fallback (nx = 10)."""
+    apply_A, apply_B, opA, opB, Vd = _problem(shape, seed=17)
+    n = int(np.prod(shape))
+    b = 37
+    prm = P.make_params(30, b, 6, method=P.METHOD_RCHFSI, filter_prec=prec, lambda_max=LMAX)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    o = rr.rayleigh_ritz(wl.random_block_complex(n, b, 18), apply_A, apply_B)
+    bounds = (o["lam"][0] - 0.5, LMAX, o["lam"][-1])
+    Y = P.colmajor_empty_complex(n, b)
+    P.chfsi_filter(ctx, P.to_colmajor_complex(o["X"]), o["lam"], P.to_colmajor_complex(o["R"]),
+                   Y, *bounds, degree=6)
+    torch.cuda.synchronize()
+    got = Y.cpu().numpy()
+    ref, RYp, _ = filters.residual_filter(apply_A, filters.identity_op(), o["X"], o["lam"],
+                                          o["R"], 6, *bounds, return_parts=True)
+    err = np.linalg.norm(got - ref, axis=0)
+    part = np.linalg.norm(RYp, axis=0)
+    print("bloch b=37", shape, "prec", prec, "max per-column err / part", np.max(err / part))
+    if prec == P.PREC_FP64:
+        assert _rel(got, ref) <= tol
+    else:
+        assert np.all(err <= tol * part)
+
+
+def test_bloch_rayleigh_ritz_many_column_pairs():
+    """37 complex vectors: the residual's wrap corrections (with the per-column
+    Ritz values on B's) over several column-pair chunks."""
+    shape = (5, 20, 64)
+    apply_A, apply_B, opA, opB, Vd = _problem(shape, seed=19)
+    n = int(np.prod(shape))
+    b = 37
+    prm = P.make_params(30, b, 4, method=P.METHOD_RCHFSI, lambda_max=LMAX)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    Yh = wl.random_block_complex(n, b, 20)
+    X, R = P.colmajor_empty_complex(n, b), P.colmajor_empty_complex(n, b)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor_complex(Yh), X, R)
+    o = rr.rayleigh_ritz(Yh, apply_A, apply_B)
+    lam = np.array(ritz)
+    assert np.max(np.abs(lam - o["lam"])) <= 1e-11 * np.max(np.abs(o["lam"]))
+    Xg, Rg = X.cpu().numpy(), R.cpu().numpy()
+    Rref = apply_A(Xg) - apply_B(Xg) * lam[None, :]
+    assert np.linalg.norm(Rg - Rref) <= 1e-10 * LMAX
+    np.testing.assert_allclose(norms, np.linalg.norm(Rref, axis=0), rtol=1e-7, atol=1e-12)
