@@ -125,3 +125,69 @@ def test_cancel_and_admission():
         tiny.submit(req3, keep3)
     assert e.value.status == P.ERR_NOMEM
     tiny.close()
+
+
+def test_complex_requests_through_the_server():
+    """Complex requests (a Bloch grid pencil and a dense Hermitian pencil) carry
+    interleaved complex blocks: the server's start block, warm-start copy and
+    X_out hold n x b complex values.  Results match LAPACK on the assembled
+    pencils, and the warm-started second request of the grid sequence needs
+    fewer iterations."""
+    from oracle import stencil
+    shape, k = (6, 8, 10), (0.3, -0.7, 1.1)
+    V, _ = wl.gaussian_wells(shape, 1, np.random.default_rng(5))
+    cA, cB = 0.5 * wl.tensor_stencil_27("stiffness"), wl.tensor_stencil_27("mass")
+    apply_A, apply_B = stencil.make_ops_bloch(cA, cB, V, shape, 2, k)
+    n = int(np.prod(shape))
+    Ad, Bd = apply_A(np.eye(n)), apply_B(np.eye(n))
+    w_grid = sla.eigh(Ad, Bd, eigvals_only=True, subset_by_index=(0, 5))
+    Vd = torch.from_numpy(np.ascontiguousarray(V).reshape(-1)).cuda()
+    hp = wl.dense_hermitian(n=517, n_low=20, block=28, degree=12, seed=83)
+    w_herm = sla.eigh(hp.A, hp.B, eigvals_only=True, subset_by_index=(0, 19))
+    Ah, Bh = P.to_colmajor_complex(hp.A), P.to_colmajor_complex(hp.B)
+    dh = torch.from_numpy(hp.dinv).cuda()
+
+    def grid_request(X0=None, X_out=None):
+        req = P.chfsi_request()
+        req.A = P.stencil_operator(shape, cA, coef_mass=cB, field=Vd, field_mode=2, bloch=k)
+        req.B = P.stencil_operator(shape, cB, bloch=k)
+        req.params = P.make_params(6, 12, 16, max_iter=100, tol=1e-10, method=P.METHOD_RCHFSI,
+                                   filter_prec=P.PREC_BF16, lambda_max=18.5)
+        req.seq_id = 7
+        req.X0 = 0 if X0 is None else X0.data_ptr()
+        req.X_out = 0 if X_out is None else X_out.data_ptr()
+        return req
+
+    herm = P.chfsi_request()
+    herm.A = P.hermitian_operator(Ah)
+    herm.B = P.hermitian_operator(Bh)
+    herm.d_inv = dh.data_ptr()
+    herm.params = P.make_params(20, 28, 12, max_iter=60, tol=1e-10, method=P.METHOD_RCHFSI,
+                                filter_prec=P.PREC_FP32,
+                                lambda_max=10.0 / (0.95 * hp.meta["dmin"]) + 0.1)
+    herm.seq_id = -1
+    herm.X0 = 0
+    herm.X_out = 0
+
+    X0 = P.to_colmajor_complex(wl.random_block_complex(n, 12, 9))
+    Xo1, Xo2 = P.colmajor_empty_complex(n, 12), P.colmajor_empty_complex(n, 12)
+    srv = P.Server(slots=2)
+    t1 = srv.submit(grid_request(X0, Xo1), (Vd, X0, Xo1))
+    th = srv.submit(herm, (Ah, Bh, dh))
+    r1 = srv.wait(t1)
+    t2 = srv.submit(grid_request(None, Xo2), (Vd, Xo2))     # warm start from the sequence
+    r2 = srv.wait(t2)
+    rh = srv.wait(th)
+    srv.close()
+    print("grid cold", r1["iterations"], "warm", r2["iterations"], "hermitian", rh["iterations"])
+    for r in (r1, r2):
+        assert r["status"] == P.OK
+        assert np.max(np.abs(np.array(r["evals"][:6]) - w_grid)) <= 1e-10 * np.max(np.abs(w_grid))
+    assert r2["iterations"] < r1["iterations"]
+    assert rh["status"] == P.OK
+    assert np.max(np.abs(np.array(rh["evals"][:20]) - w_herm)) <= 1e-10 * np.max(np.abs(w_herm))
+    for Xo, r in ((Xo1, r1), (Xo2, r2)):
+        X = Xo.cpu().numpy()[:, :6]
+        lam = np.array(r["evals"][:6])
+        assert np.linalg.norm(X.conj().T @ Bd @ X - np.eye(6)) <= 1e-9
+        assert np.max(np.linalg.norm(Ad @ X - Bd @ X * lam[None, :], axis=0)) < 1e-9
