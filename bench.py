@@ -37,6 +37,10 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.4e6}
 # the same for the BF16 z-march filter step on the 128^3 grid, block 1200
 TRAFFIC_ZMARCH = {(128, 1200, "bf16"): 21.98e9}
+# HBM bytes per Bloch filter step at 128^3 x 600 complex vectors (BF16): the
+# corrected z-march plus the boundary-correction kernel (two counter passes,
+# profiles/grid_128_b600_bloch_bf16_step_traffic.md)
+TRAFFIC_BLOCH_STEP = {(128, 600, "bf16"): 24.18e9}
 
 
 def log(*a):
@@ -438,7 +442,8 @@ def bench_grid(args):
                       "max_residual_after": rep["max_residual"]},
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                        "traffic": TRAFFIC_ZMARCH.get((g, b, args.prec)),
+                        "traffic": (TRAFFIC_BLOCH_STEP if kvec else TRAFFIC_ZMARCH).get(
+                            (g, b, args.prec)),
                         "traffic_unit": "bytes per launch",
                         "kernel": f"k_zmarch<{args.prec}> residual-filter step "
                                   f"(4 streams x {esize} B per element-step)" +
