@@ -215,3 +215,52 @@ def test_bloch_rayleigh_ritz_many_column_pairs():
     Rref = apply_A(Xg) - apply_B(Xg) * lam[None, :]
     assert np.linalg.norm(Rg - Rref) <= 1e-10 * LMAX
     np.testing.assert_allclose(norms, np.linalg.norm(Rref, axis=0), rtol=1e-7, atol=1e-12)
+
+
+def test_bloch_padded_leading_dimensions_and_identity_b():
+    """B = I, blocks with ld > n: the filter, Rayleigh-Ritz and the solve read
+    and write only the n rows of each column."""
+    shape = (6, 8, 10)
+    apply_A, _, opA, _, Vd = _problem(shape, seed=5, wells=1)
+    n = int(np.prod(shape))
+    b, ld = 12, n + 13
+    w = np.linalg.eigvalsh(apply_A(np.eye(n)))[:6]
+
+    def padded(vals=None):
+        buf = torch.zeros((b, ld), dtype=torch.complex128, device="cuda")
+        t = buf.t()[:n]
+        if vals is not None:
+            t.copy_(P.to_colmajor_complex(vals))
+        assert t.stride(1) == ld
+        return buf, t
+
+    prm = P.make_params(6, b, 16, max_iter=100, tol=1e-10, method=P.METHOD_RCHFSI,
+                        filter_prec=P.PREC_FP32, lambda_max=2.1)
+    ctx = P.chfsi_create(opA, None, None, prm, keep=(Vd,))
+    # filter on padded blocks against the oracle
+    o = rr.rayleigh_ritz(wl.random_block_complex(n, b, 41), apply_A, filters.identity_op())
+    bounds = (o["lam"][0] - 0.5, 2.1, o["lam"][-1])
+    _, Xb = padded(o["X"])
+    _, Rb = padded(o["R"])
+    ybuf, Yb = padded()
+    P.chfsi_filter(ctx, Xb, o["lam"], Rb, Yb, *bounds, degree=16)
+    torch.cuda.synchronize()
+    ref, RYp, _ = filters.residual_filter(apply_A, filters.identity_op(), o["X"], o["lam"], o["R"],
+                                          16, *bounds, return_parts=True)
+    assert np.linalg.norm(Yb.cpu().numpy() - ref) <= 1e-4 * np.linalg.norm(RYp)   # B = I here
+    assert torch.all(ybuf.t()[n:] == 0)
+    # Rayleigh-Ritz on padded blocks
+    _, Yin = padded(wl.random_block_complex(n, b, 42))
+    xbuf, Xo = padded()
+    rbuf, Ro = padded()
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, Yin, Xo, Ro)
+    o2 = rr.rayleigh_ritz(Yin.cpu().numpy(), apply_A, filters.identity_op())
+    assert np.max(np.abs(np.array(ritz) - o2["lam"])) <= 1e-11 * np.max(np.abs(o2["lam"]))
+    assert torch.all(xbuf.t()[n:] == 0) and torch.all(rbuf.t()[n:] == 0)
+    # the solve
+    sbuf, Xs = padded(wl.random_block_complex(n, b, 9))
+    st, ev, rn, rep = P.chfsi_solve(ctx, Xs)
+    print("bloch B = I padded solve:", rep["iterations"], "iterations", rep["max_residual"])
+    assert st == P.OK
+    assert np.max(np.abs(np.array(ev[:6]) - w)) <= 1e-10 * np.max(np.abs(w))
+    assert torch.all(sbuf.t()[n:] == 0)
