@@ -26,9 +26,10 @@
  *    elements -- while Ritz values and d_inv stay real.  Such a context runs
  *    the residual filter (Algorithm 3) in FP64, FP32 or BF16 and an FP64
  *    Rayleigh-Ritz on the real embedding [[G_r, -G_i], [G_i, G_r]] of the
- *    projected Hermitian pencil (no SVQB fallback: a singular Gram matrix is
- *    CHFSI_ERR_NOT_SPD; Ritz values closer than 1e-8 relative that the
- *    embedding cannot separate are CHFSI_ERR_NUMERIC).
+ *    projected Hermitian pencil.  A singular Gram matrix takes the SVQB
+ *    fallback of real blocks on the embedding, keeping and refilling whole
+ *    complex directions (chfsi_report.flags bit 0).  Equal Ritz values get
+ *    a B-orthonormal basis of their eigenspace.
  */
 #ifndef CHFSI_H_
 #define CHFSI_H_

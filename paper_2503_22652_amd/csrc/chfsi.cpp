@@ -13,6 +13,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -1420,7 +1421,217 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
 // ---------------------------------------------------------------------------
 chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, double* X,
                                    int64_t ldx, double* R, int64_t ldr, double* ritz,
-                                   double* resnorm) {
+                                   double* resnorm, bool allow_svqb = true);
+
+// The real embedding M(H) of a Hermitian H (cd x cd) has each eigenvalue of H
+// twice, with the eigenspace {[Re x; Im x], [-Im x; Re x]}, so the first vector
+// of each ascending pair is a complex eigenvector.  When eigenvalues of H are
+// equal (to 1e-8 relative), Jacobi returns an arbitrary real basis of their
+// joint eigenspace and the first vectors of its pairs need not span it.  For
+// each such cluster of the first 2 np eigenvalues (ascending, w on the host),
+// the cluster's columns of E (2 cd rows, ld lde, device) are taken to the host,
+// every one is read as a complex vector, complex modified Gram-Schmidt keeps
+// an orthonormal set of the cluster's size / 2, and the pairs are rewritten
+// as [Re x; Im x], [-Im x; Re x].  With Mg (device, the embedding M(G) of a
+// Hermitian positive definite G, ld 2 cd) the set is orthonormal in x^H G y
+// instead (columns of E in the coordinates where G is the metric).  Clusters
+// are rare; nothing moves otherwise.
+chfsi_status fix_pair_clusters(chfsi_ctx* c, double* E, int64_t lde, int64_t cd, int64_t np,
+                               const double* w, const double* Mg = nullptr) {
+  std::vector<std::complex<double>> G;   // the metric, fetched at the first cluster
+  double scale = 0.0;
+  for (int64_t j = 0; j < 2 * np; ++j) scale = std::max(scale, std::fabs(w[j]));
+  const double tol = 1e-8 * std::max(scale, 1e-300);
+  int64_t j0 = 0;
+  while (j0 < np) {
+    int64_t j1 = j0 + 1;   // pairs [j0, j1) form one cluster
+    while (j1 < np && std::fabs(w[2 * j1] - w[2 * j1 - 1]) <= tol) ++j1;
+    if (j1 - j0 > 1) {
+      const int64_t cols = 2 * (j1 - j0), rows = 2 * cd;
+      std::vector<double> h(size_t(rows) * cols);
+      CK(hipMemcpy2DAsync(h.data(), rows * sizeof(double), E + 2 * j0 * lde,
+                          lde * sizeof(double), rows * sizeof(double), cols,
+                          hipMemcpyDeviceToHost, c->stream));
+      CK(hipStreamSynchronize(c->stream));
+      if (Mg && G.empty()) {
+        std::vector<double> hm(size_t(rows) * rows);
+        CK(hipMemcpyAsync(hm.data(), Mg, hm.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+        CK(hipStreamSynchronize(c->stream));
+        G.resize(size_t(cd) * cd);   // G(i, j) = M(i, j) + i M(cd + i, j)
+        for (int64_t j = 0; j < cd; ++j)
+          for (int64_t i = 0; i < cd; ++i) G[i + j * cd] = {hm[i + j * rows], hm[cd + i + j * rows]};
+      }
+      std::vector<std::complex<double>> Gu(cd);
+      auto apply_metric = [&](const std::vector<std::complex<double>>& u) {
+        if (G.empty()) {
+          Gu = u;
+          return;
+        }
+        for (int64_t i = 0; i < cd; ++i) {
+          std::complex<double> acc = 0.0;
+          for (int64_t j = 0; j < cd; ++j) acc += G[i + j * cd] * u[j];
+          Gu[i] = acc;
+        }
+      };
+      std::vector<std::complex<double>> q;   // accepted vectors, cd each
+      for (int64_t v = 0; v < cols && int64_t(q.size()) < cd * (j1 - j0); v += 1) {
+        std::vector<std::complex<double>> u(cd);
+        for (int64_t i = 0; i < cd; ++i) u[i] = {h[v * rows + i], h[v * rows + cd + i]};
+        const auto unorm = [&]() {
+          apply_metric(u);
+          double r = 0.0;
+          for (int64_t i = 0; i < cd; ++i) r += std::real(std::conj(u[i]) * Gu[i]);
+          return std::sqrt(std::max(r, 0.0));
+        };
+        const double n0 = unorm();
+        for (int pass = 0; pass < 2; ++pass)
+          for (size_t a = 0; a < q.size(); a += cd) {
+            apply_metric(u);
+            std::complex<double> d = 0.0;   // q_a^H G u
+            for (int64_t i = 0; i < cd; ++i) d += std::conj(q[a + i]) * Gu[i];
+            for (int64_t i = 0; i < cd; ++i) u[i] -= d * q[a + i];
+          }
+        const double nrm = unorm();
+        if (!(nrm > 0.5 * n0)) continue;   // (numerically) in the span already
+        for (int64_t i = 0; i < cd; ++i) q.push_back(u[i] / nrm);
+      }
+      if (int64_t(q.size()) != cd * (j1 - j0)) {
+        set_error("a cluster of %lld equal complex eigenvalues has no orthonormal basis in the "
+                  "embedded eigenvectors", (long long)(j1 - j0));
+        return CHFSI_ERR_NUMERIC;
+      }
+      for (int64_t t = 0; t < j1 - j0; ++t)
+        for (int64_t i = 0; i < cd; ++i) {
+          const std::complex<double> x = q[t * cd + i];
+          h[(2 * t) * rows + i] = x.real();
+          h[(2 * t) * rows + cd + i] = x.imag();
+          h[(2 * t + 1) * rows + i] = -x.imag();
+          h[(2 * t + 1) * rows + cd + i] = x.real();
+        }
+      CK(hipMemcpy2DAsync(E + 2 * j0 * lde, lde * sizeof(double), h.data(),
+                          rows * sizeof(double), rows * sizeof(double), cols,
+                          hipMemcpyHostToDevice, c->stream));
+      CK(hipStreamSynchronize(c->stream));
+    }
+    j0 = j1;
+  }
+  return CHFSI_OK;
+}
+
+// SVQB reading for a numerically singular complex Gram matrix, on the real
+// embedding, where every complex direction is an eigenvalue pair: the scaled
+// embedded Gram matrix (kept in c->Linv) is M(G) = U diag(g) U^T; the pairs
+// with g > 1e-14 max g are kept whole, k of them; W = diag(s) U_k diag(g_k^{-1/2})
+// (one complex vector per pair) is a B-orthonormal basis of the kept span;
+// the k x k Hermitian problem W^H (Y^H A Y) W is solved as the 2k x 2k real
+// problem M(W)^T M(Y^H A Y) M(W); `tail` forms X, R and the norms from its
+// pairs; the b - k dropped columns are refilled with N(0,1) values (real and
+// imaginary parts) and Rayleigh-Ritz is repeated once on the refilled block.
+template <typename Tail>
+chfsi_status rayleigh_ritz_complex_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, double* X,
+                                        int64_t ldx, double* R, int64_t ldr, double* ritz,
+                                        double* resnorm, Tail& tail) {
+  const int64_t n = c->n, b = c->b, m = 2 * b;
+  hipStream_t st = c->stream;
+  int sweeps = 0;
+  CK(syev_jacobi(c->Linv, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps));
+  c->last_sweeps += sweeps;
+  CK(hipMemcpyAsync(c->h_w, c->w, m * sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  const double gmax = c->h_w[m - 1];
+  int64_t first = 0;
+  while (first < m && !(c->h_w[first] > 1e-14 * gmax)) ++first;
+  first += first & 1;                                   // whole pairs only
+  const int64_t k = (m - first) / 2;
+  if (k <= 0) {
+    set_error("Gram matrix Y^H B Y is numerically zero");
+    return CHFSI_ERR_NOT_SPD;
+  }
+  c->flags |= 1;
+  {
+    chfsi_status fs = fix_pair_clusters(c, c->E + first * m, m, b, k, c->h_w + first);
+    if (fs != CHFSI_OK) return fs;
+  }
+  std::vector<double> gs(k);
+  for (int64_t j = 0; j < k; ++j) gs[j] = 1.0 / std::sqrt(c->h_w[first + 2 * j]);
+  CK(hipEventSynchronize(c->ev_stage));
+  std::memcpy(c->h_stage, gs.data(), k * sizeof(double));
+  CK(hipMemcpyAsync(c->lamY, c->h_stage, k * sizeof(double), hipMemcpyHostToDevice, st));
+  CK(hipEventRecord(c->ev_stage, st));
+  // W (planar b x 2k) in Zx, M(W) (2b x 2k) in TL
+  CK(pairs_to_planar(c->E, m, b, first, k, c->lamY, c->svec, c->Zx, st));
+  CK(embed_block(c->Zx, b, k, c->TL, m, st));
+  {
+    GemmDesc<double> g;   // Tmp (2b x 2k) = M(Ga) M(W)
+    g.M = m;
+    g.N = 2 * k;
+    g.K = m;
+    g.A = c->Ga;
+    g.sam = 1;
+    g.sak = m;
+    g.B = c->TL;
+    g.sbk = 1;
+    g.sbn = m;
+    g.C = c->Tmp;
+    g.ldc = m;
+    CK(gemm<double>(g, st, c->ws));
+    GemmDesc<double> h;   // Hp (2k x 2k) = M(W)^T Tmp
+    h.M = 2 * k;
+    h.N = 2 * k;
+    h.K = m;
+    h.A = c->TL;
+    h.sak = 1;
+    h.sam = m;
+    h.B = c->Tmp;
+    h.sbk = 1;
+    h.sbn = m;
+    h.C = c->Hp;
+    h.ldc = m;
+    CK(gemm<double>(h, st, c->ws));
+  }
+  CK(symmetrize(c->Hp, m, 2 * k, st));
+  CK(syev_jacobi(c->Hp, m, 2 * k, c->w, c->E, m, st, c->ws_eig, &sweeps));
+  c->last_sweeps += sweeps;
+  {
+    std::vector<double> hw(2 * k);
+    CK(hipMemcpyAsync(hw.data(), c->w, 2 * k * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    chfsi_status fs = fix_pair_clusters(c, c->E, m, k, k, hw.data());
+    if (fs != CHFSI_OK) return fs;
+  }
+  {
+    GemmDesc<double> g;   // T (2b x 2k) = M(W) E: the embedded Ritz coefficient vectors
+    g.M = m;
+    g.N = 2 * k;
+    g.K = 2 * k;
+    g.A = c->TL;
+    g.sam = 1;
+    g.sak = m;
+    g.B = c->E;
+    g.sbk = 1;
+    g.sbn = m;
+    g.C = c->T;
+    g.ldc = m;
+    CK(gemm<double>(g, st, c->ws));
+  }
+  chfsi_status s = tail(k);
+  if (s != CHFSI_OK || k == b) return s;
+  // refill the dropped columns (interleaved: 2n doubles each) and repeat once
+  c->refill_seed += 1;
+  CK(fill_gaussian(X + 2 * k * ldx, 2 * ldx, 2 * n, b - k,
+                   c->prm.seed * 7919 + c->refill_seed, st));
+  double* tmp = c->Yw;   // free scratch: the input block is no longer needed
+  if (tmp == Y) tmp = const_cast<double*>(Y);
+  s = rayleigh_ritz_complex(c, X, ldx, tmp, n, R, ldr, ritz, resnorm, false);
+  if (s != CHFSI_OK) return s;
+  CK(copy_block(tmp, 2 * n, X, 2 * ldx, 2 * n, b, st));
+  return CHFSI_OK;
+}
+
+chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, double* X,
+                                   int64_t ldx, double* R, int64_t ldr, double* ritz,
+                                   double* resnorm, bool allow_svqb) {
   const int64_t n = c->n, b = c->b, m = 2 * b;
   hipStream_t st = c->stream;
   CK(fill_zero(c->dflags, 4 * sizeof(int), st));
@@ -1490,15 +1701,113 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
   };
   if ((s = gram(c->AYpl, c->Ga)) != CHFSI_OK) return s;
   if ((s = gram(BYpl, c->Gb)) != CHFSI_OK) return s;
+  // Ritz pairs from the first vector of each of the np eigenvalue pairs of the
+  // embedded problem (columns 2j of T, eigenvalues in w), then X, R and norms
+  auto tail = [&](int64_t np) -> chfsi_status {
+    // the embedded eigenvalues come in equal pairs; Ritz value j is pair j
+    CK(hipMemcpyAsync(c->h_w, c->w, m * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    double scale = 0.0, split = 0.0;
+    for (int64_t j = 0; j < 2 * np; ++j) scale = std::max(scale, std::fabs(c->h_w[j]));
+    for (int64_t j = 0; j < np; ++j)
+      split = std::max(split, std::fabs(c->h_w[2 * j + 1] - c->h_w[2 * j]));
+    if (!(split <= 1e-8 * std::max(scale, 1e-300))) {
+      set_error("embedded Ritz values are not paired (split %.3e of %.3e): nearly equal complex "
+                "Ritz values are not separated",
+                split, scale);
+      return CHFSI_ERR_NUMERIC;
+    }
+    std::vector<double> lam(b), dup(m);
+    for (int64_t j = 0; j < b; ++j) {
+      lam[j] = c->h_w[2 * std::min(j, np - 1)];   // columns past the kept pairs are zero
+      dup[j] = dup[b + j] = lam[j];
+    }
+    CK(hipEventSynchronize(c->ev_stage));
+    std::memcpy(c->h_stage, dup.data(), m * sizeof(double));
+    CK(hipMemcpyAsync(c->wdup, c->h_stage, m * sizeof(double), hipMemcpyHostToDevice, st));
+    CK(hipEventRecord(c->ev_stage, st));
+    // X~ = [[x_r, x_i], [-x_i, x_r]] (2b x 2b) from the selected complex vectors
+    CK(select_pairs_n(c->T, m, b, np, c->Zx, st));
+    CK(cplx_rhs<double>(c->Zx, b, b, c->Xt, st));
+    auto rotate = [&](const double* Src, const double* Tmat, double* Dst, double alpha,
+                      const double* accum) -> chfsi_status {
+      GemmDesc<double> g;   // Dst (n x 2b planar) = alpha Src (n x 2b planar) Tmat (2b x 2b)
+      g.M = n;
+      g.N = m;
+      g.K = m;
+      g.A = Src;
+      g.sam = 1;
+      g.sak = n;
+      g.B = Tmat;
+      g.sbk = 1;
+      g.sbn = m;
+      g.C = Dst;
+      g.ldc = n;
+      g.epi.alpha = alpha;
+      if (accum) {
+        g.epi.beta = 1.0;
+        g.epi.C1 = accum;
+        g.epi.ldc1 = n;
+      }
+      CK(gemm<double>(g, st, c->ws));
+      return CHFSI_OK;
+    };
+    if ((s = rotate(c->Ypl, c->Xt, c->Xpl, 1.0, nullptr)) != CHFSI_OK) return s;
+    if (c->bloch && stencil_separable(c->A) && (c->B_identity || stencil_separable(c->B))) {
+      // grid operators: R = A_tw X - B_tw X Lambda as one periodic stencil pass
+      // over X plus the wrap corrections (instead of rotating A Y and B Y)
+      CK(stencil_residual_f64(c->A, c->B_identity ? nullptr : &c->B, c->Xpl, n, c->wdup, c->Rpl,
+                              n, m, st));
+      CK(bloch_fix<double>(c->A, nullptr, 1.0, c->Xpl, n, c->Rpl, n, b, st));
+      if (!c->B_identity)
+        CK(bloch_fix<double>(c->B, nullptr, -1.0, c->Xpl, n, c->Rpl, n, b, st, c->wdup));
+    } else {
+      if ((s = rotate(c->AYpl, c->Xt, c->Rpl, 1.0, nullptr)) != CHFSI_OK) return s;
+      CK(copy_block(c->Xt, m, c->TL, m, m, m, st));
+      CK(scale_columns(c->TL, m, m, m, c->wdup, st));
+      if ((s = rotate(BYpl, c->TL, c->Rpl, -1.0, c->Rpl)) != CHFSI_OK) return s;
+    }
+    // residual norms: r_j^2 = ||Re R_j||^2 + ||Im R_j||^2
+    CK(column_norms(c->Rpl, n, n, m, c->norms, st));
+    CK(check_finite(c->wdup, m, c->dflags + 2, st));
+    CK(check_finite(c->norms, m, c->dflags + 2, st));
+    if (c->bloch) {
+      CK(bloch_from_planar(c->Xpl, n, b, X, ldx, twist_of(c), st));
+      CK(bloch_from_planar(c->Rpl, n, b, R, ldr, twist_of(c), st));
+    } else {
+      CK(planar_to_cplx(c->Xpl, n, b, X, ldx, st));
+      CK(planar_to_cplx(c->Rpl, n, b, R, ldr, st));
+    }
+    CK(hipMemcpyAsync(c->h_norms, c->norms, m * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (c->h_flags[2] != 0) {
+      set_error("non-finite Ritz value or residual norm");
+      return CHFSI_ERR_NUMERIC;
+    }
+    for (int64_t j = 0; j < b; ++j) {
+      ritz[j] = lam[j];
+      resnorm[j] = std::sqrt(c->h_norms[j] * c->h_norms[j] + c->h_norms[b + j] * c->h_norms[b + j]);
+    }
+    return CHFSI_OK;
+  };
   // CholQR of the scaled embedded Gram matrix, projected matrix, Jacobi
   CK(scale_gram(c->Gb, m, m, c->Gs, m, c->svec, c->dflags + 1, st));
+  CK(copy_block(c->Gs, m, c->Linv, m, m, m, st));      // kept for the SVQB fallback
   CK(potrf_lower(c->Gs, m, m, c->dflags, st, c->ws, c->tri));
   CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  if (c->h_flags[1] != 0 || c->h_flags[0] != 0) {
-    set_error("Gram matrix Y^H B Y is not positive definite (complex blocks have no SVQB "
-              "fallback)");
+  if (c->h_flags[1] != 0) {
+    set_error("Gram matrix Y^H B Y has a non-positive diagonal (a zero or non-finite column)");
     return CHFSI_ERR_NOT_SPD;
+  }
+  if (c->h_flags[0] != 0) {
+    if (!allow_svqb) {
+      set_error("Gram matrix Y^H B Y is not positive definite (pivot %d) after refill",
+                c->h_flags[0]);
+      return CHFSI_ERR_NOT_SPD;
+    }
+    return rayleigh_ritz_complex_svqb(c, Y, ldy, X, ldx, R, ldr, ritz, resnorm, tail);
   }
   CK(set_identity(c->Linv, m, m, st));
   CK(trsm_lower_left(c->Gs, m, c->Linv, m, m, m, st, c->ws, c->tri, true));
@@ -1551,92 +1860,15 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
     g.epi.rowscale = c->svec;
     CK(gemm<double>(g, st, c->ws));
   }
-  // the embedded eigenvalues come in equal pairs; Ritz value j is pair j
-  CK(hipMemcpyAsync(c->h_w, c->w, m * sizeof(double), hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  double scale = 0.0, split = 0.0;
-  for (int64_t j = 0; j < m; ++j) scale = std::max(scale, std::fabs(c->h_w[j]));
-  for (int64_t j = 0; j < b; ++j)
-    split = std::max(split, std::fabs(c->h_w[2 * j + 1] - c->h_w[2 * j]));
-  if (!(split <= 1e-8 * std::max(scale, 1e-300))) {
-    set_error("embedded Ritz values are not paired (split %.3e of %.3e): nearly equal complex "
-              "Ritz values are not separated",
-              split, scale);
-    return CHFSI_ERR_NUMERIC;
+  {
+    // equal Ritz values: the coefficient vectors of their eigenspace (columns
+    // of T, in the coordinates where Y^H B Y is the metric), made B-orthonormal
+    CK(hipMemcpyAsync(c->h_w, c->w, m * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    chfsi_status fs = fix_pair_clusters(c, c->T, m, b, b, c->h_w, c->Gb);
+    if (fs != CHFSI_OK) return fs;
   }
-  std::vector<double> lam(b), dup(m);
-  for (int64_t j = 0; j < b; ++j) {
-    lam[j] = c->h_w[2 * j];
-    dup[j] = dup[b + j] = lam[j];
-  }
-  CK(hipEventSynchronize(c->ev_stage));
-  std::memcpy(c->h_stage, dup.data(), m * sizeof(double));
-  CK(hipMemcpyAsync(c->wdup, c->h_stage, m * sizeof(double), hipMemcpyHostToDevice, st));
-  CK(hipEventRecord(c->ev_stage, st));
-  // X~ = [[x_r, x_i], [-x_i, x_r]] (2b x 2b) from the selected complex vectors
-  CK(select_pairs(c->T, b, c->Zx, st));
-  CK(cplx_rhs<double>(c->Zx, b, b, c->Xt, st));
-  auto rotate = [&](const double* Src, const double* Tmat, double* Dst, double alpha,
-                    const double* accum) -> chfsi_status {
-    GemmDesc<double> g;   // Dst (n x 2b planar) = alpha Src (n x 2b planar) Tmat (2b x 2b)
-    g.M = n;
-    g.N = m;
-    g.K = m;
-    g.A = Src;
-    g.sam = 1;
-    g.sak = n;
-    g.B = Tmat;
-    g.sbk = 1;
-    g.sbn = m;
-    g.C = Dst;
-    g.ldc = n;
-    g.epi.alpha = alpha;
-    if (accum) {
-      g.epi.beta = 1.0;
-      g.epi.C1 = accum;
-      g.epi.ldc1 = n;
-    }
-    CK(gemm<double>(g, st, c->ws));
-    return CHFSI_OK;
-  };
-  if ((s = rotate(c->Ypl, c->Xt, c->Xpl, 1.0, nullptr)) != CHFSI_OK) return s;
-  if (c->bloch && stencil_separable(c->A) && (c->B_identity || stencil_separable(c->B))) {
-    // grid operators: R = A_tw X - B_tw X Lambda as one periodic stencil pass
-    // over X plus the wrap corrections (instead of rotating A Y and B Y)
-    CK(stencil_residual_f64(c->A, c->B_identity ? nullptr : &c->B, c->Xpl, n, c->wdup, c->Rpl,
-                            n, m, st));
-    CK(bloch_fix<double>(c->A, nullptr, 1.0, c->Xpl, n, c->Rpl, n, b, st));
-    if (!c->B_identity)
-      CK(bloch_fix<double>(c->B, nullptr, -1.0, c->Xpl, n, c->Rpl, n, b, st, c->wdup));
-  } else {
-    if ((s = rotate(c->AYpl, c->Xt, c->Rpl, 1.0, nullptr)) != CHFSI_OK) return s;
-    CK(copy_block(c->Xt, m, c->TL, m, m, m, st));
-    CK(scale_columns(c->TL, m, m, m, c->wdup, st));
-    if ((s = rotate(BYpl, c->TL, c->Rpl, -1.0, c->Rpl)) != CHFSI_OK) return s;
-  }
-  // residual norms: r_j^2 = ||Re R_j||^2 + ||Im R_j||^2
-  CK(column_norms(c->Rpl, n, n, m, c->norms, st));
-  CK(check_finite(c->wdup, m, c->dflags + 2, st));
-  CK(check_finite(c->norms, m, c->dflags + 2, st));
-  if (c->bloch) {
-    CK(bloch_from_planar(c->Xpl, n, b, X, ldx, twist_of(c), st));
-    CK(bloch_from_planar(c->Rpl, n, b, R, ldr, twist_of(c), st));
-  } else {
-    CK(planar_to_cplx(c->Xpl, n, b, X, ldx, st));
-    CK(planar_to_cplx(c->Rpl, n, b, R, ldr, st));
-  }
-  CK(hipMemcpyAsync(c->h_norms, c->norms, m * sizeof(double), hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  if (c->h_flags[2] != 0) {
-    set_error("non-finite Ritz value or residual norm");
-    return CHFSI_ERR_NUMERIC;
-  }
-  for (int64_t j = 0; j < b; ++j) {
-    ritz[j] = lam[j];
-    resnorm[j] = std::sqrt(c->h_norms[j] * c->h_norms[j] + c->h_norms[b + j] * c->h_norms[b + j]);
-  }
-  return CHFSI_OK;
+  return tail(b);
 }
 
 // ---------------------------------------------------------------------------

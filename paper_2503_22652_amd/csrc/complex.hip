@@ -187,7 +187,78 @@ __global__ __launch_bounds__(kThreads) void k_select_pairs(const double* __restr
   }
 }
 
+// SVQB for the embedded problem: planar W (b x 2k, ld b; real parts then
+// imaginary parts) from the first vector of the eigenvalue pairs first,
+// first + 2, ... of the m x m eigenvector matrix E (ld lde), scaled per pair
+// by gs[j] and per row by s[i]
+__global__ __launch_bounds__(kThreads) void k_pairs_to_planar(const double* __restrict__ E,
+                                                              int64_t lde, int64_t b,
+                                                              int64_t first, int64_t k,
+                                                              const double* __restrict__ gs,
+                                                              const double* __restrict__ s,
+                                                              double* __restrict__ W) {
+  const int64_t total = b * k;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / b, i = idx - j * b;
+    const double f = gs[j] * s[i];
+    const double* e = E + (first + 2 * j) * lde;
+    W[i + j * b] = e[i] * f;
+    W[i + (k + j) * b] = e[b + i] * f;
+  }
+}
+
+// M(W) = [[W_r, -W_i], [W_i, W_r]] (2b x 2k, ld ldm) from planar W (b x 2k, ld b)
+__global__ __launch_bounds__(kThreads) void k_embed_block(const double* __restrict__ W, int64_t b,
+                                                          int64_t k, double* __restrict__ M,
+                                                          int64_t ldm) {
+  const int64_t total = b * k;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / b, i = idx - j * b;
+    const double wr = W[i + j * b], wi = W[i + (k + j) * b];
+    M[i + j * ldm] = wr;
+    M[(b + i) + j * ldm] = wi;
+    M[i + (k + j) * ldm] = -wi;
+    M[(b + i) + (k + j) * ldm] = wr;
+  }
+}
+
+// Zx (b x 2b planar, ld b) from the first vector of each of the first k
+// eigenvalue pairs of T (2b rows, ld ldt): x_j = T(0:b, 2j) + i T(b:2b, 2j);
+// columns k..b-1 of both halves are zero
+__global__ __launch_bounds__(kThreads) void k_select_pairs_n(const double* __restrict__ T,
+                                                             int64_t ldt, int64_t b, int64_t k,
+                                                             double* __restrict__ Zx) {
+  const int64_t total = b * b;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = idx / b, i = idx - j * b;
+    const bool keep = j < k;
+    Zx[i + j * b] = keep ? T[i + (2 * j) * ldt] : 0.0;
+    Zx[i + (b + j) * b] = keep ? T[(b + i) + (2 * j) * ldt] : 0.0;
+  }
+}
+
 }  // namespace
+
+hipError_t pairs_to_planar(const double* E, int64_t lde, int64_t b, int64_t first, int64_t k,
+                           const double* gs, const double* s, double* W, hipStream_t st) {
+  k_pairs_to_planar<<<grid_for(b * k), kThreads, 0, st>>>(E, lde, b, first, k, gs, s, W);
+  return hipGetLastError();
+}
+
+hipError_t embed_block(const double* W, int64_t b, int64_t k, double* M, int64_t ldm,
+                       hipStream_t st) {
+  k_embed_block<<<grid_for(b * k), kThreads, 0, st>>>(W, b, k, M, ldm);
+  return hipGetLastError();
+}
+
+hipError_t select_pairs_n(const double* T, int64_t ldt, int64_t b, int64_t k, double* Zx,
+                          hipStream_t st) {
+  k_select_pairs_n<<<grid_for(b * b), kThreads, 0, st>>>(T, ldt, b, k, Zx);
+  return hipGetLastError();
+}
 
 hipError_t cplx_to_planar(const double* Z, int64_t ldz, int64_t n, int64_t b, double* P,
                           hipStream_t st) {

@@ -132,6 +132,18 @@ hipError_t embed_gram_lower(const double* P4, int64_t b, double* M, hipStream_t 
 // Zx (b x 2b planar, ld b): column j = T(0:b, 2j), column b+j = T(b:2b, 2j)
 // of the 2b x 2b eigenvector matrix T of an embedded problem
 hipError_t select_pairs(const double* T, int64_t b, double* Zx, hipStream_t st);
+// the same for the first k pairs of a T with 2b rows and leading dimension
+// ldt; columns k..b-1 of Zx are zero
+hipError_t select_pairs_n(const double* T, int64_t ldt, int64_t b, int64_t k, double* Zx,
+                          hipStream_t st);
+// SVQB on the embedded Gram matrix: planar W (b x 2k) from the first vector of
+// the eigenvalue pairs first, first + 2, ..., first + 2(k-1) of E (ld lde),
+// column j scaled by gs[j] and row i by s[i] (device arrays)
+hipError_t pairs_to_planar(const double* E, int64_t lde, int64_t b, int64_t first, int64_t k,
+                           const double* gs, const double* s, double* W, hipStream_t st);
+// M(W) = [[W_r, -W_i], [W_i, W_r]] (2b x 2k, ld ldm) from planar W (b x 2k)
+hipError_t embed_block(const double* W, int64_t b, int64_t k, double* M, int64_t ldm,
+                       hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Bloch-phase grid operators in the twisted frame (bloch.hip).  D =

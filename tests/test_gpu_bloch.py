@@ -264,3 +264,27 @@ def test_bloch_padded_leading_dimensions_and_identity_b():
     assert st == P.OK
     assert np.max(np.abs(np.array(ev[:6]) - w)) <= 1e-10 * np.max(np.abs(w))
     assert torch.all(sbuf.t()[n:] == 0)
+
+
+def test_bloch_rayleigh_ritz_singular_gram_uses_svqb():
+    """SVQB on the Bloch grid path (twisted frame): a repeated column of exact
+    eigenvectors of the assembled pencil."""
+    shape = (6, 8, 10)
+    apply_A, apply_B, opA, opB, Vd = _problem(shape, seed=5, wells=1)
+    n = int(np.prod(shape))
+    b = 12
+    Ad, Bd = apply_A(np.eye(n)), apply_B(np.eye(n))
+    w, U = sla.eigh(Ad, Bd)
+    Y = U[:, :b].copy()
+    Y[:, -1] = Y[:, 0]
+    prm = P.make_params(6, b, 4, method=P.METHOD_RCHFSI, lambda_max=LMAX)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    X, R = P.colmajor_empty_complex(n, b), P.colmajor_empty_complex(n, b)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor_complex(Y), X, R)
+    ritz = np.asarray(ritz)
+    for lam in w[: b - 1]:
+        assert np.min(np.abs(ritz - lam)) <= 1e-10 * max(1.0, abs(lam))
+    Xg = X.cpu().numpy()
+    assert np.linalg.norm(Xg.conj().T @ Bd @ Xg - np.eye(b)) <= 1e-9
+    Rg = Ad @ Xg - (Bd @ Xg) * ritz[None, :]
+    np.testing.assert_allclose(norms, np.linalg.norm(Rg, axis=0), rtol=1e-6, atol=1e-9)

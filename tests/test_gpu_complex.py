@@ -181,3 +181,52 @@ def test_complex_standard_problem_padded_leading_dimensions():
     ref, RYp, _ = filters.residual_filter(filters.dense_op(p.A), filters.identity_op(), o["X"], lam,
                                           o["R"], 12, *bounds, return_parts=True)
     assert np.linalg.norm(Yb.cpu().numpy() - ref) <= 1e-4 * np.linalg.norm(RYp)
+
+
+def test_complex_rayleigh_ritz_singular_gram_uses_svqb(herm):
+    """A block with a repeated column: the embedded Gram matrix has a zero
+    eigenvalue pair, the SVQB reading keeps the b - 1 independent complex
+    directions (here an invariant subspace, so their Ritz values are exact
+    eigenvalues), refills one column and repeats Rayleigh-Ritz."""
+    p, lmax = herm
+    ctx = _ctx(p, P.PREC_FP32, lmax, 8)
+    w, U = sla.eigh(p.A, p.B)
+    Y = U[:, : p.block].copy()
+    Y[:, -1] = Y[:, 0]
+    X = P.colmajor_empty_complex(p.n, p.block)
+    R = P.colmajor_empty_complex(p.n, p.block)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor_complex(Y), X, R)
+    ritz = np.asarray(ritz)
+    for lam in w[: p.block - 1]:
+        assert np.min(np.abs(ritz - lam)) <= 1e-10 * max(1.0, abs(lam))
+    Xg = X.cpu().numpy()
+    assert np.linalg.norm(Xg.conj().T @ p.B @ Xg - np.eye(p.block)) <= 1e-9
+    Rg = p.A @ Xg - (p.B @ Xg) * ritz[None, :]
+    np.testing.assert_allclose(norms, np.linalg.norm(Rg, axis=0), rtol=1e-6, atol=1e-9)
+    assert np.linalg.norm(R.cpu().numpy() - Rg) <= 1e-9 * np.linalg.norm(p.A, 2)
+
+
+def test_complex_rayleigh_ritz_equal_ritz_values():
+    """Equal Ritz values: a block spanning an invariant subspace with a triple
+    and a double eigenvalue.  The embedded problem's eigenspaces of equal
+    values are 6- and 4-dimensional, and the complex Ritz vectors must still
+    be an orthonormal basis of them."""
+    n, b = 300, 12
+    lam = np.concatenate([[-1.0, -0.5, -0.5, -0.5, 0.0, 0.0, 0.25], np.linspace(1.0, 10.0, n - 7)])
+    rng = np.random.default_rng(61)
+    A = wl.hermitian_from_spectrum(lam, wl.complex_householder_vectors(rng, n, 8))
+    A = 0.5 * (A + A.conj().T)
+    w, U = np.linalg.eigh(A)
+    # a basis of the lowest 12 eigenvectors, mixed within the span (not orthonormal)
+    M = rng.standard_normal((b, b)) + 1j * rng.standard_normal((b, b))
+    Y = U[:, :b] @ M
+    Ad = P.to_colmajor_complex(A)
+    prm = P.make_params(b, b, 4, method=P.METHOD_RCHFSI, filter_prec=P.PREC_FP64, lambda_max=10.5)
+    ctx = P.chfsi_create(P.hermitian_operator(Ad), None, None, prm, keep=(Ad,))
+    X, R = P.colmajor_empty_complex(n, b), P.colmajor_empty_complex(n, b)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor_complex(Y), X, R)
+    np.testing.assert_allclose(ritz, w[:b], rtol=0, atol=1e-11)
+    Xg = X.cpu().numpy()
+    assert np.linalg.norm(Xg.conj().T @ Xg - np.eye(b)) <= 1e-10
+    assert np.max(np.linalg.norm(A @ Xg - Xg * np.array(ritz)[None, :], axis=0)) <= 1e-10
+    assert np.max(norms) <= 1e-10
