@@ -1712,8 +1712,8 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
     for (int64_t j = 0; j < np; ++j)
       split = std::max(split, std::fabs(c->h_w[2 * j + 1] - c->h_w[2 * j]));
     if (!(split <= 1e-8 * std::max(scale, 1e-300))) {
-      set_error("embedded Ritz values are not paired (split %.3e of %.3e): nearly equal complex "
-                "Ritz values are not separated",
+      set_error("embedded Ritz values do not come in equal pairs (split %.3e of %.3e): the "
+                "projected matrices are not Hermitian to working accuracy",
                 split, scale);
       return CHFSI_ERR_NUMERIC;
     }
