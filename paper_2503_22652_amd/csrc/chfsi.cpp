@@ -1474,27 +1474,47 @@ chfsi_status fix_pair_clusters(chfsi_ctx* c, double* E, int64_t lde, int64_t cd,
           Gu[i] = acc;
         }
       };
+      // pivoted: each step keeps the candidate that retains the largest part of
+      // its norm outside the vectors kept so far
       std::vector<std::complex<double>> q;   // accepted vectors, cd each
-      for (int64_t v = 0; v < cols && int64_t(q.size()) < cd * (j1 - j0); v += 1) {
-        std::vector<std::complex<double>> u(cd);
-        for (int64_t i = 0; i < cd; ++i) u[i] = {h[v * rows + i], h[v * rows + cd + i]};
-        const auto unorm = [&]() {
-          apply_metric(u);
-          double r = 0.0;
-          for (int64_t i = 0; i < cd; ++i) r += std::real(std::conj(u[i]) * Gu[i]);
-          return std::sqrt(std::max(r, 0.0));
-        };
-        const double n0 = unorm();
-        for (int pass = 0; pass < 2; ++pass)
-          for (size_t a = 0; a < q.size(); a += cd) {
-            apply_metric(u);
-            std::complex<double> d = 0.0;   // q_a^H G u
-            for (int64_t i = 0; i < cd; ++i) d += std::conj(q[a + i]) * Gu[i];
-            for (int64_t i = 0; i < cd; ++i) u[i] -= d * q[a + i];
+      std::vector<std::vector<std::complex<double>>> cand(cols, std::vector<std::complex<double>>(cd));
+      std::vector<double> n0(cols);
+      std::vector<char> used(cols, 0);
+      const auto gnorm = [&](const std::vector<std::complex<double>>& u) {
+        apply_metric(u);
+        double r = 0.0;
+        for (int64_t i = 0; i < cd; ++i) r += std::real(std::conj(u[i]) * Gu[i]);
+        return std::sqrt(std::max(r, 0.0));
+      };
+      for (int64_t v = 0; v < cols; ++v) {
+        for (int64_t i = 0; i < cd; ++i) cand[v][i] = {h[v * rows + i], h[v * rows + cd + i]};
+        n0[v] = gnorm(cand[v]);
+      }
+      for (int64_t t = 0; t < j1 - j0; ++t) {
+        int64_t best = -1;
+        double best_ratio = 0.0;
+        std::vector<std::complex<double>> best_u;
+        for (int64_t v = 0; v < cols; ++v) {
+          if (used[v] || !(n0[v] > 0.0)) continue;
+          std::vector<std::complex<double>> u = cand[v];
+          for (int pass = 0; pass < 2; ++pass)
+            for (size_t a = 0; a < q.size(); a += cd) {
+              apply_metric(u);
+              std::complex<double> d = 0.0;   // q_a^H G u
+              for (int64_t i = 0; i < cd; ++i) d += std::conj(q[a + i]) * Gu[i];
+              for (int64_t i = 0; i < cd; ++i) u[i] -= d * q[a + i];
+            }
+          const double ratio = gnorm(u) / n0[v];
+          if (ratio > best_ratio) {
+            best_ratio = ratio;
+            best = v;
+            best_u = u;
           }
-        const double nrm = unorm();
-        if (!(nrm > 0.5 * n0)) continue;   // (numerically) in the span already
-        for (int64_t i = 0; i < cd; ++i) q.push_back(u[i] / nrm);
+        }
+        if (best < 0 || !(best_ratio > 1e-6)) break;   // the cluster's span is exhausted
+        used[best] = 1;
+        const double nrm = gnorm(best_u);
+        for (int64_t i = 0; i < cd; ++i) q.push_back(best_u[i] / nrm);
       }
       if (int64_t(q.size()) != cd * (j1 - j0)) {
         set_error("a cluster of %lld equal complex eigenvalues has no orthonormal basis in the "

@@ -207,12 +207,12 @@ def test_complex_rayleigh_ritz_singular_gram_uses_svqb(herm):
 
 
 def test_complex_rayleigh_ritz_equal_ritz_values():
-    """Equal Ritz values: a block spanning an invariant subspace with a triple
+    """Equal Ritz values: a block spanning an invariant subspace with a 6-fold
     and a double eigenvalue.  The embedded problem's eigenspaces of equal
-    values are 6- and 4-dimensional, and the complex Ritz vectors must still
+    values are 12- and 4-dimensional, and the complex Ritz vectors must still
     be an orthonormal basis of them."""
     n, b = 300, 12
-    lam = np.concatenate([[-1.0, -0.5, -0.5, -0.5, 0.0, 0.0, 0.25], np.linspace(1.0, 10.0, n - 7)])
+    lam = np.concatenate([[-1.0], np.full(6, -0.5), [0.0, 0.0, 0.25], np.linspace(1.0, 10.0, n - 10)])
     rng = np.random.default_rng(61)
     A = wl.hermitian_from_spectrum(lam, wl.complex_householder_vectors(rng, n, 8))
     A = 0.5 * (A + A.conj().T)
