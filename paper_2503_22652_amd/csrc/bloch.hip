@@ -335,6 +335,22 @@ __global__ __launch_bounds__(kThreads) void k_bloch(FixArgs a, const double* __r
   }
 }
 
+// edge (ld 2 ny nz per column) = the x = 0 and x = nx-1 values of each grid
+// row of the planar block src (cols columns, ld lds)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bloch_edges(const T* __restrict__ src, int64_t lds,
+                                                          int nx, int64_t nrows, int64_t cols,
+                                                          T* __restrict__ edge) {
+  const int64_t total = nrows * cols;
+  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t c = idx / nrows, r = idx - c * nrows;
+    const T* row = src + c * lds + r * nx;
+    edge[c * 2 * nrows + 2 * r] = row[0];
+    edge[c * 2 * nrows + 2 * r + 1] = row[nx - 1];
+  }
+}
+
 FixArgs fix_args(const chfsi_operator& op) {
   FixArgs a;
   for (int o = 0; o < 27; ++o) {
@@ -395,14 +411,14 @@ hipError_t bloch_from_planar(const double* P, int64_t n, int64_t b, double* Z, i
 template <typename F>
 hipError_t bloch_fix(const chfsi_operator& op, const double* dinv, double alpha, const F* src,
                      int64_t lds, F* dst, int64_t ldd, int64_t pairs, hipStream_t st,
-                     const double* colscale) {
+                     const double* colscale, const F* edge) {
   if (!fix_ok(op, pairs) || lds < op.n || ldd < op.n) return hipErrorInvalidValue;
   const int64_t nb = bloch_boundary_points(op.nx, op.ny, op.nz);
   const dim3 grid(unsigned((nb + kThreads - 1) / kThreads * ((pairs + kPairs - 1) / kPairs)));
   // the correction accumulates in FP64 for FP64 blocks, else FP32
   using C = typename std::conditional<sizeof(F) == 8, double, float>::type;
   k_bloch<F, C, true><<<grid, kThreads, 0, st>>>(fix_args(op), op.field, dinv, alpha, colscale,
-                                                 src, lds, nullptr, dst, ldd, pairs, int(nb));
+                                                 src, lds, edge, dst, ldd, pairs, int(nb));
   return hipGetLastError();
 }
 
@@ -436,13 +452,25 @@ template hipError_t bloch_reconstruct<uint16_t>(const uint16_t*, const double*, 
                                                 int64_t, const Twist&, hipStream_t);
 template hipError_t bloch_fix<double>(const chfsi_operator&, const double*, double, const double*,
                                       int64_t, double*, int64_t, int64_t, hipStream_t,
-                                      const double*);
+                                      const double*, const double*);
 template hipError_t bloch_fix<float>(const chfsi_operator&, const double*, double, const float*,
                                      int64_t, float*, int64_t, int64_t, hipStream_t,
-                                     const double*);
+                                     const double*, const float*);
 template hipError_t bloch_fix<uint16_t>(const chfsi_operator&, const double*, double,
                                         const uint16_t*, int64_t, uint16_t*, int64_t, int64_t,
-                                        hipStream_t, const double*);
+                                        hipStream_t, const double*, const uint16_t*);
+template <typename T>
+hipError_t bloch_edges(const chfsi_operator& op, const T* src, int64_t lds, T* edge, int64_t cols,
+                       hipStream_t st) {
+  if (op.nx < 3 || lds < op.n || cols < 1) return hipErrorInvalidValue;
+  const int64_t nrows = int64_t(op.ny) * op.nz;
+  k_bloch_edges<T><<<grid_for(nrows * cols), kThreads, 0, st>>>(src, lds, op.nx, nrows, cols,
+                                                                  edge);
+  return hipGetLastError();
+}
+
+template hipError_t bloch_edges<double>(const chfsi_operator&, const double*, int64_t, double*,
+                                        int64_t, hipStream_t);
 template hipError_t bloch_corr<double, double>(const chfsi_operator&, const double*, double,
                                                const double*, int64_t, const double*, double*,
                                                int64_t, int64_t, hipStream_t);

@@ -108,6 +108,7 @@ struct chfsi_ctx {
   void* bcorr = nullptr;          // its filter step's boundary correction (nbnd x 2b)
   int64_t nbnd = 0;               // boundary points rounded up to a multiple of 4
   void* bedge[2] = {nullptr, nullptr};   // row-end values of the filter blocks (2 ny nz x 2b)
+  double* redge = nullptr;                 // row-end values of a Rayleigh-Ritz block (FP64)
   void* Lc = nullptr;
   void* dinv2 = nullptr;
   void* Zt = nullptr;
@@ -388,7 +389,8 @@ SizePlan plan_sizes_bloch(const chfsi_operator* A, const chfsi_operator* B, cons
   // the blocks' row ends
   s.a32 += size_t((bloch_boundary_points(A->nx, A->ny, A->nz) + 3) / 4 * 4) * 2 * b *
                (p->filter_prec == CHFSI_PREC_FP64 ? sizeof(double) : sizeof(float)) +
-           size_t(2) * 2 * A->ny * A->nz * 2 * b * el;
+           size_t(2) * 2 * A->ny * A->nz * 2 * b * el +
+           size_t(2) * A->ny * A->nz * 2 * b * sizeof(double);
   s.coef = size_t(p->degree + 1) * 2 * b * sizeof(double);
   s.blk = size_t(n) * b * 2 * sizeof(double);
   s.bb = size_t(m) * m * sizeof(double);
@@ -1658,6 +1660,8 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
   // a Bloch grid context works in the twisted frame (planar D Y)
   if (c->bloch) {
     CK(bloch_to_planar(Y, ldy, n, b, c->Ypl, twist_of(c), st));
+    // row ends of Y for the wrap corrections of A Y and B Y
+    CK(bloch_edges<double>(c->A, c->Ypl, n, c->redge, m, st));
   } else {
     CK(cplx_to_planar(Y, ldy, n, b, c->Ypl, st));
     CK(cplx_rhs<double>(c->Ypl, n, b, c->Yt, st));
@@ -1667,7 +1671,7 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
       // out = A_tw Y: the periodic stencil on 2b columns plus the wrap correction
       const chfsi_operator& op = useB ? c->B : c->A;
       CK(stencil_apply_f64(op, c->Ypl, n, out, n, m, st));
-      CK(bloch_fix<double>(op, nullptr, 1.0, c->Ypl, n, out, n, b, st));
+      CK(bloch_fix<double>(op, nullptr, 1.0, c->Ypl, n, out, n, b, st, nullptr, c->redge));
       return CHFSI_OK;
     }
     GemmDesc<double> g;   // out (n x 2b planar) = L (n x 2n) Y~ (2n x 2b)
@@ -1778,9 +1782,11 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
       // over X plus the wrap corrections (instead of rotating A Y and B Y)
       CK(stencil_residual_f64(c->A, c->B_identity ? nullptr : &c->B, c->Xpl, n, c->wdup, c->Rpl,
                               n, m, st));
-      CK(bloch_fix<double>(c->A, nullptr, 1.0, c->Xpl, n, c->Rpl, n, b, st));
+      CK(bloch_edges<double>(c->A, c->Xpl, n, c->redge, m, st));
+      CK(bloch_fix<double>(c->A, nullptr, 1.0, c->Xpl, n, c->Rpl, n, b, st, nullptr, c->redge));
       if (!c->B_identity)
-        CK(bloch_fix<double>(c->B, nullptr, -1.0, c->Xpl, n, c->Rpl, n, b, st, c->wdup));
+        CK(bloch_fix<double>(c->B, nullptr, -1.0, c->Xpl, n, c->Rpl, n, b, st, c->wdup,
+                             c->redge));
     } else {
       if ((s = rotate(c->AYpl, c->Xt, c->Rpl, 1.0, nullptr)) != CHFSI_OK) return s;
       CK(copy_block(c->Xt, m, c->TL, m, m, m, st));
@@ -2209,6 +2215,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
       const size_t sel = params->filter_prec == CHFSI_PREC_BF16 ? sizeof(uint16_t) : el;
       for (auto& e : c->bedge)
         e = ctx_alloc<char>(c, size_t(2) * A->ny * A->nz * 2 * b * sel, &st);
+      c->redge = ctx_alloc<double>(c, size_t(2) * A->ny * A->nz * 2 * b * sizeof(double), &st);
     } else {
       c->Lc = ctx_alloc<char>(c, size_t(n) * 2 * n * lel, &st);
       c->dinv2 = ctx_alloc<char>(c, size_t(2) * n * el, &st);

@@ -23,10 +23,16 @@ hipError_t stencil_check(const chfsi_operator& op);
 // nonzero at the n - (nx-2)(ny-2)(nz-2) boundary points only.
 // dst += alpha * colscale[j] * correction of (dinv .* src) for column pair j,
 // in place (dinv NULL: identity; colscale NULL: ones; both device arrays)
+// edge (may be null): src's row ends as for bloch_corr below.
 template <typename F>
 hipError_t bloch_fix(const chfsi_operator& op, const double* dinv, double alpha, const F* src,
                      int64_t lds, F* dst, int64_t ldd, int64_t pairs, hipStream_t st,
-                     const double* colscale = nullptr);
+                     const double* colscale = nullptr, const F* edge = nullptr);
+// edge (2 ny nz per column, ld 2 ny nz) = the x = 0 and x = nx-1 values of
+// every grid row of the planar block src (cols columns, ld lds)
+template <typename T>
+hipError_t bloch_edges(const chfsi_operator& op, const T* src, int64_t lds, T* edge, int64_t cols,
+                       hipStream_t st);
 // corr (boundary points x 2 pairs, ld ldc >= boundary points) = alpha *
 // correction of (dinv .* src), in the boundary-point enumeration of bloch.hip.
 // edge (may be null): src's x = 0 and x = nx-1 values, ((z ny + y) 2 +
