@@ -504,7 +504,11 @@ static void plan_impl(int64_t M, int64_t N, int64_t K, int batch, bool filter_la
                       int* splits) {
   (void)filter_layout;
   const int ncfg = sizeof(T) == 4 ? kNumF32 : kNumF64;
-  if (sizeof(T) == 8 && batch == 1 && M >= 128 && N >= 128 && K >= 16 * std::max(M, N)) {
+  // the long-K rule also serves the complex Gram products (two batched
+  // b x b blocks; knob CHFSI_GEMM64_LONG_BATCHED = 0 gives them the general plan)
+  const bool long_batched = env_int("CHFSI_GEMM64_LONG_BATCHED", 1) > 0 && batch <= 2;
+  if (sizeof(T) == 8 && (batch == 1 || long_batched) && M >= 128 && N >= 128 &&
+      K >= 16 * std::max(M, N)) {
     int lcfg = env_int("CHFSI_GEMM64_LONG_CFG", 1);
     if (lcfg < 0 || lcfg >= kNumF64) lcfg = 1;
     const int lsplits = env_int("CHFSI_GEMM64_LONG_SPLITS", 8);
