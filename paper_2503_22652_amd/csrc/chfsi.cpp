@@ -1477,46 +1477,56 @@ chfsi_status fix_pair_clusters(chfsi_ctx* c, double* E, int64_t lde, int64_t cd,
         }
       };
       // pivoted: each step keeps the candidate that retains the largest part of
-      // its norm outside the vectors kept so far
-      std::vector<std::complex<double>> q;   // accepted vectors, cd each
+      // its norm outside the vectors kept so far.  With the kept q_a
+      // G-orthonormal, the coefficients are (G q_a)^H u and the remaining
+      // squared norm is |u|_G^2 - sum |coefficient|^2, so G is applied once
+      // per candidate and once per kept vector.
+      std::vector<std::complex<double>> q, Gq;   // kept vectors and G times them, cd each
       std::vector<std::vector<std::complex<double>>> cand(cols, std::vector<std::complex<double>>(cd));
       std::vector<double> n0(cols);
       std::vector<char> used(cols, 0);
-      const auto gnorm = [&](const std::vector<std::complex<double>>& u) {
-        apply_metric(u);
-        double r = 0.0;
-        for (int64_t i = 0; i < cd; ++i) r += std::real(std::conj(u[i]) * Gu[i]);
-        return std::sqrt(std::max(r, 0.0));
-      };
       for (int64_t v = 0; v < cols; ++v) {
         for (int64_t i = 0; i < cd; ++i) cand[v][i] = {h[v * rows + i], h[v * rows + cd + i]};
-        n0[v] = gnorm(cand[v]);
+        apply_metric(cand[v]);
+        double r = 0.0;
+        for (int64_t i = 0; i < cd; ++i) r += std::real(std::conj(cand[v][i]) * Gu[i]);
+        n0[v] = std::sqrt(std::max(r, 0.0));
       }
       for (int64_t t = 0; t < j1 - j0; ++t) {
         int64_t best = -1;
         double best_ratio = 0.0;
-        std::vector<std::complex<double>> best_u;
         for (int64_t v = 0; v < cols; ++v) {
           if (used[v] || !(n0[v] > 0.0)) continue;
-          std::vector<std::complex<double>> u = cand[v];
-          for (int pass = 0; pass < 2; ++pass)
-            for (size_t a = 0; a < q.size(); a += cd) {
-              apply_metric(u);
-              std::complex<double> d = 0.0;   // q_a^H G u
-              for (int64_t i = 0; i < cd; ++i) d += std::conj(q[a + i]) * Gu[i];
-              for (int64_t i = 0; i < cd; ++i) u[i] -= d * q[a + i];
-            }
-          const double ratio = gnorm(u) / n0[v];
+          double rem = n0[v] * n0[v];
+          for (size_t a = 0; a < q.size(); a += cd) {
+            std::complex<double> d = 0.0;
+            for (int64_t i = 0; i < cd; ++i) d += std::conj(Gq[a + i]) * cand[v][i];
+            rem -= std::norm(d);
+          }
+          const double ratio = std::sqrt(std::max(rem, 0.0)) / n0[v];
           if (ratio > best_ratio) {
             best_ratio = ratio;
             best = v;
-            best_u = u;
           }
         }
         if (best < 0 || !(best_ratio > 1e-6)) break;   // the cluster's span is exhausted
         used[best] = 1;
-        const double nrm = gnorm(best_u);
-        for (int64_t i = 0; i < cd; ++i) q.push_back(best_u[i] / nrm);
+        std::vector<std::complex<double>> u = cand[best];
+        for (int pass = 0; pass < 2; ++pass)   // projection, repeated once for accuracy
+          for (size_t a = 0; a < q.size(); a += cd) {
+            std::complex<double> d = 0.0;
+            for (int64_t i = 0; i < cd; ++i) d += std::conj(Gq[a + i]) * u[i];
+            for (int64_t i = 0; i < cd; ++i) u[i] -= d * q[a + i];
+          }
+        apply_metric(u);
+        double r = 0.0;
+        for (int64_t i = 0; i < cd; ++i) r += std::real(std::conj(u[i]) * Gu[i]);
+        const double nrm = std::sqrt(std::max(r, 0.0));
+        if (!(nrm > 0.0)) break;
+        for (int64_t i = 0; i < cd; ++i) {
+          q.push_back(u[i] / nrm);
+          Gq.push_back(Gu[i] / nrm);
+        }
       }
       if (int64_t(q.size()) != cd * (j1 - j0)) {
         set_error("a cluster of %lld equal complex eigenvalues has no orthonormal basis in the "
