@@ -142,9 +142,10 @@ def main():
     opA, opB = P.dense_operator(A), P.dense_operator(B)
     stream = torch.cuda.current_stream()
 
-    def ctx_for(method, prec, profile=0, max_iter=60, tol=1e-8):
+    def ctx_for(method, prec, profile=0, max_iter=60, tol=1e-8, binv_exact=0):
         prm = P.make_params(nw, b, p, max_iter=max_iter, tol=tol, method=method,
-                            filter_prec=prec, lambda_max=lmax, profile=profile)
+                            filter_prec=prec, lambda_max=lmax, profile=profile,
+                            binv_exact=binv_exact)
         return P.chfsi_create(opA, opB, d, prm, stream=stream, keep=(A, B, d))
 
     # ------------------------------------------------------------------
@@ -228,16 +229,23 @@ def main():
     }
 
     # ------------------------------------------------------------------
-    # extras: time to residual 1e-8 (FP32 R-ChFSI, FP64 R-ChFSI) and the
-    # FP64 plain filter (stagnation floor with D^{-1}; its filter rate)
+    # extras: time to residual 1e-8 (FP32/BF16/FP64 R-ChFSI, the plain FP64
+    # filter with the exact inverse B^{-1}) and the plain FP64 filter with
+    # D^{-1} (stagnation floor; its filter rate)
     # ------------------------------------------------------------------
     if not args.no_extras:
         ttr = {}
         for name, method, prec, iters in (("fp32_rchfsi", P.METHOD_RCHFSI, P.PREC_FP32, 60),
                                           ("bf16_rchfsi", P.METHOD_RCHFSI, P.PREC_BF16, 60),
                                           ("fp64_rchfsi", P.METHOD_RCHFSI, P.PREC_FP64, 60),
+                                          ("fp64_chfsi_exact", P.METHOD_CHFSI, P.PREC_FP64, 60),
                                           ("fp64_chfsi_dinv", P.METHOD_CHFSI, P.PREC_FP64, 15)):
-            c2 = ctx_for(method, prec, profile=1, max_iter=iters)
+            exact = name == "fp64_chfsi_exact"
+            torch.cuda.synchronize()
+            t0c = time.perf_counter()
+            c2 = ctx_for(method, prec, profile=1, max_iter=iters, binv_exact=int(exact))
+            torch.cuda.synchronize()
+            create_s = time.perf_counter() - t0c
             Xs = P.to_colmajor(X0)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -251,6 +259,9 @@ def main():
                          "filter_ms": round(rep["time_filter_ms"], 2),
                          "rr_ms": round(rep["time_rr_ms"], 2),
                          "jacobi_sweeps": rep["jacobi_sweeps"]}
+            if exact:
+                # B^{-1} A formed once in chfsi_create (not in seconds above)
+                ttr[name]["setup_seconds"] = round(create_s, 3)
             if rep["kernel_launches"]:
                 ttr[name]["product_ms_per_launch"] = round(rep["kernel_ms"] / rep["kernel_launches"], 4)
                 ttr[name]["product_tflops"] = round(
@@ -261,6 +272,9 @@ def main():
             if ttr[lo + "_rchfsi"]["status"] == "OK" and ttr["fp64_rchfsi"]["status"] == "OK":
                 ttr[f"speedup_{lo}_vs_fp64_rchfsi"] = round(
                     ttr["fp64_rchfsi"]["seconds"] / ttr[lo + "_rchfsi"]["seconds"], 3)
+            if ttr[lo + "_rchfsi"]["status"] == "OK" and ttr["fp64_chfsi_exact"]["status"] == "OK":
+                ttr[f"speedup_{lo}_vs_fp64_chfsi_exact"] = round(
+                    ttr["fp64_chfsi_exact"]["seconds"] / ttr[lo + "_rchfsi"]["seconds"], 3)
         ttr["fp64_chfsi_filter_vs_fp32_rchfsi_filter_rate"] = round(
             ttr["fp32_rchfsi"]["filter_gflops"] / max(ttr["fp64_chfsi_dinv"]["filter_gflops"], 1e-9), 3)
         out["time_to_residual"] = ttr

@@ -148,7 +148,13 @@ typedef struct {
    *    residual block, the filter blocks and two slabs (chfsi_solve then works
    *    in the caller's X). */
   int32_t memory_mode;
-  int32_t reserved;
+  /* 1: the plain filter (CHFSI_METHOD_CHFSI, FP64) uses the exact inverse,
+   * H = B^{-1} A (Algorithm 2 with the generalized problem's own operator),
+   * for dense A and dense B.  chfsi_create forms H once from the Cholesky
+   * factor of B (B = L L^T, B^{-1} = L^{-T} L^{-1}, kept as A B^{-1} = H^T)
+   * and owns it (n^2 doubles); d_inv is not used by the filter then.
+   * 0: H = D^{-1} A. */
+  int32_t binv_exact;
 } chfsi_params;
 
 /* Per-solve report (host). */
@@ -164,7 +170,7 @@ typedef struct {
   int32_t jacobi_sweeps;       /* sum of eigensolver sweeps */
   int32_t kernel_launches;     /* profile: filter operator-product kernels timed */
   double kernel_ms;            /* profile: their summed durations (HIP events) */
-  int32_t flags;               /* bit 0: Gram Cholesky needed the diagonal shift fallback */
+  int32_t flags;               /* bit 0: a Gram matrix took the SVQB fallback */
   double history[CHFSI_MAX_HISTORY]; /* max residual after each pass (entry 0: initial RR) */
 } chfsi_report;
 
@@ -211,8 +217,12 @@ chfsi_status chfsi_filter(chfsi_ctx* ctx, const double* X, int64_t ldx, const do
  * X = Y E (B-orthonormal Ritz vectors, ascending Ritz values), R = A X - B X
  * Lambda and r_j = ||R_j||_2.  Y, X, R: device n x b; X must not alias Y.
  * ritz, resnorm: host, length b.  Synchronises the stream once.
- * Errors: CHFSI_ERR_NOT_SPD if the Gram matrix is not positive definite even
- * after column scaling and a diagonal shift; CHFSI_ERR_NUMERIC on NaN/Inf.
+ * A numerically singular Gram matrix takes the SVQB fallback: the directions
+ * above 1e-14 of its largest eigenvalue are kept, the others refilled with
+ * N(0,1) values, and Rayleigh-Ritz repeated once (chfsi_report.flags bit 0).
+ * Errors: CHFSI_ERR_NOT_SPD if the Gram matrix has a zero or non-finite
+ * column, or is not positive definite after the refill; CHFSI_ERR_NUMERIC on
+ * NaN/Inf.
  */
 chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* ctx, const double* Y, int64_t ldy, double* X,
                                  int64_t ldx, double* R, int64_t ldr, double* ritz,

@@ -42,7 +42,7 @@ class chfsi_params(C.Structure):
                 ("filter_prec", C.c_int32), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("lambda_T", C.c_double), ("seed", C.c_uint64),
                 ("init_random", C.c_int32), ("profile", C.c_int32),
-                ("memory_mode", C.c_int32), ("reserved", C.c_int32)]
+                ("memory_mode", C.c_int32), ("binv_exact", C.c_int32)]
 
 
 class chfsi_report(C.Structure):
@@ -221,13 +221,14 @@ def make_params(n_wanted: int, block: int, degree: int, max_iter: int = 100, tol
                 method: int = METHOD_RCHFSI, filter_prec: int = PREC_FP64,
                 lambda_min: float = math.nan, lambda_max: float = math.nan,
                 lambda_T: float = math.nan, seed: int = 0, init_random: int = 0,
-                profile: int = 0, memory_mode: int = 0) -> chfsi_params:
+                profile: int = 0, memory_mode: int = 0, binv_exact: int = 0) -> chfsi_params:
     p = chfsi_params()
     p.n_wanted, p.block, p.degree, p.max_iter, p.tol = n_wanted, block, degree, max_iter, tol
     p.method, p.filter_prec = method, filter_prec
     p.lambda_min, p.lambda_max, p.lambda_T = lambda_min, lambda_max, lambda_T
     p.seed, p.init_random, p.profile = seed, init_random, profile
     p.memory_mode = memory_mode
+    p.binv_exact = binv_exact
     return p
 
 

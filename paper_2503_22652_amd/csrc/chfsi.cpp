@@ -100,6 +100,7 @@ struct chfsi_ctx {
   uint16_t* A16 = nullptr;        // bfloat16 copy of a dense operator (BF16 residual filter)
   float* dinv32 = nullptr;        // FP32 D^{-1} (dense: always; stencil: only when given)
   float* Vf = nullptr;            // FP32 potential of a stencil operator (FP32/BF16 filter)
+  double* Ht = nullptr;           // exact-inverse filter operator, stored as H^T = A B^{-1} (n x n)
   // complex Hermitian operator (residual filter only): planar left operand
   // L = [A_r | A_i] (n x 2n, filter precision), [d; d], the materialised right
   // operand Z~ (2n x 2b, FP32/FP64) and its bfloat16 copy (BF16)
@@ -199,7 +200,7 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
                 "with the same wave vector and no field");
       return CHFSI_ERR_ARG;
     }
-    if (p->method != CHFSI_METHOD_RCHFSI || p->memory_mode != 0) {
+    if (p->method != CHFSI_METHOD_RCHFSI || p->memory_mode != 0 || p->binv_exact != 0) {
       set_error("complex Hermitian operators support the residual filter with memory_mode 0");
       return CHFSI_ERR_ARG;
     }
@@ -229,7 +230,7 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
       set_error("with a Hermitian A, B must be the identity or a Hermitian dense matrix of A's size");
       return CHFSI_ERR_ARG;
     }
-    if (p->method != CHFSI_METHOD_RCHFSI || p->memory_mode != 0) {
+    if (p->method != CHFSI_METHOD_RCHFSI || p->memory_mode != 0 || p->binv_exact != 0) {
       set_error("complex Hermitian operators support the residual filter with memory_mode 0");
       return CHFSI_ERR_ARG;
     }
@@ -307,6 +308,13 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
   }
   if (p->filter_prec == CHFSI_PREC_BF16 && p->method != CHFSI_METHOD_RCHFSI) {
     set_error("BF16 filters are implemented for the residual filter only");
+    return CHFSI_ERR_ARG;
+  }
+  if (p->binv_exact != 0 &&
+      (p->binv_exact != 1 || A->kind != CHFSI_OP_DENSE || is_identity(B) ||
+       B->kind != CHFSI_OP_DENSE || p->method != CHFSI_METHOD_CHFSI ||
+       p->filter_prec != CHFSI_PREC_FP64 || p->memory_mode != 0)) {
+    set_error("binv_exact needs dense A and B and the plain filter in FP64");
     return CHFSI_ERR_ARG;
   }
   if (p->memory_mode != 0) {
@@ -464,6 +472,7 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
   }
   s.total = s.a32 + filt + 2 * s.coef + rr + 10 * s.bb + 4 * b * sizeof(double) + 64 + s.ws +
             s.ws_eig + s.tri;
+  if (p->binv_exact) s.total += size_t(n) * n * sizeof(double);   // H^T (formation: 3 more, freed)
   return s;
 }
 
@@ -1012,16 +1021,18 @@ chfsi_status filter_chfsi(chfsi_ctx* c, const double* X, int64_t ldx, double* Yp
         g.M = n;
         g.N = b;
         g.K = n;
-        g.A = c->A.dense;
+        // H = D^{-1} A (A symmetric, read k-contiguous, rows scaled by D^{-1}),
+        // or the exact H = B^{-1} A read k-contiguous from its transpose A B^{-1}
+        g.A = c->Ht ? c->Ht : c->A.dense;
         g.sak = 1;
-        g.sam = c->A.ld;
+        g.sam = c->Ht ? n : c->A.ld;
         g.B = src;
         g.sbk = 1;
         g.sbn = ldsrc;
         g.C = dst;
         g.ldc = n;
         g.epi.alpha = alpha;
-        g.epi.rowscale = c->dinv;
+        g.epi.rowscale = c->Ht ? nullptr : c->dinv;
         g.epi.beta = beta;
         g.epi.C1 = src;
         g.epi.ldc1 = ldsrc;
@@ -2150,6 +2161,79 @@ void bounds_policy(const chfsi_params& p, const double* ritz, int64_t b, double*
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// H^T = A B^{-1} for the exact-inverse plain filter (Algorithm 2 with
+// H = B^{-1} A): B = L L^T (blocked Cholesky), L^{-1} by a triangular solve
+// on the identity, B^{-1} = L^{-T} L^{-1} and A B^{-1} as FP64 products.  The
+// n x n temporaries are the function's own and freed before it returns.
+chfsi_status form_exact_operator(chfsi_ctx* c, const chfsi_operator* A, const chfsi_operator* B) {
+  const int64_t n = c->n;
+  hipStream_t st = c->stream;
+  const size_t bytes = size_t(n) * n * sizeof(double);
+  double *L = nullptr, *Li = nullptr, *tri = nullptr;
+  int* info = nullptr;
+  auto release = [&]() {
+    if (L) (void)hipFree(L);
+    if (Li) (void)hipFree(Li);
+    if (tri) (void)hipFree(tri);
+    if (info) (void)hipFree(info);
+  };
+  if (hipMalloc(&L, bytes) != hipSuccess || hipMalloc(&Li, bytes) != hipSuccess ||
+      hipMalloc(&tri, tri_workspace_bytes(n, n)) != hipSuccess ||
+      hipMalloc(&info, 64) != hipSuccess) {
+    release();
+    set_error("hipMalloc failed for the exact inverse (3 n^2 doubles)");
+    return CHFSI_ERR_NOMEM;
+  }
+  chfsi_status s = CHFSI_OK;
+  auto run = [&]() -> chfsi_status {
+    CK(copy_block(B->dense, B->ld, L, n, n, n, st));
+    CK(fill_zero(info, sizeof(int), st));
+    CK(potrf_lower(L, n, n, info, st, c->ws, tri));
+    int h_info = 0;
+    CK(hipMemcpyAsync(&h_info, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (h_info != 0) {
+      set_error("B is not positive definite (Cholesky pivot %d)", h_info);
+      return CHFSI_ERR_NOT_SPD;
+    }
+    CK(set_identity(Li, n, n, st));
+    CK(trsm_lower_left(L, n, Li, n, n, n, st, c->ws, tri, true));
+    {
+      GemmDesc<double> g;   // B^{-1} = L^{-T} L^{-1}, into L
+      g.M = n;
+      g.N = n;
+      g.K = n;
+      g.A = Li;             // A(m, k) = L^{-1}(k, m)
+      g.sak = 1;
+      g.sam = n;
+      g.B = Li;
+      g.sbk = 1;
+      g.sbn = n;
+      g.C = L;
+      g.ldc = n;
+      CK(gemm<double>(g, st, c->ws));
+      GemmDesc<double> h;   // H^T = A B^{-1}
+      h.M = n;
+      h.N = n;
+      h.K = n;
+      h.A = A->dense;       // A symmetric: A(m, k) = dense[k + m ld]
+      h.sak = 1;
+      h.sam = A->ld;
+      h.B = L;
+      h.sbk = 1;
+      h.sbn = n;
+      h.C = c->Ht;
+      h.ldc = n;
+      CK(gemm<double>(h, st, c->ws));
+    }
+    CK(hipStreamSynchronize(st));
+    return CHFSI_OK;
+  };
+  s = run();
+  release();
+  return s;
+}
+
 extern "C" {
 
 const char* chfsi_last_error(void) { return g_last_error.c_str(); }
@@ -2315,6 +2399,7 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   if (!c->cplx) {
   if (!dense && params->filter_prec != CHFSI_PREC_FP64 && A->field_mode != 0)
     c->Vf = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+  if (params->binv_exact) c->Ht = ctx_alloc<double>(c, size_t(n) * n * sizeof(double), &st);
   c->coef_cap = params->degree;
   c->coef32 = ctx_alloc<float>(c, size_t(params->degree) * b * sizeof(float), &st);
   c->coef64 = ctx_alloc<double>(c, size_t(params->degree) * b * sizeof(double), &st);
@@ -2415,6 +2500,13 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   }
   if (e == hipSuccess && c->Vf) e = convert_f64_f32(A->field, n, c->Vf, n, n, 1, c->stream);
   if (e == hipSuccess && (A->kind == CHFSI_OP_STENCIL27 || c->bloch)) e = stencil_check(*A);
+  if (e == hipSuccess && c->Ht) {
+    const chfsi_status fs = form_exact_operator(c, A, B);
+    if (fs != CHFSI_OK) {
+      chfsi_destroy(c);
+      return fs;
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     set_error("context setup failed: %s", hipGetErrorString(e));

@@ -90,3 +90,23 @@ def test_bloch_operator_checks_without_gpu():
     assert P.chfsi_workspace_bytes(nan, None, P.make_params(10, 20, 8, lambda_max=5.0)) == 0
     nofield = P.stencil_operator((8, 8, 8), coef, field_mode=2, bloch=k)   # mode 2 without V
     assert P.chfsi_workspace_bytes(nofield, None, P.make_params(10, 20, 8, lambda_max=5.0)) == 0
+
+
+def test_exact_inverse_parameter_checks_without_gpu():
+    """binv_exact needs dense A and B, the plain filter and FP64."""
+    import paper_2503_22652_amd as P
+    A = P.identity_operator(64)
+    A.kind, A.dense, A.ld = P.OP_DENSE, 0x1000, 64     # never dereferenced by the size query
+    B = P.identity_operator(64)
+    B.kind, B.dense, B.ld = P.OP_DENSE, 0x2000, 64
+
+    def ws(B_, **kw):
+        return P.chfsi_workspace_bytes(A, B_, P.make_params(8, 16, 8, lambda_max=5.0, **kw))
+
+    plain = ws(B, method=P.METHOD_CHFSI, filter_prec=P.PREC_FP64)
+    exact = ws(B, method=P.METHOD_CHFSI, filter_prec=P.PREC_FP64, binv_exact=1)
+    assert exact >= plain + 64 * 64 * 8 > 0
+    assert ws(None, method=P.METHOD_CHFSI, filter_prec=P.PREC_FP64, binv_exact=1) == 0
+    assert ws(B, method=P.METHOD_RCHFSI, filter_prec=P.PREC_FP64, binv_exact=1) == 0
+    assert ws(B, method=P.METHOD_CHFSI, filter_prec=P.PREC_FP32, binv_exact=1) == 0
+    assert ws(B, method=P.METHOD_CHFSI, filter_prec=P.PREC_FP64, binv_exact=2) == 0
