@@ -1157,7 +1157,7 @@ hipError_t stencil_rchfsi_step_f64(const chfsi_operator& op, const double* dinv,
                                    double* RX, const double* Yf, int64_t ldf,
                                    const double* colcoef, StencilStep s, int64_t b,
                                    hipStream_t st, const BlochStep* bloch) {
-  if (bloch && b % 2 != 0) return hipErrorInvalidValue;
+  if (bloch && (b % 2 != 0 || bloch->ld_corr % 4 != 0)) return hipErrorInvalidValue;
   ZmArgs<double> z;
   if (!dinv && RX && Yf && zm_setup(op, 2, zm_per_wg(false), s.alpha, s.beta, &z) &&
       zm_aligned(RY, op.n, 16, 2) && zm_aligned(RX, op.n, 16, 2) && zm_aligned(Yf, ldf, 16, 2) &&
@@ -1217,7 +1217,7 @@ hipError_t stencil_rchfsi_step_f32(const chfsi_operator& op, const float* Vf, co
                                    const float* RY, float* RX, const float* Yf,
                                    const float* colcoef, StencilStep s, int64_t b, hipStream_t st,
                                    const BlochStep* bloch) {
-  if (bloch && b % 2 != 0) return hipErrorInvalidValue;
+  if (bloch && (b % 2 != 0 || bloch->ld_corr % 4 != 0)) return hipErrorInvalidValue;
   ZmArgs<float> z;
   const int pt = zm_pt_lowp();
   const size_t vb = size_t(pt) * sizeof(float);
@@ -1283,7 +1283,7 @@ hipError_t stencil_rchfsi_step_bf16(const chfsi_operator& op, const float* Vf, c
                                     const void* RY, void* RX, const void* Yf,
                                     const float* colcoef, StencilStep s, int64_t b,
                                     hipStream_t st, const BlochStep* bloch) {
-  if (bloch && b % 2 != 0) return hipErrorInvalidValue;
+  if (bloch && (b % 2 != 0 || bloch->ld_corr % 4 != 0)) return hipErrorInvalidValue;
   const uint16_t* RY16 = static_cast<const uint16_t*>(RY);
   ZmArgs<float> z;
   const int pt = zm_pt_lowp();

@@ -47,7 +47,7 @@ hipError_t bloch_corr(const chfsi_operator& op, const double* dinv, double alpha
 // bloch_fix after the step.
 struct BlochStep {
   void* corr;          // boundary points x b buffer in the step's arithmetic type
-  int64_t ld_corr;
+  int64_t ld_corr;     // >= boundary points, a multiple of 4 (16-byte aligned column starts)
   const double* dinv;  // FP64 D^{-1} of the correction (NULL: identity)
   const void* edge_in; // row-end values of RY (storage type; may be null)
   void* edge_out;      // receives the row-end values of the step's output (may be null)
