@@ -288,3 +288,31 @@ def test_bloch_rayleigh_ritz_singular_gram_uses_svqb():
     assert np.linalg.norm(Xg.conj().T @ Bd @ Xg - np.eye(b)) <= 1e-9
     Rg = Ad @ Xg - (Bd @ Xg) * ritz[None, :]
     np.testing.assert_allclose(norms, np.linalg.norm(Rg, axis=0), rtol=1e-6, atol=1e-9)
+
+
+def test_bloch_rayleigh_ritz_equal_ritz_values():
+    """V = 0 at k = 0: the pencil's spectrum is the Fourier symbol, whose lowest
+    15 eigenvalues come in clusters of 1, 2, 2, 4, 2 and 4 equal values.  A
+    mixed basis of their invariant subspace must give those values and
+    B-orthonormal Ritz vectors for every cluster."""
+    shape = (6, 8, 10)
+    n, b = int(np.prod(shape)), 15
+    cA, cB = 0.5 * wl.tensor_stencil_27("stiffness"), wl.tensor_stencil_27("mass")
+    V = np.zeros(shape)
+    apply_A, apply_B = stencil.make_ops_bloch(cA, cB, V, shape, 2, (0.0, 0.0, 0.0))
+    Ad, Bd = apply_A(np.eye(n)), apply_B(np.eye(n))
+    w, U = sla.eigh(Ad, Bd)
+    rng = np.random.default_rng(91)
+    Y = U[:, :b] @ (rng.standard_normal((b, b)) + 1j * rng.standard_normal((b, b)))
+    Vd = torch.zeros(n, dtype=torch.float64, device="cuda")
+    opA = P.stencil_operator(shape, cA, coef_mass=cB, field=Vd, field_mode=2, bloch=(0.0, 0.0, 0.0))
+    opB = P.stencil_operator(shape, cB, bloch=(0.0, 0.0, 0.0))
+    prm = P.make_params(b, b, 4, method=P.METHOD_RCHFSI, lambda_max=LMAX)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    X, R = P.colmajor_empty_complex(n, b), P.colmajor_empty_complex(n, b)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor_complex(Y), X, R)
+    np.testing.assert_allclose(ritz, w[:b], rtol=0, atol=1e-11)
+    Xg = X.cpu().numpy()
+    assert np.linalg.norm(Xg.conj().T @ Bd @ Xg - np.eye(b)) <= 1e-10
+    assert np.max(np.linalg.norm(Ad @ Xg - Bd @ Xg * np.array(ritz)[None, :], axis=0)) <= 1e-10
+    assert np.max(norms) <= 1e-10
