@@ -174,19 +174,6 @@ __global__ __launch_bounds__(kThreads) void k_embed_gram_lower(const double* __r
   }
 }
 
-// planar b x b complex matrix Zx (b x 2b, ld b) from the first vector of each
-// eigenvalue pair of the embedded problem: x_j = T(0:b, 2j) + i T(b:2b, 2j)
-__global__ __launch_bounds__(kThreads) void k_select_pairs(const double* __restrict__ T, int64_t b,
-                                                           double* __restrict__ Zx) {
-  const int64_t m = 2 * b, total = b * b;
-  for (int64_t idx = blockIdx.x * int64_t(kThreads) + threadIdx.x; idx < total;
-       idx += int64_t(gridDim.x) * kThreads) {
-    const int64_t j = idx / b, i = idx - j * b;
-    Zx[i + j * b] = T[i + (2 * j) * m];
-    Zx[i + (b + j) * b] = T[(b + i) + (2 * j) * m];
-  }
-}
-
 // SVQB for the embedded problem: planar W (b x 2k, ld b; real parts then
 // imaginary parts) from the first vector of the eigenvalue pairs first,
 // first + 2, ... of the m x m eigenvector matrix E (ld lde), scaled per pair
@@ -225,8 +212,9 @@ __global__ __launch_bounds__(kThreads) void k_embed_block(const double* __restri
 }
 
 // Zx (b x 2b planar, ld b) from the first vector of each of the first k
-// eigenvalue pairs of T (2b rows, ld ldt): x_j = T(0:b, 2j) + i T(b:2b, 2j);
-// columns k..b-1 of both halves are zero
+// eigenvalue pairs of an embedded problem's eigenvector matrix T (2b rows,
+// ld ldt): x_j = T(0:b, 2j) + i T(b:2b, 2j); columns k..b-1 of both halves
+// are zero
 __global__ __launch_bounds__(kThreads) void k_select_pairs_n(const double* __restrict__ T,
                                                              int64_t ldt, int64_t b, int64_t k,
                                                              double* __restrict__ Zx) {
@@ -274,11 +262,6 @@ hipError_t planar_to_cplx(const double* P, int64_t n, int64_t b, double* Z, int6
 
 hipError_t embed_gram_lower(const double* P4, int64_t b, double* M, hipStream_t st) {
   k_embed_gram_lower<<<grid_for(4 * b * b), kThreads, 0, st>>>(P4, b, M);
-  return hipGetLastError();
-}
-
-hipError_t select_pairs(const double* T, int64_t b, double* Zx, hipStream_t st) {
-  k_select_pairs<<<grid_for(b * b), kThreads, 0, st>>>(T, b, Zx);
   return hipGetLastError();
 }
 

@@ -130,10 +130,8 @@ hipError_t planar_to_cplx(const double* P, int64_t n, int64_t b, double* Z, int6
 // [Y_r Y_i]^T [W_r W_i] (consecutive in P4, ld b)
 hipError_t embed_gram_lower(const double* P4, int64_t b, double* M, hipStream_t st);
 // Zx (b x 2b planar, ld b): column j = T(0:b, 2j), column b+j = T(b:2b, 2j)
-// of the 2b x 2b eigenvector matrix T of an embedded problem
-hipError_t select_pairs(const double* T, int64_t b, double* Zx, hipStream_t st);
-// the same for the first k pairs of a T with 2b rows and leading dimension
-// ldt; columns k..b-1 of Zx are zero
+// for the first k eigenvalue pairs of the eigenvector matrix T (2b rows, ld
+// ldt) of an embedded problem; columns k..b-1 of Zx are zero
 hipError_t select_pairs_n(const double* T, int64_t ldt, int64_t b, int64_t k, double* Zx,
                           hipStream_t st);
 // SVQB on the embedded Gram matrix: planar W (b x 2k) from the first vector of
