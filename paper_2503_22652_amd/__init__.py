@@ -328,12 +328,16 @@ def report_dict(rep: chfsi_report) -> dict:
 
 
 def _ld(t) -> int:
-    """Leading dimension of a column-major 2D tensor view (stride of dim 1)."""
+    """Leading dimension of a column-major 2D tensor view (stride of dim 1).
+
+    A single column is addressed without its leading dimension, and the stride
+    that torch (or numpy, whose strides of size-1 dimensions are arbitrary)
+    reports for it can be anything, so its leading dimension is its length."""
     if t.dim() == 1:
         return t.shape[0]
-    if t.stride(0) != 1:
+    if t.stride(0) != 1 and t.shape[0] > 1:
         raise ValueError("blocks must be column-major (stride(0) == 1); use X.t().contiguous().t()")
-    return t.stride(1)
+    return t.shape[0] if t.shape[1] == 1 else t.stride(1)
 
 
 def colmajor_empty(n: int, b: int, dtype=None, device="cuda"):

@@ -110,3 +110,21 @@ def test_exact_inverse_parameter_checks_without_gpu():
     assert ws(B, method=P.METHOD_RCHFSI, filter_prec=P.PREC_FP64, binv_exact=1) == 0
     assert ws(B, method=P.METHOD_CHFSI, filter_prec=P.PREC_FP32, binv_exact=1) == 0
     assert ws(B, method=P.METHOD_CHFSI, filter_prec=P.PREC_FP64, binv_exact=2) == 0
+
+
+def test_leading_dimension_of_blocks_without_gpu():
+    """The binding passes a block's column stride as its leading dimension.
+    A single column's stride is arbitrary (numpy reports any value for a size-1
+    dimension), so its leading dimension is its length; a row-major block is
+    refused rather than read with the wrong layout."""
+    import numpy as np
+    torch = pytest.importorskip("torch")
+    import paper_2503_22652_amd as P
+    one = torch.from_numpy(np.ascontiguousarray(np.zeros((37, 1)).T)).t()
+    assert P._ld(one) == 37
+    assert P._ld(torch.empty((5, 40), dtype=torch.float64).t()) == 40
+    assert P._ld(torch.empty((5, 48), dtype=torch.float64).t()[:40]) == 48
+    with pytest.raises(ValueError):
+        P._ld(torch.empty((40, 5), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        P._ld(torch.empty((80, 1), dtype=torch.float64)[::2])
