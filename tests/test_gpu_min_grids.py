@@ -97,3 +97,39 @@ def test_min_grid_rayleigh_ritz_matches_oracle(bloch, shape):
     Rref = apply_A(Xg) - apply_B(Xg) * lam[None, :]
     assert np.linalg.norm(Rg - Rref) <= 1e-10 * LMAX
     np.testing.assert_allclose(norms, np.linalg.norm(Rref, axis=0), rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 8), (5, 20, 64)])
+@pytest.mark.parametrize("bloch", [None, K], ids=["real", "bloch"])
+@pytest.mark.parametrize("prec,tol", [(P.PREC_FP64, 1e-11), (P.PREC_FP32, 1e-4),
+                                      (P.PREC_BF16, 1e-1)])
+def test_single_vector_filter_and_rayleigh_ritz(prec, tol, bloch, shape):
+    """A block of one vector (one column, or one planar pair at a wave vector):
+    every column group of the kernels but the first is idle."""
+    apply_A, apply_B, opA, opB, Vd = _problem(shape, bloch, seed=10)
+    n, b, deg = int(np.prod(shape)), 1, 10
+    cplx = bloch is not None
+    prm = P.make_params(1, b, deg, method=P.METHOD_RCHFSI, filter_prec=prec, lambda_max=LMAX)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    Y0 = wl.random_block_complex(n, b, 6) if cplx else wl.random_block(n, b, 6)
+    to_cm = P.to_colmajor_complex if cplx else P.to_colmajor
+    empty = P.colmajor_empty_complex if cplx else P.colmajor_empty
+    print("single vector", shape, "bloch" if cplx else "real", "prec", prec, flush=True)
+    X, R = empty(n, b), empty(n, b)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, to_cm(Y0), X, R)
+    o = rr.rayleigh_ritz(Y0, apply_A, apply_B)
+    assert abs(ritz[0] - o["lam"][0]) <= 1e-11 * max(abs(o["lam"][0]), 1.0)
+    np.testing.assert_allclose(norms, o["resnorm"], rtol=1e-7)
+    bounds = (o["lam"][0] - 0.5, LMAX, o["lam"][0] + 0.5)
+    Y = empty(n, b)
+    P.chfsi_filter(ctx, to_cm(o["X"]), o["lam"], to_cm(o["R"]), Y, *bounds, degree=deg)
+    torch.cuda.synchronize()
+    got = Y.cpu().numpy()
+    ref, RYp, _ = filters.residual_filter(apply_A, filters.identity_op(), o["X"], o["lam"],
+                                          o["R"], deg, *bounds, return_parts=True)
+    err, part = np.linalg.norm(got - ref), np.linalg.norm(RYp)
+    print("  err / ||residual part||", err / part, "rel", _rel(got, ref))
+    if prec == P.PREC_FP64:
+        assert _rel(got, ref) <= tol
+    else:
+        assert err <= tol * part
