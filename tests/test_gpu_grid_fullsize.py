@@ -98,3 +98,47 @@ def test_bf16_bloch_grid_filter_fullsize_sampled_columns():
     print("per-column err / residual part:", err / part)
     assert np.all(np.isfinite(got))
     assert np.all(err <= 1e-1 * part)
+
+
+def test_bf16_grid160_filter_fullsize_sampled_columns():
+    """The 160^3 pencil with 200 Gaussian wells (N = 4.1M), BF16 residual filter.
+    The 2400-column block of the large grid workload leaves no room for FP64
+    copies of X, R and Y beside it (79 GB each), so this runs 240 columns: the
+    column groups are independent, and each is launched with the same tile
+    shape (rows of 160 points, the same slab height) as in the full block."""
+    torch.cuda.empty_cache()
+    prob = wl.stencil_problem(grid=160, n_wells=200, n_wanted=2000, block=2400, degree=40,
+                              seed=1004)
+    shape, b = prob.shape, 240
+    n = int(np.prod(shape))
+    apply_A, _ = stencil.make_ops(prob.coef_A, prob.coef_B, prob.V, shape, prob.field_mode)
+    Vd = torch.from_numpy(np.ascontiguousarray(prob.V).reshape(-1)).cuda()
+    opA = P.stencil_operator(shape, prob.coef_A, coef_mass=prob.coef_B, field=Vd,
+                             field_mode=prob.field_mode)
+    opB = P.stencil_operator(shape, prob.coef_B)
+    prm = P.make_params(200, b, prob.degree, method=P.METHOD_RCHFSI, filter_prec=P.PREC_BF16,
+                        lambda_max=18.5, memory_mode=1)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2004)
+    X = torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g).t()
+    R = torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g).t().mul_(1e-3)
+    lam = np.sort(np.random.default_rng(2004).uniform(-4.0, 1.0, b))
+    bounds = (lam[0] - 0.5, 18.5, lam[-1])
+    Y = P.colmajor_empty(n, b)
+    print("grid 160^3 b=240 BF16 filter, degree 4", flush=True)
+    P.chfsi_filter(ctx, X, lam, R, Y, *bounds, degree=4)
+    torch.cuda.synchronize()
+    cols = [0, 1, 2, 3, 121, b - 1]
+    Xc = X[:, cols].cpu().numpy()
+    Rc = R[:, cols].cpu().numpy()
+    got = Y[:, cols].cpu().numpy()
+    del X, R, Y
+    ctx.close()
+    ref, RYp, _ = filters.residual_filter(apply_A, filters.identity_op(), Xc, lam[cols], Rc, 4,
+                                          *bounds, return_parts=True)
+    err = np.linalg.norm(got - ref, axis=0)
+    part = np.linalg.norm(RYp, axis=0)
+    print("per-column err / residual part:", err / part)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= 1e-1 * part)
