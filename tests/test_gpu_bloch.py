@@ -316,3 +316,37 @@ def test_bloch_rayleigh_ritz_equal_ritz_values():
     assert np.linalg.norm(Xg.conj().T @ Bd @ Xg - np.eye(b)) <= 1e-10
     assert np.max(np.linalg.norm(Ad @ Xg - Bd @ Xg * np.array(ritz)[None, :], axis=0)) <= 1e-10
     assert np.max(norms) <= 1e-10
+
+
+@pytest.mark.parametrize("k", [(np.pi, np.pi, np.pi), (0.0, 0.0, 0.5), (-2.0, 0.0, 0.0)],
+                         ids=["zone-boundary", "z-only", "x-only"])
+@pytest.mark.parametrize("prec,tol", [(P.PREC_FP64, 1e-11), (P.PREC_BF16, 1e-1)])
+def test_bloch_special_wave_vectors(prec, tol, k):
+    """k = pi along every axis (the zone boundary: a wrap's phase exp(i pi n_d) is
+    +1 along x (n_x = 12) and -1 along y and z (n_y = 9, n_z = 5)), and wave
+    vectors along one axis only (the other wraps carry no phase)."""
+    shape = (5, 9, 12)
+    apply_A, apply_B, opA, opB, Vd = _problem(shape, seed=21, k=k)
+    n, b = int(np.prod(shape)), 6
+    prm = P.make_params(4, b, 8, method=P.METHOD_RCHFSI, filter_prec=prec, lambda_max=LMAX)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    Yh = wl.random_block_complex(n, b, 22)
+    X, R = P.colmajor_empty_complex(n, b), P.colmajor_empty_complex(n, b)
+    print("bloch k", k, "prec", prec, flush=True)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor_complex(Yh), X, R)
+    o = rr.rayleigh_ritz(Yh, apply_A, apply_B)
+    assert np.max(np.abs(np.array(ritz) - o["lam"])) <= 1e-11 * np.max(np.abs(o["lam"]))
+    bounds = (o["lam"][0] - 0.5, LMAX, o["lam"][-1])
+    Y = P.colmajor_empty_complex(n, b)
+    P.chfsi_filter(ctx, P.to_colmajor_complex(o["X"]), o["lam"], P.to_colmajor_complex(o["R"]),
+                   Y, *bounds, degree=8)
+    torch.cuda.synchronize()
+    got = Y.cpu().numpy()
+    ref, RYp, _ = filters.residual_filter(apply_A, filters.identity_op(), o["X"], o["lam"],
+                                          o["R"], 8, *bounds, return_parts=True)
+    err, part = np.linalg.norm(got - ref), np.linalg.norm(RYp)
+    print("  err / ||residual part||", err / part, "rel", _rel(got, ref))
+    if prec == P.PREC_FP64:
+        assert _rel(got, ref) <= tol
+    else:
+        assert err <= tol * part
