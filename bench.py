@@ -35,8 +35,9 @@ PEAK_HBM_GBS = 8000.0
 # device copy (FETCH x 2.000, WRITE x 1.000); summary under profiles/.  Other
 # shapes report null.
 TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.4e6}
-# the same for the BF16 z-march filter step on the 128^3 grid, block 1200
-TRAFFIC_ZMARCH = {(128, 1200, "bf16"): 21.98e9}
+# the same for the BF16 z-march filter step on the 128^3 grid (block 1200) and
+# the 160^3 grid (block 2400)
+TRAFFIC_ZMARCH = {(128, 1200, "bf16"): 21.98e9, (160, 2400, "bf16"): 89.61e9}
 # HBM bytes per Bloch filter step at 128^3 x 600 complex vectors (BF16): the
 # corrected z-march plus the boundary-correction kernel (two counter passes,
 # profiles/grid_128_b600_bloch_bf16_step_traffic.md)
