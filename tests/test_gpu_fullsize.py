@@ -10,6 +10,8 @@ FP32 filter (the bench's) and the BF16-product filter.
   values (tests/golden/dense_generalized_n8192_eigs.json), residuals and
   B-orthonormality recomputed on the CPU, Sylvester inertia (exactly 256
   negative eigenvalues).
+* The complex Hermitian counterpart of the same workload (device-built pencil,
+  320 complex vectors) on column samples, in FP64, FP32 and BF16.
 """
 import json
 import os
@@ -84,3 +86,48 @@ def test_rchfsi_solve_full_size(big, prec):
     assert res.max() <= 1e-8 * 1.01
     G = X[:, :64].T @ (p.B @ X[:, :64])
     np.testing.assert_allclose(G, np.eye(64), atol=1e-9)
+
+
+@pytest.mark.parametrize("prec,tol", [(P.PREC_FP64, 1e-11), (P.PREC_FP32, 1e-4),
+                                      (P.PREC_BF16, 3e-2)])
+def test_complex_filter_column_samples(prec, tol):
+    """The complex Hermitian counterpart that bench.py's dense run times (N = 8192,
+    320 complex vectors, 256 wanted, degree 20, device-built pencil with
+    ||D^-1 eps S||_2 = 0.05), in every filter precision: sampled columns of one
+    filter pass against the oracle on the host copies."""
+    from workloads.gpu import hermitian_problem
+    n, b, p = 8192, 320, 20
+    A, B, dinv, _ = hermitian_problem(n, 256, seed=1003)
+    lmax = 10.0 / (0.95 * float((1.0 / dinv).min())) + 0.1
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2003)
+    X = torch.complex(torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g),
+                      torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g)).t()
+    R = (1e-3 * torch.complex(torch.randn((b, n), dtype=torch.float64, device="cuda", generator=g),
+                              torch.randn((b, n), dtype=torch.float64, device="cuda",
+                                          generator=g))).t()
+    lam = np.sort(np.random.default_rng(2003).uniform(-1.0, 0.2, b))
+    bounds = (lam[0] - 0.05 * (lam[-1] - lam[0]), lmax, lam[-1])
+    prm = P.make_params(256, b, p, method=P.METHOD_RCHFSI, filter_prec=prec, lambda_max=lmax)
+    ctx = P.chfsi_create(P.hermitian_operator(A), P.hermitian_operator(B), dinv, prm,
+                         keep=(A, B, dinv))
+    Y = P.colmajor_empty_complex(n, b)
+    print("complex N=8192 b=320 filter, prec", prec, flush=True)
+    P.chfsi_filter(ctx, X, lam, R, Y, *bounds)
+    torch.cuda.synchronize()
+    cols = np.array([0, 1, 37, 128, 255, 256, 300, 319])
+    got = Y[:, cols].cpu().numpy()
+    Xc, Rc = X[:, cols].cpu().numpy(), R[:, cols].cpu().numpy()
+    Ah, dh = A.cpu().numpy(), dinv.cpu().numpy()
+    ctx.close()
+    del X, R, Y, A, B
+    ref, RYp, _ = filters.residual_filter(filters.dense_op(Ah), filters.diag_op(dh), Xc,
+                                          lam[cols], Rc, p, *bounds, return_parts=True)
+    err = np.linalg.norm(got - ref, axis=0)
+    part = np.linalg.norm(dh[:, None] * RYp, axis=0)
+    print("per-column err / residual part:", err / part, "rel", err / np.linalg.norm(ref, axis=0))
+    assert np.all(np.isfinite(got))
+    if prec == P.PREC_FP64:
+        assert np.all(err <= tol * np.linalg.norm(ref, axis=0))
+    else:
+        assert np.all(err <= tol * part)
