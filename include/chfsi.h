@@ -241,9 +241,11 @@ chfsi_status chfsi_solve(chfsi_ctx* ctx, double* X, int64_t ldx, double* evals, 
 
 /*
  * Profiling (params.profile = 1): total duration (ms, HIP events recorded on
- * the context's stream immediately around each launch) and count of the
- * filter's operator-product kernels -- the GEMM or stencil kernel of every
- * recurrence step, without the split-K reduction -- since the previous call.
+ * the context's stream immediately around each step) and count of the
+ * filter's recurrence steps -- every kernel of the step's fused operator
+ * product: the GEMM with its split-K reduction (which carries the three-term
+ * epilogue), the BF16 product's operand rounding, or the stencil kernel --
+ * since the previous call.
  * Synchronises the stream.  Returns CHFSI_ERR_ARG when profiling is off.
  */
 chfsi_status chfsi_filter_kernel_time(chfsi_ctx* ctx, double* total_ms, int32_t* launches);

@@ -38,6 +38,35 @@ __global__ __launch_bounds__(kThreads) void k_rchfsi_init_f32(const double* __re
   }
 }
 
+// Lambda recurrence of the residual filter (Algorithm 3; eq. ChFSIrecurrenceEigval),
+// one thread per column: Lambda_X = 1, Lambda_Y = (sigma1 / e)(lambda_j - c), then
+// for k = 2..p Lambda_X <- a Lambda_Y lambda_j - a c Lambda_Y - sigma sigma' Lambda_X
+// with sigma' = 1 / (2 / sigma1 - sigma), a = 2 sigma' / e, and the pair swaps.  The
+// step-k forcing coefficient of the block recurrence is Lambda_Y before that
+// step's update: it goes to row k - 2 of the table (FP64 and/or FP32), and the
+// final Lambda_Y to lamY for the reconstruction.
+__global__ __launch_bounds__(kThreads) void k_rchfsi_coef(const double* __restrict__ ritz,
+                                                           int64_t b, double e, double c,
+                                                           double sigma1, int p, double* coef64,
+                                                           float* coef32, double* lamY) {
+  const int64_t j = blockIdx.x * int64_t(kThreads) + threadIdx.x;
+  if (j >= b) return;
+  const double lam = ritz[j];
+  const double gamma = 2.0 / sigma1;
+  double lx = 1.0, ly = (sigma1 / e) * (lam - c), sigma = sigma1;
+  for (int k = 2; k <= p; ++k) {
+    const double sigma2 = 1.0 / (gamma - sigma);
+    const double a = 2.0 * sigma2 / e;
+    if (coef64) coef64[int64_t(k - 2) * b + j] = ly;
+    if (coef32) coef32[int64_t(k - 2) * b + j] = float(ly);
+    const double ln = a * ly * lam - a * c * ly - sigma * sigma2 * lx;
+    lx = ly;
+    ly = ln;
+    sigma = sigma2;
+  }
+  lamY[j] = ly;
+}
+
 __global__ __launch_bounds__(kThreads) void k_rchfsi_init_f64(const double* __restrict__ R,
                                                                int64_t ldr, int64_t n, int64_t b,
                                                                double scale, double* RY,
@@ -278,6 +307,13 @@ hipError_t rchfsi_init_f32(const double* R, int64_t ldr, int64_t n, int64_t b, d
                            float* RY, float* RX, float* Ycopy, int64_t ld32, hipStream_t st) {
   k_rchfsi_init_f32<<<grid_for(n * b), kThreads, 0, st>>>(R, ldr, n, b, scale, RY, RX, Ycopy,
                                                           ld32);
+  return hipGetLastError();
+}
+
+hipError_t rchfsi_coef(const double* ritz, int64_t b, double e, double c, double sigma1, int p,
+                       double* coef64, float* coef32, double* lamY, hipStream_t st) {
+  if (b <= 0) return hipSuccess;
+  k_rchfsi_coef<<<grid_for(b), kThreads, 0, st>>>(ritz, b, e, c, sigma1, p, coef64, coef32, lamY);
   return hipGetLastError();
 }
 

@@ -126,6 +126,7 @@ struct chfsi_ctx {
   float* coef32 = nullptr;        // per-step column coefficients, (p-1) x b
   double* coef64 = nullptr;
   double* lamY = nullptr;         // final Lambda_Y (device, b)
+  double* ritz_d = nullptr;       // Ritz values staged for the residual filter (device, b)
   std::vector<float> h_coef32;
   std::vector<double> h_coef64;
   int coef_cap = 0;               // steps the coefficient tables hold
@@ -470,7 +471,7 @@ SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfs
     s.slab = size_t(A->nx) * A->ny * s.slab_planes * b * sizeof(double);
     rr = s.blk + 2 * s.slab;
   }
-  s.total = s.a32 + filt + 2 * s.coef + rr + 10 * s.bb + 4 * b * sizeof(double) + 64 + s.ws +
+  s.total = s.a32 + filt + 2 * s.coef + rr + 10 * s.bb + 5 * b * sizeof(double) + 64 + s.ws +
             s.ws_eig + s.tri;
   if (p->binv_exact) s.total += size_t(n) * n * sizeof(double);   // H^T (formation: 3 more, freed)
   return s;
@@ -523,6 +524,11 @@ struct FilterScalars {
   double e, c, sigma1;
 };
 
+// Scalar coefficients of one recurrence step: R_X <- a H R_Y + bb R_Y + cc R_X (+ forcing)
+struct StepCoef {
+  double a, bb, cc;
+};
+
 FilterScalars filter_scalars(double lmin, double lmax, double lT) {
   FilterScalars f;
   f.e = (lmax - lT) / 2.0;
@@ -567,42 +573,41 @@ chfsi_status ensure_coef(chfsi_ctx* c, int p) {
 }
 
 // Algorithm 3 with the context's filter precision.
+// `ritz` is host memory, or device memory when `ritz_on_device`.
 chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const double* ritz,
                            const double* resid, int64_t ldr, double* Yp, int64_t ldy, double lmin,
-                           double lmax, double lT, int p, double* flops) {
+                           double lmax, double lT, int p, double* flops,
+                           bool ritz_on_device = false) {
   const int64_t n = c->n, b = c->b;
   chfsi_status st = ensure_coef(c, p);
   if (st != CHFSI_OK) return st;
   const FilterScalars f = filter_scalars(lmin, lmax, lT);
   const double gamma = 2.0 / f.sigma1;
-  // Lambda recurrence (eq. ChFSIrecurrenceEigval) on the host in FP64; the
-  // per-step forcing coefficients Lambda_Y (before the update) go to the device.
-  std::vector<double> LX(b, 1.0), LY(b), LN(b);
-  for (int64_t j = 0; j < b; ++j) LY[j] = (f.sigma1 / f.e) * (ritz[j] - f.c);
-  struct Step {
-    double a, bb, cc;
-  };
-  std::vector<Step> steps;
+  // the Lambda recurrence (eq. ChFSIrecurrenceEigval) runs on the device in FP64
+  // and writes each step's forcing coefficients Lambda_Y (before the update) and
+  // the final Lambda_Y for the reconstruction
+  const double* ritz_d = ritz;
+  if (!ritz_on_device) {
+    // the staging buffer may still feed an earlier asynchronous copy
+    CK(hipEventSynchronize(c->ev_stage));
+    std::memcpy(c->h_stage, ritz, b * sizeof(double));
+    CK(hipMemcpyAsync(c->ritz_d, c->h_stage, b * sizeof(double), hipMemcpyHostToDevice,
+                      c->stream));
+    CK(hipEventRecord(c->ev_stage, c->stream));
+    ritz_d = c->ritz_d;
+  }
+  const bool f64tab = c->prm.filter_prec == CHFSI_PREC_FP64;
+  CK(rchfsi_coef(ritz_d, b, f.e, f.c, f.sigma1, p, f64tab ? c->coef64 : nullptr,
+                 f64tab ? nullptr : c->coef32, c->lamY, c->stream));
+  // the block recurrence's scalar coefficients, step by step
   double sigma = f.sigma1;
-  for (int k = 2; k <= p; ++k) {
+  auto next_step = [&]() {
     const double sigma2 = 1.0 / (gamma - sigma);
     const double a = 2.0 * sigma2 / f.e;
-    steps.push_back({a, -a * f.c, -sigma * sigma2});
-    for (int64_t j = 0; j < b; ++j) {
-      c->h_coef64[(k - 2) * b + j] = LY[j];
-      c->h_coef32[(k - 2) * b + j] = float(LY[j]);
-      LN[j] = a * LY[j] * ritz[j] - a * f.c * LY[j] - sigma * sigma2 * LX[j];
-    }
-    std::swap(LX, LY);
-    std::swap(LY, LN);
+    const StepCoef sc{a, -a * f.c, -sigma * sigma2};
     sigma = sigma2;
-  }
-  // final Lambda_Y for the reconstruction; the staging buffer may still feed
-  // an earlier asynchronous copy
-  CK(hipEventSynchronize(c->ev_stage));
-  double* h_lam = reinterpret_cast<double*>(c->h_stage);
-  std::memcpy(h_lam, LY.data(), b * sizeof(double));
-  CK(hipMemcpyAsync(c->lamY, h_lam, b * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    return sc;
+  };
   const int nsteps = p - 1;
   const double scale1 = f.sigma1 / f.e;
   double fl = 0.0;
@@ -610,19 +615,12 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
   if (c->prm.filter_prec == CHFSI_PREC_FP32 || (c->prm.filter_prec == CHFSI_PREC_BF16 && dense)) {
     // FP32 filter blocks; the operator product is FP32 MFMA, or BF16 MFMA on
     // the bfloat16 copy of A (dense BF16)
-    if (nsteps > 0) {
-      float* hs = reinterpret_cast<float*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
-      std::memcpy(hs, c->h_coef32.data(), size_t(nsteps) * b * sizeof(float));
-      CK(hipMemcpyAsync(c->coef32, hs, size_t(nsteps) * b * sizeof(float), hipMemcpyHostToDevice,
-                        c->stream));
-    }
     float* RX = c->f32_a;
     float* RY = c->f32_b;
     float* Yc = c->f32_c;
-    CK(hipEventRecord(c->ev_stage, c->stream));
     CK(rchfsi_init_f32(resid, ldr, n, b, scale1, RY, RX, Yc, n, c->stream));
     for (int s = 0; s < nsteps; ++s) {
-      const Step& sp = steps[s];
+      const StepCoef sp = next_step();
       if (dense) {
         GemmDesc<float> g;
         g.M = n;
@@ -671,18 +669,11 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
     }
     CK(rchfsi_reconstruct_f32(RY, n, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
   } else if (c->prm.filter_prec == CHFSI_PREC_FP64) {
-    if (nsteps > 0) {
-      double* hs = reinterpret_cast<double*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
-      std::memcpy(hs, c->h_coef64.data(), size_t(nsteps) * b * sizeof(double));
-      CK(hipMemcpyAsync(c->coef64, hs, size_t(nsteps) * b * sizeof(double),
-                        hipMemcpyHostToDevice, c->stream));
-    }
     double* RX = c->f64_a;
     double* RY = c->f64_b;
-    CK(hipEventRecord(c->ev_stage, c->stream));
     CK(rchfsi_init_f64(resid, ldr, n, b, scale1, RY, RX, n, c->stream));
     for (int s = 0; s < nsteps; ++s) {
-      const Step& sp = steps[s];
+      const StepCoef sp = next_step();
       if (dense) {
         GemmDesc<double> g;
         g.M = n;
@@ -728,19 +719,12 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
     CK(rchfsi_reconstruct_f64(RY, n, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
   } else {
     // BF16-stored blocks, FP32 arithmetic (stencil operators)
-    if (nsteps > 0) {
-      float* hs = reinterpret_cast<float*>(static_cast<char*>(c->h_stage) + b * sizeof(double));
-      std::memcpy(hs, c->h_coef32.data(), size_t(nsteps) * b * sizeof(float));
-      CK(hipMemcpyAsync(c->coef32, hs, size_t(nsteps) * b * sizeof(float), hipMemcpyHostToDevice,
-                        c->stream));
-    }
     void* RX = c->bf_a;
     void* RY = c->bf_b;
     void* Yc = c->bf_c;
-    CK(hipEventRecord(c->ev_stage, c->stream));
     CK(rchfsi_init_bf16(resid, ldr, n, b, scale1, RY, RX, Yc, c->stream));
     for (int s = 0; s < nsteps; ++s) {
-      const Step& sp = steps[s];
+      const StepCoef sp = next_step();
       StencilStep ss{sp.a, sp.bb, sp.cc, sp.a};
       {
         hipEvent_t e0, e1;
@@ -2404,9 +2388,8 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   c->coef32 = ctx_alloc<float>(c, size_t(params->degree) * b * sizeof(float), &st);
   c->coef64 = ctx_alloc<double>(c, size_t(params->degree) * b * sizeof(double), &st);
   c->lamY = ctx_alloc<double>(c, b * sizeof(double), &st);
+  c->ritz_d = ctx_alloc<double>(c, b * sizeof(double), &st);
   c->tri = ctx_alloc<double>(c, sp.tri, &st);
-  c->h_coef32.assign(size_t(params->degree) * b, 0.0f);
-  c->h_coef64.assign(size_t(params->degree) * b, 0.0);
   if (params->memory_mode == 1) {
     c->slab_planes = sp.slab_planes;
     c->R = ctx_alloc<double>(c, sp.blk, &st);

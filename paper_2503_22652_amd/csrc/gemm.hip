@@ -632,24 +632,30 @@ static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspa
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  if (d.ev_end) {
-    err = hipEventRecord(d.ev_end, st);
-    if (err != hipSuccess) return err;
-  }
   if (c.splits > 1) {
     const int64_t total = d.M * d.N * d.batch;
+    bool done = false;
     if constexpr (sizeof(T) == 4) {
       if (reduce4_ok(a, d.batch)) {
         const int64_t blocks = std::min<int64_t>((total / 4 + 255) / 256, 16384);
         splitk_reduce4_kernel<<<dim3(blocks), dim3(256), 0, st>>>(a);
-        return hipGetLastError();
+        done = true;
       }
     }
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
-    splitk_reduce_kernel<T><<<dim3(blocks), dim3(256), 0, st>>>(a);
+    if (!done) {
+      const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+      splitk_reduce_kernel<T><<<dim3(blocks), dim3(256), 0, st>>>(a);
+    }
     err = hipGetLastError();
+    if (err != hipSuccess) return err;
   }
-  return err;
+  // the profiling interval ends after the split-K reduction, which carries the
+  // fused epilogue: it times the whole recurrence step
+  if (d.ev_end) {
+    err = hipEventRecord(d.ev_end, st);
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 // Launchers for the FP32 filter shapes (both operands k-contiguous only).
@@ -873,6 +879,27 @@ __global__ __launch_bounds__(256) void k_scale_bf16(const float* __restrict__ B,
   }
 }
 
+// Split-K factor (after rounding the k-range to whole 64-deep slices) and
+// k-range length of the BF16 product: enough work items for ~4 per CU,
+// at least 8 slices per split, at most 16 splits.
+template <int BM, int BN>
+static int bf16_splits(int64_t M, int64_t N, int64_t K, int force_splits, int64_t* kchunk_out) {
+  constexpr int BK = 64;
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int splits = force_splits;
+  if (splits <= 0) {
+    splits = 1;
+    const int64_t max_s = std::max<int64_t>(1, K / (8 * BK));
+    while (tiles * splits < int64_t(kNumCU) * 4 && splits * 2 <= max_s && splits < 16) splits *= 2;
+  }
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  if (kchunk == 0) kchunk = BK;
+  splits = int((K + kchunk - 1) / kchunk);
+  *kchunk_out = kchunk;
+  return std::max(splits, 1);
+}
+
 template <int BM, int BN>
 static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
                                    uint16_t* B16, hipStream_t st, const Workspace& ws,
@@ -908,18 +935,10 @@ static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16
   c.tiles_m = int((d.M + BM - 1) / BM);
   c.tiles_n = int((d.N + BN - 1) / BN);
   const int64_t tiles = int64_t(c.tiles_m) * c.tiles_n;
-  int splits = force_splits;
-  if (splits <= 0) {
-    splits = 1;
-    const int64_t max_s = std::max<int64_t>(1, d.K / (8 * BK));
-    while (tiles * splits < int64_t(kNumCU) * 4 && splits * 2 <= max_s && splits < 16) splits *= 2;
-  }
-  int64_t kchunk = (d.K + splits - 1) / splits;
-  kchunk = (kchunk + BK - 1) / BK * BK;
-  if (kchunk == 0) kchunk = BK;
-  splits = int((d.K + kchunk - 1) / kchunk);
+  int64_t kchunk = 0;
+  const int splits = bf16_splits<BM, BN>(d.M, d.N, d.K, force_splits, &kchunk);
   c.kchunk = kchunk;
-  c.splits = std::max(splits, 1);
+  c.splits = splits;
   a.A = nullptr;
   a.B = nullptr;
   a.kscale = nullptr;
@@ -947,7 +966,6 @@ static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16
   else
     gemm_bf16_kernel<BM, BN, BK, true><<<dim3(unsigned(grid)), dim3(256), 0, st>>>(a, a16, b16);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  if (d.ev_end && (err = hipEventRecord(d.ev_end, st)) != hipSuccess) return err;
   if (c.splits > 1) {
     const int64_t total = d.M * d.N;
     if (reduce4_ok(a, 1)) {
@@ -957,22 +975,28 @@ static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16
       const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
       splitk_reduce_kernel<float><<<dim3(blocks), dim3(256), 0, st>>>(a);
     }
-    err = hipGetLastError();
+    if ((err = hipGetLastError()) != hipSuccess) return err;
   }
-  return err;
+  // the profiling interval ends after the reduction, which carries the epilogue
+  if (d.ev_end && (err = hipEventRecord(d.ev_end, st)) != hipSuccess) return err;
+  return hipSuccess;
 }
 
 // tile shape of the BF16 product (knob CHFSI_BF16_TILE: 0 = 64x64, 1 = 64x160
 // (default), 2 = 128x64).  Measured at 8192 x 320 x 8192 on MI355X: 0.093,
 // 0.084 and 0.086 ms per product with split-K 4.
-hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
-                            uint16_t* B16, hipStream_t st, const Workspace& ws,
-                            int force_splits) {
+static int bf16_tile() {
   static const int tile = [] {
     const char* e = std::getenv("CHFSI_BF16_TILE");
     return e ? std::atoi(e) : 1;
   }();
-  switch (tile) {
+  return tile;
+}
+
+hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
+                            uint16_t* B16, hipStream_t st, const Workspace& ws,
+                            int force_splits) {
+  switch (bf16_tile()) {
     case 1: return gemm_bf16_launch<64, 160>(d, A16, lda16, B16, st, ws, force_splits);
     case 2: return gemm_bf16_launch<128, 64>(d, A16, lda16, B16, st, ws, force_splits);
     default: return gemm_bf16_launch<64, 64>(d, A16, lda16, B16, st, ws, force_splits);
@@ -981,6 +1005,17 @@ hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64
 
 size_t gemm_bf16_workspace_bytes(int64_t M, int64_t N) {
   return size_t(16) * size_t(M) * size_t(N) * sizeof(float);
+}
+
+size_t gemm_bf16_plan_bytes(int64_t M, int64_t N, int64_t K, int force_splits) {
+  int64_t kc = 0;
+  int s;
+  switch (bf16_tile()) {
+    case 1: s = bf16_splits<64, 160>(M, N, K, force_splits, &kc); break;
+    case 2: s = bf16_splits<128, 64>(M, N, K, force_splits, &kc); break;
+    default: s = bf16_splits<64, 64>(M, N, K, force_splits, &kc); break;
+  }
+  return s > 1 ? size_t(s) * size_t(M) * size_t(N) * sizeof(float) : 0;
 }
 
 template hipError_t gemm<float>(const GemmDesc<float>&, hipStream_t, const Workspace&, int, int);

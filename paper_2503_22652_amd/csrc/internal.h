@@ -59,8 +59,9 @@ struct GemmDesc {
   // (tiles strictly above it are left unwritten; mirror the lower part after)
   bool lower_only = false;
   Epilogue<T> epi;
-  // optional: events recorded on the stream right before / after the main
-  // (tile) kernel, i.e. excluding any split-K reduction
+  // optional: events recorded on the stream right before the first kernel and
+  // right after the last one of the product (the tile kernel and, with split-K,
+  // the reduction that carries the epilogue)
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
 
@@ -89,6 +90,8 @@ hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64
                             uint16_t* B16, hipStream_t st, const Workspace& ws,
                             int force_splits = 0);
 size_t gemm_bf16_workspace_bytes(int64_t M, int64_t N);
+// split-K partial bytes the BF16 product will use for this shape (0: no split)
+size_t gemm_bf16_plan_bytes(int64_t M, int64_t N, int64_t K, int force_splits);
 
 // Which tile configuration/split the heuristic picks (for reports and tests).
 template <typename T>
@@ -180,6 +183,12 @@ hipError_t rchfsi_init_f32(const double* R, int64_t ldr, int64_t n, int64_t b, d
                            float* RY, float* RX, float* Ycopy, int64_t ld32, hipStream_t st);
 hipError_t rchfsi_init_f64(const double* R, int64_t ldr, int64_t n, int64_t b, double scale,
                            double* RY, double* RX, int64_t ld, hipStream_t st);
+// Per-column Lambda recurrence of the residual filter from the Ritz values
+// (device, b): coefficient rows k - 2 = Lambda_Y before step k (FP64 table
+// and/or FP32 table, each b per row, either may be null) and the final
+// Lambda_Y in lamY.  e, c, sigma1 as in the filter's first line.
+hipError_t rchfsi_coef(const double* ritz, int64_t b, double e, double c, double sigma1, int p,
+                       double* coef64, float* coef32, double* lamY, hipStream_t st);
 // Yp[i,j] = dinv[i] * RY[i,j] + X[i,j] * lamY[j]   (dinv may be null => 1)
 hipError_t rchfsi_reconstruct_f32(const float* RY, int64_t ldry, const double* dinv,
                                   const double* X, int64_t ldx, const double* lamY, double* Yp,

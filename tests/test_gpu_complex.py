@@ -18,13 +18,13 @@ import scipy.linalg as sla
 
 import workloads as wl
 from oracle import filters, rr
+from parity import assert_columns, prec_name, residual_part
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_2503_22652_amd as P  # noqa: E402
 
-TOL = {P.PREC_FP32: 1e-4, P.PREC_BF16: 3e-2}
 
 
 @pytest.fixture(scope="module")
@@ -62,13 +62,9 @@ def test_complex_residual_filter_matches_oracle(herm, prec, degree):
     ref, RYp, _ = filters.residual_filter(filters.dense_op(p.A), filters.diag_op(p.dinv), o["X"],
                                           lam, o["R"], degree, *bounds, return_parts=True)
     assert got.dtype == np.complex128 and np.all(np.isfinite(got))
-    err = np.linalg.norm(got - ref)
-    if prec == P.PREC_FP64:
-        assert err <= 1e-11 * np.linalg.norm(ref)
-    else:
-        part = np.linalg.norm(p.dinv[:, None] * RYp)
-        print("err / ||D^-1 R_Y||", err / part)
-        assert err <= TOL[prec] * part
+    # the complex product is one real product with K = 2n terms per element
+    scale = np.linalg.norm(ref, axis=0) if prec == P.PREC_FP64 else residual_part(RYp, p.dinv)
+    assert_columns(got, ref, scale, prec_name(prec), degree, 2 * p.n, "complex filter")
 
 
 @pytest.mark.parametrize("prec", [P.PREC_FP32, P.PREC_BF16])

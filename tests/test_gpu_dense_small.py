@@ -4,9 +4,10 @@ and complex Hermitian, against the oracle.
 N below one 64-row tile (N = 37), one row past two tiles (N = 129), a block
 of one vector, and a block that spans the whole space (b = N = 64).  Every
 product then runs on partial tiles, and the eigensolver of the projected
-pencil works on a padded problem.  Bars as for the other dense tests: FP64 to
-1e-11, FP32 / BF16 residual filters within the residual part they carry
-(Theorem 3.4), Ritz values to 1e-11 of the spectrum's scale.
+pencil works on a padded problem.  Bars as for the other dense tests: filters
+column by column within the bounds of tests/parity.py (FP64 relative to the
+column, FP32 / BF16 residual filters relative to the residual part they carry,
+Theorem 3.4), Ritz values to 1e-11 of the spectrum's scale.
 """
 import numpy as np
 import pytest
@@ -14,6 +15,7 @@ import scipy.linalg as sla
 
 import workloads as wl
 from oracle import filters, rr
+from parity import assert_columns, prec_name, residual_part
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -21,7 +23,6 @@ pytestmark = pytest.mark.gpu
 import paper_2503_22652_amd as P  # noqa: E402
 
 SIZES = [(37, 1), (37, 5), (129, 3), (64, 64)]          # (N, b)
-TOL = {P.PREC_FP64: 1e-11, P.PREC_FP32: 1e-4, P.PREC_BF16: 3e-2}
 
 
 def _problem(n, b, cplx):
@@ -64,15 +65,14 @@ def test_small_dense_residual_filter_matches_oracle(prec, cplx, n, b):
     ref, RYp, _ = filters.residual_filter(filters.dense_op(p.A), filters.diag_op(p.dinv), o["X"],
                                           lam, o["R"], 8, *bounds, return_parts=True)
     assert np.all(np.isfinite(got))
-    err = np.linalg.norm(got - ref)
-    part = np.linalg.norm(p.dinv[:, None] * RYp)
-    print("  rel", err / np.linalg.norm(ref), "err / ||D^-1 R_Y||", err / part)
+    terms = 2 * n if cplx else n
     if prec == P.PREC_FP64:
-        assert err <= TOL[prec] * np.linalg.norm(ref)
+        assert_columns(got, ref, np.linalg.norm(ref, axis=0), "fp64", 8, terms, "small dense")
     else:
         # (b = N: the start block spans the space, its residual part is at
-        # the FP64 rounding level, so the FP64 bar on the whole is added)
-        assert err <= TOL[prec] * part + 1e-11 * np.linalg.norm(ref)
+        # the FP64 rounding level, so the FP64 bound on the column is added)
+        assert_columns(got, ref, residual_part(RYp, p.dinv), prec_name(prec), 8, terms,
+                       "small dense", fp64_floor=True)
 
 
 @pytest.mark.parametrize("n,b", SIZES)

@@ -7,10 +7,11 @@ rows that leave threads idle (nx = 40: 10 or 20 threads per row), block
 widths that leave a partial column group, the filter-step kernels compiled
 for rows of 128 and 160 points (with ragged last y tiles at every slab
 height: 8/8/4 and 6/6/2 rows, or 4 and 3 rows for FP64), and the scalar
-fallback (nx = 10, not a multiple of 4).  FP64 filters match the oracle to 1e-11;
-FP32 / BF16-stored residual filters have an error bounded by the size of the
-residual part they carry (Theorem 3.4); a small solve with BF16 storage
-reaches the eigenvalues of the dense pencil.
+fallback (nx = 10, not a multiple of 4).  Filters are compared column by
+column with the bounds of tests/parity.py: FP64 relative to the column,
+FP32 / BF16-stored residual filters relative to the residual part each column
+carries (Theorem 3.4); a small solve with BF16 storage reaches the eigenvalues
+of the dense pencil.
 """
 import numpy as np
 import pytest
@@ -18,6 +19,7 @@ import scipy.linalg as sla
 
 import workloads as wl
 from oracle import filters, rr, stencil
+from parity import GRID_TERMS, assert_columns, prec_name, residual_part
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -64,13 +66,13 @@ def test_plain_filter_fp64_matches_oracle(shape):
         P.chfsi_filter(ctx, P.to_colmajor(X), None, None, Y, *bounds, degree=deg)
         torch.cuda.synchronize()
         ref = filters.chebyshev_filter(apply_A, X, deg, *bounds)   # D^{-1} = I
-        assert _rel(Y.cpu().numpy(), ref) <= 1e-11
+        assert_columns(Y.cpu().numpy(), ref, np.linalg.norm(ref, axis=0), "fp64", deg,
+                       GRID_TERMS, f"grid {shape} chfsi")
 
 
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("prec,tol", [(P.PREC_FP64, 1e-11), (P.PREC_FP32, 1e-4),
-                                      (P.PREC_BF16, 1e-1)])
-def test_residual_filter_matches_oracle(prec, tol, shape):
+@pytest.mark.parametrize("prec", [P.PREC_FP64, P.PREC_FP32, P.PREC_BF16])
+def test_residual_filter_matches_oracle(prec, shape):
     shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=shape)
     n = int(np.prod(shape))
     b = 9
@@ -84,13 +86,9 @@ def test_residual_filter_matches_oracle(prec, tol, shape):
     torch.cuda.synchronize()
     ref, RYp, _ = filters.residual_filter(apply_A, filters.identity_op(), o["X"], o["lam"], o["R"],
                                           10, *bounds, return_parts=True)
-    err = np.linalg.norm(Y.cpu().numpy() - ref)
-    part = np.linalg.norm(RYp)
-    print(prec, "err / ||residual part||", err / part, "rel", _rel(Y.cpu().numpy(), ref))
-    if prec == P.PREC_FP64:
-        assert _rel(Y.cpu().numpy(), ref) <= tol
-    else:
-        assert err <= tol * part
+    got = Y.cpu().numpy()
+    scale = np.linalg.norm(ref, axis=0) if prec == P.PREC_FP64 else residual_part(RYp)
+    assert_columns(got, ref, scale, prec_name(prec), 10, GRID_TERMS, f"grid {shape} rchfsi")
 
 
 @pytest.mark.parametrize("shape", [(8, 9, 10), (5, 20, 64), (4, 30, 40)])
