@@ -78,6 +78,13 @@ def parse():
                          "R-ChFSI, FP64 R-ChFSI, FP64 ChFSI with D^-1 = I)")
     ap.add_argument("--ttr-iters", type=int, default=120)
     ap.add_argument("--ttr-chfsi-iters", type=int, default=25)
+    ap.add_argument("--ttr-runs", type=str, default="",
+                    help="grid workload: comma list of time-to-residual runs to do (names as "
+                         "in the output: <prec>_rchfsi, fp64_rchfsi, fp64_chfsi_dinv_identity); "
+                         "default all")
+    ap.add_argument("--fp64-panel", type=int, default=600,
+                    help="grid workload: column panel for the FP64 R-ChFSI filter timing when "
+                         "the full FP64 solve does not fit in device memory")
     return ap.parse_args()
 
 
@@ -474,18 +481,34 @@ def bench_grid(args):
         runs = [(args.prec + "_rchfsi", P.METHOD_RCHFSI, prec, args.ttr_iters),
                 ("fp64_rchfsi", P.METHOD_RCHFSI, P.PREC_FP64, args.ttr_iters),
                 ("fp64_chfsi_dinv_identity", P.METHOD_CHFSI, P.PREC_FP64, args.ttr_chfsi_iters)]
+        wanted_runs = set(r for r in args.ttr_runs.split(",") if r)
         for name, method, pr, iters in runs:
             if name == "fp64_rchfsi" and prec == P.PREC_FP64:
                 continue
             if kvec is not None and method == P.METHOD_CHFSI:
                 continue                        # complex contexts run the residual filter only
+            if wanted_runs and name not in wanted_runs:
+                continue
             pm = P.make_params(nw, b, p, max_iter=iters, tol=1e-8, method=method, filter_prec=pr,
                                lambda_max=lmax, seed=2002, init_random=1)
             md = 0
-            if (kvec is None and P.chfsi_workspace_bytes(opA, opB, pm) + n * b * 8 >
-                    0.9 * torch.cuda.mem_get_info()[0]):
+            torch.cuda.empty_cache()
+            free_now = torch.cuda.mem_get_info()[0]
+            # the slab-wise Rayleigh-Ritz (memory_mode 1) serves the FP32/BF16
+            # residual filters on real grids
+            if (kvec is None and pr != P.PREC_FP64 and
+                    P.chfsi_workspace_bytes(opA, opB, pm) + n * b * 8 > 0.9 * free_now):
                 md = 1
             pm.memory_mode = md
+            need = P.chfsi_workspace_bytes(opA, opB, pm) + n * b * 8 * (2 if kvec else 1)
+            if need > 0.9 * free_now and pr == P.PREC_FP64 and kvec is None:
+                # the whole FP64 block recurrence does not fit: time its filter by
+                # column panels (the filter is column-independent, so the panels'
+                # times add up to one full filter pass exactly)
+                ttr[name] = fp64_filter_by_panels(P, opA, opB, n, b, nw, p, lmax, stream,
+                                                  args.fp64_panel, Vd, need)
+                log(f"  {name}: {ttr[name]}")
+                continue
             log(f"time-to-residual: {name} (memory_mode {md}) ...")
             c2 = P.chfsi_create(opA, opB, None, pm, stream=stream, keep=(Vd,))
             X2 = P.colmajor_empty(n, b) if kvec is None else P.colmajor_empty_complex(n, b)
@@ -497,7 +520,9 @@ def bench_grid(args):
             ttr[name] = {"status": "OK" if st2 == P.OK else "ERR_NOCONV", "seconds": round(sec, 2),
                          "iterations": rep2["iterations"], "max_residual": rep2["max_residual"],
                          "filter_ms": round(rep2["time_filter_ms"], 1),
-                         "rr_ms": round(rep2["time_rr_ms"], 1), "memory_mode": md}
+                         "rr_ms": round(rep2["time_rr_ms"], 1), "memory_mode": md,
+                         "svqb_events": rep2["svqb_events"], "svqb_dropped": rep2["svqb_dropped"],
+                         "residual_history": [float("%.3g" % v) for v in rep2["history"]]}
             log(f"  {ttr[name]}")
             c2.close()
             del X2
@@ -506,6 +531,12 @@ def bench_grid(args):
         hi = ttr.get("fp64_rchfsi")
         if lo and hi and lo["status"] == "OK" and hi["status"] == "OK":
             ttr["speedup_vs_fp64_rchfsi"] = round(hi["seconds"] / lo["seconds"], 3)
+        elif lo and hi and lo["status"] == "OK" and "filter_ms_per_iteration_by_panels" in hi:
+            # estimate: the reduced-precision run's iteration count and FP64
+            # Rayleigh-Ritz time, with the FP64 filter timed by column panels
+            est = (lo["iterations"] * hi["filter_ms_per_iteration_by_panels"] + lo["rr_ms"]) / 1e3
+            hi["seconds_estimate"] = round(est, 2)
+            ttr["speedup_vs_fp64_rchfsi_estimate"] = round(est / lo["seconds"], 3)
         out["time_to_residual"] = ttr
     if args.calibrate_copy:
         nbytes = args.calibrate_copy * (1 << 20)
@@ -517,6 +548,42 @@ def bench_grid(args):
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = nbytes
     print(json.dumps(out), flush=True)
+
+
+def fp64_filter_by_panels(P, opA, opB, n, b, nw, p, lmax, stream, panel, Vd, need):
+    """FP64 residual-filter time of one outer iteration on a block too large for
+    device memory, from column panels of `panel` vectors (random Ritz-like
+    data; the filter's time does not depend on the values)."""
+    import numpy as np
+    import torch
+    panel = min(panel, b)
+    pm = P.make_params(min(nw, panel), panel, p, max_iter=1, tol=0.0,
+                       method=P.METHOD_RCHFSI, filter_prec=P.PREC_FP64, lambda_max=lmax,
+                       seed=7, init_random=0, profile=1)
+    ctx = P.chfsi_create(opA, opB, None, pm, stream=stream, keep=(Vd,))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    X = torch.randn((panel, n), dtype=torch.float64, device="cuda", generator=g).t()
+    R = torch.randn((panel, n), dtype=torch.float64, device="cuda", generator=g).t()
+    Y = P.colmajor_empty(n, panel)
+    ritz = [float(v) for v in np.linspace(-4.0, 1.0, panel)]
+    P.chfsi_filter(ctx, X, ritz, R, Y, -4.5, lmax, 1.0, degree=p)   # warm-up
+    torch.cuda.synchronize()
+    P.chfsi_filter_kernel_time(ctx)
+    t0 = time.perf_counter()
+    P.chfsi_filter(ctx, X, ritz, R, Y, -4.5, lmax, 1.0, degree=p)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    kms, launches = P.chfsi_filter_kernel_time(ctx)
+    ctx.close()
+    del X, R, Y
+    torch.cuda.synchronize()
+    panels = b / panel
+    return {"status": "does not fit in device memory",
+            "bytes_needed": int(need),
+            "filter_ms_per_iteration_by_panels": round(sec * 1e3 * panels, 1),
+            "step_ms_by_panels": round(kms / max(launches, 1), 3),
+            "panel_columns": panel, "panels": round(panels, 3)}
 
 
 def bench_serving(args):

@@ -132,10 +132,13 @@ typedef struct {
   double tol;           /* tau: stop when max_{j<n} ||A x_j - eps_j B x_j||_2 < tau */
   int32_t method;       /* chfsi_method */
   int32_t filter_prec;  /* chfsi_prec */
-  /* Filter bounds.  lambda_max must be finite (an upper bound of the spectrum
-   * of B^{-1}A).  lambda_min / lambda_T may be NaN: then each iteration uses
-   * lambda_T = largest Ritz value of the block and
-   * lambda_min = eps_1 - 0.05 (eps_b - eps_1). */
+  /* Filter bounds (Section 2.1: estimates).  lambda_max: an upper bound of
+   * the spectrum of B^{-1}A, or NaN: chfsi_solve then estimates it once per
+   * context with chfsi_estimate_bounds (lanczos_steps steps from an N(0,1)
+   * start of seed `seed`) and uses its `upper`.  lambda_min / lambda_T may be
+   * NaN: then each iteration uses lambda_T = largest Ritz value of the block
+   * and lambda_min = eps_1 - 0.05 (eps_b - eps_1).  Infinite values are
+   * rejected. */
   double lambda_min, lambda_max, lambda_T;
   uint64_t seed;        /* seed of the random start block when init_random != 0 */
   int32_t init_random;  /* chfsi_solve: 1 = fill X with N(0,1) (Philox-4x32-10), 0 = X holds the start */
@@ -155,6 +158,8 @@ typedef struct {
    * and owns it (n^2 doubles); d_inv is not used by the filter then.
    * 0: H = D^{-1} A. */
   int32_t binv_exact;
+  /* Lanczos steps of the lambda_max estimate (0: 12). */
+  int32_t lanczos_steps;
 } chfsi_params;
 
 /* Per-solve report (host). */
@@ -172,6 +177,10 @@ typedef struct {
   double kernel_ms;            /* profile: their summed durations (HIP events) */
   int32_t flags;               /* bit 0: a Gram matrix took the SVQB fallback */
   double history[CHFSI_MAX_HISTORY]; /* max residual after each pass (entry 0: initial RR) */
+  int32_t svqb_events;         /* Rayleigh-Ritz passes that took the SVQB fallback */
+  int32_t svqb_dropped;        /* directions dropped (and refilled) by those passes, summed */
+  double lambda_max_used;      /* the filter's upper bound (given, or the Lanczos estimate) */
+  double time_bounds_ms;       /* time of the Lanczos estimate in this solve (0 if none) */
 } chfsi_report;
 
 typedef struct chfsi_ctx chfsi_ctx;
@@ -227,6 +236,28 @@ chfsi_status chfsi_filter(chfsi_ctx* ctx, const double* X, int64_t ldx, const do
 chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* ctx, const double* Y, int64_t ldy, double* X,
                                  int64_t ldx, double* R, int64_t ldr, double* ritz,
                                  double* resnorm);
+
+/*
+ * Estimates of the spectrum bounds of B^{-1} A (Section 2.1 treats the
+ * filter's bounds as estimates).  A k-step Lanczos process on B^{-1} A in the
+ * B-inner product from v0 (each step: one product with A and a
+ * preconditioned conjugate-gradient solve with B to relative residual 1e-12,
+ * preconditioner D^{-1}; no solve when B = I), in FP64 on the device.  With
+ * theta_1 <= theta_k the extreme eigenvalues of the k x k tridiagonal matrix
+ * and beta_k the B-norm of the last Lanczos residual (the "Ritz value +
+ * |beta_k|" safeguard of Zhou, Saad, Tiago and Chelikowsky, J. Comput. Phys.
+ * 219 (2006)): *upper = theta_k + |beta_k|, *lower = theta_1 - |beta_k|.
+ * v0: device, length n (interleaved complex for a complex context), or NULL
+ * for N(0,1) values (Philox-4x32-10, seed params.seed).  steps: k >= 1 (0 =
+ * params.lanczos_steps or 12); fewer steps are taken if the Krylov space is
+ * exhausted.  theta: optional host array of 2 (theta_1, theta_k).  The first
+ * call on a context allocates its Lanczos vectors (12 n doubles, complex: 24
+ * n) unless chfsi_create did (lambda_max = NaN).  Synchronises the stream.
+ * Errors: CHFSI_ERR_ARG, CHFSI_ERR_NOMEM, CHFSI_ERR_NOT_SPD (B not positive
+ * definite on the Krylov space), CHFSI_ERR_DEVICE.
+ */
+chfsi_status chfsi_estimate_bounds(chfsi_ctx* ctx, const double* v0, int32_t steps,
+                                   double* lower, double* upper, double* theta);
 
 /*
  * Full eigensolve (Algorithm 1 with the context's filter).  X (device, n x b,

@@ -23,6 +23,8 @@ following the paper (arXiv 2503.22652) step by step:
   (an independent pin for the library eigensolver used in ``rr``).
 * ``stencil``    -- periodic 27-point operator application for grid pencils.
 * ``angles``     -- maximum principal angle (Definition 2.1).
+* ``bounds``     -- k-step Lanczos estimates of the spectrum of B^{-1} A,
+  the filter's bounds (Section 2.1 treats them as estimates).
 * ``diagnostics`` -- filtering error, angle and both sides of the convergence
   condition of Section 3.1 with Theorem 3.1's bound, per outer iteration
   (the check of Section 4.1.3).
@@ -30,4 +32,4 @@ following the paper (arXiv 2503.22652) step by step:
 Parity status of each function is stated in its docstring; functions without
 an independent pin say "parity unpinned".
 """
-from . import chebyshev, filters, rr, solver, jacobi, stencil, angles, diagnostics  # noqa: F401
+from . import chebyshev, filters, rr, solver, jacobi, stencil, angles, diagnostics, bounds  # noqa: F401

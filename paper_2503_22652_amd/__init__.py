@@ -42,7 +42,8 @@ class chfsi_params(C.Structure):
                 ("filter_prec", C.c_int32), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("lambda_T", C.c_double), ("seed", C.c_uint64),
                 ("init_random", C.c_int32), ("profile", C.c_int32),
-                ("memory_mode", C.c_int32), ("binv_exact", C.c_int32)]
+                ("memory_mode", C.c_int32), ("binv_exact", C.c_int32),
+                ("lanczos_steps", C.c_int32)]
 
 
 class chfsi_report(C.Structure):
@@ -51,7 +52,9 @@ class chfsi_report(C.Structure):
                 ("time_filter_ms", C.c_double), ("time_rr_ms", C.c_double),
                 ("filter_flops", C.c_double), ("jacobi_sweeps", C.c_int32),
                 ("kernel_launches", C.c_int32), ("kernel_ms", C.c_double),
-                ("flags", C.c_int32), ("history", C.c_double * MAX_HISTORY)]
+                ("flags", C.c_int32), ("history", C.c_double * MAX_HISTORY),
+                ("svqb_events", C.c_int32), ("svqb_dropped", C.c_int32),
+                ("lambda_max_used", C.c_double), ("time_bounds_ms", C.c_double)]
 
 
 class chfsi_server_config(C.Structure):
@@ -88,8 +91,9 @@ _SIGNATURES = {
     "chfsi_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_double),
                               C.POINTER(C.c_double), C.POINTER(chfsi_report)]),
     "chfsi_destroy": (None, [C.c_void_p]),
-    "chfsi_filter_kernel_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
-                                           C.POINTER(C.c_int32)]),
+    "chfsi_estimate_bounds": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]),
     "chfsi_last_error": (C.c_char_p, []),
     "chfsi_version": (C.c_char_p, []),
     "chfsi_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(chfsi_server_config)]),
@@ -221,7 +225,8 @@ def make_params(n_wanted: int, block: int, degree: int, max_iter: int = 100, tol
                 method: int = METHOD_RCHFSI, filter_prec: int = PREC_FP64,
                 lambda_min: float = math.nan, lambda_max: float = math.nan,
                 lambda_T: float = math.nan, seed: int = 0, init_random: int = 0,
-                profile: int = 0, memory_mode: int = 0, binv_exact: int = 0) -> chfsi_params:
+                profile: int = 0, memory_mode: int = 0, binv_exact: int = 0,
+                lanczos_steps: int = 0) -> chfsi_params:
     p = chfsi_params()
     p.n_wanted, p.block, p.degree, p.max_iter, p.tol = n_wanted, block, degree, max_iter, tol
     p.method, p.filter_prec = method, filter_prec
@@ -229,6 +234,7 @@ def make_params(n_wanted: int, block: int, degree: int, max_iter: int = 100, tol
     p.seed, p.init_random, p.profile = seed, init_random, profile
     p.memory_mode = memory_mode
     p.binv_exact = binv_exact
+    p.lanczos_steps = lanczos_steps
     return p
 
 
@@ -287,6 +293,15 @@ def chfsi_filter(ctx: Context, X, ritz, resid, Yp, lmin: float, lmax: float, lT:
     _check(st, "chfsi_filter")
 
 
+def chfsi_estimate_bounds(ctx: Context, v0=None, steps: int = 0):
+    """Lanczos estimates (lower, upper, theta_min, theta_max) of the spectrum of B^{-1} A."""
+    lo, hi = C.c_double(), C.c_double()
+    th = (C.c_double * 2)()
+    _check(lib().chfsi_estimate_bounds(ctx.handle, _ptr(v0), steps, C.byref(lo), C.byref(hi), th),
+           "chfsi_estimate_bounds")
+    return lo.value, hi.value, th[0], th[1]
+
+
 def chfsi_rayleigh_ritz(ctx: Context, Y, X, R):
     b = Y.shape[1]
     ritz = (C.c_double * b)()
@@ -323,6 +338,8 @@ def report_dict(rep: chfsi_report) -> dict:
             "time_total_ms": rep.time_total_ms, "time_filter_ms": rep.time_filter_ms,
             "time_rr_ms": rep.time_rr_ms, "filter_flops": rep.filter_flops,
             "jacobi_sweeps": rep.jacobi_sweeps, "flags": rep.flags,
+            "svqb_events": rep.svqb_events, "svqb_dropped": rep.svqb_dropped,
+            "lambda_max_used": rep.lambda_max_used, "time_bounds_ms": rep.time_bounds_ms,
             "kernel_launches": rep.kernel_launches, "kernel_ms": rep.kernel_ms,
             "history": [rep.history[i] for i in range(min(it + 1, MAX_HISTORY))]}
 

@@ -39,6 +39,13 @@ void set_error(const char* fmt, ...) {
   g_last_error = buf;
 }
 
+}  // namespace
+
+// the calling thread's error message, for the other translation units
+void chfsi::set_error_message(const char* msg) { g_last_error = msg; }
+
+namespace {
+
 #define CK(expr)                                                                        \
   do {                                                                                  \
     hipError_t _e = (expr);                                                             \
@@ -151,6 +158,14 @@ struct chfsi_ctx {
   hipEvent_t ev_stage = nullptr;   // last copy out of h_stage (reuse waits on it)
   int last_sweeps = 0;
   int flags = 0;
+  int svqb_events = 0;            // Rayleigh-Ritz passes that took the SVQB fallback
+  int svqb_dropped = 0;           // directions those passes dropped and refilled
+  // Lanczos bound estimate: vectors (lanczos_ctx_bytes), pinned scalars, the
+  // estimate once made
+  double* lz_work = nullptr;
+  double* h_lz = nullptr;
+  bool have_lmax = false;
+  double lmax_est = 0.0;
   const std::atomic<int>* cancel = nullptr;
   uint64_t refill_seed = 0;
   // slab-wise Rayleigh-Ritz (memory_mode 1)
@@ -416,7 +431,24 @@ SizePlan plan_sizes_bloch(const chfsi_operator* A, const chfsi_operator* B, cons
   return s;
 }
 
+// device bytes of the Lanczos bound estimate: its vectors plus the start
+// vector, a planar copy of D^{-1} and the complex product's right operand
+size_t lanczos_ctx_bytes(int64_t n, bool cplx) {
+  const int64_t L = cplx ? 2 * n : n;
+  return lanczos_workspace_bytes(L) + size_t(6) * L * sizeof(double) + 256;
+}
+
+SizePlan plan_sizes_kind(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p);
+
 SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
+  SizePlan s = plan_sizes_kind(A, B, p);
+  if (std::isnan(p->lambda_max))
+    s.total += lanczos_ctx_bytes(A->n, A->kind == CHFSI_OP_DENSE_HERMITIAN ||
+                                           A->kind == CHFSI_OP_STENCIL27_BLOCH);
+  return s;
+}
+
+SizePlan plan_sizes_kind(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
   if (A->kind == CHFSI_OP_DENSE_HERMITIAN) return plan_sizes_complex(A, p);
   if (A->kind == CHFSI_OP_STENCIL27_BLOCH) return plan_sizes_bloch(A, B, p);
   SizePlan s;
@@ -1175,6 +1207,8 @@ chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, cons
     return CHFSI_ERR_NOT_SPD;
   }
   c->flags |= 1;
+  c->svqb_events += 1;
+  c->svqb_dropped += int(b - k);
   // W (b x k) in c->T: columns first.. of U, scaled by g^{-1/2}, rows by s
   std::vector<double> colv(k);
   for (int64_t j = 0; j < k; ++j) colv[j] = 1.0 / std::sqrt(c->h_w[first + j]);
@@ -1576,6 +1610,8 @@ chfsi_status rayleigh_ritz_complex_svqb(chfsi_ctx* c, const double* Y, int64_t l
     return CHFSI_ERR_NOT_SPD;
   }
   c->flags |= 1;
+  c->svqb_events += 1;
+  c->svqb_dropped += int(b - k);
   {
     chfsi_status fs = fix_pair_clusters(c, c->E + first * m, m, b, k, c->h_w + first);
     if (fs != CHFSI_OK) return fs;
@@ -2070,6 +2106,8 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     return CHFSI_ERR_NOT_SPD;
   }
   c->flags |= 1;
+  c->svqb_events += 1;
+  c->svqb_dropped += int(b - k);
   std::vector<double> colv(k);
   for (int64_t j = 0; j < k; ++j) colv[j] = 1.0 / std::sqrt(c->h_w[first + j]);
   CK(hipEventSynchronize(c->ev_stage));
@@ -2132,9 +2170,103 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
   return rayleigh_ritz_slabs(c, X, ldx, R, ldr, ritz, resnorm, false);
 }
 
-void bounds_policy(const chfsi_params& p, const double* ritz, int64_t b, double* lmin,
-                   double* lmax, double* lT) {
-  *lmax = p.lambda_max;
+// Lanczos estimate of the spectrum bounds of B^{-1} A (lanczos.hip) on the
+// context's operators: real blocks of length n, or planar complex vectors of
+// length 2 n ([re; im], the Bloch operators in the twisted frame)
+chfsi_status estimate_bounds(chfsi_ctx* c, const double* v0_user, int steps, LanczosResult* res) {
+  const int64_t n = c->n;
+  const int64_t L = c->cplx ? 2 * n : n;
+  hipStream_t st = c->stream;
+  if (!c->lz_work) {
+    chfsi_status ls = CHFSI_OK;
+    c->lz_work = ctx_alloc<double>(c, lanczos_ctx_bytes(n, c->cplx), &ls);
+    if (ls != CHFSI_OK) return ls;
+  }
+  double* tmp = c->lz_work + (lanczos_workspace_bytes(L) + 255) / 256 * 256 / sizeof(double);
+  double* v0 = tmp;            // L
+  double* dl = tmp + L;        // L: D^{-1} on planar complex vectors
+  double* Yt = tmp + 2 * L;    // 4 n: right operand of the dense Hermitian product
+  if (v0_user) {
+    if (c->bloch)
+      CK(bloch_to_planar(v0_user, n, n, 1, v0, twist_of(c), st));
+    else if (c->cplx)
+      CK(cplx_to_planar(v0_user, n, n, 1, v0, st));
+    else
+      CK(copy_block(v0_user, n, v0, n, n, 1, st));
+  } else {
+    CK(fill_gaussian(v0, L, L, 1, c->prm.seed ^ 0x4c414e43u, st));
+  }
+  const double* dinv = c->dinv;
+  if (c->cplx && c->dinv) {
+    CK(dup_dinv<double>(c->dinv, n, dl, st));
+    dinv = dl;
+  }
+  auto apply = [c, st, n, Yt](const chfsi_operator& op, bool useB, const double* x,
+                              double* y) -> hipError_t {
+    if (c->bloch) {
+      hipError_t e = stencil_apply_f64(op, x, n, y, n, 2, st);
+      if (e != hipSuccess) return e;
+      return bloch_fix<double>(op, nullptr, 1.0, x, n, y, n, 1, st, nullptr, nullptr);
+    }
+    if (c->cplx) {
+      hipError_t e = cplx_rhs<double>(x, n, 1, Yt, st);
+      if (e != hipSuccess) return e;
+      GemmDesc<double> g;   // y (n x 2 planar) = L (n x 2n) Yt (2n x 2)
+      g.M = n;
+      g.N = 2;
+      g.K = 2 * n;
+      g.A = useB ? c->LB64 : c->LA64;
+      g.sak = 1;
+      g.sam = 2 * n;
+      g.B = Yt;
+      g.sbk = 1;
+      g.sbn = 2 * n;
+      g.C = y;
+      g.ldc = n;
+      return gemm<double>(g, st, c->ws);
+    }
+    if (op.kind == CHFSI_OP_DENSE) {
+      GemmDesc<double> g;
+      g.M = n;
+      g.N = 1;
+      g.K = n;
+      g.A = op.dense;
+      g.sak = 1;
+      g.sam = op.ld;
+      g.B = x;
+      g.sbk = 1;
+      g.sbn = n;
+      g.C = y;
+      g.ldc = n;
+      return gemm<double>(g, st, c->ws);
+    }
+    if (op.kind == CHFSI_OP_STENCIL27) return stencil_apply_f64(op, x, n, y, n, 1, st);
+    return hipErrorInvalidValue;
+  };
+  LanczosOps ops;
+  ops.apply_A = [&](const double* x, double* y) { return apply(c->A, false, x, y); };
+  if (!c->B_identity)
+    ops.apply_B = [&](const double* x, double* y) { return apply(c->B, true, x, y); };
+  ops.dinv = dinv;
+  ops.v0 = v0;
+  ops.steps = steps > 0 ? steps : (c->prm.lanczos_steps > 0 ? c->prm.lanczos_steps : 12);
+  const hipError_t e = lanczos_bounds(ops, L, c->lz_work, c->h_lz, st, res);
+  if (e == hipErrorInvalidValue) {
+    set_error("Lanczos bound estimate: B is not positive definite on the Krylov space "
+              "(or the start vector is zero)");
+    return CHFSI_ERR_NOT_SPD;
+  }
+  CK(e);
+  if (!std::isfinite(res->upper) || !std::isfinite(res->lower)) {
+    set_error("Lanczos bound estimate is not finite");
+    return CHFSI_ERR_NUMERIC;
+  }
+  return CHFSI_OK;
+}
+
+void bounds_policy(const chfsi_params& p, double lmax_used, const double* ritz, int64_t b,
+                   double* lmin, double* lmax, double* lT) {
+  *lmax = lmax_used;
   const double e1 = ritz[0], eb = ritz[b - 1];
   *lmin = std::isnan(p.lambda_min) ? e1 - 0.05 * (eb - e1) : p.lambda_min;
   *lT = std::isnan(p.lambda_T) ? eb : p.lambda_T;
@@ -2238,6 +2370,7 @@ void chfsi_destroy(chfsi_ctx* c) {
   if (c->h_norms) hipHostFree(c->h_norms);
   if (c->h_flags) hipHostFree(c->h_flags);
   if (c->h_stage) hipHostFree(c->h_stage);
+  if (c->h_lz) hipHostFree(c->h_lz);
   for (auto& e : c->ev)
     if (e) hipEventDestroy(e);
   if (c->ev_stage) hipEventDestroy(c->ev_stage);
@@ -2255,8 +2388,13 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   *out = nullptr;
   chfsi_status st = check_params(A, B, params);
   if (st != CHFSI_OK) return st;
-  if (!(std::isfinite(params->lambda_max))) {
-    set_error("lambda_max must be finite");
+  if (std::isinf(params->lambda_max) || std::isinf(params->lambda_min) ||
+      std::isinf(params->lambda_T)) {
+    set_error("filter bounds must be finite or NaN (NaN: estimated)");
+    return CHFSI_ERR_ARG;
+  }
+  if (params->lanczos_steps < 0) {
+    set_error("lanczos_steps must be >= 0");
     return CHFSI_ERR_ARG;
   }
   chfsi_ctx* c = new chfsi_ctx();
@@ -2430,7 +2568,8 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   if (hipHostMalloc(&c->h_w, hb * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&c->h_norms, hb * sizeof(double)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_flags), 64) != hipSuccess ||
-      hipHostMalloc(&c->h_stage, c->h_stage_bytes) != hipSuccess) {
+      hipHostMalloc(&c->h_stage, c->h_stage_bytes) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_lz), 64) != hipSuccess) {
     set_error("pinned host allocation failed");
     chfsi_destroy(c);
     return CHFSI_ERR_NOMEM;
@@ -2488,6 +2627,14 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     if (fs != CHFSI_OK) {
       chfsi_destroy(c);
       return fs;
+    }
+  }
+  if (e == hipSuccess && std::isnan(params->lambda_max)) {
+    chfsi_status ls = CHFSI_OK;
+    c->lz_work = ctx_alloc<double>(c, lanczos_ctx_bytes(n, c->cplx), &ls);
+    if (ls != CHFSI_OK) {
+      chfsi_destroy(c);
+      return ls;
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -2582,6 +2729,28 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, dou
   return rayleigh_ritz(c, Y, ldy, X, ldx, R, ldr, ritz, resnorm, true);
 }
 
+chfsi_status chfsi_estimate_bounds(chfsi_ctx* c, const double* v0, int32_t steps, double* lower,
+                                   double* upper, double* theta) {
+  if (!c || !lower || !upper) {
+    set_error("null argument");
+    return CHFSI_ERR_ARG;
+  }
+  if (steps < 0) {
+    set_error("steps must be >= 0");
+    return CHFSI_ERR_ARG;
+  }
+  LanczosResult lr;
+  const chfsi_status st = estimate_bounds(c, v0, steps, &lr);
+  if (st != CHFSI_OK) return st;
+  *lower = lr.lower;
+  *upper = lr.upper;
+  if (theta) {
+    theta[0] = lr.theta_min;
+    theta[1] = lr.theta_max;
+  }
+  return CHFSI_OK;
+}
+
 chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, double* resnorms,
                          chfsi_report* rep) {
   if (!c || !X || !evals || !resnorms) {
@@ -2603,8 +2772,24 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   if (c->prm.init_random) CK(fill_gaussian(X, lds, rows, b, c->prm.seed, c->stream));
   std::vector<double> ritz(b), norms(b);
   float ms = 0.0f;
+  double lmax_used = c->prm.lambda_max;
+  if (std::isnan(lmax_used)) {
+    if (!c->have_lmax) {
+      const double tb = now_ms();
+      LanczosResult lr;
+      const chfsi_status bs = estimate_bounds(c, nullptr, 0, &lr);
+      if (bs != CHFSI_OK) return bs;
+      c->lmax_est = lr.upper;
+      c->have_lmax = true;
+      r.time_bounds_ms = now_ms() - tb;
+    }
+    lmax_used = c->lmax_est;
+  }
+  r.lambda_max_used = lmax_used;
   CK(hipEventRecord(c->ev[2], c->stream));
   c->last_sweeps = 0;
+  c->svqb_events = 0;
+  c->svqb_dropped = 0;
   const bool slabs = c->prm.memory_mode == 1;
   double* Xw = slabs ? X : c->Xw;            // working Ritz block
   const int64_t ldw = slabs ? ldx : n;
@@ -2633,7 +2818,7 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
       break;
     }
     double lmin, lmax, lT;
-    bounds_policy(c->prm, ritz.data(), b, &lmin, &lmax, &lT);
+    bounds_policy(c->prm, lmax_used, ritz.data(), b, &lmin, &lmax, &lT);
     if (!(lmin < lT && lT < lmax)) {
       set_error("filter bounds collapsed (lmin %.6g, lT %.6g, lmax %.6g): lambda_max too small?",
                 lmin, lT, lmax);
@@ -2674,13 +2859,17 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
     mr = maxres();
     if (it + 1 < CHFSI_MAX_HISTORY) r.history[it + 1] = mr;
     if (progress_log())
-      std::fprintf(stderr, "chfsi_solve: iteration %d, max residual %.3e (filter %.1f ms, RR %.1f ms)\n",
-                   it + 1, mr, r.time_filter_ms, r.time_rr_ms);
+      std::fprintf(stderr,
+                   "chfsi_solve: iteration %d, max residual %.3e (filter %.1f ms, RR %.1f ms, "
+                   "SVQB fallbacks %d, dropped directions %d)\n",
+                   it + 1, mr, r.time_filter_ms, r.time_rr_ms, c->svqb_events, c->svqb_dropped);
   }
   r.iterations = it;
   r.max_residual = mr;
   r.converged = mr < c->prm.tol;
   r.flags = c->flags;
+  r.svqb_events = c->svqb_events;
+  r.svqb_dropped = c->svqb_dropped;
   if (st != CHFSI_OK && st != CHFSI_ERR_NOCONV) return st;
   if (!slabs) CK(copy_block(c->Xw, ldn, X, lds, rows, b, c->stream));
   CK(hipStreamSynchronize(c->stream));

@@ -6,12 +6,16 @@
 #include <cstdint>
 #include <cstddef>
 #include <atomic>
+#include <functional>
 
 #include "../../include/chfsi.h"
 
 struct chfsi_ctx;
 
 namespace chfsi {
+
+// Sets the calling thread's message returned by chfsi_last_error().
+void set_error_message(const char* msg);
 
 // ---------------------------------------------------------------------------
 // GEMM: C(m,n) = epilogue( sum_k A(m,k) * B(k,n) )
@@ -174,6 +178,32 @@ hipError_t bloch_to_planar(const double* Z, int64_t ldz, int64_t n, int64_t b, d
 hipError_t bloch_from_planar(const double* P, int64_t n, int64_t b, double* Z, int64_t ldz,
                              const Twist& tw, hipStream_t st);
 // (the boundary correction kernels are declared with the grid kernels, stencil_api.h)
+
+// ---------------------------------------------------------------------------
+// Spectrum-bound estimates by a k-step Lanczos process on B^{-1} A in the
+// B-inner product (lanczos.hip).  Vectors are FP64 of length L.
+// ---------------------------------------------------------------------------
+struct LanczosOps {
+  std::function<hipError_t(const double*, double*)> apply_A;  // y = A x
+  std::function<hipError_t(const double*, double*)> apply_B;  // y = B x; empty: B = I
+  const double* dinv = nullptr;   // CG preconditioner (length L; null: none)
+  const double* v0 = nullptr;     // start vector (device, length L)
+  int steps = 12;
+  double cg_tol = 1e-12;          // relative residual of the inner B-solves
+  int cg_max_iter = 1000;
+};
+struct LanczosResult {
+  int steps = 0, cg_iterations = 0;
+  double theta_min = 0.0, theta_max = 0.0, beta_last = 0.0;
+  double lower = 0.0, upper = 0.0;   // theta_min - |beta_k|, theta_max + |beta_k|
+};
+// device scratch for vectors of length L
+size_t lanczos_workspace_bytes(int64_t L);
+// host_scalars: pinned host memory for 2 doubles.  Synchronises the stream
+// at every dot product.  Returns hipErrorInvalidValue if B is not positive
+// definite on the Krylov space (a non-positive B-norm).
+hipError_t lanczos_bounds(const LanczosOps& ops, int64_t L, double* work, double* host_scalars,
+                          hipStream_t st, LanczosResult* res);
 
 // ---------------------------------------------------------------------------
 // Elementwise / reduction kernels (blas1.hip)

@@ -242,7 +242,7 @@ def test_invalid_arguments_are_rejected(gen_problem):
     with pytest.raises(P.ChfsiError):
         P.chfsi_create(opA, None, None, P.make_params(10, 40, 0, lambda_max=10.0))
     with pytest.raises(P.ChfsiError):
-        P.chfsi_create(opA, None, None, P.make_params(10, 40, 8))   # lambda_max NaN
+        P.chfsi_create(opA, None, None, P.make_params(10, 40, 8, lambda_max=float("inf")))
     ctx = P.chfsi_create(opA, None, None, P.make_params(10, 40, 8, method=P.METHOD_CHFSI,
                                                         lambda_max=10.0), keep=(A,))
     Xd = dev(np.ones((p.n, 40)))

@@ -99,7 +99,19 @@ def test_filter_error_tracks_residual(kind, prec):
                        if h["res_norm"] > 1e4 * floor and h["err"] > 1e-12])
     print("  err/||R|| over %d iterations: %.2e .. %.2e" % (len(ratios), ratios.min(), ratios.max()))
     assert len(ratios) >= 8
-    assert ratios.max() / ratios.min() < 10.0
+    # Theorem 3.4 bounds ||Delta^_p|| by a constant times u ||R||: the error
+    # falls with ||R|| (a log-log slope of at least ~1 over the decades ||R||
+    # spans; a plateau at O(u), as for the plain filter, would flatten it to
+    # 0) and the constant stays within a band (bfloat16 rounding of a few
+    # columns spreads it by up to ~10x between iterations)
+    sel = [(h["res_norm"], h["err"]) for h in hist
+           if h["res_norm"] > 1e4 * floor and h["err"] > 1e-12]
+    lr, le = np.log10([s[0] for s in sel]), np.log10([s[1] for s in sel])
+    slope = np.polyfit(lr, le, 1)[0]
+    print("  log-log slope of ||Delta|| against ||R||: %.3f" % slope)
+    assert lr.max() - lr.min() > 4.0
+    assert slope > 0.8
+    assert ratios.max() / ratios.min() < 20.0
     # measured on MI355X: FP32 at most 0.33 u, bfloat16 at most 0.06 u
     assert ratios.max() < 2.0 * UNIT[prec]
     # the residual form converges to the FP64 level in both precisions
