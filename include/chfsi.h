@@ -60,7 +60,8 @@ typedef enum {
   CHFSI_OP_DENSE = 1,           /* dense symmetric matrix in device memory */
   CHFSI_OP_STENCIL27 = 2,       /* periodic 27-point grid operator (see chfsi_operator) */
   CHFSI_OP_DENSE_HERMITIAN = 3, /* dense complex Hermitian matrix (Section 4.3; see below) */
-  CHFSI_OP_STENCIL27_BLOCH = 4  /* grid operator with Bloch phases, complex (Section 4.3) */
+  CHFSI_OP_STENCIL27_BLOCH = 4, /* grid operator with Bloch phases, complex (Section 4.3) */
+  CHFSI_OP_CSR = 5              /* sparse symmetric matrix in CSR form (see chfsi_operator) */
 } chfsi_op_kind;
 
 /* Storage / arithmetic precision of the filter's bulk work (the residual
@@ -109,6 +110,17 @@ typedef enum { CHFSI_METHOD_CHFSI = 0, CHFSI_METHOD_RCHFSI = 1 } chfsi_method;
  *    by D = diag(exp(i k.r)): the real z-marching kernels on the planar real
  *    and imaginary parts plus a correction at the boundary points for the
  *    phase of wrapped neighbours.  bloch[] is ignored for other kinds.
+ *  kind = CHFSI_OP_CSR: a real symmetric n x n matrix (the sparse
+ *    finite-element operators of Section 4.2) in compressed sparse row form,
+ *    device arrays, borrowed: rowptr (int64, n + 1 entries, rowptr[0] = 0,
+ *    non-decreasing, rowptr[n] = nnz), colind (int32, nnz entries in
+ *    [0, n)), val (double, nnz entries).  Both triangles are stored; the
+ *    library does not check symmetry.  chfsi_create checks the structure
+ *    (CHFSI_ERR_ARG if invalid), keeps an FP32 copy of val for FP32 / BF16
+ *    filters and requires n < 2^31 and memory_mode 0.  B may be NULL / the
+ *    identity, CSR or dense of A's size.  The filter's products run in the
+ *    context's filter precision (FP64, FP32, or BF16-stored blocks with FP32
+ *    arithmetic).
  */
 typedef struct {
   int32_t kind;
@@ -121,6 +133,10 @@ typedef struct {
   const double* field;
   int32_t field_mode;
   double bloch[3];
+  const int64_t* rowptr;   /* CHFSI_OP_CSR */
+  const int32_t* colind;
+  const double* val;
+  int64_t nnz;
 } chfsi_operator;
 
 /* Solver parameters (Algorithm 1 inputs: n, p, bounds, tau). */
@@ -160,6 +176,14 @@ typedef struct {
   int32_t binv_exact;
   /* Lanczos steps of the lambda_max estimate (0: 12). */
   int32_t lanczos_steps;
+  /* Stagnation: chfsi_solve stops with CHFSI_ERR_NOCONV once the max residual
+   * has stayed above its best value for stall_iters consecutive iterations
+   * (0: run to max_iter). */
+  int32_t stall_iters;
+  /* 1: keep a copy of the Ritz block of the lowest max residual (one more
+   * n x b FP64 block, allocated by chfsi_create) and return those pairs on
+   * CHFSI_ERR_NOCONV; 0: return the last pairs. */
+  int32_t keep_best;
 } chfsi_params;
 
 /* Per-solve report (host). */
@@ -175,12 +199,17 @@ typedef struct {
   int32_t jacobi_sweeps;       /* sum of eigensolver sweeps */
   int32_t kernel_launches;     /* profile: filter operator-product kernels timed */
   double kernel_ms;            /* profile: their summed durations (HIP events) */
-  int32_t flags;               /* bit 0: a Gram matrix took the SVQB fallback */
+  int32_t flags;               /* bit 0: a Gram matrix took the SVQB fallback;
+                                  bit 1: a Jacobi eigensolve reached its cap of 40 sweeps
+                                  with rotations still applied (not fully diagonalised);
+                                  bit 2: the solve stopped on stagnation (stall_iters) */
   double history[CHFSI_MAX_HISTORY]; /* max residual after each pass (entry 0: initial RR) */
   int32_t svqb_events;         /* Rayleigh-Ritz passes that took the SVQB fallback */
   int32_t svqb_dropped;        /* directions dropped (and refilled) by those passes, summed */
   double lambda_max_used;      /* the filter's upper bound (given, or the Lanczos estimate) */
   double time_bounds_ms;       /* time of the Lanczos estimate in this solve (0 if none) */
+  int32_t best_iteration;      /* pass with the lowest max residual (0: initial RR) */
+  double best_residual;        /* that lowest max residual */
 } chfsi_report;
 
 typedef struct chfsi_ctx chfsi_ctx;
@@ -264,8 +293,10 @@ chfsi_status chfsi_estimate_bounds(chfsi_ctx* ctx, const double* v0, int32_t ste
  * ld >= n): on entry the start block (or overwritten with N(0,1) values when
  * params.init_random), on exit the Ritz vectors.  evals, resnorms: host,
  * length b (ascending Ritz values and their residual norms).  rep: optional.
- * Returns CHFSI_OK on convergence, CHFSI_ERR_NOCONV after max_iter passes
- * (outputs hold the last pairs, as LAPACK's INFO > 0), other errors as above.
+ * Returns CHFSI_OK on convergence, CHFSI_ERR_NOCONV after max_iter passes or
+ * on stagnation (params.stall_iters; report flags bit 2); the outputs then hold
+ * the pairs of the lowest max residual when params.keep_best, else the last
+ * pairs (as LAPACK's INFO > 0).  Other errors as above.
  */
 chfsi_status chfsi_solve(chfsi_ctx* ctx, double* X, int64_t ldx, double* evals, double* resnorms,
                          chfsi_report* rep);
@@ -343,6 +374,23 @@ chfsi_status chfsi_wait(chfsi_server* s, uint64_t ticket, int32_t timeout_ms, ch
 /* Cancel a pending request (a running one finishes its current pass first). */
 chfsi_status chfsi_cancel(chfsi_server* s, uint64_t ticket);
 void chfsi_result_free(chfsi_result* res);
+/* Server memory.  Every context, working block and warm-start block of the
+ * server's requests is drawn from two pools (device memory, pinned host
+ * memory) that grow by whole chunks (hipMalloc / hipHostMalloc) only when no
+ * free range fits, and that are released only by chfsi_server_destroy, so a
+ * server in steady state allocates and frees nothing per request (hipFree
+ * would synchronise the whole device).  The budget charges a running request
+ * its workspace plus working block, and each sequence its warm-start block
+ * from allocation to replacement or server destruction. */
+typedef struct {
+  size_t budget;             /* device bytes admission may charge */
+  size_t used;               /* charged now: running requests + warm-start blocks */
+  size_t sequence_bytes;     /* of which warm-start blocks of live sequences */
+  int32_t device_pool_chunks;/* hipMalloc calls made by the device pool so far */
+  int32_t host_pool_chunks;  /* hipHostMalloc calls made by the pinned pool so far */
+} chfsi_server_stats_t;
+chfsi_status chfsi_server_stats(chfsi_server* s, chfsi_server_stats_t* out);
+
 /* Drain running requests and stop the scheduler. */
 void chfsi_server_destroy(chfsi_server* s);
 

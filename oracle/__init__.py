@@ -22,6 +22,8 @@ following the paper (arXiv 2503.22652) step by step:
 * ``jacobi``     -- brute-force cyclic Jacobi eigensolver for tiny matrices
   (an independent pin for the library eigensolver used in ``rr``).
 * ``stencil``    -- periodic 27-point operator application for grid pencils.
+* ``cstencil``   -- the same grid pencil and Algorithm 3 as plain C loops with
+  OpenMP (oracle/stencil27.c), FP64, for the CPU baseline at full grid size.
 * ``angles``     -- maximum principal angle (Definition 2.1).
 * ``bounds``     -- k-step Lanczos estimates of the spectrum of B^{-1} A,
   the filter's bounds (Section 2.1 treats them as estimates).

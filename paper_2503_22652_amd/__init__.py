@@ -23,7 +23,7 @@ OK, ERR_ARG, ERR_NOMEM, ERR_DEVICE, ERR_NOT_SPD, ERR_NOCONV, ERR_NUMERIC, ERR_BU
     ERR_CANCELLED, ERR_TIMEOUT = range(10)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_NOMEM", "ERR_DEVICE", "ERR_NOT_SPD", "ERR_NOCONV",
                 "ERR_NUMERIC", "ERR_BUSY", "ERR_CANCELLED", "ERR_TIMEOUT"]
-OP_IDENTITY, OP_DENSE, OP_STENCIL27, OP_DENSE_HERMITIAN, OP_STENCIL27_BLOCH = 0, 1, 2, 3, 4
+OP_IDENTITY, OP_DENSE, OP_STENCIL27, OP_DENSE_HERMITIAN, OP_STENCIL27_BLOCH, OP_CSR = range(6)
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 METHOD_CHFSI, METHOD_RCHFSI = 0, 1
 MAX_HISTORY = 512
@@ -33,7 +33,9 @@ class chfsi_operator(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int64), ("dense", C.c_void_p), ("ld", C.c_int64),
                 ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("coef", C.c_double * 27), ("coef_mass", C.c_double * 27),
-                ("field", C.c_void_p), ("field_mode", C.c_int32), ("bloch", C.c_double * 3)]
+                ("field", C.c_void_p), ("field_mode", C.c_int32), ("bloch", C.c_double * 3),
+                ("rowptr", C.c_void_p), ("colind", C.c_void_p), ("val", C.c_void_p),
+                ("nnz", C.c_int64)]
 
 
 class chfsi_params(C.Structure):
@@ -43,7 +45,8 @@ class chfsi_params(C.Structure):
                 ("lambda_max", C.c_double), ("lambda_T", C.c_double), ("seed", C.c_uint64),
                 ("init_random", C.c_int32), ("profile", C.c_int32),
                 ("memory_mode", C.c_int32), ("binv_exact", C.c_int32),
-                ("lanczos_steps", C.c_int32)]
+                ("lanczos_steps", C.c_int32), ("stall_iters", C.c_int32),
+                ("keep_best", C.c_int32)]
 
 
 class chfsi_report(C.Structure):
@@ -54,12 +57,18 @@ class chfsi_report(C.Structure):
                 ("kernel_launches", C.c_int32), ("kernel_ms", C.c_double),
                 ("flags", C.c_int32), ("history", C.c_double * MAX_HISTORY),
                 ("svqb_events", C.c_int32), ("svqb_dropped", C.c_int32),
-                ("lambda_max_used", C.c_double), ("time_bounds_ms", C.c_double)]
+                ("lambda_max_used", C.c_double), ("time_bounds_ms", C.c_double),
+                ("best_iteration", C.c_int32), ("best_residual", C.c_double)]
 
 
 class chfsi_server_config(C.Structure):
     _fields_ = [("slots", C.c_int32), ("queue_capacity", C.c_int32),
                 ("memory_budget", C.c_size_t)]
+
+
+class chfsi_server_stats_t(C.Structure):
+    _fields_ = [("budget", C.c_size_t), ("used", C.c_size_t), ("sequence_bytes", C.c_size_t),
+                ("device_pool_chunks", C.c_int32), ("host_pool_chunks", C.c_int32)]
 
 
 class chfsi_request(C.Structure):
@@ -102,6 +111,7 @@ _SIGNATURES = {
     "chfsi_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
     "chfsi_result_free": (None, [C.POINTER(chfsi_result)]),
     "chfsi_server_destroy": (None, [C.c_void_p]),
+    "chfsi_server_stats": (C.c_int, [C.c_void_p, C.POINTER(chfsi_server_stats_t)]),
 }
 
 _lib = None
@@ -181,6 +191,17 @@ def colmajor_empty_complex(n: int, b: int, device="cuda"):
     return torch.empty((b, n), dtype=torch.complex128, device=device).t()
 
 
+def csr_operator(n: int, rowptr, colind, val) -> chfsi_operator:
+    """Operator struct for a symmetric CSR matrix given as CUDA tensors
+    (rowptr int64 [n + 1], colind int32 [nnz], val float64 [nnz])."""
+    op = chfsi_operator()
+    op.kind = OP_CSR
+    op.n = n
+    op.rowptr, op.colind, op.val = _ptr(rowptr), _ptr(colind), _ptr(val)
+    op.nnz = int(val.numel())
+    return op
+
+
 def identity_operator(n: int) -> chfsi_operator:
     op = chfsi_operator()
     op.kind = OP_IDENTITY
@@ -226,7 +247,8 @@ def make_params(n_wanted: int, block: int, degree: int, max_iter: int = 100, tol
                 lambda_min: float = math.nan, lambda_max: float = math.nan,
                 lambda_T: float = math.nan, seed: int = 0, init_random: int = 0,
                 profile: int = 0, memory_mode: int = 0, binv_exact: int = 0,
-                lanczos_steps: int = 0) -> chfsi_params:
+                lanczos_steps: int = 0, stall_iters: int = 0,
+                keep_best: int = 0) -> chfsi_params:
     p = chfsi_params()
     p.n_wanted, p.block, p.degree, p.max_iter, p.tol = n_wanted, block, degree, max_iter, tol
     p.method, p.filter_prec = method, filter_prec
@@ -235,6 +257,8 @@ def make_params(n_wanted: int, block: int, degree: int, max_iter: int = 100, tol
     p.memory_mode = memory_mode
     p.binv_exact = binv_exact
     p.lanczos_steps = lanczos_steps
+    p.stall_iters = stall_iters
+    p.keep_best = keep_best
     return p
 
 
@@ -340,6 +364,7 @@ def report_dict(rep: chfsi_report) -> dict:
             "jacobi_sweeps": rep.jacobi_sweeps, "flags": rep.flags,
             "svqb_events": rep.svqb_events, "svqb_dropped": rep.svqb_dropped,
             "lambda_max_used": rep.lambda_max_used, "time_bounds_ms": rep.time_bounds_ms,
+            "best_iteration": rep.best_iteration, "best_residual": rep.best_residual,
             "kernel_launches": rep.kernel_launches, "kernel_ms": rep.kernel_ms,
             "history": [rep.history[i] for i in range(min(it + 1, MAX_HISTORY))]}
 
@@ -403,6 +428,13 @@ class Server:
         if st not in (OK, ERR_NOCONV, ERR_CANCELLED):
             raise ChfsiError(st, "chfsi_wait")
         return out
+
+    def stats(self) -> dict:
+        st = chfsi_server_stats_t()
+        _check(lib().chfsi_server_stats(self.handle, C.byref(st)), "chfsi_server_stats")
+        return {"budget": st.budget, "used": st.used, "sequence_bytes": st.sequence_bytes,
+                "device_pool_chunks": st.device_pool_chunks,
+                "host_pool_chunks": st.host_pool_chunks}
 
     def cancel(self, ticket: int) -> int:
         return lib().chfsi_cancel(self.handle, ticket)

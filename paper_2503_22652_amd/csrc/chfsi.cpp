@@ -101,6 +101,7 @@ struct chfsi_ctx {
 
   std::vector<void*> allocs;  // everything owned
   size_t bytes = 0;
+  const Allocator* al = nullptr;   // memory source (null: hipMalloc / hipHostMalloc)
 
   // filter precision copies / buffers
   float* A32 = nullptr;
@@ -158,6 +159,11 @@ struct chfsi_ctx {
   hipEvent_t ev_stage = nullptr;   // last copy out of h_stage (reuse waits on it)
   int last_sweeps = 0;
   int flags = 0;
+  int jacobi_unconv = 0;          // the last eigensolve reached its sweep cap
+  double* Xbest = nullptr;        // keep_best: Ritz block of the lowest max residual
+  // CSR operators: longest rows (checked at create) and FP32 value copies
+  int csrA_kmax = 0, csrB_kmax = 0;
+  float* val32 = nullptr;
   int svqb_events = 0;            // Rayleigh-Ritz passes that took the SVQB fallback
   int svqb_dropped = 0;           // directions those passes dropped and refilled
   // Lanczos bound estimate: vectors (lanczos_ctx_bytes), pinned scalars, the
@@ -278,8 +284,13 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
       set_error("stencil field_mode must be 0, 1 or 2 (1/2 need a field)");
       return CHFSI_ERR_ARG;
     }
+  } else if (A->kind == CHFSI_OP_CSR) {
+    if (!A->rowptr || !A->colind || !A->val || A->nnz < 0 || A->n >= (int64_t(1) << 31)) {
+      set_error("CSR A needs rowptr, colind and val device arrays, nnz >= 0 and n < 2^31");
+      return CHFSI_ERR_ARG;
+    }
   } else {
-    set_error("A must be dense or a stencil operator");
+    set_error("A must be dense, a stencil or a CSR operator");
     return CHFSI_ERR_ARG;
   }
   if (!is_identity(B)) {
@@ -296,7 +307,11 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
       set_error("stencil B must share A's grid and carry no field");
       return CHFSI_ERR_ARG;
     }
-    if (B->kind != CHFSI_OP_DENSE && B->kind != CHFSI_OP_STENCIL27) {
+    if (B->kind == CHFSI_OP_CSR && (!B->rowptr || !B->colind || !B->val || B->nnz < 0)) {
+      set_error("CSR B needs rowptr, colind and val device arrays and nnz >= 0");
+      return CHFSI_ERR_ARG;
+    }
+    if (B->kind != CHFSI_OP_DENSE && B->kind != CHFSI_OP_STENCIL27 && B->kind != CHFSI_OP_CSR) {
       set_error("unsupported B kind");
       return CHFSI_ERR_ARG;
     }
@@ -318,8 +333,8 @@ chfsi_status check_params(const chfsi_operator* A, const chfsi_operator* B,
     return CHFSI_ERR_ARG;
   }
   if (p->filter_prec == CHFSI_PREC_BF16 && A->kind != CHFSI_OP_STENCIL27 &&
-      A->kind != CHFSI_OP_DENSE) {
-    set_error("BF16 filters are implemented for dense and stencil operators");
+      A->kind != CHFSI_OP_DENSE && A->kind != CHFSI_OP_CSR) {
+    set_error("BF16 filters are implemented for dense, stencil and CSR operators");
     return CHFSI_ERR_ARG;
   }
   if (p->filter_prec == CHFSI_PREC_BF16 && p->method != CHFSI_METHOD_RCHFSI) {
@@ -442,6 +457,10 @@ SizePlan plan_sizes_kind(const chfsi_operator* A, const chfsi_operator* B, const
 
 SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
   SizePlan s = plan_sizes_kind(A, B, p);
+  if (p->keep_best) {
+    const bool cx = A->kind == CHFSI_OP_DENSE_HERMITIAN || A->kind == CHFSI_OP_STENCIL27_BLOCH;
+    s.total += size_t(A->n) * (cx ? 2 : 1) * p->block * sizeof(double);
+  }
   if (std::isnan(p->lambda_max))
     s.total += lanczos_ctx_bytes(A->n, A->kind == CHFSI_OP_DENSE_HERMITIAN ||
                                            A->kind == CHFSI_OP_STENCIL27_BLOCH);
@@ -469,8 +488,11 @@ SizePlan plan_sizes_kind(const chfsi_operator* A, const chfsi_operator* B, const
     s.bfblk = size_t(n) * b * 2;
   }
   // stencil filters in FP32/BF16: FP32 copies of D^{-1} and of the potential
-  if (!dense && p->filter_prec != CHFSI_PREC_FP64)
+  if (A->kind == CHFSI_OP_STENCIL27 && p->filter_prec != CHFSI_PREC_FP64)
     s.a32 += size_t(n) * sizeof(float) * (1 + (A->field_mode != 0 ? 1 : 0));
+  // CSR filters in FP32/BF16: FP32 copies of D^{-1} and of the values
+  if (A->kind == CHFSI_OP_CSR && p->filter_prec != CHFSI_PREC_FP64)
+    s.a32 += size_t(n) * sizeof(float) + size_t(A->nnz) * sizeof(float);
   s.coef = size_t(p->degree + 1) * b * sizeof(double);
   size_t ws = 0;
   if (dense) {
@@ -513,15 +535,42 @@ template <typename T>
 T* ctx_alloc(chfsi_ctx* c, size_t bytes, chfsi_status* st) {
   if (bytes == 0) return nullptr;
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, (bytes + 255) / 256 * 256);
-  if (e != hipSuccess) {
-    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    *st = CHFSI_ERR_NOMEM;
-    return nullptr;
+  if (c->al) {
+    p = c->al->dev_alloc(c->al->self, (bytes + 255) / 256 * 256);
+    if (!p) {
+      set_error("device pool allocation of %zu bytes failed", bytes);
+      *st = CHFSI_ERR_NOMEM;
+      return nullptr;
+    }
+  } else {
+    hipError_t e = hipMalloc(&p, (bytes + 255) / 256 * 256);
+    if (e != hipSuccess) {
+      set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+      *st = CHFSI_ERR_NOMEM;
+      return nullptr;
+    }
   }
   c->allocs.push_back(p);
   c->bytes += bytes;
   return static_cast<T*>(p);
+}
+
+// the kernels' view of a CSR operator of the context (FP64 values, or the
+// FP32 copy of A's)
+CsrMat csr_of(const chfsi_ctx* c, const chfsi_operator& op, bool f32) {
+  CsrMat m;
+  m.n = op.n;
+  m.rowptr = op.rowptr;
+  m.col = op.colind;
+  m.val = f32 ? static_cast<const void*>(c->val32) : static_cast<const void*>(op.val);
+  m.kmax = (&op == &c->B) ? c->csrB_kmax : c->csrA_kmax;
+  return m;
+}
+
+// nominal flops per element and step of an operator product (for reporting)
+double op_flops(const chfsi_operator& op) {
+  if (op.kind == CHFSI_OP_CSR) return 2.0 * double(op.nnz) / double(std::max<int64_t>(op.n, 1));
+  return stencil_flops(op);
 }
 
 // y = Op x for an n x b FP64 block
@@ -545,6 +594,10 @@ chfsi_status apply_op64(chfsi_ctx* c, const chfsi_operator* op, const double* X,
   }
   if (op->kind == CHFSI_OP_STENCIL27) {
     CK(stencil_apply_f64(*op, X, ldx, Y, ldy, b, c->stream));
+    return CHFSI_OK;
+  }
+  if (op->kind == CHFSI_OP_CSR) {
+    CK(csr_apply_f64(csr_of(c, *op, false), X, ldx, Y, ldy, b, c->stream));
     return CHFSI_OK;
   }
   set_error("unsupported operator kind");
@@ -691,11 +744,15 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
           hipEvent_t e0, e1;
           CK(prof_pair(c, &e0, &e1));
           if (e0) CK(hipEventRecord(e0, c->stream));
-          CK(stencil_rchfsi_step_f32(c->A, c->Vf, c->dinv32, RY, RX, Yc, c->coef32 + int64_t(s) * b, ss, b,
-                                     c->stream));
+          if (c->A.kind == CHFSI_OP_CSR)
+            CK(csr_rchfsi_step_f32(csr_of(c, c->A, true), c->dinv ? c->dinv32 : nullptr, RY, RX,
+                                   Yc, c->coef32 + int64_t(s) * b, ss, b, c->stream));
+          else
+            CK(stencil_rchfsi_step_f32(c->A, c->Vf, c->dinv32, RY, RX, Yc,
+                                       c->coef32 + int64_t(s) * b, ss, b, c->stream));
           if (e1) CK(hipEventRecord(e1, c->stream));
         }
-        fl += stencil_flops(c->A) * double(n) * double(b);
+        fl += op_flops(c->A) * double(n) * double(b);
       }
       std::swap(RX, RY);
     }
@@ -740,11 +797,15 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
           hipEvent_t e0, e1;
           CK(prof_pair(c, &e0, &e1));
           if (e0) CK(hipEventRecord(e0, c->stream));
-          CK(stencil_rchfsi_step_f64(c->A, c->dinv, RY, RX, resid, ldr, c->coef64 + int64_t(s) * b,
-                                     ss, b, c->stream));
+          if (c->A.kind == CHFSI_OP_CSR)
+            CK(csr_rchfsi_step_f64(csr_of(c, c->A, false), c->dinv, RY, RX, resid, ldr,
+                                   c->coef64 + int64_t(s) * b, ss, b, c->stream));
+          else
+            CK(stencil_rchfsi_step_f64(c->A, c->dinv, RY, RX, resid, ldr,
+                                       c->coef64 + int64_t(s) * b, ss, b, c->stream));
           if (e1) CK(hipEventRecord(e1, c->stream));
         }
-        fl += stencil_flops(c->A) * double(n) * double(b);
+        fl += op_flops(c->A) * double(n) * double(b);
       }
       std::swap(RX, RY);
     }
@@ -762,11 +823,15 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
         hipEvent_t e0, e1;
         CK(prof_pair(c, &e0, &e1));
         if (e0) CK(hipEventRecord(e0, c->stream));
-        CK(stencil_rchfsi_step_bf16(c->A, c->Vf, c->dinv32, RY, RX, Yc, c->coef32 + int64_t(s) * b, ss, b,
-                                    c->stream));
+        if (c->A.kind == CHFSI_OP_CSR)
+          CK(csr_rchfsi_step_bf16(csr_of(c, c->A, true), c->dinv ? c->dinv32 : nullptr, RY, RX,
+                                  Yc, c->coef32 + int64_t(s) * b, ss, b, c->stream));
+        else
+          CK(stencil_rchfsi_step_bf16(c->A, c->Vf, c->dinv32, RY, RX, Yc,
+                                      c->coef32 + int64_t(s) * b, ss, b, c->stream));
         if (e1) CK(hipEventRecord(e1, c->stream));
       }
-      fl += stencil_flops(c->A) * double(n) * double(b);
+      fl += op_flops(c->A) * double(n) * double(b);
       std::swap(RX, RY);
     }
     CK(rchfsi_reconstruct_bf16(RY, c->dinv, X, ldx, c->lamY, Yp, ldy, n, b, c->stream));
@@ -1066,10 +1131,15 @@ chfsi_status filter_chfsi(chfsi_ctx* c, const double* X, int64_t ldx, double* Yp
           hipEvent_t e0, e1;
           CK(prof_pair(c, &e0, &e1));
           if (e0) CK(hipEventRecord(e0, c->stream));
-          CK(stencil_chfsi_step_f64(c->A, c->dinv, src, ldsrc, Cprev, ldp, dst, ss, b, c->stream));
+          if (c->A.kind == CHFSI_OP_CSR)
+            CK(csr_chfsi_step_f64(csr_of(c, c->A, false), c->dinv, src, ldsrc, Cprev, ldp, dst, ss,
+                                  b, c->stream));
+          else
+            CK(stencil_chfsi_step_f64(c->A, c->dinv, src, ldsrc, Cprev, ldp, dst, ss, b,
+                                      c->stream));
           if (e1) CK(hipEventRecord(e1, c->stream));
         }
-        fl += stencil_flops(c->A) * double(n) * double(b);
+        fl += op_flops(c->A) * double(n) * double(b);
       }
       return CHFSI_OK;
     };
@@ -1194,7 +1264,8 @@ chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, cons
   hipStream_t st = c->stream;
   chfsi_status s;
   int sweeps = 0;
-  CK(syev_jacobi(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  CK(syev_jacobi(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -1248,7 +1319,8 @@ chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, cons
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, b, k, st));
-  CK(syev_jacobi(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  CK(syev_jacobi(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
     GemmDesc<double> g;   // Tfin (b x k) = W E, stored in c->Linv
@@ -1416,7 +1488,8 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   }
   CK(symmetrize(c->Hp, b, b, st));
   int sweeps = 0;
-  CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
     GemmDesc<double> g;   // T = diag(s) Linv^T E
@@ -1596,7 +1669,8 @@ chfsi_status rayleigh_ritz_complex_svqb(chfsi_ctx* c, const double* Y, int64_t l
   const int64_t n = c->n, b = c->b, m = 2 * b;
   hipStream_t st = c->stream;
   int sweeps = 0;
-  CK(syev_jacobi(c->Linv, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps));
+  CK(syev_jacobi(c->Linv, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, m * sizeof(double), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -1654,7 +1728,8 @@ chfsi_status rayleigh_ritz_complex_svqb(chfsi_ctx* c, const double* Y, int64_t l
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, m, 2 * k, st));
-  CK(syev_jacobi(c->Hp, m, 2 * k, c->w, c->E, m, st, c->ws_eig, &sweeps));
+  CK(syev_jacobi(c->Hp, m, 2 * k, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
     std::vector<double> hw(2 * k);
@@ -1909,7 +1984,8 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
   }
   CK(symmetrize(c->Hp, m, m, st));
   int sweeps = 0;
-  CK(syev_jacobi(c->Hp, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps));
+  CK(syev_jacobi(c->Hp, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
     GemmDesc<double> g;   // T = diag(s) Linv^T E
@@ -2067,7 +2143,8 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     h.ldc = b;
     CK(gemm<double>(h, st, c->ws));
     CK(symmetrize(c->Hp, b, b, st));
-    CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
+    CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
     c->last_sweeps += sweeps;
     GemmDesc<double> t;
     t.M = b;
@@ -2093,7 +2170,8 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     return CHFSI_ERR_NOT_SPD;
   }
   // SVQB on the scaled Gram matrix kept in c->Linv (same reading as rayleigh_ritz_svqb)
-  CK(syev_jacobi(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  CK(syev_jacobi(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -2146,7 +2224,8 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, b, k, st));
-  CK(syev_jacobi(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps));
+  CK(syev_jacobi(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
     GemmDesc<double> g;
@@ -2241,6 +2320,7 @@ chfsi_status estimate_bounds(chfsi_ctx* c, const double* v0_user, int steps, Lan
       return gemm<double>(g, st, c->ws);
     }
     if (op.kind == CHFSI_OP_STENCIL27) return stencil_apply_f64(op, x, n, y, n, 1, st);
+    if (op.kind == CHFSI_OP_CSR) return csr_apply_f64(csr_of(c, op, false), x, n, y, n, 1, st);
     return hipErrorInvalidValue;
   };
   LanczosOps ops;
@@ -2365,12 +2445,20 @@ size_t chfsi_workspace_bytes(const chfsi_operator* A, const chfsi_operator* B,
 void chfsi_destroy(chfsi_ctx* c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
-  for (void* p : c->allocs) hipFree(p);
-  if (c->h_w) hipHostFree(c->h_w);
-  if (c->h_norms) hipHostFree(c->h_norms);
-  if (c->h_flags) hipHostFree(c->h_flags);
-  if (c->h_stage) hipHostFree(c->h_stage);
-  if (c->h_lz) hipHostFree(c->h_lz);
+  for (void* p : c->allocs) {
+    if (c->al)
+      c->al->dev_free(c->al->self, p);
+    else
+      hipFree(p);
+  }
+  for (void* h : {static_cast<void*>(c->h_w), static_cast<void*>(c->h_norms),
+                  static_cast<void*>(c->h_flags), c->h_stage, static_cast<void*>(c->h_lz)}) {
+    if (!h) continue;
+    if (c->al)
+      c->al->host_free(c->al->self, h);
+    else
+      hipHostFree(h);
+  }
   for (auto& e : c->ev)
     if (e) hipEventDestroy(e);
   if (c->ev_stage) hipEventDestroy(c->ev_stage);
@@ -2381,6 +2469,15 @@ void chfsi_destroy(chfsi_ctx* c) {
 
 chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_operator* B,
                           const double* d_inv, const chfsi_params* params, void* stream) {
+  return chfsi::create_with_allocator(out, A, B, d_inv, params, stream, nullptr);
+}
+
+}  // extern "C"
+
+chfsi_status chfsi::create_with_allocator(chfsi_ctx** out, const chfsi_operator* A,
+                                          const chfsi_operator* B, const double* d_inv,
+                                          const chfsi_params* params, void* stream,
+                                          const Allocator* al) {
   if (!out) {
     set_error("out must be non-null");
     return CHFSI_ERR_ARG;
@@ -2393,11 +2490,12 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     set_error("filter bounds must be finite or NaN (NaN: estimated)");
     return CHFSI_ERR_ARG;
   }
-  if (params->lanczos_steps < 0) {
-    set_error("lanczos_steps must be >= 0");
+  if (params->lanczos_steps < 0 || params->stall_iters < 0) {
+    set_error("lanczos_steps and stall_iters must be >= 0");
     return CHFSI_ERR_ARG;
   }
   chfsi_ctx* c = new chfsi_ctx();
+  c->al = al;
   c->stream = static_cast<hipStream_t>(stream);
   hipGetDevice(&c->device);
   c->A = *A;
@@ -2519,8 +2617,11 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
     c->bf_c = ctx_alloc<char>(c, sp.bfblk, &st);
   }
   if (!c->cplx) {
-  if (!dense && params->filter_prec != CHFSI_PREC_FP64 && A->field_mode != 0)
+  if (A->kind == CHFSI_OP_STENCIL27 && params->filter_prec != CHFSI_PREC_FP64 &&
+      A->field_mode != 0)
     c->Vf = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+  if (A->kind == CHFSI_OP_CSR && params->filter_prec != CHFSI_PREC_FP64)
+    c->val32 = ctx_alloc<float>(c, size_t(std::max<int64_t>(A->nnz, 1)) * sizeof(float), &st);
   if (params->binv_exact) c->Ht = ctx_alloc<double>(c, size_t(n) * n * sizeof(double), &st);
   c->coef_cap = params->degree;
   c->coef32 = ctx_alloc<float>(c, size_t(params->degree) * b * sizeof(float), &st);
@@ -2565,11 +2666,18 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   c->h_stage_bytes = b * sizeof(double) + size_t(params->degree) * (c->cplx ? 2 : 1) * b *
                                                 sizeof(double) + 64;
   const int64_t hb = c->cplx ? 2 * b : b;
-  if (hipHostMalloc(&c->h_w, hb * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(&c->h_norms, hb * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->h_flags), 64) != hipSuccess ||
-      hipHostMalloc(&c->h_stage, c->h_stage_bytes) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->h_lz), 64) != hipSuccess) {
+  auto pinned = [c](void** p, size_t bytes) -> bool {
+    if (c->al) {
+      *p = c->al->host_alloc(c->al->self, bytes);
+      return *p != nullptr;
+    }
+    return hipHostMalloc(p, bytes) == hipSuccess;
+  };
+  if (!pinned(reinterpret_cast<void**>(&c->h_w), hb * sizeof(double)) ||
+      !pinned(reinterpret_cast<void**>(&c->h_norms), hb * sizeof(double)) ||
+      !pinned(reinterpret_cast<void**>(&c->h_flags), 64) ||
+      !pinned(&c->h_stage, c->h_stage_bytes) ||
+      !pinned(reinterpret_cast<void**>(&c->h_lz), 64)) {
     set_error("pinned host allocation failed");
     chfsi_destroy(c);
     return CHFSI_ERR_NOMEM;
@@ -2621,12 +2729,37 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
       e = fill_ones_f32(c->dinv32, n, c->stream);
   }
   if (e == hipSuccess && c->Vf) e = convert_f64_f32(A->field, n, c->Vf, n, n, 1, c->stream);
+  // CSR operators: structure check, longest rows, FP32 values
+  for (int which = 0; which < 2 && e == hipSuccess; ++which) {
+    const chfsi_operator& op = which == 0 ? c->A : c->B;
+    if (op.kind != CHFSI_OP_CSR) continue;
+    int kmax = 0;
+    const hipError_t ce = csr_check(op, c->dflags, c->h_flags, &kmax, c->stream);
+    if (ce == hipErrorInvalidValue) {
+      set_error("CSR %s: invalid structure (rowptr must start at 0, not decrease and end at nnz; "
+                "column indices must lie in [0, n))", which == 0 ? "A" : "B");
+      chfsi_destroy(c);
+      return CHFSI_ERR_ARG;
+    }
+    e = ce;
+    (which == 0 ? c->csrA_kmax : c->csrB_kmax) = kmax;
+  }
+  if (e == hipSuccess && c->val32 && A->nnz > 0)
+    e = convert_f64_f32(A->val, A->nnz, c->val32, A->nnz, A->nnz, 1, c->stream);
   if (e == hipSuccess && (A->kind == CHFSI_OP_STENCIL27 || c->bloch)) e = stencil_check(*A);
   if (e == hipSuccess && c->Ht) {
     const chfsi_status fs = form_exact_operator(c, A, B);
     if (fs != CHFSI_OK) {
       chfsi_destroy(c);
       return fs;
+    }
+  }
+  if (e == hipSuccess && params->keep_best) {
+    chfsi_status ks = CHFSI_OK;
+    c->Xbest = ctx_alloc<double>(c, size_t(n) * (c->cplx ? 2 : 1) * b * sizeof(double), &ks);
+    if (ks != CHFSI_OK) {
+      chfsi_destroy(c);
+      return ks;
     }
   }
   if (e == hipSuccess && std::isnan(params->lambda_max)) {
@@ -2646,6 +2779,8 @@ chfsi_status chfsi_create(chfsi_ctx** out, const chfsi_operator* A, const chfsi_
   *out = c;
   return CHFSI_OK;
 }
+
+extern "C" {
 
 chfsi_status chfsi_filter(chfsi_ctx* c, const double* X, int64_t ldx, const double* ritz,
                           const double* resid, int64_t ldr, double* Yp, int64_t ldy, double lmin,
@@ -2790,6 +2925,7 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   c->last_sweeps = 0;
   c->svqb_events = 0;
   c->svqb_dropped = 0;
+  c->flags = 0;
   const bool slabs = c->prm.memory_mode == 1;
   double* Xw = slabs ? X : c->Xw;            // working Ritz block
   const int64_t ldw = slabs ? ldx : n;
@@ -2810,6 +2946,18 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   };
   double mr = maxres();
   r.history[0] = mr;
+  // lowest max residual so far (and, with keep_best, its pairs)
+  double best = mr;
+  int best_it = 0;
+  std::vector<double> best_ritz, best_norms;
+  auto keep = [&]() -> chfsi_status {
+    if (!c->Xbest) return CHFSI_OK;
+    CK(copy_block(Xw, c->cplx ? 2 * ldw : ldw, c->Xbest, ldn, rows, b, c->stream));
+    best_ritz = ritz;
+    best_norms = norms;
+    return CHFSI_OK;
+  };
+  if ((st = keep()) != CHFSI_OK) return st;
   int it = 0;
   for (; it < c->prm.max_iter && !(mr < c->prm.tol); ++it) {
     if (c->cancel && c->cancel->load()) {
@@ -2858,6 +3006,20 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
     }
     mr = maxres();
     if (it + 1 < CHFSI_MAX_HISTORY) r.history[it + 1] = mr;
+    if (mr < best) {
+      best = mr;
+      best_it = it + 1;
+      if ((st = keep()) != CHFSI_OK) break;
+    } else if (c->prm.stall_iters > 0 && it + 1 - best_it >= c->prm.stall_iters &&
+               !(mr < c->prm.tol)) {
+      // stagnation: no new lowest max residual for stall_iters passes
+      c->flags |= 4;
+      ++it;
+      if (progress_log())
+        std::fprintf(stderr, "chfsi_solve: stagnation after %d iterations (best %.3e at %d)\n",
+                     it, best, best_it);
+      break;
+    }
     if (progress_log())
       std::fprintf(stderr,
                    "chfsi_solve: iteration %d, max residual %.3e (filter %.1f ms, RR %.1f ms, "
@@ -2867,7 +3029,16 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   r.iterations = it;
   r.max_residual = mr;
   r.converged = mr < c->prm.tol;
+  r.best_iteration = best_it;
+  r.best_residual = best;
   r.flags = c->flags;
+  if (st == CHFSI_OK && !r.converged && c->Xbest && best_it != it) {
+    // CHFSI_ERR_NOCONV with keep_best: return the pairs of the lowest max residual
+    CK(copy_block(c->Xbest, ldn, Xw, c->cplx ? 2 * ldw : ldw, rows, b, c->stream));
+    ritz = best_ritz;
+    norms = best_norms;
+    r.max_residual = best;
+  }
   r.svqb_events = c->svqb_events;
   r.svqb_dropped = c->svqb_dropped;
   if (st != CHFSI_OK && st != CHFSI_ERR_NOCONV) return st;

@@ -11,10 +11,12 @@
 // embarrassingly parallel, (ii) it converges quadratically when the matrix is
 // nearly diagonal -- which is what the projected matrix becomes as subspace
 // iteration converges -- and (iii) it is accurate to a small multiple of the
-// unit roundoff.  The block variant pairs 32-wide column blocks in a
-// round-robin tournament, diagonalises every 64 x 64 pair subproblem fully in
-// LDS (one workgroup each), and applies the resulting orthogonal 64 x 64
-// factors to the rest of the matrix and to the eigenvector accumulator.
+// unit roundoff.  The block variant pairs JB-wide column blocks (JB = 16) in a
+// round-robin tournament, applies one inner sweep of rotations to every
+// JP x JP pair subproblem (JP = 2 JB = 32) in LDS (one workgroup each), and
+// applies the resulting orthogonal JP x JP factors to the rest of the matrix
+// and to the eigenvector accumulator with MFMA.  Sweeps repeat until no
+// rotation is applied or a cap of 40 sweeps is reached (then reported).
 #include "internal.h"
 
 #include <algorithm>
@@ -598,7 +600,8 @@ size_t syev_workspace_bytes(int64_t b) {
 }
 
 hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
-                       hipStream_t st, const Workspace& ws, int* sweeps_out) {
+                       hipStream_t st, const Workspace& ws, int* sweeps_out,
+                       int* unconverged_out) {
   const int64_t bp = jacobi_padded(b);
   const int nblk = int(bp / JB);     // even
   const int npairs = nblk / 2;
@@ -618,7 +621,9 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   k_fro_final<<<1, 64, 0, st>>>(scal + 16, scal);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tol = 1e-15;
-  const int max_outer = 40;
+  // sweep cap (knob CHFSI_JACOBI_MAX_SWEEPS, for tests of the cap's report)
+  int max_outer = 40;
+  if (const char* e = std::getenv("CHFSI_JACOBI_MAX_SWEEPS")) max_outer = std::max(1, std::atoi(e));
   // inner Jacobi sweeps per pair subproblem (one suffices for the block
   // method's convergence; the knob is for tuning)
   int inner = 1;
@@ -650,6 +655,8 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   k_jacobi_gather<<<grid_for(b * b), 256, 0, st>>>(Vp, bp, b, perm, V, ldv);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (sweeps_out) *sweeps_out = sweeps;
+  // the last sweep still rotated: the tolerance was not met within the cap
+  if (unconverged_out) *unconverged_out = host_count != 0 ? 1 : 0;
   return hipSuccess;
 }
 

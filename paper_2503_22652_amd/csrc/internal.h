@@ -14,6 +14,23 @@ struct chfsi_ctx;
 
 namespace chfsi {
 
+// Memory source of a context (the server's pools): device and pinned host
+// allocations; frees return memory to the source.  A context without one
+// allocates with hipMalloc / hipHostMalloc.
+struct Allocator {
+  void* self = nullptr;
+  void* (*dev_alloc)(void* self, size_t bytes) = nullptr;
+  void (*dev_free)(void* self, void* p) = nullptr;
+  void* (*host_alloc)(void* self, size_t bytes) = nullptr;
+  void (*host_free)(void* self, void* p) = nullptr;
+};
+// chfsi_create with every allocation of the context drawn from `al`
+// (chfsi_destroy returns it there).
+chfsi_status create_with_allocator(chfsi_ctx** out, const chfsi_operator* A,
+                                   const chfsi_operator* B, const double* d_inv,
+                                   const chfsi_params* params, void* stream,
+                                   const Allocator* al);
+
 // Sets the calling thread's message returned by chfsi_last_error().
 void set_error_message(const char* msg);
 
@@ -280,9 +297,12 @@ hipError_t trsm_lower_left(const double* L, int64_t ldl, double* X, int64_t ldx,
                            bool inverses_ready);
 // Symmetric eigensolver (parallel block Jacobi).  A (b x b) is destroyed.
 // w: ascending eigenvalues (device, b); V: eigenvectors (device, b x b, ldv).
-// scratch from ws; sweeps reported through *sweeps_out (host) if non-null.
+// scratch from ws; sweeps reported through *sweeps_out (host) if non-null;
+// *unconverged_out (host, if non-null) = 1 when the sweep cap was reached with
+// rotations still being applied (the result is then not fully diagonalised).
 hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
-                       hipStream_t st, const Workspace& ws, int* sweeps_out);
+                       hipStream_t st, const Workspace& ws, int* sweeps_out,
+                       int* unconverged_out = nullptr);
 size_t syev_workspace_bytes(int64_t b);
 size_t potrf_workspace_bytes(int64_t b);
 

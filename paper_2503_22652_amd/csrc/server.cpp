@@ -17,12 +17,15 @@
 //    has its own scratch), so its result is bitwise identical either way.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <map>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -57,6 +60,92 @@ struct Seq {
   bool busy = false;
 };
 
+// First-fit pool over large chunks (device memory from hipMalloc, or pinned
+// host memory from hipHostMalloc), so that a running server makes no
+// allocation or free call per request: a chunk is added only when no free
+// range fits (the first requests of each new size), and chunks are released
+// only by the server's destruction.  hipFree, the call avoided, synchronises
+// the whole device.  Ranges are 256-byte aligned; freed ranges merge with
+// their free neighbours.
+class Pool {
+ public:
+  Pool(bool host, size_t chunk_min) : host_(host), chunk_min_(chunk_min) {}
+  ~Pool() {
+    for (auto& c : chunks_) {
+      if (host_)
+        (void)hipHostFree(c.base);
+      else
+        (void)hipFree(c.base);
+    }
+  }
+  void* alloc(size_t bytes) {
+    bytes = std::max<size_t>(256, (bytes + 255) / 256 * 256);
+    std::lock_guard<std::mutex> lk(mu_);
+    for (size_t ci = 0; ci < chunks_.size(); ++ci) {
+      auto& fr = chunks_[ci].free;
+      for (auto it = fr.begin(); it != fr.end(); ++it) {
+        if (it->second < bytes) continue;
+        const size_t off = it->first, len = it->second;
+        fr.erase(it);
+        if (len > bytes) fr[off + bytes] = len - bytes;
+        char* p = chunks_[ci].base + off;
+        live_[p] = {ci, bytes};
+        return p;
+      }
+    }
+    const size_t sz = std::max(bytes, chunk_min_);
+    void* base = nullptr;
+    const hipError_t e = host_ ? hipHostMalloc(&base, sz) : hipMalloc(&base, sz);
+    if (e != hipSuccess) return nullptr;
+    ++grow_events_;
+    Chunk c;
+    c.base = static_cast<char*>(base);
+    c.size = sz;
+    if (sz > bytes) c.free[bytes] = sz - bytes;
+    chunks_.push_back(std::move(c));
+    live_[static_cast<char*>(base)] = {chunks_.size() - 1, bytes};
+    return base;
+  }
+  void free(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = live_.find(static_cast<char*>(p));
+    if (it == live_.end()) return;
+    const size_t ci = it->second.first, len = it->second.second;
+    live_.erase(it);
+    auto& fr = chunks_[ci].free;
+    size_t off = size_t(static_cast<char*>(p) - chunks_[ci].base), n = len;
+    auto nx = fr.lower_bound(off);
+    if (nx != fr.end() && nx->first == off + n) {   // merge with the next free range
+      n += nx->second;
+      nx = fr.erase(nx);
+    }
+    if (nx != fr.begin()) {                          // and with the previous one
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        n += pv->second;
+        fr.erase(pv);
+      }
+    }
+    fr[off] = n;
+  }
+  int grow_events() const { return grow_events_; }
+
+ private:
+  struct Chunk {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free;   // offset -> length
+  };
+  bool host_;
+  size_t chunk_min_;
+  std::mutex mu_;
+  std::vector<Chunk> chunks_;
+  std::map<char*, std::pair<size_t, size_t>> live_;   // range start -> (chunk, length)
+  int grow_events_ = 0;
+};
+
 double clock_ms(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -77,6 +166,9 @@ struct chfsi_server {
   std::vector<hipStream_t> streams;
   uint64_t next_ticket = 1;
   bool stop = false;
+  // memory of every request (contexts, blocks) and of the sequences' warm starts
+  std::unique_ptr<Pool> dev_pool, host_pool;
+  chfsi::Allocator al{};
 };
 
 namespace {
@@ -89,12 +181,27 @@ size_t block_bytes(const chfsi_request& r) {
   return size_t(r.A.n) * size_t(r.params.block) * sizeof(double) * (cplx ? 2 : 1);
 }
 
-size_t footprint_of(const chfsi_request& r, bool new_seq) {
+// device bytes a running request holds (released when it finishes): its
+// context's workspace and its working block.  A sequence's warm-start block
+// is charged separately, from its allocation until it is replaced or the
+// server is destroyed.
+size_t footprint_of(const chfsi_request& r) {
   const chfsi_operator* B = r.B.kind == CHFSI_OP_IDENTITY ? nullptr : &r.B;
   const size_t ws = chfsi_workspace_bytes(&r.A, B, &r.params);
   if (ws == 0) return 0;
+  return ws + block_bytes(r);
+}
+
+// the warm-start block a finished request of this sequence will need to
+// (re)allocate: 0 when the sequence already holds one of the right size
+size_t seq_growth(chfsi_server* s, const chfsi_request& r) {
+  if (r.seq_id < 0) return 0;
+  auto f = s->seqs.find(r.seq_id);
   const size_t blk = block_bytes(r);
-  return ws + blk + (new_seq ? blk : 0);
+  if (f == s->seqs.end() || !f->second.X) return blk;
+  return f->second.bytes == blk && f->second.n == r.A.n && f->second.b == r.params.block
+             ? 0
+             : blk;
 }
 
 // pick the first admissible pending request; called with the lock held
@@ -102,23 +209,18 @@ Req* pick(chfsi_server* s) {
   for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
     Req* q = *it;
     const int64_t sid = q->r.seq_id;
-    bool new_seq = true;
     if (sid >= 0) {
       auto f = s->seqs.find(sid);
-      if (f != s->seqs.end()) {
-        if (f->second.busy) continue;   // predecessor still running
-        new_seq = f->second.X == nullptr;
-      }
+      if (f != s->seqs.end() && f->second.busy) continue;   // predecessor still running
       // an earlier pending request of the same sequence goes first
       bool earlier = false;
       for (auto jt = s->pending.begin(); jt != it; ++jt)
         if ((*jt)->r.seq_id == sid) earlier = true;
       if (earlier) continue;
     }
-    const size_t need = footprint_of(q->r, new_seq);
-    if (s->used + need > s->budget) continue;
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b) continue;
+    const size_t need = footprint_of(q->r);
+    // room for the request and for a (re)allocated warm-start block of its sequence
+    if (s->used + need + seq_growth(s, q->r) > s->budget) continue;
     q->footprint = need;
     s->used += need;
     s->pending.erase(it);
@@ -142,7 +244,8 @@ void run_one(chfsi_server* s, Req* q, hipStream_t stream) {
     seq = &s->seqs[r.seq_id];
   }
   do {
-    if (hipMalloc(&X, blk) != hipSuccess) {
+    X = static_cast<double*>(s->dev_pool->alloc(blk));
+    if (!X) {
       st = CHFSI_ERR_NOMEM;
       break;
     }
@@ -161,7 +264,7 @@ void run_one(chfsi_server* s, Req* q, hipStream_t stream) {
       }
     }
     prm.init_random = (!warm && !r.X0) ? 1 : 0;
-    st = chfsi_create(&ctx, &r.A, B, r.d_inv, &prm, stream);
+    st = chfsi::create_with_allocator(&ctx, &r.A, B, r.d_inv, &prm, stream, &s->al);
     if (st != CHFSI_OK) break;
     chfsi::ctx_set_cancel_flag(ctx, &q->cancel_flag);
     q->evals.assign(b, 0.0);
@@ -173,12 +276,17 @@ void run_one(chfsi_server* s, Req* q, hipStream_t stream) {
     if (st == CHFSI_OK || st == CHFSI_ERR_NOCONV) {
       if (seq) {
         if (!seq->X || seq->n != n || seq->b != b || seq->bytes != blk) {
-          if (seq->X) hipFree(seq->X);
-          seq->X = nullptr;
-          if (hipMalloc(&seq->X, blk) != hipSuccess) seq->X = nullptr;
+          // (re)place the warm-start block and move its charge in the budget
+          std::lock_guard<std::mutex> lk(s->mu);
+          if (seq->X) {
+            s->dev_pool->free(seq->X);
+            s->used -= seq->bytes;
+          }
+          seq->X = static_cast<double*>(s->dev_pool->alloc(blk));
           seq->n = n;
           seq->b = b;
-          seq->bytes = blk;
+          seq->bytes = seq->X ? blk : 0;
+          s->used += seq->bytes;
         }
         if (seq->X) hipMemcpyAsync(seq->X, X, blk, hipMemcpyDeviceToDevice, stream);
       }
@@ -188,7 +296,10 @@ void run_one(chfsi_server* s, Req* q, hipStream_t stream) {
   } while (false);
   if (st != CHFSI_OK) g_srv_err = chfsi_last_error();
   if (ctx) chfsi_destroy(ctx);
-  if (X) hipFree(X);
+  if (X) {
+    hipStreamSynchronize(stream);   // the pool may hand X to another slot next
+    s->dev_pool->free(X);
+  }
   q->status = st;
 }
 
@@ -234,6 +345,20 @@ chfsi_status chfsi_server_create(chfsi_server** out, const chfsi_server_config* 
     return CHFSI_ERR_DEVICE;
   }
   s->budget = cfg->memory_budget ? cfg->memory_budget : size_t(0.9 * double(free_b));
+  // device chunks of at least 1 GiB (or a fifth of the budget, if smaller),
+  // pinned host chunks of 4 MiB
+  s->dev_pool.reset(new Pool(false, std::min<size_t>(size_t(1) << 30,
+                                                     std::max<size_t>(s->budget / 5, 1 << 20))));
+  s->host_pool.reset(new Pool(true, size_t(4) << 20));
+  s->al.self = s;
+  s->al.dev_alloc = [](void* self, size_t bytes) -> void* {
+    return static_cast<chfsi_server*>(self)->dev_pool->alloc(bytes);
+  };
+  s->al.dev_free = [](void* self, void* p) { static_cast<chfsi_server*>(self)->dev_pool->free(p); };
+  s->al.host_alloc = [](void* self, size_t bytes) -> void* {
+    return static_cast<chfsi_server*>(self)->host_pool->alloc(bytes);
+  };
+  s->al.host_free = [](void* self, void* p) { static_cast<chfsi_server*>(self)->host_pool->free(p); };
   for (int i = 0; i < cfg->slots; ++i) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -250,7 +375,7 @@ chfsi_status chfsi_server_create(chfsi_server** out, const chfsi_server_config* 
 
 chfsi_status chfsi_submit(chfsi_server* s, const chfsi_request* req, uint64_t* ticket) {
   if (!s || !req || !ticket) return CHFSI_ERR_ARG;
-  const size_t need = footprint_of(*req, true);
+  const size_t need = footprint_of(*req) + (req->seq_id >= 0 ? block_bytes(*req) : 0);
   if (need == 0) return CHFSI_ERR_ARG;
   Req* q = new Req();
   q->r = *req;
@@ -345,6 +470,19 @@ void chfsi_result_free(chfsi_result* res) {
   res->resnorms = nullptr;
 }
 
+chfsi_status chfsi_server_stats(chfsi_server* s, chfsi_server_stats_t* out) {
+  if (!s || !out) return CHFSI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->budget = s->budget;
+  out->used = s->used;
+  out->device_pool_chunks = s->dev_pool->grow_events();
+  out->host_pool_chunks = s->host_pool->grow_events();
+  size_t seq_bytes = 0;
+  for (auto& kv : s->seqs) seq_bytes += kv.second.bytes;
+  out->sequence_bytes = seq_bytes;
+  return CHFSI_OK;
+}
+
 void chfsi_server_destroy(chfsi_server* s) {
   if (!s) return;
   {
@@ -360,10 +498,10 @@ void chfsi_server_destroy(chfsi_server* s) {
   s->cv_done.notify_all();
   for (auto& t : s->workers) t.join();
   for (auto& kv : s->seqs)
-    if (kv.second.X) hipFree(kv.second.X);
+    if (kv.second.X) s->dev_pool->free(kv.second.X);
   for (auto& kv : s->reqs) delete kv.second;
   for (auto st : s->streams) hipStreamDestroy(st);
-  delete s;
+  delete s;   // the pools release their chunks
 }
 
 }  // extern "C"

@@ -1,4 +1,5 @@
-// Internal interface of the periodic 27-point grid operator kernels.
+// Internal interface of the operator kernels other than the dense GEMM: the
+// periodic 27-point grid operators and the sparse (CSR) operators.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -93,6 +94,44 @@ hipError_t stencil_residual_f64(const chfsi_operator& A, const chfsi_operator* B
                                 hipStream_t st);
 // true when the z-marching class-sum kernels apply (tensor-product coefficients)
 bool stencil_separable(const chfsi_operator& op);
+
+// ---------------------------------------------------------------------------
+// Sparse symmetric operators in CSR form (csr.hip).  val is double for the
+// FP64 kernels and float (the context's copy) for the FP32 / BF16 ones; kmax
+// is the longest row.
+// ---------------------------------------------------------------------------
+struct CsrMat {
+  int64_t n = 0;
+  const int64_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const void* val = nullptr;
+  int kmax = 0;
+};
+// Validates the structure of op (rowptr[0] = 0, non-decreasing, rowptr[n] =
+// nnz, column indices in [0, n)) and returns its longest row in *kmax;
+// flags_dev: 2 device ints of scratch, flags_host: 2 pinned host ints.
+// Synchronises the stream.  hipErrorInvalidValue: invalid structure.
+hipError_t csr_check(const chfsi_operator& op, int* flags_dev, int* flags_host, int* kmax,
+                     hipStream_t st);
+// Y = A X (FP64), column-major n x b blocks
+hipError_t csr_apply_f64(const CsrMat& A, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                         int64_t b, hipStream_t st);
+// residual-filter step (ld n): RX <- alpha A (dinv .* RY) + beta RY + gamma RX
+//                                    + delta colcoef[j] Yf
+hipError_t csr_rchfsi_step_f64(const CsrMat& A, const double* dinv, const double* RY, double* RX,
+                               const double* Yf, int64_t ldf, const double* colcoef,
+                               StencilStep s, int64_t b, hipStream_t st);
+hipError_t csr_rchfsi_step_f32(const CsrMat& A32, const float* dinv, const float* RY, float* RX,
+                               const float* Yf, const float* colcoef, StencilStep s, int64_t b,
+                               hipStream_t st);
+// bfloat16-stored blocks, FP32 arithmetic
+hipError_t csr_rchfsi_step_bf16(const CsrMat& A32, const float* dinv, const void* RY, void* RX,
+                                const void* Yf, const float* colcoef, StencilStep s, int64_t b,
+                                hipStream_t st);
+// plain-filter step: dst <- alpha dinv .* (A src) + beta src + gamma prev (prev may be null)
+hipError_t csr_chfsi_step_f64(const CsrMat& A, const double* dinv, const double* src,
+                              int64_t lds, const double* prev, int64_t ldp, double* dst,
+                              StencilStep s, int64_t b, hipStream_t st);
 
 // BF16 block helpers
 hipError_t rchfsi_init_bf16(const double* R, int64_t ldr, int64_t n, int64_t b, double scale,

@@ -303,3 +303,49 @@ def test_chfsi_exact_inverse_filter_and_solve():
     print("exact-inverse ChFSI solve:", rep["iterations"], "iterations", rep["max_residual"])
     assert st == P.OK
     np.testing.assert_allclose(ev[:32], w[:32], rtol=0, atol=1e-10 * np.max(np.abs(w[:32])))
+
+
+def test_stagnation_stops_early_and_returns_best_pairs():
+    """ChFSI with D^{-1} != B^{-1} stalls (Theorem 3.2).  With stall_iters the
+    solve stops once the max residual has not reached a new low for that many
+    passes (report flags bit 2, CHFSI_ERR_NOCONV), and with keep_best the
+    returned pairs are those of the lowest max residual: their residuals,
+    recomputed on the CPU, are the reported ones."""
+    p = wl.dense_generalized(n=1536, n_low=48, block=64, degree=20, seed=1001)
+    w = sla.eigvalsh(p.A, p.B)
+    params = P.make_params(48, 64, 20, max_iter=60, tol=1e-9, method=P.METHOD_CHFSI,
+                           filter_prec=P.PREC_FP64, lambda_max=float(w[-1]) + 0.5,
+                           stall_iters=4, keep_best=1)
+    ctx = _ctx(p, params)
+    Xd = dev(wl.random_block(p.n, p.block, 2001))
+    st, ev, rn, rep = P.chfsi_solve(ctx, Xd)
+    print(rep["iterations"], rep["best_iteration"], rep["best_residual"],
+          ["%.2e" % h for h in rep["history"]])
+    assert st == P.ERR_NOCONV
+    assert rep["flags"] & 4
+    assert rep["iterations"] < 60
+    assert rep["iterations"] - rep["best_iteration"] >= 4
+    hist = rep["history"]
+    assert rep["best_residual"] == min(hist)
+    assert rep["max_residual"] == rep["best_residual"]
+    X = host(Xd)
+    ev = np.asarray(ev)
+    rcpu = np.linalg.norm(p.A @ X[:, :48] - (p.B @ X[:, :48]) * ev[None, :48], axis=0)
+    np.testing.assert_allclose(rcpu, np.asarray(rn[:48]), rtol=1e-6, atol=1e-12)
+    assert abs(rcpu.max() - rep["best_residual"]) <= 1e-6 * rep["best_residual"]
+
+
+def test_jacobi_sweep_cap_is_reported(monkeypatch):
+    """An eigensolve stopped by its sweep cap (forced to 1 sweep here) with
+    rotations still pending raises report flags bit 1."""
+    p = wl.dense_generalized(n=512, n_low=16, block=40, degree=8, seed=1001)
+    w = sla.eigvalsh(p.A, p.B)
+    params = P.make_params(16, 40, 8, max_iter=1, tol=1e-12, method=P.METHOD_RCHFSI,
+                           filter_prec=P.PREC_FP64, lambda_max=float(w[-1]) + 0.5)
+    ctx = _ctx(p, params)
+    monkeypatch.setenv("CHFSI_JACOBI_MAX_SWEEPS", "1")
+    st, ev, rn, rep = P.chfsi_solve(ctx, dev(wl.random_block(p.n, 40, 7)))
+    assert rep["flags"] & 2
+    monkeypatch.delenv("CHFSI_JACOBI_MAX_SWEEPS")
+    st, ev, rn, rep = P.chfsi_solve(ctx, dev(wl.random_block(p.n, 40, 7)))
+    assert not rep["flags"] & 2

@@ -191,3 +191,39 @@ def test_complex_requests_through_the_server():
         lam = np.array(r["evals"][:6])
         assert np.linalg.norm(X.conj().T @ Bd @ X - np.eye(6)) <= 1e-9
         assert np.max(np.linalg.norm(Ad @ X - Bd @ X * lam[None, :], axis=0)) < 1e-9
+
+
+def test_budget_accounting_and_steady_state_pools():
+    """The budget charges each running request its workspace and block, and each
+    sequence its warm-start block for as long as the sequence holds it.  With a
+    budget that fits one running request plus both sequences' blocks, the two
+    sequences' first requests run one after the other and the charge left when
+    the server is idle is exactly the two warm-start blocks.  Later requests of
+    the same sizes draw everything from the pools: no new chunk is allocated."""
+    p = wl.dense_generalized(n=512, n_low=16, block=20, degree=12, seed=60)
+    w = sla.eigvalsh(p.A, p.B)
+    lmax = float(w[-1]) + 0.5
+    req0, keep0 = _request(p, lmax, seq_id=1)
+    ws = P.chfsi_workspace_bytes(req0.A, req0.B, req0.params)
+    blk = p.n * p.block * 8
+    budget = ws + blk + 2 * blk + 4096
+    srv = P.Server(slots=2, memory_budget=budget)
+    rs = []
+    for sid in (1, 2):
+        req, keep = _request(p, lmax, seq_id=sid, X0=wl.random_block(p.n, p.block, 70 + sid))
+        rs.append(srv.submit(req, keep))
+    out = [srv.wait(t) for t in rs]
+    assert all(o["status"] == P.OK for o in out)
+    # one after the other: the second starts when the first has finished
+    assert out[1]["start_ms"] >= out[0]["finish_ms"] or out[0]["start_ms"] >= out[1]["finish_ms"]
+    st = srv.stats()
+    assert st["used"] == 2 * blk and st["sequence_bytes"] == 2 * blk
+    chunks = (st["device_pool_chunks"], st["host_pool_chunks"])
+    for t in range(3):                       # warm-started requests of both sequences
+        ts = [srv.submit(*_request(p, lmax, seq_id=sid)) for sid in (1, 2)]
+        for tk in ts:
+            assert srv.wait(tk)["status"] == P.OK
+    st2 = srv.stats()
+    assert st2["used"] == 2 * blk
+    assert (st2["device_pool_chunks"], st2["host_pool_chunks"]) == chunks
+    srv.close()

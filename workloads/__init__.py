@@ -435,6 +435,77 @@ def stencil_problem(grid: int = 128, n_wells: int = 64, n_wanted: int = 1000, bl
 
 
 # ----------------------------------------------------------------------------
+# sparse (CSR) pencils
+# ----------------------------------------------------------------------------
+
+def grid_pencil_csr(shape, coef_A: np.ndarray, coef_B: np.ndarray, V: np.ndarray,
+                    field_mode: int):
+    """The periodic 27-point grid pencil (A, B) assembled as scipy CSR matrices.
+
+    Entry (i, j) of a stencil operator is the coefficient of the offset from
+    grid point i to grid point j (periodic wrap; offsets that wrap onto the
+    same point on grids of width 1 or 2 add up).  The potential term: field_mode
+    1 adds V_i on the diagonal, field_mode 2 adds B_ij (V_i + V_j) / 2."""
+    import scipy.sparse as sp
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    idx = np.arange(n).reshape(nz, ny, nx)
+
+    def assemble(coef):
+        rows, cols, vals = [], [], []
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    c = coef[dz + 1, dy + 1, dx + 1]
+                    if c == 0.0:
+                        continue
+                    nb = np.roll(idx, shift=(-dz, -dy, -dx), axis=(0, 1, 2))
+                    rows.append(idx.reshape(-1))
+                    cols.append(nb.reshape(-1))
+                    vals.append(np.full(n, c))
+        M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(n, n)).tocsr()
+        M.sum_duplicates()
+        return M
+
+    A, B = assemble(coef_A), assemble(coef_B)
+    v = np.asarray(V, dtype=np.float64).reshape(-1)
+    if field_mode == 1:
+        A = A + sp.diags(v)
+    elif field_mode == 2:
+        A = A + 0.5 * (sp.diags(v) @ B + B @ sp.diags(v))
+    A, B = A.tocsr(), B.tocsr()
+    A.sort_indices()
+    B.sort_indices()
+    return A, B
+
+
+def random_sparse_pencil(n: int, per_row: int, long_rows: int, long_len: int, seed: int):
+    """A random symmetric sparse A (about per_row entries per row plus `long_rows`
+    rows and columns of `long_len` entries, values N(0,1), diagonal N(0,1) + 2)
+    and an SPD diagonally dominant sparse B = I + 0.05 S (S symmetric, random
+    pattern); CSR, sorted indices.  D^{-1} = 1 / diag(B)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    r = rng.integers(0, n, n * per_row // 2)
+    c = rng.integers(0, n, n * per_row // 2)
+    lr = rng.choice(n, long_rows, replace=False)
+    r = np.concatenate([r, np.repeat(lr, long_len)])
+    c = np.concatenate([c, rng.integers(0, n, long_rows * long_len)])
+    G = sp.coo_matrix((rng.standard_normal(r.size), (r, c)), shape=(n, n)).tocsr()
+    A = (0.5 * (G + G.T) + sp.diags(rng.standard_normal(n) + 2.0)).tocsr()
+    r2 = rng.integers(0, n, 2 * n)
+    c2 = rng.integers(0, n, 2 * n)
+    H = sp.coo_matrix((rng.uniform(-1.0, 1.0, r2.size), (r2, c2)), shape=(n, n)).tocsr()
+    S = 0.5 * (H + H.T)
+    rowsum = np.asarray(abs(S).sum(axis=1)).reshape(-1)
+    B = (sp.eye(n) + 0.05 * (S + sp.diags(rowsum))).tocsr()
+    A.sort_indices()
+    B.sort_indices()
+    return A, B, 1.0 / B.diagonal()
+
+
+# ----------------------------------------------------------------------------
 # serving workload
 # ----------------------------------------------------------------------------
 
