@@ -312,6 +312,43 @@ chfsi_status chfsi_solve(chfsi_ctx* ctx, double* X, int64_t ldx, double* evals, 
  */
 chfsi_status chfsi_filter_kernel_time(chfsi_ctx* ctx, double* total_ms, int32_t* launches);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * residual filter of chfsi_filter (method CHFSI_METHOD_RCHFSI, filter_prec
+ * CHFSI_PREC_FP64) without a context and without any allocation.
+ *
+ * A: CHFSI_OP_DENSE (device, symmetric, ld >= n) or CHFSI_OP_STENCIL27
+ *    (any field_mode), borrowed for the call.  d_inv: device, length n, or
+ *    NULL for D^{-1} = I.  b: number of columns (b = 0: only binds the
+ *    scratch array on the current device and returns; do this once before a
+ *    stream capture).  X, resid (Y = A X - B X Lambda), Yp: device, n x b,
+ *    column-major (ld >= n); Yp may alias X.  ritz: DEVICE array of the b
+ *    Ritz values (unlike chfsi_filter, so that the call records no host
+ *    copy).  lmin < lT < lmax, degree p >= 1, stream: as chfsi_filter.
+ *    Result: Yp = D^{-1} R_Y + X diag(Lambda_Y) after p - 1 steps, computed by
+ *    the same kernels as chfsi_filter with an FP64 context.
+ *
+ * Every intermediate (the Lambda_Y table, R_X, R_Y, split-K partial sums)
+ * lives in one static device array of CHFSI_STATIC_SCRATCH_BYTES per GPU,
+ * held from its first use on that GPU until the process ends.  The
+ * call needs chfsi_filter_static_bytes(n, b, degree) of it and returns
+ * CHFSI_ERR_ARG, with a message, when that exceeds the maximum; split-K
+ * partials use what is left (fewer or no k-splits when little is).  The call
+ * makes no hipMalloc / hipFree or other allocating call; it is
+ * stream-ordered and asynchronous.  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (different streams or threads
+ * without ordering) race and give undefined results.
+ * Errors: CHFSI_ERR_ARG, CHFSI_ERR_DEVICE.
+ */
+#define CHFSI_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+size_t chfsi_filter_static_bytes(int64_t n, int64_t b, int32_t degree);
+chfsi_status chfsi_filter_static(const chfsi_operator* A, const double* d_inv, int64_t b,
+                                 const double* X, int64_t ldx, const double* ritz,
+                                 const double* resid, int64_t ldr, double* Yp, int64_t ldy,
+                                 double lmin, double lmax, double lT, int32_t degree,
+                                 void* stream);
+
 /* Release the context and everything it owns (borrowed arrays untouched). */
 void chfsi_destroy(chfsi_ctx* ctx);
 

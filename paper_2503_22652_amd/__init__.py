@@ -103,6 +103,13 @@ _SIGNATURES = {
     "chfsi_estimate_bounds": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32,
                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]),
+    "chfsi_filter_static_bytes": (C.c_size_t, [C.c_int64, C.c_int64, C.c_int32]),
+    "chfsi_filter_static": (C.c_int, [C.POINTER(chfsi_operator), C.c_void_p, C.c_int64,
+                                      C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                      C.c_int32, C.c_void_p]),
+    "chfsi_filter_kernel_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_int32)]),
     "chfsi_last_error": (C.c_char_p, []),
     "chfsi_version": (C.c_char_p, []),
     "chfsi_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(chfsi_server_config)]),
@@ -315,6 +322,27 @@ def chfsi_filter(ctx: Context, X, ritz, resid, Yp, lmin: float, lmax: float, lT:
                             _ld(resid) if resid is not None else n, _ptr(Yp), _ld(Yp),
                             lmin, lmax, lT, degree)
     _check(st, "chfsi_filter")
+
+
+STATIC_SCRATCH_BYTES = 128 << 20
+
+
+def chfsi_filter_static_bytes(n: int, b: int, degree: int) -> int:
+    return int(lib().chfsi_filter_static_bytes(n, b, degree))
+
+
+def chfsi_filter_static(A: chfsi_operator, d_inv, X, ritz_d, resid, Yp, lmin: float, lmax: float,
+                        lT: float, degree: int, stream=None) -> None:
+    """FP64 residual filter that allocates nothing (a static device scratch array).
+    X/resid/Yp: float64 CUDA tensors (n x b, column-major); ritz_d: float64 CUDA
+    tensor of the b Ritz values.  X = None binds the scratch array only (b = 0)."""
+    b = 0 if X is None else X.shape[1]
+    n = A.n
+    st = lib().chfsi_filter_static(C.byref(A), _ptr(d_inv), b, _ptr(X), _ld(X) if X is not None else n,
+                                   _ptr(ritz_d), _ptr(resid), _ld(resid) if resid is not None else n,
+                                   _ptr(Yp), _ld(Yp) if Yp is not None else n, lmin, lmax, lT,
+                                   degree, _stream_handle(stream))
+    _check(st, "chfsi_filter_static")
 
 
 def chfsi_estimate_bounds(ctx: Context, v0=None, steps: int = 0):

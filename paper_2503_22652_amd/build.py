@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libchfsi.so")
 
 SOURCES = ["gemm.hip", "blas1.hip", "dense_small.hip", "stencil.hip", "complex.hip", "bloch.hip",
-           "lanczos.hip", "csr.hip", "chfsi.cpp", "server.cpp"]
+           "noalloc.hip", "lanczos.hip", "csr.hip", "chfsi.cpp", "server.cpp"]
 # Packed FP32 VALU instructions are disabled for every HIP compile.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
