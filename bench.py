@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "filter GFLOP/s + time-to-residual 1e-8, FP64 ChFSI vs FP32/BF16 R-ChFSI; p99 lat"
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the FP32 filter GEMM (64x64x32 tiles, split-K 8) at
 # N = 8192, b = 320: FETCH_SIZE and WRITE_SIZE from two rocprofv3 counter
@@ -35,6 +36,9 @@ PEAK_HBM_GBS = 8000.0
 # device copy (FETCH x 2.000, WRITE x 1.000); summary under profiles/.  Other
 # shapes report null.
 TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.4e6}
+# the same for the BF16-product step (operand rounding, product, split-K
+# reduction); null until its counter passes are taken
+TRAFFIC_BF16_FILTER_STEP = {}
 # the same for the BF16 z-march filter step on the 128^3 grid (block 1200) and
 # the 160^3 grid (block 2400)
 TRAFFIC_ZMARCH = {(128, 1200, "bf16"): 21.98e9, (160, 2400, "bf16"): 89.61e9}
@@ -59,6 +63,9 @@ def parse():
     ap.add_argument("--degree", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip time-to-residual runs")
+    ap.add_argument("--dense-prec", choices=("fp32", "bf16"), default="fp32",
+                    help="dense workload: precision of the timed residual-filter steps (the "
+                         "metric is quoted on FP32; bf16 times the bfloat16-product filter)")
     ap.add_argument("--no-grid", action="store_true",
                     help="dense workload: skip the 128^3 grid extra")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -87,6 +94,9 @@ def parse():
     ap.add_argument("--ttr-memory-mode", type=int, default=-1,
                     help="grid workload: force memory_mode of the reduced-precision "
                          "time-to-residual run (-1: by free memory)")
+    ap.add_argument("--ttr-escalate", type=int, default=0,
+                    help="grid workload: > 0 lets the BF16 time-to-residual run switch to FP32 "
+                         "after this many passes without a new lowest max residual")
     ap.add_argument("--fp64-panel", type=int, default=600,
                     help="grid workload: column panel for the FP64 R-ChFSI filter timing when "
                          "the full FP64 solve does not fit in device memory")
@@ -163,7 +173,9 @@ def main():
     # ------------------------------------------------------------------
     # timed steps: FP32 R-ChFSI outer iterations (filter + RR + residuals)
     # ------------------------------------------------------------------
-    ctx = ctx_for(P.METHOD_RCHFSI, P.PREC_FP32, profile=1)
+    dprec = P.PREC_BF16 if args.dense_prec == "bf16" else P.PREC_FP32
+    peak = PEAK_BF16_MFMA_TFLOPS if args.dense_prec == "bf16" else PEAK_FP32_MFMA_TFLOPS
+    ctx = ctx_for(P.METHOD_RCHFSI, dprec, profile=1)
     # lambda_max for the explicit filter calls: the library's Lanczos estimate
     torch.cuda.synchronize()
     t_b = time.perf_counter()
@@ -225,7 +237,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.dense_prec == "fp32" else "bf16 products, f32 blocks",
         "data": "synthetic",
         "config": {
             "workload": f"dense generalized A x = lambda B x, N={n}, block {b}, {nw} wanted, "
@@ -238,12 +250,16 @@ def main():
         "roofline": {
             "bound": "mfma",
             "achieved": round(achieved_tflops, 2),
-            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
-            "traffic": TRAFFIC_F32_FILTER_GEMM.get((n, b)),
+            "frac": round(achieved_tflops / peak, 4),
+            "traffic": (TRAFFIC_F32_FILTER_GEMM if args.dense_prec == "fp32"
+                        else TRAFFIC_BF16_FILTER_STEP).get((n, b)),
             "traffic_unit": "bytes per launch",
-            "kernel": "gemm_kernel<float> (FP32 residual-filter step, 2*N^2*b flops per launch)",
+            "kernel": ("gemm_kernel<float> + splitk_reduce4_kernel (FP32 residual-filter step, "
+                       "2*N^2*b flops per launch)") if args.dense_prec == "fp32" else
+                      ("k_scale_bf16 + gemm_bf16_kernel + splitk_reduce4_kernel (BF16-product "
+                       "residual-filter step, 2*N^2*b flops per launch)"),
             "ms_per_launch": round(per_launch_ms, 4),
         },
     }
@@ -584,6 +600,8 @@ def bench_grid(args):
                 continue
             pm = P.make_params(nw, b, p, max_iter=iters, tol=1e-8, method=method, filter_prec=pr,
                                seed=2002, init_random=1)
+            if args.ttr_escalate > 0 and pr == P.PREC_BF16 and kvec is None:
+                pm.stall_iters, pm.escalate = args.ttr_escalate, 1
             md = 0
             torch.cuda.empty_cache()
             free_now = torch.cuda.mem_get_info()[0]
@@ -619,6 +637,7 @@ def bench_grid(args):
                          "lambda_max_used": round(rep2["lambda_max_used"], 6),
                          "bounds_ms": round(rep2["time_bounds_ms"], 1),
                          "svqb_events": rep2["svqb_events"], "svqb_dropped": rep2["svqb_dropped"],
+                         "escalation_iteration": rep2["escalation_iteration"],
                          "residual_history": [float("%.3g" % v) for v in rep2["history"]]}
             log(f"  {ttr[name]}")
             c2.close()

@@ -176,14 +176,23 @@ typedef struct {
   int32_t binv_exact;
   /* Lanczos steps of the lambda_max estimate (0: 12). */
   int32_t lanczos_steps;
-  /* Stagnation: chfsi_solve stops with CHFSI_ERR_NOCONV once the max residual
-   * has stayed above its best value for stall_iters consecutive iterations
+  /* Stagnation: chfsi_solve stops with CHFSI_ERR_NOCONV once the lowest max
+   * residual so far has not halved for stall_iters consecutive iterations
    * (0: run to max_iter). */
   int32_t stall_iters;
   /* 1: keep a copy of the Ritz block of the lowest max residual (one more
    * n x b FP64 block, allocated by chfsi_create) and return those pairs on
    * CHFSI_ERR_NOCONV; 0: return the last pairs. */
   int32_t keep_best;
+  /* 1: precision escalation for a BF16 filter on a real operator (dense,
+   * grid or CSR): when the max residual stagnates for stall_iters passes
+   * (which must be > 0), the remaining passes filter in FP32 (FP32 blocks;
+   * dense: FP32 products) instead of stopping (report flags bit 3,
+   * escalation_iteration).  A reduced-precision filter has a largest usable
+   * degree (Section 3.1's condition); past it the BF16 iteration stalls.  The
+   * context then holds FP32 filter blocks from the start (dense: also an FP32
+   * copy of A), as an FP32 context does. */
+  int32_t escalate;
 } chfsi_params;
 
 /* Per-solve report (host). */
@@ -202,7 +211,8 @@ typedef struct {
   int32_t flags;               /* bit 0: a Gram matrix took the SVQB fallback;
                                   bit 1: a Jacobi eigensolve reached its cap of 40 sweeps
                                   with rotations still applied (not fully diagonalised);
-                                  bit 2: the solve stopped on stagnation (stall_iters) */
+                                  bit 2: the solve stopped on stagnation (stall_iters);
+                                  bit 3: the filter precision was escalated to FP32 */
   double history[CHFSI_MAX_HISTORY]; /* max residual after each pass (entry 0: initial RR) */
   int32_t svqb_events;         /* Rayleigh-Ritz passes that took the SVQB fallback */
   int32_t svqb_dropped;        /* directions dropped (and refilled) by those passes, summed */
@@ -210,6 +220,7 @@ typedef struct {
   double time_bounds_ms;       /* time of the Lanczos estimate in this solve (0 if none) */
   int32_t best_iteration;      /* pass with the lowest max residual (0: initial RR) */
   double best_residual;        /* that lowest max residual */
+  int32_t escalation_iteration;/* params.escalate: pass after which FP32 took over (0: none) */
 } chfsi_report;
 
 typedef struct chfsi_ctx chfsi_ctx;
@@ -270,7 +281,7 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* ctx, const double* Y, int64_t ldy, d
  * Estimates of the spectrum bounds of B^{-1} A (Section 2.1 treats the
  * filter's bounds as estimates).  A k-step Lanczos process on B^{-1} A in the
  * B-inner product from v0 (each step: one product with A and a
- * preconditioned conjugate-gradient solve with B to relative residual 1e-12,
+ * preconditioned conjugate-gradient solve with B to relative residual 1e-10,
  * preconditioner D^{-1}; no solve when B = I), in FP64 on the device.  With
  * theta_1 <= theta_k the extreme eigenvalues of the k x k tridiagonal matrix
  * and beta_k the B-norm of the last Lanczos residual (the "Ritz value +

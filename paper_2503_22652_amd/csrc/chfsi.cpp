@@ -484,9 +484,12 @@ SizePlan plan_sizes_kind(const chfsi_operator* A, const chfsi_operator* B, const
     s.a32 = size_t(n) * n * sizeof(uint16_t) + size_t(n) * sizeof(float) + size_t(n) * b * 2;
   } else if (p->filter_prec == CHFSI_PREC_FP64) {
     s.f64blk = s.blk;
+  } else if (p->escalate) {
+    s.f32blk = size_t(n) * b * sizeof(float);   // FP32 blocks; BF16 data in their first halves
   } else {
     s.bfblk = size_t(n) * b * 2;
   }
+  if (p->escalate && dense) s.a32 += size_t(n) * n * sizeof(float);   // FP32 copy of A
   // stencil filters in FP32/BF16: FP32 copies of D^{-1} and of the potential
   if (A->kind == CHFSI_OP_STENCIL27 && p->filter_prec != CHFSI_PREC_FP64)
     s.a32 += size_t(n) * sizeof(float) * (1 + (A->field_mode != 0 ? 1 : 0));
@@ -732,7 +735,7 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
         g.epi.C3 = Yc;
         g.epi.ldc3 = n;
         CK(prof_pair(c, &g.ev_begin, &g.ev_end));
-        if (c->A16)
+        if (c->prm.filter_prec == CHFSI_PREC_BF16)
           CK(gemm_bf16_filter(g, c->A16, n, static_cast<uint16_t*>(c->bf_a), c->stream, c->ws,
                               filter_gemm_splits()));
         else
@@ -2304,21 +2307,7 @@ chfsi_status estimate_bounds(chfsi_ctx* c, const double* v0_user, int steps, Lan
       g.ldc = n;
       return gemm<double>(g, st, c->ws);
     }
-    if (op.kind == CHFSI_OP_DENSE) {
-      GemmDesc<double> g;
-      g.M = n;
-      g.N = 1;
-      g.K = n;
-      g.A = op.dense;
-      g.sak = 1;
-      g.sam = op.ld;
-      g.B = x;
-      g.sbk = 1;
-      g.sbn = n;
-      g.C = y;
-      g.ldc = n;
-      return gemm<double>(g, st, c->ws);
-    }
+    if (op.kind == CHFSI_OP_DENSE) return gemv_rows_f64(op.dense, op.ld, n, x, y, st);
     if (op.kind == CHFSI_OP_STENCIL27) return stencil_apply_f64(op, x, n, y, n, 1, st);
     if (op.kind == CHFSI_OP_CSR) return csr_apply_f64(csr_of(c, op, false), x, n, y, n, 1, st);
     return hipErrorInvalidValue;
@@ -2494,6 +2483,13 @@ chfsi_status chfsi::create_with_allocator(chfsi_ctx** out, const chfsi_operator*
     set_error("lanczos_steps and stall_iters must be >= 0");
     return CHFSI_ERR_ARG;
   }
+  if (params->escalate != 0 &&
+      (params->escalate != 1 || params->stall_iters <= 0 ||
+       params->filter_prec != CHFSI_PREC_BF16 || params->method != CHFSI_METHOD_RCHFSI ||
+       (A->kind != CHFSI_OP_DENSE && A->kind != CHFSI_OP_STENCIL27 && A->kind != CHFSI_OP_CSR))) {
+    set_error("escalate needs stall_iters > 0 and a BF16 residual filter on a real operator");
+    return CHFSI_ERR_ARG;
+  }
   chfsi_ctx* c = new chfsi_ctx();
   c->al = al;
   c->stream = static_cast<hipStream_t>(stream);
@@ -2605,11 +2601,21 @@ chfsi_status chfsi::create_with_allocator(chfsi_ctx** out, const chfsi_operator*
     c->f64_b = ctx_alloc<double>(c, sp.f64blk, &st);
   } else if (dense) {
     c->A16 = ctx_alloc<uint16_t>(c, size_t(n) * n * sizeof(uint16_t), &st);
+    if (params->escalate) c->A32 = ctx_alloc<float>(c, size_t(n) * n * sizeof(float), &st);
     c->bf_a = ctx_alloc<char>(c, size_t(n) * b * sizeof(uint16_t), &st);   // bf16(D^-1 R_Y)
     c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
     c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
     c->f32_b = ctx_alloc<float>(c, sp.f32blk, &st);
     c->f32_c = ctx_alloc<float>(c, sp.f32blk, &st);
+  } else if (params->escalate) {
+    // FP32 blocks for the escalated passes; the BF16 blocks live in their first halves
+    if (d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
+    c->f32_a = ctx_alloc<float>(c, sp.f32blk, &st);
+    c->f32_b = ctx_alloc<float>(c, sp.f32blk, &st);
+    c->f32_c = ctx_alloc<float>(c, sp.f32blk, &st);
+    c->bf_a = c->f32_a;
+    c->bf_b = c->f32_b;
+    c->bf_c = c->f32_c;
   } else {
     if (d_inv) c->dinv32 = ctx_alloc<float>(c, size_t(n) * sizeof(float), &st);
     c->bf_a = ctx_alloc<char>(c, sp.bfblk, &st);
@@ -2946,9 +2952,13 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   };
   double mr = maxres();
   r.history[0] = mr;
-  // lowest max residual so far (and, with keep_best, its pairs)
+  // lowest max residual so far (and, with keep_best, its pairs); the stall
+  // test counts the passes since the lowest value last fell below half of the
+  // value at the previous such point
   double best = mr;
   int best_it = 0;
+  double mark = mr;
+  int mark_it = 0;
   std::vector<double> best_ritz, best_norms;
   auto keep = [&]() -> chfsi_status {
     if (!c->Xbest) return CHFSI_OK;
@@ -3010,8 +3020,25 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
       best = mr;
       best_it = it + 1;
       if ((st = keep()) != CHFSI_OK) break;
-    } else if (c->prm.stall_iters > 0 && it + 1 - best_it >= c->prm.stall_iters &&
-               !(mr < c->prm.tol)) {
+    }
+    if (best < 0.5 * mark) {
+      mark = best;
+      mark_it = it + 1;
+    }
+    if (mr < c->prm.tol) {
+      // converged
+    } else if (c->prm.stall_iters > 0 && it + 1 - mark_it >= c->prm.stall_iters &&
+               c->prm.escalate && c->prm.filter_prec == CHFSI_PREC_BF16) {
+      // stagnation of the BF16 filter: the remaining passes filter in FP32
+      c->prm.filter_prec = CHFSI_PREC_FP32;
+      c->flags |= 8;
+      r.escalation_iteration = it + 1;
+      mark = best;
+      mark_it = it + 1;
+      if (progress_log())
+        std::fprintf(stderr, "chfsi_solve: BF16 filter stagnated at %.3e; FP32 from iteration %d\n",
+                     mr, it + 2);
+    } else if (c->prm.stall_iters > 0 && it + 1 - mark_it >= c->prm.stall_iters) {
       // stagnation: no new lowest max residual for stall_iters passes
       c->flags |= 4;
       ++it;
@@ -3026,6 +3053,7 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
                    "SVQB fallbacks %d, dropped directions %d)\n",
                    it + 1, mr, r.time_filter_ms, r.time_rr_ms, c->svqb_events, c->svqb_dropped);
   }
+  if (c->prm.escalate) c->prm.filter_prec = CHFSI_PREC_BF16;   // the context's own precision
   r.iterations = it;
   r.max_residual = mr;
   r.converged = mr < c->prm.tol;

@@ -206,7 +206,7 @@ struct LanczosOps {
   const double* dinv = nullptr;   // CG preconditioner (length L; null: none)
   const double* v0 = nullptr;     // start vector (device, length L)
   int steps = 12;
-  double cg_tol = 1e-12;          // relative residual of the inner B-solves
+  double cg_tol = 1e-10;          // relative residual of the inner B-solves
   int cg_max_iter = 1000;
 };
 struct LanczosResult {
@@ -216,6 +216,9 @@ struct LanczosResult {
 };
 // device scratch for vectors of length L
 size_t lanczos_workspace_bytes(int64_t L);
+// y = A x, A dense symmetric n x n (ld), FP64; one wave per row
+hipError_t gemv_rows_f64(const double* A, int64_t ld, int64_t n, const double* x, double* y,
+                         hipStream_t st);
 // host_scalars: pinned host memory for 2 doubles.  Synchronises the stream
 // at every dot product.  Returns hipErrorInvalidValue if B is not positive
 // definite on the Krylov space (a non-positive B-norm).

@@ -171,7 +171,30 @@ double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, i
   return 0.5 * (lo + hi);
 }
 
+// y = A x for a dense symmetric A read by rows (A(m, k) = A[k + m ld]): one
+// wave per row, lanes over k, a fixed-order wave reduction
+__global__ __launch_bounds__(kThreads) void k_gemv_rows(const double* __restrict__ A, int64_t ld,
+                                                        int64_t n, const double* __restrict__ x,
+                                                        double* __restrict__ y) {
+  const int64_t m = int64_t(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6);
+  if (m >= n) return;
+  const int lane = threadIdx.x & 63;
+  const double* row = A + m * ld;
+  double s = 0.0;
+  for (int64_t k = lane; k < n; k += 64) s += row[k] * x[k];
+  s = wave_sum(s);
+  if (lane == 0) y[m] = s;
+}
+
 }  // namespace
+
+hipError_t gemv_rows_f64(const double* A, int64_t ld, int64_t n, const double* x, double* y,
+                         hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + kThreads / 64 - 1) / (kThreads / 64);
+  k_gemv_rows<<<dim3(unsigned(blocks)), kThreads, 0, st>>>(A, ld, n, x, y);
+  return hipGetLastError();
+}
 
 size_t lanczos_workspace_bytes(int64_t L) {
   return size_t(10) * size_t(L) * sizeof(double) + size_t(2 * kMaxBlocks + 8) * sizeof(double);

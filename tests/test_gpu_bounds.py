@@ -3,7 +3,7 @@ oracle.bounds, and solves with lambda_max = NaN (estimated inside the library).
 
 The filter's bounds are estimates (Section 2.1).  Both sides run k Lanczos
 steps on B^{-1} A in the B-inner product from the same seeded start vector;
-the library solves with B by preconditioned CG to relative residual 1e-12,
+the library solves with B by preconditioned CG to relative residual 1e-10,
 the oracle exactly, so the Ritz values theta_1, theta_k and the safeguarded
 estimates agree to ~1e-10.  Pencils: the dense generalized recipe (dense B,
 D^{-1} preconditioner), the grid pencil with wells (mass matrix B, no

@@ -307,7 +307,7 @@ def test_chfsi_exact_inverse_filter_and_solve():
 
 def test_stagnation_stops_early_and_returns_best_pairs():
     """ChFSI with D^{-1} != B^{-1} stalls (Theorem 3.2).  With stall_iters the
-    solve stops once the max residual has not reached a new low for that many
+    solve stops once its lowest max residual has not halved for that many
     passes (report flags bit 2, CHFSI_ERR_NOCONV), and with keep_best the
     returned pairs are those of the lowest max residual: their residuals,
     recomputed on the CPU, are the reported ones."""
@@ -324,8 +324,9 @@ def test_stagnation_stops_early_and_returns_best_pairs():
     assert st == P.ERR_NOCONV
     assert rep["flags"] & 4
     assert rep["iterations"] < 60
-    assert rep["iterations"] - rep["best_iteration"] >= 4
     hist = rep["history"]
+    # stopped because the lowest max residual did not halve over the last 4 passes
+    assert min(hist) >= 0.5 * min(hist[: len(hist) - 4])
     assert rep["best_residual"] == min(hist)
     assert rep["max_residual"] == rep["best_residual"]
     X = host(Xd)
@@ -349,3 +350,33 @@ def test_jacobi_sweep_cap_is_reported(monkeypatch):
     monkeypatch.delenv("CHFSI_JACOBI_MAX_SWEEPS")
     st, ev, rn, rep = P.chfsi_solve(ctx, dev(wl.random_block(p.n, 40, 7)))
     assert not rep["flags"] & 2
+
+
+def test_bf16_stagnation_escalates_to_fp32():
+    """A reduced-precision filter has a largest usable degree (Section 3.1's
+    condition): on the toy spectrum of Section 4.1 (m = 1000, 10 wanted, gap 1)
+    the BF16-product residual filter stalls at degree 64.  With escalate the
+    stalled solve continues in FP32 and converges to LAPACK's eigenvalues;
+    without it the same solve stops on stagnation."""
+    t = wl.toy_standard(1000, 10, seed=31)
+    A = t["A"]
+    w = np.linalg.eigvalsh(A)
+    Ad = dev(A)
+    anorm = float(np.abs(w).max())
+    for escalate in (0, 1):
+        # the bounds of the controlled experiments (Section 4.1), block = n
+        params = P.make_params(10, 10, 64, max_iter=80, tol=1e-9 * anorm,
+                               method=P.METHOD_RCHFSI, filter_prec=P.PREC_BF16,
+                               lambda_min=float(w[0]) - 0.05, lambda_max=float(w[-1]) + 0.1,
+                               lambda_T=0.5 * float(w[9] + w[10]), stall_iters=5,
+                               escalate=escalate)
+        ctx = P.chfsi_create(P.dense_operator(Ad), None, None, params, keep=(Ad,))
+        Xd = dev(wl.random_block(1000, 10, 42))
+        st, ev, rn, rep = P.chfsi_solve(ctx, Xd)
+        print("escalate", escalate, P.STATUS_NAMES[st], rep["iterations"],
+              rep["escalation_iteration"], ["%.1e" % h for h in rep["history"]])
+        if escalate:
+            assert st == P.OK and rep["flags"] & 8 and rep["escalation_iteration"] > 0
+            np.testing.assert_allclose(ev[:10], w[:10], rtol=1e-10, atol=1e-10 * anorm)
+        else:
+            assert st == P.ERR_NOCONV and rep["flags"] & 4
