@@ -161,6 +161,7 @@ struct chfsi_ctx {
   int flags = 0;
   int jacobi_unconv = 0;          // the last eigensolve reached its sweep cap
   double* Xbest = nullptr;        // keep_best: Ritz block of the lowest max residual
+  double* gs_work = nullptr;      // complex contexts: scratch of the equal-Ritz-value Gram-Schmidt
   // CSR operators: longest rows (checked at create) and FP32 value copies
   int csrA_kmax = 0, csrB_kmax = 0;
   float* val32 = nullptr;
@@ -457,6 +458,8 @@ SizePlan plan_sizes_kind(const chfsi_operator* A, const chfsi_operator* B, const
 
 SizePlan plan_sizes(const chfsi_operator* A, const chfsi_operator* B, const chfsi_params* p) {
   SizePlan s = plan_sizes_kind(A, B, p);
+  if (A->kind == CHFSI_OP_DENSE_HERMITIAN || A->kind == CHFSI_OP_STENCIL27_BLOCH)
+    s.total += cluster_gs_work_bytes(p->block, p->block) + 256;
   if (p->keep_best) {
     const bool cx = A->kind == CHFSI_OP_DENSE_HERMITIAN || A->kind == CHFSI_OP_STENCIL27_BLOCH;
     s.total += size_t(A->n) * (cx ? 2 : 1) * p->block * sizeof(double);
@@ -1536,120 +1539,42 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
 // equal (to 1e-8 relative), Jacobi returns an arbitrary real basis of their
 // joint eigenspace and the first vectors of its pairs need not span it.  For
 // each such cluster of the first 2 np eigenvalues (ascending, w on the host),
-// the cluster's columns of E (2 cd rows, ld lde, device) are taken to the host,
-// every one is read as a complex vector, complex modified Gram-Schmidt keeps
-// an orthonormal set of the cluster's size / 2, and the pairs are rewritten
-// as [Re x; Im x], [-Im x; Re x].  With Mg (device, the embedding M(G) of a
+// the cluster's columns of E (2 cd rows, ld lde, device) are read as complex
+// vectors and a pivoted complex Gram-Schmidt on the device (one workgroup,
+// cluster_orthonormalize) keeps an orthonormal set of the cluster's size / 2;
+// the pairs are rewritten as [Re x; Im x], [-Im x; Re x].  With Mg (device, the embedding M(G) of a
 // Hermitian positive definite G, ld 2 cd) the set is orthonormal in x^H G y
 // instead (columns of E in the coordinates where G is the metric).  Clusters
 // are rare; nothing moves otherwise.
 chfsi_status fix_pair_clusters(chfsi_ctx* c, double* E, int64_t lde, int64_t cd, int64_t np,
                                const double* w, const double* Mg = nullptr) {
-  std::vector<std::complex<double>> G;   // the metric, fetched at the first cluster
   double scale = 0.0;
   for (int64_t j = 0; j < 2 * np; ++j) scale = std::max(scale, std::fabs(w[j]));
   const double tol = 1e-8 * std::max(scale, 1e-300);
+  hipStream_t st = c->stream;
+  // the cluster's Gram-Schmidt runs on the device in the context's scratch
+  // for it (sized for a cluster of b pairs of length b)
+  const size_t tmp_bytes = cluster_gs_work_bytes(c->b, c->b);
   int64_t j0 = 0;
   while (j0 < np) {
     int64_t j1 = j0 + 1;   // pairs [j0, j1) form one cluster
     while (j1 < np && std::fabs(w[2 * j1] - w[2 * j1 - 1]) <= tol) ++j1;
     if (j1 - j0 > 1) {
-      const int64_t cols = 2 * (j1 - j0), rows = 2 * cd;
-      std::vector<double> h(size_t(rows) * cols);
-      CK(hipMemcpy2DAsync(h.data(), rows * sizeof(double), E + 2 * j0 * lde,
-                          lde * sizeof(double), rows * sizeof(double), cols,
-                          hipMemcpyDeviceToHost, c->stream));
-      CK(hipStreamSynchronize(c->stream));
-      if (Mg && G.empty()) {
-        std::vector<double> hm(size_t(rows) * rows);
-        CK(hipMemcpyAsync(hm.data(), Mg, hm.size() * sizeof(double), hipMemcpyDeviceToHost,
-                          c->stream));
-        CK(hipStreamSynchronize(c->stream));
-        G.resize(size_t(cd) * cd);   // G(i, j) = M(i, j) + i M(cd + i, j)
-        for (int64_t j = 0; j < cd; ++j)
-          for (int64_t i = 0; i < cd; ++i) G[i + j * cd] = {hm[i + j * rows], hm[cd + i + j * rows]};
-      }
-      std::vector<std::complex<double>> Gu(cd);
-      auto apply_metric = [&](const std::vector<std::complex<double>>& u) {
-        if (G.empty()) {
-          Gu = u;
-          return;
-        }
-        for (int64_t i = 0; i < cd; ++i) {
-          std::complex<double> acc = 0.0;
-          for (int64_t j = 0; j < cd; ++j) acc += G[i + j * cd] * u[j];
-          Gu[i] = acc;
-        }
-      };
-      // pivoted: each step keeps the candidate that retains the largest part of
-      // its norm outside the vectors kept so far.  With the kept q_a
-      // G-orthonormal, the coefficients are (G q_a)^H u and the remaining
-      // squared norm is |u|_G^2 - sum |coefficient|^2, so G is applied once
-      // per candidate and once per kept vector.
-      std::vector<std::complex<double>> q, Gq;   // kept vectors and G times them, cd each
-      std::vector<std::vector<std::complex<double>>> cand(cols, std::vector<std::complex<double>>(cd));
-      std::vector<double> n0(cols);
-      std::vector<char> used(cols, 0);
-      for (int64_t v = 0; v < cols; ++v) {
-        for (int64_t i = 0; i < cd; ++i) cand[v][i] = {h[v * rows + i], h[v * rows + cd + i]};
-        apply_metric(cand[v]);
-        double r = 0.0;
-        for (int64_t i = 0; i < cd; ++i) r += std::real(std::conj(cand[v][i]) * Gu[i]);
-        n0[v] = std::sqrt(std::max(r, 0.0));
-      }
-      for (int64_t t = 0; t < j1 - j0; ++t) {
-        int64_t best = -1;
-        double best_ratio = 0.0;
-        for (int64_t v = 0; v < cols; ++v) {
-          if (used[v] || !(n0[v] > 0.0)) continue;
-          double rem = n0[v] * n0[v];
-          for (size_t a = 0; a < q.size(); a += cd) {
-            std::complex<double> d = 0.0;
-            for (int64_t i = 0; i < cd; ++i) d += std::conj(Gq[a + i]) * cand[v][i];
-            rem -= std::norm(d);
-          }
-          const double ratio = std::sqrt(std::max(rem, 0.0)) / n0[v];
-          if (ratio > best_ratio) {
-            best_ratio = ratio;
-            best = v;
-          }
-        }
-        if (best < 0 || !(best_ratio > 1e-6)) break;   // the cluster's span is exhausted
-        used[best] = 1;
-        std::vector<std::complex<double>> u = cand[best];
-        for (int pass = 0; pass < 2; ++pass)   // projection, repeated once for accuracy
-          for (size_t a = 0; a < q.size(); a += cd) {
-            std::complex<double> d = 0.0;
-            for (int64_t i = 0; i < cd; ++i) d += std::conj(Gq[a + i]) * u[i];
-            for (int64_t i = 0; i < cd; ++i) u[i] -= d * q[a + i];
-          }
-        apply_metric(u);
-        double r = 0.0;
-        for (int64_t i = 0; i < cd; ++i) r += std::real(std::conj(u[i]) * Gu[i]);
-        const double nrm = std::sqrt(std::max(r, 0.0));
-        if (!(nrm > 0.0)) break;
-        for (int64_t i = 0; i < cd; ++i) {
-          q.push_back(u[i] / nrm);
-          Gq.push_back(Gu[i] / nrm);
-        }
-      }
-      if (int64_t(q.size()) != cd * (j1 - j0)) {
-        set_error("a cluster of %lld equal complex eigenvalues has no orthonormal basis in the "
-                  "embedded eigenvectors", (long long)(j1 - j0));
+      const int64_t ncl = j1 - j0;
+      if (cluster_gs_work_bytes(cd, ncl) > tmp_bytes) {
+        set_error("a cluster of %lld equal complex eigenvalues is too large for the "
+                  "orthonormalisation scratch", (long long)ncl);
         return CHFSI_ERR_NUMERIC;
       }
-      for (int64_t t = 0; t < j1 - j0; ++t)
-        for (int64_t i = 0; i < cd; ++i) {
-          const std::complex<double> x = q[t * cd + i];
-          h[(2 * t) * rows + i] = x.real();
-          h[(2 * t) * rows + cd + i] = x.imag();
-          h[(2 * t + 1) * rows + i] = -x.imag();
-          h[(2 * t + 1) * rows + cd + i] = x.real();
-        }
-      CK(hipMemcpy2DAsync(E + 2 * j0 * lde, lde * sizeof(double), h.data(),
-                          rows * sizeof(double), rows * sizeof(double), cols,
-                          hipMemcpyHostToDevice, c->stream));
-      CK(hipStreamSynchronize(c->stream));
+      CK(cluster_orthonormalize(E + 2 * j0 * lde, lde, cd, ncl, Mg, 2 * cd, c->gs_work,
+                                c->dflags + 3, st));
+      CK(hipMemcpyAsync(c->h_flags + 3, c->dflags + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      if (c->h_flags[3] != 0) {
+        set_error("a cluster of %lld equal complex eigenvalues has no orthonormal basis in the "
+                  "embedded eigenvectors", (long long)ncl);
+        return CHFSI_ERR_NUMERIC;
+      }
     }
     j0 = j1;
   }
@@ -2582,6 +2507,7 @@ chfsi_status chfsi::create_with_allocator(chfsi_ctx** out, const chfsi_operator*
     c->TL = ctx_alloc<double>(c, sp.bb, &st);
     c->Xt = ctx_alloc<double>(c, sp.bb, &st);
     c->Zx = ctx_alloc<double>(c, sp.bb, &st);
+    c->gs_work = ctx_alloc<double>(c, cluster_gs_work_bytes(b, b), &st);
     c->svec = ctx_alloc<double>(c, m * sizeof(double), &st);
     c->w = ctx_alloc<double>(c, m * sizeof(double), &st);
     c->norms = ctx_alloc<double>(c, m * sizeof(double), &st);

@@ -298,6 +298,172 @@ hipError_t cplx_reconstruct(const F* RY, const double* dinv, const double* X, in
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Equal complex Ritz values: a G-orthonormal basis of a cluster's eigenspace
+// from the embedded eigenvectors, by pivoted Gram-Schmidt in one workgroup.
+//
+// The 2 ncl columns of E (each [Re u; Im u], 2 cd rows, ld lde) are read as
+// complex candidate vectors u_v of length cd.  G is the identity (Mg null) or
+// the Hermitian metric with G(i, j) = Mg(i, j) + i Mg(cd + i, j) (the real
+// embedding M(G), ld ldm).  Each step keeps the candidate that retains the
+// largest part of its G-norm outside the vectors kept so far (with the kept
+// q_a G-orthonormal the coefficients are (G q_a)^H u and the remainder is
+// |u|_G^2 - sum |coefficient|^2), projects it twice, and normalises it.  The
+// kept vectors overwrite E as the pairs [Re q; Im q], [-Im q; Re q].  status:
+// 0, or 1 when fewer than ncl independent directions are found (E untouched).
+// work: (2 ncl + 2 ncl + 2) cd complex + 2 ncl doubles.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kGsThreads = 256;
+
+// block sum of (re, im) pairs; every thread gets the result
+__device__ double2 block_sum2(double2 v, double2* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kGsThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[threadIdx.x].x += red[threadIdx.x + w].x;
+      red[threadIdx.x].y += red[threadIdx.x + w].y;
+    }
+    __syncthreads();
+  }
+  const double2 r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// conj(a) . b over cd complex entries
+__device__ double2 cdot(const double2* a, const double2* b, int64_t cd, double2* red) {
+  double2 s = make_double2(0.0, 0.0);
+  for (int64_t i = threadIdx.x; i < cd; i += kGsThreads) {
+    s.x += a[i].x * b[i].x + a[i].y * b[i].y;
+    s.y += a[i].x * b[i].y - a[i].y * b[i].x;
+  }
+  return block_sum2(s, red);
+}
+
+// out = G u
+__device__ void apply_metric(const double* Mg, int64_t ldm, const double2* u, int64_t cd,
+                             double2* out) {
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < cd; i += kGsThreads) {
+    if (!Mg) {
+      out[i] = u[i];
+      continue;
+    }
+    double re = 0.0, im = 0.0;
+    for (int64_t j = 0; j < cd; ++j) {
+      const double gr = Mg[i + j * ldm], gi = Mg[cd + i + j * ldm];
+      re += gr * u[j].x - gi * u[j].y;
+      im += gr * u[j].y + gi * u[j].x;
+    }
+    out[i] = make_double2(re, im);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kGsThreads) void k_cluster_gs(double* E, int64_t lde, int64_t cd,
+                                                           int ncl, const double* Mg, int64_t ldm,
+                                                           double* work, int* status) {
+  __shared__ double2 red[kGsThreads];
+  __shared__ int best_s;
+  const int cols = 2 * ncl;
+  double2* cand = reinterpret_cast<double2*>(work);
+  double2* q = cand + int64_t(cols) * cd;
+  double2* Gq = q + int64_t(ncl) * cd;
+  double2* u = Gq + int64_t(ncl) * cd;
+  double2* Gu = u + cd;
+  double* n0 = reinterpret_cast<double*>(Gu + cd);
+  double* used = n0 + cols;
+  for (int v = 0; v < cols; ++v) {
+    for (int64_t i = threadIdx.x; i < cd; i += kGsThreads)
+      cand[int64_t(v) * cd + i] = make_double2(E[v * lde + i], E[v * lde + cd + i]);
+    apply_metric(Mg, ldm, cand + int64_t(v) * cd, cd, Gu);
+    const double2 r = cdot(cand + int64_t(v) * cd, Gu, cd, red);
+    if (threadIdx.x == 0) {
+      n0[v] = sqrt(fmax(r.x, 0.0));
+      used[v] = 0.0;
+    }
+  }
+  __syncthreads();
+  int kept = 0;
+  for (int t = 0; t < ncl; ++t) {
+    // the candidate keeping the largest fraction of its norm
+    double best_ratio = 0.0;
+    int best = -1;
+    for (int v = 0; v < cols; ++v) {
+      if (used[v] != 0.0 || !(n0[v] > 0.0)) continue;
+      double rem = n0[v] * n0[v];
+      for (int a = 0; a < kept; ++a) {
+        const double2 d = cdot(Gq + int64_t(a) * cd, cand + int64_t(v) * cd, cd, red);
+        rem -= d.x * d.x + d.y * d.y;
+      }
+      const double ratio = sqrt(fmax(rem, 0.0)) / n0[v];
+      if (ratio > best_ratio) {
+        best_ratio = ratio;
+        best = v;
+      }
+    }
+    if (threadIdx.x == 0) best_s = (best >= 0 && best_ratio > 1e-6) ? best : -1;
+    __syncthreads();
+    const int bsel = best_s;
+    __syncthreads();
+    if (bsel < 0) break;
+    if (threadIdx.x == 0) used[bsel] = 1.0;
+    for (int64_t i = threadIdx.x; i < cd; i += kGsThreads) u[i] = cand[int64_t(bsel) * cd + i];
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass)     // projection, repeated once for accuracy
+      for (int a = 0; a < kept; ++a) {
+        const double2 d = cdot(Gq + int64_t(a) * cd, u, cd, red);
+        for (int64_t i = threadIdx.x; i < cd; i += kGsThreads) {
+          const double2 qa = q[int64_t(a) * cd + i];
+          u[i].x -= d.x * qa.x - d.y * qa.y;
+          u[i].y -= d.x * qa.y + d.y * qa.x;
+        }
+        __syncthreads();
+      }
+    apply_metric(Mg, ldm, u, cd, Gu);
+    const double2 r = cdot(u, Gu, cd, red);
+    const double nrm = sqrt(fmax(r.x, 0.0));
+    if (!(nrm > 0.0)) break;
+    for (int64_t i = threadIdx.x; i < cd; i += kGsThreads) {
+      q[int64_t(kept) * cd + i] = make_double2(u[i].x / nrm, u[i].y / nrm);
+      Gq[int64_t(kept) * cd + i] = make_double2(Gu[i].x / nrm, Gu[i].y / nrm);
+    }
+    __syncthreads();
+    ++kept;
+  }
+  if (kept != ncl) {
+    if (threadIdx.x == 0) *status = 1;
+    return;
+  }
+  for (int t = 0; t < ncl; ++t)
+    for (int64_t i = threadIdx.x; i < cd; i += kGsThreads) {
+      const double2 x = q[int64_t(t) * cd + i];
+      E[(2 * t) * lde + i] = x.x;
+      E[(2 * t) * lde + cd + i] = x.y;
+      E[(2 * t + 1) * lde + i] = -x.y;
+      E[(2 * t + 1) * lde + cd + i] = x.x;
+    }
+  if (threadIdx.x == 0) *status = 0;
+}
+
+}  // namespace
+
+size_t cluster_gs_work_bytes(int64_t cd, int64_t ncl) {
+  return size_t(4 * ncl + 2) * size_t(cd) * 2 * sizeof(double) + size_t(2 * ncl) * sizeof(double);
+}
+
+hipError_t cluster_orthonormalize(double* E, int64_t lde, int64_t cd, int64_t ncl,
+                                  const double* Mg, int64_t ldm, double* work, int* status,
+                                  hipStream_t st) {
+  if (ncl <= 0 || cd <= 0) return hipSuccess;
+  if (ncl > 0x3fffffff) return hipErrorInvalidValue;
+  k_cluster_gs<<<1, kGsThreads, 0, st>>>(E, lde, cd, int(ncl), Mg, ldm, work, status);
+  return hipGetLastError();
+}
+
 template hipError_t herm_to_planar<float>(const double*, int64_t, int64_t, float*, hipStream_t);
 template hipError_t herm_to_planar<double>(const double*, int64_t, int64_t, double*, hipStream_t);
 template hipError_t herm_to_planar<uint16_t>(const double*, int64_t, int64_t, uint16_t*,

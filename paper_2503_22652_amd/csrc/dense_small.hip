@@ -633,8 +633,8 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   for (; sweeps < max_outer; ++sweeps) {
     if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
     for (int r = 0; r < nblk - 1; ++r) {
-      k_jacobi_pair_solve<<<dim3(npairs), kPairThreads, 0, st>>>(P, bp, nblk, r, scal, tol, U, skip,
-                                                        counter, inner);
+      k_jacobi_pair_solve<<<dim3(npairs), kPairThreads, 0, st>>>(P, bp, nblk, r, scal, tol, U,
+                                                                 skip, counter, inner);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       k_jacobi_apply_A<<<dim3(npairs, npairs), 256, 0, st>>>(P, bp, nblk, r, U, skip);
       if ((e = hipGetLastError()) != hipSuccess) return e;

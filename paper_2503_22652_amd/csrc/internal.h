@@ -163,6 +163,16 @@ hipError_t select_pairs_n(const double* T, int64_t ldt, int64_t b, int64_t k, do
 // column j scaled by gs[j] and row i by s[i] (device arrays)
 hipError_t pairs_to_planar(const double* E, int64_t lde, int64_t b, int64_t first, int64_t k,
                            const double* gs, const double* s, double* W, hipStream_t st);
+// Equal complex Ritz values: overwrite the 2 ncl columns of E (each [Re u;
+// Im u], 2 cd rows, ld lde) with the pairs [Re q; Im q], [-Im q; Re q] of ncl
+// G-orthonormal complex vectors q spanning the candidates, by pivoted
+// Gram-Schmidt (one workgroup).  G: identity (Mg null) or G(i, j) = Mg(i, j)
+// + i Mg(cd + i, j) (ld ldm).  *status (device): 0, or 1 if fewer than ncl
+// independent directions exist (E then untouched).
+size_t cluster_gs_work_bytes(int64_t cd, int64_t ncl);
+hipError_t cluster_orthonormalize(double* E, int64_t lde, int64_t cd, int64_t ncl,
+                                  const double* Mg, int64_t ldm, double* work, int* status,
+                                  hipStream_t st);
 // M(W) = [[W_r, -W_i], [W_i, W_r]] (2b x 2k, ld ldm) from planar W (b x 2k)
 hipError_t embed_block(const double* W, int64_t b, int64_t k, double* M, int64_t ldm,
                        hipStream_t st);
