@@ -13,9 +13,11 @@
 // iteration converges -- and (iii) it is accurate to a small multiple of the
 // unit roundoff.  The block variant pairs JB-wide column blocks (JB = 16) in a
 // round-robin tournament, applies one inner sweep of rotations to every
-// JP x JP pair subproblem (JP = 2 JB = 32) in LDS (one workgroup each), and
-// applies the resulting orthogonal JP x JP factors to the rest of the matrix
-// and to the eigenvector accumulator with MFMA.  Sweeps repeat until no
+// JP x JP pair subproblem (JP = 2 JB = 32) in LDS (one workgroup each, waves
+// specialised so that a round costs one barrier: the next round's rotations,
+// this round's update, the accumulation of U), and applies the resulting
+// orthogonal JP x JP factors to the rest of the matrix and to the eigenvector
+// accumulator with MFMA, in one launch per outer round.  Sweeps repeat until no
 // rotation is applied or a cap of 40 sweeps is reached (then reported).
 #include "internal.h"
 
@@ -126,90 +128,6 @@ __device__ __forceinline__ int rr_slot(int slot, int r, int n) {
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-// Cyclic Jacobi sweeps on the JP x JP symmetric matrix a (LDS, ld LDJ),
-// accumulating the rotations into u (LDS, starts as identity).  Each round
-// applies JP/2 disjoint rotations J = [[c, s], [-s, c]] (a <- J^T a J, u <- u J)
-// in one pass over 2x2 blocks.  Stops after a sweep without rotations or
-// after max_sweeps.  Returns the number of rotations applied.
-__device__ int lds_jacobi(double* a, double* u, double thresh, int max_sweeps) {
-  constexpr int n = JP, half = JP / 2;
-  __shared__ int pp[half], qq[half];
-  __shared__ double cc[half], ss[half];
-  __shared__ int sweep_rot;
-  int total = 0;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (threadIdx.x == 0) sweep_rot = 0;
-    __syncthreads();
-    for (int r = 0; r < n - 1; ++r) {
-      static_assert(half <= 64, "the rotations of a round are computed by one wave");
-      if (threadIdx.x < half) {
-        const int k = threadIdx.x;
-        int p = rr_slot(k, r, n), q = rr_slot(n - 1 - k, r, n);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        const double apq = a[p + q * LDJ];
-        double c = 1.0, sn = 0.0;
-        const bool rot = fabs(apq) > thresh;
-        if (rot) {
-          const double app = a[p + p * LDJ], aqq = a[q + q * LDJ];
-          const double theta = (aqq - app) / (2.0 * apq);
-          double t;
-          if (fabs(theta) > 1e150)
-            t = 0.5 / theta;
-          else
-            t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          sn = t * c;
-        }
-        // one count per round (a single LDS update instead of one atomic per rotation)
-        const unsigned long long m = __ballot(rot);
-        if (k == 0) sweep_rot += __popcll(m);
-        pp[k] = p;
-        qq[k] = q;
-        cc[k] = c;
-        ss[k] = sn;
-      }
-      __syncthreads();
-      // two-sided update, one 2x2 block (pair k1 rows, pair k2 columns) per item
-      for (int idx = threadIdx.x; idx < half * half; idx += blockDim.x) {
-        const int k1 = idx / half, k2 = idx - k1 * half;
-        const double s1 = ss[k1], s2 = ss[k2];
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        const double c1 = cc[k1], c2 = cc[k2];
-        const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-        const double x11 = a[p1 + p2 * LDJ], x12 = a[p1 + q2 * LDJ];
-        const double x21 = a[q1 + p2 * LDJ], x22 = a[q1 + q2 * LDJ];
-        const double y11 = c1 * x11 - s1 * x21, y12 = c1 * x12 - s1 * x22;
-        const double y21 = s1 * x11 + c1 * x21, y22 = s1 * x12 + c1 * x22;
-        a[p1 + p2 * LDJ] = c2 * y11 - s2 * y12;
-        a[q1 + q2 * LDJ] = s2 * y21 + c2 * y22;
-        // the pair's own rotation annihilates its off-diagonal entry
-        a[p1 + q2 * LDJ] = (k1 == k2) ? 0.0 : s2 * y11 + c2 * y12;
-        a[q1 + p2 * LDJ] = (k1 == k2) ? 0.0 : c2 * y21 - s2 * y22;
-      }
-      for (int idx = threadIdx.x; idx < n * half; idx += blockDim.x) {
-        const int k = idx / n, i = idx - k * n;
-        const double sn = ss[k];
-        if (sn == 0.0) continue;
-        const double c = cc[k];
-        const int p = pp[k], q = qq[k];
-        const double up = u[i + p * LDJ], uq = u[i + q * LDJ];
-        u[i + p * LDJ] = c * up - sn * uq;
-        u[i + q * LDJ] = sn * up + c * uq;
-      }
-      __syncthreads();
-    }
-    const int rot = sweep_rot;
-    total += rot;
-    __syncthreads();
-    if (rot == 0) break;
-  }
-  return total;
-}
-
 // Block indices of pair k in round r of the block tournament (nblk blocks).
 __device__ __forceinline__ void block_pair(int k, int r, int nblk, int* I, int* J) {
   int a = rr_slot(k, r, nblk), b = rr_slot(nblk - 1 - k, r, nblk);
@@ -222,49 +140,254 @@ __device__ __forceinline__ int pair_index(int l, int I, int J) {
   return l < JB ? I * JB + l : J * JB + (l - JB);
 }
 
-// One workgroup per pair of the round: gather the JP x JP subproblem, skip it
-// when already diagonal (to the threshold), else run `inner` Jacobi sweeps.
-// Writes U (JP x JP) and skip[pair] (1 = U is the identity).  The rotation
-// rounds are latency-bound; 8 waves per subproblem measured fastest on
-// MI355X (whole Rayleigh-Ritz, N = 8192, b = 320: 12.2 ms with 512 threads,
-// 12.9 with 256, 22.2 with one wave; 1024 as 512).
-constexpr int kPairThreads = 512;
-__global__ __launch_bounds__(kPairThreads) void k_jacobi_pair_solve(
-    const double* A, int64_t lda, int nblk, int round, const double* scale, double tol, double* U,
-    int* skip, int* counter, int inner) {
-  __shared__ double a[JP * LDJ];
-  __shared__ double u[JP * LDJ];
-  __shared__ double red[kPairThreads];
-  int I, J;
-  block_pair(blockIdx.x, round, nblk, &I, &J);
-  double mx = 0.0;
-  for (int idx = threadIdx.x; idx < JP * JP; idx += kPairThreads) {
-    const int i = idx % JP, j = idx / JP;
-    const double v = A[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
-    a[i + j * LDJ] = v;
-    u[i + j * LDJ] = (i == j) ? 1.0 : 0.0;
-    if (i != j) mx = fmax(mx, fabs(v));
-  }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = kPairThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const double thresh = tol * (*scale);
-  if (!(red[0] > thresh)) {
-    if (threadIdx.x == 0) skip[blockIdx.x] = 1;
+// ---------------------------------------------------------------------------
+// Pair subproblem, wave-specialised (one sweep of JP - 1 rounds, one barrier
+// per round).
+// Round r of the circle schedule pairs slots (k, JP-1-k), k < JP/2; between
+// rounds every index moves from slot s to slot sigma(s) = s - 1 (1 -> JP-1,
+// slot 0 fixed).  The subproblem is therefore stored by slot, not by index:
+// round r reads LDS buffer r % 2 and writes the shifted entries into buffer
+// (r + 1) % 2, so every thread touches the same addresses in every round and
+// no index arithmetic remains inside the loop.  Only the lower triangle (in
+// slot order) is kept.  The rotation of pair k acts on (first, second) =
+// (slot k, slot JP-1-k): J = [[c, s], [-s, c]], a <- J^T a J.
+//  * wave 0, lane k < JP/2: the rotation of pair k in the NEXT round.  The
+//    three entries it needs after this round are formed from this round's
+//    buffer and rotations with the same arithmetic (rot_block, same operand
+//    order) as the update waves, so they are bit-identical to what those
+//    waves store.
+//  * waves 2..4 (k1 >= k2 of 16 x 16 pair blocks, 136 threads): this round's
+//    two-sided update of one 2 x 2 block each.
+//  * wave 1, lane i < JP: row i of the accumulated rotation U in registers,
+//    by index (the round loop is unrolled, so the indices of each round's
+//    pairs are constants).
+// ---------------------------------------------------------------------------
+constexpr int kHalf = JP / 2;       // rotations per round
+constexpr int kRounds = JP - 1;     // rounds per sweep
+constexpr int kPairThreads = 5 * 64;
+
+// lower-triangle LDS offset of symmetric entry (i, j) (slot coordinates)
+__device__ __forceinline__ int sym_idx(int i, int j) { return i >= j ? i + j * LDJ : j + i * LDJ; }
+// slot of an index after one round, and before it
+__device__ __forceinline__ int slot_next(int s) { return s == 0 ? 0 : (s == 1 ? JP - 1 : s - 1); }
+__device__ __forceinline__ int slot_prev(int s) { return s == 0 ? 0 : (s == JP - 1 ? 1 : s + 1); }
+// pair of slot s, and whether s is the pair's first slot
+__device__ __forceinline__ int slot_pair(int s) { return s < kHalf ? s : JP - 1 - s; }
+
+// out = J1^T X J2 for the 2 x 2 block X (rows first/second of pair 1,
+// columns first/second of pair 2); explicit fma so that every caller rounds
+// alike
+__device__ __forceinline__ void rot_block(double x11, double x12, double x21, double x22,
+                                          double c1, double s1, double c2, double s2,
+                                          double* o11, double* o12, double* o21, double* o22) {
+  const double y11 = fma(c1, x11, -(s1 * x21)), y12 = fma(c1, x12, -(s1 * x22));
+  const double y21 = fma(s1, x11, c1 * x21), y22 = fma(s1, x12, c1 * x22);
+  *o11 = fma(c2, y11, -(s2 * y12));
+  *o12 = fma(s2, y11, c2 * y12);
+  *o21 = fma(c2, y21, -(s2 * y22));
+  *o22 = fma(s2, y21, c2 * y22);
+}
+
+// 1/sqrt(x) for normal x > 0: the hardware estimate and two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-(x * y), y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-(x * y), y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// rotation (c, s) with J^T [[app, apq], [apq, aqq]] J diagonal (apq != 0):
+// t = tan(phi) = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = aqq - app, e = 2 apq,
+// c = 1 / sqrt(1 + t^2), s = t c -- written with g = |d| + sqrt(d^2 + e^2) as
+// c = g / sqrt(g^2 + e^2), s = sign(d) e / sqrt(g^2 + e^2), two square roots
+// and no division.  Outside the range where d^2 + e^2 is a normal number the
+// textbook form with divisions is used.
+__device__ __forceinline__ void jacobi_cs(double app, double aqq, double apq, double* c,
+                                          double* s) {
+  const double d = aqq - app, e = 2.0 * apq;
+  const double h2 = fma(d, d, e * e);
+  if (h2 > 1e-300 && h2 < 1e300) {
+    const double h = h2 * rsqrt_nr(h2);
+    const double g = fabs(d) + h;
+    const double r = rsqrt_nr(fma(g, g, e * e));
+    *c = g * r;
+    *s = (d < 0.0 ? -e : e) * r;
     return;
   }
-  const int nrot = lds_jacobi(a, u, thresh, inner);
-  double* Uo = U + int64_t(blockIdx.x) * JP * JP;
-  for (int idx = threadIdx.x; idx < JP * JP; idx += kPairThreads) {
+  const double theta = d / e;
+  const double t = fabs(theta) > 1e150
+                       ? 0.5 / theta
+                       : copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+  *c = 1.0 / sqrt(t * t + 1.0);
+  *s = t * (*c);
+}
+
+// One workgroup per pair of the outer round: gather the JP x JP subproblem,
+// skip it when already diagonal (to the threshold), else one Jacobi sweep.
+// Writes U (JP x JP) and skip[pair] (1 = U is the identity).
+__global__ __launch_bounds__(kPairThreads) void k_jacobi_pair_solve(
+    const double* A, int64_t lda, int nblk, int round, const double* scale, double tol, double* U,
+    int* skip, int* counter) {
+  __shared__ double buf[2][JP * LDJ];
+  __shared__ double2 cs[2][kHalf];
+  __shared__ double wmax[kPairThreads / 64];
+  __shared__ int nrot_total;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int I, J;
+  block_pair(blockIdx.x, round, nblk, &I, &J);
+  // round 0 has index s in slot s
+  double mx = 0.0;
+  for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
     const int i = idx % JP, j = idx / JP;
-    Uo[i + j * JP] = u[i + j * LDJ];
+    if (i < j) continue;
+    const double v = A[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
+    buf[0][i + j * LDJ] = v;
+    if (i != j) mx = fmax(mx, fabs(v));
   }
-  if (threadIdx.x == 0) {
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if (lane == 0) wmax[wave] = mx;
+  if (tid == 0) nrot_total = 0;
+  __syncthreads();
+  mx = wmax[0];
+#pragma unroll
+  for (int w = 1; w < kPairThreads / 64; ++w) mx = fmax(mx, wmax[w]);
+  const double thresh = tol * (*scale);
+  if (!(mx > thresh)) {
+    if (tid == 0) skip[blockIdx.x] = 1;
+    return;
+  }
+  if (wave == 0 && lane < kHalf) {
+    const int f = lane, s = JP - 1 - lane;
+    const double apq = buf[0][sym_idx(s, f)];
+    double c = 1.0, sn = 0.0;
+    if (fabs(apq) > thresh) jacobi_cs(buf[0][sym_idx(f, f)], buf[0][sym_idx(s, s)], apq, &c, &sn);
+    cs[0][lane] = make_double2(c, sn);
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // next-round pair `lane` = this round's slots x (first) and y (second)
+    const int k = lane < kHalf ? lane : 0;
+    const int x = slot_prev(k), y = slot_prev(JP - 1 - k);
+    const int kx = slot_pair(x), ky = slot_pair(y);
+    // diagonal blocks of kx and ky: first/second slots and which output
+    const int fx = kx, sx = JP - 1 - kx, fy = ky, sy = JP - 1 - ky;
+    const int ax_ff = sym_idx(fx, fx), ax_sf = sym_idx(sx, fx), ax_ss = sym_idx(sx, sx);
+    const int ay_ff = sym_idx(fy, fy), ay_sf = sym_idx(sy, fy), ay_ss = sym_idx(sy, sy);
+    const bool x_first = x == fx, y_first = y == fy;
+    // off-diagonal (y, x): block (K1, K2) = rows of the pair with the larger index
+    const bool xrow = kx > ky;
+    const int K1 = xrow ? kx : ky, K2 = xrow ? ky : kx;
+    const int f1 = K1, s1 = JP - 1 - K1, f2 = K2, s2 = JP - 1 - K2;
+    const int b11 = sym_idx(f1, f2), b12 = sym_idx(f1, s2), b21 = sym_idx(s1, f2),
+              b22 = sym_idx(s1, s2);
+    const int rowv = xrow ? x : y, colv = xrow ? y : x;
+    const int osel = (rowv == f1 ? 0 : 2) + (colv == f2 ? 0 : 1);
+    int count = 0;
+    for (int r = 0; r < kRounds; ++r) {
+      const double* a = buf[r & 1];
+      const double2* t = cs[r & 1];
+      if (lane < kHalf) {
+        const unsigned long long m = __ballot(t[lane].y != 0.0);
+        if (r + 1 < kRounds) {
+          const double2 tx = t[kx], ty = t[ky], t1 = t[K1], t2 = t[K2];
+          double o11, o12, o21, o22;
+          const double xsf = a[ax_sf];
+          rot_block(a[ax_ff], xsf, xsf, a[ax_ss], tx.x, tx.y, tx.x, tx.y, &o11, &o12, &o21, &o22);
+          const double app = x_first ? o11 : o22;
+          const double ysf = a[ay_sf];
+          rot_block(a[ay_ff], ysf, ysf, a[ay_ss], ty.x, ty.y, ty.x, ty.y, &o11, &o12, &o21, &o22);
+          const double aqq = y_first ? o11 : o22;
+          rot_block(a[b11], a[b12], a[b21], a[b22], t1.x, t1.y, t2.x, t2.y, &o11, &o12, &o21,
+                    &o22);
+          const double apq = osel == 0 ? o11 : (osel == 1 ? o12 : (osel == 2 ? o21 : o22));
+          double c = 1.0, sn = 0.0;
+          if (fabs(apq) > thresh) jacobi_cs(app, aqq, apq, &c, &sn);
+          cs[(r + 1) & 1][lane] = make_double2(c, sn);
+        }
+        count += __popcll(m);
+      }
+      __syncthreads();
+    }
+    if (lane == 0) nrot_total = count;
+  } else if (wave >= 2) {
+    // block (k1, k2), k1 >= k2, of the 16 x 16 pair blocks (136 of 192 threads)
+    const int idx = tid - 128;
+    int k1 = 0, k2 = 0;
+    {
+      int rem = idx;
+      while (k1 < kHalf && rem > k1) {
+        rem -= k1 + 1;
+        ++k1;
+      }
+      k2 = rem;
+    }
+    const bool active = idx < kHalf * (kHalf + 1) / 2;
+    const int f1 = k1, s1 = JP - 1 - k1, f2 = k2, s2 = JP - 1 - k2;
+    const int i11 = sym_idx(f1, f2), i12 = sym_idx(f1, s2), i21 = sym_idx(s1, f2),
+              i22 = sym_idx(s1, s2);
+    const int o11i = sym_idx(slot_next(f1), slot_next(f2)),
+              o12i = sym_idx(slot_next(f1), slot_next(s2)),
+              o21i = sym_idx(slot_next(s1), slot_next(f2)),
+              o22i = sym_idx(slot_next(s1), slot_next(s2));
+    for (int r = 0; r < kRounds; ++r) {
+      if (active) {
+        const double* a = buf[r & 1];
+        double* o = buf[(r + 1) & 1];
+        const double2 t1 = cs[r & 1][k1], t2 = cs[r & 1][k2];
+        double v11, v12, v21, v22;
+        if (k1 == k2) {
+          const double x21 = a[i21];
+          rot_block(a[i11], x21, x21, a[i22], t1.x, t1.y, t1.x, t1.y, &v11, &v12, &v21, &v22);
+          o[o11i] = v11;
+          o[o22i] = v22;
+          o[o21i] = t1.y != 0.0 ? 0.0 : x21;
+        } else {
+          rot_block(a[i11], a[i12], a[i21], a[i22], t1.x, t1.y, t2.x, t2.y, &v11, &v12, &v21,
+                    &v22);
+          o[o11i] = v11;
+          o[o12i] = v12;
+          o[o21i] = v21;
+          o[o22i] = v22;
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    double ur[JP];
+#pragma unroll
+    for (int j = 0; j < JP; ++j) ur[j] = (j == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      if (lane < JP) {
+#pragma unroll
+        for (int k = 0; k < kHalf; ++k) {
+          // indices in slots k and JP-1-k at round r
+          const int p = (k == 0) ? 0 : 1 + (k - 1 + r) % (JP - 1);
+          const int q = 1 + (JP - 2 - k + r) % (JP - 1);
+          const double2 t = cs[r & 1][k];
+          const double up = ur[p], uq = ur[q];
+          ur[p] = fma(t.x, up, -(t.y * uq));
+          ur[q] = fma(t.y, up, t.x * uq);
+        }
+      }
+      __syncthreads();
+    }
+    // row `lane` of U into LDS (the subproblem itself is no longer needed)
+    if (lane < JP) {
+#pragma unroll
+      for (int j = 0; j < JP; ++j) buf[0][lane + j * LDJ] = ur[j];
+    }
+  }
+  __syncthreads();
+  double* Uo = U + int64_t(blockIdx.x) * JP * JP;
+  for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
+    const int i = idx % JP, j = idx / JP;
+    Uo[i + j * JP] = buf[0][i + j * LDJ];
+  }
+  if (tid == 0) {
     skip[blockIdx.x] = 0;
-    if (nrot > 0) atomicAdd(counter, nrot);
+    if (nrot_total > 0) atomicAdd(counter, nrot_total);
   }
 }
 
@@ -335,66 +458,72 @@ __device__ __forceinline__ void load_u_or_identity(double* dst, const double* U,
   }
 }
 
-// A[SP, SQ] <- U_P^T A[SP, SQ] U_Q for pair blocks P (blockIdx.x), Q (blockIdx.y)
-__global__ __launch_bounds__(256) void k_jacobi_apply_A(double* A, int64_t lda, int nblk,
-                                                        int round, const double* U,
-                                                        const int* skip) {
-  const bool sp = skip[blockIdx.x] != 0, sq = skip[blockIdx.y] != 0;
-  if (sp && sq) return;
+// The outer round's rotations, one launch: blockIdx.y < npairs updates the
+// matrix block pair (P, Q) = (blockIdx.x, blockIdx.y), P >= Q:
+// A[SP, SQ] <- U_P^T A[SP, SQ] U_Q, written with its transpose into A[SQ, SP];
+// blockIdx.y >= npairs updates JP rows (chunk blockIdx.y - npairs) of the
+// eigenvector accumulator: V[rows, SP] <- V[rows, SP] U_P.
+__global__ __launch_bounds__(256) void k_jacobi_apply(double* A, int64_t lda, double* V,
+                                                      int64_t ldv, int nblk, int npairs,
+                                                      int round, const double* U,
+                                                      const int* skip) {
   __shared__ double m[JP * LDJ];
   __shared__ double up[JP * LDJ];
   __shared__ double uq[JP * LDJ];
-  int IP, JPb, IQ, JQ;
-  block_pair(blockIdx.x, round, nblk, &IP, &JPb);
-  block_pair(blockIdx.y, round, nblk, &IQ, &JQ);
+  const int P = blockIdx.x;
+  int IP, JPb;
+  block_pair(P, round, nblk, &IP, &JPb);
+  double t[NT][NT][4];
+  if (int(blockIdx.y) >= npairs) {
+    if (skip[P]) return;
+    const int64_t r0 = int64_t(blockIdx.y - npairs) * JP;
+    for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+      const int i = idx % JP, j = idx / JP;
+      m[i + j * LDJ] = V[r0 + i + int64_t(pair_index(j, IP, JPb)) * ldv];
+    }
+    load_u_or_identity(up, U + int64_t(P) * JP * JP, false);
+    __syncthreads();
+    lds_mm<false>(m, up, t);
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          V[r0 + mm_row(i, r) + int64_t(pair_index(mm_col(j), IP, JPb)) * ldv] = t[i][j][r];
+    return;
+  }
+  const int Q = blockIdx.y;
+  if (P < Q) return;
+  const bool sp = skip[P] != 0, sq = skip[Q] != 0;
+  if (sp && sq) return;
+  int IQ, JQ;
+  block_pair(Q, round, nblk, &IQ, &JQ);
   for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
     const int i = idx % JP, j = idx / JP;
     m[i + j * LDJ] = A[pair_index(i, IP, JPb) + int64_t(pair_index(j, IQ, JQ)) * lda];
   }
-  load_u_or_identity(up, U + int64_t(blockIdx.x) * JP * JP, sp);
-  load_u_or_identity(uq, U + int64_t(blockIdx.y) * JP * JP, sq);
+  load_u_or_identity(up, U + int64_t(P) * JP * JP, sp);
+  load_u_or_identity(uq, U + int64_t(Q) * JP * JP, sq);
   __syncthreads();
-  double t[NT][NT][4];
   lds_mm<true>(up, m, t);         // U_P^T M
   __syncthreads();
   lds_mm_store(m, t);
   __syncthreads();
   lds_mm<false>(m, uq, t);        // (U_P^T M) U_Q
-#pragma unroll
-  for (int i = 0; i < NT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        A[pair_index(mm_row(i, r), IP, JPb) + int64_t(pair_index(mm_col(j), IQ, JQ)) * lda] =
-            t[i][j][r];
-}
-
-// V[rows chunk, SP] <- V[rows chunk, SP] U_P ; blockIdx.x = pair, blockIdx.y = JP-row chunk
-__global__ __launch_bounds__(256) void k_jacobi_apply_V(double* V, int64_t ldv, int nblk,
-                                                        int round, const double* U,
-                                                        const int* skip) {
-  if (skip[blockIdx.x]) return;
-  __shared__ double m[JP * LDJ];
-  __shared__ double up[JP * LDJ];
-  int IP, JPb;
-  block_pair(blockIdx.x, round, nblk, &IP, &JPb);
-  const int64_t r0 = int64_t(blockIdx.y) * JP;
+  __syncthreads();
+  lds_mm_store(m, t);
+  __syncthreads();
   for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
     const int i = idx % JP, j = idx / JP;
-    m[i + j * LDJ] = V[r0 + i + int64_t(pair_index(j, IP, JPb)) * ldv];
+    A[pair_index(i, IP, JPb) + int64_t(pair_index(j, IQ, JQ)) * lda] = m[i + j * LDJ];
   }
-  load_u_or_identity(up, U + int64_t(blockIdx.x) * JP * JP, false);
-  __syncthreads();
-  double t[NT][NT][4];
-  lds_mm<false>(m, up, t);
-#pragma unroll
-  for (int i = 0; i < NT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        V[r0 + mm_row(i, r) + int64_t(pair_index(mm_col(j), IP, JPb)) * ldv] = t[i][j][r];
+  if (P != Q) {
+    for (int idx = threadIdx.x; idx < JP * JP; idx += 256) {
+      const int i = idx % JP, j = idx / JP;
+      A[pair_index(i, IQ, JQ) + int64_t(pair_index(j, IP, JPb)) * lda] = m[j + i * LDJ];
+    }
+  }
 }
 
 // padded copy: P (bp x bp) = [A 0; 0 0]; V = I
@@ -624,21 +753,16 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   // sweep cap (knob CHFSI_JACOBI_MAX_SWEEPS, for tests of the cap's report)
   int max_outer = 40;
   if (const char* e = std::getenv("CHFSI_JACOBI_MAX_SWEEPS")) max_outer = std::max(1, std::atoi(e));
-  // inner Jacobi sweeps per pair subproblem (one suffices for the block
-  // method's convergence; the knob is for tuning)
-  int inner = 1;
-  if (const char* e = std::getenv("CHFSI_JACOBI_INNER")) inner = std::max(1, std::atoi(e));
   int sweeps = 0;
   int host_count = 0;
   for (; sweeps < max_outer; ++sweeps) {
     if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
     for (int r = 0; r < nblk - 1; ++r) {
       k_jacobi_pair_solve<<<dim3(npairs), kPairThreads, 0, st>>>(P, bp, nblk, r, scal, tol, U,
-                                                                 skip, counter, inner);
+                                                                 skip, counter);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      k_jacobi_apply_A<<<dim3(npairs, npairs), 256, 0, st>>>(P, bp, nblk, r, U, skip);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      k_jacobi_apply_V<<<dim3(npairs, unsigned(bp / JP)), 256, 0, st>>>(Vp, bp, nblk, r, U, skip);
+      k_jacobi_apply<<<dim3(npairs, unsigned(npairs + bp / JP)), 256, 0, st>>>(
+          P, bp, Vp, bp, nblk, npairs, r, U, skip);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = hipMemcpyAsync(&host_count, counter, sizeof(int), hipMemcpyDeviceToHost, st)) !=

@@ -860,6 +860,168 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(KernelArgs<float> arg
   }
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// BF16 product on v_mfma_f32_32x32x16_bf16 for aligned shapes (M % 128 == 0,
+// N % (64 TN) == 0, K and the split length multiples of 64, 16-byte aligned
+// operands with leading dimensions multiples of 8).  A 32 x 32 x 16 product
+// reads one 16-byte fragment of each operand per lane for 32 x 32 x 16 x 2
+// flops, half the operand traffic per flop of the 16 x 16 x 32 form.
+//  * Workgroup tile 128 x 64 TN, four waves as 2 (m) x 2 (n), each wave
+//    64 x 32 TN (2 x TN accumulator tiles of 32 x 32).
+//  * The right operand (N x K, K contiguous) is staged through LDS in 64-deep
+//    slices, double-buffered; its rows are 128 bytes with the 16-byte chunks
+//    XOR-swizzled by (row & 7), so that the eight rows a fragment read touches
+//    at once fall on distinct banks.
+//  * The left operand (M x K, K contiguous) goes from global memory straight
+//    into registers, two slices ahead: lane l (row l % 32, half h = l / 32)
+//    takes k = h*32 + 8s .. +8 at step s of a slice, i.e. 64 contiguous bytes
+//    per row and slice.  The right operand's fragments use the same order of
+//    k, which leaves every dot product's terms unchanged.
+template <int TN>
+__global__ __launch_bounds__(256, 1) void gemm_bf16_wide_kernel(
+    KernelArgs<float> args, const unsigned short* __restrict__ A16,
+    const unsigned short* __restrict__ B16) {
+  constexpr int BM = 128, BN = 64 * TN, BK = 64, TM = 2;
+  constexpr int NVB = BN * BK / 8 / 256;       // 16-byte right-operand vectors per thread
+  static_assert(NVB * 8 * 256 == BN * BK, "tile / thread mismatch");
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN * BK];
+
+  const KernelArgsCommon& c = args.c;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int tiles_mn = c.tiles_m * c.tiles_n;
+  const int n_tile = t % c.tiles_n;
+  const int m_tile = (t / c.tiles_n) % c.tiles_m;
+  const int split = t / tiles_mn;
+  const int64_t m0 = int64_t(m_tile) * BM, n0 = int64_t(n_tile) * BN;
+  const int64_t kbeg = int64_t(split) * c.kchunk;
+  const int64_t kend = std::min<int64_t>(c.K, kbeg + c.kchunk);
+  const int nk = kend > kbeg ? int((kend - kbeg) / BK) : 0;
+  const int64_t lda = c.sam, ldb = c.sbn;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l32 = lane & 31, h = lane >> 5;
+
+  const unsigned short* Ap[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) Ap[i] = A16 + (m0 + wm * 64 + i * 32 + l32) * lda + kbeg + h * 32;
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  u16x8_t a0[TM][4], a1[TM][4], a2[TM][4];
+  u16x8_t bst[NVB];
+  auto load_a = [&](u16x8_t (&R)[TM][4], int s) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        R[i][q] = *reinterpret_cast<const u16x8_t*>(Ap[i] + int64_t(s) * BK + q * 8);
+  };
+  auto load_b = [&](int s) __attribute__((always_inline)) {
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const int idx = threadIdx.x + v * 256, row = idx >> 3, ch = idx & 7;
+      bst[v] = *reinterpret_cast<const u16x8_t*>(B16 + (n0 + row) * ldb + kbeg +
+                                                  int64_t(s) * BK + ch * 8);
+    }
+  };
+  auto store_b = [&](int stg) __attribute__((always_inline)) {
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const int idx = threadIdx.x + v * 256, row = idx >> 3, ch = idx & 7;
+      *reinterpret_cast<u16x8_t*>(&Bs[stg][row * BK + ((ch ^ (row & 7)) << 3)]) = bst[v];
+    }
+  };
+  auto compute = [&](int stg, const u16x8_t (&R)[TM][4]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      bf16x8_t bf[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int row = wn * 32 * TN + j * 32 + l32, ch = 4 * h + s;
+        bf[j] = __builtin_bit_cast(
+            bf16x8_t, *reinterpret_cast<const u16x8_t*>(&Bs[stg][row * BK + ((ch ^ (row & 7)) << 3)]));
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const bf16x8_t af = __builtin_bit_cast(bf16x8_t, R[i][s]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  // one step of the slice loop: slice kt in stage kt & 1 with left-operand
+  // registers RC; slice kt + 2 is loaded into RN, slice kt + 1's right operand
+  // goes to the other stage
+  auto step = [&](int kt, const u16x8_t (&RC)[TM][4], u16x8_t (&RN)[TM][4])
+      __attribute__((always_inline)) {
+    if (kt + 2 < nk) load_a(RN, kt + 2);
+    compute(kt & 1, RC);
+    if (kt + 1 < nk) store_b((kt + 1) & 1);
+    __syncthreads();
+    if (kt + 2 < nk) load_b(kt + 2);
+  };
+
+  if (nk > 0) {
+    load_a(a0, 0);
+    load_b(0);
+    store_b(0);
+    if (nk > 1) {
+      load_a(a1, 1);
+      load_b(1);
+    }
+  }
+  __syncthreads();
+  // three left-operand register sets rotate: slices kt, kt+1 in flight, kt+2 loading
+  int kt = 0;
+  for (; kt + 3 <= nk; kt += 3) {
+    step(kt, a0, a2);
+    step(kt + 1, a1, a0);
+    step(kt + 2, a2, a1);
+  }
+  if (kt < nk) step(kt, a0, a2);
+  if (kt + 1 < nk) step(kt + 1, a1, a0);
+
+  // output element r of tile (i, j): row 8 (r / 4) + 4 h + r % 4, column l32
+  if (c.splits == 1) {
+    const Epilogue<float> e = args.epi;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * 32 * TN + j * 32 + l32;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t m = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+          args.C[m + n * c.ldc] = apply_epilogue(e, acc[i][j][r], m, n);
+        }
+      }
+  } else {
+    float* P = args.partial + int64_t(split) * c.M * c.N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t n = n0 + wn * 32 * TN + j * 32 + l32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int64_t m = m0 + wm * 64 + i * 32 + 8 * g + 4 * h;
+          *reinterpret_cast<f32x4*>(P + m + n * c.M) =
+              f32x4{acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2],
+                    acc[i][j][4 * g + 3]};
+        }
+      }
+  }
+}
+
 // B16 (n x b, ld ldo) = bfloat16(kscale .* B) (nearest-even)
 __global__ __launch_bounds__(256) void k_scale_bf16(const float* __restrict__ B, int64_t ldb,
                                                     const float* __restrict__ ks, int64_t n,
@@ -882,7 +1044,9 @@ __global__ __launch_bounds__(256) void k_scale_bf16(const float* __restrict__ B,
 // Split-K factor (after rounding the k-range to whole 64-deep slices) and
 // k-range length of the BF16 product: enough work items for ~4 per CU,
 // at least 8 slices per split, at most 16 splits.
-template <int BM, int BN>
+// The 32 x 32 x 16 kernel (WIDE) runs one workgroup per CU: splits until the
+// work items reach the CU count.
+template <int BM, int BN, bool WIDE = false>
 static int bf16_splits(int64_t M, int64_t N, int64_t K, int force_splits, int64_t* kchunk_out) {
   constexpr int BK = 64;
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
@@ -890,7 +1054,8 @@ static int bf16_splits(int64_t M, int64_t N, int64_t K, int force_splits, int64_
   if (splits <= 0) {
     splits = 1;
     const int64_t max_s = std::max<int64_t>(1, K / (8 * BK));
-    while (tiles * splits < int64_t(kNumCU) * 4 && splits * 2 <= max_s && splits < 16) splits *= 2;
+    const int64_t target = int64_t(kNumCU) * (WIDE ? 1 : 4);
+    while (tiles * splits < target && splits * 2 <= max_s && splits < 16) splits *= 2;
   }
   int64_t kchunk = (K + splits - 1) / splits;
   kchunk = (kchunk + BK - 1) / BK * BK;
@@ -900,7 +1065,7 @@ static int bf16_splits(int64_t M, int64_t N, int64_t K, int force_splits, int64_
   return std::max(splits, 1);
 }
 
-template <int BM, int BN>
+template <int BM, int BN, bool WIDE = false>
 static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
                                    uint16_t* B16, hipStream_t st, const Workspace& ws,
                                    int force_splits) {
@@ -936,7 +1101,7 @@ static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16
   c.tiles_n = int((d.N + BN - 1) / BN);
   const int64_t tiles = int64_t(c.tiles_m) * c.tiles_n;
   int64_t kchunk = 0;
-  const int splits = bf16_splits<BM, BN>(d.M, d.N, d.K, force_splits, &kchunk);
+  const int splits = bf16_splits<BM, BN, WIDE>(d.M, d.N, d.K, force_splits, &kchunk);
   c.kchunk = kchunk;
   c.splits = splits;
   a.A = nullptr;
@@ -961,10 +1126,15 @@ static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16
                        reinterpret_cast<uintptr_t>(B16) % 16 == 0;
   const unsigned short* a16 = reinterpret_cast<const unsigned short*>(A16);
   const unsigned short* b16 = reinterpret_cast<const unsigned short*>(B16);
-  if (aligned)
+  if constexpr (WIDE) {
+    static_assert(BM == 128 && BN % 64 == 0, "wide tile shape");
+    if (!aligned) return hipErrorInvalidValue;
+    gemm_bf16_wide_kernel<BN / 64><<<dim3(unsigned(grid)), dim3(256), 0, st>>>(a, a16, b16);
+  } else if (aligned) {
     gemm_bf16_kernel<BM, BN, BK, false><<<dim3(unsigned(grid)), dim3(256), 0, st>>>(a, a16, b16);
-  else
+  } else {
     gemm_bf16_kernel<BM, BN, BK, true><<<dim3(unsigned(grid)), dim3(256), 0, st>>>(a, a16, b16);
+  }
   if ((err = hipGetLastError()) != hipSuccess) return err;
   if (c.splits > 1) {
     const int64_t total = d.M * d.N;
@@ -993,9 +1163,26 @@ static int bf16_tile() {
   return tile;
 }
 
+// the 32 x 32 x 16 kernel for shapes it takes (knob CHFSI_BF16_WIDE=0: off)
+static bool bf16_wide() {
+  static const bool on = [] {
+    const char* e = std::getenv("CHFSI_BF16_WIDE");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return on;
+}
+
 hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
                             uint16_t* B16, hipStream_t st, const Workspace& ws,
                             int force_splits) {
+  const bool wide_ok = bf16_wide() && d.sbk == 1 && d.batch == 1 && A16 && B16 &&
+                       d.M % 128 == 0 && d.K % 64 == 0 && lda16 % 8 == 0 &&
+                       reinterpret_cast<uintptr_t>(A16) % 16 == 0 &&
+                       reinterpret_cast<uintptr_t>(B16) % 16 == 0;
+  if (wide_ok && d.N % 320 == 0)
+    return gemm_bf16_launch<128, 320, true>(d, A16, lda16, B16, st, ws, force_splits);
+  if (wide_ok && d.N % 128 == 0)
+    return gemm_bf16_launch<128, 128, true>(d, A16, lda16, B16, st, ws, force_splits);
   switch (bf16_tile()) {
     case 1: return gemm_bf16_launch<64, 160>(d, A16, lda16, B16, st, ws, force_splits);
     case 2: return gemm_bf16_launch<128, 64>(d, A16, lda16, B16, st, ws, force_splits);

@@ -59,6 +59,29 @@ def _ritz_start(p, seed=5):
     return rr.rayleigh_ritz(X0, filters.dense_op(p.A), Bop)
 
 
+@pytest.mark.parametrize("n,block", [(768, 128), (1024, 128), (1280, 320)])
+def test_rchfsi_bf16_filter_aligned_shapes(n, block):
+    """Shapes the 32 x 32 x 16 BF16 product takes (n a multiple of 128, the
+    block of 128 or 320): one split with the epilogue in the product (768),
+    two splits with the reduction (1024, 1280); column-by-column bounds as for
+    the other BF16 filters."""
+    p = wl.dense_generalized(n=n, n_low=block // 2, block=block, degree=8, seed=n + block)
+    w = sla.eigvalsh(p.A, p.B)
+    bounds = (w[0] - 0.1, w[-1] + 0.5, 0.5 * (w[block - 1] + w[block]))
+    params = P.make_params(block // 2, block, 8, method=P.METHOD_RCHFSI,
+                           filter_prec=P.PREC_BF16, lambda_max=bounds[1])
+    ctx = _ctx(p, params)
+    st = _ritz_start(p)
+    X, lam, R = st["X"], st["lam"], st["R"]
+    Yd = P.colmajor_empty(p.n, p.block)
+    P.chfsi_filter(ctx, dev(X), lam, dev(R), Yd, *bounds, degree=8)
+    torch.cuda.synchronize()
+    ref, RYp, _ = filters.residual_filter(filters.dense_op(p.A), filters.diag_op(p.dinv), X, lam,
+                                          R, 8, *bounds, return_parts=True)
+    assert_columns(host(Yd), ref, residual_part(RYp, p.dinv), "bf16", 8, p.n,
+                   f"bf16 aligned n={n} b={block}")
+
+
 @pytest.mark.parametrize("prec", [P.PREC_FP64, P.PREC_FP32])
 def test_chfsi_filter_matches_oracle(gen_problem, prec):
     p, w = gen_problem
