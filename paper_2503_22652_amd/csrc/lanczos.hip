@@ -75,9 +75,9 @@ __global__ __launch_bounds__(kThreads) void k_dot2_partial(const double* __restr
   }
 }
 
-// out[t] = sum_b partial[2 b + t] over nb blocks, one wave, fixed order
+// *out0 (and *out1) = sum_b partial[2 b + t] over nb blocks, one wave, fixed order
 __global__ __launch_bounds__(64) void k_dot2_final(const double* __restrict__ partial, int nb,
-                                                   double* out) {
+                                                   double* out0, double* out1) {
   double s0 = 0.0, s1 = 0.0;
   for (int b = threadIdx.x; b < nb; b += 64) {
     s0 += partial[2 * b];
@@ -86,8 +86,8 @@ __global__ __launch_bounds__(64) void k_dot2_final(const double* __restrict__ pa
   s0 = wave_sum(s0);
   s1 = wave_sum(s1);
   if (threadIdx.x == 0) {
-    out[0] = s0;
-    out[1] = s1;
+    *out0 = s0;
+    if (out1) *out1 = s1;
   }
 }
 
@@ -104,14 +104,43 @@ __global__ __launch_bounds__(kThreads) void k_lincomb3(double a, const double* x
   }
 }
 
-// one CG update: x += alpha p; r -= alpha q; z = dinv .* r; partial sums of
-// r . r and r . z
-__global__ __launch_bounds__(kThreads) void k_cg_update(double alpha, const double* __restrict__ p,
+// out = a x - (*bp) y + c z (null z skipped): a coefficient that stays on the device
+__global__ __launch_bounds__(kThreads) void k_lincomb3_dev(double a, const double* x,
+                                                           const double* __restrict__ bp,
+                                                           const double* y, double c,
+                                                           const double* z, int64_t L,
+                                                           double* out) {
+  const double b = -*bp;
+  for (int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x; i < L;
+       i += int64_t(gridDim.x) * kThreads) {
+    double v = a * x[i];
+    v += b * y[i];
+    if (z) v += c * z[i];
+    out[i] = v;
+  }
+}
+
+// CG direction p = z + (*rz_new / *rz_old) p
+__global__ __launch_bounds__(kThreads) void k_cg_dir(const double* __restrict__ rz_new,
+                                                     const double* __restrict__ rz_old,
+                                                     const double* z, int64_t L, double* p) {
+  const double beta = *rz_new / *rz_old;
+  for (int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x; i < L;
+       i += int64_t(gridDim.x) * kThreads)
+    p[i] = z[i] + beta * p[i];
+}
+
+// one CG update with alpha = *rz / *pq: x += alpha p; r -= alpha q;
+// z = dinv .* r; partial sums of r . r and r . z
+__global__ __launch_bounds__(kThreads) void k_cg_update(const double* __restrict__ rz,
+                                                        const double* __restrict__ pq,
+                                                        const double* __restrict__ p,
                                                         const double* __restrict__ q, double* x,
                                                         double* r, double* z,
                                                         const double* __restrict__ dinv,
                                                         int64_t L, double* partial) {
   __shared__ double lds[kThreads / 64];
+  const double alpha = *rz / *pq;
   double srr = 0.0, srz = 0.0;
   for (int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x; i < L;
        i += int64_t(gridDim.x) * kThreads) {
@@ -221,11 +250,13 @@ hipError_t lanczos_bounds(const LanczosOps& ops, int64_t L, double* work, double
   do {                                    \
     if ((e = (x)) != hipSuccess) return e; \
   } while (0)
+  // device scalars: dres[0] r.r, dres[1..2] r.z (alternating), dres[3] p.B p,
+  // dres[4] alpha_j, dres[5] ||u||_B^2
   // two dot products on the device, read back (synchronises the stream)
   auto dot2 = [&](const double* a0, const double* b0, const double* a1, const double* b1,
                   double* o0, double* o1) -> hipError_t {
     k_dot2_partial<<<nb, kThreads, 0, st>>>(a0, b0, a1, b1, L, partial);
-    k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres);
+    k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres, dres + 1);
     hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return e2;
     e2 = hipMemcpyAsync(host_scalars, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -236,34 +267,37 @@ hipError_t lanczos_bounds(const LanczosOps& ops, int64_t L, double* work, double
     if (o1) *o1 = host_scalars[1];
     return hipSuccess;
   };
-  // solve B x = y by preconditioned CG from x = 0 (relative tolerance cg_tol)
+  // solve B x = y by preconditioned CG from x = 0 (relative tolerance cg_tol);
+  // alpha and the direction update take their scalars on the device, so each
+  // iteration reads back once (the convergence test)
   auto bsolve = [&](const double* y, double* x) -> hipError_t {
     LZ_CK(fill_zero(x, size_t(L) * sizeof(double), st));
     LZ_CK(hipMemcpyAsync(r, y, size_t(L) * sizeof(double), hipMemcpyDeviceToDevice, st));
     k_precond<<<lb, kThreads, 0, st>>>(ops.dinv, r, L, z);
     LZ_CK(hipGetLastError());
     LZ_CK(hipMemcpyAsync(p, z, size_t(L) * sizeof(double), hipMemcpyDeviceToDevice, st));
-    double rr0 = 0.0, rz = 0.0;
-    LZ_CK(dot2(r, r, r, z, &rr0, &rz));
+    double rr0 = 0.0, rz0 = 0.0;
+    LZ_CK(dot2(r, r, r, z, &rr0, &rz0));             // dres[0] = r.r, dres[1] = r.z
     if (!(rr0 > 0.0)) return hipSuccess;
     const double stop = ops.cg_tol * ops.cg_tol * rr0;
+    double* rz_cur = dres + 1;
+    double* rz_nxt = dres + 2;
     for (int it = 0; it < ops.cg_max_iter; ++it) {
       LZ_CK(ops.apply_B(p, q));
-      double pq = 0.0;
-      LZ_CK(dot2(p, q, nullptr, nullptr, &pq, nullptr));
-      if (!(pq > 0.0)) return hipErrorInvalidValue;   // B not positive definite
-      const double alpha = rz / pq;
-      k_cg_update<<<nb, kThreads, 0, st>>>(alpha, p, q, x, r, z, ops.dinv, L, partial);
-      k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres);
+      k_dot2_partial<<<nb, kThreads, 0, st>>>(p, q, nullptr, nullptr, L, partial);
+      k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres + 3, nullptr);
+      k_cg_update<<<nb, kThreads, 0, st>>>(rz_cur, dres + 3, p, q, x, r, z, ops.dinv, L,
+                                           partial);
+      k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres, rz_nxt);
       LZ_CK(hipGetLastError());
-      LZ_CK(hipMemcpyAsync(host_scalars, dres, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      LZ_CK(hipMemcpyAsync(host_scalars, dres, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       LZ_CK(hipStreamSynchronize(st));
-      const double rr = host_scalars[0], rz_new = host_scalars[1];
+      if (!(host_scalars[3] > 0.0)) return hipErrorInvalidValue;   // B not positive definite
       res->cg_iterations += 1;
-      if (rr <= stop) break;
-      k_lincomb3<<<lb, kThreads, 0, st>>>(1.0, z, rz_new / rz, p, 0.0, nullptr, L, p);
+      if (host_scalars[0] <= stop) break;
+      k_cg_dir<<<lb, kThreads, 0, st>>>(rz_nxt, rz_cur, z, L, p);
       LZ_CK(hipGetLastError());
-      rz = rz_new;
+      std::swap(rz_cur, rz_nxt);
     }
     return hipSuccess;
   };
@@ -291,15 +325,21 @@ hipError_t lanczos_bounds(const LanczosOps& ops, int64_t L, double* work, double
       LZ_CK(bsolve(w, u));                            // u = B^{-1} A v_j
     else
       LZ_CK(hipMemcpyAsync(u, w, size_t(L) * sizeof(double), hipMemcpyDeviceToDevice, st));
-    double a = 0.0;
-    LZ_CK(dot2(v, w, nullptr, nullptr, &a, nullptr));
-    alpha.push_back(a);
+    // alpha_j = v_j . w stays on the device until ||u||_B is read back with it
+    k_dot2_partial<<<nb, kThreads, 0, st>>>(v, w, nullptr, nullptr, L, partial);
+    k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres + 4, nullptr);
     // u -= a v_j + beta_{j-1} v_{j-1};  B u = w - a B v_j - beta_{j-1} B v_{j-1} (into w)
-    k_lincomb3<<<lb, kThreads, 0, st>>>(1.0, u, -a, v, -beta_prev, j > 0 ? v_prev : nullptr, L, u);
-    k_lincomb3<<<lb, kThreads, 0, st>>>(1.0, w, -a, Bv, -beta_prev, j > 0 ? Bv_prev : nullptr, L, w);
+    k_lincomb3_dev<<<lb, kThreads, 0, st>>>(1.0, u, dres + 4, v, -beta_prev,
+                                            j > 0 ? v_prev : nullptr, L, u);
+    k_lincomb3_dev<<<lb, kThreads, 0, st>>>(1.0, w, dres + 4, Bv, -beta_prev,
+                                            j > 0 ? Bv_prev : nullptr, L, w);
+    k_dot2_partial<<<nb, kThreads, 0, st>>>(u, w, nullptr, nullptr, L, partial);
+    k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres + 5, nullptr);
     LZ_CK(hipGetLastError());
-    double bb = 0.0;
-    LZ_CK(dot2(u, w, nullptr, nullptr, &bb, nullptr));
+    LZ_CK(hipMemcpyAsync(host_scalars, dres + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    LZ_CK(hipStreamSynchronize(st));
+    const double a = host_scalars[0], bb = host_scalars[1];
+    alpha.push_back(a);
     const double bj = std::sqrt(std::max(bb, 0.0));
     beta.push_back(bj);
     if (j + 1 == ops.steps || !(bj > 1e-14 * std::fabs(a) + 1e-300)) break;
