@@ -36,45 +36,39 @@ constexpr int JP = 2 * JB;      // Jacobi pair subproblem size
 constexpr int LDJ = JP + 1;     // padded LDS leading dimension
 
 // ---------------------------------------------------------------------------
-// Cholesky of the diagonal block (jb <= 64) in LDS; right-looking.
+// Cholesky of the diagonal block (jb <= 64) in LDS; right-looking, one barrier
+// per column: step k subtracts a_ik a_jk / d_k (d_k = a_kk at step k) from the
+// trailing lower triangle, the columns are scaled by 1/sqrt(d_k) at the end.
+// Threads form a 16 x 16 grid over the trailing triangle (no index division).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int jb, int* info,
                                                     int j0) {
   __shared__ double a[NB * (NB + 1)];
-  __shared__ int fail;
   constexpr int L = NB + 1;
-  if (threadIdx.x == 0) fail = (*info != 0);
+  if (*info != 0) return;
   for (int idx = threadIdx.x; idx < jb * jb; idx += 256) {
     const int i = idx % jb, j = idx / jb;
     a[i + j * L] = A[i + j * lda];
   }
   __syncthreads();
-  if (fail) return;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   for (int k = 0; k < jb; ++k) {
-    if (threadIdx.x == 0) {
-      const double d = a[k + k * L];
-      if (!(d > 0.0) || !isfinite(d)) {
-        fail = 1;
-        atomicCAS(info, 0, j0 + k + 1);
-      } else {
-        a[k + k * L] = sqrt(d);
-      }
+    const double d = a[k + k * L];
+    if (!(d > 0.0) || !isfinite(d)) {      // the same decision in every thread
+      if (threadIdx.x == 0) atomicCAS(info, 0, j0 + k + 1);
+      return;
     }
-    __syncthreads();
-    if (fail) return;
-    const double piv = a[k + k * L];
-    for (int i = k + 1 + threadIdx.x; i < jb; i += 256) a[i + k * L] /= piv;
-    __syncthreads();
-    const int m = jb - k - 1;
-    for (int idx = threadIdx.x; idx < m * m; idx += 256) {
-      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (j <= i) a[i + j * L] -= a[i + k * L] * a[j + k * L];
+    const double inv = 1.0 / d;
+    for (int j = k + 1 + ty; j < jb; j += 16) {
+      const double ljk = a[j + k * L] * inv;
+      for (int i = j + tx; i < jb; i += 16) a[i + j * L] -= a[i + k * L] * ljk;
     }
     __syncthreads();
   }
   for (int idx = threadIdx.x; idx < jb * jb; idx += 256) {
     const int i = idx % jb, j = idx / jb;
-    A[i + j * lda] = (i >= j) ? a[i + j * L] : 0.0;
+    const double dj = sqrt(a[j + j * L]);
+    A[i + j * lda] = i > j ? a[i + j * L] / dj : (i == j ? dj : 0.0);
   }
 }
 
@@ -567,6 +561,34 @@ __global__ __launch_bounds__(64) void k_fro_final(const double* part, double* ou
   }
 }
 
+// largest off-diagonal magnitude of the bp x bp matrix: per-workgroup column
+// ranges (k_offmax_part), then out[0] = 1 if it is at most thresh_rel * scal[0]
+// (the Frobenius norm), else 0
+__global__ __launch_bounds__(256) void k_offmax_part(const double* P, int64_t bp, double* part) {
+  __shared__ double red[256];
+  double m = 0.0;
+  const int64_t c0 = bp * blockIdx.x / kFroParts, c1 = bp * (blockIdx.x + 1) / kFroParts;
+  for (int64_t idx = threadIdx.x; idx < (c1 - c0) * bp; idx += 256) {
+    const int64_t i = idx % bp, j = c0 + idx / bp;
+    if (i != j) m = fmax(m, fabs(P[i + j * bp]));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(64) void k_offmax_final(const double* part, const double* scal,
+                                                     double thresh_rel, int* done) {
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < kFroParts; ++i) m = fmax(m, part[i]);
+    *done = (m <= thresh_rel * scal[0]) ? 1 : 0;
+  }
+}
+
 // ascending sort of the diagonal (first b entries) by rank counting, then
 // gather eigenvector columns
 __global__ __launch_bounds__(256) void k_jacobi_rank(const double* P, int64_t bp, int64_t b,
@@ -755,6 +777,7 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   if (const char* e = std::getenv("CHFSI_JACOBI_MAX_SWEEPS")) max_outer = std::max(1, std::atoi(e));
   int sweeps = 0;
   int host_count = 0;
+  bool converged = false;
   for (; sweeps < max_outer; ++sweeps) {
     if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
     for (int r = 0; r < nblk - 1; ++r) {
@@ -765,11 +788,19 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
           P, bp, Vp, bp, nblk, npairs, r, U, skip);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = hipMemcpyAsync(&host_count, counter, sizeof(int), hipMemcpyDeviceToHost, st)) !=
+    // converged when the sweep rotated nothing, or when no off-diagonal entry
+    // is left above the threshold (every pair of a further sweep would skip)
+    k_offmax_part<<<kFroParts, 256, 0, st>>>(P, bp, scal + 16);
+    k_offmax_final<<<1, 64, 0, st>>>(scal + 16, scal, tol, counter + 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int host_flags[2] = {0, 0};
+    if ((e = hipMemcpyAsync(host_flags, counter, 2 * sizeof(int), hipMemcpyDeviceToHost, st)) !=
         hipSuccess)
       return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-    if (host_count == 0) {
+    host_count = host_flags[0];
+    if (host_count == 0 || host_flags[1] != 0) {
+      converged = true;
       ++sweeps;
       break;
     }
@@ -779,8 +810,8 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   k_jacobi_gather<<<grid_for(b * b), 256, 0, st>>>(Vp, bp, b, perm, V, ldv);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (sweeps_out) *sweeps_out = sweeps;
-  // the last sweep still rotated: the tolerance was not met within the cap
-  if (unconverged_out) *unconverged_out = host_count != 0 ? 1 : 0;
+  // the tolerance was not met within the cap
+  if (unconverged_out) *unconverged_out = converged ? 0 : 1;
   return hipSuccess;
 }
 
