@@ -193,6 +193,16 @@ typedef struct {
    * context then holds FP32 filter blocks from the start (dense: also an FP32
    * copy of A), as an FP32 context does. */
   int32_t escalate;
+  /* Amplification guard.  A pass filters the unwanted end of the spectrum by
+   * up to T_p(|L(lambda_min)|) relative to the damped interval (L maps
+   * [lambda_T, lambda_max] onto [-1, 1]); rounding in a reduced-precision
+   * filter is amplified by that much (Section 3.1's condition), and past
+   * ~1e12 a pass is likely to lose the wanted columns' accuracy.  Every pass
+   * reports it (report max_amplification; flags bit 4 when it exceeds 1e12).
+   * amp_cap > 0 caps it: a pass then filters at the largest degree
+   * p' <= degree with T_p'(|L(lambda_min)|) <= amp_cap (at least 1; flags
+   * bit 5, report min_degree_used).  0: no cap. */
+  double amp_cap;
 } chfsi_params;
 
 /* Per-solve report (host). */
@@ -212,7 +222,10 @@ typedef struct {
                                   bit 1: a Jacobi eigensolve reached its cap of 40 sweeps
                                   with rotations still applied (not fully diagonalised);
                                   bit 2: the solve stopped on stagnation (stall_iters);
-                                  bit 3: the filter precision was escalated to FP32 */
+                                  bit 3: the filter precision was escalated to FP32;
+                                  bit 4: a pass's amplification T_p(|L(lambda_min)|)
+                                  exceeded 1e12;
+                                  bit 5: amp_cap lowered a pass's degree */
   double history[CHFSI_MAX_HISTORY]; /* max residual after each pass (entry 0: initial RR) */
   int32_t svqb_events;         /* Rayleigh-Ritz passes that took the SVQB fallback */
   int32_t svqb_dropped;        /* directions dropped (and refilled) by those passes, summed */
@@ -221,6 +234,9 @@ typedef struct {
   int32_t best_iteration;      /* pass with the lowest max residual (0: initial RR) */
   double best_residual;        /* that lowest max residual */
   int32_t escalation_iteration;/* params.escalate: pass after which FP32 took over (0: none) */
+  double max_amplification;    /* largest T_p(|L(lambda_min)|) of the passes, at the degree used */
+  int32_t min_degree_used;     /* smallest filter degree of the passes (params.degree unless
+                                  amp_cap lowered it; 0 if no pass ran) */
 } chfsi_report;
 
 typedef struct chfsi_ctx chfsi_ctx;

@@ -46,7 +46,8 @@ class chfsi_params(C.Structure):
                 ("init_random", C.c_int32), ("profile", C.c_int32),
                 ("memory_mode", C.c_int32), ("binv_exact", C.c_int32),
                 ("lanczos_steps", C.c_int32), ("stall_iters", C.c_int32),
-                ("keep_best", C.c_int32), ("escalate", C.c_int32)]
+                ("keep_best", C.c_int32), ("escalate", C.c_int32),
+                ("amp_cap", C.c_double)]
 
 
 class chfsi_report(C.Structure):
@@ -59,7 +60,8 @@ class chfsi_report(C.Structure):
                 ("svqb_events", C.c_int32), ("svqb_dropped", C.c_int32),
                 ("lambda_max_used", C.c_double), ("time_bounds_ms", C.c_double),
                 ("best_iteration", C.c_int32), ("best_residual", C.c_double),
-                ("escalation_iteration", C.c_int32)]
+                ("escalation_iteration", C.c_int32),
+                ("max_amplification", C.c_double), ("min_degree_used", C.c_int32)]
 
 
 class chfsi_server_config(C.Structure):
@@ -256,7 +258,7 @@ def make_params(n_wanted: int, block: int, degree: int, max_iter: int = 100, tol
                 lambda_T: float = math.nan, seed: int = 0, init_random: int = 0,
                 profile: int = 0, memory_mode: int = 0, binv_exact: int = 0,
                 lanczos_steps: int = 0, stall_iters: int = 0,
-                keep_best: int = 0, escalate: int = 0) -> chfsi_params:
+                keep_best: int = 0, escalate: int = 0, amp_cap: float = 0.0) -> chfsi_params:
     p = chfsi_params()
     p.n_wanted, p.block, p.degree, p.max_iter, p.tol = n_wanted, block, degree, max_iter, tol
     p.method, p.filter_prec = method, filter_prec
@@ -268,6 +270,7 @@ def make_params(n_wanted: int, block: int, degree: int, max_iter: int = 100, tol
     p.stall_iters = stall_iters
     p.keep_best = keep_best
     p.escalate = escalate
+    p.amp_cap = amp_cap
     return p
 
 
@@ -396,6 +399,7 @@ def report_dict(rep: chfsi_report) -> dict:
             "lambda_max_used": rep.lambda_max_used, "time_bounds_ms": rep.time_bounds_ms,
             "best_iteration": rep.best_iteration, "best_residual": rep.best_residual,
             "escalation_iteration": rep.escalation_iteration,
+            "max_amplification": rep.max_amplification, "min_degree_used": rep.min_degree_used,
             "kernel_launches": rep.kernel_launches, "kernel_ms": rep.kernel_ms,
             "history": [rep.history[i] for i in range(min(it + 1, MAX_HISTORY))]}
 

@@ -98,25 +98,42 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const TR* __restrict__
   }
 }
 
-// one workgroup per column: strided partial sums, then a fixed LDS tree
+// one workgroup per column: 16-byte loads (two doubles per lane) when the
+// column is 16-byte aligned, per-lane partial sums, a butterfly across each
+// wave's 64 lanes, then the wave sums in a fixed order (deterministic)
 __global__ __launch_bounds__(kThreads) void k_column_norms(const double* __restrict__ R,
                                                             int64_t ldr, int64_t n,
                                                             double* out) {
-  __shared__ double red[kThreads];
+  __shared__ double wsum[kThreads / 64];
   const int64_t j = blockIdx.x;
   const double* col = R + j * ldr;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+  double s0 = 0.0, s1 = 0.0;
+  int64_t tail = 0;
+  if ((reinterpret_cast<uintptr_t>(col) & 15) == 0) {
+    const int64_t nv = n / 2;
+    const double2* cv = reinterpret_cast<const double2*>(col);
+#pragma unroll 4
+    for (int64_t v = threadIdx.x; v < nv; v += kThreads) {
+      const double2 x = cv[v];
+      s0 += x.x * x.x;
+      s1 += x.y * x.y;
+    }
+    tail = 2 * nv;
+  }
+  for (int64_t i = tail + threadIdx.x; i < n; i += kThreads) {
     const double v = col[i];
-    s += v * v;
+    s0 += v * v;
   }
-  red[threadIdx.x] = s;
+  double s = s0 + s1;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += wsum[w];
+    out[j] = sqrt(t);
   }
-  if (threadIdx.x == 0) out[j] = sqrt(red[0]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_convert(const double* __restrict__ in, int64_t ldi,

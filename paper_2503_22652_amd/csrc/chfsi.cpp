@@ -28,6 +28,20 @@ using namespace chfsi;
 
 namespace {
 
+// the CholQR factorisation of a Gram matrix under a roctx range
+hipError_t potrf_traced(double* A, int64_t lda, int64_t b, int* info, hipStream_t st,
+                        const Workspace& ws, double* tri) {
+  TraceRange tr("chfsi cholqr factor");
+  return potrf_lower(A, lda, b, info, st, ws, tri);
+}
+
+// the eigensolver under a roctx range
+hipError_t syev_traced(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
+                       hipStream_t st, const Workspace& ws, int* sweeps, int* unconverged) {
+  TraceRange tr("chfsi jacobi eigensolve");
+  return syev_jacobi(A, lda, b, w, V, ldv, st, ws, sweeps, unconverged);
+}
+
 thread_local std::string g_last_error;
 
 void set_error(const char* fmt, ...) {
@@ -1270,7 +1284,7 @@ chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, cons
   hipStream_t st = c->stream;
   chfsi_status s;
   int sweeps = 0;
-  CK(syev_jacobi(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1325,7 +1339,7 @@ chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, cons
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, b, k, st));
-  CK(syev_jacobi(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -1361,6 +1375,7 @@ chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, cons
 chfsi_status rotate_and_residual(chfsi_ctx* c, const double* Y, int64_t ldy, const double* BY,
                                  int64_t ldby, const double* Tm, int64_t k, double* X,
                                  int64_t ldx, double* R, int64_t ldr) {
+  TraceRange tr("chfsi rotation + residual");
   const int64_t n = c->n, b = c->b;
   hipStream_t st = c->stream;
   auto rotate = [&](const double* Src, int64_t lds, const double* Tmat, double* Dst, int64_t ldd,
@@ -1444,7 +1459,7 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   // column scaling s = diag(Gb)^{-1/2}; Cholesky of the scaled Gram matrix
   CK(scale_gram(c->Gb, b, b, c->Gs, b, c->svec, c->dflags + 1, st));
   CK(copy_block(c->Gs, b, c->Linv, b, b, b, st));      // kept for the SVQB fallback
-  CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws, c->tri));
+  CK(potrf_traced(c->Gs, b, b, c->dflags, st, c->ws, c->tri));
   CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   if (c->h_flags[1] != 0) {
@@ -1494,7 +1509,7 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   }
   CK(symmetrize(c->Hp, b, b, st));
   int sweeps = 0;
-  CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -1597,7 +1612,7 @@ chfsi_status rayleigh_ritz_complex_svqb(chfsi_ctx* c, const double* Y, int64_t l
   const int64_t n = c->n, b = c->b, m = 2 * b;
   hipStream_t st = c->stream;
   int sweeps = 0;
-  CK(syev_jacobi(c->Linv, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Linv, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, m * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1656,7 +1671,7 @@ chfsi_status rayleigh_ritz_complex_svqb(chfsi_ctx* c, const double* Y, int64_t l
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, m, 2 * k, st));
-  CK(syev_jacobi(c->Hp, m, 2 * k, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, m, 2 * k, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -1864,7 +1879,7 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
   // CholQR of the scaled embedded Gram matrix, projected matrix, Jacobi
   CK(scale_gram(c->Gb, m, m, c->Gs, m, c->svec, c->dflags + 1, st));
   CK(copy_block(c->Gs, m, c->Linv, m, m, m, st));      // kept for the SVQB fallback
-  CK(potrf_lower(c->Gs, m, m, c->dflags, st, c->ws, c->tri));
+  CK(potrf_traced(c->Gs, m, m, c->dflags, st, c->ws, c->tri));
   CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   if (c->h_flags[1] != 0) {
@@ -1912,7 +1927,7 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
   }
   CK(symmetrize(c->Hp, m, m, st));
   int sweeps = 0;
-  CK(syev_jacobi(c->Hp, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -2032,7 +2047,7 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
   if ((s = slab_grams(c, X, ldx)) != CHFSI_OK) return s;
   CK(scale_gram(c->Gb, b, b, c->Gs, b, c->svec, c->dflags + 1, st));
   CK(copy_block(c->Gs, b, c->Linv, b, b, b, st));
-  CK(potrf_lower(c->Gs, b, b, c->dflags, st, c->ws, c->tri));
+  CK(potrf_traced(c->Gs, b, b, c->dflags, st, c->ws, c->tri));
   CK(hipMemcpyAsync(c->h_flags, c->dflags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   if (c->h_flags[1] != 0) {
@@ -2071,7 +2086,7 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     h.ldc = b;
     CK(gemm<double>(h, st, c->ws));
     CK(symmetrize(c->Hp, b, b, st));
-    CK(syev_jacobi(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+    CK(syev_traced(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
     c->last_sweeps += sweeps;
     GemmDesc<double> t;
@@ -2098,7 +2113,7 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     return CHFSI_ERR_NOT_SPD;
   }
   // SVQB on the scaled Gram matrix kept in c->Linv (same reading as rayleigh_ritz_svqb)
-  CK(syev_jacobi(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2152,7 +2167,7 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, b, k, st));
-  CK(syev_jacobi(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -2181,6 +2196,7 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
 // context's operators: real blocks of length n, or planar complex vectors of
 // length 2 n ([re; im], the Bloch operators in the twisted frame)
 chfsi_status estimate_bounds(chfsi_ctx* c, const double* v0_user, int steps, LanczosResult* res) {
+  TraceRange tr("chfsi lanczos bound estimate");
   const int64_t n = c->n;
   const int64_t L = c->cplx ? 2 * n : n;
   hipStream_t st = c->stream;
@@ -2264,6 +2280,24 @@ void bounds_policy(const chfsi_params& p, double lmax_used, const double* ritz, 
   const double e1 = ritz[0], eb = ritz[b - 1];
   *lmin = std::isnan(p.lambda_min) ? e1 - 0.05 * (eb - e1) : p.lambda_min;
   *lT = std::isnan(p.lambda_T) ? eb : p.lambda_T;
+}
+
+// Amplification of one pass (Section 3.1's condition): the filter maps
+// [lT, lmax] onto [-1, 1] by L(x) = (x - c) / e, c = (lT + lmax) / 2,
+// e = (lmax - lT) / 2, and scales the lowest part of the spectrum by up to
+// T_p(|L(lmin)|) = cosh(p acosh |L(lmin)|) relative to it.  With amp_cap > 0
+// the pass uses the largest p' <= p whose amplification stays within the cap
+// (at least 1).  Returns the degree; *amp receives its amplification.
+int pass_degree(const chfsi_params& prm, double lmin, double lmax, double lT, double* amp) {
+  const double cc = 0.5 * (lT + lmax), e = 0.5 * (lmax - lT);
+  const double ax = std::acosh(std::max(std::fabs((lmin - cc) / e), 1.0));
+  int p = prm.degree;
+  if (prm.amp_cap > 0.0 && ax > 0.0) {
+    const double pmax = std::acosh(std::max(prm.amp_cap, 1.0)) / ax;
+    if (pmax < double(p)) p = std::max(1, int(std::floor(pmax)));
+  }
+  *amp = std::cosh(double(p) * ax);
+  return p;
 }
 
 }  // namespace
@@ -2406,6 +2440,10 @@ chfsi_status chfsi::create_with_allocator(chfsi_ctx** out, const chfsi_operator*
   }
   if (params->lanczos_steps < 0 || params->stall_iters < 0) {
     set_error("lanczos_steps and stall_iters must be >= 0");
+    return CHFSI_ERR_ARG;
+  }
+  if (!(params->amp_cap >= 0.0)) {
+    set_error("amp_cap must be >= 0 (0: no cap)");
     return CHFSI_ERR_ARG;
   }
   if (params->escalate != 0 &&
@@ -2717,6 +2755,7 @@ extern "C" {
 chfsi_status chfsi_filter(chfsi_ctx* c, const double* X, int64_t ldx, const double* ritz,
                           const double* resid, int64_t ldr, double* Yp, int64_t ldy, double lmin,
                           double lmax, double lT, int32_t degree) {
+  TraceRange tr("chfsi_filter");
   if (!c || !X || !Yp) {
     set_error("ctx, X and Yp must be non-null");
     return CHFSI_ERR_ARG;
@@ -2767,6 +2806,7 @@ chfsi_status chfsi_filter_kernel_time(chfsi_ctx* c, double* total_ms, int32_t* l
 chfsi_status chfsi_rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X,
                                  int64_t ldx, double* R, int64_t ldr, double* ritz,
                                  double* resnorm) {
+  TraceRange tr("chfsi_rayleigh_ritz");
   if (!c || !Y || !X || !R || !ritz || !resnorm) {
     set_error("null argument");
     return CHFSI_ERR_ARG;
@@ -2820,6 +2860,7 @@ chfsi_status chfsi_estimate_bounds(chfsi_ctx* c, const double* v0, int32_t steps
 
 chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, double* resnorms,
                          chfsi_report* rep) {
+  TraceRange tr("chfsi_solve");
   if (!c || !X || !evals || !resnorms) {
     set_error("null argument");
     return CHFSI_ERR_ARG;
@@ -2909,22 +2950,35 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
       st = CHFSI_ERR_ARG;
       break;
     }
+    double amp = 0.0;
+    const int deg = pass_degree(c->prm, lmin, lmax, lT, &amp);
+    r.max_amplification = std::max(r.max_amplification, amp);
+    r.min_degree_used = r.min_degree_used == 0 ? deg : std::min(r.min_degree_used, deg);
+    if (amp > 1e12) c->flags |= 16;
+    if (deg < c->prm.degree) c->flags |= 32;
     CK(hipEventRecord(c->ev[0], c->stream));
-    if (c->cplx)
-      st = filter_rchfsi_complex(c, c->Xw, n, ritz.data(), c->R, n, c->Yw, n, lmin, lmax, lT,
-                                 c->prm.degree, &r.filter_flops);
-    else if (c->prm.method == CHFSI_METHOD_RCHFSI)
-      st = filter_rchfsi(c, Xw, ldw, ritz.data(), c->R, n, slabs ? Xw : c->Yw, slabs ? ldw : n,
-                         lmin, lmax, lT, c->prm.degree, &r.filter_flops);
-    else
-      st = filter_chfsi(c, c->Xw, n, c->Yw, n, lmin, lmax, lT, c->prm.degree, &r.filter_flops);
+    {
+      TraceRange tr("chfsi filter");
+      if (c->cplx)
+        st = filter_rchfsi_complex(c, c->Xw, n, ritz.data(), c->R, n, c->Yw, n, lmin, lmax, lT,
+                                   deg, &r.filter_flops);
+      else if (c->prm.method == CHFSI_METHOD_RCHFSI)
+        st = filter_rchfsi(c, Xw, ldw, ritz.data(), c->R, n, slabs ? Xw : c->Yw,
+                           slabs ? ldw : n, lmin, lmax, lT, deg, &r.filter_flops);
+      else
+        st = filter_chfsi(c, c->Xw, n, c->Yw, n, lmin, lmax, lT, deg, &r.filter_flops);
+    }
     if (st != CHFSI_OK) break;
     CK(hipEventRecord(c->ev[1], c->stream));
     c->last_sweeps = 0;
-    st = c->cplx ? rayleigh_ritz_complex(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(),
-                                         norms.data())
-         : slabs ? rayleigh_ritz_slabs(c, Xw, ldw, c->R, n, ritz.data(), norms.data(), true)
-                 : rayleigh_ritz(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(), norms.data(), true);
+    {
+      TraceRange tr("chfsi rayleigh-ritz");
+      st = c->cplx ? rayleigh_ritz_complex(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(),
+                                           norms.data())
+           : slabs ? rayleigh_ritz_slabs(c, Xw, ldw, c->R, n, ritz.data(), norms.data(), true)
+                   : rayleigh_ritz(c, c->Yw, n, c->Xw, n, c->R, n, ritz.data(), norms.data(),
+                                   true);
+    }
     if (st != CHFSI_OK) break;
     CK(hipEventRecord(c->ev[3], c->stream));
     CK(hipEventSynchronize(c->ev[3]));

@@ -8,11 +8,24 @@
 #include <atomic>
 #include <functional>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/chfsi.h"
 
 struct chfsi_ctx;
 
 namespace chfsi {
+
+// roctx range over a phase of the solver (filter, Rayleigh-Ritz, CholQR,
+// eigensolve, residual, bound estimate), visible with rocprofv3 --marker-trace
+// and free when no tool is attached.
+class TraceRange {
+ public:
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Memory source of a context (the server's pools): device and pinned host
 // allocations; frees return memory to the source.  A context without one

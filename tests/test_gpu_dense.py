@@ -403,3 +403,45 @@ def test_bf16_stagnation_escalates_to_fp32():
             np.testing.assert_allclose(ev[:10], w[:10], rtol=1e-10, atol=1e-10 * anorm)
         else:
             assert st == P.ERR_NOCONV and rep["flags"] & 4
+
+
+def test_amplification_guard_reports_and_caps():
+    """Section 3.1's amplification T_p(|L(lambda_min)|) of a pass: one pass is
+    reported as the oracle's closed form from the start block's Ritz values
+    (bounds policy: lambda_min = eps_1 - 0.05 (eps_b - eps_1), lambda_T = eps_b);
+    a degree-40 pass exceeds 1e12 (flags bit 4); with amp_cap every pass stays
+    within the cap at a lower degree (flags bit 5) and the solve still reaches
+    LAPACK's eigenvalues."""
+    from oracle import chebyshev
+    p = wl.dense_generalized(n=1024, n_low=32, block=40, degree=40, seed=91)
+    w = sla.eigvalsh(p.A, p.B)
+    lmax = float(w[-1]) + 0.5
+    X0 = wl.random_block(p.n, p.block, 92)
+    st0 = rr.rayleigh_ritz(X0, filters.dense_op(p.A), filters.dense_op(p.B))
+    e1, eb = float(st0["lam"][0]), float(st0["lam"][-1])
+    lmin, lT = e1 - 0.05 * (eb - e1), eb
+    e, c, _ = chebyshev.affine(lmin, lmax, lT)
+    ref = float(chebyshev.cheb_T(40, np.array([(lmin - c) / e]))[0])
+    ref = abs(ref)
+    params = P.make_params(32, 40, 40, max_iter=1, tol=1e-30, method=P.METHOD_RCHFSI,
+                           filter_prec=P.PREC_FP32, lambda_max=lmax)
+    ctx = _ctx(p, params)
+    st, ev, rn, rep = P.chfsi_solve(ctx, dev(X0))
+    print("one pass: amplification", rep["max_amplification"], "oracle", ref, "flags", rep["flags"])
+    assert rep["min_degree_used"] == 40
+    assert abs(rep["max_amplification"] - ref) <= 1e-6 * ref
+    assert bool(rep["flags"] & 16) == (ref > 1e12) and not rep["flags"] & 32
+    cap = 1e8
+    params = P.make_params(32, 40, 40, max_iter=100, tol=1e-10, method=P.METHOD_RCHFSI,
+                           filter_prec=P.PREC_FP32, lambda_max=lmax, amp_cap=cap)
+    ctx = _ctx(p, params)
+    st, ev, rn, rep = P.chfsi_solve(ctx, dev(X0))
+    print("capped:", rep["iterations"], "passes, degree >=", rep["min_degree_used"],
+          "amplification", rep["max_amplification"], "flags", rep["flags"])
+    assert st == P.OK
+    assert rep["flags"] & 32 and not rep["flags"] & 16
+    assert 1 <= rep["min_degree_used"] < 40 and rep["max_amplification"] <= cap
+    np.testing.assert_allclose(ev[:32], w[:32], rtol=0, atol=1e-10 * np.max(np.abs(w[:32])))
+    with pytest.raises(P.ChfsiError):
+        P.chfsi_create(P.dense_operator(dev(p.A)), None, None,
+                       P.make_params(8, 16, 8, lambda_max=lmax, amp_cap=math.nan))
