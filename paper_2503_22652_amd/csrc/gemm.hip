@@ -454,6 +454,196 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(KernelArgs<T> args) 
 }
 
 // ---------------------------------------------------------------------------
+// FP64 Gram product C = A B over a long k range (A: M x K, B: K x N, both
+// k-contiguous; M = N; only tiles reaching the diagonal or below): the
+// Rayleigh-Ritz Gram matrices Y^T W of the grid pencils.
+//
+// A 256 x 128 tile per workgroup of eight waves (4 x 2, 64 x 64 each on
+// v_mfma_f64_16x16x4f64), one workgroup per CU.  Split-K over the eight XCDs:
+// every workgroup of one k-range runs on one XCD, and with at most 32 tiles
+// per k-range (M <= 1280) all of them are resident at once on that XCD's 32
+// CUs, start together and march through k at the same pace, so each k-slice
+// of Y and W is fetched into that XCD's L2 about once and read there by every
+// tile that needs it.  (With 128 x 64 tiles, 109 tiles per k-range at
+// b = 1200 cannot all be resident; the late ones re-read their panels.)
+// Measured at 128^3 x 1200: 76 GB of L2 fills per Gram product (operands
+// 40 GB) against 336 GB, 76 ms against 84 ms: two waves per SIMD and one
+// slice of prefetch (a second register set does not fit) leave it at half
+// the FP64 MFMA peak.  Partial sums go to the split-K buffer; the reduction
+// applies the epilogue.
+// ---------------------------------------------------------------------------
+constexpr int kGramBM = 256, kGramBN = 128, kGramBK = 16, kGramLDK = kGramBK + 2;
+
+__global__ __launch_bounds__(512, 1) void gram_f64_kernel(KernelArgs<double> args, int ntiles) {
+  using MF = Mfma<double>;
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  __shared__ __attribute__((aligned(16))) double As[2][kGramBM * kGramLDK];
+  __shared__ __attribute__((aligned(16))) double Bs[2][kGramBN * kGramLDK];
+  const KernelArgsCommon& c = args.c;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int split = t / ntiles;
+  int tile = t - split * ntiles;
+  // lower tiles in row-major order: row i holds n-tiles 0 .. min(2 (i + 1), tiles_n) - 1
+  int mi = 0;
+  for (;;) {
+    const int cnt = min(2 * (mi + 1), c.tiles_n);
+    if (tile < cnt) break;
+    tile -= cnt;
+    ++mi;
+  }
+  const int64_t m0 = int64_t(mi) * kGramBM, n0 = int64_t(tile) * kGramBN;
+  const int64_t kbeg = int64_t(split) * c.kchunk;
+  const int64_t kend = min(c.K, kbeg + c.kchunk);
+  const int nk = kend > kbeg ? int((kend - kbeg) / kGramBK) : 0;
+  const double* __restrict__ A = args.A;
+  const double* __restrict__ B = args.B;
+  const int64_t lda = c.sam, ldb = c.sbn;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 3, wn = wave >> 2;
+  const int l16 = lane & 15, lg = lane >> 4;
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // staging: A slice 256 rows x 16 k (4 vectors of 2 doubles per thread),
+  // B slice 128 rows x 16 k (2 per thread); rows past M (N) read as zero.
+  // One register set, loaded a slice ahead (two sets do not fit the 256
+  // registers of two waves per SIMD).
+  f64x2 ra[4], rb[2];
+  auto load = [&](int s) __attribute__((always_inline)) {
+    const int64_t k0 = kbeg + int64_t(s) * kGramBK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int v = threadIdx.x + q * 512, row = v >> 3, kk = (v & 7) * 2;
+      const int64_t gr = m0 + row;
+      ra[q] = gr < c.M ? *reinterpret_cast<const f64x2*>(A + gr * lda + k0 + kk) : f64x2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int v = threadIdx.x + q * 512, row = v >> 3, kk = (v & 7) * 2;
+      const int64_t gr = n0 + row;
+      rb[q] = gr < c.N ? *reinterpret_cast<const f64x2*>(B + gr * ldb + k0 + kk) : f64x2{0.0, 0.0};
+    }
+  };
+  auto store = [&](int stg) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int v = threadIdx.x + q * 512, row = v >> 3, kk = (v & 7) * 2;
+      *reinterpret_cast<f64x2*>(&As[stg][row * kGramLDK + kk]) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int v = threadIdx.x + q * 512, row = v >> 3, kk = (v & 7) * 2;
+      *reinterpret_cast<f64x2*>(&Bs[stg][row * kGramLDK + kk]) = rb[q];
+    }
+  };
+  auto compute = [&](int stg) __attribute__((always_inline)) {
+    const double* as = &As[stg][(wm * 64 + l16) * kGramLDK + lg];
+    const double* bs = &Bs[stg][(wn * 64 + l16) * kGramLDK + lg];
+#pragma unroll
+    for (int k4 = 0; k4 < kGramBK; k4 += 4) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = as[i * 16 * kGramLDK + k4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = bs[j * 16 * kGramLDK + k4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = MF::mma(af[i], bf[j], acc[i][j]);
+    }
+  };
+
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load(kt + 1);
+    compute(kt & 1);
+    if (kt + 1 < nk) store((kt + 1) & 1);
+    __syncthreads();
+  }
+
+  double* P = args.partial + int64_t(split) * c.M * c.N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t n = n0 + wn * 64 + j * 16 + l16;
+      if (n >= c.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 64 + i * 16 + MF::out_row(lg, r);
+        if (m < c.M) P[m + n * c.M] = acc[i][j][r];
+      }
+    }
+}
+
+// The Gram kernel for the shapes it takes (a long k range, lower only,
+// k-contiguous 16-byte aligned operands, K and the split length multiples of
+// 16, 1024 < M = N <= 1280 (20-30 tiles per k-range: enough workgroups to
+// fill the GPU, few enough to be resident together), room for the partial
+// sums); returns false otherwise.
+// Knob CHFSI_GRAM_KERNEL=0 turns it off.
+static bool gram_launch(const GemmDesc<double>& d, hipStream_t st, const Workspace& ws,
+                        hipError_t* err) {
+  static const bool on = [] {
+    const char* e = std::getenv("CHFSI_GRAM_KERNEL");
+    return !(e && std::atoi(e) == 0);
+  }();
+  if (!on || !d.lower_only || d.batch != 1 || d.kscale || d.sak != 1 || d.sbk != 1) return false;
+  if (d.M != d.N || d.M > 1280 || d.M <= 1024 || d.K < 16 * d.M || d.K % (kGramBK * 8) != 0)
+    return false;
+  if (reinterpret_cast<uintptr_t>(d.A) % 16 || reinterpret_cast<uintptr_t>(d.B) % 16 ||
+      d.sam % 2 || d.sbn % 2)
+    return false;
+  constexpr int splits = 8;   // one k-range per XCD
+  const size_t need = size_t(splits) * d.M * d.N * sizeof(double);
+  if (need > ws.bytes || ws.ptr == nullptr) return false;
+  KernelArgs<double> a;
+  KernelArgsCommon& c = a.c;
+  c.M = d.M;
+  c.N = d.N;
+  c.K = d.K;
+  c.sam = d.sam;
+  c.sak = 1;
+  c.sbk = 1;
+  c.sbn = d.sbn;
+  c.ldc = d.ldc;
+  c.batch = 1;
+  c.bsA = c.bsB = c.bsC = c.bsC1 = 0;
+  c.lower = 1;
+  c.tiles_m = int((d.M + kGramBM - 1) / kGramBM);
+  c.tiles_n = int((d.N + kGramBN - 1) / kGramBN);
+  c.kchunk = d.K / splits;   // a multiple of 16
+  c.splits = splits;
+  int ntiles = 0;
+  for (int i = 0; i < c.tiles_m; ++i) ntiles += std::min(2 * (i + 1), c.tiles_n);
+  a.A = d.A;
+  a.B = d.B;
+  a.kscale = nullptr;
+  a.C = d.C;
+  a.epi = d.epi;
+  a.partial = static_cast<double*>(ws.ptr);
+  if (d.ev_begin && (*err = hipEventRecord(d.ev_begin, st)) != hipSuccess) return true;
+  gram_f64_kernel<<<dim3(unsigned(ntiles * splits)), dim3(512), 0, st>>>(a, ntiles);
+  if ((*err = hipGetLastError()) != hipSuccess) return true;
+  const int64_t total = d.M * d.N;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+  splitk_reduce_kernel<double><<<dim3(blocks), dim3(256), 0, st>>>(a);
+  if ((*err = hipGetLastError()) != hipSuccess) return true;
+  if (d.ev_end && (*err = hipEventRecord(d.ev_end, st)) != hipSuccess) return true;
+  *err = hipSuccess;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // configurations and dispatch
 // ---------------------------------------------------------------------------
 struct Cfg {
@@ -680,6 +870,10 @@ hipError_t gemm(const GemmDesc<T>& d, hipStream_t st, const Workspace& ws, int f
     cfg = force_config;
   if (force_splits > 0) splits = force_splits;
   if (d.K <= 0) splits = 1;
+  if constexpr (sizeof(T) == 8) {
+    hipError_t gerr = hipSuccess;
+    if (force_config < 0 && force_splits <= 0 && gram_launch(d, st, ws, &gerr)) return gerr;
+  }
   if constexpr (sizeof(T) == 4) {
     if (!filter_layout) return launch_cfg<float, 64, 64, 32, 4>(d, st, ws, splits);
     switch (cfg) {

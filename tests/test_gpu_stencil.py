@@ -132,6 +132,29 @@ def test_rayleigh_ritz_wide_block(memory_mode):
                                atol=1e-11)
 
 
+def test_rayleigh_ritz_gram_kernel_block_1100():
+    """b = 1100 on a 24 x 28 x 32 grid (n = 21504 = 168 x 128): the Gram
+    matrices Y^T A Y and Y^T B Y take the 256 x 128 long-reduction kernel (29
+    lower tiles, eight k-ranges, ragged last row and column of tiles); Ritz
+    values, residual norms and X^T B X = I against the oracle."""
+    shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=(24, 28, 32), wells=4, seed=13)
+    n = int(np.prod(shape))
+    b = 1100
+    opA, opB, Vd = _ops(shape, cA, cB, V)
+    prm = P.make_params(900, b, 6, method=P.METHOD_RCHFSI, filter_prec=P.PREC_BF16,
+                        lambda_max=18.5)
+    ctx = P.chfsi_create(opA, opB, None, prm, keep=(Vd,))
+    Y = wl.random_block(n, b, 14)
+    Xd, Rd = P.colmajor_empty(n, b), P.colmajor_empty(n, b)
+    ritz, norms = P.chfsi_rayleigh_ritz(ctx, P.to_colmajor(Y), Xd, Rd)
+    o = rr.rayleigh_ritz(Y, apply_A, apply_B)
+    np.testing.assert_allclose(ritz, o["lam"], atol=1e-11 * np.abs(o["lam"]).max())
+    np.testing.assert_allclose(norms, o["resnorm"], rtol=1e-7)
+    X = Xd.cpu().numpy()
+    cols = np.arange(0, b, 37)
+    np.testing.assert_allclose(X[:, cols].T @ apply_B(X[:, cols]), np.eye(len(cols)), atol=1e-10)
+
+
 @pytest.mark.parametrize("prec", [P.PREC_FP64, P.PREC_BF16])
 def test_small_grid_solve(prec):
     shape, cA, cB, V, apply_A, apply_B = _grid_problem(shape=(8, 8, 8), wells=2, seed=5)
