@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--wanted", type=int, default=256)
     ap.add_argument("--degree", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-solve", type=str, default="",
+                    help="comma list of cfg0,cfg1: also time full CPU oracle solves at full size")
     ap.add_argument("--no-extras", action="store_true", help="skip time-to-residual runs")
     ap.add_argument("--dense-prec", choices=("fp32", "bf16"), default="fp32",
                     help="dense workload: precision of the timed residual-filter steps (the "
@@ -103,12 +105,37 @@ def parse():
     return ap.parse_args()
 
 
+def host_info():
+    """CPU model and the BLAS library NumPy dispatches to, for the CPU baselines."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = {"library": "unknown", "threads": None}
+    try:
+        from threadpoolctl import threadpool_info
+        for i in threadpool_info():
+            if i.get("user_api") == "blas":
+                blas = {"library": f"{i.get('internal_api')} {i.get('version')}",
+                        "arch": i.get("architecture"), "threads": i.get("num_threads")}
+                break
+    except ImportError:
+        pass
+    return {"cpu_model": model, "blas": blas}
+
+
 def cpu_baseline(prob, X0, seconds_target=20.0):
     """Time the CPU oracle's residual filter (Algorithm 3, FP64 NumPy) on a column sample."""
     import numpy as np
     from oracle import filters, rr
     n = prob.n
-    cores = len(os.sched_getaffinity(0))
+    hinfo = host_info()
+    cores = hinfo["blas"]["threads"] or len(os.sched_getaffinity(0))
     bcols = min(prob.block, 80)
     Xs = np.ascontiguousarray(X0[:, :bcols])
     o = rr.rayleigh_ritz(Xs, filters.dense_op(prob.A), filters.dense_op(prob.B))
@@ -126,9 +153,69 @@ def cpu_baseline(prob, X0, seconds_target=20.0):
     dt = (time.perf_counter() - t0) / reps
     flops = 2.0 * n * n * bcols * (p - 1)
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            **hinfo,
             "sample": f"Algorithm 3 FP64 NumPy filter, N={n}, {bcols} of {prob.block} columns "
                       f"(the filter is column-independent), degree {p}, {reps} pass(es), "
                       f"{dt:.2f} s per pass"}
+
+
+def cpu_solve_times(configs=("cfg0", "cfg1"), max_iter=60):
+    """Full solves of the CPU oracle (Algorithm 1, FP64 NumPy) at full size.
+
+    cfg0: dense standard N = 1024, 32 wanted, block 40, degree 16, tolerance 1e-10.
+    cfg1: dense generalized N = 8192, 256 wanted, block 320, degree 20, tolerance 1e-8;
+    R-ChFSI with the approximate inverse D^{-1}, and ChFSI with the exact B^{-1}
+    (Cholesky solves), the paper's FP64 baseline.  lambda_max comes from 12 oracle
+    Lanczos steps (Section 2.1's estimate), included in the time, as the GPU
+    solves estimate it inside the library.  Same seeded inputs as the GPU runs."""
+    import numpy as np
+    import scipy.linalg as sla
+    import workloads as wl
+    from oracle import bounds as obounds
+    from oracle import filters, solver
+    hinfo = host_info()
+    res = {"kind": "oracle", **hinfo,
+           "cores": hinfo["blas"]["threads"] or len(os.sched_getaffinity(0))}
+    for cfg in configs:
+        if cfg == "cfg0":
+            p = wl.dense_standard(n=1024, n_low=32, block=40, degree=16, seed=1000)
+            B = None
+            tol = 1e-10
+            runs = (("fp64_rchfsi", "rchfsi"), ("fp64_chfsi", "chfsi"))
+        else:
+            p = wl.dense_generalized(n=8192, n_low=256, block=320, degree=20, seed=1001)
+            B = p.B
+            tol = 1e-8
+            runs = (("fp64_rchfsi", "rchfsi"), ("fp64_chfsi", "chfsi"))
+        X0 = wl.random_block(p.n, p.block, 2001)
+        nw = p.n_wanted
+        apply_A = filters.dense_op(p.A)
+        out = {"n": p.n, "block": p.block, "wanted": nw, "degree": p.degree, "tol": tol}
+        for label, method in runs:
+            t0 = time.perf_counter()
+            if B is None:
+                apply_B = filters.identity_op()
+                dinv_op = filters.identity_op()
+                solve_B = lambda y: y
+            else:
+                apply_B = filters.dense_op(B)
+                cf = sla.cho_factor(B)
+                solve_B = lambda y, cf=cf: sla.cho_solve(cf, y)
+                dinv_op = (filters.diag_op(p.dinv) if method == "rchfsi"
+                           else (lambda V, cf=cf: sla.cho_solve(cf, V)))
+            v0 = wl.random_block(p.n, 1, 5)[:, 0]
+            est = obounds.lanczos_bounds(lambda x: p.A @ x, lambda x: apply_B(x[:, None])[:, 0],
+                                         solve_B, v0, 12)
+            r = solver.solve(apply_A, apply_B, dinv_op, X0, nw, p.degree, tol, max_iter,
+                             ("ritz", est["upper"]), method=method)
+            dt = time.perf_counter() - t0
+            out[label] = {"seconds": round(dt, 2), "iterations": int(r["iters"]),
+                          "converged": bool(r["converged"]),
+                          "max_res": float(np.max(r["resnorm"][:nw]))}
+            log(f"CPU oracle {cfg} {label}: {dt:.1f} s, {r['iters']} iterations, "
+                f"converged {r['converged']}")
+        res[cfg] = out
+    return res
 
 
 def main():
@@ -333,6 +420,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(prob, X0)
+    if args.cpu_solve:
+        out["cpu_solve"] = cpu_solve_times(tuple(c for c in args.cpu_solve.split(",") if c))
 
     # ------------------------------------------------------------------
     # grid extra: the 128^3 x 1200 BF16 grid pencil (HBM-bound stencil
@@ -567,7 +656,7 @@ def grid_cpu_baseline(prob, seconds_target=10.0):
     el_steps = float(n) * k * (p - 1)
     return {"value": round(el_steps * 8.0 / dt / 1e9, 2), "unit": "GB/s",
             "element_steps_per_s": round(el_steps / dt, 1), "cores": cstencil.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": host_info()["cpu_model"],
             "sample": f"Algorithm 3 FP64 C/OpenMP grid filter (oracle/stencil27.c), "
                       f"{shape[0]}^3 grid, {k} of {prob.block} columns (the filter is "
                       f"column-independent), degree {p}, {dt:.2f} s; rate in element-steps "
