@@ -53,6 +53,12 @@ def rayleigh_ritz(Y: np.ndarray, apply_A, apply_B, drop_tol: float = 1e-14):
     svqb = False
     dropped = 0
     try:
+        # breakdown: a Cholesky pivot of the unit-diagonal scaled Gram matrix at
+        # or below drop_tol (its smallest eigenvalue is then below drop_tol
+        # times the largest, so SVQB would drop a direction)
+        piv = np.abs(np.diag(np.linalg.cholesky(Gbs))) ** 2
+        if not np.min(piv) > drop_tol:
+            raise np.linalg.LinAlgError("numerically singular Gram matrix")
         lam, E = sla.eigh(Gas, Gbs)
         W = s[:, None] * E
     except np.linalg.LinAlgError:

@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -28,11 +29,15 @@ using namespace chfsi;
 
 namespace {
 
-// the CholQR factorisation of a Gram matrix under a roctx range
+// The CholQR factorisation of a column-scaled (unit-diagonal) Gram matrix
+// under a roctx range.  A pivot at or below the SVQB drop tolerance 1e-14 counts
+// as a breakdown: the smallest eigenvalue is then below 1e-14 times the largest
+// (which is at least 1), so the SVQB reading would drop a direction.
+constexpr double kGramPivotTol = 1e-14;
 hipError_t potrf_traced(double* A, int64_t lda, int64_t b, int* info, hipStream_t st,
                         const Workspace& ws, double* tri) {
   TraceRange tr("chfsi cholqr factor");
-  return potrf_lower(A, lda, b, info, st, ws, tri);
+  return potrf_lower(A, lda, b, info, st, ws, tri, kGramPivotTol);
 }
 
 // the eigensolver under a roctx range
@@ -187,6 +192,10 @@ struct chfsi_ctx {
   double* h_lz = nullptr;
   bool have_lmax = false;
   double lmax_est = 0.0;
+  // second stream (default priority) for the estimate overlapped with the
+  // first Rayleigh-Ritz pass, and the event that orders it after the caller's work
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_aux = nullptr;
   const std::atomic<int>* cancel = nullptr;
   uint64_t refill_seed = 0;
   // slab-wise Rayleigh-Ritz (memory_mode 1)
@@ -724,6 +733,8 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
     float* RY = c->f32_b;
     float* Yc = c->f32_c;
     CK(rchfsi_init_f32(resid, ldr, n, b, scale1, RY, RX, Yc, n, c->stream));
+    // dense BF16: each step's split-K reduction also rounds D^{-1} R_Y for the next
+    bool b16_ready = false;
     for (int s = 0; s < nsteps; ++s) {
       const StepCoef sp = next_step();
       if (dense) {
@@ -752,10 +763,14 @@ chfsi_status filter_rchfsi(chfsi_ctx* c, const double* X, int64_t ldx, const dou
         g.epi.C3 = Yc;
         g.epi.ldc3 = n;
         CK(prof_pair(c, &g.ev_begin, &g.ev_end));
-        if (c->prm.filter_prec == CHFSI_PREC_BF16)
-          CK(gemm_bf16_filter(g, c->A16, n, static_cast<uint16_t*>(c->bf_a), c->stream, c->ws,
-                              filter_gemm_splits()));
-        else
+        if (c->prm.filter_prec == CHFSI_PREC_BF16) {
+          uint16_t* b16 = static_cast<uint16_t*>(c->bf_a);
+          bool next_ready = false;
+          CK(gemm_bf16_filter(g, c->A16, n, b16, c->stream, c->ws, filter_gemm_splits(),
+                              b16_ready, s + 1 < nsteps ? b16 : nullptr, c->dinv32,
+                              &next_ready));
+          b16_ready = next_ready;
+        } else
           CK(gemm<float>(g, c->stream, c->ws, filter_gemm_splits(), filter_gemm_cfg()));
         fl += 2.0 * double(n) * double(n) * double(b);
       } else {
@@ -2195,14 +2210,23 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
 // Lanczos estimate of the spectrum bounds of B^{-1} A (lanczos.hip) on the
 // context's operators: real blocks of length n, or planar complex vectors of
 // length 2 n ([re; im], the Bloch operators in the twisted frame)
-chfsi_status estimate_bounds(chfsi_ctx* c, const double* v0_user, int steps, LanczosResult* res) {
+// the estimate's vectors (allocated on first use)
+chfsi_status ensure_lanczos_work(chfsi_ctx* c) {
+  if (c->lz_work) return CHFSI_OK;
+  chfsi_status ls = CHFSI_OK;
+  c->lz_work = ctx_alloc<double>(c, lanczos_ctx_bytes(c->n, c->cplx), &ls);
+  return ls;
+}
+
+// stream: where the estimate runs (null: the context's stream)
+chfsi_status estimate_bounds(chfsi_ctx* c, const double* v0_user, int steps, LanczosResult* res,
+                             hipStream_t stream = nullptr) {
   TraceRange tr("chfsi lanczos bound estimate");
   const int64_t n = c->n;
   const int64_t L = c->cplx ? 2 * n : n;
-  hipStream_t st = c->stream;
-  if (!c->lz_work) {
-    chfsi_status ls = CHFSI_OK;
-    c->lz_work = ctx_alloc<double>(c, lanczos_ctx_bytes(n, c->cplx), &ls);
+  hipStream_t st = stream ? stream : c->stream;
+  {
+    const chfsi_status ls = ensure_lanczos_work(c);
     if (ls != CHFSI_OK) return ls;
   }
   double* tmp = c->lz_work + (lanczos_workspace_bytes(L) + 255) / 256 * 256 / sizeof(double);
@@ -2272,6 +2296,15 @@ chfsi_status estimate_bounds(chfsi_ctx* c, const double* v0_user, int steps, Lan
     return CHFSI_ERR_NUMERIC;
   }
   return CHFSI_OK;
+}
+
+// overlap the estimate with the first Rayleigh-Ritz pass: dense real operators
+// whose memory the library allocates itself (knob CHFSI_LANCZOS_OVERLAP=0: off)
+bool lanczos_overlap_ok(const chfsi_ctx* c) {
+  const char* e = std::getenv("CHFSI_LANCZOS_OVERLAP");
+  if (e && std::atoi(e) == 0) return false;
+  return !c->cplx && !c->bloch && c->al == nullptr && c->A.kind == CHFSI_OP_DENSE &&
+         (c->B_identity || c->B.kind == CHFSI_OP_DENSE);
 }
 
 void bounds_policy(const chfsi_params& p, double lmax_used, const double* ritz, int64_t b,
@@ -2410,6 +2443,11 @@ void chfsi_destroy(chfsi_ctx* c) {
   for (auto& e : c->ev)
     if (e) hipEventDestroy(e);
   if (c->ev_stage) hipEventDestroy(c->ev_stage);
+  if (c->aux_stream) {
+    hipStreamSynchronize(c->aux_stream);
+    hipStreamDestroy(c->aux_stream);
+  }
+  if (c->ev_aux) hipEventDestroy(c->ev_aux);
   for (auto e : c->pev)
     if (e) hipEventDestroy(e);
   delete c;
@@ -2881,8 +2919,43 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   std::vector<double> ritz(b), norms(b);
   float ms = 0.0f;
   double lmax_used = c->prm.lambda_max;
-  if (std::isnan(lmax_used)) {
-    if (!c->have_lmax) {
+  // The Lanczos estimate of lambda_max (when needed) does not depend on the
+  // first Rayleigh-Ritz pass.  For dense real operators it runs on a second
+  // stream from a helper thread while this thread runs that pass: its
+  // matrix-vector products stream the operator from HBM, the eigensolver of
+  // the pass keeps a few CUs busy.  Joined before the first filter.
+  std::thread lz_thread;
+  struct Joiner {
+    std::thread& t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  } lz_join{lz_thread};
+  chfsi_status lz_status = CHFSI_OK;
+  std::string lz_error;
+  LanczosResult lz_res;
+  double lz_ms = 0.0;
+  if (std::isnan(lmax_used) && !c->have_lmax) {
+    if (lanczos_overlap_ok(c)) {
+      if (!c->aux_stream) CK(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+      if (!c->ev_aux) CK(hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming));
+      const chfsi_status ls = ensure_lanczos_work(c);
+      if (ls != CHFSI_OK) return ls;
+      // after everything the caller queued on the context's stream
+      CK(hipEventRecord(c->ev_aux, c->stream));
+      CK(hipStreamWaitEvent(c->aux_stream, c->ev_aux, 0));
+      lz_thread = std::thread([c, &lz_status, &lz_error, &lz_res, &lz_ms]() {
+        const double tb = now_ms();
+        if (hipSetDevice(c->device) != hipSuccess) {
+          lz_status = CHFSI_ERR_DEVICE;
+          lz_error = "hipSetDevice failed in the bound-estimate thread";
+          return;
+        }
+        lz_status = estimate_bounds(c, nullptr, 0, &lz_res, c->aux_stream);
+        if (lz_status != CHFSI_OK) lz_error = chfsi_last_error();
+        lz_ms = now_ms() - tb;
+      });
+    } else {
       const double tb = now_ms();
       LanczosResult lr;
       const chfsi_status bs = estimate_bounds(c, nullptr, 0, &lr);
@@ -2891,9 +2964,7 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
       c->have_lmax = true;
       r.time_bounds_ms = now_ms() - tb;
     }
-    lmax_used = c->lmax_est;
   }
-  r.lambda_max_used = lmax_used;
   CK(hipEventRecord(c->ev[2], c->stream));
   c->last_sweeps = 0;
   c->svqb_events = 0;
@@ -2912,6 +2983,18 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   CK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
   r.time_rr_ms += ms;
   r.jacobi_sweeps += c->last_sweeps;
+  if (lz_thread.joinable()) {
+    lz_thread.join();
+    if (lz_status != CHFSI_OK) {
+      set_error_message(lz_error.c_str());
+      return lz_status;
+    }
+    c->lmax_est = lz_res.upper;
+    c->have_lmax = true;
+    r.time_bounds_ms = lz_ms;
+  }
+  if (std::isnan(lmax_used)) lmax_used = c->lmax_est;
+  r.lambda_max_used = lmax_used;
   auto maxres = [&]() {
     double m = 0.0;
     for (int64_t j = 0; j < nw; ++j) m = std::max(m, norms[j]);

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <utility>
 #include <vector>
 
 namespace chfsi {
@@ -42,7 +43,7 @@ constexpr int LDJ = JP + 1;     // padded LDS leading dimension
 // Threads form a 16 x 16 grid over the trailing triangle (no index division).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int jb, int* info,
-                                                    int j0) {
+                                                    int j0, double piv_tol) {
   __shared__ double a[NB * (NB + 1)];
   constexpr int L = NB + 1;
   if (*info != 0) return;
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int 
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   for (int k = 0; k < jb; ++k) {
     const double d = a[k + k * L];
-    if (!(d > 0.0) || !isfinite(d)) {      // the same decision in every thread
+    if (!(d > piv_tol) || !isfinite(d)) {  // the same decision in every thread
       if (threadIdx.x == 0) atomicCAS(info, 0, j0 + k + 1);
       return;
     }
@@ -70,6 +71,110 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int64_t lda, int 
     const double dj = sqrt(a[j + j * L]);
     A[i + j * lda] = i > j ? a[i + j * L] / dj : (i == j ? dj : 0.0);
   }
+}
+
+// Cholesky of the diagonal block (jb <= NB) and the inverse of its factor in
+// one wave: lane i holds row i in registers (the block padded to NB x NB with
+// the identity).  Step k: the pivot d = a_kk is read from lane k, g = 1/sqrt(d)
+// comes from the hardware estimate and two Newton steps, lane i forms
+// l_ik = a_ik g (l_kk = d g) and puts it in LDS (two alternating buffers), and
+// every lane subtracts l_ik l_jk from its row (the l_jk are LDS broadcasts).
+// Then lane c forms column c of L^{-1} by forward substitution with the
+// pivots' g, reading the rows of L from LDS in 16-byte pairs; the sum of each
+// step runs in four partial sums (j mod 4), which shortens the chain of
+// dependent FP64 operations fourfold.  Writes L (upper part of the block
+// zeroed) and L^{-1} (NB x NB, ld NB, identity-padded) to Li.  The steps are
+// expanded from templates, so every register index is a constant.  Measured
+// at b = 320 (five blocks per factorisation): see the kernel table.
+constexpr int LDR = NB + 2;     // row stride of L in LDS (16-byte aligned rows)
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(unsigned(u), lane);
+  const unsigned hi = __builtin_amdgcn_readlane(unsigned(u >> 32), lane);
+  return __longlong_as_double((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// 1/sqrt(x) for normal x > 0: the hardware estimate and two Newton steps
+__device__ __forceinline__ double rsqrt_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-(x * y), y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-(x * y), y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+template <int K>
+__device__ __forceinline__ bool chol_step(double (&r)[NB], double (*col)[NB], double* invd,
+                                          double piv_tol) {
+  const int i = threadIdx.x;
+  const double d = readlane_f64(r[K], K);
+  if (!(d > piv_tol) || !isfinite(d)) return false;   // the same decision in every lane
+  const double g = rsqrt_newton(d);
+  const double l = i == K ? d * g : r[K] * g;
+  r[K] = l;
+  col[K & 1][i] = l;
+  if (i == 0) invd[K] = g;
+  __syncthreads();
+#pragma unroll
+  for (int j = K + 1; j < NB; ++j) r[j] = fma(-l, col[K & 1][j], r[j]);
+  return true;
+}
+
+template <int K>
+__device__ __forceinline__ void trtri_step(double (&x)[NB], const double* lt, const double* invd) {
+  double s[4] = {(int(threadIdx.x) == K) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < K; ++j) s[j & 3] = fma(-lt[K * LDR + j], x[j], s[j & 3]);
+  x[K] = ((s[0] + s[1]) + (s[2] + s[3])) * invd[K];
+}
+
+template <int... Ks>
+__device__ __forceinline__ int chol_all(std::integer_sequence<int, Ks...>, double (&r)[NB],
+                                        double (*col)[NB], double* invd, double piv_tol) {
+  int failed = -1;
+  // left to right; a failed pivot stops the remaining steps
+  ((failed < 0 && !chol_step<Ks>(r, col, invd, piv_tol) ? (failed = Ks) : 0), ...);
+  return failed;
+}
+
+template <int... Ks>
+__device__ __forceinline__ void trtri_all(std::integer_sequence<int, Ks...>, double (&x)[NB],
+                                          const double* lt, const double* invd) {
+  (trtri_step<Ks>(x, lt, invd), ...);
+}
+
+__global__ __launch_bounds__(64) void k_potrf_trtri_diag(double* A, int64_t lda, int jb,
+                                                         int* info, int j0, double* Li,
+                                                         double piv_tol) {
+  __shared__ __attribute__((aligned(16))) double col[2][NB];
+  __shared__ __attribute__((aligned(16))) double lt[NB * LDR];
+  __shared__ double invd[NB];
+  if (*info != 0) return;
+  const int i = threadIdx.x;
+  double r[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    r[j] = (i < jb && j < jb) ? A[i + j * lda] : (i == j ? 1.0 : 0.0);
+  const int failed = chol_all(std::make_integer_sequence<int, NB>{}, r, col, invd, piv_tol);
+  if (failed >= 0) {
+    if (i == 0) atomicCAS(info, 0, j0 + failed + 1);
+    return;
+  }
+  // L (lower, zero above): row i to LDS (row-major) and to the block
+#pragma unroll
+  for (int j = 0; j < NB; ++j) lt[i * LDR + j] = j <= i ? r[j] : 0.0;
+  if (i < jb) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (j < jb) A[i + j * lda] = j <= i ? r[j] : 0.0;
+  }
+  __syncthreads();
+  // column i of L^{-1}: x_k = (delta_ki - sum_{j<k} l_kj x_j) / l_kk
+  double x[NB];
+  trtri_all(std::make_integer_sequence<int, NB>{}, x, lt, invd);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) Li[k + i * NB] = x[k];
 }
 
 // Inverse of one lower-triangular diagonal block (jb <= NB) of L: one wave,
@@ -217,28 +322,29 @@ __device__ __forceinline__ void jacobi_cs(double app, double aqq, double apq, do
   *s = t * (*c);
 }
 
-// One workgroup per pair of the outer round: gather the JP x JP subproblem,
-// skip it when already diagonal (to the threshold), else one Jacobi sweep.
-// Writes U (JP x JP) and skip[pair] (1 = U is the identity).
-__global__ __launch_bounds__(kPairThreads) void k_jacobi_pair_solve(
-    const double* A, int64_t lda, int nblk, int round, const double* scale, double tol, double* U,
-    int* skip, int* counter) {
-  __shared__ double buf[2][JP * LDJ];
-  __shared__ double2 cs[2][kHalf];
-  __shared__ double wmax[kPairThreads / 64];
-  __shared__ int nrot_total;
+// LDS of one pair subproblem: the slot-ordered lower triangle (ping-pong
+// buffers), the rotations of the current and next round, the wave maxima
+struct PairSmem {
+  double buf[2][JP * LDJ];
+  double2 cs[2][kHalf];
+  double wmax[kPairThreads / 64];
+  int nrot_total;
+};
+
+// One inner sweep of the pair subproblem held in S.buf[0] (lower triangle,
+// local order = slot order of round 0); `mx` is this thread's largest
+// off-diagonal magnitude among the entries it stored.  Skips (skip_out = 1)
+// when the subproblem is already diagonal to the threshold, else writes the
+// accumulated JP x JP rotation to Uo (skip_out = 0) and adds its rotation
+// count to the sweep counter.
+__device__ __forceinline__ void pair_solve_core(PairSmem& S, double mx, const double* scale,
+                                                double tol, double* Uo, int* skip_out,
+                                                int* counter) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  int I, J;
-  block_pair(blockIdx.x, round, nblk, &I, &J);
-  // round 0 has index s in slot s
-  double mx = 0.0;
-  for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
-    const int i = idx % JP, j = idx / JP;
-    if (i < j) continue;
-    const double v = A[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
-    buf[0][i + j * LDJ] = v;
-    if (i != j) mx = fmax(mx, fabs(v));
-  }
+  auto& buf = S.buf;
+  auto& cs = S.cs;
+  auto& wmax = S.wmax;
+  int& nrot_total = S.nrot_total;
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
   if (lane == 0) wmax[wave] = mx;
   if (tid == 0) nrot_total = 0;
@@ -248,7 +354,7 @@ __global__ __launch_bounds__(kPairThreads) void k_jacobi_pair_solve(
   for (int w = 1; w < kPairThreads / 64; ++w) mx = fmax(mx, wmax[w]);
   const double thresh = tol * (*scale);
   if (!(mx > thresh)) {
-    if (tid == 0) skip[blockIdx.x] = 1;
+    if (tid == 0) *skip_out = 1;
     return;
   }
   if (wave == 0 && lane < kHalf) {
@@ -374,16 +480,39 @@ __global__ __launch_bounds__(kPairThreads) void k_jacobi_pair_solve(
     }
   }
   __syncthreads();
-  double* Uo = U + int64_t(blockIdx.x) * JP * JP;
   for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
     const int i = idx % JP, j = idx / JP;
     Uo[i + j * JP] = buf[0][i + j * LDJ];
   }
   if (tid == 0) {
-    skip[blockIdx.x] = 0;
+    *skip_out = 0;
     if (nrot_total > 0) atomicAdd(counter, nrot_total);
   }
 }
+
+// One workgroup per pair of the outer round: gather the JP x JP subproblem,
+// skip it when already diagonal (to the threshold), else one Jacobi sweep.
+// Writes U (JP x JP) and skip[pair] (1 = U is the identity).
+__global__ __launch_bounds__(kPairThreads) void k_jacobi_pair_solve(
+    const double* A, int64_t lda, int nblk, int round, const double* scale, double tol, double* U,
+    int* skip, int* counter) {
+  __shared__ PairSmem S;
+  const int tid = threadIdx.x;
+  int I, J;
+  block_pair(blockIdx.x, round, nblk, &I, &J);
+  // round 0 has index s in slot s
+  double mx = 0.0;
+  for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
+    const int i = idx % JP, j = idx / JP;
+    if (i < j) continue;
+    const double v = A[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
+    S.buf[0][i + j * LDJ] = v;
+    if (i != j) mx = fmax(mx, fabs(v));
+  }
+  pair_solve_core(S, mx, scale, tol, U + int64_t(blockIdx.x) * JP * JP, skip + blockIdx.x,
+                  counter);
+}
+
 
 // out = op(X) * Y for JP x JP matrices in LDS (ld LDJ) on FP64 MFMA
 // (v_mfma_f64_16x16x4f64: lane l supplies X(l%16, l/16) and Y(l/16, l%16);
@@ -520,6 +649,246 @@ __global__ __launch_bounds__(256) void k_jacobi_apply(double* A, int64_t lda, do
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined outer rounds: one launch carries the pair solves of round r and
+// the rotations of round r - 1.  The pair workgroups do not wait for the
+// rotated matrix: each forms the three 16 x 16 blocks of it that its
+// subproblem needs from the matrix before round r - 1 and that round's
+// factors, with the same products in the same order as the rotation
+// workgroups (so the entries are bit-identical to the ones those store),
+// while the rotation workgroups write the rotated matrix into the other
+// buffer.  A sweep of R rounds takes R + 1 launches instead of 2 R, and the
+// rotations leave the critical path.
+// ---------------------------------------------------------------------------
+
+// pair of round r that holds block x, and x's offset (0 or JB) in it
+__device__ __forceinline__ void block_locate(int x, int r, int nblk, int* pair, int* off) {
+  const int n1 = nblk - 1;
+  const int s = x == 0 ? 0 : 1 + ((x - 1 - r) % n1 + n1) % n1;
+  const int k = s < nblk / 2 ? s : nblk - 1 - s;
+  int I, J;
+  block_pair(k, r, nblk, &I, &J);
+  *pair = k;
+  *off = x == I ? 0 : JB;
+}
+
+constexpr int LDZ = JB + 1;   // leading dimension of a 16-row slice in LDS
+
+// rows oR..oR+15 of U_R^T M (both 16-column halves), M = A[S_R, S_C] (pair R
+// rows (IR, JR), pair C columns (IC, JC)); operands from global memory with the
+// values and the k order of lds_mm<true>(U_R, M).  idR: U_R is the identity.
+__device__ __forceinline__ void rot_rows(const double* A, int64_t lda, const double* UR, bool idR,
+                                         int oR, int IR, int JR, int IC, int JC, f64x4_t* acc0,
+                                         f64x4_t* acc1) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
+  const int m = oR + l16;
+  const int64_t col0 = int64_t(pair_index(l16, IC, JC)) * lda;
+  const int64_t col1 = int64_t(pair_index(JB + l16, IC, JC)) * lda;
+  double xa[JP / 4], y0[JP / 4], y1[JP / 4];
+#pragma unroll
+  for (int t = 0; t < JP / 4; ++t) {
+    const int k = 4 * t + g;
+    const int64_t row = pair_index(k, IR, JR);
+    xa[t] = idR ? (k == m ? 1.0 : 0.0) : UR[k + m * JP];
+    y0[t] = A[row + col0];
+    y1[t] = A[row + col1];
+  }
+  f64x4_t a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < JP / 4; ++t) {
+    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[t], y0[t], a0, 0, 0, 0);
+    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[t], y1[t], a1, 0, 0, 0);
+  }
+  *acc0 = a0;
+  *acc1 = a1;
+}
+
+// U_C[:, oC..oC+15] in the lane order of the B operand of rot_cols
+__device__ __forceinline__ void load_ucols(const double* UC, bool idC, int oC, double (&yb)[JP / 4]) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
+  const int n = oC + l16;
+#pragma unroll
+  for (int t = 0; t < JP / 4; ++t) {
+    const int k = 4 * t + g;
+    yb[t] = idC ? (k == n ? 1.0 : 0.0) : UC[k + n * JP];
+  }
+}
+
+// the 16 x 16 tile Z U_C[:, oC..oC+15] for a 16-row slice Z (LDS, ld LDZ),
+// with the values and the k order of lds_mm<false>(Z, U_C)
+__device__ __forceinline__ f64x4_t rot_cols(const double* Z, const double (&yb)[JP / 4]) {
+  const int lane = threadIdx.x & 63, l16 = lane & 15, g = lane >> 4;
+  f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < JP / 4; ++t) {
+    const int k = 4 * t + g;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Z[l16 + k * LDZ], yb[t], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+union RoundSmem {
+  struct {
+    PairSmem ps;
+    double z[3][JP * LDZ];
+  } pair;
+  struct {
+    double m[JP * LDJ];
+    double up[JP * LDJ];
+    double uq[JP * LDJ];
+  } apply;
+};
+
+// Workgroups [0, npairs) (when rcur >= 0): pair solves of round rcur on the
+// matrix after round rprev (rprev < 0: Pin itself).  The rest (when
+// rprev >= 0): round rprev's rotations as in k_jacobi_apply, Pin -> Pout (a
+// block both of whose factors are identities is copied), V in place.
+__global__ __launch_bounds__(kPairThreads) void k_jacobi_round(
+    const double* __restrict__ Pin, double* __restrict__ Pout, int64_t lda, double* V,
+    int64_t ldv, int nblk, int npairs, int rprev, const double* Uprev, const int* skipprev,
+    int rcur, double* Ucur, int* skipcur, const double* scale, double tol, int* counter) {
+  __shared__ RoundSmem sm;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int npw = rcur >= 0 ? npairs : 0;
+  if (int(blockIdx.x) < npw) {
+    PairSmem& S = sm.pair.ps;
+    int I, J;
+    block_pair(blockIdx.x, rcur, nblk, &I, &J);
+    double mx = 0.0;
+    if (rprev < 0) {
+      for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
+        const int i = idx % JP, j = idx / JP;
+        if (i < j) continue;
+        const double v = Pin[pair_index(i, I, J) + int64_t(pair_index(j, I, J)) * lda];
+        S.buf[0][i + j * LDJ] = v;
+        if (i != j) mx = fmax(mx, fabs(v));
+      }
+    } else {
+      int pI, oI, pJ, oJ;
+      block_locate(I, rprev, nblk, &pI, &oI);
+      block_locate(J, rprev, nblk, &pJ, &oJ);
+      // tile 0: (I, I); tile 1: (J, J); tile 2: the (J, I) block, formed as
+      // the rotation workgroup of the pair with the larger index forms it
+      const bool jrow = pJ > pI;
+      auto tile = [&](int t, int* R, int* oR, int* C, int* oC) {
+        if (t == 0) { *R = pI; *oR = oI; *C = pI; *oC = oI; }
+        else if (t == 1) { *R = pJ; *oR = oJ; *C = pJ; *oC = oJ; }
+        else if (jrow) { *R = pJ; *oR = oJ; *C = pI; *oC = oI; }
+        else { *R = pI; *oR = oI; *C = pJ; *oC = oJ; }
+      };
+      // waves 0..2: tile `wave`; the right factor of the second product is
+      // loaded with the first product's operands
+      const int l16 = lane & 15, g = lane >> 4;
+      const int t = wave;
+      int R = 0, oR = 0, C = 0, oC = 0;
+      double ucol[JP / 4];
+      if (wave < 3) {
+        tile(t, &R, &oR, &C, &oC);
+        int IR, JR, IC, JC;
+        block_pair(R, rprev, nblk, &IR, &JR);
+        block_pair(C, rprev, nblk, &IC, &JC);
+        load_ucols(Uprev + int64_t(C) * JP * JP, skipprev[C] != 0, oC, ucol);
+        f64x4_t a0, a1;
+        rot_rows(Pin, lda, Uprev + int64_t(R) * JP * JP, skipprev[R] != 0, oR, IR, JR, IC, JC,
+                 &a0, &a1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          sm.pair.z[t][(g + 4 * r) + l16 * LDZ] = a0[r];
+          sm.pair.z[t][(g + 4 * r) + (JB + l16) * LDZ] = a1[r];
+        }
+      }
+      __syncthreads();
+      if (wave < 3) {
+        const f64x4_t acc = rot_cols(sm.pair.z[t], ucol);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = g + 4 * r, bcol = l16;   // element (a, bcol) of the tile
+          int i, j;                              // local (slot) coordinates
+          if (t == 0) { i = a; j = bcol; }
+          else if (t == 1) { i = JB + a; j = JB + bcol; }
+          else if (jrow) { i = JB + a; j = bcol; }
+          else { i = JB + bcol; j = a; }
+          if (i < j) continue;
+          S.buf[0][i + j * LDJ] = acc[r];
+          if (i != j) mx = fmax(mx, fabs(acc[r]));
+        }
+      }
+    }
+    pair_solve_core(S, mx, scale, tol, Ucur + int64_t(blockIdx.x) * JP * JP,
+                    skipcur + blockIdx.x, counter);
+    return;
+  }
+  if (rprev < 0) return;
+  // rotations of round rprev
+  const int a = int(blockIdx.x) - npw;
+  const int P = a % npairs, y = a / npairs;
+  int IP, JPb;
+  block_pair(P, rprev, nblk, &IP, &JPb);
+  double* m = sm.apply.m;
+  double* up = sm.apply.up;
+  double* uq = sm.apply.uq;
+  double t[NT][NT][4];
+  if (y >= npairs) {
+    if (skipprev[P]) return;
+    const int64_t r0 = int64_t(y - npairs) * JP;
+    for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
+      const int i = idx % JP, j = idx / JP;
+      m[i + j * LDJ] = V[r0 + i + int64_t(pair_index(j, IP, JPb)) * ldv];
+      up[i + j * LDJ] = Uprev[int64_t(P) * JP * JP + i + j * JP];
+    }
+    __syncthreads();
+    if (wave < 4) {
+      lds_mm<false>(m, up, t);
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            V[r0 + mm_row(i, r) + int64_t(pair_index(mm_col(j), IP, JPb)) * ldv] = t[i][j][r];
+    }
+    return;
+  }
+  const int Q = y;
+  if (P < Q) return;
+  const bool sp = skipprev[P] != 0, sq = skipprev[Q] != 0;
+  int IQ, JQ;
+  block_pair(Q, rprev, nblk, &IQ, &JQ);
+  if (sp && sq) {
+    for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
+      const int i = idx % JP, j = idx / JP;
+      const int64_t o1 = pair_index(i, IP, JPb) + int64_t(pair_index(j, IQ, JQ)) * lda;
+      Pout[o1] = Pin[o1];
+      if (P != Q) {
+        const int64_t o2 = pair_index(i, IQ, JQ) + int64_t(pair_index(j, IP, JPb)) * lda;
+        Pout[o2] = Pin[o2];
+      }
+    }
+    return;
+  }
+  for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
+    const int i = idx % JP, j = idx / JP;
+    m[i + j * LDJ] = Pin[pair_index(i, IP, JPb) + int64_t(pair_index(j, IQ, JQ)) * lda];
+    up[i + j * LDJ] = sp ? (i == j ? 1.0 : 0.0) : Uprev[int64_t(P) * JP * JP + i + j * JP];
+    uq[i + j * LDJ] = sq ? (i == j ? 1.0 : 0.0) : Uprev[int64_t(Q) * JP * JP + i + j * JP];
+  }
+  __syncthreads();
+  if (wave < 4) lds_mm<true>(up, m, t);         // U_P^T M
+  __syncthreads();
+  if (wave < 4) lds_mm_store(m, t);
+  __syncthreads();
+  if (wave < 4) lds_mm<false>(m, uq, t);        // (U_P^T M) U_Q
+  __syncthreads();
+  if (wave < 4) lds_mm_store(m, t);
+  __syncthreads();
+  for (int idx = tid; idx < JP * JP; idx += kPairThreads) {
+    const int i = idx % JP, j = idx / JP;
+    Pout[pair_index(i, IP, JPb) + int64_t(pair_index(j, IQ, JQ)) * lda] = m[i + j * LDJ];
+    if (P != Q)
+      Pout[pair_index(j, IQ, JQ) + int64_t(pair_index(i, IP, JPb)) * lda] = m[i + j * LDJ];
+  }
+}
+
 // padded copy: P (bp x bp) = [A 0; 0 0]; V = I
 __global__ __launch_bounds__(256) void k_jacobi_setup(const double* A, int64_t lda, int64_t b,
                                                       double* P, double* V, int64_t bp) {
@@ -590,19 +959,30 @@ __global__ __launch_bounds__(64) void k_offmax_final(const double* part, const d
 }
 
 // ascending sort of the diagonal (first b entries) by rank counting, then
-// gather eigenvector columns
+// gather eigenvector columns; the diagonal is staged through LDS in chunks
 __global__ __launch_bounds__(256) void k_jacobi_rank(const double* P, int64_t bp, int64_t b,
                                                      double* w, int* perm) {
+  constexpr int kChunk = 1024;
+  __shared__ double dg[kChunk];
   const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
-  if (i >= b) return;
-  const double di = P[i + i * bp];
+  const double di = i < b ? P[i + i * bp] : 0.0;
   int64_t rank = 0;
-  for (int64_t j = 0; j < b; ++j) {
-    const double dj = P[j + j * bp];
-    rank += (dj < di) || (dj == di && j < i);
+  for (int64_t c0 = 0; c0 < b; c0 += kChunk) {
+    const int cn = int(b - c0 < kChunk ? b - c0 : kChunk);
+    __syncthreads();
+    for (int t = threadIdx.x; t < cn; t += 256) dg[t] = P[(c0 + t) + (c0 + t) * bp];
+    __syncthreads();
+    if (i < b) {
+      for (int t = 0; t < cn; ++t) {
+        const double dj = dg[t];
+        rank += (dj < di) || (dj == di && c0 + t < i);
+      }
+    }
   }
-  w[rank] = di;
-  perm[rank] = int(i);
+  if (i < b) {
+    w[rank] = di;
+    perm[rank] = int(i);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_jacobi_gather(const double* V, int64_t bp, int64_t b,
@@ -633,18 +1013,31 @@ size_t tri_workspace_bytes(int64_t b, int64_t nrhs) {
 // Blocked right-looking Cholesky.  Per diagonal block: factor it in LDS,
 // invert it (kept in tri for trsm_lower_left), form the panel below as a GEMM
 // with the inverse, then update the trailing matrix with a GEMM.
+// one-wave Cholesky-and-inverse of the diagonal blocks (knob CHFSI_POTRF_FUSED=0:
+// the 256-thread Cholesky and a separate inverse)
+static bool potrf_fused() {
+  const char* e = std::getenv("CHFSI_POTRF_FUSED");
+  return !(e && std::atoi(e) == 0);
+}
+
 hipError_t potrf_lower(double* A, int64_t lda, int64_t b, int* info, hipStream_t st,
-                       const Workspace& ws, double* tri) {
+                       const Workspace& ws, double* tri, double piv_tol) {
   hipError_t e = hipSuccess;
   const int64_t nblk = (b + NB - 1) / NB;
   double* tmp = tri + nblk * NB * NB;
   for (int64_t j0 = 0; j0 < b; j0 += NB) {
     const int jb = int(std::min<int64_t>(NB, b - j0));
     double* Li = tri + (j0 / NB) * NB * NB;
-    k_potrf_diag<<<1, 256, 0, st>>>(A + j0 + j0 * lda, lda, jb, info, int(j0));
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_trtri_diag<<<1, 64, 0, st>>>(A, lda, b, j0, Li, info);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (potrf_fused()) {
+      k_potrf_trtri_diag<<<1, 64, 0, st>>>(A + j0 + j0 * lda, lda, jb, info, int(j0), Li,
+                                           piv_tol);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+      k_potrf_diag<<<1, 256, 0, st>>>(A + j0 + j0 * lda, lda, jb, info, int(j0), piv_tol);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      k_trtri_diag<<<1, 64, 0, st>>>(A, lda, b, j0, Li, info);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const int64_t rows = b - j0 - jb;
     if (rows <= 0) break;
     {   // tmp (rows x jb) = A21 L11^{-T}; A21 <- tmp
@@ -746,8 +1139,15 @@ static int64_t jacobi_padded(int64_t b) { return std::max<int64_t>(JP, (b + JP -
 size_t syev_workspace_bytes(int64_t b) {
   const int64_t bp = jacobi_padded(b);
   const int64_t npairs = bp / JP;
-  return size_t(2 * bp * bp + npairs * JP * JP + 16 + kFroParts) * sizeof(double) +
-         size_t(b + 64 + npairs) * sizeof(int);
+  return size_t(3 * bp * bp + 2 * npairs * JP * JP + 16 + kFroParts) * sizeof(double) +
+         size_t(b + 64 + 2 * npairs) * sizeof(int);
+}
+
+// pipelined outer rounds (knob CHFSI_JACOBI_PIPE=0: a pair-solve launch and a
+// rotation launch per round; read at every call, so that tests can compare both)
+static bool jacobi_pipelined() {
+  const char* e = std::getenv("CHFSI_JACOBI_PIPE");
+  return !(e && std::atoi(e) == 0);
 }
 
 hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
@@ -759,11 +1159,12 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   if (ws.bytes < syev_workspace_bytes(b)) return hipErrorInvalidValue;
   double* P = static_cast<double*>(ws.ptr);
   double* Vp = P + bp * bp;
-  double* U = Vp + bp * bp;
-  double* scal = U + int64_t(npairs) * JP * JP;   // [0]: Frobenius norm
+  double* P2 = Vp + bp * bp;                      // the pipelined rounds' second buffer
+  double* U = P2 + bp * bp;                       // two sets of npairs JP x JP factors
+  double* scal = U + 2 * int64_t(npairs) * JP * JP;   // [0]: Frobenius norm
   int* counter = reinterpret_cast<int*>(scal + 16 + kFroParts);
   int* perm = counter + 64;
-  int* skip = perm + b;
+  int* skip = perm + b;                           // two sets of npairs flags
   hipError_t e;
   k_jacobi_setup<<<grid_for(bp * bp), 256, 0, st>>>(A, lda, b, P, Vp, bp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -778,15 +1179,37 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   int sweeps = 0;
   int host_count = 0;
   bool converged = false;
+  const bool pipe = jacobi_pipelined();
+  const int R = nblk - 1;                          // rounds per sweep
+  const unsigned napply = unsigned(npairs) * unsigned(npairs + bp / JP);
+  const int64_t usz = int64_t(npairs) * JP * JP;
   for (; sweeps < max_outer; ++sweeps) {
     if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
-    for (int r = 0; r < nblk - 1; ++r) {
-      k_jacobi_pair_solve<<<dim3(npairs), kPairThreads, 0, st>>>(P, bp, nblk, r, scal, tol, U,
-                                                                 skip, counter);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      k_jacobi_apply<<<dim3(npairs, unsigned(npairs + bp / JP)), 256, 0, st>>>(
-          P, bp, Vp, bp, nblk, npairs, r, U, skip);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (pipe) {
+      // launch r: pair solves of round r (on the matrix after round r - 1,
+      // formed in the pair workgroups) and round r - 1's rotations P -> P2;
+      // a last launch applies round R - 1
+      for (int r = 0; r <= R; ++r) {
+        const bool solve = r < R, rotate = r > 0;
+        const int cu = r & 1, pu = (r - 1) & 1;
+        k_jacobi_round<<<dim3((solve ? unsigned(npairs) : 0u) + (rotate ? napply : 0u)),
+                         kPairThreads, 0, st>>>(
+            P, P2, bp, Vp, bp, nblk, npairs, rotate ? r - 1 : -1, rotate ? U + pu * usz : nullptr,
+            rotate ? skip + pu * npairs : nullptr, solve ? r : -1,
+            solve ? U + cu * usz : nullptr, solve ? skip + cu * npairs : nullptr, scal, tol,
+            counter);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (rotate) std::swap(P, P2);
+      }
+    } else {
+      for (int r = 0; r < R; ++r) {
+        k_jacobi_pair_solve<<<dim3(npairs), kPairThreads, 0, st>>>(P, bp, nblk, r, scal, tol, U,
+                                                                   skip, counter);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_jacobi_apply<<<dim3(npairs, unsigned(npairs + bp / JP)), 256, 0, st>>>(
+            P, bp, Vp, bp, nblk, npairs, r, U, skip);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
     }
     // converged when the sweep rotated nothing, or when no off-diagonal entry
     // is left above the threshold (every pair of a further sweep would skip)

@@ -93,7 +93,19 @@ struct KernelArgs {
   T* C;
   T* partial;
   Epilogue<T> epi;
+  // optional second output of the vectorised split-K reduction: out16 (M x N,
+  // ld M) = bfloat16(scale16 .* C), the next BF16 product's right operand
+  unsigned short* out16 = nullptr;
+  const T* scale16 = nullptr;
 };
+
+// float -> bfloat16, round to nearest even (NaN stays a quiet NaN)
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
 
 __device__ __forceinline__ int xcd_remap(int h, int G) {
   // Dispatch is round-robin over 8 XCDs: WG h runs on XCD h % 8.  Give each
@@ -400,14 +412,16 @@ __global__ __launch_bounds__(256, MINW) void gemm_kernel(KernelArgs<T> args) {
 // Sum split-K partials in split order, then apply the epilogue; four rows per
 // thread with 16-byte accesses (M and every leading dimension multiples of 4,
 // 16-byte aligned bases; batch 1).
+// grid: x over 1024-row chunks, y over columns (grid-stride beyond gridDim.y)
 __global__ __launch_bounds__(256) void splitk_reduce4_kernel(KernelArgs<float> args) {
   const KernelArgsCommon& c = args.c;
-  const int64_t MN = c.M * c.N, M4 = c.M / 4;
-  const int64_t total = M4 * c.N;
+  const int64_t MN = c.M * c.N;
+  const int64_t m = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4;
+  if (m >= c.M) return;
   const Epilogue<float> ep = args.epi;
-  for (int64_t idx = blockIdx.x * int64_t(256) + threadIdx.x; idx < total;
-       idx += int64_t(gridDim.x) * 256) {
-    const int64_t n = idx / M4, m = (idx - n * M4) * 4;
+  f32x4 sc16 = {1.f, 1.f, 1.f, 1.f};
+  if (args.out16 && args.scale16) sc16 = *reinterpret_cast<const f32x4*>(args.scale16 + m);
+  for (int64_t n = blockIdx.y; n < c.N; n += gridDim.y) {
     const float* P = args.partial + m + n * c.M;
     f32x4 s = *reinterpret_cast<const f32x4*>(P);
     for (int q = 1; q < c.splits; ++q) s += *reinterpret_cast<const f32x4*>(P + q * MN);
@@ -421,7 +435,17 @@ __global__ __launch_bounds__(256) void splitk_reduce4_kernel(KernelArgs<float> a
       v += f * *reinterpret_cast<const f32x4*>(ep.C3 + m + n * ep.ldc3);
     }
     *reinterpret_cast<f32x4*>(args.C + m + n * c.ldc) = v;
+    if (args.out16) {
+      const f32x4 w = v * sc16;
+      const uint32_t lo = uint32_t(f32_to_bf16_rne(w[0])) | (uint32_t(f32_to_bf16_rne(w[1])) << 16);
+      const uint32_t hi = uint32_t(f32_to_bf16_rne(w[2])) | (uint32_t(f32_to_bf16_rne(w[3])) << 16);
+      *reinterpret_cast<uint2*>(args.out16 + m + n * c.M) = make_uint2(lo, hi);
+    }
   }
+}
+
+static dim3 reduce4_grid(int64_t M, int64_t N) {
+  return dim3(unsigned((M / 4 + 255) / 256), unsigned(std::min<int64_t>(N, 65535)));
 }
 
 static bool reduce4_ok(const KernelArgs<float>& a, int batch) {
@@ -827,8 +851,7 @@ static hipError_t launch_cfg(const GemmDesc<T>& d, hipStream_t st, const Workspa
     bool done = false;
     if constexpr (sizeof(T) == 4) {
       if (reduce4_ok(a, d.batch)) {
-        const int64_t blocks = std::min<int64_t>((total / 4 + 255) / 256, 16384);
-        splitk_reduce4_kernel<<<dim3(blocks), dim3(256), 0, st>>>(a);
+        splitk_reduce4_kernel<<<reduce4_grid(d.M, d.N), dim3(256), 0, st>>>(a);
         done = true;
       }
     }
@@ -1216,21 +1239,26 @@ __global__ __launch_bounds__(256, 1) void gemm_bf16_wide_kernel(
   }
 }
 
-// B16 (n x b, ld ldo) = bfloat16(kscale .* B) (nearest-even)
+// B16 (n x b, ld ldo) = bfloat16(kscale .* B) (nearest-even); grid x over
+// 1024-row chunks (4 rows per thread when n % 4 == 0 and the pointers and
+// leading dimensions allow 16-byte loads), y over columns
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_scale_bf16(const float* __restrict__ B, int64_t ldb,
                                                     const float* __restrict__ ks, int64_t n,
                                                     int64_t b, unsigned short* __restrict__ out,
                                                     int64_t ldo) {
-  const int64_t total = n * b;
-  for (int64_t idx = blockIdx.x * int64_t(256) + threadIdx.x; idx < total;
-       idx += int64_t(gridDim.x) * 256) {
-    const int64_t j = idx / n, i = idx - j * n;
-    uint32_t u = __float_as_uint(B[i + j * ldb] * (ks ? ks[i] : 1.f));
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-      out[i + j * ldo] = (unsigned short)((u >> 16) | 0x40u);
+  const int64_t i0 = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4;
+  if (i0 >= n) return;
+  for (int64_t j = blockIdx.y; j < b; j += gridDim.y) {
+    if constexpr (VEC) {
+      f32x4 v = *reinterpret_cast<const f32x4*>(B + i0 + j * ldb);
+      if (ks) v *= *reinterpret_cast<const f32x4*>(ks + i0);
+      const uint32_t lo = uint32_t(f32_to_bf16_rne(v[0])) | (uint32_t(f32_to_bf16_rne(v[1])) << 16);
+      const uint32_t hi = uint32_t(f32_to_bf16_rne(v[2])) | (uint32_t(f32_to_bf16_rne(v[3])) << 16);
+      *reinterpret_cast<uint2*>(out + i0 + j * ldo) = make_uint2(lo, hi);
     } else {
-      u += 0x7fffu + ((u >> 16) & 1u);
-      out[i + j * ldo] = (unsigned short)(u >> 16);
+      for (int64_t i = i0; i < std::min<int64_t>(n, i0 + 4); ++i)
+        out[i + j * ldo] = f32_to_bf16_rne(B[i + j * ldb] * (ks ? ks[i] : 1.f));
     }
   }
 }
@@ -1262,19 +1290,27 @@ static int bf16_splits(int64_t M, int64_t N, int64_t K, int force_splits, int64_
 template <int BM, int BN, bool WIDE = false>
 static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
                                    uint16_t* B16, hipStream_t st, const Workspace& ws,
-                                   int force_splits) {
+                                   int force_splits, bool b16_ready, uint16_t* next16,
+                                   const float* next_scale, bool* next_ready) {
   constexpr int BK = 64;
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
   if (d.sbk != 1 || d.batch != 1 || !A16 || !B16) return hipErrorInvalidValue;
   hipError_t err;
   // (the profiling interval covers the rounding pass and the product)
   if (d.ev_begin && (err = hipEventRecord(d.ev_begin, st)) != hipSuccess) return err;
-  // the product's right operand in bfloat16, D^{-1} applied (ld = K)
-  {
-    const int64_t total = d.K * d.N;
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
-    k_scale_bf16<<<dim3(unsigned(blocks)), dim3(256), 0, st>>>(
-        d.B, d.sbn, d.kscale, d.K, d.N, reinterpret_cast<unsigned short*>(B16), d.K);
+  // the product's right operand in bfloat16, D^{-1} applied (ld = K), unless
+  // the previous step's reduction already wrote it
+  if (!b16_ready) {
+    const dim3 grid(unsigned(((d.K + 3) / 4 + 255) / 256), unsigned(std::min<int64_t>(d.N, 65535)));
+    auto al = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+    const bool vec = d.K % 4 == 0 && d.sbn % 4 == 0 && al(d.B) && al(B16) &&
+                     (!d.kscale || al(d.kscale));
+    if (vec)
+      k_scale_bf16<true><<<grid, dim3(256), 0, st>>>(
+          d.B, d.sbn, d.kscale, d.K, d.N, reinterpret_cast<unsigned short*>(B16), d.K);
+    else
+      k_scale_bf16<false><<<grid, dim3(256), 0, st>>>(
+          d.B, d.sbn, d.kscale, d.K, d.N, reinterpret_cast<unsigned short*>(B16), d.K);
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
   }
@@ -1330,11 +1366,18 @@ static hipError_t gemm_bf16_launch(const GemmDesc<float>& d, const uint16_t* A16
     gemm_bf16_kernel<BM, BN, BK, true><<<dim3(unsigned(grid)), dim3(256), 0, st>>>(a, a16, b16);
   }
   if ((err = hipGetLastError()) != hipSuccess) return err;
+  if (next_ready) *next_ready = false;
   if (c.splits > 1) {
     const int64_t total = d.M * d.N;
     if (reduce4_ok(a, 1)) {
-      const int64_t blocks = std::min<int64_t>((total / 4 + 255) / 256, 16384);
-      splitk_reduce4_kernel<<<dim3(blocks), dim3(256), 0, st>>>(a);
+      // the next step's right operand, rounded here from the values just formed
+      auto al = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+      if (next16 && al(next16) && (!next_scale || al(next_scale))) {
+        a.out16 = reinterpret_cast<unsigned short*>(next16);
+        a.scale16 = next_scale;
+        if (next_ready) *next_ready = true;
+      }
+      splitk_reduce4_kernel<<<reduce4_grid(d.M, d.N), dim3(256), 0, st>>>(a);
     } else {
       const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
       splitk_reduce_kernel<float><<<dim3(blocks), dim3(256), 0, st>>>(a);
@@ -1368,19 +1411,28 @@ static bool bf16_wide() {
 
 hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
                             uint16_t* B16, hipStream_t st, const Workspace& ws,
-                            int force_splits) {
+                            int force_splits, bool b16_ready, uint16_t* next16,
+                            const float* next_scale, bool* next_ready) {
+  if (next_ready) *next_ready = false;
+  // the fused rounding writes an M x N block with ld M into the K x N buffer
+  if (next16 && d.M != d.K) next16 = nullptr;
   const bool wide_ok = bf16_wide() && d.sbk == 1 && d.batch == 1 && A16 && B16 &&
                        d.M % 128 == 0 && d.K % 64 == 0 && lda16 % 8 == 0 &&
                        reinterpret_cast<uintptr_t>(A16) % 16 == 0 &&
                        reinterpret_cast<uintptr_t>(B16) % 16 == 0;
   if (wide_ok && d.N % 320 == 0)
-    return gemm_bf16_launch<128, 320, true>(d, A16, lda16, B16, st, ws, force_splits);
+    return gemm_bf16_launch<128, 320, true>(d, A16, lda16, B16, st, ws, force_splits, b16_ready,
+                                                   next16, next_scale, next_ready);
   if (wide_ok && d.N % 128 == 0)
-    return gemm_bf16_launch<128, 128, true>(d, A16, lda16, B16, st, ws, force_splits);
+    return gemm_bf16_launch<128, 128, true>(d, A16, lda16, B16, st, ws, force_splits, b16_ready,
+                                                   next16, next_scale, next_ready);
   switch (bf16_tile()) {
-    case 1: return gemm_bf16_launch<64, 160>(d, A16, lda16, B16, st, ws, force_splits);
-    case 2: return gemm_bf16_launch<128, 64>(d, A16, lda16, B16, st, ws, force_splits);
-    default: return gemm_bf16_launch<64, 64>(d, A16, lda16, B16, st, ws, force_splits);
+    case 1: return gemm_bf16_launch<64, 160>(d, A16, lda16, B16, st, ws, force_splits, b16_ready,
+                                                   next16, next_scale, next_ready);
+    case 2: return gemm_bf16_launch<128, 64>(d, A16, lda16, B16, st, ws, force_splits, b16_ready,
+                                                   next16, next_scale, next_ready);
+    default: return gemm_bf16_launch<64, 64>(d, A16, lda16, B16, st, ws, force_splits, b16_ready,
+                                                   next16, next_scale, next_ready);
   }
 }
 

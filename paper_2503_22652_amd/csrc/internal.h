@@ -120,9 +120,16 @@ size_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, size_t elem);
 // B16 (K x N bfloat16, ld K) receives the rounded right operand; FP32
 // accumulation and epilogue.  Split-K partials need at most
 // gemm_bf16_workspace_bytes(M, N) of ws.
+// Chained steps (M == K): b16_ready says B16 already holds bfloat16(kscale .*
+// B) and skips the rounding pass; with next16, the split-K reduction (when the
+// product takes it) also writes next16 (M x N, ld M) = bfloat16(next_scale .*
+// C) and sets *next_ready -- the next step's right operand, rounded from the
+// values just formed.  next16 may be B16: the reduction runs after the product.
 hipError_t gemm_bf16_filter(const GemmDesc<float>& d, const uint16_t* A16, int64_t lda16,
                             uint16_t* B16, hipStream_t st, const Workspace& ws,
-                            int force_splits = 0);
+                            int force_splits = 0, bool b16_ready = false,
+                            uint16_t* next16 = nullptr, const float* next_scale = nullptr,
+                            bool* next_ready = nullptr);
 size_t gemm_bf16_workspace_bytes(int64_t M, int64_t N);
 // split-K partial bytes the BF16 product will use for this shape (0: no split)
 size_t gemm_bf16_plan_bytes(int64_t M, int64_t N, int64_t K, int force_splits);
@@ -312,10 +319,10 @@ hipError_t check_finite(const double* v, int64_t n, int* flag, hipStream_t st);
 // scratch of potrf_lower / trsm_lower_left: inverses of the diagonal blocks
 // and one block row or column of temporaries
 size_t tri_workspace_bytes(int64_t b, int64_t nrhs);
-// lower Cholesky factor in place (upper part zeroed); info: first failing
-// pivot (1-based) or 0
+// lower Cholesky factor in place (upper part zeroed); info: first pivot
+// (1-based) that is not above piv_tol (or not finite), or 0
 hipError_t potrf_lower(double* A, int64_t lda, int64_t b, int* info, hipStream_t st,
-                       const Workspace& ws, double* tri);
+                       const Workspace& ws, double* tri, double piv_tol = 0.0);
 // X <- L^{-1} X (L lower b x b, X b x nrhs); inverses_ready: tri holds the
 // diagonal blocks' inverses of this L (left by potrf_lower)
 hipError_t trsm_lower_left(const double* L, int64_t ldl, double* X, int64_t ldx, int64_t b,

@@ -19,6 +19,8 @@
 // products are two-stage reductions in a fixed order (bitwise reproducible).
 #include "internal.h"
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -215,13 +217,62 @@ __global__ __launch_bounds__(kThreads) void k_gemv_rows(const double* __restrict
   if (lane == 0) y[m] = s;
 }
 
+// The same product with 16-byte loads (A, x and ld allow them, n % 128 == 0):
+// lane l takes the pairs at k = 2 l + 128 i; four partial sums over i mod 4,
+// added in a fixed order, then the wave reduction
+__global__ __launch_bounds__(kThreads) void k_gemv_rows_vec(const double* __restrict__ A,
+                                                            int64_t ld, int64_t n,
+                                                            const double* __restrict__ x,
+                                                            double* __restrict__ y) {
+  const int64_t m = int64_t(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6);
+  if (m >= n) return;
+  const int lane = threadIdx.x & 63;
+  const double2* row = reinterpret_cast<const double2*>(A + m * ld) + lane;
+  const double2* xv = reinterpret_cast<const double2*>(x) + lane;
+  const int64_t steps = n / 128;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = 0;
+  for (; i + 4 <= steps; i += 4) {
+    double2 a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = row[(i + u) * 64];
+      b[u] = xv[(i + u) * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = fma(a[u].y, b[u].y, fma(a[u].x, b[u].x, acc[u]));
+  }
+  for (; i < steps; ++i) {
+    const double2 a = row[i * 64], b = xv[i * 64];
+    acc[i & 3] = fma(a.y, b.y, fma(a.x, b.x, acc[i & 3]));
+  }
+  double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  s = wave_sum(s);
+  if (lane == 0) y[m] = s;
+}
+
 }  // namespace
+
+// 16-byte-load GEMV where the layout allows it (knob CHFSI_GEMV_VEC=0: off)
+static bool gemv_vec_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("CHFSI_GEMV_VEC");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return on;
+}
 
 hipError_t gemv_rows_f64(const double* A, int64_t ld, int64_t n, const double* x, double* y,
                          hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + kThreads / 64 - 1) / (kThreads / 64);
-  k_gemv_rows<<<dim3(unsigned(blocks)), kThreads, 0, st>>>(A, ld, n, x, y);
+  const bool vec = gemv_vec_on() && n % 128 == 0 && ld % 2 == 0 &&
+                   reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(x) % 16 == 0;
+  if (vec)
+    k_gemv_rows_vec<<<dim3(unsigned(blocks)), kThreads, 0, st>>>(A, ld, n, x, y);
+  else
+    k_gemv_rows<<<dim3(unsigned(blocks)), kThreads, 0, st>>>(A, ld, n, x, y);
   return hipGetLastError();
 }
 

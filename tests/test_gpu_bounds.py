@@ -159,3 +159,31 @@ def test_solve_grid_with_estimated_lambda_max(prec):
     assert st == P.OK
     assert rep["lambda_max_used"] >= w[-1]
     np.testing.assert_allclose(ev[:6], w[:6], rtol=1e-9, atol=1e-10)
+
+
+def test_overlapped_estimate_matches_sequential(monkeypatch):
+    """The estimate of lambda_max made on a second stream during the first
+    Rayleigh-Ritz pass (dense real operators) is bit-identical to the one made
+    before it on the context's stream (knob CHFSI_LANCZOS_OVERLAP=0), and so is
+    the whole solve."""
+    p = wl.dense_generalized(n=1536, n_low=48, block=64, degree=20, seed=1001)
+    A, B = P.to_colmajor(p.A), P.to_colmajor(p.B)
+    d = torch.from_numpy(p.dinv).cuda()
+    out = {}
+    for knob in ("0", "1"):
+        monkeypatch.setenv("CHFSI_LANCZOS_OVERLAP", knob)
+        prm = P.make_params(48, 64, 20, max_iter=40, tol=1e-9, method=P.METHOD_RCHFSI,
+                            filter_prec=P.PREC_FP32)          # lambda_max = NaN: estimated
+        ctx = P.chfsi_create(P.dense_operator(A), P.dense_operator(B), d, prm, keep=(A, B, d))
+        Xd = P.to_colmajor(wl.random_block(p.n, 64, 2001))
+        print("solve with the estimate overlapped:", knob, flush=True)
+        st, ev, rn, rep = P.chfsi_solve(ctx, Xd)
+        assert st == P.OK
+        out[knob] = (rep["lambda_max_used"], rep["iterations"], np.asarray(ev), np.asarray(rn),
+                     Xd.cpu().numpy())
+        print(knob, rep["lambda_max_used"], rep["iterations"], rep["time_bounds_ms"],
+              rep["time_total_ms"] if "time_total_ms" in rep else "")
+    a, b = out["0"], out["1"]
+    assert a[0] == b[0] and a[1] == b[1]
+    for x, y in zip(a[2:], b[2:]):
+        assert np.array_equal(x, y)

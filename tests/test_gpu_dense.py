@@ -375,6 +375,34 @@ def test_jacobi_sweep_cap_is_reported(monkeypatch):
     assert not rep["flags"] & 2
 
 
+@pytest.mark.parametrize("n,b", [(512, 40), (1024, 100), (2048, 320)])
+def test_jacobi_pipelined_rounds_bitwise(monkeypatch, n, b):
+    """The pipelined outer rounds (a round's pair solves launched with the
+    previous round's rotations, the pair workgroups forming their rotated
+    blocks themselves) give bit-identical Rayleigh-Ritz results to a pair-solve
+    launch followed by a rotation launch per round (knob CHFSI_JACOBI_PIPE=0):
+    padded blocks of 2, 4 and 10 pairs."""
+    p = wl.dense_generalized(n=n, n_low=b // 2, block=b, degree=8, seed=1001)
+    w = sla.eigvalsh(p.A, p.B)
+    params = P.make_params(b // 2, b, 8, method=P.METHOD_RCHFSI, filter_prec=P.PREC_FP64,
+                           lambda_max=float(w[-1]) + 0.5)
+    ctx = _ctx(p, params)
+    Y = dev(wl.random_block(n, b, 13))
+    out = {}
+    for pipe in ("0", "1"):
+        monkeypatch.setenv("CHFSI_JACOBI_PIPE", pipe)
+        X, R = P.colmajor_empty(n, b), P.colmajor_empty(n, b)
+        print("Rayleigh-Ritz n", n, "b", b, "pipelined", pipe, flush=True)
+        ritz, norms = P.chfsi_rayleigh_ritz(ctx, Y, X, R)
+        out[pipe] = (np.asarray(ritz), np.asarray(norms), host(X), host(R))
+    for a, c in zip(out["0"], out["1"]):
+        assert np.array_equal(a, c)
+    lam = out["1"][0]
+    scale = np.abs(w).max()
+    o = rr.rayleigh_ritz(host(Y), filters.dense_op(p.A), filters.dense_op(p.B))
+    np.testing.assert_allclose(lam, o["lam"], rtol=0, atol=1e-11 * scale)
+
+
 def test_bf16_stagnation_escalates_to_fp32():
     """A reduced-precision filter has a largest usable degree (Section 3.1's
     condition): on the toy spectrum of Section 4.1 (m = 1000, 10 wanted, gap 1)

@@ -85,6 +85,26 @@ def test_svqb_fallback_on_rank_deficient_block(rng):
     np.testing.assert_allclose(out["lam"], lam[: b - 1], atol=1e-11)
 
 
+def test_svqb_fallback_on_numerically_singular_block(rng):
+    """A column that differs from another by 1e-9 (relative): the scaled Gram
+    matrix is positive definite in exact arithmetic, but its smallest
+    eigenvalue (~1e-18) is below the 1e-14 drop tolerance, so the Cholesky
+    pivot test takes the SVQB fallback, drops that one direction, and the kept
+    span (an invariant subspace) gives the exact eigenvalues; a pivot above the
+    tolerance keeps the Cholesky path."""
+    n, b = 60, 8
+    lam = np.sort(rng.uniform(-1, 5, n))
+    Q, A = _sym(rng, lam)
+    Y = Q[:, :b].copy()
+    Y[:, -1] = Y[:, 0] + 1e-9 * Q[:, b]
+    out = rr.rayleigh_ritz(Y, filters.dense_op(A), filters.identity_op())
+    assert out["svqb"] and out["dropped"] == 1
+    np.testing.assert_allclose(out["lam"], lam[: b - 1], atol=1e-11)
+    Y[:, -1] = Y[:, 0] + 1e-5 * Q[:, b]      # smallest eigenvalue ~5e-11: Cholesky
+    out = rr.rayleigh_ritz(Y, filters.dense_op(A), filters.identity_op())
+    assert not out["svqb"] and out["dropped"] == 0
+
+
 def test_pencil_eigenvalues_shared_basis_and_jacobi(rng):
     """Full-space Rayleigh-Ritz = the pencil's spectrum: exact lam_j / b_j for a
     shared eigenbasis (the paper's generalized toy construction) and the
