@@ -36,9 +36,10 @@ PEAK_HBM_GBS = 8000.0
 # device copy (FETCH x 2.000, WRITE x 1.000); summary under profiles/.  Other
 # shapes report null.
 TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.4e6}
-# the same for the BF16-product step (operand rounding, product, split-K
-# reduction: profiles/dense_n8192_b320_bf16_wide_step_traffic.md)
-TRAFFIC_BF16_FILTER_STEP = {(8192, 320): 287.6e6}
+# the same for the BF16-product step (product, split-K reduction that also
+# rounds the next step's operand; the rounding pass of a filter's first step
+# averaged over its 19 steps: profiles/dense_n8192_b320_bf16_wide_step_traffic.md)
+TRAFFIC_BF16_FILTER_STEP = {(8192, 320): 277.2e6}
 # the same for the BF16 z-march filter step on the 128^3 grid (block 1200) and
 # the 160^3 grid (block 2400)
 TRAFFIC_ZMARCH = {(128, 1200, "bf16"): 21.98e9, (160, 2400, "bf16"): 89.61e9}
