@@ -40,11 +40,13 @@ hipError_t potrf_traced(double* A, int64_t lda, int64_t b, int* info, hipStream_
   return potrf_lower(A, lda, b, info, st, ws, tri, kGramPivotTol);
 }
 
-// the eigensolver under a roctx range
+// the eigensolver under a roctx range; pinned (two ints of pinned host memory)
+// and ev let it queue the next sweep's first launches before each read-back
 hipError_t syev_traced(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
-                       hipStream_t st, const Workspace& ws, int* sweeps, int* unconverged) {
+                       hipStream_t st, const Workspace& ws, int* sweeps, int* unconverged,
+                       int* pinned = nullptr, hipEvent_t ev = nullptr) {
   TraceRange tr("chfsi jacobi eigensolve");
-  return syev_jacobi(A, lda, b, w, V, ldv, st, ws, sweeps, unconverged);
+  return syev_jacobi(A, lda, b, w, V, ldv, st, ws, sweeps, unconverged, pinned, ev);
 }
 
 thread_local std::string g_last_error;
@@ -176,6 +178,7 @@ struct chfsi_ctx {
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_stage = nullptr;   // last copy out of h_stage (reuse waits on it)
+  hipEvent_t ev_jac = nullptr;     // the eigensolver's read-back of its sweep flags (h_flags[8..9])
   int last_sweeps = 0;
   int flags = 0;
   int jacobi_unconv = 0;          // the last eigensolve reached its sweep cap
@@ -1299,7 +1302,8 @@ chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, cons
   hipStream_t st = c->stream;
   chfsi_status s;
   int sweeps = 0;
-  CK(syev_traced(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1354,7 +1358,8 @@ chfsi_status rayleigh_ritz_svqb(chfsi_ctx* c, const double* Y, int64_t ldy, cons
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, b, k, st));
-  CK(syev_traced(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -1524,7 +1529,8 @@ chfsi_status rayleigh_ritz(chfsi_ctx* c, const double* Y, int64_t ldy, double* X
   }
   CK(symmetrize(c->Hp, b, b, st));
   int sweeps = 0;
-  CK(syev_traced(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -1627,7 +1633,8 @@ chfsi_status rayleigh_ritz_complex_svqb(chfsi_ctx* c, const double* Y, int64_t l
   const int64_t n = c->n, b = c->b, m = 2 * b;
   hipStream_t st = c->stream;
   int sweeps = 0;
-  CK(syev_traced(c->Linv, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Linv, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, m * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1686,7 +1693,8 @@ chfsi_status rayleigh_ritz_complex_svqb(chfsi_ctx* c, const double* Y, int64_t l
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, m, 2 * k, st));
-  CK(syev_traced(c->Hp, m, 2 * k, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, m, 2 * k, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -1942,7 +1950,8 @@ chfsi_status rayleigh_ritz_complex(chfsi_ctx* c, const double* Y, int64_t ldy, d
   }
   CK(symmetrize(c->Hp, m, m, st));
   int sweeps = 0;
-  CK(syev_traced(c->Hp, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, m, m, c->w, c->E, m, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -2101,7 +2110,8 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     h.ldc = b;
     CK(gemm<double>(h, st, c->ws));
     CK(symmetrize(c->Hp, b, b, st));
-    CK(syev_traced(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+    CK(syev_traced(c->Hp, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
     c->last_sweeps += sweeps;
     GemmDesc<double> t;
@@ -2128,7 +2138,8 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     return CHFSI_ERR_NOT_SPD;
   }
   // SVQB on the scaled Gram matrix kept in c->Linv (same reading as rayleigh_ritz_svqb)
-  CK(syev_traced(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Linv, b, b, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   CK(hipMemcpyAsync(c->h_w, c->w, b * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2182,7 +2193,8 @@ chfsi_status rayleigh_ritz_slabs(chfsi_ctx* c, double* X, int64_t ldx, double* R
     CK(gemm<double>(h, st, c->ws));
   }
   CK(symmetrize(c->Hp, b, k, st));
-  CK(syev_traced(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv));
+  CK(syev_traced(c->Hp, b, k, c->w, c->E, b, st, c->ws_eig, &sweeps, &c->jacobi_unconv,
+                 c->h_flags + 8, c->ev_jac));
   if (c->jacobi_unconv) c->flags |= 2;
   c->last_sweeps += sweeps;
   {
@@ -2443,6 +2455,7 @@ void chfsi_destroy(chfsi_ctx* c) {
   for (auto& e : c->ev)
     if (e) hipEventDestroy(e);
   if (c->ev_stage) hipEventDestroy(c->ev_stage);
+  if (c->ev_jac) hipEventDestroy(c->ev_jac);
   if (c->aux_stream) {
     hipStreamSynchronize(c->aux_stream);
     hipStreamDestroy(c->aux_stream);
@@ -2691,6 +2704,7 @@ chfsi_status chfsi::create_with_allocator(chfsi_ctx** out, const chfsi_operator*
     return CHFSI_ERR_NOMEM;
   }
   if (hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_jac, hipEventDisableTiming) != hipSuccess ||
       hipEventRecord(c->ev_stage, c->stream) != hipSuccess) {
     set_error("hipEventCreate failed");
     chfsi_destroy(c);

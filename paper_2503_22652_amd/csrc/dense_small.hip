@@ -973,10 +973,22 @@ __global__ __launch_bounds__(256) void k_jacobi_rank(const double* P, int64_t bp
     for (int t = threadIdx.x; t < cn; t += 256) dg[t] = P[(c0 + t) + (c0 + t) * bp];
     __syncthreads();
     if (i < b) {
-      for (int t = 0; t < cn; ++t) {
-        const double dj = dg[t];
-        rank += (dj < di) || (dj == di && c0 + t < i);
+      // eight independent counts, so that the LDS reads are not serialised
+      int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int t = 0;
+      for (; t + 8 <= cn; t += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double dj = dg[t + u];
+          cnt[u] += (dj < di) || (dj == di && c0 + t + u < i);
+        }
       }
+      for (; t < cn; ++t) {
+        const double dj = dg[t];
+        cnt[0] += (dj < di) || (dj == di && c0 + t < i);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rank += cnt[u];
     }
   }
   if (i < b) {
@@ -1152,7 +1164,7 @@ static bool jacobi_pipelined() {
 
 hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
                        hipStream_t st, const Workspace& ws, int* sweeps_out,
-                       int* unconverged_out) {
+                       int* unconverged_out, int* pinned_flags, hipEvent_t ev) {
   const int64_t bp = jacobi_padded(b);
   const int nblk = int(bp / JB);     // even
   const int npairs = nblk / 2;
@@ -1183,24 +1195,35 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
   const int R = nblk - 1;                          // rounds per sweep
   const unsigned napply = unsigned(npairs) * unsigned(npairs + bp / JP);
   const int64_t usz = int64_t(npairs) * JP * JP;
+  // launch r of the pipelined sweep: pair solves of round r (on the matrix
+  // after round r - 1, formed in the pair workgroups) and round r - 1's
+  // rotations P -> P2; launch R applies round R - 1
+  auto launch = [&](int r) -> hipError_t {
+    const bool solve = r < R, rotate = r > 0;
+    const int cu = r & 1, pu = (r - 1) & 1;
+    k_jacobi_round<<<dim3((solve ? unsigned(npairs) : 0u) + (rotate ? napply : 0u)), kPairThreads,
+                     0, st>>>(
+        P, P2, bp, Vp, bp, nblk, npairs, rotate ? r - 1 : -1, rotate ? U + pu * usz : nullptr,
+        rotate ? skip + pu * npairs : nullptr, solve ? r : -1, solve ? U + cu * usz : nullptr,
+        solve ? skip + cu * npairs : nullptr, scal, tol, counter);
+    const hipError_t le = hipGetLastError();
+    if (le == hipSuccess && rotate) std::swap(P, P2);
+    return le;
+  };
+  // With a pinned flag buffer and an event, the first two launches of the
+  // next sweep are queued before the convergence flags of this one are read
+  // back, so the device does not idle while the host waits.  After
+  // convergence those launches change nothing: every pair subproblem is below
+  // the threshold (skipped), the rotation workgroups copy the matrix into the
+  // other buffer, and only that buffer swap is undone.
+  const bool early = pipe && pinned_flags && ev && R >= 2;
+  int started = 0;   // launches of the current sweep already queued
   for (; sweeps < max_outer; ++sweeps) {
-    if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
+    if (started == 0 && (e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
     if (pipe) {
-      // launch r: pair solves of round r (on the matrix after round r - 1,
-      // formed in the pair workgroups) and round r - 1's rotations P -> P2;
-      // a last launch applies round R - 1
-      for (int r = 0; r <= R; ++r) {
-        const bool solve = r < R, rotate = r > 0;
-        const int cu = r & 1, pu = (r - 1) & 1;
-        k_jacobi_round<<<dim3((solve ? unsigned(npairs) : 0u) + (rotate ? napply : 0u)),
-                         kPairThreads, 0, st>>>(
-            P, P2, bp, Vp, bp, nblk, npairs, rotate ? r - 1 : -1, rotate ? U + pu * usz : nullptr,
-            rotate ? skip + pu * npairs : nullptr, solve ? r : -1,
-            solve ? U + cu * usz : nullptr, solve ? skip + cu * npairs : nullptr, scal, tol,
-            counter);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (rotate) std::swap(P, P2);
-      }
+      for (int r = started; r <= R; ++r)
+        if ((e = launch(r)) != hipSuccess) return e;
+      started = 0;
     } else {
       for (int r = 0; r < R; ++r) {
         k_jacobi_pair_solve<<<dim3(npairs), kPairThreads, 0, st>>>(P, bp, nblk, r, scal, tol, U,
@@ -1216,6 +1239,28 @@ hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, 
     k_offmax_part<<<kFroParts, 256, 0, st>>>(P, bp, scal + 16);
     k_offmax_final<<<1, 64, 0, st>>>(scal + 16, scal, tol, counter + 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (early) {
+      if ((e = hipMemcpyAsync(pinned_flags, counter, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                              st)) != hipSuccess)
+        return e;
+      if ((e = hipEventRecord(ev, st)) != hipSuccess) return e;
+      if (sweeps + 1 < max_outer) {
+        if ((e = fill_zero(counter, sizeof(int), st)) != hipSuccess) return e;
+        for (int r = 0; r < 2; ++r)
+          if ((e = launch(r)) != hipSuccess) return e;
+        started = 2;
+      }
+      if ((e = hipEventSynchronize(ev)) != hipSuccess) return e;
+      host_count = pinned_flags[0];
+      if (host_count == 0 || pinned_flags[1] != 0) {
+        if (started == 2) std::swap(P, P2);   // launch 1 copied the matrix into P2
+        started = 0;
+        converged = true;
+        ++sweeps;
+        break;
+      }
+      continue;
+    }
     int host_flags[2] = {0, 0};
     if ((e = hipMemcpyAsync(host_flags, counter, 2 * sizeof(int), hipMemcpyDeviceToHost, st)) !=
         hipSuccess)

@@ -333,9 +333,13 @@ hipError_t trsm_lower_left(const double* L, int64_t ldl, double* X, int64_t ldx,
 // scratch from ws; sweeps reported through *sweeps_out (host) if non-null;
 // *unconverged_out (host, if non-null) = 1 when the sweep cap was reached with
 // rotations still being applied (the result is then not fully diagonalised).
+// pinned_flags (two ints of pinned host memory) and ev (an event of the
+// stream's device): optional; with both, the next sweep's first launches are
+// queued before each convergence read-back
 hipError_t syev_jacobi(double* A, int64_t lda, int64_t b, double* w, double* V, int64_t ldv,
                        hipStream_t st, const Workspace& ws, int* sweeps_out,
-                       int* unconverged_out = nullptr);
+                       int* unconverged_out = nullptr, int* pinned_flags = nullptr,
+                       hipEvent_t ev = nullptr);
 size_t syev_workspace_bytes(int64_t b);
 size_t potrf_workspace_bytes(int64_t b);
 
