@@ -359,15 +359,18 @@ def test_stagnation_stops_early_and_returns_best_pairs():
     assert abs(rcpu.max() - rep["best_residual"]) <= 1e-6 * rep["best_residual"]
 
 
-def test_jacobi_sweep_cap_is_reported(monkeypatch):
-    """An eigensolve stopped by its sweep cap (forced to 1 sweep here) with
-    rotations still pending raises report flags bit 1."""
+@pytest.mark.parametrize("cap", ["1", "2"])
+def test_jacobi_sweep_cap_is_reported(monkeypatch, cap):
+    """An eigensolve stopped by its sweep cap (forced to 1 or 2 sweeps here;
+    with 2, the second sweep's first launches are queued before the first
+    sweep's flags are read) with rotations still pending raises report flags
+    bit 1."""
     p = wl.dense_generalized(n=512, n_low=16, block=40, degree=8, seed=1001)
     w = sla.eigvalsh(p.A, p.B)
     params = P.make_params(16, 40, 8, max_iter=1, tol=1e-12, method=P.METHOD_RCHFSI,
                            filter_prec=P.PREC_FP64, lambda_max=float(w[-1]) + 0.5)
     ctx = _ctx(p, params)
-    monkeypatch.setenv("CHFSI_JACOBI_MAX_SWEEPS", "1")
+    monkeypatch.setenv("CHFSI_JACOBI_MAX_SWEEPS", cap)
     st, ev, rn, rep = P.chfsi_solve(ctx, dev(wl.random_block(p.n, 40, 7)))
     assert rep["flags"] & 2
     monkeypatch.delenv("CHFSI_JACOBI_MAX_SWEEPS")
