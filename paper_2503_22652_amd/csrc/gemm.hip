@@ -734,13 +734,20 @@ static void plan_impl(int64_t M, int64_t N, int64_t K, int batch, bool filter_la
     *splits = s;
     return;
   }
-  const Cfg& f = (sizeof(T) == 4 ? kCfgF32 : kCfgF64)[ncfg - 1];
+  // FP64 products with a large output (M N >= 2^24, e.g. the grid rotation
+  // X = Y Q): knob CHFSI_GEMM64_BIG_CFG (0 = 128x128, 1 = 128x64, 2 = 64x64)
+  int gcfg = ncfg - 1;
+  if (sizeof(T) == 8 && M * N >= (int64_t(1) << 24)) {
+    const int bc = env_int("CHFSI_GEMM64_BIG_CFG", ncfg - 1);
+    if (bc >= 0 && bc < ncfg) gcfg = bc;
+  }
+  const Cfg& f = (sizeof(T) == 4 ? kCfgF32 : kCfgF64)[gcfg];
   const int64_t tiles = ((M + f.BM - 1) / f.BM) * ((N + f.BN - 1) / f.BN) * batch;
   const int64_t target = int64_t(kNumCU) * (sizeof(T) == 4 ? 16 : 8);
   const int64_t max_s = std::max<int64_t>(1, K / (8 * f.BK));
   int s = 1;
   while (tiles * s < target && s * 2 <= max_s && s < 64) s *= 2;
-  *config = ncfg - 1;
+  *config = gcfg;
   *splits = s;
 }
 
