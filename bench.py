@@ -346,7 +346,8 @@ def main():
             "traffic_unit": "bytes per launch",
             "kernel": ("gemm_kernel<float> + splitk_reduce4_kernel (FP32 residual-filter step, "
                        "2*N^2*b flops per launch)") if args.dense_prec == "fp32" else
-                      ("k_scale_bf16 + gemm_bf16_kernel + splitk_reduce4_kernel (BF16-product "
+                      ("gemm_bf16_wide_kernel + splitk_reduce4_kernel, which also rounds the "
+                       "next step's operand (k_scale_bf16 on a filter's first step) (BF16-product "
                        "residual-filter step, 2*N^2*b flops per launch)"),
             "ms_per_launch": round(per_launch_ms, 4),
         },
