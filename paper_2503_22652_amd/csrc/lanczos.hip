@@ -251,6 +251,57 @@ __global__ __launch_bounds__(kThreads) void k_gemv_rows_vec(const double* __rest
   if (lane == 0) y[m] = s;
 }
 
+// The same product with x staged in LDS: 16 waves (rows) per workgroup share
+// one copy of x per 4096-element chunk, so the x reads come from LDS instead
+// of competing with the A stream for the caches; four partial sums per lane
+// over the pairs k = 2 l + 128 i (i mod 4), added in a fixed order
+constexpr int kLdsWaves = 16;
+constexpr int kXChunk = 4096;
+__global__ __launch_bounds__(64 * kLdsWaves) void k_gemv_rows_lds(const double* __restrict__ A,
+                                                                  int64_t ld, int64_t n,
+                                                                  const double* __restrict__ x,
+                                                                  double* __restrict__ y) {
+  __shared__ double2 xs[kXChunk / 2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t m = int64_t(blockIdx.x) * kLdsWaves + wave;
+  const double2* row = reinterpret_cast<const double2*>(A + (m < n ? m : 0) * ld) + lane;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = 0;   // global pair-step index (k = 2 lane + 128 i)
+  for (int64_t c0 = 0; c0 < n; c0 += kXChunk) {
+    const int cn = int(n - c0 < kXChunk ? n - c0 : kXChunk);   // a multiple of 128
+    __syncthreads();
+    for (int t = threadIdx.x; t < cn / 2; t += 64 * kLdsWaves)
+      xs[t] = reinterpret_cast<const double2*>(x + c0)[t];
+    __syncthreads();
+    if (m < n) {
+      const int steps = cn / 128;
+      int s = 0;
+      for (; s + 4 <= steps; s += 4) {
+        double2 a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = row[(i + s + u) * 64];
+          b[u] = xs[lane + (s + u) * 64];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = int((i + s + u) & 3);
+          acc[q] = fma(a[u].y, b[u].y, fma(a[u].x, b[u].x, acc[q]));
+        }
+      }
+      for (; s < steps; ++s) {
+        const double2 a = row[(i + s) * 64], b = xs[lane + s * 64];
+        const int q = int((i + s) & 3);
+        acc[q] = fma(a.y, b.y, fma(a.x, b.x, acc[q]));
+      }
+    }
+    i += cn / 128;
+  }
+  double sres = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  sres = wave_sum(sres);
+  if (m < n && lane == 0) y[m] = sres;
+}
+
 }  // namespace
 
 // 16-byte-load GEMV where the layout allows it (knob CHFSI_GEMV_VEC=0: off)
@@ -269,7 +320,12 @@ hipError_t gemv_rows_f64(const double* A, int64_t ld, int64_t n, const double* x
   const bool vec = gemv_vec_on() && n % 128 == 0 && ld % 2 == 0 &&
                    reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
                    reinterpret_cast<uintptr_t>(x) % 16 == 0;
-  if (vec)
+  const char* ev = std::getenv("CHFSI_GEMV_LDS");
+  const bool lds = vec && !(ev && std::atoi(ev) == 0);
+  if (lds)
+    k_gemv_rows_lds<<<dim3(unsigned((n + kLdsWaves - 1) / kLdsWaves)), 64 * kLdsWaves, 0, st>>>(
+        A, ld, n, x, y);
+  else if (vec)
     k_gemv_rows_vec<<<dim3(unsigned(blocks)), kThreads, 0, st>>>(A, ld, n, x, y);
   else
     k_gemv_rows<<<dim3(unsigned(blocks)), kThreads, 0, st>>>(A, ld, n, x, y);
