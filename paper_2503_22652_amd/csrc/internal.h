@@ -249,8 +249,8 @@ size_t lanczos_workspace_bytes(int64_t L);
 // y = A x, A dense symmetric n x n (ld), FP64; one wave per row
 hipError_t gemv_rows_f64(const double* A, int64_t ld, int64_t n, const double* x, double* y,
                          hipStream_t st);
-// host_scalars: pinned host memory for 2 doubles.  Synchronises the stream
-// at every dot product.  Returns hipErrorInvalidValue if B is not positive
+// host_scalars: pinned host memory for 8 doubles.  Synchronises the stream
+// once per Lanczos step and once per batch of CG iterations.  Returns hipErrorInvalidValue if B is not positive
 // definite on the Krylov space (a non-positive B-norm).
 hipError_t lanczos_bounds(const LanczosOps& ops, int64_t L, double* work, double* host_scalars,
                           hipStream_t st, LanczosResult* res);

@@ -126,23 +126,28 @@ __global__ __launch_bounds__(kThreads) void k_lincomb3_dev(double a, const doubl
 __global__ __launch_bounds__(kThreads) void k_cg_dir(const double* __restrict__ rz_new,
                                                      const double* __restrict__ rz_old,
                                                      const double* z, int64_t L, double* p) {
-  const double beta = *rz_new / *rz_old;
+  // (a zero residual, which a batch of iterations can run into, keeps p)
+  const double beta = *rz_old != 0.0 ? *rz_new / *rz_old : 0.0;
   for (int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x; i < L;
        i += int64_t(gridDim.x) * kThreads)
     p[i] = z[i] + beta * p[i];
 }
 
 // one CG update with alpha = *rz / *pq: x += alpha p; r -= alpha q;
-// z = dinv .* r; partial sums of r . r and r . z
+// z = dinv .* r; partial sums of r . r and r . z.  A non-positive p . B p with
+// a nonzero residual (B not positive definite on the Krylov space) sets the
+// sticky flag *bad; a zero residual gives alpha = 0.
 __global__ __launch_bounds__(kThreads) void k_cg_update(const double* __restrict__ rz,
                                                         const double* __restrict__ pq,
                                                         const double* __restrict__ p,
                                                         const double* __restrict__ q, double* x,
                                                         double* r, double* z,
                                                         const double* __restrict__ dinv,
-                                                        int64_t L, double* partial) {
+                                                        int64_t L, double* partial, double* bad) {
   __shared__ double lds[kThreads / 64];
-  const double alpha = *rz / *pq;
+  const double d = *pq, rzv = *rz;
+  if (!(d > 0.0) && rzv != 0.0 && blockIdx.x == 0 && threadIdx.x == 0) *bad = 1.0;
+  const double alpha = d > 0.0 ? rzv / d : 0.0;
   double srr = 0.0, srz = 0.0;
   for (int64_t i = blockIdx.x * int64_t(kThreads) + threadIdx.x; i < L;
        i += int64_t(gridDim.x) * kThreads) {
@@ -374,38 +379,54 @@ hipError_t lanczos_bounds(const LanczosOps& ops, int64_t L, double* work, double
     if (o1) *o1 = host_scalars[1];
     return hipSuccess;
   };
-  // solve B x = y by preconditioned CG from x = 0 (relative tolerance cg_tol);
-  // alpha and the direction update take their scalars on the device, so each
-  // iteration reads back once (the convergence test)
+  // solve B x = y by preconditioned CG from x = 0 (relative tolerance cg_tol).
+  // alpha and the direction update take their scalars on the device, and the
+  // iterations run in batches: as many as the previous solve needed, then one
+  // read-back (r.r, r0.r0 and the sticky not-positive-definite flag); the
+  // first solve, and iterations past a batch, read back after each.  Extra
+  // iterations of a batch that overshoots only refine x.
+  int cg_batch = 1;
   auto bsolve = [&](const double* y, double* x) -> hipError_t {
     LZ_CK(fill_zero(x, size_t(L) * sizeof(double), st));
     LZ_CK(hipMemcpyAsync(r, y, size_t(L) * sizeof(double), hipMemcpyDeviceToDevice, st));
     k_precond<<<lb, kThreads, 0, st>>>(ops.dinv, r, L, z);
     LZ_CK(hipGetLastError());
     LZ_CK(hipMemcpyAsync(p, z, size_t(L) * sizeof(double), hipMemcpyDeviceToDevice, st));
-    double rr0 = 0.0, rz0 = 0.0;
-    LZ_CK(dot2(r, r, r, z, &rr0, &rz0));             // dres[0] = r.r, dres[1] = r.z
-    if (!(rr0 > 0.0)) return hipSuccess;
-    const double stop = ops.cg_tol * ops.cg_tol * rr0;
+    // dres[7] = r0 . r0, dres[1] = r0 . z0, dres[6] = 0 (flag)
+    k_dot2_partial<<<nb, kThreads, 0, st>>>(r, r, r, z, L, partial);
+    k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres + 7, dres + 1);
+    LZ_CK(hipGetLastError());
+    LZ_CK(fill_zero(dres + 6, sizeof(double), st));
     double* rz_cur = dres + 1;
     double* rz_nxt = dres + 2;
-    for (int it = 0; it < ops.cg_max_iter; ++it) {
-      LZ_CK(ops.apply_B(p, q));
-      k_dot2_partial<<<nb, kThreads, 0, st>>>(p, q, nullptr, nullptr, L, partial);
-      k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres + 3, nullptr);
-      k_cg_update<<<nb, kThreads, 0, st>>>(rz_cur, dres + 3, p, q, x, r, z, ops.dinv, L,
-                                           partial);
-      k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres, rz_nxt);
-      LZ_CK(hipGetLastError());
-      LZ_CK(hipMemcpyAsync(host_scalars, dres, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    int it = 0;
+    int batch = cg_batch;
+    while (it < ops.cg_max_iter) {
+      const int m = std::min(batch, ops.cg_max_iter - it);
+      for (int j = 0; j < m; ++j) {
+        if (it + j > 0) {
+          k_cg_dir<<<lb, kThreads, 0, st>>>(rz_nxt, rz_cur, z, L, p);
+          std::swap(rz_cur, rz_nxt);
+        }
+        LZ_CK(ops.apply_B(p, q));
+        k_dot2_partial<<<nb, kThreads, 0, st>>>(p, q, nullptr, nullptr, L, partial);
+        k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres + 3, nullptr);
+        k_cg_update<<<nb, kThreads, 0, st>>>(rz_cur, dres + 3, p, q, x, r, z, ops.dinv, L,
+                                             partial, dres + 6);
+        k_dot2_final<<<1, 64, 0, st>>>(partial, nb, dres, rz_nxt);
+        LZ_CK(hipGetLastError());
+      }
+      it += m;
+      res->cg_iterations += m;
+      LZ_CK(hipMemcpyAsync(host_scalars, dres, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
       LZ_CK(hipStreamSynchronize(st));
-      if (!(host_scalars[3] > 0.0)) return hipErrorInvalidValue;   // B not positive definite
-      res->cg_iterations += 1;
-      if (host_scalars[0] <= stop) break;
-      k_cg_dir<<<lb, kThreads, 0, st>>>(rz_nxt, rz_cur, z, L, p);
-      LZ_CK(hipGetLastError());
-      std::swap(rz_cur, rz_nxt);
+      if (host_scalars[6] != 0.0) return hipErrorInvalidValue;   // B not positive definite
+      const double rr0 = host_scalars[7];
+      if (!(rr0 > 0.0)) break;                                     // zero right-hand side
+      if (host_scalars[0] <= ops.cg_tol * ops.cg_tol * rr0) break;
+      batch = 1;
     }
+    cg_batch = std::max(1, it);
     return hipSuccess;
   };
   // v_1 = v_0 / ||v_0||_B
