@@ -2938,6 +2938,12 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
   // stream from a helper thread while this thread runs that pass: its
   // matrix-vector products stream the operator from HBM, the eigensolver of
   // the pass keeps a few CUs busy.  Joined before the first filter.
+  // (the thread's results are declared before the thread and its joiner, so
+  // that on every return the joiner runs while they still exist)
+  chfsi_status lz_status = CHFSI_OK;
+  std::string lz_error;
+  LanczosResult lz_res;
+  double lz_ms = 0.0;
   std::thread lz_thread;
   struct Joiner {
     std::thread& t;
@@ -2945,10 +2951,6 @@ chfsi_status chfsi_solve(chfsi_ctx* c, double* X, int64_t ldx, double* evals, do
       if (t.joinable()) t.join();
     }
   } lz_join{lz_thread};
-  chfsi_status lz_status = CHFSI_OK;
-  std::string lz_error;
-  LanczosResult lz_res;
-  double lz_ms = 0.0;
   if (std::isnan(lmax_used) && !c->have_lmax) {
     if (lanczos_overlap_ok(c)) {
       if (!c->aux_stream) CK(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
