@@ -30,12 +30,13 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of the FP32 filter GEMM (64x64x32 tiles, split-K 8) at
-# N = 8192, b = 320: FETCH_SIZE and WRITE_SIZE from two rocprofv3 counter
-# passes over this script, scaled by what the same counters read for a 1 GiB
-# device copy (FETCH x 2.000, WRITE x 1.000); summary under profiles/.  Other
-# shapes report null.
-TRAFFIC_F32_FILTER_GEMM = {(8192, 320): 385.4e6}
+# HBM bytes per FP32 filter step at N = 8192, b = 320: the GEMM (64x64x32
+# tiles, split-K 8) plus the split-K reduction that carries the three-term
+# epilogue, the two kernels the step's timing brackets.  FETCH_SIZE and
+# WRITE_SIZE from two rocprofv3 counter passes over this script, scaled by what
+# the same counters read for a 1 GiB device copy (FETCH x 2.000, WRITE x 1.000);
+# summary under profiles/.  Other shapes report null.
+TRAFFIC_F32_FILTER_STEP = {(8192, 320): 511.5e6}
 # the same for the BF16-product step (product, split-K reduction that also
 # rounds the next step's operand; the rounding pass of a filter's first step
 # averaged over its 19 steps: profiles/dense_n8192_b320_bf16_wide_step_traffic.md)
@@ -341,7 +342,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / peak, 4),
-            "traffic": (TRAFFIC_F32_FILTER_GEMM if args.dense_prec == "fp32"
+            "traffic": (TRAFFIC_F32_FILTER_STEP if args.dense_prec == "fp32"
                         else TRAFFIC_BF16_FILTER_STEP).get((n, b)),
             "traffic_unit": "bytes per launch",
             "kernel": ("gemm_kernel<float> + splitk_reduce4_kernel (FP32 residual-filter step, "
